@@ -1,0 +1,235 @@
+"""p-multigrid V-cycle and the outer solvers (oracle, FP64).
+
+Passages followed:
+* Sec. 4.1, level degrees p_l = p_0 2^l (l < L), p_L = p, p_0 = 2;
+  Alg. 3 (V-cycle) with nu_pre,l = nu_post,l = 1 ("kMG") or 2^(L-l)
+  ("kvMG"); coarse-grid CG on the condensed system at p_0 = 2;
+* Alg. 4 (MG solver: V-cycles as a fixed-point iteration);
+* Alg. 5 (Krylov-accelerated MG: inexact preconditioned CG with the
+  V-cycle as preconditioner);
+* Sec. 5.2, convergence rate rho = (|r_n10| / |r_0|)^(1/n10).
+
+Readings where the paper is silent (each also listed in the design notes):
+* the coarse CG is Jacobi-preconditioned (diagonal of the condensed
+  operator) and stops when the D^-1-weighted residual norm has dropped by
+  ``coarse_rtol`` or after ``coarse_maxit`` iterations; ``coarse_rtol = 0``
+  gives a fixed iteration count;
+* the per-level damping omega_l multiplies the smoother output
+  (u_l += omega_l Smoother(...)); omega_l = 1 is the paper's method;
+  ``omega[j]`` is indexed from the finest level (j = L - l);
+* stopping test |r|_2 <= rtol |r_0|_2 over the unique condensed unknowns.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import matfree
+from .mesh import Mesh, level_degrees
+
+
+def dot(a, b):
+    return float(np.sum(np.asarray(a) * np.asarray(b)))
+
+
+def norm(a):
+    return float(np.sqrt(dot(a, a)))
+
+
+class Hierarchy:
+    """Levels 0..L of one mesh and the V-cycle of Alg. 3."""
+
+    def __init__(self, mesh: Mesh, nu_mode: str = "kMG", omega=None,
+                 coarse_rtol: float = 1e-8, coarse_maxit: int = 2000,
+                 exact_coarse: bool = False):
+        self.degs = level_degrees(mesh.p)
+        self.L = len(self.degs) - 1
+        self.meshes = [mesh.with_degree(q) for q in self.degs]
+        self.meshes[-1] = mesh
+        L = self.L
+        if nu_mode == "kMG":
+            self.nu = [1] * (L + 1)
+        elif nu_mode == "kvMG":
+            self.nu = [2 ** (L - l) for l in range(L + 1)]
+        else:
+            raise ValueError(nu_mode)
+        om = [1.0] * (L + 1)
+        if omega is not None:
+            for j, w in enumerate(omega):
+                if j <= L - 1:
+                    om[L - j] = float(w)
+        self.omega = om
+        self.coarse_rtol = coarse_rtol
+        self.coarse_maxit = coarse_maxit
+        self.exact_coarse = exact_coarse
+        self._diag0 = None
+        self._dense0 = None
+        self.coarse_iters = []
+
+    # ---- coarse grid ----------------------------------------------------
+    def coarse_solve(self, F0):
+        m0 = self.meshes[0]
+        if self.exact_coarse:
+            if self._dense0 is None:
+                from .dense import CondensedSystem
+                self._dense0 = CondensedSystem(m0)
+            cs = self._dense0
+            return cs.to_grid(np.linalg.solve(cs.Hhat, cs.to_vec(F0)))
+        if self._diag0 is None:
+            self._diag0 = matfree.condensed_diagonal(m0)
+        return jacobi_pcg(lambda x: matfree.condensed_op(m0, x), F0,
+                          self._diag0, self.coarse_rtol, self.coarse_maxit,
+                          self.coarse_iters)
+
+    # ---- Alg. 3 -----------------------------------------------------------
+    def vcycle(self, u, F):
+        L = self.L
+        ms = self.meshes
+        us = [None] * (L + 1)
+        Fs = [None] * (L + 1)
+        us[L] = None if u is None else np.asarray(u, dtype=np.float64)
+        Fs[L] = np.asarray(F, dtype=np.float64)
+
+        def residual(l):
+            if us[l] is None:
+                return Fs[l]
+            return Fs[l] - matfree.condensed_op(ms[l], us[l])
+
+        def smooth(l):
+            du = matfree.smoother(ms[l], residual(l), self.omega[l])
+            us[l] = du if us[l] is None else us[l] + du
+
+        for l in range(L, 0, -1):
+            if l != L:
+                us[l] = None                       # u_l <- 0
+            for _ in range(self.nu[l]):
+                smooth(l)
+            Fs[l - 1] = matfree.restrict(ms[l], ms[l - 1], residual(l))
+        us[0] = self.coarse_solve(Fs[0])
+        for l in range(1, L + 1):
+            pu = matfree.prolong(ms[l - 1], ms[l], us[l - 1])
+            us[l] = pu if us[l] is None else us[l] + pu
+            for _ in range(self.nu[l]):
+                smooth(l)
+        return us[L]
+
+
+def jacobi_pcg(apply, b, diag, rtol, maxit, log=None):
+    """Jacobi-preconditioned CG from x = 0.
+
+    Stops before an iteration when sqrt(<r, D^-1 r>) <= rtol sqrt(<b, D^-1 b>)
+    or after ``maxit`` iterations.
+    """
+    x = np.zeros_like(b)
+    r = np.array(b, dtype=np.float64)
+    z = r / diag
+    p = z.copy()
+    rz = dot(r, z)
+    rz0 = rz
+    it = 0
+    while it < maxit:
+        if rz <= (rtol * rtol) * rz0 or rz == 0.0:
+            break
+        q = apply(p)
+        alpha = rz / dot(p, q)
+        x = x + alpha * p
+        r = r - alpha * q
+        z = r / diag
+        rz_new = dot(r, z)
+        beta = rz_new / rz
+        rz = rz_new
+        p = z + beta * p
+        it += 1
+    if log is not None:
+        log.append(it)
+    return x
+
+
+class SolveResult:
+    def __init__(self, u, uhat, iters, hist):
+        self.u = u
+        self.uhat = uhat
+        self.iters = iters
+        self.hist = hist
+
+    @property
+    def rho(self):
+        """Mean convergence rate over the iterations (Sec. 5.2)."""
+        if self.iters == 0:
+            return 0.0
+        return (self.hist[-1] / self.hist[0]) ** (1.0 / self.iters)
+
+
+def ipcg(mesh: Mesh, Fhat, rtol=1e-10, maxit=200, hier: Hierarchy = None,
+         precond=None, **hkw):
+    """Alg. 5 on the condensed system; returns (uhat, iters, history)."""
+    hier = hier or Hierarchy(mesh, **hkw)
+    A = lambda x: matfree.condensed_op(mesh, x)
+    M = precond or (lambda r: hier.vcycle(None, r))
+    u = np.zeros_like(Fhat)
+    r = np.array(Fhat, dtype=np.float64)     # r = F - H u with u = 0
+    s = r.copy()
+    p = np.zeros_like(r)
+    delta = 1.0
+    hist = [norm(r)]
+    eps = rtol * hist[0]
+    it = 0
+    while hist[-1] > eps and it < maxit:
+        z = M(r)
+        gamma = dot(z, r)
+        gamma0 = dot(z, s)
+        beta = (gamma - gamma0) / delta
+        delta = gamma
+        p = beta * p + z
+        q = A(p)
+        alpha = gamma / dot(q, p)
+        s = r
+        u = u + alpha * p
+        r = r - alpha * q
+        hist.append(norm(r))
+        it += 1
+    return u, it, hist
+
+
+def mg_solve(mesh: Mesh, Fhat, rtol=1e-10, maxit=200, hier=None, **hkw):
+    """Alg. 4: repeated V-cycles until |F - H u| <= rtol |F|."""
+    hier = hier or Hierarchy(mesh, **hkw)
+    u = np.zeros_like(Fhat)
+    r = np.array(Fhat, dtype=np.float64)
+    hist = [norm(r)]
+    eps = rtol * hist[0]
+    it = 0
+    while hist[-1] > eps and it < maxit:
+        u = hier.vcycle(u, Fhat)
+        r = Fhat - matfree.condensed_op(mesh, u)
+        hist.append(norm(r))
+        it += 1
+    return u, it, hist
+
+
+def mixed_precond(hier: Hierarchy):
+    """Mixed-precision preconditioner form: z = |r| up(M(down(r / |r|))).
+
+    The oracle rounds the scaled residual and the correction to float32
+    around an FP64 V-cycle; it reproduces the data flow, not the float32
+    arithmetic inside the cycle.
+    """
+    def M(r):
+        nr = norm(r)
+        if nr == 0.0:
+            return np.zeros_like(r)
+        r32 = (r / nr).astype(np.float32).astype(np.float64)
+        z = hier.vcycle(None, r32)
+        return nr * z.astype(np.float32).astype(np.float64)
+    return M
+
+
+def solve(mesh: Mesh, f_grid, method="kMG", rtol=1e-10, maxit=200, **hkw):
+    """Full solve: condense, iterate, recover (Alg. 4 / Alg. 5)."""
+    Fhat = matfree.condense_rhs(mesh, f_grid)
+    if method == "MG":
+        uhat, it, hist = mg_solve(mesh, Fhat, rtol, maxit, **hkw)
+    else:
+        nu_mode = "kvMG" if method == "kvMG" else "kMG"
+        uhat, it, hist = ipcg(mesh, Fhat, rtol, maxit, nu_mode=nu_mode, **hkw)
+    u = matfree.recover_interior(mesh, f_grid, uhat)
+    return SolveResult(u, uhat, it, hist)
