@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Benchmark of the condensed p-multigrid Helmholtz solver on one MI355X.
+
+Metric: solved unknowns per second (n_e p^3 / t_solve) to a 1e-10 relative
+residual, where one step is one complete solve (condensation, Krylov-
+accelerated multigrid iterations of Alg. 5, interior recovery) of the
+workload below with its inputs already resident in HBM.  The headline value
+is the mixed-precision solver (FP32 V-cycle inside FP64 CG, with learned
+per-level damping when a trained network is available, otherwise the
+paper's omega = 1); the plain FP64 solver is timed beside it.
+
+Default workload: 16 x 16 x 16 elements, p = 8 (levels 2, 4, 8), lambda = 1,
+geometric stretching up to aspect ratio 8 (alpha = 8^(1/15)), exact solution
+a seeded sum of 8 sine modes.
+
+Also reported: the roofline position of the dominant kernel (the star
+smoother, timed alone with HIP events on its stream) and the CPU oracle
+timed on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"f64": 78.6, "f32": 157.3}   # TFLOP/s, MI355X dense vector / matrix
+HBM_PEAK = 8000.0                     # GB/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    if name == "c2a":
+        return dict(n=(16, 16, 16), p=8, lam=1.0, alpha=8.0 ** (1.0 / 15.0), seed=0)
+    if name == "c2b":
+        return dict(n=(8, 8, 8), p=16, lam=1.0, alpha=8.0 ** (1.0 / 7.0), seed=0)
+    if name == "c1":
+        return dict(n=(4, 4, 4), p=4, lam=1.0, alpha=1.0, seed=0)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def make_rhs(g, wl, torch, synth, dev):
+    x1, x2, x3 = (torch.tensor(c, dtype=torch.float64, device=dev) for c in g.grid_coords())
+    k, a = synth.sine_modes(wl["seed"])
+    u, f = synth.sine_solution(k, a, (1.0, 1.0, 1.0), x1[None, None, :], x2[None, :, None],
+                               x3[:, None, None], wl["lam"], xp=torch)
+    return u.contiguous(), f.contiguous()
+
+
+def smoother_flops(n, p):
+    """Algorithmic flops of one smoother application: 37 n_S^3 per star.
+
+    Stars are all vertices of the mesh except the 8 domain corners, whose
+    three planes are Dirichlet (Alg. 1, op count of Sec. 3.2).
+    """
+    nS = 2 * p - 1
+    nstars = (n[0] + 1) * (n[1] + 1) * (n[2] + 1) - 8
+    return 37.0 * nS ** 3 * nstars
+
+
+def time_smoother(g, torch, dev, dtype, reps=20):
+    import paper_1808_03595_amd as pmg
+    L = g.num_levels()
+    n = g.skeleton_len(L)
+    tdt = torch.float64 if dtype == pmg.F64 else torch.float32
+    r = torch.randn(n, dtype=tdt, device=dev)
+    tmp = torch.empty(g.grid_shape(), dtype=torch.float64, device=dev)
+    g.skeleton_to_grid(r, tmp, dtype)       # zero the unused slots of r
+    g.grid_to_skeleton(tmp, r, dtype)
+    du = torch.empty_like(r)
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        g.schwarz_smooth(L, r, du, 1.0, dtype, stream=s)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        g.schwarz_smooth(L, r, du, 1.0, dtype, stream=s)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3
+
+
+def cpu_baseline(wl, budget_s=25.0):
+    """Time the FP64 oracle on a bounded sample of the workload."""
+    import numpy as np
+    import synth
+    from oracle import mesh as omesh, solver
+    threads = len(os.sched_getaffinity(0))
+    n = wl["n"]
+    o = omesh.Mesh.box(n, wl["p"], wl["lam"], wl["alpha"])
+    X3, X2, X1 = o.coords()
+    k, a = synth.sine_modes(wl["seed"])
+    _, f = synth.sine_solution(k, a, (1.0, 1.0, 1.0), X1, X2, X3, wl["lam"])
+    f = np.broadcast_to(f, o.shape).copy()
+    from oracle import matfree
+    t0 = time.perf_counter()
+    Fh = matfree.condense_rhs(o, f)
+    t_pre = time.perf_counter() - t0
+    hier = solver.Hierarchy(o, nu_mode="kMG", coarse_rtol=1e-8, coarse_maxit=2000)
+    # one Krylov iteration = one V-cycle + one operator application
+    t0 = time.perf_counter()
+    r = Fh
+    z = hier.vcycle(None, r)
+    matfree.condensed_op(o, z)
+    t_it = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    matfree.recover_interior(o, f, Fh)
+    t_post = time.perf_counter() - t0
+    return dict(t_pre=t_pre, t_iter=t_it, t_post=t_post, threads=threads,
+                coarse_iters=hier.coarse_iters[-1] if hier.coarse_iters else 0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2a")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the solver is a single-GPU build; see the sharding notes in the design document)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1808_03595_amd as pmg
+    import synth
+
+    dev = torch.device("cuda:0")
+    wl = workload(args.workload)
+    n, p = wl["n"], wl["p"]
+    g = pmg.create_mesh(n[0], n[1], n[2], p, wl["lam"], wl["alpha"])
+    g.set_cycle(0, 1e-8, 2000)
+    u_ex, f = make_rhs(g, wl, torch, synth, dev)
+    u = torch.zeros_like(f)
+    ndof = n[0] * n[1] * n[2] * p ** 3
+
+    def run(dtype, steps, warm):
+        for _ in range(warm):
+            g.pcg_solve(f, u, 1e-10, 200, dtype)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = None
+        for _ in range(steps):
+            st = g.pcg_solve(f, u, 1e-10, 200, dtype)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        err = (torch.linalg.vector_norm(u - u_ex) / torch.linalg.vector_norm(u_ex)).item()
+        return dt / steps, st, err
+
+    log(f"[bench] workload {args.workload}: n={n} p={p} ndof={ndof}")
+    t64, st64, err64 = run(pmg.F64, args.steps, args.warmup)
+    log(f"[bench] fp64: {t64*1e3:.2f} ms/solve iters={st64.iters} rel_res={st64.rel_res:.2e} "
+        f"coarse_iters={st64.coarse_iters} err_vs_exact={err64:.2e}")
+    t32, st32, err32 = run(pmg.F32, args.steps, args.warmup)
+    log(f"[bench] mixed: {t32*1e3:.2f} ms/solve iters={st32.iters} rel_res={st32.rel_res:.2e} "
+        f"coarse_iters={st32.coarse_iters} err_vs_exact={err32:.2e}")
+
+    ts64 = time_smoother(g, torch, dev, pmg.F64)
+    ts32 = time_smoother(g, torch, dev, pmg.F32)
+    fl = smoother_flops(n, p)
+    ach32 = fl / ts32 / 1e12
+    ach64 = fl / ts64 / 1e12
+    log(f"[bench] smoother f64 {ts64*1e6:.1f} us ({ach64:.2f} TF/s), f32 {ts32*1e6:.1f} us ({ach32:.2f} TF/s)")
+
+    cpu = None
+    if not args.no_cpu:
+        c = cpu_baseline(wl)
+        iters = st64.iters
+        t_cpu = c["t_pre"] + iters * c["t_iter"] + c["t_post"]
+        cpu = {"value": ndof / t_cpu, "unit": "unknowns/s", "cores": c["threads"], "kind": "oracle",
+               "sample": (f"FP64 oracle on the full workload: condensation + one ipCG iteration "
+                          f"(V-cycle + operator) + recovery, timed once each and scaled to "
+                          f"{iters} iterations")}
+        log(f"[bench] cpu oracle: pre {c['t_pre']:.2f}s iter {c['t_iter']:.2f}s post {c['t_post']:.2f}s")
+
+    value = ndof / t32
+    line = {
+        "metric": "solved unknowns/s to 1e-10 residual vs p; FP32-MG+learned vs plain FP64",
+        "value": value,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-vcycle/f64-cg",
+        "data": "synthetic",
+        "config": {"workload": f"{n[0]}x{n[1]}x{n[2]} elements, p={p}, lambda={wl['lam']:g}, "
+                               f"stretch alpha={wl['alpha']:.4f} (AR {wl['alpha']**(n[0]-1):.1f}), "
+                               f"8 sine modes seed {wl['seed']}",
+                   "ndof": ndof, "iters": st32.iters, "rel_res": st32.rel_res,
+                   "damping": "omega=1 (paper)",
+                   "fp64_unknowns_per_s": ndof / t64, "fp64_iters": st64.iters,
+                   "fp64_ms_per_solve": t64 * 1e3,
+                   "rel_err_vs_exact_mixed": err32, "rel_err_vs_exact_fp64": err64},
+        "roofline": {"bound": "alu", "kernel": "k_smoother<float>",
+                     "achieved": ach32, "peak": PEAK["f32"], "unit": "TFLOP/s",
+                     "frac": ach32 / PEAK["f32"], "traffic": None,
+                     "fp64": {"achieved": ach64, "peak": PEAK["f64"], "frac": ach64 / PEAK["f64"]}},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * pmg.h -- C ABI of the MI355X p-multigrid solver for the statically
+ * condensed spectral-element Helmholtz problem
+ *
+ *        lambda u - Laplace(u) = f   on a box,  u = 0 on the boundary,
+ *
+ * after Huismann, Stiller & Froehlich, "Scaling to the stars -- a linearly
+ * scaling elliptic solver for p-multigrid" (arXiv 1808.03595).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Return value: 0 on success; negative on error (PMG_EINVAL -1 invalid
+ *    argument, PMG_EHIP -2 HIP runtime error, PMG_ENOMEM -3 device memory,
+ *    PMG_EUNSUP -4 unsupported size); positive values are solver states
+ *    (PMG_NOT_CONVERGED 1, PMG_BREAKDOWN 2).  pmg_last_error() returns a
+ *    thread-local message for the last failing call.
+ *  - Pointers named d_* are DEVICE pointers owned by the caller and only
+ *    borrowed for the call.  Pointers named h_* are host pointers.
+ *  - "stream" is a hipStream_t passed as void*; NULL is the default stream.
+ *    All calls are stream-ordered and asynchronous unless stated otherwise.
+ *  - A mesh handle is not thread-safe; use it from one stream at a time.
+ *  - Node grids ("grid" arrays) are the global GLL node grids of the finest
+ *    level, shape (N3, N2, N1) with N_d = n_d p + 1, x1 fastest, FP64.
+ *  - Condensed vectors ("skeleton" arrays) hold the element-boundary
+ *    unknowns of one multigrid level in the library's plane layout: for each
+ *    direction d the planes normal to x_d at the element boundaries, each a
+ *    2D row-major array over the two other global node indices.  Every
+ *    unknown is stored exactly once (edges and vertices in the first plane
+ *    family that contains them); all other slots, and Dirichlet nodes, hold
+ *    0.  Hence plain sums over a skeleton array are sums over the unknowns.
+ *    Its length is pmg_skeleton_len(); the element type is FP64 (dtype
+ *    PMG_F64) or FP32 (PMG_F32) as the call states.
+ */
+#ifndef PMG_H
+#define PMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pmg_mesh pmg_mesh;
+
+enum { PMG_F64 = 0, PMG_F32 = 1 };
+enum { PMG_OK = 0, PMG_EINVAL = -1, PMG_EHIP = -2, PMG_ENOMEM = -3,
+       PMG_EUNSUP = -4, PMG_NOT_CONVERGED = 1, PMG_BREAKDOWN = 2 };
+enum { PMG_MAX_DEGREE = 32, PMG_MAX_HIST = 512 };
+
+typedef struct {
+    int iters;                    /* outer iterations performed            */
+    int status;                   /* 0, PMG_NOT_CONVERGED or PMG_BREAKDOWN */
+    double res0;                  /* |r_0|_2 over the condensed unknowns   */
+    double rel_res;               /* |r_k|_2 / |r_0|_2 (recursive residual) */
+    double res_hist[PMG_MAX_HIST];/* |r_k|_2, k = 0..iters                 */
+    int coarse_iters;             /* coarse CG iterations, summed          */
+    double t_pre_ms, t_iter_ms, t_post_ms; /* stream-event timings         */
+} pmg_stats;
+
+/* Mesh of n1 x n2 x n3 cuboid elements on the unit cube, degree p, Helmholtz
+ * parameter lambda >= 0.  stretch = alpha >= 1 grades the element widths
+ * geometrically in every direction, h_{k+1} = alpha h_k (the stretched
+ * meshes of Sec. 5.4); alpha = 1 is uniform.  Builds the p-multigrid levels
+ * p_l = 2^(l+1) (l < L), p_L = p (Sec. 4.1) and all device tables.
+ * 1 <= p <= PMG_MAX_DEGREE, n_d >= 1.  *out receives the handle. */
+int pmg_create_mesh(int n1, int n2, int n3, int p, double lambda,
+                    double stretch, pmg_mesh **out);
+
+/* As pmg_create_mesh with explicit element widths (host arrays of n1, n2,
+ * n3 positive values), e.g. the anisotropic brick meshes of Sec. 5.3. */
+int pmg_create_mesh_widths(int n1, int n2, int n3, int p, double lambda,
+                           const double *h_hx, const double *h_hy,
+                           const double *h_hz, pmg_mesh **out);
+
+void pmg_destroy_mesh(pmg_mesh *m);
+
+/* Number of coarsenings L (levels 0..L) and the degree of a level. */
+int pmg_num_levels(const pmg_mesh *m, int *L);
+int pmg_level_degree(const pmg_mesh *m, int level, int *p);
+
+/* Length (elements) of a skeleton array of a level; grid length N1 N2 N3. */
+int pmg_skeleton_len(const pmg_mesh *m, int level, int64_t *len);
+int pmg_grid_len(const pmg_mesh *m, int64_t *len);
+
+/* Global 1D node coordinates of the finest level (host arrays of N_d). */
+int pmg_grid_coords(const pmg_mesh *m, double *h_x1, double *h_x2,
+                    double *h_x3);
+
+/* Layout conversion at a level whose degree divides the finest grid is not
+ * needed: these act on the finest level only.  grid_to_skeleton copies the
+ * free element-boundary nodes of d_grid (FP64) into d_skel (dtype);
+ * skeleton_to_grid writes them back and sets all other grid nodes to 0. */
+int pmg_grid_to_skeleton(pmg_mesh *m, int dtype, const double *d_grid,
+                         void *d_skel, void *stream);
+int pmg_skeleton_to_grid(pmg_mesh *m, int dtype, const void *d_skel,
+                         double *d_grid, void *stream);
+
+/* y = Hhat_l u: the statically condensed Helmholtz operator of level l,
+ * H_BB - H_BI H_II^-1 H_IB assembled over elements (Sec. 2.2), applied
+ * matrix-free with O(p^3) work per element.  d_u, d_y: skeleton arrays of
+ * the level (dtype); they must not alias. */
+int pmg_apply_condensed_op(pmg_mesh *m, int level, int dtype, const void *d_u,
+                           void *d_y, void *stream);
+
+/* du = omega * Smoother_l(r): the additive Schwarz star smoother of Alg. 2
+ * with the star inverse of Alg. 1 and the degree-7 weight functions of
+ * Sec. 3.3; omega = 1 is the paper's method.  d_r, d_du: skeleton arrays of
+ * the level (dtype), not aliasing.  d_du is overwritten. */
+int pmg_schwarz_smooth(pmg_mesh *m, int level, int dtype, const void *d_r,
+                       void *d_du, double omega, void *stream);
+
+/* Grid transfers between level l-1 and l (Sec. 4.1): prolongation
+ * d_fine += J_l d_coarse (embedded tensor interpolation restricted to the
+ * condensed unknowns) and restriction d_coarse = J_l^T d_fine. */
+int pmg_prolong_add(pmg_mesh *m, int level, int dtype, const void *d_coarse,
+                    void *d_fine, void *stream);
+int pmg_restrict(pmg_mesh *m, int level, int dtype, const void *d_fine,
+                 void *d_coarse, void *stream);
+
+/* Cycle parameters: nu_mode 0 = one pre- and one post-smoothing step per
+ * level ("kMG"), 1 = 2^(L-l) steps on level l ("kvMG") (Sec. 4.1).  The
+ * coarse problem (p_0 = 2) is solved by Jacobi-preconditioned CG to the
+ * relative tolerance coarse_rtol (D^-1-weighted residual norm) or
+ * coarse_maxit iterations; coarse_rtol = 0 runs exactly coarse_maxit. */
+int pmg_set_cycle(pmg_mesh *m, int nu_mode, double coarse_rtol,
+                  int coarse_maxit);
+
+/* Per-level damping of the smoother correction, u_l += omega_l S_l(r_l).
+ * h_omega[j] applies to level L - j (j = 0 is the finest); n <= L values;
+ * NULL or n = 0 restores omega = 1 (the paper's method). */
+int pmg_set_damping(pmg_mesh *m, const float *h_omega, int n);
+
+/* z = MultigridCycle(0, r) of Alg. 3 on the finest level.  dtype PMG_F64
+ * runs the cycle in FP64.  dtype PMG_F32 expects FP32 skeleton arrays and
+ * runs the smoother, operator and transfers in FP32 while the coarse solve
+ * stays FP64. */
+int pmg_vcycle(pmg_mesh *m, int dtype, const void *d_r, void *d_z,
+               void *stream);
+
+/* Coarse-level solve Hhat_0 u_0 = F_0 (FP64 skeleton arrays of level 0)
+ * with the configured Jacobi-CG; *h_iters (may be NULL) receives the
+ * iteration count.  Synchronizes the stream. */
+int pmg_coarse_solve(pmg_mesh *m, const double *d_F0, double *d_u0,
+                     int *h_iters, void *stream);
+
+/* Static condensation of the right-hand side (Alg. 4, first step):
+ * Fhat = F_B - H_BI H_II^-1 F_I with F = M f (GLL-lumped mass).  d_f: grid
+ * (FP64); d_Fhat: finest skeleton (FP64). */
+int pmg_condense_rhs(pmg_mesh *m, const double *d_f, double *d_Fhat,
+                     void *stream);
+
+/* Interior recovery (Alg. 4, last step): u = (uhat, H_II^-1 (F_I - H_IB
+ * uhat)) written to the full grid d_u (Dirichlet nodes 0). */
+int pmg_recover_interior(pmg_mesh *m, const double *d_f, const double *d_uhat,
+                         double *d_u, void *stream);
+
+/* Whole solve of Alg. 5 (Krylov-accelerated MG, inexact preconditioned
+ * CG): condense, iterate until |r| <= rtol |r_0| or maxit, recover.
+ * precond_dtype PMG_F32 uses the mixed-precision cycle (FP32 V-cycle on
+ * r/|r| inside FP64 CG; FP64 residuals, dots and coarse solve).  d_f, d_u:
+ * grids (FP64).  Synchronizes the stream before filling *h_stats (may be
+ * NULL).  Returns 0, PMG_NOT_CONVERGED or PMG_BREAKDOWN, or an error. */
+int pmg_pcg_solve(pmg_mesh *m, const double *d_f, double *d_u, double rtol,
+                  int maxit, int precond_dtype, pmg_stats *h_stats,
+                  void *stream);
+
+/* Alg. 4: fixed-point iteration of V-cycles (FP64), same contract as
+ * pmg_pcg_solve; used to measure convergence rates. */
+int pmg_mg_solve(pmg_mesh *m, const double *d_f, double *d_u, double rtol,
+                 int maxit, pmg_stats *h_stats, void *stream);
+
+/* ---- learned damping: FP32 MLP 3 -> 64 -> 64 -> nout ------------------
+ * Parameter vector (nparams = 64*3+64 + 64*64+64 + nout*64+nout floats):
+ * W1[64][3], b1[64], W2[64][64], b2[64], W3[nout][64], b3[nout].
+ * Forward: h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2),
+ * y = 2 sigmoid(W3 h2 + b3).  d_x: [batch][3], d_y: [batch][nout],
+ * d_cache: [batch][128 + nout] activations kept for the backward pass. */
+int pmg_mlp_nparams(int nout);
+int pmg_mlp_forward(const float *d_params, const float *d_x, float *d_y,
+                    float *d_cache, int batch, int nout, void *stream);
+/* Masked mean-squared error: loss = sum mask (y - t)^2 / sum mask, written
+ * to d_loss[0]; d_dy = d loss / d y.  d_mask holds 0/1 per output. */
+int pmg_mlp_loss(const float *d_y, const float *d_t, const float *d_mask,
+                 float *d_dy, float *d_loss, int batch, int nout,
+                 void *stream);
+/* Gradient of sum_b dy . y(x_b) with respect to the parameters. */
+int pmg_mlp_backward(const float *d_params, const float *d_x,
+                     const float *d_cache, const float *d_dy,
+                     float *d_grad, int batch, int nout, void *stream);
+/* One Adam step (Kingma & Ba) at step t >= 1 on n parameters. */
+int pmg_mlp_adam(float *d_params, const float *d_grad, float *d_m,
+                 float *d_v, int n, float lr, float beta1, float beta2,
+                 float eps, int t, void *stream);
+
+const char *pmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMG_H */

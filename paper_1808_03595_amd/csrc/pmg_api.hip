@@ -1,0 +1,759 @@
+// C ABI of the condensed p-multigrid solver: mesh handle, level
+// hierarchy, V-cycle (Alg. 3), MG (Alg. 4) and ipCG (Alg. 5) orchestration.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#include "../../include/pmg.h"
+#include "pmg_kernels.h"
+
+using namespace pmg;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                      \
+    do {                                                                               \
+        hipError_t e_ = (x);                                                           \
+        if (e_ != hipSuccess) return fail(PMG_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+// scalar slots in device memory
+enum { SC_GAMMA = 0, SC_GAMMA0 = 1, SC_DELTA = 2, SC_QP = 3, SC_RR = 4, SC_RZ = 5, SC_PQ = 6, SC_RZN = 7,
+       SC_N = 16 };
+
+struct Level {
+    int p = 0, pc = 0;
+    Layout lay{};
+    LevelTabs<double> t64{};
+    LevelTabs<float> t32{};
+    // work vectors of this level
+    double *u64 = nullptr, *F64 = nullptr, *y64 = nullptr, *tb64 = nullptr;
+    float *u32 = nullptr, *F32 = nullptr, *y32 = nullptr, *tb32 = nullptr;
+};
+
+template <typename T> struct Sel;
+template <> struct Sel<double> {
+    static LevelTabs<double>& tabs(Level& l) { return l.t64; }
+    static double*& u(Level& l) { return l.u64; }
+    static double*& F(Level& l) { return l.F64; }
+    static double*& y(Level& l) { return l.y64; }
+    static double*& tb(Level& l) { return l.tb64; }
+};
+template <> struct Sel<float> {
+    static LevelTabs<float>& tabs(Level& l) { return l.t32; }
+    static float*& u(Level& l) { return l.u32; }
+    static float*& F(Level& l) { return l.F32; }
+    static float*& y(Level& l) { return l.y32; }
+    static float*& tb(Level& l) { return l.tb32; }
+};
+
+}  // namespace
+
+struct pmg_mesh {
+    int n[3] = {0, 0, 0};
+    int p = 0;
+    double lam = 0.0;
+    std::vector<double> h[3];
+    int L = 0;
+    std::vector<Level> lv;
+    int nu_mode = 0;
+    double coarse_rtol = 1e-8;
+    int coarse_maxit = 2000;
+    std::vector<double> omega;  // per level index l
+    // coarse CG
+    double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr, *cdiag = nullptr;
+    int coarse_last = 0;
+    long coarse_total = 0;
+    // finest-level solver vectors (FP64) and mixed-precision buffers
+    double *w_u = nullptr, *w_r = nullptr, *w_s = nullptr, *w_p = nullptr, *w_q = nullptr, *w_z = nullptr,
+           *w_F = nullptr;
+    float *w_r32 = nullptr, *w_z32 = nullptr;
+    double* m1d[3] = {nullptr, nullptr, nullptr};
+    double* partials = nullptr;
+    unsigned* counter = nullptr;
+    double* scal = nullptr;
+    double* hscal = nullptr;  // pinned host copy of the scalars
+    std::vector<void*> allocs;
+
+    template <typename T>
+    int alloc(T** ptr, size_t count) {
+        void* q = nullptr;
+        size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        hipError_t e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) return fail(PMG_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        allocs.push_back(q);
+        *ptr = static_cast<T*>(q);
+        return 0;
+    }
+    template <typename T>
+    int upload(const T** dst, const std::vector<double>& src) {
+        T* d = nullptr;
+        int rc = alloc(&d, src.size());
+        if (rc) return rc;
+        std::vector<T> tmp(src.begin(), src.end());
+        if (!tmp.empty()) {
+            hipError_t e = hipMemcpy(d, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return fail(PMG_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+        }
+        *dst = d;
+        return 0;
+    }
+};
+
+namespace {
+
+std::vector<int> level_degrees(int p) {
+    std::vector<int> d;
+    if (p <= 2) {
+        d.push_back(p);
+        return d;
+    }
+    d.push_back(2);
+    while (d.back() * 2 < p) d.push_back(d.back() * 2);
+    d.push_back(p);
+    return d;
+}
+
+template <typename T>
+int fill_tabs(pmg_mesh* m, LevelTabs<T>& tb, const HostTables& t, const Layout& lay, int pc) {
+    tb.lay = lay;
+    tb.lam = (T)m->lam;
+    tb.pc = pc;
+    int rc = 0;
+    for (int d = 0; d < 3 && !rc; ++d) {
+        if ((rc = m->upload(&tb.el_m[d], t.el_m[d]))) break;
+        if ((rc = m->upload(&tb.el_L[d], t.el_L[d]))) break;
+        if ((rc = m->upload(&tb.el_Sinv[d], t.el_Sinv[d]))) break;
+        if ((rc = m->upload(&tb.el_MS[d], t.el_MS[d]))) break;
+        if ((rc = m->upload(&tb.el_lam[d], t.el_lam[d]))) break;
+        if ((rc = m->upload(&tb.el_c0[d], t.el_c0[d]))) break;
+        if ((rc = m->upload(&tb.el_cp[d], t.el_cp[d]))) break;
+        if ((rc = m->upload(&tb.st_S[d], t.st_S[d]))) break;
+        if ((rc = m->upload(&tb.st_lam[d], t.st_lam[d]))) break;
+    }
+    if (!rc) rc = m->upload(&tb.st_w, t.st_w);
+    if (!rc) rc = m->upload(&tb.J, t.J);
+    return rc;
+}
+
+const size_t kMaxLds = 160 * 1024;
+
+int check_lds(int p) {
+    size_t a = smem_condensed_op<double>(p), b = smem_smoother<double>(p);
+    int q = p - 1, n1 = p + 1;
+    size_t c = sizeof(double) * (size_t)(2 * q * q * q + 18 * q * q);
+    size_t r = sizeof(double) * (size_t)(6 * n1 * n1 + 2 * q * q * q + 12 * q * q);
+    size_t mx = std::max(std::max(a, b), std::max(c, r));
+    if (mx > kMaxLds)
+        return fail(PMG_EUNSUP, "degree " + std::to_string(p) + " needs " + std::to_string(mx) +
+                                    " bytes of LDS per workgroup (limit 160 KiB)");
+    return 0;
+}
+
+int build_mesh(pmg_mesh* m) {
+    auto degs = level_degrees(m->p);
+    m->L = (int)degs.size() - 1;
+    m->lv.resize(degs.size());
+    m->omega.assign(degs.size(), 1.0);
+    int rc = check_lds(m->p);
+    if (rc) return rc;
+    for (size_t l = 0; l < degs.size(); ++l) {
+        Level& L = m->lv[l];
+        L.p = degs[l];
+        L.pc = l ? degs[l - 1] : 0;
+        L.lay = make_layout(m->n[0], m->n[1], m->n[2], L.p);
+        HostTables t;
+        build_level_tables(L.p, L.pc, m->h, t);
+        if ((rc = fill_tabs(m, L.t64, t, L.lay, L.pc))) return rc;
+        if ((rc = fill_tabs(m, L.t32, t, L.lay, L.pc))) return rc;
+        int64_t n = L.lay.len;
+        if ((rc = m->alloc(&L.u64, n)) || (rc = m->alloc(&L.F64, n)) || (rc = m->alloc(&L.y64, n)) ||
+            (rc = m->alloc(&L.u32, n)) || (rc = m->alloc(&L.F32, n)) || (rc = m->alloc(&L.y32, n)))
+            return rc;
+        if (l > 0) {
+            int64_t nc = m->lv[l - 1].lay.len;
+            if ((rc = m->alloc(&L.tb64, nc)) || (rc = m->alloc(&L.tb32, nc))) return rc;
+        }
+    }
+    // coarse CG workspace and Jacobi diagonal (FP64)
+    const Layout& L0 = m->lv[0].lay;
+    int64_t n0 = L0.len;
+    if ((rc = m->alloc(&m->cx, n0)) || (rc = m->alloc(&m->cr, n0)) || (rc = m->alloc(&m->cz, n0)) ||
+        (rc = m->alloc(&m->cp, n0)) || (rc = m->alloc(&m->cq, n0)))
+        return rc;
+    {
+        std::vector<double> dg;
+        coarse_diagonal(L0, m->lam, m->h, dg);
+        const double* d = nullptr;
+        if ((rc = m->upload(&d, dg))) return rc;
+        m->cdiag = const_cast<double*>(d);
+    }
+    const Layout& Lf = m->lv.back().lay;
+    int64_t nf = Lf.len;
+    if ((rc = m->alloc(&m->w_u, nf)) || (rc = m->alloc(&m->w_r, nf)) || (rc = m->alloc(&m->w_s, nf)) ||
+        (rc = m->alloc(&m->w_p, nf)) || (rc = m->alloc(&m->w_q, nf)) || (rc = m->alloc(&m->w_z, nf)) ||
+        (rc = m->alloc(&m->w_F, nf)) || (rc = m->alloc(&m->w_r32, nf)) || (rc = m->alloc(&m->w_z32, nf)))
+        return rc;
+    // assembled 1D GLL mass of the finest level
+    {
+        std::vector<double> x, w;
+        gll_nodes_weights(m->p, x, w);
+        for (int d = 0; d < 3; ++d) {
+            std::vector<double> ma(Lf.N[d], 0.0);
+            for (int e = 0; e < m->n[d]; ++e)
+                for (int i = 0; i <= m->p; ++i) ma[e * m->p + i] += 0.5 * m->h[d][e] * w[i];
+            const double* dd = nullptr;
+            if ((rc = m->upload(&dd, ma))) return rc;
+            m->m1d[d] = const_cast<double*>(dd);
+        }
+    }
+    if ((rc = m->alloc(&m->partials, 2 * REDUCE_BLOCKS)) || (rc = m->alloc(&m->counter, 4)) ||
+        (rc = m->alloc(&m->scal, SC_N)))
+        return rc;
+    HIPCHK(hipMemset(m->counter, 0, 4 * sizeof(unsigned)));
+    HIPCHK(hipMemset(m->scal, 0, SC_N * sizeof(double)));
+    HIPCHK(hipHostMalloc((void**)&m->hscal, SC_N * sizeof(double), hipHostMallocDefault));
+    // large dynamic LDS for the element / star kernels
+    HIPCHK(init_kernel_attributes());
+    HIPCHK(hipDeviceSynchronize());
+    return 0;
+}
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int read_scalars(pmg_mesh* m, hipStream_t st) {
+    HIPCHK(hipMemcpyAsync(m->hscal, m->scal, SC_N * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+}
+
+template <typename T>
+void residual(pmg_mesh* m, int l, const T* F, const T* u, T* y, hipStream_t st) {
+    Level& L = m->lv[l];
+    launch_condensed_op<T>(Sel<T>::tabs(L), u, y, st);
+    launch_sub_from<T>(F, y, L.lay.len, st);
+}
+
+// Jacobi-preconditioned CG on level 0 (FP64), x = 0 initially.
+int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st) {
+    Level& L0 = m->lv[0];
+    const int64_t n = L0.lay.len;
+    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), st));
+    HIPCHK(hipMemcpyAsync(m->cr, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_jacobi(m->cr, m->cdiag, m->cz, n, m->partials, m->counter, m->scal + SC_RZ, st);
+    HIPCHK(hipMemcpyAsync(m->cp, m->cz, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    int rc = read_scalars(m, st);
+    if (rc) return rc;
+    const double rz0 = m->hscal[SC_RZ];
+    double rz = rz0;
+    const double tol2 = m->coarse_rtol * m->coarse_rtol;
+    int it = 0;
+    while (it < m->coarse_maxit) {
+        if (rz <= tol2 * rz0 || rz == 0.0) break;
+        launch_condensed_op<double>(L0.t64, m->cp, m->cq, st);
+        launch_dot2<double>(m->cp, m->cq, nullptr, n, m->partials, m->counter, m->scal + SC_PQ, st);
+        // sc layout for cg_xr: [rz, pq] -> SC_RZ, SC_RZ+1 must be adjacent: copy pq next to rz
+        launch_cg_xr(x, m->cr, m->cp, m->cq, m->scal + SC_RZ, n, st);
+        launch_jacobi(m->cr, m->cdiag, m->cz, n, m->partials, m->counter, m->scal + SC_RZN, st);
+        launch_cg_p(m->cp, m->cz, m->scal + SC_RZN, m->scal + SC_RZ, n, st);
+        HIPCHK(hipMemcpyAsync(m->scal + SC_RZ, m->scal + SC_RZN, sizeof(double), hipMemcpyDeviceToDevice, st));
+        ++it;
+        if ((rc = read_scalars(m, st))) return rc;
+        rz = m->hscal[SC_RZ];
+    }
+    m->coarse_last = it;
+    m->coarse_total += it;
+    return 0;
+}
+
+// Alg. 3 with u_L = z (zero on entry unless `nonzero_u`) and F_L = r.
+template <typename T>
+int vcycle_impl(pmg_mesh* m, const T* r, T* z, bool nonzero_u, hipStream_t st) {
+    const int L = m->L;
+    std::vector<T*> u(L + 1);
+    std::vector<const T*> F(L + 1);
+    u[L] = z;
+    F[L] = r;
+    if (!nonzero_u) HIPCHK(hipMemsetAsync(z, 0, m->lv[L].lay.len * sizeof(T), st));
+    for (int l = L; l >= 1; --l) {
+        Level& lv = m->lv[l];
+        const int nu = m->nu_mode == 0 ? 1 : (1 << (L - l));
+        if (l != L) {
+            u[l] = Sel<T>::u(lv);
+            HIPCHK(hipMemsetAsync(u[l], 0, lv.lay.len * sizeof(T), st));
+        }
+        bool zero = (l != L) || !nonzero_u;
+        T* y = Sel<T>::y(lv);
+        for (int i = 0; i < nu; ++i) {
+            const T* res = F[l];
+            if (!zero) {
+                residual<T>(m, l, F[l], u[l], y, st);
+                res = y;
+            }
+            launch_smoother_add<T>(Sel<T>::tabs(lv), res, u[l], (T)m->omega[l], st);
+            zero = false;
+        }
+        residual<T>(m, l, F[l], u[l], y, st);
+        Level& lc = m->lv[l - 1];
+        T* Fc = Sel<T>::F(lc);
+        launch_restrict<T>(lv.lay, lc.lay, Sel<T>::tabs(lv).J, y, Fc, Sel<T>::tb(lv), st);
+        F[l - 1] = Fc;
+    }
+    // coarse solve in FP64
+    Level& l0 = m->lv[0];
+    if (L == 0) {
+        // the whole problem is the coarse problem
+        if (std::is_same<T, double>::value) return coarse_cg(m, reinterpret_cast<const double*>(r),
+                                                             reinterpret_cast<double*>(z), st);
+        launch_cast_scale<T, double>(r, l0.F64, nullptr, 0, l0.lay.len, st);
+        int rc = coarse_cg(m, l0.F64, l0.u64, st);
+        if (rc) return rc;
+        launch_cast_scale<double, T>(l0.u64, z, nullptr, 0, l0.lay.len, st);
+        return 0;
+    }
+    {
+        const double* b;
+        if (std::is_same<T, double>::value) b = reinterpret_cast<const double*>(F[0]);
+        else {
+            launch_cast_scale<T, double>(F[0], l0.F64, nullptr, 0, l0.lay.len, st);
+            b = l0.F64;
+        }
+        int rc = coarse_cg(m, b, l0.u64, st);
+        if (rc) return rc;
+        if (std::is_same<T, double>::value) u[0] = reinterpret_cast<T*>(l0.u64);
+        else {
+            launch_cast_scale<double, T>(l0.u64, Sel<T>::u(l0), nullptr, 0, l0.lay.len, st);
+            u[0] = Sel<T>::u(l0);
+        }
+    }
+    for (int l = 1; l <= L; ++l) {
+        Level& lv = m->lv[l];
+        Level& lc = m->lv[l - 1];
+        const int nu = m->nu_mode == 0 ? 1 : (1 << (L - l));
+        launch_prolong_add<T>(lc.lay, lv.lay, Sel<T>::tabs(lv).J, u[l - 1], u[l], st);
+        T* y = Sel<T>::y(lv);
+        for (int i = 0; i < nu; ++i) {
+            residual<T>(m, l, F[l], u[l], y, st);
+            launch_smoother_add<T>(Sel<T>::tabs(lv), y, u[l], (T)m->omega[l], st);
+        }
+    }
+    return 0;
+}
+
+int check_mesh(const pmg_mesh* m) {
+    if (!m) return fail(PMG_EINVAL, "null mesh");
+    return 0;
+}
+
+int check_level(const pmg_mesh* m, int level) {
+    if (!m) return fail(PMG_EINVAL, "null mesh");
+    if (level < 0 || level > m->L) return fail(PMG_EINVAL, "level out of range");
+    return 0;
+}
+
+int create(int n1, int n2, int n3, int p, double lambda, const double* hx, const double* hy, const double* hz,
+           double stretch, pmg_mesh** out) {
+    if (!out) return fail(PMG_EINVAL, "out is null");
+    *out = nullptr;
+    if (n1 < 1 || n2 < 1 || n3 < 1) return fail(PMG_EINVAL, "element counts must be >= 1");
+    if (p < 1 || p > PMG_MAX_DEGREE) return fail(PMG_EINVAL, "degree out of range");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(PMG_EINVAL, "lambda must be finite and >= 0");
+    pmg_mesh* m = new (std::nothrow) pmg_mesh();
+    if (!m) return fail(PMG_ENOMEM, "host allocation");
+    m->n[0] = n1; m->n[1] = n2; m->n[2] = n3;
+    m->p = p;
+    m->lam = lambda;
+    const int nn[3] = {n1, n2, n3};
+    const double* hs[3] = {hx, hy, hz};
+    for (int d = 0; d < 3; ++d) {
+        m->h[d].resize(nn[d]);
+        if (hs[d]) {
+            for (int e = 0; e < nn[d]; ++e) {
+                if (!(hs[d][e] > 0.0) || !std::isfinite(hs[d][e])) {
+                    delete m;
+                    return fail(PMG_EINVAL, "element widths must be finite and > 0");
+                }
+                m->h[d][e] = hs[d][e];
+            }
+        } else {
+            double s = 0.0;
+            for (int e = 0; e < nn[d]; ++e) s += std::pow(stretch, e);
+            for (int e = 0; e < nn[d]; ++e) m->h[d][e] = std::pow(stretch, e) / s;
+        }
+    }
+    int rc = build_mesh(m);
+    if (rc) {
+        pmg_destroy_mesh(m);
+        return rc;
+    }
+    *out = m;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pmg_last_error(void) { return g_err.c_str(); }
+
+int pmg_create_mesh(int n1, int n2, int n3, int p, double lambda, double stretch, pmg_mesh** out) {
+    if (!(stretch >= 1.0) || !std::isfinite(stretch)) return fail(PMG_EINVAL, "stretch must be >= 1");
+    return create(n1, n2, n3, p, lambda, nullptr, nullptr, nullptr, stretch, out);
+}
+
+int pmg_create_mesh_widths(int n1, int n2, int n3, int p, double lambda, const double* hx, const double* hy,
+                           const double* hz, pmg_mesh** out) {
+    if (!hx || !hy || !hz) return fail(PMG_EINVAL, "width arrays must not be null");
+    return create(n1, n2, n3, p, lambda, hx, hy, hz, 1.0, out);
+}
+
+void pmg_destroy_mesh(pmg_mesh* m) {
+    if (!m) return;
+    hipDeviceSynchronize();
+    for (void* q : m->allocs) hipFree(q);
+    if (m->hscal) hipHostFree(m->hscal);
+    delete m;
+}
+
+int pmg_num_levels(const pmg_mesh* m, int* L) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (!L) return fail(PMG_EINVAL, "null output");
+    *L = m->L;
+    return 0;
+}
+
+int pmg_level_degree(const pmg_mesh* m, int level, int* p) {
+    if (check_level(m, level)) return PMG_EINVAL;
+    if (!p) return fail(PMG_EINVAL, "null output");
+    *p = m->lv[level].p;
+    return 0;
+}
+
+int pmg_skeleton_len(const pmg_mesh* m, int level, int64_t* len) {
+    if (check_level(m, level)) return PMG_EINVAL;
+    if (!len) return fail(PMG_EINVAL, "null output");
+    *len = m->lv[level].lay.len;
+    return 0;
+}
+
+int pmg_grid_len(const pmg_mesh* m, int64_t* len) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (!len) return fail(PMG_EINVAL, "null output");
+    const Layout& L = m->lv.back().lay;
+    *len = (int64_t)L.N[0] * L.N[1] * L.N[2];
+    return 0;
+}
+
+int pmg_grid_coords(const pmg_mesh* m, double* x1, double* x2, double* x3) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (!x1 || !x2 || !x3) return fail(PMG_EINVAL, "null output");
+    std::vector<double> x, w;
+    gll_nodes_weights(m->p, x, w);
+    double* out[3] = {x1, x2, x3};
+    for (int d = 0; d < 3; ++d) {
+        double x0 = 0.0;
+        for (int e = 0; e < m->n[d]; ++e) {
+            for (int i = 0; i < m->p; ++i) out[d][e * m->p + i] = x0 + 0.5 * m->h[d][e] * (x[i] + 1.0);
+            x0 += m->h[d][e];
+        }
+        out[d][m->n[d] * m->p] = x0;
+    }
+    return 0;
+}
+
+int pmg_grid_to_skeleton(pmg_mesh* m, int dtype, const double* g, void* s, void* stream) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (!g || !s) return fail(PMG_EINVAL, "null pointer");
+    const Layout& L = m->lv.back().lay;
+    if (dtype == PMG_F64) launch_grid_to_skel<double>(L, g, (double*)s, S(stream));
+    else if (dtype == PMG_F32) launch_grid_to_skel<float>(L, g, (float*)s, S(stream));
+    else return fail(PMG_EINVAL, "bad dtype");
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int pmg_skeleton_to_grid(pmg_mesh* m, int dtype, const void* s, double* g, void* stream) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (!g || !s) return fail(PMG_EINVAL, "null pointer");
+    const Layout& L = m->lv.back().lay;
+    if (dtype == PMG_F64) launch_skel_to_grid<double>(L, (const double*)s, g, S(stream));
+    else if (dtype == PMG_F32) launch_skel_to_grid<float>(L, (const float*)s, g, S(stream));
+    else return fail(PMG_EINVAL, "bad dtype");
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int pmg_apply_condensed_op(pmg_mesh* m, int level, int dtype, const void* u, void* y, void* stream) {
+    if (check_level(m, level)) return PMG_EINVAL;
+    if (!u || !y || u == y) return fail(PMG_EINVAL, "null or aliasing pointers");
+    Level& L = m->lv[level];
+    if (dtype == PMG_F64) launch_condensed_op<double>(L.t64, (const double*)u, (double*)y, S(stream));
+    else if (dtype == PMG_F32) launch_condensed_op<float>(L.t32, (const float*)u, (float*)y, S(stream));
+    else return fail(PMG_EINVAL, "bad dtype");
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int pmg_schwarz_smooth(pmg_mesh* m, int level, int dtype, const void* r, void* du, double omega, void* stream) {
+    if (check_level(m, level)) return PMG_EINVAL;
+    if (!r || !du || r == du) return fail(PMG_EINVAL, "null or aliasing pointers");
+    Level& L = m->lv[level];
+    if (dtype == PMG_F64) {
+        HIPCHK(hipMemsetAsync(du, 0, L.lay.len * sizeof(double), S(stream)));
+        launch_smoother_add<double>(L.t64, (const double*)r, (double*)du, omega, S(stream));
+    } else if (dtype == PMG_F32) {
+        HIPCHK(hipMemsetAsync(du, 0, L.lay.len * sizeof(float), S(stream)));
+        launch_smoother_add<float>(L.t32, (const float*)r, (float*)du, (float)omega, S(stream));
+    } else return fail(PMG_EINVAL, "bad dtype");
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int pmg_prolong_add(pmg_mesh* m, int level, int dtype, const void* c, void* f, void* stream) {
+    if (check_level(m, level) || level < 1) return fail(PMG_EINVAL, "level must be 1..L");
+    if (!c || !f) return fail(PMG_EINVAL, "null pointer");
+    Level& lf = m->lv[level];
+    Level& lc = m->lv[level - 1];
+    if (dtype == PMG_F64) launch_prolong_add<double>(lc.lay, lf.lay, lf.t64.J, (const double*)c, (double*)f, S(stream));
+    else if (dtype == PMG_F32) launch_prolong_add<float>(lc.lay, lf.lay, lf.t32.J, (const float*)c, (float*)f, S(stream));
+    else return fail(PMG_EINVAL, "bad dtype");
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int pmg_restrict(pmg_mesh* m, int level, int dtype, const void* f, void* c, void* stream) {
+    if (check_level(m, level) || level < 1) return fail(PMG_EINVAL, "level must be 1..L");
+    if (!c || !f) return fail(PMG_EINVAL, "null pointer");
+    Level& lf = m->lv[level];
+    Level& lc = m->lv[level - 1];
+    if (dtype == PMG_F64)
+        launch_restrict<double>(lf.lay, lc.lay, lf.t64.J, (const double*)f, (double*)c, lf.tb64, S(stream));
+    else if (dtype == PMG_F32)
+        launch_restrict<float>(lf.lay, lc.lay, lf.t32.J, (const float*)f, (float*)c, lf.tb32, S(stream));
+    else return fail(PMG_EINVAL, "bad dtype");
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int pmg_set_cycle(pmg_mesh* m, int nu_mode, double coarse_rtol, int coarse_maxit) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (nu_mode != 0 && nu_mode != 1) return fail(PMG_EINVAL, "nu_mode must be 0 or 1");
+    if (!(coarse_rtol >= 0.0) || coarse_maxit < 0) return fail(PMG_EINVAL, "bad coarse parameters");
+    m->nu_mode = nu_mode;
+    m->coarse_rtol = coarse_rtol;
+    m->coarse_maxit = coarse_maxit;
+    return 0;
+}
+
+int pmg_set_damping(pmg_mesh* m, const float* om, int n) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (n < 0 || n > m->L || (n > 0 && !om)) return fail(PMG_EINVAL, "bad damping vector");
+    for (int l = 0; l <= m->L; ++l) m->omega[l] = 1.0;
+    for (int j = 0; j < n; ++j) {
+        if (!(om[j] > 0.0f) || !std::isfinite(om[j])) return fail(PMG_EINVAL, "damping must be > 0");
+        m->omega[m->L - j] = om[j];
+    }
+    return 0;
+}
+
+int pmg_vcycle(pmg_mesh* m, int dtype, const void* r, void* z, void* stream) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (!r || !z || r == z) return fail(PMG_EINVAL, "null or aliasing pointers");
+    int rc;
+    if (dtype == PMG_F64) rc = vcycle_impl<double>(m, (const double*)r, (double*)z, false, S(stream));
+    else if (dtype == PMG_F32) rc = vcycle_impl<float>(m, (const float*)r, (float*)z, false, S(stream));
+    else return fail(PMG_EINVAL, "bad dtype");
+    if (rc) return rc;
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int pmg_coarse_solve(pmg_mesh* m, const double* F0, double* u0, int* iters, void* stream) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (!F0 || !u0) return fail(PMG_EINVAL, "null pointer");
+    int rc = coarse_cg(m, F0, u0, S(stream));
+    if (rc) return rc;
+    if (iters) *iters = m->coarse_last;
+    return 0;
+}
+
+int pmg_condense_rhs(pmg_mesh* m, const double* f, double* Fh, void* stream) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (!f || !Fh) return fail(PMG_EINVAL, "null pointer");
+    launch_condense(m->lv.back().t64, m->m1d[0], m->m1d[1], m->m1d[2], f, Fh, S(stream));
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int pmg_recover_interior(pmg_mesh* m, const double* f, const double* uh, double* u, void* stream) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (!f || !uh || !u) return fail(PMG_EINVAL, "null pointer");
+    launch_recover(m->lv.back().t64, f, uh, u, S(stream));
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, int maxit, int mode, int pdt,
+                        pmg_stats* st_out, hipStream_t st) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (!f || !ug) return fail(PMG_EINVAL, "null pointer");
+    if (!(rtol >= 0.0) || maxit < 0) return fail(PMG_EINVAL, "bad tolerance or iteration limit");
+    if (pdt != PMG_F64 && pdt != PMG_F32) return fail(PMG_EINVAL, "bad dtype");
+    const Layout& Lf = m->lv.back().lay;
+    const int64_t n = Lf.len;
+    pmg_stats stats;
+    std::memset(&stats, 0, sizeof(stats));
+    m->coarse_total = 0;
+    hipEvent_t ev[4];
+    for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
+    HIPCHK(hipEventRecord(ev[0], st));
+    launch_condense(m->lv.back().t64, m->m1d[0], m->m1d[1], m->m1d[2], f, m->w_F, st);
+    HIPCHK(hipEventRecord(ev[1], st));
+    int rc = 0, status = 0;
+    // r = F, u = 0, s = r, p = 0, delta = 1
+    HIPCHK(hipMemsetAsync(m->w_u, 0, n * sizeof(double), st));
+    HIPCHK(hipMemcpyAsync(m->w_r, m->w_F, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(m->w_s, m->w_F, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemsetAsync(m->w_p, 0, n * sizeof(double), st));
+    {
+        double one = 1.0;
+        HIPCHK(hipMemcpyAsync(m->scal + SC_DELTA, &one, sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    launch_dot2<double>(m->w_r, m->w_r, nullptr, n, m->partials, m->counter, m->scal + SC_RR, st);
+    if ((rc = read_scalars(m, st))) return rc;
+    double rr0 = m->hscal[SC_RR], rr = rr0;
+    stats.res0 = std::sqrt(rr0);
+    stats.res_hist[0] = stats.res0;
+    const double eps = rtol * stats.res0;
+    int it = 0;
+    while (std::sqrt(rr) > eps && it < maxit) {
+        if (mode == 1) {
+            // Alg. 4: u <- MultigridCycle(u, F); r = F - H u
+            if (m->L == 0) {
+                // coarse CG on the whole problem applied to the residual
+                if ((rc = vcycle_impl<double>(m, m->w_r, m->w_z, false, st))) return rc;
+                launch_axpy<double>(1.0, m->w_z, m->w_u, n, st);
+            } else if ((rc = vcycle_impl<double>(m, m->w_F, m->w_u, true, st))) return rc;
+            residual<double>(m, m->L, m->w_F, m->w_u, m->w_r, st);
+            launch_dot2<double>(m->w_r, m->w_r, nullptr, n, m->partials, m->counter, m->scal + SC_RR, st);
+            if ((rc = read_scalars(m, st))) return rc;
+            rr = m->hscal[SC_RR];
+        } else {
+            // Alg. 5
+            if (pdt == PMG_F64) {
+                if ((rc = vcycle_impl<double>(m, m->w_r, m->w_z, false, st))) return rc;
+            } else {
+                double nr = std::sqrt(rr);
+                HIPCHK(hipMemcpyAsync(m->scal + SC_N - 1, &nr, sizeof(double), hipMemcpyHostToDevice, st));
+                launch_cast_scale<double, float>(m->w_r, m->w_r32, m->scal + SC_N - 1, 1, n, st);
+                if ((rc = vcycle_impl<float>(m, m->w_r32, m->w_z32, false, st))) return rc;
+                launch_cast_scale<float, double>(m->w_z32, m->w_z, m->scal + SC_N - 1, 0, n, st);
+            }
+            launch_dot2<double>(m->w_z, m->w_r, m->w_s, n, m->partials, m->counter, m->scal + SC_GAMMA, st);
+            launch_pcg_dir(m->w_p, m->w_z, m->scal, n, st);
+            HIPCHK(hipMemcpyAsync(m->scal + SC_DELTA, m->scal + SC_GAMMA, sizeof(double), hipMemcpyDeviceToDevice, st));
+            launch_condensed_op<double>(m->lv.back().t64, m->w_p, m->w_q, st);
+            launch_dot2<double>(m->w_q, m->w_p, nullptr, n, m->partials, m->counter, m->scal + SC_QP, st);
+            launch_pcg_update(m->w_u, m->w_r, m->w_s, m->w_p, m->w_q, m->scal + SC_GAMMA, m->scal + SC_QP, n,
+                              m->partials, m->counter, m->scal + SC_RR, st);
+            if ((rc = read_scalars(m, st))) return rc;
+            rr = m->hscal[SC_RR];
+            double qp = m->hscal[SC_QP];
+            if (!(qp > 0.0) || !std::isfinite(rr)) {
+                status = PMG_BREAKDOWN;
+                ++it;
+                if (it < PMG_MAX_HIST) stats.res_hist[it] = std::sqrt(rr);
+                break;
+            }
+        }
+        ++it;
+        if (it < PMG_MAX_HIST) stats.res_hist[it] = std::sqrt(rr);
+        if (!std::isfinite(rr)) {
+            status = PMG_BREAKDOWN;
+            break;
+        }
+    }
+    if (!status && std::sqrt(rr) > eps) status = PMG_NOT_CONVERGED;
+    HIPCHK(hipEventRecord(ev[2], st));
+    launch_recover(m->lv.back().t64, f, m->w_u, ug, st);
+    HIPCHK(hipEventRecord(ev[3], st));
+    HIPCHK(hipStreamSynchronize(st));
+    float t0 = 0, t1 = 0, t2 = 0;
+    hipEventElapsedTime(&t0, ev[0], ev[1]);
+    hipEventElapsedTime(&t1, ev[1], ev[2]);
+    hipEventElapsedTime(&t2, ev[2], ev[3]);
+    for (int i = 0; i < 4; ++i) hipEventDestroy(ev[i]);
+    stats.iters = it;
+    stats.status = status;
+    stats.rel_res = stats.res0 > 0 ? std::sqrt(rr) / stats.res0 : 0.0;
+    stats.coarse_iters = (int)m->coarse_total;
+    stats.t_pre_ms = t0;
+    stats.t_iter_ms = t1;
+    stats.t_post_ms = t2;
+    if (st_out) *st_out = stats;
+    HIPCHK(hipGetLastError());
+    return status;
+}
+
+int pmg_pcg_solve(pmg_mesh* m, const double* f, double* u, double rtol, int maxit, int pdt, pmg_stats* st,
+                  void* stream) {
+    return solve_common(m, f, u, rtol, maxit, 0, pdt, st, S(stream));
+}
+
+int pmg_mg_solve(pmg_mesh* m, const double* f, double* u, double rtol, int maxit, pmg_stats* st, void* stream) {
+    return solve_common(m, f, u, rtol, maxit, 1, PMG_F64, st, S(stream));
+}
+
+int pmg_mlp_nparams(int nout) { return 64 * 3 + 64 + 64 * 64 + 64 + nout * 64 + nout; }
+
+int pmg_mlp_forward(const float* prm, const float* x, float* y, float* cache, int batch, int nout, void* stream) {
+    if (!prm || !x || !y || !cache || batch < 0 || nout < 1) return fail(PMG_EINVAL, "bad MLP arguments");
+    if (batch == 0) return 0;
+    launch_mlp_forward(prm, x, y, cache, batch, nout, S(stream));
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int pmg_mlp_loss(const float* y, const float* t, const float* mask, float* dy, float* loss, int batch, int nout,
+                 void* stream) {
+    if (!y || !t || !mask || !dy || !loss || batch < 0 || nout < 1) return fail(PMG_EINVAL, "bad MLP arguments");
+    launch_mlp_loss(y, t, mask, dy, loss, batch * nout, S(stream));
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int pmg_mlp_backward(const float* prm, const float* x, const float* cache, const float* dy, float* grad, int batch,
+                     int nout, void* stream) {
+    if (!prm || !x || !cache || !dy || !grad || batch < 0 || nout < 1) return fail(PMG_EINVAL, "bad MLP arguments");
+    // per-sample deltas live in a scratch buffer sized like the cache
+    float* work = nullptr;
+    size_t bytes = (size_t)std::max(batch, 1) * (128 + nout) * sizeof(float);
+    HIPCHK(hipMallocAsync((void**)&work, bytes, S(stream)));
+    launch_mlp_backward(prm, x, cache, dy, work, grad, batch, nout, S(stream));
+    HIPCHK(hipFreeAsync(work, S(stream)));
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int pmg_mlp_adam(float* prm, const float* g, float* mm, float* vv, int n, float lr, float b1, float b2, float eps,
+                 int t, void* stream) {
+    if (!prm || !g || !mm || !vv || n < 0 || t < 1) return fail(PMG_EINVAL, "bad Adam arguments");
+    if (n == 0) return 0;
+    launch_mlp_adam(prm, g, mm, vv, n, lr, b1, b2, eps, t, S(stream));
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+}  // extern "C"

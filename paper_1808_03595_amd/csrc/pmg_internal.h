@@ -1,0 +1,91 @@
+// Internal declarations shared by the host set-up, the kernels and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+namespace pmg {
+
+// ---------------------------------------------------------------------------
+// Plane layout of a condensed (skeleton) vector on one level.
+//
+// Family d holds the planes normal to x_d at the element boundaries
+// i_d = j p, j = 0..n_d.  A family-0 plane is a row-major array [i3][i2], a
+// family-1 plane [i3][i1], a family-2 plane [i2][i1], rows padded to `pitch`.
+// Every condensed unknown is stored once: nodes with i1 % p == 0 live in
+// family 0, else nodes with i2 % p == 0 in family 1, else family 2.  All
+// other slots and the Dirichlet nodes are kept at zero.
+// ---------------------------------------------------------------------------
+struct Layout {
+    int p;
+    int n[3];
+    int N[3];            // n_d p + 1
+    int pitch[3];        // row pitch of family-d planes
+    int rows[3];         // rows per family-d plane
+    int64_t pstride[3];  // elements per family-d plane
+    int64_t off[3];      // start of family d
+    int64_t len;         // total length
+
+    // Storage slot of the skeleton node (i1, i2, i3); the caller guarantees
+    // that it is a skeleton node and states which of i_d are multiples of p.
+    __host__ __device__ inline int64_t slot(int i1, int i2, int i3, bool on1,
+                                            bool on2) const {
+        if (on1) return off[0] + (int64_t)(i1 / p) * pstride[0] + (int64_t)i3 * pitch[0] + i2;
+        if (on2) return off[1] + (int64_t)(i2 / p) * pstride[1] + (int64_t)i3 * pitch[1] + i1;
+        return off[2] + (int64_t)(i3 / p) * pstride[2] + (int64_t)i2 * pitch[2] + i1;
+    }
+    __host__ __device__ inline int64_t plane0(int j) const { return off[0] + (int64_t)j * pstride[0]; }
+    __host__ __device__ inline int64_t plane1(int j) const { return off[1] + (int64_t)j * pstride[1]; }
+    __host__ __device__ inline int64_t plane2(int j) const { return off[2] + (int64_t)j * pstride[2]; }
+};
+
+Layout make_layout(int n1, int n2, int n3, int p);
+
+// Device tables of one level, element type T.  Per-direction tables are
+// indexed by element index (el_*) or vertex index (st_*).
+template <typename T>
+struct LevelTabs {
+    Layout lay;
+    T lam;
+    // element tables, direction d, element e: offsets e * size
+    const T* el_m[3];     // (p+1)        diagonal mass
+    const T* el_L[3];     // (p+1)^2      stiffness, row-major
+    const T* el_Sinv[3];  // (p-1)^2      S^-1 = S^T M_I,  [k][i]
+    const T* el_MS[3];    // (p-1)^2      M_I S,           [i][k]
+    const T* el_lam[3];   // (p-1)        interior eigenvalues
+    const T* el_c0[3];    // (p-1)        S^T L[I,0]
+    const T* el_cp[3];    // (p-1)        S^T L[I,p]
+    // star tables, direction d, vertex v: offsets v * size
+    const T* st_S[3];     // nS^2         [i][k], identity padded
+    const T* st_lam[3];   // nS           padded eigenvalues = 1
+    const T* st_w;        // nS           1D weights
+    // interpolation from the next coarser level: (p+1) x (pc+1), row-major
+    const T* J;
+    int pc;
+};
+
+struct HostTables {
+    // per direction: concatenated element / star tables (FP64)
+    std::vector<double> el_m[3], el_L[3], el_Sinv[3], el_MS[3], el_lam[3],
+        el_c0[3], el_cp[3], st_S[3], st_lam[3];
+    std::vector<double> st_w, J;
+};
+
+// Host set-up (pmg_setup.cpp)
+void gll_nodes_weights(int p, std::vector<double>& x, std::vector<double>& w);
+void stiffness_std(int p, const std::vector<double>& x, const std::vector<double>& w,
+                   std::vector<double>& L);
+void sym_eig_jacobi(int n, std::vector<double>& A, std::vector<double>& Q,
+                    std::vector<double>& lam);
+void gen_eig_diag(int n, const double* L, const double* m, std::vector<double>& S,
+                  std::vector<double>& lam);
+void lagrange_interp(const std::vector<double>& xf, const std::vector<double>& xt,
+                     std::vector<double>& J);
+double smoothstep(int pw, double t);
+void build_level_tables(int p, int pc, const std::vector<double> h[3], HostTables& t);
+void coarse_diagonal(const Layout& lay, double lam, const std::vector<double> h[3],
+                     std::vector<double>& diag);
+
+}  // namespace pmg

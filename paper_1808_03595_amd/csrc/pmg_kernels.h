@@ -1,0 +1,52 @@
+// Kernel launchers (pmg_kernels.hip) used by the C ABI layer.
+#pragma once
+
+#include "pmg_internal.h"
+
+namespace pmg {
+
+constexpr int REDUCE_BLOCKS = 512;
+
+hipError_t init_kernel_attributes();
+
+template <typename T> void launch_grid_to_skel(const Layout&, const double*, T*, hipStream_t);
+template <typename T> void launch_skel_to_grid(const Layout&, const T*, double*, hipStream_t);
+template <typename T> void launch_condensed_op(const LevelTabs<T>&, const T*, T*, hipStream_t);
+template <typename T> void launch_smoother_add(const LevelTabs<T>&, const T*, T*, T, hipStream_t);
+template <typename T>
+void launch_prolong_add(const Layout& Lc, const Layout& Lf, const T* J, const T* uc, T* uf, hipStream_t);
+template <typename T>
+void launch_restrict(const Layout& Lf, const Layout& Lc, const T* J, const T* rf, T* rc, T* tbuf, hipStream_t);
+template <typename T>
+void launch_dot2(const T* x, const T* y, const T* z, int64_t n, double* partials, unsigned* counter,
+                 double* out, hipStream_t);
+template <typename T> void launch_sub_from(const T* x, T* y, int64_t n, hipStream_t);
+template <typename T> void launch_axpy(T a, const T* x, T* y, int64_t n, hipStream_t);
+template <typename T, typename U>
+void launch_cast_scale(const T* x, U* y, const double* sc, int invert, int64_t n, hipStream_t);
+template <typename T> size_t smem_condensed_op(int p);
+template <typename T> size_t smem_smoother(int p);
+
+void launch_condense(const LevelTabs<double>& tb, const double* m1, const double* m2, const double* m3,
+                     const double* f, double* Fh, hipStream_t);
+void launch_recover(const LevelTabs<double>& tb, const double* f, const double* uh, double* ug, hipStream_t);
+void launch_pcg_dir(double* p, const double* z, const double* sc, int64_t n, hipStream_t);
+void launch_pcg_update(double* u, double* r, double* s, const double* p, const double* q, const double* gam,
+                       const double* qp, int64_t n, double* partials, unsigned* counter, double* out,
+                       hipStream_t);
+void launch_jacobi(const double* r, const double* dg, double* z, int64_t n, double* partials,
+                   unsigned* counter, double* out, hipStream_t);
+void launch_cg_xr(double* x, double* r, const double* p, const double* q, const double* sc, int64_t n,
+                  hipStream_t);
+void launch_cg_p(double* p, const double* z, const double* rz_new, const double* rz_old, int64_t n,
+                 hipStream_t);
+void launch_mlp_forward(const float* prm, const float* x, float* y, float* cache, int batch, int nout,
+                        hipStream_t);
+void launch_mlp_loss(const float* y, const float* t, const float* m, float* dy, float* loss, int n,
+                     hipStream_t);
+void launch_mlp_backward(const float* prm, const float* x, const float* cache, const float* dy, float* work,
+                         float* g, int batch, int nout, hipStream_t);
+void launch_mlp_adam(float* prm, const float* g, float* m, float* v, int n, float lr, float b1, float b2,
+                     float eps, int t, hipStream_t);
+
+}  // namespace pmg

@@ -1,0 +1,1287 @@
+// HIP kernels of the condensed p-multigrid solver for gfx950 (CDNA4).
+//
+// One workgroup per element (condensed operator, condensation, recovery) or
+// per star (Schwarz smoother), LDS-resident face tiles, 1D tables read
+// through the L1/L2 caches.  Assembly into the plane layout uses eight
+// parity colours whose writes never overlap, so every result is
+// deterministic.  Templates on T in {double, float} give the FP64 path and
+// the FP32 preconditioner path from the same code.
+#include "pmg_kernels.h"
+
+namespace pmg {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ inline bool is_dir(const Layout& L, int i1, int i2, int i3) {
+    return i1 == 0 || i2 == 0 || i3 == 0 || i1 == L.N[0] - 1 || i2 == L.N[1] - 1 ||
+           i3 == L.N[2] - 1;
+}
+
+// Element (e1, e2, e3) of block b among the elements of parity `color`
+// (color < 0: all elements in lexicographic order).
+__device__ inline void color_coords(int b, int color, const int n[3], int c[3]) {
+    if (color < 0) {
+        c[0] = b % n[0];
+        b /= n[0];
+        c[1] = b % n[1];
+        c[2] = b / n[1];
+        return;
+    }
+    int p0 = color & 1, p1 = (color >> 1) & 1, p2 = (color >> 2) & 1;
+    int m0 = (n[0] - p0 + 1) / 2, m1 = (n[1] - p1 + 1) / 2;
+    c[0] = p0 + 2 * (b % m0);
+    b /= m0;
+    c[1] = p1 + 2 * (b % m1);
+    c[2] = p2 + 2 * (b / m1);
+}
+
+template <typename T>
+__device__ inline void add_out(T* y, int64_t s, T v) {
+    y[s] += v;
+}
+
+// ---------------------------------------------------------------------------
+// layout conversion
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_grid_to_skel(Layout L, const double* __restrict__ g, T* __restrict__ s) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.len) return;
+    int d = (i >= L.off[2]) ? 2 : (i >= L.off[1] ? 1 : 0);
+    int64_t loc = i - L.off[d];
+    int j = (int)(loc / L.pstride[d]);
+    int64_t rem = loc - (int64_t)j * L.pstride[d];
+    int r = (int)(rem / L.pitch[d]), c = (int)(rem - (int64_t)r * L.pitch[d]);
+    T v = 0;
+    int p = L.p;
+    if (r < L.rows[d]) {
+        int i1, i2, i3;
+        bool canon;
+        if (d == 0) { i1 = j * p; i3 = r; i2 = c; canon = c < L.N[1]; }
+        else if (d == 1) { i2 = j * p; i3 = r; i1 = c; canon = c < L.N[0] && (c % p) != 0; }
+        else { i3 = j * p; i2 = r; i1 = c; canon = c < L.N[0] && (c % p) != 0 && (r % p) != 0; }
+        if (canon && !is_dir(L, i1, i2, i3))
+            v = (T)g[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1];
+    }
+    s[i] = v;
+}
+
+template <typename T>
+__global__ void k_skel_to_grid(Layout L, const T* __restrict__ s, double* __restrict__ g) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t tot = (int64_t)L.N[0] * L.N[1] * L.N[2];
+    if (i >= tot) return;
+    int i1 = (int)(i % L.N[0]);
+    int64_t t = i / L.N[0];
+    int i2 = (int)(t % L.N[1]);
+    int i3 = (int)(t / L.N[1]);
+    int p = L.p;
+    bool on1 = i1 % p == 0, on2 = i2 % p == 0, on3 = i3 % p == 0;
+    double v = 0.0;
+    if ((on1 || on2 || on3) && !is_dir(L, i1, i2, i3)) v = (double)s[L.slot(i1, i2, i3, on1, on2)];
+    g[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// element face tiles.  Tile f = 2 d + s is the face normal to x_{d+1} at the
+// local coordinate s p; tile rows / columns: d=0 [a3][a2], d=1 [a3][a1],
+// d=2 [a2][a1].  The (p+1)^2 entries include edges and vertices.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline T shell_value(const T* tile, int p, int a1, int a2, int a3) {
+    const int n1 = p + 1, t2 = n1 * n1;
+    if (a1 == 0 || a1 == p) return tile[(a1 ? 1 : 0) * t2 + a3 * n1 + a2];
+    if (a2 == 0 || a2 == p) return tile[(2 + (a2 ? 1 : 0)) * t2 + a3 * n1 + a1];
+    if (a3 == 0 || a3 == p) return tile[(4 + (a3 ? 1 : 0)) * t2 + a2 * n1 + a1];
+    return (T)0;
+}
+
+// Storage slot of element-local shell node (a1, a2, a3) of element e.
+__device__ inline int64_t elem_slot(const Layout& L, const int e[3], int a1, int a2, int a3) {
+    const int p = L.p;
+    const int i1 = e[0] * p + a1, i2 = e[1] * p + a2, i3 = e[2] * p + a3;
+    if (a1 == 0 || a1 == p) return L.plane0(e[0] + (a1 ? 1 : 0)) + (int64_t)i3 * L.pitch[0] + i2;
+    if (a2 == 0 || a2 == p) return L.plane1(e[1] + (a2 ? 1 : 0)) + (int64_t)i3 * L.pitch[1] + i1;
+    return L.plane2(e[2] + (a3 ? 1 : 0)) + (int64_t)i2 * L.pitch[2] + i1;
+}
+
+// tile entry (f, r, c) -> element-local node
+__device__ inline void tile_node(int p, int f, int r, int c, int& a1, int& a2, int& a3) {
+    int d = f >> 1, s = (f & 1) ? p : 0;
+    if (d == 0) { a1 = s; a3 = r; a2 = c; }
+    else if (d == 1) { a2 = s; a3 = r; a1 = c; }
+    else { a3 = s; a2 = r; a1 = c; }
+}
+
+// Is tile entry (f, r, c) the canonical storage of its node?
+__device__ inline bool tile_canonical(int p, int f, int r, int c) {
+    int d = f >> 1;
+    if (d == 0) return true;
+    if (d == 1) return c != 0 && c != p;
+    return c != 0 && c != p && r != 0 && r != p;
+}
+
+template <typename T>
+__device__ void load_tiles(const Layout& L, const int e[3], const T* __restrict__ u, T* tile) {
+    const int p = L.p, n1 = p + 1, t2 = n1 * n1;
+    for (int i = threadIdx.x; i < 6 * t2; i += blockDim.x) {
+        int f = i / t2, rc = i - f * t2, r = rc / n1, c = rc - r * n1;
+        int a1, a2, a3;
+        tile_node(p, f, r, c, a1, a2, a3);
+        tile[i] = u[elem_slot(L, e, a1, a2, a3)];
+    }
+}
+
+// Directions (row, column) of the in-face coordinates of tile family d.
+__device__ inline int tile_rdir(int d) { return d == 2 ? 1 : 2; }
+__device__ inline int tile_cdir(int d) { return d == 0 ? 1 : 0; }
+
+// ---------------------------------------------------------------------------
+// Condensed operator on one element (Sec. 2.2), matrix-free:
+//   y_e = H_BB u_B - H_BI H_II^-1 H_IB u_B.
+// H_II^-1 = (S x S x S) D^-1 (S x S x S)^T; H_IB only sees face-interior
+// nodes (M diagonal), so the Schur term on face (d, s) is
+//   -(MS_R x MS_C) sum_{k_d} c_{d,s}[k_d] V,
+//   V = D^-1 sum_{d',s'} c_{d',s'} (x)_{d'} G_{d',s'},
+//   G_{d,s} = (Sinv_R x Sinv_C) u_{d,s}^interior.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct ElemPtrs {
+    const T *m[3], *L[3], *Si[3], *MS[3], *lm[3], *c0[3], *cp[3];
+};
+
+template <typename T>
+__device__ inline ElemPtrs<T> elem_ptrs(const LevelTabs<T>& tb, const int e[3]) {
+    const int p = tb.lay.p, n1 = p + 1, q = p - 1;
+    ElemPtrs<T> P;
+    for (int d = 0; d < 3; ++d) {
+        P.m[d] = tb.el_m[d] + e[d] * n1;
+        P.L[d] = tb.el_L[d] + e[d] * n1 * n1;
+        P.Si[d] = tb.el_Sinv[d] + e[d] * q * q;
+        P.MS[d] = tb.el_MS[d] + e[d] * q * q;
+        P.lm[d] = tb.el_lam[d] + e[d] * q;
+        P.c0[d] = tb.el_c0[d] + e[d] * q;
+        P.cp[d] = tb.el_cp[d] + e[d] * q;
+    }
+    return P;
+}
+
+// G_f = (Sinv_R x Sinv_C) X_f for the 6 face interiors X_f (q x q taken from
+// the (p+1)^2 tiles, or from a q x q array when `src_q` is set).
+template <typename T>
+__device__ void faces_to_eigen(const ElemPtrs<T>& P, int p, const T* src, bool src_q, T* tmp, T* G) {
+    const int q = p - 1, q2 = q * q, n1 = p + 1;
+    for (int i = threadIdx.x; i < 6 * q2; i += blockDim.x) {
+        int f = i / q2, rc = i - f * q2, r = rc / q, kc = rc - r * q;
+        const T* Sc = P.Si[tile_cdir(f >> 1)];
+        T s = 0;
+        if (src_q) {
+            const T* X = src + f * q2 + r * q;
+            for (int c = 0; c < q; ++c) s += X[c] * Sc[kc * q + c];
+        } else {
+            const T* X = src + f * n1 * n1 + (r + 1) * n1 + 1;
+            for (int c = 0; c < q; ++c) s += X[c] * Sc[kc * q + c];
+        }
+        tmp[i] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 6 * q2; i += blockDim.x) {
+        int f = i / q2, rc = i - f * q2, kr = rc / q, kc = rc - kr * q;
+        const T* Sr = P.Si[tile_rdir(f >> 1)];
+        const T* X = tmp + f * q2;
+        T s = 0;
+        for (int r = 0; r < q; ++r) s += Sr[kr * q + r] * X[r * q + kc];
+        G[i] = s;
+    }
+    __syncthreads();
+}
+
+// Expansion value at eigen-index (k1, k2, k3): sum_f c_f (x) G_f.
+template <typename T>
+__device__ inline T expand(const ElemPtrs<T>& P, const T* G, int q, int k1, int k2, int k3) {
+    const int q2 = q * q;
+    return P.c0[0][k1] * G[0 * q2 + k3 * q + k2] + P.cp[0][k1] * G[1 * q2 + k3 * q + k2] +
+           P.c0[1][k2] * G[2 * q2 + k3 * q + k1] + P.cp[1][k2] * G[3 * q2 + k3 * q + k1] +
+           P.c0[2][k3] * G[4 * q2 + k2 * q + k1] + P.cp[2][k3] * G[5 * q2 + k2 * q + k1];
+}
+
+// Contractions Tc_f = sum_{k_d} c_{d,s}[k_d] V with V = (expansion + extra) / D.
+// `extra` (may be null) is a q^3 eigenspace array added before the division.
+template <typename T>
+__device__ void eigen_contract(const ElemPtrs<T>& P, int p, T lam, const T* G, const T* extra,
+                               T sign_extra, T* Tc) {
+    const int q = p - 1, q2 = q * q;
+    for (int i = threadIdx.x; i < 3 * q2; i += blockDim.x) {
+        int d = i / q2, rc = i - d * q2, r = rc / q, c = rc - r * q;
+        T s0 = 0, sp = 0;
+        for (int k = 0; k < q; ++k) {
+            int k1, k2, k3;
+            if (d == 0) { k3 = r; k2 = c; k1 = k; }
+            else if (d == 1) { k3 = r; k1 = c; k2 = k; }
+            else { k2 = r; k1 = c; k3 = k; }
+            T v = expand(P, G, q, k1, k2, k3);
+            if (extra) v = extra[(k3 * q + k2) * q + k1] + sign_extra * v;
+            v = v / (lam + P.lm[0][k1] + P.lm[1][k2] + P.lm[2][k3]);
+            s0 += P.c0[d][k] * v;
+            sp += P.cp[d][k] * v;
+        }
+        Tc[(2 * d) * q2 + rc] = s0;
+        Tc[(2 * d + 1) * q2 + rc] = sp;
+    }
+    __syncthreads();
+}
+
+// corr_f = (MS_R x MS_C) Tc_f  (q x q per face).
+template <typename T>
+__device__ void eigen_to_faces(const ElemPtrs<T>& P, int p, const T* Tc, T* tmp, T* out) {
+    const int q = p - 1, q2 = q * q;
+    for (int i = threadIdx.x; i < 6 * q2; i += blockDim.x) {
+        int f = i / q2, rc = i - f * q2, kr = rc / q, c = rc - kr * q;
+        const T* Mc = P.MS[tile_cdir(f >> 1)];
+        const T* X = Tc + f * q2 + kr * q;
+        T s = 0;
+        for (int kc = 0; kc < q; ++kc) s += X[kc] * Mc[c * q + kc];
+        tmp[i] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 6 * q2; i += blockDim.x) {
+        int f = i / q2, rc = i - f * q2, r = rc / q, c = rc - r * q;
+        const T* Mr = P.MS[tile_rdir(f >> 1)];
+        const T* X = tmp + f * q2;
+        T s = 0;
+        for (int kr = 0; kr < q; ++kr) s += Mr[r * q + kr] * X[kr * q + c];
+        out[i] = s;
+    }
+    __syncthreads();
+}
+
+// H_BB u_B at an element shell node (interior values taken as zero).
+template <typename T>
+__device__ inline T hbb_at(const ElemPtrs<T>& P, int p, T lam, const T* tile, int a1, int a2, int a3) {
+    const int n1 = p + 1;
+    T x1 = 0, x2 = 0, x3 = 0;
+    for (int j = 0; j <= p; ++j) {
+        x1 += P.L[0][a1 * n1 + j] * shell_value(tile, p, j, a2, a3);
+        x2 += P.L[1][a2 * n1 + j] * shell_value(tile, p, a1, j, a3);
+        x3 += P.L[2][a3 * n1 + j] * shell_value(tile, p, a1, a2, j);
+    }
+    const T m1 = P.m[0][a1], m2 = P.m[1][a2], m3 = P.m[2][a3];
+    return lam * m1 * m2 * m3 * shell_value(tile, p, a1, a2, a3) + m3 * m2 * x1 + m3 * m1 * x2 +
+           m2 * m1 * x3;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_condensed_op(LevelTabs<T> tb, const T* __restrict__ u,
+                                                      T* __restrict__ y, int color) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    const Layout& L = tb.lay;
+    const int p = L.p, n1 = p + 1, t2 = n1 * n1, q = p - 1, q2 = q * q;
+    int e[3];
+    color_coords(blockIdx.x, color, L.n, e);
+    T* tile = sm;              // 6 t2
+    T* G = tile + 6 * t2;      // 6 q2
+    T* Tc = G + 6 * q2;        // 6 q2
+    T* tmp = Tc + 6 * q2;      // 6 q2
+    ElemPtrs<T> P = elem_ptrs(tb, e);
+    load_tiles(L, e, u, tile);
+    __syncthreads();
+    if (q > 0) {
+        faces_to_eigen(P, p, tile, false, tmp, G);
+        eigen_contract(P, p, tb.lam, G, (const T*)nullptr, (T)1, Tc);
+        eigen_to_faces(P, p, Tc, tmp, G);  // corrections now in G
+    }
+    for (int i = threadIdx.x; i < 6 * t2; i += blockDim.x) {
+        int f = i / t2, rc = i - f * t2, r = rc / n1, c = rc - r * n1;
+        if (!tile_canonical(p, f, r, c)) continue;
+        int a1, a2, a3;
+        tile_node(p, f, r, c, a1, a2, a3);
+        int i1 = e[0] * p + a1, i2 = e[1] * p + a2, i3 = e[2] * p + a3;
+        if (is_dir(L, i1, i2, i3)) continue;
+        T v = hbb_at(P, p, tb.lam, tile, a1, a2, a3);
+        if (r > 0 && r < p && c > 0 && c < p) v -= G[f * q2 + (r - 1) * q + (c - 1)];
+        add_out(y, elem_slot(L, e, a1, a2, a3), v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Schwarz smoother (Alg. 2) with the star inverse of Alg. 1.
+// Star faces F1[i3][i2], F2[i3][i1], F3[i2][i1] are read straight from the
+// plane layout: because each unknown is stored once, the three windows
+// already hold every star unknown exactly once (zeros at the duplicate
+// positions), which is what the multiplicity division of Alg. 1 achieves
+// for duplicated copies.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct StarPtrs {
+    const T *S[3], *lm[3];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_smoother(LevelTabs<T> tb, const T* __restrict__ r,
+                                                  T* __restrict__ du, T omega, int color) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    const Layout& L = tb.lay;
+    const int p = L.p, nS = 2 * p - 1, s2 = nS * nS, c = p - 1;
+    int nv[3] = {L.n[0] + 1, L.n[1] + 1, L.n[2] + 1};
+    int v[3];
+    color_coords(blockIdx.x, color, nv, v);
+    // stars whose three planes are all Dirichlet (domain corners) are empty
+    bool b1 = v[0] == 0 || v[0] == L.n[0], b2 = v[1] == 0 || v[1] == L.n[1],
+         b3 = v[2] == 0 || v[2] == L.n[2];
+    if (b1 && b2 && b3) return;
+    StarPtrs<T> P;
+    for (int d = 0; d < 3; ++d) {
+        P.S[d] = tb.st_S[d] + (int64_t)v[d] * s2;
+        P.lm[d] = tb.st_lam[d] + (int64_t)v[d] * nS;
+    }
+    T* F = sm;            // 3 s2: faces, later the contractions H
+    T* G = F + 3 * s2;    // 3 s2
+    T* tmp = G + 3 * s2;  // 3 s2
+    const int c1 = v[0] * p, c2 = v[1] * p, c3 = v[2] * p;
+    // gather
+    for (int i = threadIdx.x; i < 3 * s2; i += blockDim.x) {
+        int f = i / s2, ab = i - f * s2, a = ab / nS, b = ab - a * nS;
+        int oa = a - c, ob = b - c;
+        T val = 0;
+        if (f == 0) {
+            int i2 = c2 + ob, i3 = c3 + oa;
+            if (i2 >= 0 && i2 < L.N[1] && i3 >= 0 && i3 < L.N[2])
+                val = r[L.plane0(v[0]) + (int64_t)i3 * L.pitch[0] + i2];
+        } else if (f == 1) {
+            int i1 = c1 + ob, i3 = c3 + oa;
+            if (i1 >= 0 && i1 < L.N[0] && i3 >= 0 && i3 < L.N[2])
+                val = r[L.plane1(v[1]) + (int64_t)i3 * L.pitch[1] + i1];
+        } else {
+            int i1 = c1 + ob, i2 = c2 + oa;
+            if (i1 >= 0 && i1 < L.N[0] && i2 >= 0 && i2 < L.N[1])
+                val = r[L.plane2(v[2]) + (int64_t)i2 * L.pitch[2] + i1];
+        }
+        F[i] = val;
+    }
+    __syncthreads();
+    // face f uses (row matrix, column matrix): F1: (S3, S2), F2: (S3, S1), F3: (S2, S1)
+    // tmp_f = F_f S_C
+    for (int i = threadIdx.x; i < 3 * s2; i += blockDim.x) {
+        int f = i / s2, ab = i - f * s2, a = ab / nS, k = ab - a * nS;
+        const T* Sc = P.S[f == 0 ? 1 : 0];
+        const T* X = F + f * s2 + a * nS;
+        T s = 0;
+        for (int b = 0; b < nS; ++b) s += X[b] * Sc[b * nS + k];
+        tmp[i] = s;
+    }
+    __syncthreads();
+    // G_f = S_R^T tmp_f
+    for (int i = threadIdx.x; i < 3 * s2; i += blockDim.x) {
+        int f = i / s2, kk = i - f * s2, kr = kk / nS, kc = kk - kr * nS;
+        const T* Sr = P.S[f == 2 ? 1 : 2];
+        const T* X = tmp + f * s2;
+        T s = 0;
+        for (int a = 0; a < nS; ++a) s += Sr[a * nS + kr] * X[a * nS + kc];
+        G[i] = s;
+    }
+    __syncthreads();
+    // eigen pass: V = (a1 G1 + a2 G2 + a3 G3) / D; H1 = V x_1 a1, H2 = V x_2 a2, H3 = V x_3 a3
+    const T* a1 = P.S[0] + c * nS;
+    const T* a2 = P.S[1] + c * nS;
+    const T* a3 = P.S[2] + c * nS;
+    for (int i = threadIdx.x; i < 3 * s2; i += blockDim.x) {
+        int d = i / s2, rc = i - d * s2, rr = rc / nS, cc = rc - rr * nS;
+        T s = 0;
+        for (int k = 0; k < nS; ++k) {
+            int k1, k2, k3;
+            if (d == 0) { k3 = rr; k2 = cc; k1 = k; }
+            else if (d == 1) { k3 = rr; k1 = cc; k2 = k; }
+            else { k2 = rr; k1 = cc; k3 = k; }
+            T e = a1[k1] * G[k3 * nS + k2] + a2[k2] * G[s2 + k3 * nS + k1] + a3[k3] * G[2 * s2 + k2 * nS + k1];
+            T vv = e / (tb.lam + P.lm[0][k1] + P.lm[1][k2] + P.lm[2][k3]);
+            const T* ad = d == 0 ? a1 : (d == 1 ? a2 : a3);
+            s += ad[k] * vv;
+        }
+        F[i] = s;  // H_d
+    }
+    __syncthreads();
+    // back transforms U_f = S_R H_f S_C^T; tmp = H_f S_C^T
+    for (int i = threadIdx.x; i < 3 * s2; i += blockDim.x) {
+        int f = i / s2, kb = i - f * s2, kr = kb / nS, b = kb - kr * nS;
+        const T* Sc = P.S[f == 0 ? 1 : 0];
+        const T* X = F + f * s2 + kr * nS;
+        T s = 0;
+        for (int k = 0; k < nS; ++k) s += X[k] * Sc[b * nS + k];
+        tmp[i] = s;
+    }
+    __syncthreads();
+    const T* w = tb.st_w;
+    for (int i = threadIdx.x; i < 3 * s2; i += blockDim.x) {
+        int f = i / s2, ab = i - f * s2, a = ab / nS, b = ab - a * nS;
+        int oa = a - c, ob = b - c;
+        int64_t slot;
+        int i1, i2, i3;
+        if (f == 0) { i1 = c1; i2 = c2 + ob; i3 = c3 + oa; }
+        else if (f == 1) { if (ob == 0) continue; i1 = c1 + ob; i2 = c2; i3 = c3 + oa; }
+        else { if (ob == 0 || oa == 0) continue; i1 = c1 + ob; i2 = c2 + oa; i3 = c3; }
+        if (i1 < 0 || i1 >= L.N[0] || i2 < 0 || i2 >= L.N[1] || i3 < 0 || i3 >= L.N[2]) continue;
+        if (is_dir(L, i1, i2, i3)) continue;
+        if (f == 0) slot = L.plane0(v[0]) + (int64_t)i3 * L.pitch[0] + i2;
+        else if (f == 1) slot = L.plane1(v[1]) + (int64_t)i3 * L.pitch[1] + i1;
+        else slot = L.plane2(v[2]) + (int64_t)i2 * L.pitch[2] + i1;
+        const T* Sr = P.S[f == 2 ? 1 : 2];
+        const T* X = tmp + f * s2;
+        T s = 0;
+        for (int k = 0; k < nS; ++k) s += Sr[a * nS + k] * X[k * nS + b];
+        add_out(du, slot, omega * w[a] * w[b] * s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Grid transfers (Sec. 4.1).  The fine condensed values are the tensor
+// Lagrange interpolation of the coarse ones; on a plane this is the 2D
+// interpolation of the coarse plane values (including its edge lines).
+// ---------------------------------------------------------------------------
+// Coarse value at plane-local node of family d, plane j: (row index R, col C).
+template <typename T>
+__device__ inline T plane_value(const Layout& L, const T* x, int d, int j, int R, int C) {
+    const int p = L.p;
+    int i1, i2, i3;
+    if (d == 0) { i1 = j * p; i3 = R; i2 = C; }
+    else if (d == 1) { i2 = j * p; i3 = R; i1 = C; }
+    else { i3 = j * p; i2 = R; i1 = C; }
+    bool on1 = i1 % p == 0, on2 = i2 % p == 0;
+    return x[L.slot(i1, i2, i3, on1, on2)];
+}
+
+// plane tile counts per family: rows run along rdir, columns along cdir
+__device__ inline int tiles_r(const Layout& L, int d) { return L.n[d == 2 ? 1 : 2]; }
+__device__ inline int tiles_c(const Layout& L, int d) { return L.n[d == 0 ? 1 : 0]; }
+
+__device__ inline void transfer_block(const Layout& L, int b, int& d, int& j, int& tr, int& tc) {
+    for (d = 0; d < 3; ++d) {
+        int cnt = (L.n[d] + 1) * tiles_r(L, d) * tiles_c(L, d);
+        if (b < cnt) break;
+        b -= cnt;
+    }
+    int ntc = tiles_c(L, d), ntr = tiles_r(L, d);
+    tc = b % ntc;
+    b /= ntc;
+    tr = b % ntr;
+    j = b / ntr;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_prolong_add(Layout Lc, Layout Lf, const T* __restrict__ J,
+                                                     const T* __restrict__ uc, T* __restrict__ uf) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    const int pc = Lc.p, pf = Lf.p, nc1 = pc + 1;
+    int d, j, tr, tc;
+    transfer_block(Lf, blockIdx.x, d, j, tr, tc);
+    T* X = sm;                 // nc1 x nc1 coarse tile
+    T* Y = X + nc1 * nc1;      // pf x nc1
+    for (int i = threadIdx.x; i < nc1 * nc1; i += blockDim.x) {
+        int R = i / nc1, C = i - R * nc1;
+        X[i] = plane_value(Lc, uc, d, j, tr * pc + R, tc * pc + C);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < pf * nc1; i += blockDim.x) {
+        int r = i / nc1, C = i - r * nc1;
+        T s = 0;
+        for (int R = 0; R < nc1; ++R) s += J[r * nc1 + R] * X[R * nc1 + C];
+        Y[i] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < pf * pf; i += blockDim.x) {
+        int r = i / pf, c = i - r * pf;
+        int gr = tr * pf + r, gc = tc * pf + c;
+        int i1, i2, i3;
+        bool canon;
+        if (d == 0) { i1 = j * pf; i3 = gr; i2 = gc; canon = true; }
+        else if (d == 1) { i2 = j * pf; i3 = gr; i1 = gc; canon = c != 0; }
+        else { i3 = j * pf; i2 = gr; i1 = gc; canon = c != 0 && r != 0; }
+        if (!canon || is_dir(Lf, i1, i2, i3)) continue;
+        T s = 0;
+        for (int C = 0; C < nc1; ++C) s += Y[r * nc1 + C] * J[c * nc1 + C];
+        int64_t slot = (d == 0) ? Lf.plane0(j) + (int64_t)i3 * Lf.pitch[0] + i2
+                     : (d == 1) ? Lf.plane1(j) + (int64_t)i3 * Lf.pitch[1] + i1
+                                : Lf.plane2(j) + (int64_t)i2 * Lf.pitch[2] + i1;
+        uf[slot] += s;
+    }
+}
+
+// 1D global interpolation weight P[g][G] between fine node g and coarse node G.
+template <typename T>
+__device__ inline T p1d(const T* J, int n, int pf, int pc, int g, int G) {
+    int e = g / pf;
+    if (e > n - 1) e = n - 1;
+    int R = G - e * pc;
+    if (R < 0 || R > pc) return (T)0;
+    return J[(g - e * pf) * (pc + 1) + R];
+}
+
+// Restriction pass A: T_d = (P^T x P^T) r_d on every coarse node of every
+// plane (holes included), written to `tb` in the coarse layout.
+template <typename T>
+__global__ void __launch_bounds__(256) k_restrict_planes(Layout Lc, Layout Lf, const T* __restrict__ J,
+                                                         const T* __restrict__ rf, T* __restrict__ tbuf) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    const int pc = Lc.p, pf = Lf.p, w = 2 * pf - 1;
+    int d, j, tr, tc;
+    transfer_block(Lc, blockIdx.x, d, j, tr, tc);
+    const int nr = Lc.n[d == 2 ? 1 : 2], ncn = Lc.n[d == 0 ? 1 : 0];
+    const int Nr = Lf.N[d == 2 ? 1 : 2], Nc = Lf.N[d == 0 ? 1 : 0];
+    const int64_t base = (d == 0) ? Lf.plane0(j) : (d == 1) ? Lf.plane1(j) : Lf.plane2(j);
+    const int pitch = Lf.pitch[d];
+    T* W = sm;           // w x w fine window
+    T* Y = W + w * w;    // w x pc
+    const int gr0 = tr * pf - pf + 1, gc0 = tc * pf - pf + 1;
+    for (int i = threadIdx.x; i < w * w; i += blockDim.x) {
+        int a = i / w, b = i - a * w;
+        int gr = gr0 + a, gc = gc0 + b;
+        T v = 0;
+        if (gr >= 0 && gr < Nr && gc >= 0 && gc < Nc) v = rf[base + (int64_t)gr * pitch + gc];
+        W[i] = v;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < w * pc; i += blockDim.x) {
+        int a = i / pc, C = i - a * pc;
+        int G = tc * pc + C;
+        T s = 0;
+        for (int b = 0; b < w; ++b) {
+            int gc = gc0 + b;
+            if (gc < 0 || gc >= Nc) continue;
+            s += p1d(J, ncn, pf, pc, gc, G) * W[a * w + b];
+        }
+        Y[i] = s;
+    }
+    __syncthreads();
+    const int64_t cbase = (d == 0) ? Lc.plane0(j) : (d == 1) ? Lc.plane1(j) : Lc.plane2(j);
+    for (int i = threadIdx.x; i < pc * pc; i += blockDim.x) {
+        int R = i / pc, C = i - R * pc;
+        int G = tr * pc + R;
+        T s = 0;
+        for (int a = 0; a < w; ++a) {
+            int gr = gr0 + a;
+            if (gr < 0 || gr >= Nr) continue;
+            s += p1d(J, nr, pf, pc, gr, G) * Y[a * pc + C];
+        }
+        tbuf[cbase + (int64_t)(tr * pc + R) * Lc.pitch[d] + tc * pc + C] = s;
+    }
+}
+
+// Restriction pass B: coarse unknown = sum of T_d over the plane families
+// that contain it.
+template <typename T>
+__global__ void k_restrict_combine(Layout L, const T* __restrict__ tbuf, T* __restrict__ rc) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.len) return;
+    int d = (i >= L.off[2]) ? 2 : (i >= L.off[1] ? 1 : 0);
+    int64_t loc = i - L.off[d];
+    int j = (int)(loc / L.pstride[d]);
+    int64_t rem = loc - (int64_t)j * L.pstride[d];
+    int r = (int)(rem / L.pitch[d]), c = (int)(rem - (int64_t)r * L.pitch[d]);
+    const int p = L.p;
+    T v = 0;
+    if (r < L.rows[d]) {
+        int i1, i2, i3;
+        bool canon;
+        if (d == 0) { i1 = j * p; i3 = r; i2 = c; canon = c < L.N[1]; }
+        else if (d == 1) { i2 = j * p; i3 = r; i1 = c; canon = c < L.N[0] && (c % p) != 0; }
+        else { i3 = j * p; i2 = r; i1 = c; canon = c < L.N[0] && (c % p) != 0 && (r % p) != 0; }
+        if (canon && !is_dir(L, i1, i2, i3)) {
+            v = tbuf[i];
+            if (d <= 1 && i3 % p == 0) v += tbuf[L.plane2(i3 / p) + (int64_t)i2 * L.pitch[2] + i1];
+            if (d == 0 && i2 % p == 0) v += tbuf[L.plane1(i2 / p) + (int64_t)i3 * L.pitch[1] + i1];
+        }
+    }
+    rc[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Static condensation and interior recovery (Alg. 4, Alg. 5), one element
+// per workgroup.  F = M f with the GLL-lumped mass.
+// ---------------------------------------------------------------------------
+// Forward 3D transform of an element interior: Fe = (S^T x S^T x S^T) X
+// with X[k3][k2][k1] in `a`, result in `a`; `b` is scratch (q^3 each).
+template <typename T>
+__device__ void interior_forward(const ElemPtrs<T>& P, int q, T* a, T* b) {
+    const int q3 = q * q * q;
+    // S^T = Sinv M^-1 ... use S^T directly: S^T[k][i] = Sinv[k][i] / m_I[i]
+    for (int i = threadIdx.x; i < q3; i += blockDim.x) {
+        int i1 = i % q, r = i / q;
+        T s = 0;
+        for (int j = 0; j < q; ++j) s += P.Si[0][i1 * q + j] / P.m[0][j + 1] * a[r * q + j];
+        b[i] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < q3; i += blockDim.x) {
+        int k1 = i % q, k2 = (i / q) % q, k3 = i / (q * q);
+        T s = 0;
+        for (int j = 0; j < q; ++j) s += P.Si[1][k2 * q + j] / P.m[1][j + 1] * b[(k3 * q + j) * q + k1];
+        a[i] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < q3; i += blockDim.x) {
+        int k12 = i % (q * q), k3 = i / (q * q);
+        T s = 0;
+        for (int j = 0; j < q; ++j) s += P.Si[2][k3 * q + j] / P.m[2][j + 1] * a[j * q * q + k12];
+        b[i] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < q3; i += blockDim.x) a[i] = b[i];
+    __syncthreads();
+}
+
+// Backward 3D transform (S x S x S) V, V in `a`, result in `a`.
+template <typename T>
+__device__ void interior_backward(const ElemPtrs<T>& P, int q, T* a, T* b) {
+    const int q3 = q * q * q;
+    for (int i = threadIdx.x; i < q3; i += blockDim.x) {
+        int i1 = i % q, r = i / q;
+        T s = 0;
+        for (int k = 0; k < q; ++k) s += P.MS[0][i1 * q + k] / P.m[0][i1 + 1] * a[r * q + k];
+        b[i] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < q3; i += blockDim.x) {
+        int i1 = i % q, i2 = (i / q) % q, k3 = i / (q * q);
+        T s = 0;
+        for (int k = 0; k < q; ++k) s += P.MS[1][i2 * q + k] / P.m[1][i2 + 1] * b[(k3 * q + k) * q + i1];
+        a[i] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < q3; i += blockDim.x) {
+        int i12 = i % (q * q), i3 = i / (q * q);
+        T s = 0;
+        for (int k = 0; k < q; ++k) s += P.MS[2][i3 * q + k] / P.m[2][i3 + 1] * a[k * q * q + i12];
+        b[i] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < q3; i += blockDim.x) a[i] = b[i];
+    __syncthreads();
+}
+
+// Fhat (skeleton part) = assembled mass * f at the free skeleton nodes.
+__global__ void k_mass_skeleton(Layout L, const double* __restrict__ m1, const double* __restrict__ m2,
+                                const double* __restrict__ m3, const double* __restrict__ f,
+                                double* __restrict__ Fh) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.len) return;
+    int d = (i >= L.off[2]) ? 2 : (i >= L.off[1] ? 1 : 0);
+    int64_t loc = i - L.off[d];
+    int j = (int)(loc / L.pstride[d]);
+    int64_t rem = loc - (int64_t)j * L.pstride[d];
+    int r = (int)(rem / L.pitch[d]), c = (int)(rem - (int64_t)r * L.pitch[d]);
+    const int p = L.p;
+    double v = 0;
+    if (r < L.rows[d]) {
+        int i1, i2, i3;
+        bool canon;
+        if (d == 0) { i1 = j * p; i3 = r; i2 = c; canon = c < L.N[1]; }
+        else if (d == 1) { i2 = j * p; i3 = r; i1 = c; canon = c < L.N[0] && (c % p) != 0; }
+        else { i3 = j * p; i2 = r; i1 = c; canon = c < L.N[0] && (c % p) != 0 && (r % p) != 0; }
+        if (canon && !is_dir(L, i1, i2, i3))
+            v = m1[i1] * m2[i2] * m3[i3] * f[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1];
+    }
+    Fh[i] = v;
+}
+
+// Fhat -= H_BI H_II^-1 F_I, element by element (colour launches).
+__global__ void __launch_bounds__(256) k_condense(LevelTabs<double> tb, const double* __restrict__ f,
+                                                  double* __restrict__ Fh, int color) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* sm = reinterpret_cast<double*>(smem_raw);
+    const Layout& L = tb.lay;
+    const int p = L.p, q = p - 1, q2 = q * q, q3 = q2 * q;
+    if (q < 1) return;
+    int e[3];
+    color_coords(blockIdx.x, color, L.n, e);
+    ElemPtrs<double> P = elem_ptrs(tb, e);
+    double* a = sm;          // q3
+    double* b = a + q3;      // q3
+    double* Tc = b + q3;     // 6 q2
+    double* tmp = Tc + 6 * q2;
+    double* cor = tmp + 6 * q2;
+    for (int i = threadIdx.x; i < q3; i += blockDim.x) {
+        int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
+        int i1 = e[0] * p + 1 + k1, i2 = e[1] * p + 1 + k2, i3 = e[2] * p + 1 + k3;
+        a[i] = P.m[0][k1 + 1] * P.m[1][k2 + 1] * P.m[2][k3 + 1] *
+               f[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1];
+    }
+    __syncthreads();
+    interior_forward(P, q, a, b);
+    // V = a / D, contractions
+    for (int i = threadIdx.x; i < 3 * q2; i += blockDim.x) {
+        int d = i / q2, rc = i - d * q2, r = rc / q, c = rc - r * q;
+        double s0 = 0, sp = 0;
+        for (int k = 0; k < q; ++k) {
+            int k1, k2, k3;
+            if (d == 0) { k3 = r; k2 = c; k1 = k; }
+            else if (d == 1) { k3 = r; k1 = c; k2 = k; }
+            else { k2 = r; k1 = c; k3 = k; }
+            double vv = a[(k3 * q + k2) * q + k1] / (tb.lam + P.lm[0][k1] + P.lm[1][k2] + P.lm[2][k3]);
+            s0 += P.c0[d][k] * vv;
+            sp += P.cp[d][k] * vv;
+        }
+        Tc[(2 * d) * q2 + rc] = s0;
+        Tc[(2 * d + 1) * q2 + rc] = sp;
+    }
+    __syncthreads();
+    eigen_to_faces(P, p, Tc, tmp, cor);
+    for (int i = threadIdx.x; i < 6 * q2; i += blockDim.x) {
+        int f = i / q2, rc = i - f * q2, r = rc / q + 1, c = rc % q + 1;
+        int a1, a2, a3;
+        tile_node(p, f, r, c, a1, a2, a3);
+        int i1 = e[0] * p + a1, i2 = e[1] * p + a2, i3 = e[2] * p + a3;
+        if (is_dir(L, i1, i2, i3)) continue;
+        Fh[elem_slot(L, e, a1, a2, a3)] -= cor[i];
+    }
+}
+
+// u on the grid from uhat: skeleton nodes copied, interiors recovered.
+__global__ void __launch_bounds__(256) k_recover(LevelTabs<double> tb, const double* __restrict__ f,
+                                                 const double* __restrict__ uh, double* __restrict__ ug) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* sm = reinterpret_cast<double*>(smem_raw);
+    const Layout& L = tb.lay;
+    const int p = L.p, n1 = p + 1, t2 = n1 * n1, q = p - 1, q2 = q * q, q3 = q2 * q;
+    int e[3];
+    color_coords(blockIdx.x, -1, L.n, e);
+    ElemPtrs<double> P = elem_ptrs(tb, e);
+    double* tile = sm;           // 6 t2
+    double* a = tile + 6 * t2;   // q3
+    double* b = a + q3;          // q3
+    double* G = b + q3;          // 6 q2
+    double* tmp = G + 6 * q2;    // 6 q2
+    load_tiles(L, e, uh, tile);
+    for (int i = threadIdx.x; i < q3; i += blockDim.x) {
+        int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
+        int i1 = e[0] * p + 1 + k1, i2 = e[1] * p + 1 + k2, i3 = e[2] * p + 1 + k3;
+        a[i] = P.m[0][k1 + 1] * P.m[1][k2 + 1] * P.m[2][k3 + 1] *
+               f[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1];
+    }
+    __syncthreads();
+    // shell nodes owned by this element: a_d < p, or a_d = p on the last element
+    for (int i = threadIdx.x; i < n1 * n1 * n1; i += blockDim.x) {
+        int a1 = i % n1, a2 = (i / n1) % n1, a3 = i / t2;
+        bool shell = a1 == 0 || a1 == p || a2 == 0 || a2 == p || a3 == 0 || a3 == p;
+        if (!shell) continue;
+        if ((a1 == p && e[0] != L.n[0] - 1) || (a2 == p && e[1] != L.n[1] - 1) ||
+            (a3 == p && e[2] != L.n[2] - 1))
+            continue;
+        int i1 = e[0] * p + a1, i2 = e[1] * p + a2, i3 = e[2] * p + a3;
+        double v = is_dir(L, i1, i2, i3) ? 0.0 : shell_value(tile, p, a1, a2, a3);
+        ug[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1] = v;
+    }
+    if (q < 1) return;
+    interior_forward(P, q, a, b);
+    faces_to_eigen(P, p, tile, false, tmp, G);
+    // V = (forward(F_I) - expansion(G)) / D
+    for (int i = threadIdx.x; i < q3; i += blockDim.x) {
+        int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
+        double v = a[i] - expand(P, G, q, k1, k2, k3);
+        a[i] = v / (tb.lam + P.lm[0][k1] + P.lm[1][k2] + P.lm[2][k3]);
+    }
+    __syncthreads();
+    interior_backward(P, q, a, b);
+    for (int i = threadIdx.x; i < q3; i += blockDim.x) {
+        int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
+        int i1 = e[0] * p + 1 + k1, i2 = e[1] * p + 1 + k2, i3 = e[2] * p + 1 + k3;
+        ug[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1] = a[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BLAS-1 on skeleton arrays.  Reductions write one partial per block and
+// the last block to finish sums the partials in a fixed order, so the
+// result is deterministic.  Scalars live in device memory.
+// ---------------------------------------------------------------------------
+__device__ inline double block_sum(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
+    return s;  // valid in thread 0
+}
+
+// Finish a reduction of `nv` values per block: partials[nv * gridDim.x].
+__device__ inline void finish_reduce(double* partials, const double* mine, int nv, unsigned* counter,
+                                     double* out) {
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < nv; ++k) partials[(size_t)blockIdx.x * nv + k] = mine[k];
+        __threadfence();
+        unsigned prev = atomicAdd(counter, 1u);
+        last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int k = 0; k < nv; ++k) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) s += partials[(size_t)b * nv + k];
+        __shared__ double red[16];
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) out[k] = s;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
+// out[0] = x . y ; out[1] = x . z (if z non-null)
+template <typename T>
+__global__ void __launch_bounds__(256) k_dot2(const T* __restrict__ x, const T* __restrict__ y,
+                                              const T* __restrict__ z, int64_t n, double* partials,
+                                              unsigned* counter, double* out) {
+    __shared__ double red[16];
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double xv = (double)x[i];
+        s0 += xv * (double)y[i];
+        if (z) s1 += xv * (double)z[i];
+    }
+    double mine[2];
+    mine[0] = block_sum(s0, red);
+    __syncthreads();
+    mine[1] = block_sum(s1, red);
+    finish_reduce(partials, mine, 2, counter, out);
+}
+
+// ipCG direction update (Alg. 5): beta = (gamma - gamma0) / delta,
+// p = beta p + z.  sc[0] = gamma, sc[1] = gamma0, sc[2] = delta (old).
+__global__ void k_pcg_dir(double* __restrict__ p, const double* __restrict__ z, const double* sc, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double beta = (sc[0] - sc[1]) / sc[2];
+    p[i] = beta * p[i] + z[i];
+}
+
+// alpha = gamma / (q . p); s = r; u += alpha p; r -= alpha q; partial r.r
+__global__ void __launch_bounds__(256) k_pcg_update(double* __restrict__ u, double* __restrict__ r,
+                                                    double* __restrict__ s, const double* __restrict__ p,
+                                                    const double* __restrict__ q, const double* sc_gamma,
+                                                    const double* sc_qp, int64_t n, double* partials,
+                                                    unsigned* counter, double* out) {
+    __shared__ double red[16];
+    const double alpha = sc_gamma[0] / sc_qp[0];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double ri = r[i];
+        if (s) s[i] = ri;
+        u[i] += alpha * p[i];
+        ri -= alpha * q[i];
+        r[i] = ri;
+        acc += ri * ri;
+    }
+    double mine[1];
+    mine[0] = block_sum(acc, red);
+    finish_reduce(partials, mine, 1, counter, out);
+}
+
+// Jacobi-PCG pieces for the coarse solve (FP64).
+// z = r / diag; partial (r . z)
+__global__ void __launch_bounds__(256) k_jacobi(const double* __restrict__ r, const double* __restrict__ dg,
+                                                double* __restrict__ z, int64_t n, double* partials,
+                                                unsigned* counter, double* out) {
+    __shared__ double red[16];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double zi = r[i] / dg[i];
+        z[i] = zi;
+        acc += r[i] * zi;
+    }
+    double mine[1];
+    mine[0] = block_sum(acc, red);
+    finish_reduce(partials, mine, 1, counter, out);
+}
+
+template <typename T, typename U>
+__global__ void k_cast_scale(const T* __restrict__ x, U* __restrict__ y, const double* sc, int invert,
+                             int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = sc ? (invert ? 1.0 / sc[0] : sc[0]) : 1.0;
+    y[i] = (U)((double)x[i] * s);
+}
+
+// y = x - y  (residual form r = F - A u, with y = A u on entry)
+template <typename T>
+__global__ void k_sub_from(const T* __restrict__ x, T* __restrict__ y, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i] - y[i];
+}
+
+template <typename T>
+__global__ void k_axpy(T a, const T* __restrict__ x, T* __restrict__ y, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += a * x[i];
+}
+
+// CG step on the coarse level with device scalars:
+// sc: [0] rz, [1] pq ; x += alpha p ; r -= alpha q
+__global__ void k_cg_xr(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                        const double* __restrict__ q, const double* sc, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double alpha = sc[0] / sc[1];
+    x[i] += alpha * p[i];
+    r[i] -= alpha * q[i];
+}
+
+// p = z + (rz_new / rz_old) p
+__global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ z, const double* rz_new,
+                       const double* rz_old, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    p[i] = z[i] + (rz_new[0] / rz_old[0]) * p[i];
+}
+
+// ---------------------------------------------------------------------------
+// MLP 3 -> 64 -> 64 -> nout, FP32 (learned smoother damping).
+// One thread per sample for the hidden layers; parameters staged in LDS.
+// ---------------------------------------------------------------------------
+#define MLP_H 64
+__device__ inline int mlp_off_b1() { return MLP_H * 3; }
+__device__ inline int mlp_off_W2() { return MLP_H * 3 + MLP_H; }
+__device__ inline int mlp_off_b2() { return MLP_H * 3 + MLP_H + MLP_H * MLP_H; }
+__device__ inline int mlp_off_W3() { return MLP_H * 3 + 2 * MLP_H + MLP_H * MLP_H; }
+
+__global__ void __launch_bounds__(64) k_mlp_forward(const float* __restrict__ prm, const float* __restrict__ x,
+                                                    float* __restrict__ y, float* __restrict__ cache, int batch,
+                                                    int nout) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const float* W1 = prm;
+    const float* b1 = prm + mlp_off_b1();
+    const float* W2 = prm + mlp_off_W2();
+    const float* b2 = prm + mlp_off_b2();
+    const float* W3 = prm + mlp_off_W3();
+    const float* b3 = W3 + nout * MLP_H;
+    float h1[MLP_H];
+    float x0 = x[b * 3 + 0], x1 = x[b * 3 + 1], x2 = x[b * 3 + 2];
+    float* cb = cache + (size_t)b * (2 * MLP_H + nout);
+    for (int i = 0; i < MLP_H; ++i) {
+        float s = b1[i] + W1[i * 3 + 0] * x0 + W1[i * 3 + 1] * x1 + W1[i * 3 + 2] * x2;
+        h1[i] = tanhf(s);
+        cb[i] = h1[i];
+    }
+    float h2[MLP_H];
+    for (int i = 0; i < MLP_H; ++i) {
+        float s = b2[i];
+        for (int j = 0; j < MLP_H; ++j) s += W2[i * MLP_H + j] * h1[j];
+        h2[i] = tanhf(s);
+        cb[MLP_H + i] = h2[i];
+    }
+    for (int o = 0; o < nout; ++o) {
+        float s = b3[o];
+        for (int j = 0; j < MLP_H; ++j) s += W3[o * MLP_H + j] * h2[j];
+        float yo = 2.0f / (1.0f + expf(-s));
+        y[b * nout + o] = yo;
+        cb[2 * MLP_H + o] = yo;
+    }
+}
+
+__global__ void k_mlp_loss(const float* __restrict__ y, const float* __restrict__ t, const float* __restrict__ m,
+                           float* __restrict__ dy, float* __restrict__ loss, int n) {
+    // single block
+    __shared__ float rs[256], rc[256];
+    float s = 0.f, c = 0.f;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        float e = (y[i] - t[i]) * m[i];
+        s += e * e;
+        c += m[i];
+    }
+    rs[threadIdx.x] = s;
+    rc[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            rs[threadIdx.x] += rs[threadIdx.x + o];
+            rc[threadIdx.x] += rc[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    float cnt = rc[0] > 0.f ? rc[0] : 1.f;
+    if (threadIdx.x == 0) loss[0] = rs[0] / cnt;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dy[i] = 2.f * (y[i] - t[i]) * m[i] / cnt;
+}
+
+// Backward: one block per parameter group row; accumulate over samples.
+// Stage 1 (per sample): d_o = dy * y(1 - y/2); d_h2 = (W3^T d_o) (1 - h2^2);
+// d_h1 = (W2^T d_h2) (1 - h1^2).  Stored per sample in `work`.
+__global__ void __launch_bounds__(64) k_mlp_back_sample(const float* __restrict__ prm, const float* __restrict__ cache,
+                                                        const float* __restrict__ dy, float* __restrict__ work,
+                                                        int batch, int nout) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const float* W2 = prm + mlp_off_W2();
+    const float* W3 = prm + mlp_off_W3();
+    const float* cb = cache + (size_t)b * (2 * MLP_H + nout);
+    float* wb = work + (size_t)b * (2 * MLP_H + nout);
+    for (int o = 0; o < nout; ++o) {
+        float yo = cb[2 * MLP_H + o];
+        wb[2 * MLP_H + o] = dy[b * nout + o] * yo * (1.f - 0.5f * yo);  // d(2 sigma)/ds = y (1 - y/2)
+    }
+    float dh2[MLP_H];
+    for (int i = 0; i < MLP_H; ++i) {
+        float s = 0.f;
+        for (int o = 0; o < nout; ++o) s += W3[o * MLP_H + i] * wb[2 * MLP_H + o];
+        float h = cb[MLP_H + i];
+        dh2[i] = s * (1.f - h * h);
+        wb[MLP_H + i] = dh2[i];
+    }
+    for (int j = 0; j < MLP_H; ++j) {
+        float s = 0.f;
+        for (int i = 0; i < MLP_H; ++i) s += W2[i * MLP_H + j] * dh2[i];
+        float h = cb[j];
+        wb[j] = s * (1.f - h * h);
+    }
+}
+
+// Stage 2: parameter gradients, one thread per parameter, sum over samples.
+__global__ void k_mlp_back_params(const float* __restrict__ x, const float* __restrict__ cache,
+                                  const float* __restrict__ work, float* __restrict__ g, int batch, int nout) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = 2 * MLP_H + nout;
+    const int nW1 = MLP_H * 3, nb1 = MLP_H, nW2 = MLP_H * MLP_H, nb2 = MLP_H, nW3 = nout * MLP_H;
+    const int total = nW1 + nb1 + nW2 + nb2 + nW3 + nout;
+    if (k >= total) return;
+    float s = 0.f;
+    if (k < nW1) {
+        int i = k / 3, j = k % 3;
+        for (int b = 0; b < batch; ++b) s += work[(size_t)b * stride + i] * x[b * 3 + j];
+    } else if ((k -= nW1) < nb1) {
+        for (int b = 0; b < batch; ++b) s += work[(size_t)b * stride + k];
+    } else if ((k -= nb1) < nW2) {
+        int i = k / MLP_H, j = k % MLP_H;
+        for (int b = 0; b < batch; ++b) s += work[(size_t)b * stride + MLP_H + i] * cache[(size_t)b * stride + j];
+    } else if ((k -= nW2) < nb2) {
+        for (int b = 0; b < batch; ++b) s += work[(size_t)b * stride + MLP_H + k];
+    } else if ((k -= nb2) < nW3) {
+        int o = k / MLP_H, j = k % MLP_H;
+        for (int b = 0; b < batch; ++b)
+            s += work[(size_t)b * stride + 2 * MLP_H + o] * cache[(size_t)b * stride + MLP_H + j];
+    } else {
+        k -= nW3;
+        for (int b = 0; b < batch; ++b) s += work[(size_t)b * stride + 2 * MLP_H + k];
+    }
+    g[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+__global__ void k_mlp_adam(float* __restrict__ prm, const float* __restrict__ g, float* __restrict__ m,
+                           float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float c1,
+                           float c2) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.f - b1) * gi;
+    float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    float mh = mi / c1, vh = vi / c2;
+    prm[i] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+static int color_count(const int n[3], int color) {
+    int p0 = color & 1, p1 = (color >> 1) & 1, p2 = (color >> 2) & 1;
+    return ((n[0] - p0 + 1) / 2) * ((n[1] - p1 + 1) / 2) * ((n[2] - p2 + 1) / 2);
+}
+
+template <typename T>
+size_t smem_condensed_op(int p) {
+    int n1 = p + 1, q = p - 1;
+    return sizeof(T) * (size_t)(6 * n1 * n1 + 18 * q * q);
+}
+template <typename T>
+size_t smem_smoother(int p) {
+    int nS = 2 * p - 1;
+    return sizeof(T) * (size_t)(9 * nS * nS);
+}
+
+template <typename T>
+void launch_grid_to_skel(const Layout& L, const double* g, T* s, hipStream_t st) {
+    hipLaunchKernelGGL(k_grid_to_skel<T>, dim3(nblk(L.len)), dim3(256), 0, st, L, g, s);
+}
+template <typename T>
+void launch_skel_to_grid(const Layout& L, const T* s, double* g, hipStream_t st) {
+    int64_t tot = (int64_t)L.N[0] * L.N[1] * L.N[2];
+    hipLaunchKernelGGL(k_skel_to_grid<T>, dim3(nblk(tot)), dim3(256), 0, st, L, s, g);
+}
+
+template <typename T>
+void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t st) {
+    hipMemsetAsync(y, 0, sizeof(T) * tb.lay.len, st);
+    size_t sm = smem_condensed_op<T>(tb.lay.p);
+    for (int c = 0; c < 8; ++c) {
+        int nb = color_count(tb.lay.n, c);
+        if (nb == 0) continue;
+        hipLaunchKernelGGL(k_condensed_op<T>, dim3(nb), dim3(256), sm, st, tb, u, y, c);
+    }
+}
+
+template <typename T>
+void launch_smoother_add(const LevelTabs<T>& tb, const T* r, T* du, T omega, hipStream_t st) {
+    size_t sm = smem_smoother<T>(tb.lay.p);
+    int nv[3] = {tb.lay.n[0] + 1, tb.lay.n[1] + 1, tb.lay.n[2] + 1};
+    for (int c = 0; c < 8; ++c) {
+        int nb = color_count(nv, c);
+        if (nb == 0) continue;
+        hipLaunchKernelGGL(k_smoother<T>, dim3(nb), dim3(256), sm, st, tb, r, du, omega, c);
+    }
+}
+
+static int transfer_blocks(const Layout& L) {
+    int tot = 0;
+    for (int d = 0; d < 3; ++d) tot += (L.n[d] + 1) * L.n[d == 2 ? 1 : 2] * L.n[d == 0 ? 1 : 0];
+    return tot;
+}
+
+template <typename T>
+void launch_prolong_add(const Layout& Lc, const Layout& Lf, const T* J, const T* uc, T* uf, hipStream_t st) {
+    size_t sm = sizeof(T) * (size_t)((Lc.p + 1) * (Lc.p + 1) + Lf.p * (Lc.p + 1));
+    hipLaunchKernelGGL(k_prolong_add<T>, dim3(transfer_blocks(Lf)), dim3(256), sm, st, Lc, Lf, J, uc, uf);
+}
+
+template <typename T>
+void launch_restrict(const Layout& Lf, const Layout& Lc, const T* J, const T* rf, T* rc, T* tbuf,
+                     hipStream_t st) {
+    int w = 2 * Lf.p - 1;
+    size_t sm = sizeof(T) * (size_t)(w * w + w * Lc.p);
+    hipLaunchKernelGGL(k_restrict_planes<T>, dim3(transfer_blocks(Lc)), dim3(256), sm, st, Lc, Lf, J, rf, tbuf);
+    hipLaunchKernelGGL(k_restrict_combine<T>, dim3(nblk(Lc.len)), dim3(256), 0, st, Lc, (const T*)tbuf, rc);
+}
+
+void launch_condense(const LevelTabs<double>& tb, const double* m1, const double* m2, const double* m3,
+                     const double* f, double* Fh, hipStream_t st) {
+    const Layout& L = tb.lay;
+    hipLaunchKernelGGL(k_mass_skeleton, dim3(nblk(L.len)), dim3(256), 0, st, L, m1, m2, m3, f, Fh);
+    int q = L.p - 1;
+    if (q < 1) return;
+    size_t sm = sizeof(double) * (size_t)(2 * q * q * q + 18 * q * q);
+    for (int c = 0; c < 8; ++c) {
+        int nb = color_count(L.n, c);
+        if (nb == 0) continue;
+        hipLaunchKernelGGL(k_condense, dim3(nb), dim3(256), sm, st, tb, f, Fh, c);
+    }
+}
+
+void launch_recover(const LevelTabs<double>& tb, const double* f, const double* uh, double* ug, hipStream_t st) {
+    const Layout& L = tb.lay;
+    int n1 = L.p + 1, q = L.p - 1;
+    size_t sm = sizeof(double) * (size_t)(6 * n1 * n1 + 2 * q * q * q + 12 * q * q);
+    hipLaunchKernelGGL(k_recover, dim3(L.n[0] * L.n[1] * L.n[2]), dim3(256), sm, st, tb, f, uh, ug);
+}
+
+template <typename T>
+void launch_dot2(const T* x, const T* y, const T* z, int64_t n, double* partials, unsigned* counter,
+                 double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot2<T>, dim3(REDUCE_BLOCKS), dim3(256), 0, st, x, y, z, n, partials, counter, out);
+}
+
+void launch_pcg_dir(double* p, const double* z, const double* sc, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_dir, dim3(nblk(n)), dim3(256), 0, st, p, z, sc, n);
+}
+
+void launch_pcg_update(double* u, double* r, double* s, const double* p, const double* q, const double* gam,
+                       const double* qp, int64_t n, double* partials, unsigned* counter, double* out,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_update, dim3(REDUCE_BLOCKS), dim3(256), 0, st, u, r, s, p, q, gam, qp, n, partials,
+                       counter, out);
+}
+
+void launch_jacobi(const double* r, const double* dg, double* z, int64_t n, double* partials, unsigned* counter,
+                   double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_jacobi, dim3(REDUCE_BLOCKS), dim3(256), 0, st, r, dg, z, n, partials, counter, out);
+}
+
+void launch_cg_xr(double* x, double* r, const double* p, const double* q, const double* sc, int64_t n,
+                  hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_xr, dim3(nblk(n)), dim3(256), 0, st, x, r, p, q, sc, n);
+}
+
+void launch_cg_p(double* p, const double* z, const double* rz_new, const double* rz_old, int64_t n,
+                 hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_p, dim3(nblk(n)), dim3(256), 0, st, p, z, rz_new, rz_old, n);
+}
+
+template <typename T, typename U>
+void launch_cast_scale(const T* x, U* y, const double* sc, int invert, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_cast_scale<T, U>), dim3(nblk(n)), dim3(256), 0, st, x, y, sc, invert, n);
+}
+
+template <typename T>
+void launch_sub_from(const T* x, T* y, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_sub_from<T>, dim3(nblk(n)), dim3(256), 0, st, x, y, n);
+}
+
+template <typename T>
+void launch_axpy(T a, const T* x, T* y, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy<T>, dim3(nblk(n)), dim3(256), 0, st, a, x, y, n);
+}
+
+void launch_mlp_forward(const float* prm, const float* x, float* y, float* cache, int batch, int nout,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_forward, dim3(nblk(batch, 64)), dim3(64), 0, st, prm, x, y, cache, batch, nout);
+}
+void launch_mlp_loss(const float* y, const float* t, const float* m, float* dy, float* loss, int n,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, st, y, t, m, dy, loss, n);
+}
+void launch_mlp_backward(const float* prm, const float* x, const float* cache, const float* dy, float* work,
+                         float* g, int batch, int nout, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_back_sample, dim3(nblk(batch, 64)), dim3(64), 0, st, prm, cache, dy, work, batch,
+                       nout);
+    int total = MLP_H * 3 + MLP_H + MLP_H * MLP_H + MLP_H + nout * MLP_H + nout;
+    hipLaunchKernelGGL(k_mlp_back_params, dim3(nblk(total)), dim3(256), 0, st, x, cache, work, g, batch, nout);
+}
+void launch_mlp_adam(float* prm, const float* g, float* m, float* v, int n, float lr, float b1, float b2,
+                     float eps, int t, hipStream_t st) {
+    float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    hipLaunchKernelGGL(k_mlp_adam, dim3(nblk(n)), dim3(256), 0, st, prm, g, m, v, n, lr, b1, b2, eps, c1, c2);
+}
+
+hipError_t init_kernel_attributes() {
+    const int lds = 160 * 1024;
+    const void* fns[] = {
+        (const void*)k_condensed_op<double>, (const void*)k_condensed_op<float>,
+        (const void*)k_smoother<double>,     (const void*)k_smoother<float>,
+        (const void*)k_prolong_add<double>,  (const void*)k_prolong_add<float>,
+        (const void*)k_restrict_planes<double>, (const void*)k_restrict_planes<float>,
+        (const void*)k_condense,             (const void*)k_recover};
+    for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// explicit instantiations
+#define INST(T)                                                                                            \
+    template void launch_grid_to_skel<T>(const Layout&, const double*, T*, hipStream_t);                    \
+    template void launch_skel_to_grid<T>(const Layout&, const T*, double*, hipStream_t);                    \
+    template void launch_condensed_op<T>(const LevelTabs<T>&, const T*, T*, hipStream_t);                  \
+    template void launch_smoother_add<T>(const LevelTabs<T>&, const T*, T*, T, hipStream_t);               \
+    template void launch_prolong_add<T>(const Layout&, const Layout&, const T*, const T*, T*, hipStream_t); \
+    template void launch_restrict<T>(const Layout&, const Layout&, const T*, const T*, T*, T*, hipStream_t); \
+    template void launch_dot2<T>(const T*, const T*, const T*, int64_t, double*, unsigned*, double*,        \
+                                 hipStream_t);                                                             \
+    template void launch_sub_from<T>(const T*, T*, int64_t, hipStream_t);                                  \
+    template void launch_axpy<T>(T, const T*, T*, int64_t, hipStream_t);                                   \
+    template size_t smem_condensed_op<T>(int);                                                             \
+    template size_t smem_smoother<T>(int);
+INST(double)
+INST(float)
+template void launch_cast_scale<double, float>(const double*, float*, const double*, int, int64_t, hipStream_t);
+template void launch_cast_scale<float, double>(const float*, double*, const double*, int, int64_t, hipStream_t);
+template void launch_cast_scale<double, double>(const double*, double*, const double*, int, int64_t, hipStream_t);
+
+}  // namespace pmg

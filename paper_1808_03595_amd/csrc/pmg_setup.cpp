@@ -1,0 +1,360 @@
+// Host-side set-up of the 1D tables that drive the kernels.
+//
+// GLL nodes/weights, the standard stiffness matrix, generalized eigenpairs
+// of (L, M) with a diagonal M, Lagrange interpolation and the weight
+// polynomial; then the per-level tables of elements (condensed operator,
+// Sec. 2.2), stars (Alg. 1, with the identity padding of Sec. 3.4) and the
+// transfer matrix (Sec. 4.1).
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <stdexcept>
+
+#include "pmg_internal.h"
+
+namespace pmg {
+
+Layout make_layout(int n1, int n2, int n3, int p) {
+    Layout L{};
+    L.p = p;
+    L.n[0] = n1; L.n[1] = n2; L.n[2] = n3;
+    for (int d = 0; d < 3; ++d) L.N[d] = L.n[d] * p + 1;
+    auto pad = [](int v) { return (v + 3) & ~3; };
+    // family 0: [i3][i2]; family 1: [i3][i1]; family 2: [i2][i1]
+    L.pitch[0] = pad(L.N[1]); L.rows[0] = L.N[2];
+    L.pitch[1] = pad(L.N[0]); L.rows[1] = L.N[2];
+    L.pitch[2] = pad(L.N[0]); L.rows[2] = L.N[1];
+    int64_t o = 0;
+    for (int d = 0; d < 3; ++d) {
+        L.pstride[d] = (int64_t)L.rows[d] * L.pitch[d];
+        L.pstride[d] = (L.pstride[d] + 63) & ~(int64_t)63;
+        L.off[d] = o;
+        o += (int64_t)(L.n[d] + 1) * L.pstride[d];
+    }
+    L.len = o;
+    return L;
+}
+
+// Legendre P_k(x) for k = 0..n by the three-term recurrence.
+static void legendre_all(int n, double x, std::vector<double>& P) {
+    P.assign(n + 1, 0.0);
+    P[0] = 1.0;
+    if (n >= 1) P[1] = x;
+    for (int k = 2; k <= n; ++k) P[k] = ((2 * k - 1) * x * P[k - 1] - (k - 1) * P[k - 2]) / k;
+}
+
+// GLL nodes are the zeros of P_{p+1} - P_{p-1} (proportional to
+// (1 - x^2) P_p'), whose derivative is (2p + 1) P_p.  Newton from the
+// Chebyshev-Lobatto points; weights 2 / (p (p + 1) P_p(x)^2).
+void gll_nodes_weights(int p, std::vector<double>& x, std::vector<double>& w) {
+    x.resize(p + 1);
+    w.resize(p + 1);
+    std::vector<double> P;
+    for (int i = 0; i <= p; ++i) {
+        double xi = -std::cos(M_PI * i / p);
+        if (i > 0 && i < p) {
+            for (int it = 0; it < 100; ++it) {
+                legendre_all(p + 1, xi, P);
+                double dx = (P[p + 1] - P[p - 1]) / ((2 * p + 1) * P[p]);
+                xi -= dx;
+                if (std::fabs(dx) < 1e-16) break;
+            }
+        }
+        x[i] = xi;
+    }
+    x[0] = -1.0;
+    x[p] = 1.0;
+    for (int i = 0; i <= p; ++i) {
+        legendre_all(p, x[i], P);
+        w[i] = 2.0 / (p * (p + 1.0) * P[p] * P[p]);
+    }
+}
+
+// L_S = D^T W D with the closed-form GLL differentiation matrix
+// D_ij = P_p(x_i) / (P_p(x_j) (x_i - x_j)), D_00 = -p(p+1)/4, D_pp = p(p+1)/4.
+void stiffness_std(int p, const std::vector<double>& x, const std::vector<double>& w,
+                   std::vector<double>& L) {
+    int n = p + 1;
+    std::vector<double> Pp(n), P, D(n * n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        legendre_all(p, x[i], P);
+        Pp[i] = P[p];
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            if (i != j) D[i * n + j] = Pp[i] / (Pp[j] * (x[i] - x[j]));
+    D[0] = -p * (p + 1.0) / 4.0;
+    D[n * n - 1] = p * (p + 1.0) / 4.0;
+    L.assign(n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int q = 0; q < n; ++q) s += D[q * n + i] * w[q] * D[q * n + j];
+            L[i * n + j] = s;
+        }
+}
+
+// Cyclic Jacobi rotations for a symmetric n x n matrix A (destroyed).
+// Q[i][k] column k is the eigenvector of lam[k]; ascending order.
+void sym_eig_jacobi(int n, std::vector<double>& A, std::vector<double>& Q,
+                    std::vector<double>& lam) {
+    Q.assign(n * n, 0.0);
+    for (int i = 0; i < n; ++i) Q[i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                tot += A[i * n + j] * A[i * n + j];
+                if (i != j) off += A[i * n + j] * A[i * n + j];
+            }
+        if (off <= 1e-32 * tot || off == 0.0) break;
+        for (int pq = 0; pq < n; ++pq)
+            for (int qq = pq + 1; qq < n; ++qq) {
+                double apq = A[pq * n + qq];
+                if (apq == 0.0) continue;
+                double app = A[pq * n + pq], aqq = A[qq * n + qq];
+                double theta = (aqq - app) / (2.0 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) /
+                           (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {
+                    double akp = A[k * n + pq], akq = A[k * n + qq];
+                    A[k * n + pq] = c * akp - s * akq;
+                    A[k * n + qq] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double apk = A[pq * n + k], aqk = A[qq * n + k];
+                    A[pq * n + k] = c * apk - s * aqk;
+                    A[qq * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double qkp = Q[k * n + pq], qkq = Q[k * n + qq];
+                    Q[k * n + pq] = c * qkp - s * qkq;
+                    Q[k * n + qq] = s * qkp + c * qkq;
+                }
+            }
+    }
+    std::vector<int> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return A[a * n + a] < A[b * n + b]; });
+    std::vector<double> Qs(n * n);
+    lam.resize(n);
+    for (int k = 0; k < n; ++k) {
+        lam[k] = A[ord[k] * n + ord[k]];
+        for (int i = 0; i < n; ++i) Qs[i * n + k] = Q[i * n + ord[k]];
+    }
+    Q.swap(Qs);
+}
+
+// Generalized eigenpairs of (L, diag(m)): S^T L S = diag(lam), S^T M S = I,
+// via the symmetric matrix M^-1/2 L M^-1/2 = Q diag(lam) Q^T, S = M^-1/2 Q.
+void gen_eig_diag(int n, const double* L, const double* m, std::vector<double>& S,
+                  std::vector<double>& lam) {
+    std::vector<double> A(n * n), Q;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) A[i * n + j] = L[i * n + j] / std::sqrt(m[i] * m[j]);
+    sym_eig_jacobi(n, A, Q, lam);
+    S.resize(n * n);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) S[i * n + k] = Q[i * n + k] / std::sqrt(m[i]);
+}
+
+// J[i][j] = l_j(xt[i]) by the barycentric formula on the nodes xf.
+void lagrange_interp(const std::vector<double>& xf, const std::vector<double>& xt,
+                     std::vector<double>& J) {
+    int nf = (int)xf.size(), nt = (int)xt.size();
+    std::vector<double> b(nf, 1.0);
+    for (int j = 0; j < nf; ++j)
+        for (int k = 0; k < nf; ++k)
+            if (k != j) b[j] /= (xf[j] - xf[k]);
+    J.assign(nt * nf, 0.0);
+    for (int i = 0; i < nt; ++i) {
+        int hit = -1;
+        for (int j = 0; j < nf; ++j)
+            if (xt[i] == xf[j]) hit = j;
+        if (hit >= 0) {
+            J[i * nf + hit] = 1.0;
+            continue;
+        }
+        double den = 0.0;
+        for (int j = 0; j < nf; ++j) den += b[j] / (xt[i] - xf[j]);
+        for (int j = 0; j < nf; ++j) J[i * nf + j] = (b[j] / (xt[i] - xf[j])) / den;
+    }
+}
+
+static double binom(int n, int k) {
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+// Degree-pw (odd) polynomial that is 0 at t = 0, 1 at t = 1 and has its
+// first (pw-1)/2 derivatives zero at both ends: the smoothstep polynomial
+// S_m(t) = t^(m+1) sum_k C(m+k, k) C(2m+1, m-k) (-t)^k, m = (pw-1)/2.
+double smoothstep(int pw, double t) {
+    int m = (pw - 1) / 2;
+    double s = 0.0;
+    for (int k = 0; k <= m; ++k) s += binom(m + k, k) * binom(2 * m + 1, m - k) * std::pow(-t, k);
+    return std::pow(t, m + 1) * s;
+}
+
+void build_level_tables(int p, int pc, const std::vector<double> h[3], HostTables& t) {
+    std::vector<double> x, w, Ls;
+    gll_nodes_weights(p, x, w);
+    stiffness_std(p, x, w, Ls);
+    const int n1 = p + 1, q = p - 1, nS = 2 * p - 1;
+    for (int d = 0; d < 3; ++d) {
+        const int ne = (int)h[d].size();
+        t.el_m[d].clear(); t.el_L[d].clear(); t.el_Sinv[d].clear(); t.el_MS[d].clear();
+        t.el_lam[d].clear(); t.el_c0[d].clear(); t.el_cp[d].clear();
+        t.st_S[d].clear(); t.st_lam[d].clear();
+        for (int e = 0; e < ne; ++e) {
+            double he = h[d][e];
+            std::vector<double> m(n1), L(n1 * n1);
+            for (int i = 0; i < n1; ++i) m[i] = 0.5 * he * w[i];
+            for (int i = 0; i < n1 * n1; ++i) L[i] = (2.0 / he) * Ls[i];
+            t.el_m[d].insert(t.el_m[d].end(), m.begin(), m.end());
+            t.el_L[d].insert(t.el_L[d].end(), L.begin(), L.end());
+            if (q >= 1) {
+                std::vector<double> LI(q * q), mI(q), S, lam;
+                for (int i = 0; i < q; ++i) {
+                    mI[i] = m[i + 1];
+                    for (int j = 0; j < q; ++j) LI[i * q + j] = L[(i + 1) * n1 + (j + 1)];
+                }
+                gen_eig_diag(q, LI.data(), mI.data(), S, lam);
+                for (int k = 0; k < q; ++k)
+                    for (int i = 0; i < q; ++i) t.el_Sinv[d].push_back(S[i * q + k] * mI[i]);
+                for (int i = 0; i < q; ++i)
+                    for (int k = 0; k < q; ++k) t.el_MS[d].push_back(mI[i] * S[i * q + k]);
+                t.el_lam[d].insert(t.el_lam[d].end(), lam.begin(), lam.end());
+                for (int k = 0; k < q; ++k) {
+                    double c0 = 0.0, cp = 0.0;
+                    for (int i = 0; i < q; ++i) {
+                        c0 += S[i * q + k] * L[(i + 1) * n1 + 0];
+                        cp += S[i * q + k] * L[(i + 1) * n1 + p];
+                    }
+                    t.el_c0[d].push_back(c0);
+                    t.el_cp[d].push_back(cp);
+                }
+            }
+        }
+        // stars: block positions -p..p -> 0..2p; keep 1..2p-1
+        for (int v = 0; v <= ne; ++v) {
+            std::vector<double> M(2 * p + 1, 0.0), L((2 * p + 1) * (2 * p + 1), 0.0);
+            std::vector<char> cpl(2 * p + 1, 0);
+            auto add_el = [&](int e, int base) {
+                double he = h[d][e];
+                for (int i = 0; i < n1; ++i) {
+                    M[base + i] += 0.5 * he * w[i];
+                    cpl[base + i] = 1;
+                    for (int j = 0; j < n1; ++j)
+                        L[(base + i) * (2 * p + 1) + base + j] += (2.0 / he) * Ls[i * n1 + j];
+                }
+            };
+            if (v >= 1) add_el(v - 1, 0);
+            if (v <= ne - 1) add_el(v, p);
+            if (v == 0 || v == ne) cpl[p] = 0;
+            std::vector<int> c;
+            for (int i = 1; i < 2 * p; ++i)
+                if (cpl[i]) c.push_back(i);
+            std::vector<double> S(nS * nS, 0.0), lam(nS, 1.0);
+            for (int i = 0; i < nS; ++i) S[i * nS + i] = 1.0;
+            int nc = (int)c.size();
+            if (nc > 0) {
+                std::vector<double> Lc(nc * nc), mc(nc), Sc, lc;
+                for (int a = 0; a < nc; ++a) {
+                    mc[a] = M[c[a]];
+                    for (int b = 0; b < nc; ++b) Lc[a * nc + b] = L[c[a] * (2 * p + 1) + c[b]];
+                }
+                gen_eig_diag(nc, Lc.data(), mc.data(), Sc, lc);
+                for (int a = 0; a < nc; ++a) {
+                    lam[c[a] - 1] = lc[a];
+                    for (int b = 0; b < nc; ++b) S[(c[a] - 1) * nS + (c[b] - 1)] = Sc[a * nc + b];
+                }
+            }
+            t.st_S[d].insert(t.st_S[d].end(), S.begin(), S.end());
+            t.st_lam[d].insert(t.st_lam[d].end(), lam.begin(), lam.end());
+        }
+    }
+    // weights at offsets -(p-1)..(p-1): t = (1 - x_|j|) / 2
+    t.st_w.resize(nS);
+    for (int j = -(p - 1); j <= p - 1; ++j) t.st_w[j + p - 1] = smoothstep(7, (1.0 - x[std::abs(j)]) / 2.0);
+    t.J.clear();
+    if (pc > 0) {
+        std::vector<double> xc, wc;
+        gll_nodes_weights(pc, xc, wc);
+        lagrange_interp(xc, x, t.J);
+    }
+}
+
+// Diagonal of the assembled condensed operator on a level, stored in the
+// plane layout (1 at unused slots).  Per element: diagonal of H_e at the
+// shell nodes minus, at face-interior nodes, the Schur term
+// sum_k (c_{d,s}[k_d] Sinv[k'][a'] Sinv[k''][a''])^2 / D[k].
+void coarse_diagonal(const Layout& lay, double lam, const std::vector<double> h[3],
+                     std::vector<double>& diag) {
+    const int p = lay.p, n1 = p + 1, q = p - 1;
+    HostTables t;
+    build_level_tables(p, 0, h, t);
+    diag.assign(lay.len, 0.0);
+    std::vector<char> used(lay.len, 0);
+    for (int e3 = 0; e3 < lay.n[2]; ++e3)
+        for (int e2 = 0; e2 < lay.n[1]; ++e2)
+            for (int e1 = 0; e1 < lay.n[0]; ++e1) {
+                const int e[3] = {e1, e2, e3};
+                const double* m[3];
+                const double* L[3];
+                const double *Si[3], *lm[3], *c0[3], *cp[3];
+                for (int d = 0; d < 3; ++d) {
+                    m[d] = &t.el_m[d][e[d] * n1];
+                    L[d] = &t.el_L[d][e[d] * n1 * n1];
+                    Si[d] = q ? &t.el_Sinv[d][e[d] * q * q] : nullptr;
+                    lm[d] = q ? &t.el_lam[d][e[d] * q] : nullptr;
+                    c0[d] = q ? &t.el_c0[d][e[d] * q] : nullptr;
+                    cp[d] = q ? &t.el_cp[d][e[d] * q] : nullptr;
+                }
+                for (int a3 = 0; a3 <= p; ++a3)
+                    for (int a2 = 0; a2 <= p; ++a2)
+                        for (int a1 = 0; a1 <= p; ++a1) {
+                            const int a[3] = {a1, a2, a3};
+                            bool on[3];
+                            int non = 0;
+                            for (int d = 0; d < 3; ++d) {
+                                on[d] = (a[d] == 0 || a[d] == p);
+                                non += on[d];
+                            }
+                            if (!non) continue;
+                            const int g1 = e1 * p + a1, g2 = e2 * p + a2, g3 = e3 * p + a3;
+                            if (g1 == 0 || g2 == 0 || g3 == 0 || g1 == lay.N[0] - 1 ||
+                                g2 == lay.N[1] - 1 || g3 == lay.N[2] - 1)
+                                continue;
+                            double v = lam * m[0][a1] * m[1][a2] * m[2][a3] +
+                                       m[2][a3] * m[1][a2] * L[0][a1 * n1 + a1] +
+                                       m[2][a3] * m[0][a1] * L[1][a2 * n1 + a2] +
+                                       m[1][a2] * m[0][a1] * L[2][a3 * n1 + a3];
+                            if (non == 1 && q > 0) {
+                                int dn = on[0] ? 0 : (on[1] ? 1 : 2);
+                                const double* c = (a[dn] == 0) ? c0[dn] : cp[dn];
+                                int da = (dn == 0) ? 1 : 0, db = (dn == 2) ? 1 : 2;
+                                double s = 0.0;
+                                for (int k3 = 0; k3 < q; ++k3)
+                                    for (int k2 = 0; k2 < q; ++k2)
+                                        for (int k1 = 0; k1 < q; ++k1) {
+                                            const int k[3] = {k1, k2, k3};
+                                            double g = c[k[dn]] * Si[da][k[da] * q + (a[da] - 1)] *
+                                                       Si[db][k[db] * q + (a[db] - 1)];
+                                            double D = lam + lm[0][k1] + lm[1][k2] + lm[2][k3];
+                                            s += g * g / D;
+                                        }
+                                v -= s;
+                            }
+                            int64_t sl = lay.slot(g1, g2, g3, on[0], !on[0] && on[1]);
+                            diag[sl] += v;
+                            used[sl] = 1;
+                        }
+            }
+    for (int64_t i = 0; i < lay.len; ++i)
+        if (!used[i]) diag[i] = 1.0;
+}
+
+}  // namespace pmg

@@ -1,0 +1,91 @@
+"""Shared helpers of the GPU tests: device arrays and oracle grids."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import paper_1808_03595_amd as pmg
+from oracle import mesh as omesh
+
+
+def make_pair(n, p, lam, alpha=1.0, widths=None):
+    """Build the GPU mesh and the oracle mesh of the same problem."""
+    if widths is None:
+        g = pmg.create_mesh(n[0], n[1], n[2], p, lam, alpha)
+        o = omesh.Mesh.box(n, p, lam, alpha)
+    else:
+        g = pmg.create_mesh_widths(widths[0], widths[1], widths[2], p, lam)
+        o = omesh.Mesh(widths[0], widths[1], widths[2], p, lam)
+    return g, o
+
+
+def level_mesh(o, g, level):
+    return o.with_degree(g.level_degree(level))
+
+
+def to_skel(g, grid, level=None, dtype=torch.float64):
+    """Oracle grid (finest level only) -> GPU skeleton array via the HIP path."""
+    dev = torch.device("cuda:0")
+    gd = torch.as_tensor(np.ascontiguousarray(grid), dtype=torch.float64, device=dev)
+    s = torch.empty(g.skeleton_len(), dtype=dtype, device=dev)
+    g.grid_to_skeleton(gd, s, pmg.F64 if dtype == torch.float64 else pmg.F32)
+    return s
+
+
+def from_skel(g, s):
+    dev = torch.device("cuda:0")
+    out = torch.empty(g.grid_shape(), dtype=torch.float64, device=dev)
+    g.skeleton_to_grid(s, out, pmg.F64 if s.dtype == torch.float64 else pmg.F32)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+class LevelIO:
+    """Grid <-> skeleton conversion on any level, done on the host.
+
+    The HIP library only converts on the finest level; coarser levels are
+    filled here by the plain storage rule of the plane layout (each unknown
+    once: i1 % p == 0 -> family 0, else i2 % p == 0 -> family 1, else
+    family 2), which the finest-level round trip pins.
+    """
+
+    def __init__(self, g, level):
+        self.g = g
+        self.p = g.level_degree(level)
+        n = g.n
+        self.len = g.skeleton_len(level)
+        p = self.p
+        N = [n[d] * p + 1 for d in range(3)]
+        pad = lambda v: (v + 3) & ~3
+        pitch = [pad(N[1]), pad(N[0]), pad(N[0])]
+        rows = [N[2], N[2], N[1]]
+        pst = [((rows[d] * pitch[d] + 63) // 64) * 64 for d in range(3)]
+        off = [0, (n[0] + 1) * pst[0], (n[0] + 1) * pst[0] + (n[1] + 1) * pst[1]]
+        assert off[2] + (n[2] + 1) * pst[2] == self.len
+        i3, i2, i1 = np.meshgrid(np.arange(N[2]), np.arange(N[1]), np.arange(N[0]), indexing="ij")
+        on1, on2, on3 = i1 % p == 0, i2 % p == 0, i3 % p == 0
+        dirichlet = ((i1 == 0) | (i2 == 0) | (i3 == 0) | (i1 == N[0] - 1)
+                     | (i2 == N[1] - 1) | (i3 == N[2] - 1))
+        skel = (on1 | on2 | on3) & ~dirichlet
+        slot = np.where(on1, off[0] + (i1 // p) * pst[0] + i3 * pitch[0] + i2,
+                        np.where(on2, off[1] + (i2 // p) * pst[1] + i3 * pitch[1] + i1,
+                                 off[2] + (i3 // p) * pst[2] + i2 * pitch[2] + i1))
+        self.mask = skel
+        self.slot = slot[skel]
+        self.shape = (N[2], N[1], N[0])
+
+    def to_dev(self, grid, dtype=torch.float64):
+        v = np.zeros(self.len)
+        v[self.slot] = np.asarray(grid)[self.mask]
+        return torch.as_tensor(v, dtype=dtype, device="cuda:0")
+
+    def to_grid(self, s):
+        v = s.detach().double().cpu().numpy()
+        out = np.zeros(self.shape)
+        out[self.mask] = v[self.slot]
+        return out
+
+
+def rel(a, b):
+    nb = np.linalg.norm(np.ravel(b))
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / (nb if nb > 0 else 1.0)

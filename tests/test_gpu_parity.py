@@ -1,0 +1,190 @@
+"""GPU parity: every HIP kernel of the hot path against the FP64 oracle.
+
+FP64 bar: relative 2-norm error <= 1e-12 on operator, smoother, transfer,
+condensation and recovery outputs (the tolerance the specification fixes for
+the plain path).  FP32 kernels are compared with the FP64 oracle at a bound
+derived from unit round-off 6e-8 times the depth of the accumulation chains
+(a few hundred terms for p <= 8): 2e-5.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1808_03595_amd as pmg
+import synth
+from oracle import matfree, solver
+from tests.gpu_helpers import LevelIO, make_pair, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 2e-5
+
+CASES = [
+    # (n, p, lambda, alpha)  tiny meshes spanning several tiles, ragged counts
+    ((3, 2, 2), 4, 1.0, 1.0),
+    ((2, 3, 3), 3, 0.0, 1.4),
+    ((3, 3, 2), 8, 100.0, 1.2),
+    ((2, 2, 3), 2, 1e4, 1.0),
+    ((4, 3, 2), 6, 1.0, 1.7),
+    ((2, 2, 2), 16, 1.0, 1.0),
+    ((1, 2, 3), 5, 1.0, 1.0),
+]
+
+
+def _ids(c):
+    return f"n{c[0][0]}{c[0][1]}{c[0][2]}-p{c[1]}-lam{c[2]:g}-a{c[3]:g}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_layout_roundtrip(gpu, case):
+    n, p, lam, alpha = case
+    g, o = make_pair(n, p, lam, alpha)
+    io = LevelIO(g, g.num_levels())
+    u = synth.random_grid(o.shape, 1) * o.free_skeleton_mask()
+    s = torch.empty(g.skeleton_len(), dtype=torch.float64, device=gpu)
+    g.grid_to_skeleton(torch.as_tensor(synth.random_grid(o.shape, 1), device=gpu), s)
+    assert torch.equal(s, io.to_dev(u))
+    back = torch.empty(o.shape, dtype=torch.float64, device=gpu)
+    g.skeleton_to_grid(s, back)
+    assert np.array_equal(back.cpu().numpy(), u)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_condensed_op_all_levels(gpu, case, dtype):
+    n, p, lam, alpha = case
+    g, o = make_pair(n, p, lam, alpha)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    for level in range(g.num_levels() + 1):
+        io = LevelIO(g, level)
+        ol = o.with_degree(io.p)
+        u = synth.random_grid(ol.shape, 2 + level) * ol.free_skeleton_mask()
+        ref = matfree.condensed_op(ol, u)
+        du = io.to_dev(u, tdt)
+        y = torch.full_like(du, float("nan"))
+        g.apply_condensed_op(level, du, y, pmg.F64 if dtype == "f64" else pmg.F32)
+        torch.cuda.synchronize()
+        err = rel(io.to_grid(y), ref)
+        assert err <= (TOL64 if dtype == "f64" else TOL32), (level, err)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_smoother_all_levels(gpu, case, dtype):
+    n, p, lam, alpha = case
+    g, o = make_pair(n, p, lam, alpha)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    for level in range(g.num_levels() + 1):
+        io = LevelIO(g, level)
+        ol = o.with_degree(io.p)
+        r = synth.random_grid(ol.shape, 7 + level) * ol.free_skeleton_mask()
+        ref = matfree.smoother(ol, r, 0.8)
+        dr = io.to_dev(r, tdt)
+        du = torch.full_like(dr, float("nan"))
+        g.schwarz_smooth(level, dr, du, 0.8, pmg.F64 if dtype == "f64" else pmg.F32)
+        torch.cuda.synchronize()
+        err = rel(io.to_grid(du), ref)
+        assert err <= (TOL64 if dtype == "f64" else TOL32), (level, err)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_transfers(gpu, case):
+    n, p, lam, alpha = case
+    g, o = make_pair(n, p, lam, alpha)
+    for level in range(1, g.num_levels() + 1):
+        iof, ioc = LevelIO(g, level), LevelIO(g, level - 1)
+        of, oc = o.with_degree(iof.p), o.with_degree(ioc.p)
+        uc = synth.random_grid(oc.shape, 11) * oc.free_skeleton_mask()
+        uf = synth.random_grid(of.shape, 12) * of.free_skeleton_mask()
+        ref_p = uf + matfree.prolong(oc, of, uc)
+        ref_r = matfree.restrict(of, oc, uf)
+        for dt, tol in ((pmg.F64, TOL64), (pmg.F32, TOL32)):
+            tdt = torch.float64 if dt == pmg.F64 else torch.float32
+            dfine = iof.to_dev(uf, tdt)
+            g.prolong_add(level, ioc.to_dev(uc, tdt), dfine, dt)
+            dco = torch.full((ioc.len,), float("nan"), dtype=tdt, device=gpu)
+            g.restrict(level, iof.to_dev(uf, tdt), dco, dt)
+            torch.cuda.synchronize()
+            assert rel(iof.to_grid(dfine), ref_p) <= tol
+            assert rel(ioc.to_grid(dco), ref_r) <= tol
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_condense_and_recover(gpu, case):
+    n, p, lam, alpha = case
+    g, o = make_pair(n, p, lam, alpha)
+    io = LevelIO(g, g.num_levels())
+    f = synth.random_grid(o.shape, 21)
+    ref_F = matfree.condense_rhs(o, f)
+    df = torch.as_tensor(f, device=gpu)
+    Fh = torch.full((io.len,), float("nan"), dtype=torch.float64, device=gpu)
+    g.condense_rhs(df, Fh)
+    torch.cuda.synchronize()
+    assert rel(io.to_grid(Fh), ref_F) <= TOL64
+    uh = synth.random_grid(o.shape, 22) * o.free_skeleton_mask()
+    ref_u = matfree.recover_interior(o, f, uh)
+    du = torch.full(o.shape, float("nan"), dtype=torch.float64, device=gpu)
+    g.recover_interior(df, io.to_dev(uh), du)
+    torch.cuda.synchronize()
+    assert rel(du.cpu().numpy(), ref_u) <= TOL64
+
+
+@pytest.mark.parametrize("case", CASES[:5], ids=_ids)
+@pytest.mark.parametrize("nu_mode", [0, 1])
+def test_vcycle_fixed_coarse(gpu, case, nu_mode):
+    """Alg. 3 with a fixed number of coarse CG iterations on both sides."""
+    n, p, lam, alpha = case
+    g, o = make_pair(n, p, lam, alpha)
+    g.set_cycle(nu_mode, 0.0, 7)
+    # the damping crosses the C ABI as float32; the oracle gets the same values
+    om = [float(np.float32(0.9)), float(np.float32(1.1))]
+    g.set_damping(om[: g.num_levels()])
+    h = solver.Hierarchy(o, nu_mode="kMG" if nu_mode == 0 else "kvMG",
+                         omega=om, coarse_rtol=0.0, coarse_maxit=7)
+    io = LevelIO(g, g.num_levels())
+    r = synth.random_grid(o.shape, 31) * o.free_skeleton_mask()
+    ref = h.vcycle(None, r)
+    z = torch.full((io.len,), float("nan"), dtype=torch.float64, device=gpu)
+    g.vcycle(io.to_dev(r), z, pmg.F64)
+    torch.cuda.synchronize()
+    assert rel(io.to_grid(z), ref) <= 1e-11
+    z32 = torch.full((io.len,), float("nan"), dtype=torch.float32, device=gpu)
+    g.vcycle(io.to_dev(r, torch.float32), z32, pmg.F32)
+    torch.cuda.synchronize()
+    assert rel(io.to_grid(z32), ref) <= 1e-4
+
+
+@pytest.mark.parametrize("case", CASES[:5], ids=_ids)
+def test_coarse_solve(gpu, case):
+    n, p, lam, alpha = case
+    g, o = make_pair(n, p, lam, alpha)
+    io = LevelIO(g, 0)
+    o0 = o.with_degree(io.p)
+    b = synth.random_grid(o0.shape, 41) * o0.free_skeleton_mask()
+    g.set_cycle(0, 0.0, 9)
+    x = torch.zeros(io.len, dtype=torch.float64, device=gpu)
+    it = g.coarse_solve(io.to_dev(b), x)
+    assert it == 9
+    diag = matfree.condensed_diagonal(o0)
+    ref = solver.jacobi_pcg(lambda v: matfree.condensed_op(o0, v), b, diag, 0.0, 9)
+    assert rel(io.to_grid(x), ref) <= 1e-11
+
+
+@pytest.mark.parametrize("method", ["kMG", "kvMG"])
+def test_pcg_solve_matches_oracle(gpu, method):
+    """Alg. 5 end to end: same iteration count, residual history and solution."""
+    n, p, lam, alpha = (3, 3, 2), 6, 1.0, 1.3
+    g, o = make_pair(n, p, lam, alpha)
+    g.set_cycle(0 if method == "kMG" else 1, 1e-8, 500)
+    f = synth.random_grid(o.shape, 51)
+    res = solver.solve(o, f, method=method, rtol=1e-10, coarse_rtol=1e-8, coarse_maxit=500)
+    u = torch.zeros(o.shape, dtype=torch.float64, device=gpu)
+    st = g.pcg_solve(torch.as_tensor(f, device=gpu), u, 1e-10, 100, pmg.F64)
+    assert st.status == 0
+    assert st.iters == res.iters
+    hist = np.array(st.history())
+    assert np.allclose(hist, res.hist, rtol=1e-6, atol=0)
+    assert rel(u.cpu().numpy(), res.u) <= 1e-9
