@@ -114,31 +114,42 @@ class Hierarchy:
 
 
 def jacobi_pcg(apply, b, diag, rtol, maxit, log=None):
-    """Jacobi-preconditioned CG from x = 0.
+    """Jacobi-preconditioned CG from x = 0 (Chronopoulos-Gear form).
 
-    Stops before an iteration when sqrt(<r, D^-1 r>) <= rtol sqrt(<b, D^-1 b>)
-    or after ``maxit`` iterations.
+    The single-reduction form of preconditioned CG: per iteration one
+    operator application w = A z and the two inner products (r, z) and
+    (w, z) taken together; p and q = A p follow by recurrences.  In exact
+    arithmetic it produces the iterates of standard PCG.  Stops when
+    (r, D^-1 r) <= rtol^2 (b, D^-1 b) or after ``maxit`` updates of x.
     """
     x = np.zeros_like(b)
     r = np.array(b, dtype=np.float64)
     z = r / diag
-    p = z.copy()
-    rz = dot(r, z)
-    rz0 = rz
+    w = apply(z)
+    gamma = dot(r, z)
+    delta = dot(w, z)
+    gamma0 = gamma
     it = 0
-    while it < maxit:
-        if rz <= (rtol * rtol) * rz0 or rz == 0.0:
-            break
-        q = apply(p)
-        alpha = rz / dot(p, q)
-        x = x + alpha * p
-        r = r - alpha * q
-        z = r / diag
-        rz_new = dot(r, z)
-        beta = rz_new / rz
-        rz = rz_new
-        p = z + beta * p
-        it += 1
+    if gamma > 0.0 and maxit > 0:
+        p, q = z.copy(), w.copy()
+        alpha = gamma / delta
+        while True:
+            x = x + alpha * p
+            r = r - alpha * q
+            it += 1
+            if it >= maxit:
+                break
+            z = r / diag
+            w = apply(z)
+            gamma_new = dot(r, z)
+            delta = dot(w, z)
+            if gamma_new <= (rtol * rtol) * gamma0:
+                break
+            beta = gamma_new / gamma
+            alpha = gamma_new / (delta - beta * gamma_new / alpha)
+            gamma = gamma_new
+            p = z + beta * p
+            q = w + beta * q
     if log is not None:
         log.append(it)
     return x

@@ -72,8 +72,11 @@ struct pmg_mesh {
     double coarse_rtol = 1e-8;
     int coarse_maxit = 2000;
     std::vector<double> omega;  // per level index l
-    // coarse CG
-    double *cx = nullptr, *cr = nullptr, *cz = nullptr, *cp = nullptr, *cq = nullptr, *cdiag = nullptr;
+    // coarse CG (persistent kernel, compact numbering of the level-0 unknowns)
+    CoarseArgs ca{};
+    int coarse_blocks = 16;
+    int* d_coarse_iters = nullptr;
+    int* d_coarse_err = nullptr;
     int coarse_last = 0;
     long coarse_total = 0;
     // finest-level solver vectors (FP64) and mixed-precision buffers
@@ -162,6 +165,104 @@ int check_lds(int p) {
     return 0;
 }
 
+// Free canonical node of a plane-layout slot (host mirror of the kernels'
+// storage rule); returns false for holes, padding and Dirichlet nodes.
+bool decode_slot(const Layout& L, int64_t s, int& i1, int& i2, int& i3) {
+    int d = (s >= L.off[2]) ? 2 : (s >= L.off[1] ? 1 : 0);
+    int64_t loc = s - L.off[d];
+    int j = (int)(loc / L.pstride[d]);
+    int64_t rem = loc - (int64_t)j * L.pstride[d];
+    int r = (int)(rem / L.pitch[d]), c = (int)(rem - (int64_t)r * L.pitch[d]);
+    const int p = L.p;
+    if (r >= L.rows[d]) return false;
+    bool canon;
+    if (d == 0) { i1 = j * p; i3 = r; i2 = c; canon = c < L.N[1]; }
+    else if (d == 1) { i2 = j * p; i3 = r; i1 = c; canon = c < L.N[0] && (c % p) != 0; }
+    else { i3 = j * p; i2 = r; i1 = c; canon = c < L.N[0] && (c % p) != 0 && (r % p) != 0; }
+    if (!canon) return false;
+    return !(i1 == 0 || i2 == 0 || i3 == 0 || i1 == L.N[0] - 1 || i2 == L.N[1] - 1 || i3 == L.N[2] - 1);
+}
+
+int build_coarse(pmg_mesh* m) {
+    const Layout& L0 = m->lv[0].lay;
+    const int p0 = L0.p, nn = p0 + 1;
+    if (p0 > 2) return fail(PMG_EUNSUP, "coarse level degree must be 1 or 2");
+    std::vector<int> slot2c(L0.len, -1), cslot;
+    for (int64_t s = 0; s < L0.len; ++s) {
+        int i1, i2, i3;
+        if (decode_slot(L0, s, i1, i2, i3)) {
+            slot2c[s] = (int)cslot.size();
+            cslot.push_back((int)s);
+        }
+    }
+    const int N0 = (int)cslot.size();
+    const int ne = m->n[0] * m->n[1] * m->n[2];
+    std::vector<int> enodes((size_t)ne * 27, -1), radj((size_t)std::max(N0, 1) * 8, -1), cnt(std::max(N0, 1), 0);
+    for (int e = 0; e < ne; ++e) {
+        int c[3] = {e % m->n[0], (e / m->n[0]) % m->n[1], e / (m->n[0] * m->n[1])};
+        for (int a3 = 0; a3 < nn; ++a3)
+            for (int a2 = 0; a2 < nn; ++a2)
+                for (int a1 = 0; a1 < nn; ++a1) {
+                    int i1 = c[0] * p0 + a1, i2 = c[1] * p0 + a2, i3 = c[2] * p0 + a3;
+                    bool on1 = i1 % p0 == 0, on2 = i2 % p0 == 0, on3 = i3 % p0 == 0;
+                    if (!(on1 || on2 || on3)) continue;
+                    if (i1 == 0 || i2 == 0 || i3 == 0 || i1 == L0.N[0] - 1 || i2 == L0.N[1] - 1 ||
+                        i3 == L0.N[2] - 1)
+                        continue;
+                    int gi = slot2c[L0.slot(i1, i2, i3, on1, on2)];
+                    int l = (a3 * nn + a2) * nn + a1;
+                    enodes[(size_t)e * 27 + l] = gi;
+                    if (gi >= 0) {
+                        if (cnt[gi] >= 8) return fail(PMG_EUNSUP, "coarse adjacency overflow");
+                        radj[(size_t)gi * 8 + cnt[gi]++] = e * 27 + l;
+                    }
+                }
+    }
+    std::vector<double> dg;
+    coarse_diagonal(L0, m->lam, m->h, dg);
+    std::vector<double> dc(std::max(N0, 1), 1.0);
+    for (int i = 0; i < N0; ++i) dc[i] = dg[cslot[i]];
+    CoarseArgs& a = m->ca;
+    a.N0 = N0;
+    a.ne = ne;
+    for (int d = 0; d < 3; ++d) {
+        a.n[d] = m->n[d];
+        a.el_m[d] = m->lv[0].t64.el_m[d];
+        a.el_L[d] = m->lv[0].t64.el_L[d];
+    }
+    a.p0 = p0;
+    a.lam = m->lam;
+    int rc;
+    auto up_int = [&](const int** dst, const std::vector<int>& v) -> int {
+        int* d = nullptr;
+        int r = m->alloc(&d, v.size());
+        if (r) return r;
+        if (hipMemcpy(d, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(PMG_EHIP, "hipMemcpy coarse tables");
+        *dst = d;
+        return 0;
+    };
+    if ((rc = up_int(&a.c_slot, cslot.empty() ? std::vector<int>(1, 0) : cslot))) return rc;
+    if ((rc = up_int(&a.e_nodes, enodes))) return rc;
+    if ((rc = up_int(&a.r_adj, radj))) return rc;
+    if ((rc = m->upload(&a.diag, dc))) return rc;
+    size_t nv = std::max(N0, 1);
+    if ((rc = m->alloc(&a.x, nv)) || (rc = m->alloc(&a.r, nv)) || (rc = m->alloc(&a.z, nv)) ||
+        (rc = m->alloc(&a.p, nv)) || (rc = m->alloc(&a.q, nv)) || (rc = m->alloc(&a.E, (size_t)ne * 27)))
+        return rc;
+    // workgroups: about one element per thread, 8..64 groups
+    int G = (ne + 255) / 256;
+    G = std::max(8, std::min(64, G));
+    m->coarse_blocks = G;
+    if ((rc = m->alloc(&a.partials, 2 * (size_t)G)) || (rc = m->alloc(&a.bar, 2)) ||
+        (rc = m->alloc(&a.err, 1)) || (rc = m->alloc(&a.iters, 1)))
+        return rc;
+    HIPCHK(hipMemset(a.bar, 0, 2 * sizeof(unsigned)));
+    HIPCHK(hipMemset(a.err, 0, sizeof(int)));
+    HIPCHK(hipMemset(a.iters, 0, sizeof(int)));
+    return 0;
+}
+
 int build_mesh(pmg_mesh* m) {
     auto degs = level_degrees(m->p);
     m->L = (int)degs.size() - 1;
@@ -187,19 +288,7 @@ int build_mesh(pmg_mesh* m) {
             if ((rc = m->alloc(&L.tb64, nc)) || (rc = m->alloc(&L.tb32, nc))) return rc;
         }
     }
-    // coarse CG workspace and Jacobi diagonal (FP64)
-    const Layout& L0 = m->lv[0].lay;
-    int64_t n0 = L0.len;
-    if ((rc = m->alloc(&m->cx, n0)) || (rc = m->alloc(&m->cr, n0)) || (rc = m->alloc(&m->cz, n0)) ||
-        (rc = m->alloc(&m->cp, n0)) || (rc = m->alloc(&m->cq, n0)))
-        return rc;
-    {
-        std::vector<double> dg;
-        coarse_diagonal(L0, m->lam, m->h, dg);
-        const double* d = nullptr;
-        if ((rc = m->upload(&d, dg))) return rc;
-        m->cdiag = const_cast<double*>(d);
-    }
+    if ((rc = build_coarse(m))) return rc;
     const Layout& Lf = m->lv.back().lay;
     int64_t nf = Lf.len;
     if ((rc = m->alloc(&m->w_u, nf)) || (rc = m->alloc(&m->w_r, nf)) || (rc = m->alloc(&m->w_s, nf)) ||
@@ -246,35 +335,28 @@ void residual(pmg_mesh* m, int l, const T* F, const T* u, T* y, hipStream_t st) 
     launch_sub_from<T>(F, y, L.lay.len, st);
 }
 
-// Jacobi-preconditioned CG on level 0 (FP64), x = 0 initially.
+// Jacobi-preconditioned CG on level 0 (FP64), x = 0 initially: one
+// persistent cooperative kernel.  b and x are level-0 skeleton arrays.
 int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st) {
     Level& L0 = m->lv[0];
-    const int64_t n = L0.lay.len;
-    HIPCHK(hipMemsetAsync(x, 0, n * sizeof(double), st));
-    HIPCHK(hipMemcpyAsync(m->cr, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    launch_jacobi(m->cr, m->cdiag, m->cz, n, m->partials, m->counter, m->scal + SC_RZ, st);
-    HIPCHK(hipMemcpyAsync(m->cp, m->cz, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    int rc = read_scalars(m, st);
-    if (rc) return rc;
-    const double rz0 = m->hscal[SC_RZ];
-    double rz = rz0;
-    const double tol2 = m->coarse_rtol * m->coarse_rtol;
-    int it = 0;
-    while (it < m->coarse_maxit) {
-        if (rz <= tol2 * rz0 || rz == 0.0) break;
-        launch_condensed_op<double>(L0.t64, m->cp, m->cq, st);
-        launch_dot2<double>(m->cp, m->cq, nullptr, n, m->partials, m->counter, m->scal + SC_PQ, st);
-        // sc layout for cg_xr: [rz, pq] -> SC_RZ, SC_RZ+1 must be adjacent: copy pq next to rz
-        launch_cg_xr(x, m->cr, m->cp, m->cq, m->scal + SC_RZ, n, st);
-        launch_jacobi(m->cr, m->cdiag, m->cz, n, m->partials, m->counter, m->scal + SC_RZN, st);
-        launch_cg_p(m->cp, m->cz, m->scal + SC_RZN, m->scal + SC_RZ, n, st);
-        HIPCHK(hipMemcpyAsync(m->scal + SC_RZ, m->scal + SC_RZN, sizeof(double), hipMemcpyDeviceToDevice, st));
-        ++it;
-        if ((rc = read_scalars(m, st))) return rc;
-        rz = m->hscal[SC_RZ];
+    HIPCHK(hipMemsetAsync(x, 0, L0.lay.len * sizeof(double), st));
+    if (m->ca.N0 == 0) return 0;
+    HIPCHK(launch_coarse_cg(m->ca, m->coarse_blocks, b, x, m->coarse_maxit, m->coarse_rtol, st));
+    return 0;
+}
+
+// Read and reset the device-side coarse iteration counter and error flag.
+int coarse_stats(pmg_mesh* m, hipStream_t st, int* iters) {
+    int h[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&h[0], m->ca.iters, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&h[1], m->ca.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemsetAsync(m->ca.iters, 0, sizeof(int), st));
+    if (h[1]) {
+        hipMemsetAsync(m->ca.err, 0, sizeof(int), st);
+        return fail(PMG_EHIP, "coarse solver: grid barrier wait timed out");
     }
-    m->coarse_last = it;
-    m->coarse_total += it;
+    *iters = h[0];
     return 0;
 }
 
@@ -583,9 +665,12 @@ int pmg_vcycle(pmg_mesh* m, int dtype, const void* r, void* z, void* stream) {
 int pmg_coarse_solve(pmg_mesh* m, const double* F0, double* u0, int* iters, void* stream) {
     if (check_mesh(m)) return PMG_EINVAL;
     if (!F0 || !u0) return fail(PMG_EINVAL, "null pointer");
-    int rc = coarse_cg(m, F0, u0, S(stream));
-    if (rc) return rc;
-    if (iters) *iters = m->coarse_last;
+    int it = 0, rc;
+    if ((rc = coarse_stats(m, S(stream), &it))) return rc;
+    if ((rc = coarse_cg(m, F0, u0, S(stream)))) return rc;
+    if ((rc = coarse_stats(m, S(stream), &it))) return rc;
+    m->coarse_last = it;
+    if (iters) *iters = it;
     return 0;
 }
 
@@ -615,7 +700,11 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
     const int64_t n = Lf.len;
     pmg_stats stats;
     std::memset(&stats, 0, sizeof(stats));
-    m->coarse_total = 0;
+    {
+        int dummy;
+        int rc0 = coarse_stats(m, st, &dummy);
+        if (rc0) return rc0;
+    }
     hipEvent_t ev[4];
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
     HIPCHK(hipEventRecord(ev[0], st));
@@ -698,7 +787,12 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
     stats.iters = it;
     stats.status = status;
     stats.rel_res = stats.res0 > 0 ? std::sqrt(rr) / stats.res0 : 0.0;
-    stats.coarse_iters = (int)m->coarse_total;
+    {
+        int cit = 0;
+        int rc1 = coarse_stats(m, st, &cit);
+        if (rc1) return rc1;
+        stats.coarse_iters = cit;
+    }
     stats.t_pre_ms = t0;
     stats.t_iter_ms = t1;
     stats.t_post_ms = t2;

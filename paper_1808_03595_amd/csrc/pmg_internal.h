@@ -89,3 +89,28 @@ void coarse_diagonal(const Layout& lay, double lam, const std::vector<double> h[
                      std::vector<double>& diag);
 
 }  // namespace pmg
+
+namespace pmg {
+
+// Coarse-level (p_0 <= 2) problem in compact numbering, for the persistent
+// Jacobi-CG kernel.  Unknown i lives at plane-layout slot c_slot[i].
+struct CoarseArgs {
+    int N0;          // unknowns
+    int ne;          // elements
+    int n[3];
+    int p0;          // 1 or 2
+    double lam;
+    const int* c_slot;    // [N0]
+    const int* e_nodes;   // [ne][27] compact index of local node or -1
+    const int* r_adj;     // [N0][8]  e * 27 + local, or -1
+    const double* diag;   // [N0]
+    const double* el_m[3];  // level-0 element tables
+    const double* el_L[3];
+    double *x, *r, *z, *p, *q, *E;  // work vectors ([N0], E: [ne][27])
+    double* partials;     // [2 * blocks]
+    unsigned* bar;        // [2]: arrival counter, generation
+    int* err;             // set to 1 if a barrier wait timed out
+    int* iters;           // accumulated iteration count
+};
+
+}  // namespace pmg

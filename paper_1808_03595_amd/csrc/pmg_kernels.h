@@ -8,6 +8,8 @@ namespace pmg {
 constexpr int REDUCE_BLOCKS = 512;
 
 hipError_t init_kernel_attributes();
+hipError_t launch_coarse_cg(const CoarseArgs& a, int blocks, const double* b, double* x, int maxit,
+                            double rtol, hipStream_t st);
 
 template <typename T> void launch_grid_to_skel(const Layout&, const double*, T*, hipStream_t);
 template <typename T> void launch_skel_to_grid(const Layout&, const T*, double*, hipStream_t);

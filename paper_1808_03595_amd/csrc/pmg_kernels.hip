@@ -941,6 +941,216 @@ __global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ z, con
 }
 
 // ---------------------------------------------------------------------------
+// Coarse-grid solve (Sec. 4.1: CG on the condensed system at p_0 = 2) as one
+// persistent cooperative kernel: Jacobi-preconditioned CG in the
+// single-reduction (Chronopoulos-Gear) form, two grid barriers per
+// iteration.  Rows (compact unknowns) and elements are split into
+// contiguous chunks per workgroup; the condensed operator is applied element
+// by element into a per-element buffer E and gathered per row, so every
+// sum is taken in a fixed order and the result is deterministic.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nb, int* err) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned g = __hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned prev = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == nb - 1) {
+            __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            // bounded wait: all blocks are co-resident (cooperative launch),
+            // the limit only guards against a broken launch
+            long spins = 0;
+            while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (1L << 26)) {
+                    atomicExch(err, 1);
+                    break;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    __threadfence();
+}
+
+// Sum of per-block pairs partials[2*b + k] over all blocks, same order in
+// every block; result broadcast to all threads.
+__device__ inline void sum_partials(const double* partials, double& a, double& b) {
+    __shared__ double red[16];
+    __shared__ double res[2];
+    double va = 0.0, vb = 0.0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
+        va += __hip_atomic_load(partials + 2 * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        vb += __hip_atomic_load(partials + 2 * i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    double sa = block_sum(va, red);
+    __syncthreads();
+    double sb = block_sum(vb, red);
+    if (threadIdx.x == 0) {
+        res[0] = sa;
+        res[1] = sb;
+    }
+    __syncthreads();
+    a = res[0];
+    b = res[1];
+    __syncthreads();
+}
+
+__device__ inline void write_partials(double* partials, double a, double b) {
+    __shared__ double red[16];
+    double sa = block_sum(a, red);
+    __syncthreads();
+    double sb = block_sum(b, red);
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(partials + 2 * blockIdx.x, sa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(partials + 2 * blockIdx.x + 1, sb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// y_e = Hhat_e z_e for the elements of this block, one element per thread;
+// returns this thread's part of sum_e y_e . z_e.
+template <int P0>
+__device__ double coarse_elements_t(const CoarseArgs& a, int e0, int e1) {
+    constexpr int nn = P0 + 1, nl = nn * nn * nn;
+    double part = 0.0;
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        int gi[nl];
+        double u[nl];
+#pragma unroll
+        for (int l = 0; l < nl; ++l) {
+            gi[l] = a.e_nodes[e * 27 + l];
+            u[l] = gi[l] >= 0 ? a.z[gi[l]] : 0.0;
+        }
+        const int c1 = e % a.n[0], c2 = (e / a.n[0]) % a.n[1], c3 = e / (a.n[0] * a.n[1]);
+        double m1[nn], m2[nn], m3[nn], L1[nn * nn], L2[nn * nn], L3[nn * nn];
+#pragma unroll
+        for (int i = 0; i < nn; ++i) {
+            m1[i] = a.el_m[0][c1 * nn + i];
+            m2[i] = a.el_m[1][c2 * nn + i];
+            m3[i] = a.el_m[2][c3 * nn + i];
+        }
+#pragma unroll
+        for (int i = 0; i < nn * nn; ++i) {
+            L1[i] = a.el_L[0][c1 * nn * nn + i];
+            L2[i] = a.el_L[1][c2 * nn * nn + i];
+            L3[i] = a.el_L[2][c3 * nn * nn + i];
+        }
+        double s = 0.0, hii = 1.0;
+        if (P0 == 2) {
+            // Schur complement of the single interior node (1,1,1):
+            // s = H_IB u_B, hii = H_II
+            s = m3[1] * m2[1] * (L1[3] * u[13 - 1] + L1[5] * u[13 + 1]) +
+                m3[1] * m1[1] * (L2[3] * u[13 - 3] + L2[5] * u[13 + 3]) +
+                m2[1] * m1[1] * (L3[3] * u[13 - 9] + L3[5] * u[13 + 9]);
+            hii = a.lam * m1[1] * m2[1] * m3[1] + m3[1] * m2[1] * L1[4] + m3[1] * m1[1] * L2[4] +
+                  m2[1] * m1[1] * L3[4];
+        }
+        const double sh = s / hii;
+#pragma unroll
+        for (int l = 0; l < nl; ++l) {
+            if (gi[l] < 0) continue;
+            const int a1 = l % nn, a2 = (l / nn) % nn, a3 = l / (nn * nn);
+            double x1 = 0.0, x2 = 0.0, x3 = 0.0;
+#pragma unroll
+            for (int j = 0; j < nn; ++j) {
+                x1 += L1[a1 * nn + j] * u[(a3 * nn + a2) * nn + j];
+                x2 += L2[a2 * nn + j] * u[(a3 * nn + j) * nn + a1];
+                x3 += L3[a3 * nn + j] * u[(j * nn + a2) * nn + a1];
+            }
+            double t = a.lam * m1[a1] * m2[a2] * m3[a3] * u[l] + m3[a3] * m2[a2] * x1 + m3[a3] * m1[a1] * x2 +
+                       m2[a2] * m1[a1] * x3;
+            if (P0 == 2) {
+                double col = 0.0;
+                if (a2 == 1 && a3 == 1) col = m3[1] * m2[1] * L1[a1 * 3 + 1];
+                else if (a1 == 1 && a3 == 1) col = m3[1] * m1[1] * L2[a2 * 3 + 1];
+                else if (a1 == 1 && a2 == 1) col = m2[1] * m1[1] * L3[a3 * 3 + 1];
+                t -= sh * col;
+            }
+            a.E[e * 27 + l] = t;
+            part += t * u[l];
+        }
+    }
+    return part;
+}
+
+__device__ inline double coarse_elements(const CoarseArgs& a, int e0, int e1) {
+    return a.p0 == 2 ? coarse_elements_t<2>(a, e0, e1) : coarse_elements_t<1>(a, e0, e1);
+}
+
+__global__ void __launch_bounds__(256) k_coarse_cg(CoarseArgs a, const double* __restrict__ b_in,
+                                                   double* __restrict__ x_out, int maxit, double rtol) {
+    const unsigned nb = gridDim.x;
+    const int R = (a.N0 + (int)nb - 1) / (int)nb;
+    const int r0 = blockIdx.x * R, r1 = min(a.N0, r0 + R);
+    const int EB = (a.ne + (int)nb - 1) / (int)nb;
+    const int e0 = min(a.ne, (int)blockIdx.x * EB), e1 = min(a.ne, e0 + EB);
+    // r = b, x = 0, z = D^-1 r, gamma partial
+    double g_part = 0.0;
+    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        double ri = b_in[a.c_slot[i]];
+        double zi = ri / a.diag[i];
+        a.x[i] = 0.0;
+        a.r[i] = ri;
+        a.z[i] = zi;
+        g_part += ri * zi;
+    }
+    grid_barrier(a.bar, nb, a.err);
+    double d_part = coarse_elements(a, e0, e1);
+    write_partials(a.partials, g_part, d_part);
+    grid_barrier(a.bar, nb, a.err);
+    double gamma, delta;
+    sum_partials(a.partials, gamma, delta);
+    const double gamma0 = gamma;
+    int it = 0;
+    if (gamma > 0.0 && maxit > 0) {
+        double alpha = gamma / delta, beta = 0.0;
+        bool first = true;
+        while (true) {
+            // rows: w = gather(E); p = z + beta p; q = w + beta q;
+            //       x += alpha p; r -= alpha q; z = D^-1 r; gamma partial
+            g_part = 0.0;
+            for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+                double w = 0.0;
+                const int* adj = a.r_adj + (size_t)i * 8;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    int s = adj[k];
+                    if (s >= 0) w += a.E[s];
+                }
+                double pi = first ? a.z[i] : a.z[i] + beta * a.p[i];
+                double qi = first ? w : w + beta * a.q[i];
+                a.p[i] = pi;
+                a.q[i] = qi;
+                double xi = a.x[i] + alpha * pi;
+                double ri = a.r[i] - alpha * qi;
+                a.x[i] = xi;
+                a.r[i] = ri;
+                double zi = ri / a.diag[i];
+                a.z[i] = zi;
+                g_part += ri * zi;
+            }
+            first = false;
+            ++it;
+            if (it >= maxit) break;
+            grid_barrier(a.bar, nb, a.err);
+            d_part = coarse_elements(a, e0, e1);
+            write_partials(a.partials, g_part, d_part);
+            grid_barrier(a.bar, nb, a.err);
+            double gnew;
+            sum_partials(a.partials, gnew, delta);
+            if (gnew <= rtol * rtol * gamma0) break;
+            beta = gnew / gamma;
+            alpha = gnew / (delta - beta * gnew / alpha);
+            gamma = gnew;
+        }
+    }
+    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) x_out[a.c_slot[i]] = a.x[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.iters, it);
+}
+
+// ---------------------------------------------------------------------------
 // MLP 3 -> 64 -> 64 -> nout, FP32 (learned smoother damping).
 // One thread per sample for the hidden layers; parameters staged in LDS.
 // ---------------------------------------------------------------------------
@@ -1247,6 +1457,15 @@ void launch_mlp_adam(float* prm, const float* g, float* m, float* v, int n, floa
                      float eps, int t, hipStream_t st) {
     float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
     hipLaunchKernelGGL(k_mlp_adam, dim3(nblk(n)), dim3(256), 0, st, prm, g, m, v, n, lr, b1, b2, eps, c1, c2);
+}
+
+hipError_t launch_coarse_cg(const CoarseArgs& a, int blocks, const double* b, double* x, int maxit,
+                            double rtol, hipStream_t st) {
+    CoarseArgs aa = a;
+    const double* bb = b;
+    double* xx = x;
+    void* args[] = {&aa, &bb, &xx, &maxit, &rtol};
+    return hipLaunchCooperativeKernel((const void*)k_coarse_cg, dim3(blocks), dim3(256), args, 0, st);
 }
 
 hipError_t init_kernel_attributes() {
