@@ -145,7 +145,10 @@ int fill_tabs(pmg_mesh* m, LevelTabs<T>& tb, const HostTables& t, const Layout& 
         if ((rc = m->upload(&tb.el_cp[d], t.el_cp[d]))) break;
         if ((rc = m->upload(&tb.st_S[d], t.st_S[d]))) break;
         if ((rc = m->upload(&tb.st_lam[d], t.st_lam[d]))) break;
+        if ((rc = m->upload(&tb.st_S16[d], t.st_S16[d]))) break;
+        if ((rc = m->upload(&tb.st_lam16[d], t.st_lam16[d]))) break;
     }
+    if (!rc) rc = m->upload(&tb.st_w16, t.st_w16);
     if (!rc) rc = m->upload(&tb.st_w, t.st_w);
     if (!rc) rc = m->upload(&tb.J, t.J);
     return rc;

@@ -61,6 +61,11 @@ struct LevelTabs {
     const T* st_S[3];     // nS^2         [i][k], identity padded
     const T* st_lam[3];   // nS           padded eigenvalues = 1
     const T* st_w;        // nS           1D weights
+    // the same star tables padded to 16 x 16 (zeros; eigenvalue 1; weight 0)
+    // for the matrix-core smoother, present when nS <= 16
+    const T* st_S16[3];   // 256 per vertex
+    const T* st_lam16[3]; // 16 per vertex
+    const T* st_w16;      // 16
     // interpolation from the next coarser level: (p+1) x (pc+1), row-major
     const T* J;
     int pc;
@@ -71,6 +76,7 @@ struct HostTables {
     std::vector<double> el_m[3], el_L[3], el_Sinv[3], el_MS[3], el_lam[3],
         el_c0[3], el_cp[3], st_S[3], st_lam[3];
     std::vector<double> st_w, J;
+    std::vector<double> st_S16[3], st_lam16[3], st_w16;
 };
 
 // Host set-up (pmg_setup.cpp)

@@ -8,6 +8,7 @@ namespace pmg {
 constexpr int REDUCE_BLOCKS = 512;
 
 hipError_t init_kernel_attributes();
+void set_mfma_min_degree(int p);
 hipError_t launch_coarse_cg(const CoarseArgs& a, int blocks, const double* b, double* x, int maxit,
                             double rtol, hipStream_t st);
 

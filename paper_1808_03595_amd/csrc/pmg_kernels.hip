@@ -436,6 +436,244 @@ __global__ void __launch_bounds__(256) k_smoother(LevelTabs<T> tb, const T* __re
 }
 
 // ---------------------------------------------------------------------------
+// Matrix-core star smoother for n_S = 2p - 1 <= 16 (p <= 8).
+//
+// One wavefront per star.  The twelve 2D transforms of Alg. 1 are 16x16x16
+// products on MFMA (v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4); the result of
+// the first product of each pair stays in registers and feeds the second
+// product directly, because its output lane layout is the input layout of
+// the B operand when the k index of step s in lane group q is chosen as the
+// output row held in register s by that group.  The eigenspace pass runs
+// on VALU in 4x4x4 tiles per lane; its three contractions are reduced
+// across the four tiles that share an index through LDS.  Corrections are
+// added to the plane layout with hardware atomics (one launch, no colours).
+// ---------------------------------------------------------------------------
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // row of the 16x16 result held in register v by lane group q (FP64:
+    // rows interleaved across the groups)
+    static __device__ __forceinline__ int row(int q, int v) { return q + 4 * v; }
+    // hardware reciprocal (relative error ~5e-8) refined by one Newton step
+    static __device__ __forceinline__ double rcp(double d) {
+        double r = __builtin_amdgcn_rcp(d);
+        double e = __builtin_fma(-d, r, 1.0);
+        return __builtin_fma(r, e, r);
+    }
+};
+template <> struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // FP32: rows blocked per group
+    static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
+    static __device__ __forceinline__ float rcp(float d) { return __builtin_amdgcn_rcpf(d); }
+};
+
+// C = A B for 16 x 16 operands held as a[s] = A[j][row(q,s)] and
+// b[s] = B[row(q,s)][j] in lane (q, j); returns c[v] = C[row(q,v)][j].
+template <typename T>
+__device__ __forceinline__ typename Mfma<T>::v4 gemm16(const T a[4], const T b[4]) {
+    typename Mfma<T>::v4 c = {0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c = Mfma<T>::mma(a[s], b[s], c);
+    return c;
+}
+
+template <typename T>
+__device__ __forceinline__ void v4_to(const typename Mfma<T>::v4& c, T o[4]) {
+    o[0] = c[0];
+    o[1] = c[1];
+    o[2] = c[2];
+    o[3] = c[3];
+}
+
+constexpr int SM_MFMA_PER_WAVE = 3072;
+
+template <typename T, int WPB>
+__global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, const T* __restrict__ r,
+                                                            T* __restrict__ du, T omega) {
+    typedef Mfma<T> M;
+    typedef typename M::v4 v4;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int q = lane >> 4, j = lane & 15;
+    T* sm = reinterpret_cast<T*>(smem_raw) + wv * SM_MFMA_PER_WAVE;
+    const Layout& L = tb.lay;
+    const int p = L.p, nS = 2 * p - 1, c = p - 1;
+    const int nv1 = L.n[0] + 1, nv2 = L.n[1] + 1, nv3 = L.n[2] + 1;
+    const int star = blockIdx.x * WPB + wv;
+    bool active = star < nv1 * nv2 * nv3;
+    int v1 = 0, v2 = 0, v3 = 0;
+    if (active) {
+        v1 = star % nv1;
+        v2 = (star / nv1) % nv2;
+        v3 = star / (nv1 * nv2);
+        bool b1 = v1 == 0 || v1 == L.n[0], b2 = v2 == 0 || v2 == L.n[1], b3 = v3 == 0 || v3 == L.n[2];
+        if (b1 && b2 && b3) active = false;  // corner: all three planes Dirichlet
+    }
+    const T* S1 = tb.st_S16[0] + (size_t)v1 * 256;
+    const T* S2 = tb.st_S16[1] + (size_t)v2 * 256;
+    const T* S3 = tb.st_S16[2] + (size_t)v3 * 256;
+    const int c1 = v1 * p, c2 = v2 * p, c3 = v3 * p;
+    // S in both operand patterns: Sb[s] = S[row(q,s)][j], Sa[s] = S[j][row(q,s)]
+    T Sb1[4], Sb2[4], Sb3[4], Sa1[4], Sa2[4], Sa3[4];
+    T f1[4], f2[4], f3[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = M::row(q, s);
+        Sb1[s] = S1[k * 16 + j];
+        Sb2[s] = S2[k * 16 + j];
+        Sb3[s] = S3[k * 16 + j];
+        Sa1[s] = S1[j * 16 + k];
+        Sa2[s] = S2[j * 16 + k];
+        Sa3[s] = S3[j * 16 + k];
+        // face residuals as A operands: F[a = j][b = k]
+        const int oa = j - c, ob = k - c;
+        const bool ok = active && j < nS && k < nS;
+        T x1 = 0, x2 = 0, x3 = 0;
+        if (ok) {
+            int i1 = c1 + ob, i2 = c2 + ob, i3 = c3 + oa, i2a = c2 + oa;
+            if (i2 >= 0 && i2 < L.N[1] && i3 >= 0 && i3 < L.N[2])
+                x1 = r[L.plane0(v1) + (int64_t)i3 * L.pitch[0] + i2];
+            if (i1 >= 0 && i1 < L.N[0] && i3 >= 0 && i3 < L.N[2])
+                x2 = r[L.plane1(v2) + (int64_t)i3 * L.pitch[1] + i1];
+            if (i1 >= 0 && i1 < L.N[0] && i2a >= 0 && i2a < L.N[1])
+                x3 = r[L.plane2(v3) + (int64_t)i2a * L.pitch[2] + i1];
+        }
+        f1[s] = x1;
+        f2[s] = x2;
+        f3[s] = x3;
+    }
+    // G1 = S3^T (F1 S2), G2 = S3^T (F2 S1), G3 = S2^T (F3 S1)
+    T t[4];
+    v4_to<T>(gemm16<T>(f1, Sb2), t);
+    v4 g1 = gemm16<T>(Sb3, t);
+    v4_to<T>(gemm16<T>(f2, Sb1), t);
+    v4 g2 = gemm16<T>(Sb3, t);
+    v4_to<T>(gemm16<T>(f3, Sb1), t);
+    v4 g3 = gemm16<T>(Sb2, t);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int rr = M::row(q, v);
+        sm[rr * 16 + j] = g1[v];        // G1[k3][k2]
+        sm[256 + rr * 16 + j] = g2[v];  // G2[k3][k1]
+        sm[512 + rr * 16 + j] = g3[v];  // G3[k2][k1]
+    }
+    __syncthreads();
+    // eigenspace pass on the 4x4x4 tile (t1, t2, t3) of this lane
+    const int t1 = lane & 3, t2 = (lane >> 2) & 3, t3 = lane >> 4;
+    const int k1b = 4 * t1, k2b = 4 * t2, k3b = 4 * t3;
+    T a1[4], a2[4], a3[4], l3[4], E12[4][4], G3r[4][4];
+    T H1p[4][4], H2p[4][4], H3p[4][4];
+    {
+        const T* L1 = tb.st_lam16[0] + v1 * 16;
+        const T* L2 = tb.st_lam16[1] + v2 * 16;
+        const T* L3 = tb.st_lam16[2] + v3 * 16;
+        T l1[4], l2[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            a1[i] = S1[c * 16 + k1b + i];
+            a2[i] = S2[c * 16 + k2b + i];
+            a3[i] = S3[c * 16 + k3b + i];
+            l1[i] = L1[k1b + i];
+            l2[i] = L2[k2b + i];
+            l3[i] = L3[k3b + i];
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                E12[b][a] = tb.lam + l2[b] + l1[a];
+                G3r[b][a] = sm[512 + (k2b + b) * 16 + k1b + a];
+                H1p[b][a] = 0;
+                H2p[b][a] = 0;
+                H3p[b][a] = 0;
+            }
+    }
+#pragma unroll
+    for (int i3 = 0; i3 < 4; ++i3) {
+        const int k3 = k3b + i3;
+        T g1r[4], g2r[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            g1r[i] = sm[k3 * 16 + k2b + i];
+            g2r[i] = sm[256 + k3 * 16 + k1b + i];
+        }
+#pragma unroll
+        for (int i2 = 0; i2 < 4; ++i2)
+#pragma unroll
+            for (int i1 = 0; i1 < 4; ++i1) {
+                T e = a1[i1] * g1r[i2] + a2[i2] * g2r[i1] + a3[i3] * G3r[i2][i1];
+                T V = e * M::rcp(E12[i2][i1] + l3[i3]);
+                H1p[i3][i2] += a1[i1] * V;
+                H2p[i3][i1] += a2[i2] * V;
+                H3p[i2][i1] += a3[i3] * V;
+            }
+    }
+    __syncthreads();  // all G reads done; reuse the region for the partials
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            sm[(t1 * 16 + k3b + b) * 16 + k2b + a] = H1p[b][a];          // P1[t1][k3][k2]
+            sm[1024 + (t2 * 16 + k3b + b) * 16 + k1b + a] = H2p[b][a];   // P2[t2][k3][k1]
+            sm[2048 + (t3 * 16 + k2b + b) * 16 + k1b + a] = H3p[b][a];   // P3[t3][k2][k1]
+        }
+    __syncthreads();
+    T h1[4], h2[4], h3[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = M::row(q, s);
+        T x = 0, y = 0, z = 0;
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            x += sm[(tt * 16 + j) * 16 + k];
+            y += sm[1024 + (tt * 16 + j) * 16 + k];
+            z += sm[2048 + (tt * 16 + j) * 16 + k];
+        }
+        h1[s] = x;  // H1[k3 = j][k2 = k]
+        h2[s] = y;  // H2[k3 = j][k1 = k]
+        h3[s] = z;  // H3[k2 = j][k1 = k]
+    }
+    // U1 = S3 (H1 S2^T), U2 = S3 (H2 S1^T), U3 = S2 (H3 S1^T)
+    v4_to<T>(gemm16<T>(h1, Sa2), t);
+    v4 u1 = gemm16<T>(Sa3, t);
+    v4_to<T>(gemm16<T>(h2, Sa1), t);
+    v4 u2 = gemm16<T>(Sa3, t);
+    v4_to<T>(gemm16<T>(h3, Sa1), t);
+    v4 u3 = gemm16<T>(Sa2, t);
+    if (!active) return;
+    const T* w = tb.st_w16;
+    const int ob = j - c;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int a = M::row(q, v), oa = a - c;
+        if (a >= nS || j >= nS) continue;
+        const T wt = omega * w[a] * w[j];
+        {   // face normal to x1: (i1, i2, i3) = (c1, c2 + ob, c3 + oa)
+            int i1 = c1, i2 = c2 + ob, i3 = c3 + oa;
+            if (i2 >= 0 && i2 < L.N[1] && i3 >= 0 && i3 < L.N[2] && !is_dir(L, i1, i2, i3))
+                unsafeAtomicAdd(du + L.plane0(v1) + (int64_t)i3 * L.pitch[0] + i2, wt * u1[v]);
+        }
+        if (ob != 0) {  // face normal to x2 without the x3-axis line (stored in family 0)
+            int i1 = c1 + ob, i2 = c2, i3 = c3 + oa;
+            if (i1 >= 0 && i1 < L.N[0] && i3 >= 0 && i3 < L.N[2] && !is_dir(L, i1, i2, i3))
+                unsafeAtomicAdd(du + L.plane1(v2) + (int64_t)i3 * L.pitch[1] + i1, wt * u2[v]);
+        }
+        if (ob != 0 && oa != 0) {  // face normal to x3 without both axis lines
+            int i1 = c1 + ob, i2 = c2 + oa, i3 = c3;
+            if (i1 >= 0 && i1 < L.N[0] && i2 >= 0 && i2 < L.N[1] && !is_dir(L, i1, i2, i3))
+                unsafeAtomicAdd(du + L.plane2(v3) + (int64_t)i2 * L.pitch[2] + i1, wt * u3[v]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Grid transfers (Sec. 4.1).  The fine condensed values are the tensor
 // Lagrange interpolation of the coarse ones; on a plane this is the 2D
 // interpolation of the coarse plane values (including its edge lines).
@@ -1299,6 +1537,10 @@ __global__ void k_mlp_adam(float* __restrict__ prm, const float* __restrict__ g,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// smallest degree that uses the matrix-core smoother (settable for tests)
+int g_mfma_min_p = 3;
+void set_mfma_min_degree(int p) { g_mfma_min_p = p; }
+
 static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 static int color_count(const int n[3], int color) {
@@ -1338,8 +1580,17 @@ void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t s
     }
 }
 
+constexpr int MFMA_WPB = 2;
+
 template <typename T>
 void launch_smoother_add(const LevelTabs<T>& tb, const T* r, T* du, T omega, hipStream_t st) {
+    if (2 * tb.lay.p - 1 <= 16 && tb.lay.p >= g_mfma_min_p) {
+        int ns = (tb.lay.n[0] + 1) * (tb.lay.n[1] + 1) * (tb.lay.n[2] + 1);
+        size_t smm = sizeof(T) * SM_MFMA_PER_WAVE * MFMA_WPB;
+        hipLaunchKernelGGL((k_smoother_mfma<T, MFMA_WPB>), dim3((ns + MFMA_WPB - 1) / MFMA_WPB),
+                           dim3(64 * MFMA_WPB), smm, st, tb, r, du, omega);
+        return;
+    }
     size_t sm = smem_smoother<T>(tb.lay.p);
     int nv[3] = {tb.lay.n[0] + 1, tb.lay.n[1] + 1, tb.lay.n[2] + 1};
     for (int c = 0; c < 8; ++c) {
@@ -1475,7 +1726,8 @@ hipError_t init_kernel_attributes() {
         (const void*)k_smoother<double>,     (const void*)k_smoother<float>,
         (const void*)k_prolong_add<double>,  (const void*)k_prolong_add<float>,
         (const void*)k_restrict_planes<double>, (const void*)k_restrict_planes<float>,
-        (const void*)k_condense,             (const void*)k_recover};
+        (const void*)k_condense,             (const void*)k_recover,
+        (const void*)k_smoother_mfma<double, MFMA_WPB>, (const void*)k_smoother_mfma<float, MFMA_WPB>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
