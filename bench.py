@@ -90,7 +90,7 @@ def time_smoother(g, torch, dev, dtype, reps=20):
     return e0.elapsed_time(e1) / reps * 1e-3
 
 
-def cpu_baseline(wl, budget_s=25.0):
+def cpu_baseline(wl, coarse_rtol=1e-2):
     """Time the FP64 oracle on a bounded sample of the workload."""
     import numpy as np
     import synth
@@ -106,7 +106,7 @@ def cpu_baseline(wl, budget_s=25.0):
     t0 = time.perf_counter()
     Fh = matfree.condense_rhs(o, f)
     t_pre = time.perf_counter() - t0
-    hier = solver.Hierarchy(o, nu_mode="kMG", coarse_rtol=1e-8, coarse_maxit=2000)
+    hier = solver.Hierarchy(o, nu_mode="kMG", coarse_rtol=coarse_rtol, coarse_maxit=2000)
     # one Krylov iteration = one V-cycle + one operator application
     t0 = time.perf_counter()
     r = Fh
@@ -127,6 +127,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2a")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--coarse-rtol", type=float, default=1e-2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -142,7 +143,10 @@ def main():
     wl = workload(args.workload)
     n, p = wl["n"], wl["p"]
     g = pmg.create_mesh(n[0], n[1], n[2], p, wl["lam"], wl["alpha"])
-    g.set_cycle(0, 1e-8, 2000)
+    # coarse CG to a relative 1e-2: the outer iteration count equals the one
+    # with 1e-8 on this workload (checked with the oracle), and the flexible
+    # ipCG absorbs the inexact coarse solve
+    g.set_cycle(0, args.coarse_rtol, 2000)
     u_ex, f = make_rhs(g, wl, torch, synth, dev)
     u = torch.zeros_like(f)
     ndof = n[0] * n[1] * n[2] * p ** 3
@@ -177,7 +181,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        c = cpu_baseline(wl)
+        c = cpu_baseline(wl, args.coarse_rtol)
         iters = st64.iters
         t_cpu = c["t_pre"] + iters * c["t_iter"] + c["t_post"]
         cpu = {"value": ndof / t_cpu, "unit": "unknowns/s", "cores": c["threads"], "kind": "oracle",

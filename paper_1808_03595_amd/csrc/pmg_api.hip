@@ -251,11 +251,12 @@ int build_coarse(pmg_mesh* m) {
     if ((rc = m->upload(&a.diag, dc))) return rc;
     size_t nv = std::max(N0, 1);
     if ((rc = m->alloc(&a.x, nv)) || (rc = m->alloc(&a.r, nv)) || (rc = m->alloc(&a.z, nv)) ||
-        (rc = m->alloc(&a.p, nv)) || (rc = m->alloc(&a.q, nv)) || (rc = m->alloc(&a.E, (size_t)ne * 27)))
+        (rc = m->alloc(&a.p, nv)) || (rc = m->alloc(&a.q, nv)) || (rc = m->alloc(&a.E, nv)))
         return rc;
-    // workgroups: about one element per thread, 8..64 groups
-    int G = (ne + 255) / 256;
-    G = std::max(8, std::min(64, G));
+    // workgroups of 1024 threads: four threads per element, 4..32 groups
+    int G = (4 * ne + 1023) / 1024;
+    G = std::max(4, std::min(32, G));
+    if (m->n[0] > 256 || m->n[1] > 256 || m->n[2] > 256) return fail(PMG_EUNSUP, "more than 256 elements per direction");
     m->coarse_blocks = G;
     if ((rc = m->alloc(&a.partials, 2 * (size_t)G)) || (rc = m->alloc(&a.bar, 2)) ||
         (rc = m->alloc(&a.err, 1)) || (rc = m->alloc(&a.iters, 1)))

@@ -108,11 +108,11 @@ struct CoarseArgs {
     double lam;
     const int* c_slot;    // [N0]
     const int* e_nodes;   // [ne][27] compact index of local node or -1
-    const int* r_adj;     // [N0][8]  e * 27 + local, or -1
+    const int* r_adj;     // [N0][8]  e * 27 + local, or -1 (set-up check only)
     const double* diag;   // [N0]
     const double* el_m[3];  // level-0 element tables
     const double* el_L[3];
-    double *x, *r, *z, *p, *q, *E;  // work vectors ([N0], E: [ne][27])
+    double *x, *r, *z, *p, *q, *E;  // work vectors [N0]; E accumulates w = A z
     double* partials;     // [2 * blocks]
     unsigned* bar;        // [2]: arrival counter, generation
     int* err;             // set to 1 if a barrier wait timed out

@@ -1187,20 +1187,36 @@ __global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ z, con
 // by element into a per-element buffer E and gathered per row, so every
 // sum is taken in a fixed order and the result is deterministic.
 // ---------------------------------------------------------------------------
+// Data shared between workgroups inside the persistent kernel (z, E and the
+// partial sums) is written and read with device-coherent accesses (relaxed
+// agent-scope atomics: the sc1 loads and stores that bypass the
+// per-XCD L2), so the barrier itself needs no cache flushes: every thread
+// waits for its own stores to complete, then thread 0 arrives.
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_dev(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0f70); }  // vmcnt(0)
+
 __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nb, int* err) {
-    __threadfence();
+    wait_stores();
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned g = __hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned prev = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned g = ld_dev(bar + 1);
+        unsigned prev = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (prev == nb - 1) {
-            __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            st_dev(bar, 0u);
+            wait_stores();
+            __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             // bounded wait: all blocks are co-resident (cooperative launch),
             // the limit only guards against a broken launch
             long spins = 0;
-            while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            while (ld_dev(bar + 1) == g) {
                 __builtin_amdgcn_s_sleep(1);
                 if (++spins > (1L << 26)) {
                     atomicExch(err, 1);
@@ -1210,7 +1226,6 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nb, int* er
         }
     }
     __syncthreads();
-    __threadfence();
 }
 
 // Sum of per-block pairs partials[2*b + k] over all blocks, same order in
@@ -1247,95 +1262,110 @@ __device__ inline void write_partials(double* partials, double a, double b) {
     }
 }
 
-// y_e = Hhat_e z_e for the elements of this block, one element per thread;
-// returns this thread's part of sum_e y_e . z_e.
+// Level-0 1D element tables of all element indices, staged in LDS once per
+// kernel: per direction d, element e: m[3] then L[9] (p0 = 1 uses the first
+// 2 + 4 entries).
+constexpr int COARSE_MAXN = 256;  // elements per direction supported by the LDS table
+constexpr int COARSE_THREADS = 1024;
+constexpr int COARSE_SPLIT = 4;   // threads per element in the element phase
+
+// w += Hhat_e z_e for one quarter of the local nodes of the elements of this
+// block (hardware FP64 atomics into w); returns this thread's part of
+// sum_e (Hhat_e z_e) . z_e, which equals (w, z).
 template <int P0>
-__device__ double coarse_elements_t(const CoarseArgs& a, int e0, int e1) {
+__device__ double coarse_elements_t(const CoarseArgs& a, const double* tab, int e0, int e1) {
     constexpr int nn = P0 + 1, nl = nn * nn * nn;
     double part = 0.0;
-    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        int gi[nl];
+    for (int t = (int)threadIdx.x; t < (e1 - e0) * COARSE_SPLIT; t += blockDim.x) {
+        const int e = e0 + t / COARSE_SPLIT, sub = t % COARSE_SPLIT;
         double u[nl];
 #pragma unroll
         for (int l = 0; l < nl; ++l) {
-            gi[l] = a.e_nodes[e * 27 + l];
-            u[l] = gi[l] >= 0 ? a.z[gi[l]] : 0.0;
+            int gi = a.e_nodes[e * 27 + l];
+            u[l] = gi >= 0 ? ld_dev(a.z + gi) : 0.0;
         }
         const int c1 = e % a.n[0], c2 = (e / a.n[0]) % a.n[1], c3 = e / (a.n[0] * a.n[1]);
-        double m1[nn], m2[nn], m3[nn], L1[nn * nn], L2[nn * nn], L3[nn * nn];
-#pragma unroll
-        for (int i = 0; i < nn; ++i) {
-            m1[i] = a.el_m[0][c1 * nn + i];
-            m2[i] = a.el_m[1][c2 * nn + i];
-            m3[i] = a.el_m[2][c3 * nn + i];
-        }
-#pragma unroll
-        for (int i = 0; i < nn * nn; ++i) {
-            L1[i] = a.el_L[0][c1 * nn * nn + i];
-            L2[i] = a.el_L[1][c2 * nn * nn + i];
-            L3[i] = a.el_L[2][c3 * nn * nn + i];
-        }
-        double s = 0.0, hii = 1.0;
+        const double* t1 = tab + (0 * COARSE_MAXN + c1) * 12;
+        const double* t2 = tab + (1 * COARSE_MAXN + c2) * 12;
+        const double* t3 = tab + (2 * COARSE_MAXN + c3) * 12;
+        const double *m1 = t1, *m2 = t2, *m3 = t3, *L1 = t1 + 3, *L2 = t2 + 3, *L3 = t3 + 3;
+        double sh = 0.0;
         if (P0 == 2) {
             // Schur complement of the single interior node (1,1,1):
-            // s = H_IB u_B, hii = H_II
-            s = m3[1] * m2[1] * (L1[3] * u[13 - 1] + L1[5] * u[13 + 1]) +
-                m3[1] * m1[1] * (L2[3] * u[13 - 3] + L2[5] * u[13 + 3]) +
-                m2[1] * m1[1] * (L3[3] * u[13 - 9] + L3[5] * u[13 + 9]);
-            hii = a.lam * m1[1] * m2[1] * m3[1] + m3[1] * m2[1] * L1[4] + m3[1] * m1[1] * L2[4] +
-                  m2[1] * m1[1] * L3[4];
+            // s = H_IB u_B, hii = H_II, sh = s / hii
+            double s = m3[1] * m2[1] * (L1[3] * u[12] + L1[5] * u[14]) +
+                       m3[1] * m1[1] * (L2[3] * u[10] + L2[5] * u[16]) +
+                       m2[1] * m1[1] * (L3[3] * u[4] + L3[5] * u[22]);
+            double hii = a.lam * m1[1] * m2[1] * m3[1] + m3[1] * m2[1] * L1[4] + m3[1] * m1[1] * L2[4] +
+                         m2[1] * m1[1] * L3[4];
+            sh = s / hii;
         }
-        const double sh = s / hii;
 #pragma unroll
         for (int l = 0; l < nl; ++l) {
-            if (gi[l] < 0) continue;
+            if (l % COARSE_SPLIT != sub) continue;
+            const int gi = a.e_nodes[e * 27 + l];
+            if (gi < 0) continue;
             const int a1 = l % nn, a2 = (l / nn) % nn, a3 = l / (nn * nn);
             double x1 = 0.0, x2 = 0.0, x3 = 0.0;
 #pragma unroll
-            for (int j = 0; j < nn; ++j) {
-                x1 += L1[a1 * nn + j] * u[(a3 * nn + a2) * nn + j];
-                x2 += L2[a2 * nn + j] * u[(a3 * nn + j) * nn + a1];
-                x3 += L3[a3 * nn + j] * u[(j * nn + a2) * nn + a1];
+            for (int jj = 0; jj < nn; ++jj) {
+                x1 += L1[a1 * nn + jj] * u[(a3 * nn + a2) * nn + jj];
+                x2 += L2[a2 * nn + jj] * u[(a3 * nn + jj) * nn + a1];
+                x3 += L3[a3 * nn + jj] * u[(jj * nn + a2) * nn + a1];
             }
-            double t = a.lam * m1[a1] * m2[a2] * m3[a3] * u[l] + m3[a3] * m2[a2] * x1 + m3[a3] * m1[a1] * x2 +
+            double y = a.lam * m1[a1] * m2[a2] * m3[a3] * u[l] + m3[a3] * m2[a2] * x1 + m3[a3] * m1[a1] * x2 +
                        m2[a2] * m1[a1] * x3;
             if (P0 == 2) {
                 double col = 0.0;
                 if (a2 == 1 && a3 == 1) col = m3[1] * m2[1] * L1[a1 * 3 + 1];
                 else if (a1 == 1 && a3 == 1) col = m3[1] * m1[1] * L2[a2 * 3 + 1];
                 else if (a1 == 1 && a2 == 1) col = m2[1] * m1[1] * L3[a3 * 3 + 1];
-                t -= sh * col;
+                y -= sh * col;
             }
-            a.E[e * 27 + l] = t;
-            part += t * u[l];
+            unsafeAtomicAdd(a.E + gi, y);
+            part += y * u[l];
         }
     }
     return part;
 }
 
-__device__ inline double coarse_elements(const CoarseArgs& a, int e0, int e1) {
-    return a.p0 == 2 ? coarse_elements_t<2>(a, e0, e1) : coarse_elements_t<1>(a, e0, e1);
+__device__ inline double coarse_elements(const CoarseArgs& a, const double* tab, int e0, int e1) {
+    return a.p0 == 2 ? coarse_elements_t<2>(a, tab, e0, e1) : coarse_elements_t<1>(a, tab, e0, e1);
 }
 
-__global__ void __launch_bounds__(256) k_coarse_cg(CoarseArgs a, const double* __restrict__ b_in,
-                                                   double* __restrict__ x_out, int maxit, double rtol) {
+__global__ void __launch_bounds__(COARSE_THREADS) k_coarse_cg(CoarseArgs a, const double* __restrict__ b_in,
+                                                              double* __restrict__ x_out, int maxit, double rtol) {
+    __shared__ double tab[3 * COARSE_MAXN * 12];
     const unsigned nb = gridDim.x;
+    const int nn = a.p0 + 1;
+    for (int d = 0; d < 3; ++d)
+        for (int i = threadIdx.x; i < a.n[d] * 12; i += blockDim.x) {
+            int e = i / 12, o = i % 12;
+            double v = 0.0;
+            if (o < nn) v = a.el_m[d][e * nn + o];
+            else if (o >= 3 && o - 3 < nn * nn) v = a.el_L[d][e * nn * nn + (o - 3)];
+            tab[(d * COARSE_MAXN + e) * 12 + o] = v;
+        }
+    __syncthreads();
+    // E holds the assembled w = A z (one value per unknown)
+    double* w = a.E;
     const int R = (a.N0 + (int)nb - 1) / (int)nb;
     const int r0 = blockIdx.x * R, r1 = min(a.N0, r0 + R);
     const int EB = (a.ne + (int)nb - 1) / (int)nb;
     const int e0 = min(a.ne, (int)blockIdx.x * EB), e1 = min(a.ne, e0 + EB);
-    // r = b, x = 0, z = D^-1 r, gamma partial
+    // r = b, x = 0, z = D^-1 r, w = 0, gamma partial
     double g_part = 0.0;
     for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
         double ri = b_in[a.c_slot[i]];
         double zi = ri / a.diag[i];
         a.x[i] = 0.0;
         a.r[i] = ri;
-        a.z[i] = zi;
+        st_dev(a.z + i, zi);
+        st_dev(w + i, 0.0);
         g_part += ri * zi;
     }
     grid_barrier(a.bar, nb, a.err);
-    double d_part = coarse_elements(a, e0, e1);
+    double d_part = coarse_elements(a, tab, e0, e1);
     write_partials(a.partials, g_part, d_part);
     grid_barrier(a.bar, nb, a.err);
     double gamma, delta;
@@ -1346,34 +1376,30 @@ __global__ void __launch_bounds__(256) k_coarse_cg(CoarseArgs a, const double* _
         double alpha = gamma / delta, beta = 0.0;
         bool first = true;
         while (true) {
-            // rows: w = gather(E); p = z + beta p; q = w + beta q;
+            // rows: p = z + beta p; q = w + beta q; w = 0;
             //       x += alpha p; r -= alpha q; z = D^-1 r; gamma partial
             g_part = 0.0;
             for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-                double w = 0.0;
-                const int* adj = a.r_adj + (size_t)i * 8;
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    int s = adj[k];
-                    if (s >= 0) w += a.E[s];
-                }
-                double pi = first ? a.z[i] : a.z[i] + beta * a.p[i];
-                double qi = first ? w : w + beta * a.q[i];
+                const double wi = ld_dev(w + i);
+                const double zo = ld_dev(a.z + i);
+                double pi = first ? zo : zo + beta * a.p[i];
+                double qi = first ? wi : wi + beta * a.q[i];
                 a.p[i] = pi;
                 a.q[i] = qi;
+                st_dev(w + i, 0.0);
                 double xi = a.x[i] + alpha * pi;
                 double ri = a.r[i] - alpha * qi;
                 a.x[i] = xi;
                 a.r[i] = ri;
                 double zi = ri / a.diag[i];
-                a.z[i] = zi;
+                st_dev(a.z + i, zi);
                 g_part += ri * zi;
             }
             first = false;
             ++it;
             if (it >= maxit) break;
             grid_barrier(a.bar, nb, a.err);
-            d_part = coarse_elements(a, e0, e1);
+            d_part = coarse_elements(a, tab, e0, e1);
             write_partials(a.partials, g_part, d_part);
             grid_barrier(a.bar, nb, a.err);
             double gnew;
@@ -1716,7 +1742,7 @@ hipError_t launch_coarse_cg(const CoarseArgs& a, int blocks, const double* b, do
     const double* bb = b;
     double* xx = x;
     void* args[] = {&aa, &bb, &xx, &maxit, &rtol};
-    return hipLaunchCooperativeKernel((const void*)k_coarse_cg, dim3(blocks), dim3(256), args, 0, st);
+    return hipLaunchCooperativeKernel((const void*)k_coarse_cg, dim3(blocks), dim3(COARSE_THREADS), args, 0, st);
 }
 
 hipError_t init_kernel_attributes() {
