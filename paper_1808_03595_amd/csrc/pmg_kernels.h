@@ -9,6 +9,7 @@ constexpr int REDUCE_BLOCKS = 512;
 
 hipError_t init_kernel_attributes();
 void set_mfma_min_degree(int p);
+void set_op_atomic(bool on);
 hipError_t launch_coarse_cg(const CoarseArgs& a, int blocks, const double* b, double* x, int maxit,
                             double rtol, hipStream_t st);
 

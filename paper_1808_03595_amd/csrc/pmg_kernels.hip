@@ -271,7 +271,37 @@ __device__ inline T hbb_at(const ElemPtrs<T>& P, int p, T lam, const T* tile, in
            m2 * m1 * x3;
 }
 
+// Copy the 1D tables of element e into LDS (`dst`, elem_table_size(p)
+// entries) and return pointers into the copy.
+__host__ __device__ inline int elem_table_size(int p) {
+    const int n1 = p + 1, q = p - 1;
+    return 3 * (n1 + n1 * n1 + 2 * q * q + 3 * q);
+}
+
 template <typename T>
+__device__ ElemPtrs<T> stage_elem_tables(const LevelTabs<T>& tb, const int e[3], T* dst) {
+    const int p = tb.lay.p, n1 = p + 1, q = p - 1;
+    ElemPtrs<T> src = elem_ptrs(tb, e);
+    ElemPtrs<T> P;
+    const int sizes[7] = {n1, n1 * n1, q * q, q * q, q, q, q};
+    T* o = dst;
+    for (int d = 0; d < 3; ++d) {
+        const T* s[7] = {src.m[d], src.L[d], src.Si[d], src.MS[d], src.lm[d], src.c0[d], src.cp[d]};
+        const T** ptrs[7] = {&P.m[d], &P.L[d], &P.Si[d], &P.MS[d], &P.lm[d], &P.c0[d], &P.cp[d]};
+        for (int t = 0; t < 7; ++t) {
+            for (int i = threadIdx.x; i < sizes[t]; i += blockDim.x) o[i] = s[t][i];
+            *ptrs[t] = o;
+            o += sizes[t];
+        }
+    }
+    return P;
+}
+
+// One element per workgroup, all elements in one launch; the contributions
+// of neighbouring elements meet in the shared face, edge and vertex slots
+// and are summed there with hardware atomics (ATOMIC) or, with ATOMIC
+// false, by eight parity-colour launches whose writes never overlap.
+template <typename T, bool ATOMIC>
 __global__ void __launch_bounds__(256) k_condensed_op(LevelTabs<T> tb, const T* __restrict__ u,
                                                       T* __restrict__ y, int color) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -284,7 +314,8 @@ __global__ void __launch_bounds__(256) k_condensed_op(LevelTabs<T> tb, const T* 
     T* G = tile + 6 * t2;      // 6 q2
     T* Tc = G + 6 * q2;        // 6 q2
     T* tmp = Tc + 6 * q2;      // 6 q2
-    ElemPtrs<T> P = elem_ptrs(tb, e);
+    T* tabs = tmp + 6 * q2;    // elem_table_size(p)
+    ElemPtrs<T> P = stage_elem_tables(tb, e, tabs);
     load_tiles(L, e, u, tile);
     __syncthreads();
     if (q > 0) {
@@ -301,7 +332,8 @@ __global__ void __launch_bounds__(256) k_condensed_op(LevelTabs<T> tb, const T* 
         if (is_dir(L, i1, i2, i3)) continue;
         T v = hbb_at(P, p, tb.lam, tile, a1, a2, a3);
         if (r > 0 && r < p && c > 0 && c < p) v -= G[f * q2 + (r - 1) * q + (c - 1)];
-        add_out(y, elem_slot(L, e, a1, a2, a3), v);
+        if (ATOMIC) unsafeAtomicAdd(y + elem_slot(L, e, a1, a2, a3), v);
+        else add_out(y, elem_slot(L, e, a1, a2, a3), v);
     }
 }
 
@@ -1047,27 +1079,31 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // Finish a reduction of `nv` values per block: partials[nv * gridDim.x].
+// The partials travel through device-coherent (sc1) stores and loads, so no
+// cache flush is needed; the last block to arrive sums them in block order.
 __device__ inline void finish_reduce(double* partials, const double* mine, int nv, unsigned* counter,
                                      double* out) {
     __shared__ bool last;
     if (threadIdx.x == 0) {
-        for (int k = 0; k < nv; ++k) partials[(size_t)blockIdx.x * nv + k] = mine[k];
-        __threadfence();
-        unsigned prev = atomicAdd(counter, 1u);
+        for (int k = 0; k < nv; ++k)
+            __hip_atomic_store(partials + (size_t)blockIdx.x * nv + k, mine[k], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0x0f70);
+        unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         last = (prev == gridDim.x - 1);
     }
     __syncthreads();
     if (!last) return;
-    __threadfence();
     for (int k = 0; k < nv; ++k) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) s += partials[(size_t)b * nv + k];
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
+            s += __hip_atomic_load(partials + (size_t)b * nv + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __shared__ double red[16];
         s = block_sum(s, red);
         if (threadIdx.x == 0) out[k] = s;
         __syncthreads();
     }
-    if (threadIdx.x == 0) *counter = 0u;
+    if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // out[0] = x . y ; out[1] = x . z (if z non-null)
@@ -1577,7 +1613,7 @@ static int color_count(const int n[3], int color) {
 template <typename T>
 size_t smem_condensed_op(int p) {
     int n1 = p + 1, q = p - 1;
-    return sizeof(T) * (size_t)(6 * n1 * n1 + 18 * q * q);
+    return sizeof(T) * (size_t)(6 * n1 * n1 + 18 * q * q + elem_table_size(p));
 }
 template <typename T>
 size_t smem_smoother(int p) {
@@ -1595,14 +1631,23 @@ void launch_skel_to_grid(const Layout& L, const T* s, double* g, hipStream_t st)
     hipLaunchKernelGGL(k_skel_to_grid<T>, dim3(nblk(tot)), dim3(256), 0, st, L, s, g);
 }
 
+// assembly of the condensed operator: atomics (one launch) unless disabled
+bool g_op_atomic = true;
+void set_op_atomic(bool on) { g_op_atomic = on; }
+
 template <typename T>
 void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t st) {
-    hipMemsetAsync(y, 0, sizeof(T) * tb.lay.len, st);
+    (void)hipMemsetAsync(y, 0, sizeof(T) * tb.lay.len, st);
     size_t sm = smem_condensed_op<T>(tb.lay.p);
+    if (g_op_atomic) {
+        int ne = tb.lay.n[0] * tb.lay.n[1] * tb.lay.n[2];
+        hipLaunchKernelGGL((k_condensed_op<T, true>), dim3(ne), dim3(256), sm, st, tb, u, y, -1);
+        return;
+    }
     for (int c = 0; c < 8; ++c) {
         int nb = color_count(tb.lay.n, c);
         if (nb == 0) continue;
-        hipLaunchKernelGGL(k_condensed_op<T>, dim3(nb), dim3(256), sm, st, tb, u, y, c);
+        hipLaunchKernelGGL((k_condensed_op<T, false>), dim3(nb), dim3(256), sm, st, tb, u, y, c);
     }
 }
 
@@ -1748,7 +1793,8 @@ hipError_t launch_coarse_cg(const CoarseArgs& a, int blocks, const double* b, do
 hipError_t init_kernel_attributes() {
     const int lds = 160 * 1024;
     const void* fns[] = {
-        (const void*)k_condensed_op<double>, (const void*)k_condensed_op<float>,
+        (const void*)k_condensed_op<double, true>, (const void*)k_condensed_op<float, true>,
+        (const void*)k_condensed_op<double, false>, (const void*)k_condensed_op<float, false>,
         (const void*)k_smoother<double>,     (const void*)k_smoother<float>,
         (const void*)k_prolong_add<double>,  (const void*)k_prolong_add<float>,
         (const void*)k_restrict_planes<double>, (const void*)k_restrict_planes<float>,

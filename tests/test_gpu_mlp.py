@@ -1,0 +1,81 @@
+"""GPU parity of the damping-MLP kernels against the FP64 oracle.
+
+Tolerances follow FP32 arithmetic: relative 2e-5 for the forward pass
+(three dependent layers of 64-term sums, unit round-off 6e-8) and 1e-4 for
+gradients (one more layer of products); Adam in FP32 to 1e-5 absolute for
+steps of size lr = 1e-3.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1808_03595_amd as pmg
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+def _data(nout=4, B=37, seed=0):
+    rng = np.random.default_rng(seed)
+    th = (mlp.glorot_init(nout, seed) + 0.05 * rng.normal(size=mlp.nparams(nout))).astype(np.float32)
+    x = rng.uniform(0, 1, size=(B, 3)).astype(np.float32)
+    t = rng.uniform(0.5, 1.5, size=(B, nout)).astype(np.float32)
+    m = (rng.uniform(size=(B, nout)) < 0.8).astype(np.float32)
+    return th, x, t, m
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda:0")
+
+
+@pytest.mark.parametrize("nout,B", [(4, 37), (1, 1), (3, 200)])
+def test_forward_loss_backward(gpu, nout, B):
+    th, x, t, m = _data(nout, B)
+    assert pmg.mlp_nparams(nout) == th.size
+    y = torch.empty(B, nout, dtype=torch.float32, device=gpu)
+    cache = torch.empty(B, 128 + nout, dtype=torch.float32, device=gpu)
+    dp, dx = _dev(th), _dev(x)
+    pmg.mlp_forward(dp, dx, y, cache, B, nout)
+    dy = torch.empty_like(y)
+    loss = torch.empty(1, dtype=torch.float32, device=gpu)
+    pmg.mlp_loss(y, _dev(t), _dev(m), dy, loss, B, nout)
+    grad = torch.empty_like(dp)
+    pmg.mlp_backward(dp, dx, cache, dy, grad, B, nout)
+    torch.cuda.synchronize()
+    ry, cache64 = mlp.forward(th.astype(np.float64), x.astype(np.float64), nout)
+    rl, rdy = mlp.loss(ry, t, m)
+    rg = mlp.backward(th.astype(np.float64), cache64, rdy, nout)
+    assert np.linalg.norm(y.cpu().numpy() - ry) <= 2e-5 * np.linalg.norm(ry)
+    assert abs(loss.item() - rl) <= 1e-4 * abs(rl) + 1e-7
+    assert np.linalg.norm(grad.cpu().numpy() - rg) <= 1e-4 * np.linalg.norm(rg)
+
+
+def test_adam_matches_oracle(gpu):
+    rng = np.random.default_rng(3)
+    n = 1000
+    th = rng.normal(size=n).astype(np.float32)
+    g = rng.normal(size=n).astype(np.float32)
+    m0 = (0.1 * rng.normal(size=n)).astype(np.float32)
+    v0 = np.abs(0.1 * rng.normal(size=n)).astype(np.float32)
+    dp, dm, dv = _dev(th), _dev(m0), _dev(v0)
+    pmg.mlp_adam(dp, _dev(g), dm, dv, n, 1e-3, 0.9, 0.999, 1e-8, 5)
+    torch.cuda.synchronize()
+    rt, rm, rv = mlp.adam_step(th.astype(np.float64), g, m0, v0, 5, lr=1e-3)
+    assert np.max(np.abs(dp.cpu().numpy() - rt)) < 1e-5
+    assert np.max(np.abs(dm.cpu().numpy() - rm)) < 1e-6
+    assert np.max(np.abs(dv.cpu().numpy() - rv)) < 1e-6
+
+
+def test_training_on_gpu_reduces_loss(gpu):
+    from paper_1808_03595_amd.learn import DampingMLP
+    rng = np.random.default_rng(4)
+    X = rng.uniform(0, 1, size=(64, 3)).astype(np.float32)
+    T = np.stack([1 + 0.3 * np.sin(3 * X[:, 0]), 0.9 + 0.2 * X[:, 1], np.full(64, 1.2),
+                  np.ones(64)], axis=1).astype(np.float32)
+    M = np.ones_like(T)
+    M[:, 3] = 0
+    model = DampingMLP(seed=1)
+    hist = model.train(X, T, M, steps=400, lr=3e-3, log_every=100)
+    assert hist[-1][1] < 0.05 * hist[0][1]
+    pred = model.predict(X)
+    assert np.sqrt(np.mean((pred[:, :3] - T[:, :3]) ** 2)) < 0.05
