@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <type_traits>
@@ -251,11 +252,13 @@ int build_coarse(pmg_mesh* m) {
     if ((rc = m->upload(&a.diag, dc))) return rc;
     size_t nv = std::max(N0, 1);
     if ((rc = m->alloc(&a.x, nv)) || (rc = m->alloc(&a.r, nv)) || (rc = m->alloc(&a.z, nv)) ||
-        (rc = m->alloc(&a.p, nv)) || (rc = m->alloc(&a.q, nv)) || (rc = m->alloc(&a.E, nv)))
+        (rc = m->alloc(&a.p, nv)) || (rc = m->alloc(&a.q, nv)) || (rc = m->alloc(&a.E, std::max(nv, (size_t)ne * 27))))
         return rc;
-    // workgroups of 1024 threads: four threads per element, 4..32 groups
-    int G = (4 * ne + 1023) / 1024;
-    G = std::max(4, std::min(32, G));
+    // one workgroup (small problems, set by PMG_COARSE_BLOCKS or the size)
+    // or several cooperative workgroups of 1024 threads, four threads per element
+    int G = ne / 128;
+    G = std::max(8, std::min(64, G));
+    if (const char* env = std::getenv("PMG_COARSE_BLOCKS")) G = std::max(1, std::min(64, std::atoi(env)));
     if (m->n[0] > 256 || m->n[1] > 256 || m->n[2] > 256) return fail(PMG_EUNSUP, "more than 256 elements per direction");
     m->coarse_blocks = G;
     if ((rc = m->alloc(&a.partials, 2 * (size_t)G)) || (rc = m->alloc(&a.bar, 2)) ||

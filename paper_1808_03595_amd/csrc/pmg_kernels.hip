@@ -1450,6 +1450,146 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_coarse_cg(CoarseArgs a, cons
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.iters, it);
 }
 
+// Single-workgroup variant for small coarse problems: the whole CG runs in
+// one workgroup of COARSE_THREADS threads on one CU, so workgroup barriers
+// replace grid barriers and plain cached memory accesses are coherent.  The
+// condensed operator is applied element by element into E[e][27] and
+// gathered per unknown through r_adj (fixed summation order).
+template <int P0>
+__device__ double coarse_elements_local(const CoarseArgs& a, const double* tab) {
+    constexpr int nn = P0 + 1, nl = nn * nn * nn;
+    double part = 0.0;
+    for (int t = (int)threadIdx.x; t < a.ne * COARSE_SPLIT; t += blockDim.x) {
+        const int e = t / COARSE_SPLIT, sub = t % COARSE_SPLIT;
+        double u[nl];
+#pragma unroll
+        for (int l = 0; l < nl; ++l) {
+            int gi = a.e_nodes[e * 27 + l];
+            u[l] = gi >= 0 ? a.z[gi] : 0.0;
+        }
+        const int c1 = e % a.n[0], c2 = (e / a.n[0]) % a.n[1], c3 = e / (a.n[0] * a.n[1]);
+        const double* t1 = tab + (0 * COARSE_MAXN + c1) * 12;
+        const double* t2 = tab + (1 * COARSE_MAXN + c2) * 12;
+        const double* t3 = tab + (2 * COARSE_MAXN + c3) * 12;
+        const double *m1 = t1, *m2 = t2, *m3 = t3, *L1 = t1 + 3, *L2 = t2 + 3, *L3 = t3 + 3;
+        double sh = 0.0;
+        if (P0 == 2) {
+            double s = m3[1] * m2[1] * (L1[3] * u[12] + L1[5] * u[14]) +
+                       m3[1] * m1[1] * (L2[3] * u[10] + L2[5] * u[16]) +
+                       m2[1] * m1[1] * (L3[3] * u[4] + L3[5] * u[22]);
+            double hii = a.lam * m1[1] * m2[1] * m3[1] + m3[1] * m2[1] * L1[4] + m3[1] * m1[1] * L2[4] +
+                         m2[1] * m1[1] * L3[4];
+            sh = s / hii;
+        }
+#pragma unroll
+        for (int l = 0; l < nl; ++l) {
+            if (l % COARSE_SPLIT != sub) continue;
+            if (a.e_nodes[e * 27 + l] < 0) continue;
+            const int a1 = l % nn, a2 = (l / nn) % nn, a3 = l / (nn * nn);
+            double x1 = 0.0, x2 = 0.0, x3 = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < nn; ++jj) {
+                x1 += L1[a1 * nn + jj] * u[(a3 * nn + a2) * nn + jj];
+                x2 += L2[a2 * nn + jj] * u[(a3 * nn + jj) * nn + a1];
+                x3 += L3[a3 * nn + jj] * u[(jj * nn + a2) * nn + a1];
+            }
+            double y = a.lam * m1[a1] * m2[a2] * m3[a3] * u[l] + m3[a3] * m2[a2] * x1 + m3[a3] * m1[a1] * x2 +
+                       m2[a2] * m1[a1] * x3;
+            if (P0 == 2) {
+                double col = 0.0;
+                if (a2 == 1 && a3 == 1) col = m3[1] * m2[1] * L1[a1 * 3 + 1];
+                else if (a1 == 1 && a3 == 1) col = m3[1] * m1[1] * L2[a2 * 3 + 1];
+                else if (a1 == 1 && a2 == 1) col = m2[1] * m1[1] * L3[a3 * 3 + 1];
+                y -= sh * col;
+            }
+            a.E[(size_t)e * 27 + l] = y;
+            part += y * u[l];
+        }
+    }
+    return part;
+}
+
+__device__ inline double block_sum_all(double v) {
+    __shared__ double red[16];
+    __shared__ double res;
+    double s = block_sum(v, red);
+    if (threadIdx.x == 0) res = s;
+    __syncthreads();
+    double out = res;
+    __syncthreads();
+    return out;
+}
+
+__global__ void __launch_bounds__(COARSE_THREADS) k_coarse_cg_single(CoarseArgs a, const double* __restrict__ b_in,
+                                                                     double* __restrict__ x_out, int maxit,
+                                                                     double rtol) {
+    __shared__ double tab[3 * COARSE_MAXN * 12];
+    const int nn = a.p0 + 1;
+    for (int d = 0; d < 3; ++d)
+        for (int i = threadIdx.x; i < a.n[d] * 12; i += blockDim.x) {
+            int e = i / 12, o = i % 12;
+            double v = 0.0;
+            if (o < nn) v = a.el_m[d][e * nn + o];
+            else if (o >= 3 && o - 3 < nn * nn) v = a.el_L[d][e * nn * nn + (o - 3)];
+            tab[(d * COARSE_MAXN + e) * 12 + o] = v;
+        }
+    double g_part = 0.0;
+    for (int i = threadIdx.x; i < a.N0; i += blockDim.x) {
+        double ri = b_in[a.c_slot[i]];
+        double zi = ri / a.diag[i];
+        a.x[i] = 0.0;
+        a.r[i] = ri;
+        a.z[i] = zi;
+        g_part += ri * zi;
+    }
+    __syncthreads();
+    double d_part = a.p0 == 2 ? coarse_elements_local<2>(a, tab) : coarse_elements_local<1>(a, tab);
+    double gamma = block_sum_all(g_part);
+    double delta = block_sum_all(d_part);
+    const double gamma0 = gamma;
+    int it = 0;
+    if (gamma > 0.0 && maxit > 0) {
+        double alpha = gamma / delta, beta = 0.0;
+        bool first = true;
+        while (true) {
+            g_part = 0.0;
+            for (int i = threadIdx.x; i < a.N0; i += blockDim.x) {
+                const int4 adj0 = *reinterpret_cast<const int4*>(a.r_adj + (size_t)i * 8);
+                const int4 adj1 = *reinterpret_cast<const int4*>(a.r_adj + (size_t)i * 8 + 4);
+                const int adj[8] = {adj0.x, adj0.y, adj0.z, adj0.w, adj1.x, adj1.y, adj1.z, adj1.w};
+                double w = 0.0;
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) w += adj[kk] >= 0 ? a.E[adj[kk]] : 0.0;
+                const double zo = a.z[i];
+                double pi = first ? zo : zo + beta * a.p[i];
+                double qi = first ? w : w + beta * a.q[i];
+                a.p[i] = pi;
+                a.q[i] = qi;
+                double ri = a.r[i] - alpha * qi;
+                a.x[i] += alpha * pi;
+                a.r[i] = ri;
+                double zi = ri / a.diag[i];
+                a.z[i] = zi;
+                g_part += ri * zi;
+            }
+            first = false;
+            ++it;
+            if (it >= maxit) break;
+            __syncthreads();
+            d_part = a.p0 == 2 ? coarse_elements_local<2>(a, tab) : coarse_elements_local<1>(a, tab);
+            double gnew = block_sum_all(g_part);
+            delta = block_sum_all(d_part);
+            if (gnew <= rtol * rtol * gamma0) break;
+            beta = gnew / gamma;
+            alpha = gnew / (delta - beta * gnew / alpha);
+            gamma = gnew;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < a.N0; i += blockDim.x) x_out[a.c_slot[i]] = a.x[i];
+    if (threadIdx.x == 0) atomicAdd(a.iters, it);
+}
+
 // ---------------------------------------------------------------------------
 // MLP 3 -> 64 -> 64 -> nout, FP32 (learned smoother damping).
 // One thread per sample for the hidden layers; parameters staged in LDS.
@@ -1783,6 +1923,10 @@ void launch_mlp_adam(float* prm, const float* g, float* m, float* v, int n, floa
 
 hipError_t launch_coarse_cg(const CoarseArgs& a, int blocks, const double* b, double* x, int maxit,
                             double rtol, hipStream_t st) {
+    if (blocks <= 1) {
+        hipLaunchKernelGGL(k_coarse_cg_single, dim3(1), dim3(COARSE_THREADS), 0, st, a, b, x, maxit, rtol);
+        return hipGetLastError();
+    }
     CoarseArgs aa = a;
     const double* bb = b;
     double* xx = x;
