@@ -128,6 +128,10 @@ def main():
     ap.add_argument("--workload", default="c2a")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--coarse-rtol", type=float, default=1e-2)
+    ap.add_argument("--hmg-levels", type=int, default=0,
+                    help="degree-1 levels below p_0 (0: the paper's CG on p_0 = 2)")
+    ap.add_argument("--hmg-omega", type=float, default=0.8)
+    ap.add_argument("--hmg-nu", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -147,6 +151,8 @@ def main():
     # with 1e-8 on this workload (checked with the oracle), and the flexible
     # ipCG absorbs the inexact coarse solve
     g.set_cycle(0, args.coarse_rtol, 2000)
+    if args.hmg_levels:
+        g.set_coarse_mg(args.hmg_levels, args.hmg_omega, args.hmg_nu)
     u_ex, f = make_rhs(g, wl, torch, synth, dev)
     u = torch.zeros_like(f)
     ndof = n[0] * n[1] * n[2] * p ** 3

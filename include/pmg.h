@@ -125,6 +125,17 @@ int pmg_restrict(pmg_mesh *m, int level, int dtype, const void *d_fine,
 int pmg_set_cycle(pmg_mesh *m, int nu_mode, double coarse_rtol,
                   int coarse_maxit);
 
+/* Optional low-order multigrid for the coarse problem (not the paper's
+ * coarse solver; the remedy its complexity discussion in Sec. 4.2 names for
+ * the O(n_e^(4/3)) coarse cost).  levels = 0 restores the paper's CG at
+ * p_0 = 2.  levels >= 1 inserts degree-1 levels below p_0: first on the same
+ * mesh, then on meshes with pairs of elements merged in every direction
+ * (while all element counts are even and >= 4), at most `levels` of them;
+ * each is smoothed `nu` times before and after the coarse correction by
+ * the degree-1 star smoother (a point-Jacobi step) damped by `omega`; the
+ * Jacobi CG then runs on the smallest mesh.  Synchronizes the device. */
+int pmg_set_coarse_mg(pmg_mesh *m, int levels, double omega, int nu);
+
 /* Per-level damping of the smoother correction, u_l += omega_l S_l(r_l).
  * h_omega[j] applies to level L - j (j = 0 is the finest); n <= L values;
  * NULL or n = 0 restores omega = 1 (the paper's method). */

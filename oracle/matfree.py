@@ -427,6 +427,53 @@ def restrict(mesh_f: Mesh, mesh_c: Mesh, rf_grid):
 
 
 # --------------------------------------------------------------------------
+# h-transfers between degree-1 meshes (coarse-grid multigrid below p_0)
+# --------------------------------------------------------------------------
+def merged_widths(hs):
+    """Element widths of the mesh with pairs of neighbouring elements merged."""
+    hs = np.asarray(hs, dtype=np.float64)
+    if len(hs) % 2:
+        raise ValueError("even element count required")
+    return hs[0::2] + hs[1::2]
+
+
+def _h_interp_1d(hf):
+    """Linear interpolation from the vertices of the merged mesh to the
+    vertices of the mesh with widths ``hf`` (rows fine, columns coarse)."""
+    nf = len(hf)
+    P = np.zeros((nf + 1, nf // 2 + 1))
+    for i in range(nf + 1):
+        if i % 2 == 0:
+            P[i, i // 2] = 1.0
+        else:
+            t = hf[i - 1] / (hf[i - 1] + hf[i])
+            P[i, (i - 1) // 2] = 1.0 - t
+            P[i, (i + 1) // 2] = t
+    return P
+
+
+def h_prolong(mesh_c: Mesh, mesh_f: Mesh, uc_grid):
+    """Trilinear interpolation of degree-1 nodal values from the merged mesh."""
+    assert mesh_c.p == 1 and mesh_f.p == 1
+    P = [_h_interp_1d(mesh_f.h[d]) for d in range(3)]
+    u = np.where(mesh_c.free_skeleton_mask(), np.asarray(uc_grid), 0.0)
+    u = np.einsum("ia,cba->cbi", P[0], u, optimize=True)
+    u = np.einsum("ib,cba->cia", P[1], u, optimize=True)
+    u = np.einsum("ic,cba->iba", P[2], u, optimize=True)
+    return np.where(mesh_f.free_skeleton_mask(), u, 0.0)
+
+
+def h_restrict(mesh_f: Mesh, mesh_c: Mesh, rf_grid):
+    """Exact transpose of ``h_prolong``."""
+    P = [_h_interp_1d(mesh_f.h[d]) for d in range(3)]
+    r = np.where(mesh_f.free_skeleton_mask(), np.asarray(rf_grid), 0.0)
+    r = np.einsum("ia,cbi->cba", P[0], r, optimize=True)
+    r = np.einsum("ib,cia->cba", P[1], r, optimize=True)
+    r = np.einsum("ic,iba->cba", P[2], r, optimize=True)
+    return np.where(mesh_c.free_skeleton_mask(), r, 0.0)
+
+
+# --------------------------------------------------------------------------
 # diagonal of the condensed operator (coarse-grid Jacobi preconditioner)
 # --------------------------------------------------------------------------
 def condensed_diagonal(mesh: Mesh):

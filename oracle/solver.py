@@ -18,6 +18,15 @@ Readings where the paper is silent (each also listed in the design notes):
   (u_l += omega_l Smoother(...)); omega_l = 1 is the paper's method;
   ``omega[j]`` is indexed from the finest level (j = L - l);
 * stopping test |r|_2 <= rtol |r_0|_2 over the unique condensed unknowns.
+
+Optional extension below p_0 (``hmg_levels`` > 0; not the paper's coarse
+solver, but the remedy its complexity discussion (Sec. 4.2) names for the
+O(n_e^(4/3)) coarse cost: a low-order multigrid): the p_0 = 2 level is
+followed by degree-1 levels, first on the same mesh (p-transfer 2 -> 1), then
+on meshes with pairs of elements merged in every direction (trilinear
+h-transfers), each smoothed by the star smoother of degree 1 (a damped
+point-Jacobi step, damping ``hmg_omega``) with ``hmg_nu`` pre- and
+post-smoothing steps; the coarse CG then runs on the smallest mesh.
 """
 from __future__ import annotations
 
@@ -40,22 +49,47 @@ class Hierarchy:
 
     def __init__(self, mesh: Mesh, nu_mode: str = "kMG", omega=None,
                  coarse_rtol: float = 1e-8, coarse_maxit: int = 2000,
-                 exact_coarse: bool = False):
+                 exact_coarse: bool = False, hmg_levels: int = 0,
+                 hmg_omega: float = 0.6, hmg_nu: int = 1):
         self.degs = level_degrees(mesh.p)
-        self.L = len(self.degs) - 1
-        self.meshes = [mesh.with_degree(q) for q in self.degs]
-        self.meshes[-1] = mesh
-        L = self.L
+        Lp = len(self.degs) - 1
+        pmeshes = [mesh.with_degree(q) for q in self.degs]
+        pmeshes[-1] = mesh
+        # levels below p_0: degree 1 on the same mesh, then merged meshes
+        hmeshes = []
+        if hmg_levels > 0 and self.degs[0] >= 2:
+            cur = mesh.with_degree(1)
+            hmeshes.append(cur)
+            for _ in range(hmg_levels - 1):
+                if any(len(h) % 2 or len(h) < 4 for h in cur.h):
+                    break
+                cur = Mesh(*(matfree.merged_widths(h) for h in cur.h), 1, mesh.lam)
+                hmeshes.append(cur)
+        self.nh = len(hmeshes)
+        self.meshes = hmeshes[::-1] + pmeshes
+        self.L = L = len(self.meshes) - 1
+        # transfer kind between level l-1 and l: "h" (merged mesh) or "p"
+        self.kind = [None] + ["h" if self.meshes[l].n != self.meshes[l - 1].n else "p"
+                              for l in range(1, L + 1)]
+        nh = self.nh
         if nu_mode == "kMG":
             self.nu = [1] * (L + 1)
         elif nu_mode == "kvMG":
             self.nu = [2 ** (L - l) for l in range(L + 1)]
         else:
             raise ValueError(nu_mode)
+        for l in range(nh + 1):          # degree-1 levels and the old p_0 level
+            if l < nh:
+                self.nu[l] = hmg_nu
+        if nu_mode == "kvMG":
+            for l in range(nh, L + 1):
+                self.nu[l] = 2 ** (L - l)
         om = [1.0] * (L + 1)
+        for l in range(nh):
+            om[l] = hmg_omega
         if omega is not None:
             for j, w in enumerate(omega):
-                if j <= L - 1:
+                if j <= Lp - 1:
                     om[L - j] = float(w)
         self.omega = om
         self.coarse_rtol = coarse_rtol
@@ -64,6 +98,16 @@ class Hierarchy:
         self._diag0 = None
         self._dense0 = None
         self.coarse_iters = []
+
+    def _prolong(self, l, uc):
+        if self.kind[l] == "h":
+            return matfree.h_prolong(self.meshes[l - 1], self.meshes[l], uc)
+        return matfree.prolong(self.meshes[l - 1], self.meshes[l], uc)
+
+    def _restrict(self, l, rf):
+        if self.kind[l] == "h":
+            return matfree.h_restrict(self.meshes[l], self.meshes[l - 1], rf)
+        return matfree.restrict(self.meshes[l], self.meshes[l - 1], rf)
 
     # ---- coarse grid ----------------------------------------------------
     def coarse_solve(self, F0):
@@ -103,10 +147,10 @@ class Hierarchy:
                 us[l] = None                       # u_l <- 0
             for _ in range(self.nu[l]):
                 smooth(l)
-            Fs[l - 1] = matfree.restrict(ms[l], ms[l - 1], residual(l))
+            Fs[l - 1] = self._restrict(l, residual(l))
         us[0] = self.coarse_solve(Fs[0])
         for l in range(1, L + 1):
-            pu = matfree.prolong(ms[l - 1], ms[l], us[l - 1])
+            pu = self._prolong(l, us[l - 1])
             us[l] = pu if us[l] is None else us[l] + pu
             for _ in range(self.nu[l]):
                 smooth(l)

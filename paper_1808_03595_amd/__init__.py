@@ -76,6 +76,7 @@ SIGNATURES = {
     "pmg_restrict": (_I, [_VP, _I, _I, _VP, _VP, _VP]),
     "pmg_set_cycle": (_I, [_VP, _I, _D, _I]),
     "pmg_set_damping": (_I, [_VP, _FP, _I]),
+    "pmg_set_coarse_mg": (_I, [_VP, _I, _D, _I]),
     "pmg_vcycle": (_I, [_VP, _I, _VP, _VP, _VP]),
     "pmg_coarse_solve": (_I, [_VP, _VP, _VP, _IP, _VP]),
     "pmg_condense_rhs": (_I, [_VP, _VP, _VP, _VP]),
@@ -203,6 +204,9 @@ class Mesh:
 
     def set_cycle(self, nu_mode=0, coarse_rtol=1e-8, coarse_maxit=2000):
         _check(lib().pmg_set_cycle(self.h, nu_mode, coarse_rtol, coarse_maxit))
+
+    def set_coarse_mg(self, levels=0, omega=0.6, nu=1):
+        _check(lib().pmg_set_coarse_mg(self.h, levels, omega, nu))
 
     def set_damping(self, omega=None):
         if omega is None or len(omega) == 0:

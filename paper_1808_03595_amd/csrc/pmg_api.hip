@@ -37,11 +37,31 @@ enum { SC_GAMMA = 0, SC_GAMMA0 = 1, SC_DELTA = 2, SC_QP = 3, SC_RR = 4, SC_RZ = 
 struct Level {
     int p = 0, pc = 0;
     Layout lay{};
+    std::vector<double> h[3];   // element widths of this level's mesh
     LevelTabs<double> t64{};
     LevelTabs<float> t32{};
     // work vectors of this level
     double *u64 = nullptr, *F64 = nullptr, *y64 = nullptr, *tb64 = nullptr;
     float *u32 = nullptr, *F32 = nullptr, *y32 = nullptr, *tb32 = nullptr;
+    // place in the active cycle (set by rebuild_active)
+    char kind = 'p';            // transfer from the next coarser active level
+    int nu = 1;
+    double omega = 1.0;
+    const double* Jd64 = nullptr;  // p-transfer matrix from the next coarser level
+    const float* Jd32 = nullptr;
+    // degree-1 levels: linear h-transfer weights of this (finer) mesh, and the
+    // diagonal of the operator for the point smoother
+    const double* ht64[3] = {nullptr, nullptr, nullptr};
+    const float* ht32[3] = {nullptr, nullptr, nullptr};
+    const double* jd64 = nullptr;
+    const float* jd32 = nullptr;
+    // p_0 = 2 level when degree-1 levels are active: J from degree 1
+    const double* Jlow64 = nullptr;
+    const float* Jlow32 = nullptr;
+    // coarse CG structures when this level is the bottom of the cycle
+    CoarseArgs ca{};
+    bool has_ca = false;
+    int coarse_blocks = 16;
 };
 
 template <typename T> struct Sel;
@@ -73,9 +93,14 @@ struct pmg_mesh {
     double coarse_rtol = 1e-8;
     int coarse_maxit = 2000;
     std::vector<double> omega;  // per level index l
-    // coarse CG (persistent kernel, compact numbering of the level-0 unknowns)
-    CoarseArgs ca{};
-    int coarse_blocks = 16;
+    // degree-1 levels below p_0 (optional low-order multigrid for the coarse
+    // problem) and the active cycle, coarsest first
+    std::vector<Level> hlv;
+    std::vector<Level*> act;
+    int hmg_levels = 0;
+    double hmg_omega = 0.6;
+    int hmg_nu = 1;
+    // coarse CG counters shared by all bottom levels
     int* d_coarse_iters = nullptr;
     int* d_coarse_err = nullptr;
     int coarse_last = 0;
@@ -187,8 +212,9 @@ bool decode_slot(const Layout& L, int64_t s, int& i1, int& i2, int& i3) {
     return !(i1 == 0 || i2 == 0 || i3 == 0 || i1 == L.N[0] - 1 || i2 == L.N[1] - 1 || i3 == L.N[2] - 1);
 }
 
-int build_coarse(pmg_mesh* m) {
-    const Layout& L0 = m->lv[0].lay;
+int build_coarse(pmg_mesh* m, Level& lev) {
+    if (lev.has_ca) return 0;
+    const Layout& L0 = lev.lay;
     const int p0 = L0.p, nn = p0 + 1;
     if (p0 > 2) return fail(PMG_EUNSUP, "coarse level degree must be 1 or 2");
     std::vector<int> slot2c(L0.len, -1), cslot;
@@ -200,10 +226,11 @@ int build_coarse(pmg_mesh* m) {
         }
     }
     const int N0 = (int)cslot.size();
-    const int ne = m->n[0] * m->n[1] * m->n[2];
+    const int* nl = L0.n;
+    const int ne = nl[0] * nl[1] * nl[2];
     std::vector<int> enodes((size_t)ne * 27, -1), radj((size_t)std::max(N0, 1) * 8, -1), cnt(std::max(N0, 1), 0);
     for (int e = 0; e < ne; ++e) {
-        int c[3] = {e % m->n[0], (e / m->n[0]) % m->n[1], e / (m->n[0] * m->n[1])};
+        int c[3] = {e % nl[0], (e / nl[0]) % nl[1], e / (nl[0] * nl[1])};
         for (int a3 = 0; a3 < nn; ++a3)
             for (int a2 = 0; a2 < nn; ++a2)
                 for (int a1 = 0; a1 < nn; ++a1) {
@@ -223,16 +250,16 @@ int build_coarse(pmg_mesh* m) {
                 }
     }
     std::vector<double> dg;
-    coarse_diagonal(L0, m->lam, m->h, dg);
+    coarse_diagonal(L0, m->lam, lev.h, dg);
     std::vector<double> dc(std::max(N0, 1), 1.0);
     for (int i = 0; i < N0; ++i) dc[i] = dg[cslot[i]];
-    CoarseArgs& a = m->ca;
+    CoarseArgs& a = lev.ca;
     a.N0 = N0;
     a.ne = ne;
     for (int d = 0; d < 3; ++d) {
-        a.n[d] = m->n[d];
-        a.el_m[d] = m->lv[0].t64.el_m[d];
-        a.el_L[d] = m->lv[0].t64.el_L[d];
+        a.n[d] = nl[d];
+        a.el_m[d] = lev.t64.el_m[d];
+        a.el_L[d] = lev.t64.el_L[d];
     }
     a.p0 = p0;
     a.lam = m->lam;
@@ -259,43 +286,139 @@ int build_coarse(pmg_mesh* m) {
     int G = ne / 128;
     G = std::max(8, std::min(64, G));
     if (const char* env = std::getenv("PMG_COARSE_BLOCKS")) G = std::max(1, std::min(64, std::atoi(env)));
-    if (m->n[0] > 256 || m->n[1] > 256 || m->n[2] > 256) return fail(PMG_EUNSUP, "more than 256 elements per direction");
-    m->coarse_blocks = G;
-    if ((rc = m->alloc(&a.partials, 2 * (size_t)G)) || (rc = m->alloc(&a.bar, 2)) ||
-        (rc = m->alloc(&a.err, 1)) || (rc = m->alloc(&a.iters, 1)))
-        return rc;
+    if (nl[0] > 256 || nl[1] > 256 || nl[2] > 256) return fail(PMG_EUNSUP, "more than 256 elements per direction");
+    lev.coarse_blocks = G;
+    if ((rc = m->alloc(&a.partials, 2 * (size_t)G)) || (rc = m->alloc(&a.bar, 2))) return rc;
     HIPCHK(hipMemset(a.bar, 0, 2 * sizeof(unsigned)));
-    HIPCHK(hipMemset(a.err, 0, sizeof(int)));
-    HIPCHK(hipMemset(a.iters, 0, sizeof(int)));
+    a.err = m->d_coarse_err;
+    a.iters = m->d_coarse_iters;
+    lev.has_ca = true;
     return 0;
+}
+
+// Allocate the tables and work vectors of one level of degree p on the mesh
+// with element widths h (pc: degree of the next coarser p-level, 0 = none).
+int build_level(pmg_mesh* m, Level& L, int p, int pc, const std::vector<double> h[3]) {
+    L.p = p;
+    L.pc = pc;
+    for (int d = 0; d < 3; ++d) L.h[d] = h[d];
+    L.lay = make_layout((int)h[0].size(), (int)h[1].size(), (int)h[2].size(), p);
+    HostTables t;
+    build_level_tables(p, pc, h, t);
+    int rc;
+    if ((rc = fill_tabs(m, L.t64, t, L.lay, pc))) return rc;
+    if ((rc = fill_tabs(m, L.t32, t, L.lay, pc))) return rc;
+    int64_t n = L.lay.len;
+    if ((rc = m->alloc(&L.u64, n)) || (rc = m->alloc(&L.F64, n)) || (rc = m->alloc(&L.y64, n)) ||
+        (rc = m->alloc(&L.u32, n)) || (rc = m->alloc(&L.F32, n)) || (rc = m->alloc(&L.y32, n)))
+        return rc;
+    return 0;
+}
+
+// Degree-1 levels below p_0: hlv[0] on the mesh of p_0, hlv[k] on the mesh
+// with pairs of elements of hlv[k-1] merged (while every count is even and
+// at least 4).  Built on demand; hlv[k-1] keeps the linear h-transfer
+// weights of its mesh and the restriction buffer for hlv[k].
+int build_h_levels(pmg_mesh* m, int want) {
+    int rc;
+    while ((int)m->hlv.size() < want) {
+        const int k = (int)m->hlv.size();
+        std::vector<double> h[3];
+        if (k == 0) {
+            for (int d = 0; d < 3; ++d) h[d] = m->h[d];
+        } else {
+            const Level& f = m->hlv[k - 1];
+            bool ok = true;
+            for (int d = 0; d < 3; ++d) ok = ok && f.h[d].size() % 2 == 0 && f.h[d].size() >= 4;
+            if (!ok) break;
+            for (int d = 0; d < 3; ++d)
+                for (size_t e = 0; e + 1 < f.h[d].size(); e += 2) h[d].push_back(f.h[d][e] + f.h[d][e + 1]);
+        }
+        m->hlv.emplace_back();
+        Level& L = m->hlv.back();
+        if ((rc = build_level(m, L, 1, 0, h))) return rc;
+        std::vector<double> dg;
+        coarse_diagonal(L.lay, m->lam, L.h, dg);
+        if ((rc = m->upload(&L.jd64, dg)) || (rc = m->upload(&L.jd32, dg))) return rc;
+        if (k > 0) {
+            // the finer level hlv[k-1] gets the weights t_i = h_{i-1} / (h_{i-1} + h_i)
+            // of its odd vertices and the restriction buffer
+            Level& f = m->hlv[k - 1];
+            for (int d = 0; d < 3; ++d) {
+                std::vector<double> t(f.h[d].size() + 1, 0.0);
+                for (size_t i = 1; i < f.h[d].size(); i += 2) t[i] = f.h[d][i - 1] / (f.h[d][i - 1] + f.h[d][i]);
+                if ((rc = m->upload(&f.ht64[d], t)) || (rc = m->upload(&f.ht32[d], t))) return rc;
+            }
+        }
+    }
+    // p_0 level: transfer matrix from degree 1 and restriction buffer
+    Level& p0 = m->lv[0];
+    if (!m->hlv.empty() && !p0.Jlow64) {
+        std::vector<double> xc, wc, xf, wf, J;
+        gll_nodes_weights(1, xc, wc);
+        gll_nodes_weights(p0.p, xf, wf);
+        lagrange_interp(xc, xf, J);
+        if ((rc = m->upload(&p0.Jlow64, J)) || (rc = m->upload(&p0.Jlow32, J))) return rc;
+        if ((rc = m->alloc(&p0.tb64, m->hlv[0].lay.len)) || (rc = m->alloc(&p0.tb32, m->hlv[0].lay.len))) return rc;
+    }
+    for (size_t k = 1; k < m->hlv.size(); ++k) {
+        Level& f = m->hlv[k - 1];
+        if (!f.tb64) {
+            if ((rc = m->alloc(&f.tb64, m->hlv[k].lay.len)) || (rc = m->alloc(&f.tb32, m->hlv[k].lay.len))) return rc;
+        }
+    }
+    return 0;
+}
+
+// Active cycle, coarsest level first: hlv[k-1..0] then the p-levels.
+int rebuild_active(pmg_mesh* m) {
+    int nh = std::min(m->hmg_levels, (int)m->hlv.size());
+    m->act.clear();
+    for (int k = nh - 1; k >= 0; --k) m->act.push_back(&m->hlv[k]);
+    for (auto& L : m->lv) m->act.push_back(&L);
+    const int L = (int)m->act.size() - 1;
+    for (int l = 0; l <= L; ++l) {
+        Level& v = *m->act[l];
+        if (l < nh) {
+            v.nu = m->hmg_nu;
+            v.omega = m->hmg_omega;
+        } else {
+            v.nu = m->nu_mode == 0 ? 1 : (1 << std::min(20, L - l));
+            v.omega = m->omega[l - nh];
+        }
+        if (l > 0) {
+            const Level& c = *m->act[l - 1];
+            bool same = c.lay.n[0] == v.lay.n[0] && c.lay.n[1] == v.lay.n[1] && c.lay.n[2] == v.lay.n[2];
+            v.kind = same ? 'p' : 'h';
+            if (same) {
+                v.Jd64 = (l == nh) ? v.Jlow64 : v.t64.J;
+                v.Jd32 = (l == nh) ? v.Jlow32 : v.t32.J;
+            }
+        }
+    }
+    return build_coarse(m, *m->act[0]);
 }
 
 int build_mesh(pmg_mesh* m) {
     auto degs = level_degrees(m->p);
     m->L = (int)degs.size() - 1;
     m->lv.resize(degs.size());
+    m->hlv.reserve(32);
     m->omega.assign(degs.size(), 1.0);
     int rc = check_lds(m->p);
     if (rc) return rc;
+    if ((rc = m->alloc(&m->d_coarse_iters, 1)) || (rc = m->alloc(&m->d_coarse_err, 1))) return rc;
+    HIPCHK(hipMemset(m->d_coarse_iters, 0, sizeof(int)));
+    HIPCHK(hipMemset(m->d_coarse_err, 0, sizeof(int)));
     for (size_t l = 0; l < degs.size(); ++l) {
         Level& L = m->lv[l];
-        L.p = degs[l];
-        L.pc = l ? degs[l - 1] : 0;
-        L.lay = make_layout(m->n[0], m->n[1], m->n[2], L.p);
-        HostTables t;
-        build_level_tables(L.p, L.pc, m->h, t);
-        if ((rc = fill_tabs(m, L.t64, t, L.lay, L.pc))) return rc;
-        if ((rc = fill_tabs(m, L.t32, t, L.lay, L.pc))) return rc;
-        int64_t n = L.lay.len;
-        if ((rc = m->alloc(&L.u64, n)) || (rc = m->alloc(&L.F64, n)) || (rc = m->alloc(&L.y64, n)) ||
-            (rc = m->alloc(&L.u32, n)) || (rc = m->alloc(&L.F32, n)) || (rc = m->alloc(&L.y32, n)))
-            return rc;
+        if ((rc = build_level(m, L, degs[l], l ? degs[l - 1] : 0, m->h))) return rc;
         if (l > 0) {
             int64_t nc = m->lv[l - 1].lay.len;
             if ((rc = m->alloc(&L.tb64, nc)) || (rc = m->alloc(&L.tb32, nc))) return rc;
         }
     }
-    if ((rc = build_coarse(m))) return rc;
+    if ((rc = rebuild_active(m))) return rc;
     const Layout& Lf = m->lv.back().lay;
     int64_t nf = Lf.len;
     if ((rc = m->alloc(&m->w_u, nf)) || (rc = m->alloc(&m->w_r, nf)) || (rc = m->alloc(&m->w_s, nf)) ||
@@ -336,72 +459,98 @@ int read_scalars(pmg_mesh* m, hipStream_t st) {
 }
 
 template <typename T>
-void residual(pmg_mesh* m, int l, const T* F, const T* u, T* y, hipStream_t st) {
-    Level& L = m->lv[l];
+void residual(Level& L, const T* F, const T* u, T* y, hipStream_t st) {
     launch_condensed_op<T>(Sel<T>::tabs(L), u, y, st);
     launch_sub_from<T>(F, y, L.lay.len, st);
+}
+
+template <typename T>
+void residual(pmg_mesh* m, int l, const T* F, const T* u, T* y, hipStream_t st) {
+    residual<T>(m->lv[l], F, u, y, st);
+}
+
+template <typename T> const T* jdiag(const Level& L);
+template <> const double* jdiag<double>(const Level& L) { return L.jd64; }
+template <> const float* jdiag<float>(const Level& L) { return L.jd32; }
+template <typename T> const T* jdown(const Level& L);
+template <> const double* jdown<double>(const Level& L) { return L.Jd64; }
+template <> const float* jdown<float>(const Level& L) { return L.Jd32; }
+template <typename T> const T* const* hweights(const Level& L);
+template <> const double* const* hweights<double>(const Level& L) { return L.ht64; }
+template <> const float* const* hweights<float>(const Level& L) { return L.ht32; }
+
+// u += omega Smoother(r) on one level: the star smoother of Alg. 2, or on
+// degree-1 levels its equivalent point form (each star is a single vertex,
+// so the local solve is a division by the diagonal).
+template <typename T>
+void smooth_add(Level& L, const T* r, T* u, hipStream_t st) {
+    if (L.p == 1 && jdiag<T>(L)) launch_point_smooth<T>(L.lay, jdiag<T>(L), r, u, (T)L.omega, st);
+    else launch_smoother_add<T>(Sel<T>::tabs(L), r, u, (T)L.omega, st);
 }
 
 // Jacobi-preconditioned CG on level 0 (FP64), x = 0 initially: one
 // persistent cooperative kernel.  b and x are level-0 skeleton arrays.
 int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st) {
-    Level& L0 = m->lv[0];
+    Level& L0 = *m->act[0];
     HIPCHK(hipMemsetAsync(x, 0, L0.lay.len * sizeof(double), st));
-    if (m->ca.N0 == 0) return 0;
-    HIPCHK(launch_coarse_cg(m->ca, m->coarse_blocks, b, x, m->coarse_maxit, m->coarse_rtol, st));
+    if (L0.ca.N0 == 0) return 0;
+    HIPCHK(launch_coarse_cg(L0.ca, L0.coarse_blocks, b, x, m->coarse_maxit, m->coarse_rtol, st));
     return 0;
 }
 
 // Read and reset the device-side coarse iteration counter and error flag.
 int coarse_stats(pmg_mesh* m, hipStream_t st, int* iters) {
     int h[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(&h[0], m->ca.iters, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(&h[1], m->ca.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&h[0], m->d_coarse_iters, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&h[1], m->d_coarse_err, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipMemsetAsync(m->ca.iters, 0, sizeof(int), st));
+    HIPCHK(hipMemsetAsync(m->d_coarse_iters, 0, sizeof(int), st));
     if (h[1]) {
-        hipMemsetAsync(m->ca.err, 0, sizeof(int), st);
+        (void)hipMemsetAsync(m->d_coarse_err, 0, sizeof(int), st);
         return fail(PMG_EHIP, "coarse solver: grid barrier wait timed out");
     }
     *iters = h[0];
     return 0;
 }
 
-// Alg. 3 with u_L = z (zero on entry unless `nonzero_u`) and F_L = r.
+// Alg. 3 over the active cycle (coarsest level first), with u_L = z (zero on
+// entry unless `nonzero_u`) and F_L = r.  The coarsest level is solved by the
+// persistent CG kernel in FP64.
 template <typename T>
 int vcycle_impl(pmg_mesh* m, const T* r, T* z, bool nonzero_u, hipStream_t st) {
-    const int L = m->L;
+    auto& A = m->act;
+    const int L = (int)A.size() - 1;
     std::vector<T*> u(L + 1);
     std::vector<const T*> F(L + 1);
     u[L] = z;
     F[L] = r;
-    if (!nonzero_u) HIPCHK(hipMemsetAsync(z, 0, m->lv[L].lay.len * sizeof(T), st));
+    if (!nonzero_u) HIPCHK(hipMemsetAsync(z, 0, A[L]->lay.len * sizeof(T), st));
     for (int l = L; l >= 1; --l) {
-        Level& lv = m->lv[l];
-        const int nu = m->nu_mode == 0 ? 1 : (1 << (L - l));
+        Level& lv = *A[l];
         if (l != L) {
             u[l] = Sel<T>::u(lv);
             HIPCHK(hipMemsetAsync(u[l], 0, lv.lay.len * sizeof(T), st));
         }
         bool zero = (l != L) || !nonzero_u;
         T* y = Sel<T>::y(lv);
-        for (int i = 0; i < nu; ++i) {
+        for (int i = 0; i < lv.nu; ++i) {
             const T* res = F[l];
             if (!zero) {
-                residual<T>(m, l, F[l], u[l], y, st);
+                residual<T>(lv, F[l], u[l], y, st);
                 res = y;
             }
-            launch_smoother_add<T>(Sel<T>::tabs(lv), res, u[l], (T)m->omega[l], st);
+            smooth_add<T>(lv, res, u[l], st);
             zero = false;
         }
-        residual<T>(m, l, F[l], u[l], y, st);
-        Level& lc = m->lv[l - 1];
+        residual<T>(lv, F[l], u[l], y, st);
+        Level& lc = *A[l - 1];
         T* Fc = Sel<T>::F(lc);
-        launch_restrict<T>(lv.lay, lc.lay, Sel<T>::tabs(lv).J, y, Fc, Sel<T>::tb(lv), st);
+        if (lv.kind == 'p') launch_restrict<T>(lv.lay, lc.lay, jdown<T>(lv), y, Fc, Sel<T>::tb(lv), st);
+        else launch_hrestrict<T>(lv.lay, lc.lay, hweights<T>(lv), y, Fc, st);
         F[l - 1] = Fc;
     }
     // coarse solve in FP64
-    Level& l0 = m->lv[0];
+    Level& l0 = *A[0];
     if (L == 0) {
         // the whole problem is the coarse problem
         if (std::is_same<T, double>::value) return coarse_cg(m, reinterpret_cast<const double*>(r),
@@ -428,14 +577,14 @@ int vcycle_impl(pmg_mesh* m, const T* r, T* z, bool nonzero_u, hipStream_t st) {
         }
     }
     for (int l = 1; l <= L; ++l) {
-        Level& lv = m->lv[l];
-        Level& lc = m->lv[l - 1];
-        const int nu = m->nu_mode == 0 ? 1 : (1 << (L - l));
-        launch_prolong_add<T>(lc.lay, lv.lay, Sel<T>::tabs(lv).J, u[l - 1], u[l], st);
+        Level& lv = *A[l];
+        Level& lc = *A[l - 1];
+        if (lv.kind == 'p') launch_prolong_add<T>(lc.lay, lv.lay, jdown<T>(lv), u[l - 1], u[l], st);
+        else launch_hprolong_add<T>(lc.lay, lv.lay, hweights<T>(lv), u[l - 1], u[l], st);
         T* y = Sel<T>::y(lv);
-        for (int i = 0; i < nu; ++i) {
-            residual<T>(m, l, F[l], u[l], y, st);
-            launch_smoother_add<T>(Sel<T>::tabs(lv), y, u[l], (T)m->omega[l], st);
+        for (int i = 0; i < lv.nu; ++i) {
+            residual<T>(lv, F[l], u[l], y, st);
+            smooth_add<T>(lv, y, u[l], st);
         }
     }
     return 0;
@@ -643,6 +792,21 @@ int pmg_set_cycle(pmg_mesh* m, int nu_mode, double coarse_rtol, int coarse_maxit
     m->nu_mode = nu_mode;
     m->coarse_rtol = coarse_rtol;
     m->coarse_maxit = coarse_maxit;
+    return rebuild_active(m);
+}
+
+int pmg_set_coarse_mg(pmg_mesh* m, int levels, double omega, int nu) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (levels < 0 || levels > 16 || !(omega > 0.0) || !std::isfinite(omega) || nu < 1 || nu > 16)
+        return fail(PMG_EINVAL, "bad coarse multigrid parameters");
+    if (levels > 0 && m->lv[0].p < 2) return fail(PMG_EUNSUP, "degree-1 levels need p_0 = 2");
+    int rc;
+    if ((rc = build_h_levels(m, levels))) return rc;
+    m->hmg_levels = levels;
+    m->hmg_omega = omega;
+    m->hmg_nu = nu;
+    if ((rc = rebuild_active(m))) return rc;
+    HIPCHK(hipDeviceSynchronize());
     return 0;
 }
 
@@ -654,7 +818,7 @@ int pmg_set_damping(pmg_mesh* m, const float* om, int n) {
         if (!(om[j] > 0.0f) || !std::isfinite(om[j])) return fail(PMG_EINVAL, "damping must be > 0");
         m->omega[m->L - j] = om[j];
     }
-    return 0;
+    return rebuild_active(m);
 }
 
 int pmg_vcycle(pmg_mesh* m, int dtype, const void* r, void* z, void* stream) {
@@ -737,7 +901,7 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
     while (std::sqrt(rr) > eps && it < maxit) {
         if (mode == 1) {
             // Alg. 4: u <- MultigridCycle(u, F); r = F - H u
-            if (m->L == 0) {
+            if (m->act.size() == 1) {
                 // coarse CG on the whole problem applied to the residual
                 if ((rc = vcycle_impl<double>(m, m->w_r, m->w_z, false, st))) return rc;
                 launch_axpy<double>(1.0, m->w_z, m->w_u, n, st);

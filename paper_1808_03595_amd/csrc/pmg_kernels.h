@@ -28,6 +28,12 @@ template <typename T> void launch_sub_from(const T* x, T* y, int64_t n, hipStrea
 template <typename T> void launch_axpy(T a, const T* x, T* y, int64_t n, hipStream_t);
 template <typename T, typename U>
 void launch_cast_scale(const T* x, U* y, const double* sc, int invert, int64_t n, hipStream_t);
+template <typename T>
+void launch_hprolong_add(const Layout& Lc, const Layout& Lf, const T* const* t, const T* uc, T* uf, hipStream_t);
+template <typename T>
+void launch_hrestrict(const Layout& Lf, const Layout& Lc, const T* const* t, const T* rf, T* rc, hipStream_t);
+template <typename T>
+void launch_point_smooth(const Layout& L, const T* dg, const T* r, T* u, T omega, hipStream_t);
 template <typename T> size_t smem_condensed_op(int p);
 template <typename T> size_t smem_smoother(int p);
 

@@ -869,6 +869,101 @@ __global__ void k_restrict_combine(Layout L, const T* __restrict__ tbuf, T* __re
 }
 
 // ---------------------------------------------------------------------------
+// Degree-1 levels (optional multigrid below p_0).  With p = 1 every node is
+// stored in a family-0 plane, so a level is a plain 3D array [i1][i3][i2].
+// h-transfers between a mesh and the mesh with pairs of elements merged:
+// even fine vertices coincide with coarse vertices, odd ones interpolate
+// linearly with t_i = h_{i-1} / (h_{i-1} + h_i); restriction = transpose.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline T* p1_at(const Layout& L, T* x, int i1, int i2, int i3) {
+    return x + L.plane0(i1) + (int64_t)i3 * L.pitch[0] + i2;
+}
+
+template <typename T>
+__global__ void k_hprolong_add(Layout Lc, Layout Lf, const T* __restrict__ t1, const T* __restrict__ t2,
+                               const T* __restrict__ t3, const T* __restrict__ uc, T* __restrict__ uf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)Lf.N[0] * Lf.N[1] * Lf.N[2];
+    if (i >= tot) return;
+    const int f1 = (int)(i % Lf.N[0]);
+    const int64_t rest = i / Lf.N[0];
+    const int f2 = (int)(rest % Lf.N[1]), f3 = (int)(rest / Lf.N[1]);
+    if (is_dir(Lf, f1, f2, f3)) return;
+    int c[3][2];
+    T w[3][2];
+    const int f[3] = {f1, f2, f3};
+    const T* tt[3] = {t1, t2, t3};
+    for (int d = 0; d < 3; ++d) {
+        if (f[d] % 2 == 0) {
+            c[d][0] = c[d][1] = f[d] / 2;
+            w[d][0] = 1;
+            w[d][1] = 0;
+        } else {
+            c[d][0] = (f[d] - 1) / 2;
+            c[d][1] = (f[d] + 1) / 2;
+            w[d][1] = tt[d][f[d]];
+            w[d][0] = (T)1 - w[d][1];
+        }
+    }
+    T s = 0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int cc = 0; cc < 2; ++cc) {
+                T wt = w[0][a] * w[1][b] * w[2][cc];
+                if (wt != (T)0) s += wt * *p1_at(Lc, uc, c[0][a], c[1][b], c[2][cc]);
+            }
+    *p1_at(Lf, uf, f1, f2, f3) += s;
+}
+
+template <typename T>
+__global__ void k_hrestrict(Layout Lf, Layout Lc, const T* __restrict__ t1, const T* __restrict__ t2,
+                            const T* __restrict__ t3, const T* __restrict__ rf, T* __restrict__ rc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Lc.len) return;
+    // every slot of the coarse array is written (zero outside the unknowns)
+    int d0 = (i >= Lc.off[2]) ? 2 : (i >= Lc.off[1] ? 1 : 0);
+    T s = 0;
+    if (d0 == 0) {
+        int64_t loc = i;
+        int j = (int)(loc / Lc.pstride[0]);
+        int64_t rem = loc - (int64_t)j * Lc.pstride[0];
+        int r = (int)(rem / Lc.pitch[0]), cidx = (int)(rem - (int64_t)r * Lc.pitch[0]);
+        if (r < Lc.rows[0] && cidx < Lc.N[1] && !is_dir(Lc, j, cidx, r)) {
+            const int C[3] = {j, cidx, r};
+            const T* tt[3] = {t1, t2, t3};
+            int fi[3][3];
+            T fw[3][3];
+            for (int d = 0; d < 3; ++d) {
+                fi[d][0] = 2 * C[d] - 1;
+                fw[d][0] = tt[d][2 * C[d] - 1 >= 0 ? 2 * C[d] - 1 : 0];
+                fi[d][1] = 2 * C[d];
+                fw[d][1] = 1;
+                fi[d][2] = 2 * C[d] + 1;
+                fw[d][2] = (2 * C[d] + 1 < Lf.N[d]) ? (T)1 - tt[d][2 * C[d] + 1] : (T)0;
+                if (fi[d][0] < 0) fw[d][0] = 0;
+            }
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    for (int cc = 0; cc < 3; ++cc) {
+                        T wt = fw[0][a] * fw[1][b] * fw[2][cc];
+                        if (wt == (T)0) continue;
+                        s += wt * *p1_at(Lf, rf, fi[0][a], fi[1][b], fi[2][cc]);
+                    }
+        }
+    }
+    rc[i] = s;
+}
+
+// u += omega r / diag on every slot (diag = 1 and r = 0 outside the unknowns)
+template <typename T>
+__global__ void k_point_smooth(int64_t n, const T* __restrict__ dg, const T* __restrict__ r, T* __restrict__ u,
+                               T omega) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) u[i] += omega * r[i] / dg[i];
+}
+
+// ---------------------------------------------------------------------------
 // Static condensation and interior recovery (Alg. 4, Alg. 5), one element
 // per workgroup.  F = M f with the GLL-lumped mass.
 // ---------------------------------------------------------------------------
@@ -1832,6 +1927,20 @@ void launch_restrict(const Layout& Lf, const Layout& Lc, const T* J, const T* rf
     hipLaunchKernelGGL(k_restrict_combine<T>, dim3(nblk(Lc.len)), dim3(256), 0, st, Lc, (const T*)tbuf, rc);
 }
 
+template <typename T>
+void launch_hprolong_add(const Layout& Lc, const Layout& Lf, const T* const* t, const T* uc, T* uf, hipStream_t st) {
+    int64_t tot = (int64_t)Lf.N[0] * Lf.N[1] * Lf.N[2];
+    hipLaunchKernelGGL(k_hprolong_add<T>, dim3(nblk(tot)), dim3(256), 0, st, Lc, Lf, t[0], t[1], t[2], uc, uf);
+}
+template <typename T>
+void launch_hrestrict(const Layout& Lf, const Layout& Lc, const T* const* t, const T* rf, T* rc, hipStream_t st) {
+    hipLaunchKernelGGL(k_hrestrict<T>, dim3(nblk(Lc.len)), dim3(256), 0, st, Lf, Lc, t[0], t[1], t[2], rf, rc);
+}
+template <typename T>
+void launch_point_smooth(const Layout& L, const T* dg, const T* r, T* u, T omega, hipStream_t st) {
+    hipLaunchKernelGGL(k_point_smooth<T>, dim3(nblk(L.len)), dim3(256), 0, st, L.len, dg, r, u, omega);
+}
+
 void launch_condense(const LevelTabs<double>& tb, const double* m1, const double* m2, const double* m3,
                      const double* f, double* Fh, hipStream_t st) {
     const Layout& L = tb.lay;
@@ -1964,7 +2073,12 @@ hipError_t init_kernel_attributes() {
     template void launch_sub_from<T>(const T*, T*, int64_t, hipStream_t);                                  \
     template void launch_axpy<T>(T, const T*, T*, int64_t, hipStream_t);                                   \
     template size_t smem_condensed_op<T>(int);                                                             \
-    template size_t smem_smoother<T>(int);
+    template size_t smem_smoother<T>(int);                                                                 \
+    template void launch_hprolong_add<T>(const Layout&, const Layout&, const T* const*, const T*, T*,       \
+                                         hipStream_t);                                                     \
+    template void launch_hrestrict<T>(const Layout&, const Layout&, const T* const*, const T*, T*,          \
+                                      hipStream_t);                                                        \
+    template void launch_point_smooth<T>(const Layout&, const T*, const T*, T*, T, hipStream_t);
 INST(double)
 INST(float)
 template void launch_cast_scale<double, float>(const double*, float*, const double*, int, int64_t, hipStream_t);

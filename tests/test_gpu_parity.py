@@ -188,3 +188,29 @@ def test_pcg_solve_matches_oracle(gpu, method):
     hist = np.array(st.history())
     assert np.allclose(hist, res.hist, rtol=1e-6, atol=0)
     assert rel(u.cpu().numpy(), res.u) <= 1e-9
+
+
+@pytest.mark.parametrize("n,p,lam,alpha,levels", [((4, 4, 4), 4, 1.0, 1.0, 3), ((8, 4, 4), 3, 0.0, 1.3, 2),
+                                                  ((4, 8, 4), 8, 100.0, 1.0, 4), ((6, 4, 4), 4, 1.0, 1.2, 1)])
+def test_vcycle_with_degree1_levels(gpu, n, p, lam, alpha, levels):
+    """V-cycle with the optional degree-1 levels below p_0 (fixed coarse CG)."""
+    g, o = make_pair(n, p, lam, alpha)
+    g.set_cycle(0, 0.0, 5)
+    g.set_coarse_mg(levels, 0.7, 2)
+    h = solver.Hierarchy(o, nu_mode="kMG", coarse_rtol=0.0, coarse_maxit=5, hmg_levels=levels,
+                         hmg_omega=0.7, hmg_nu=2)
+    io = LevelIO(g, g.num_levels())
+    r = synth.random_grid(o.shape, 61) * o.free_skeleton_mask()
+    ref = h.vcycle(None, r)
+    for dt, tol in ((pmg.F64, 1e-11), (pmg.F32, 1e-4)):
+        tdt = torch.float64 if dt == pmg.F64 else torch.float32
+        z = torch.full((io.len,), float("nan"), dtype=tdt, device=gpu)
+        g.vcycle(io.to_dev(r, tdt), z, dt)
+        torch.cuda.synchronize()
+        assert rel(io.to_grid(z), ref) <= tol
+    g.set_coarse_mg(0)
+    h0 = solver.Hierarchy(o, nu_mode="kMG", coarse_rtol=0.0, coarse_maxit=5)
+    z = torch.full((io.len,), float("nan"), dtype=torch.float64, device=gpu)
+    g.vcycle(io.to_dev(r), z, pmg.F64)
+    torch.cuda.synchronize()
+    assert rel(io.to_grid(z), h0.vcycle(None, r)) <= 1e-11

@@ -270,3 +270,76 @@ def test_paper_iteration_table(p, alpha, method):
     res = solver.solve(m, f, method, rtol=1e-10, maxit=80, coarse_rtol=1e-10)
     tol = 2 if (method == "MG" and alpha == "1.5" and p == 4) else 1
     assert abs(res.iters - want) <= tol, (res.iters, want)
+
+
+# ---- optional degree-1 levels below p_0 (Sec. 4.2's low-order multigrid) ----
+
+def _hat_interp_dense(mc, mf):
+    """Prolongation of degree-1 nodal values from mesh ``mc`` to the finer
+    mesh ``mf`` as a dense matrix over free nodes, built column by column
+    from numpy's piecewise-linear interpolation of each coarse hat function."""
+    xc = [np.concatenate([[0.0], np.cumsum(h)]) for h in mc.h]
+    xf = [np.concatenate([[0.0], np.cumsum(h)]) for h in mf.h]
+    phi = [np.stack([np.interp(xf[d], xc[d], np.eye(len(xc[d]))[a]) for a in range(len(xc[d]))], 1)
+           for d in range(3)]
+    csc, csf = dense.CondensedSystem(mc), dense.CondensedSystem(mf)
+    P = np.zeros((len(csf.B), len(csc.B)))
+    for j in range(len(csc.B)):
+        e = csc.to_grid(np.eye(len(csc.B))[j])
+        u = np.einsum("ia,jb,kc,cba->kji", phi[0], phi[1], phi[2], e)
+        P[:, j] = csf.to_vec(u)
+    return P
+
+
+@pytest.mark.parametrize("n,a", [((4, 4, 4), 1.0), ((8, 4, 6), 1.3)])
+def test_h_transfers_interpolate_and_adjoint(n, a):
+    mf = M.Mesh.box(n, 1, 1.0, a)
+    mc = M.Mesh(*(matfree.merged_widths(h) for h in mf.h), 1, 1.0)
+    csc, csf = dense.CondensedSystem(mc), dense.CondensedSystem(mf)
+    P = _hat_interp_dense(mc, mf)
+    x = synth.random_grid(mc.shape, 3) * mc.free_skeleton_mask()
+    y = synth.random_grid(mf.shape, 4) * mf.free_skeleton_mask()
+    assert rel(matfree.h_prolong(mc, mf, x), csf.to_grid(P @ csc.to_vec(x))) < 1e-14
+    assert rel(matfree.h_restrict(mf, mc, y), csc.to_grid(P.T @ csf.to_vec(y))) < 1e-14
+
+
+def test_vcycle_with_degree1_levels_matches_dense_cycle():
+    """Alg. 3 over p = 4, 2, then degree 1 on the same mesh and on the merged
+    mesh, with dense operators, point-Jacobi smoothing on degree 1 and a
+    direct coarse solve, equals the matrix-free cycle."""
+    m = M.Mesh.box((4, 4, 4), 4, 1.0, 1.3)
+    h = solver.Hierarchy(m, exact_coarse=True, hmg_levels=2, hmg_omega=0.7, hmg_nu=2)
+    assert [x.p for x in h.meshes] == [1, 1, 2, 4] and h.kind[1:] == ["h", "p", "p"]
+    assert h.nu == [2, 2, 1, 1] and h.omega == [0.7, 0.7, 1.0, 1.0]
+    cs = [dense.CondensedSystem(x) for x in h.meshes]
+    Sm = []
+    for c, w, x in zip(cs, h.omega, h.meshes):
+        Sm.append(w * np.diag(1.0 / np.diag(c.Hhat)) if x.p == 1 else c.smoother_matrix(omega=w))
+    Pm = [None, _hat_interp_dense(h.meshes[0], h.meshes[1])]
+    Pm += [dense.prolongation_matrix(h.meshes[l - 1], h.meshes[l]) for l in (2, 3)]
+    L = 3
+    F = synth.random_grid(m.shape, 9) * m.free_skeleton_mask()
+    us, Fs = [None] * 4, [None] * 4
+    Fs[L] = cs[L].to_vec(F)
+    for l in range(L, 0, -1):
+        us[l] = np.zeros(len(cs[l].B))
+        for _ in range(h.nu[l]):
+            us[l] = us[l] + Sm[l] @ (Fs[l] - cs[l].Hhat @ us[l])
+        Fs[l - 1] = Pm[l].T @ (Fs[l] - cs[l].Hhat @ us[l])
+    us[0] = np.linalg.solve(cs[0].Hhat, Fs[0])
+    for l in range(1, L + 1):
+        us[l] = us[l] + Pm[l] @ us[l - 1]
+        for _ in range(h.nu[l]):
+            us[l] = us[l] + Sm[l] @ (Fs[l] - cs[l].Hhat @ us[l])
+    assert rel(h.vcycle(None, F), cs[L].to_grid(us[L])) < 1e-12
+
+
+def test_solve_with_degree1_levels_reaches_same_solution():
+    m = M.Mesh.box((8, 8, 8), 4, 1.0, 1.2)
+    F = synth.random_grid(m.shape, 11)
+    r0 = solver.solve(m, F, method="kMG", rtol=1e-11)
+    h = solver.Hierarchy(m, coarse_rtol=1e-2, hmg_levels=3, hmg_omega=0.8, hmg_nu=2)
+    r1 = solver.solve(m, F, method="kMG", rtol=1e-11, hier=h)
+    assert len(h.meshes) == 5 and h.meshes[0].n == [2, 2, 2]
+    assert r1.hist[-1] <= 1e-11 * r1.hist[0] and r1.iters <= 2 * r0.iters
+    assert rel(r1.u, r0.u) < 1e-9
