@@ -61,7 +61,7 @@ struct Level {
     // coarse CG structures when this level is the bottom of the cycle
     CoarseArgs ca{};
     bool has_ca = false;
-    int coarse_blocks = 16;
+    hipGraphExec_t coarse_exec = nullptr;  // COARSE_RING iteration launches
 };
 
 template <typename T> struct Sel;
@@ -102,7 +102,8 @@ struct pmg_mesh {
     int hmg_nu = 1;
     // coarse CG counters shared by all bottom levels
     int* d_coarse_iters = nullptr;
-    int* d_coarse_err = nullptr;
+    int* h_cstat = nullptr;             // pinned copy of the coarse done flag and count
+    hipStream_t cap_stream = nullptr;   // private stream for graph capture
     int coarse_last = 0;
     long coarse_total = 0;
     // finest-level solver vectors (FP64) and mixed-precision buffers
@@ -228,7 +229,7 @@ int build_coarse(pmg_mesh* m, Level& lev) {
     const int N0 = (int)cslot.size();
     const int* nl = L0.n;
     const int ne = nl[0] * nl[1] * nl[2];
-    std::vector<int> enodes((size_t)ne * 27, -1), radj((size_t)std::max(N0, 1) * 8, -1), cnt(std::max(N0, 1), 0);
+    std::vector<int> enodes((size_t)ne * 27, -1);
     for (int e = 0; e < ne; ++e) {
         int c[3] = {e % nl[0], (e / nl[0]) % nl[1], e / (nl[0] * nl[1])};
         for (int a3 = 0; a3 < nn; ++a3)
@@ -240,13 +241,7 @@ int build_coarse(pmg_mesh* m, Level& lev) {
                     if (i1 == 0 || i2 == 0 || i3 == 0 || i1 == L0.N[0] - 1 || i2 == L0.N[1] - 1 ||
                         i3 == L0.N[2] - 1)
                         continue;
-                    int gi = slot2c[L0.slot(i1, i2, i3, on1, on2)];
-                    int l = (a3 * nn + a2) * nn + a1;
-                    enodes[(size_t)e * 27 + l] = gi;
-                    if (gi >= 0) {
-                        if (cnt[gi] >= 8) return fail(PMG_EUNSUP, "coarse adjacency overflow");
-                        radj[(size_t)gi * 8 + cnt[gi]++] = e * 27 + l;
-                    }
+                    enodes[(size_t)e * 27 + (a3 * nn + a2) * nn + a1] = slot2c[L0.slot(i1, i2, i3, on1, on2)];
                 }
     }
     std::vector<double> dg;
@@ -275,23 +270,38 @@ int build_coarse(pmg_mesh* m, Level& lev) {
     };
     if ((rc = up_int(&a.c_slot, cslot.empty() ? std::vector<int>(1, 0) : cslot))) return rc;
     if ((rc = up_int(&a.e_nodes, enodes))) return rc;
-    if ((rc = up_int(&a.r_adj, radj))) return rc;
     if ((rc = m->upload(&a.diag, dc))) return rc;
     size_t nv = std::max(N0, 1);
-    if ((rc = m->alloc(&a.x, nv)) || (rc = m->alloc(&a.r, nv)) || (rc = m->alloc(&a.z, nv)) ||
-        (rc = m->alloc(&a.p, nv)) || (rc = m->alloc(&a.q, nv)) || (rc = m->alloc(&a.E, std::max(nv, (size_t)ne * 27))))
-        return rc;
-    // one workgroup (small problems, set by PMG_COARSE_BLOCKS or the size)
-    // or several cooperative workgroups of 1024 threads, four threads per element
-    int G = ne / 128;
-    G = std::max(8, std::min(64, G));
-    if (const char* env = std::getenv("PMG_COARSE_BLOCKS")) G = std::max(1, std::min(64, std::atoi(env)));
-    if (nl[0] > 256 || nl[1] > 256 || nl[2] > 256) return fail(PMG_EUNSUP, "more than 256 elements per direction");
-    lev.coarse_blocks = G;
-    if ((rc = m->alloc(&a.partials, 2 * (size_t)G)) || (rc = m->alloc(&a.bar, 2))) return rc;
-    HIPCHK(hipMemset(a.bar, 0, 2 * sizeof(unsigned)));
-    a.err = m->d_coarse_err;
+    if ((rc = m->alloc(&a.x, nv)) || (rc = m->alloc(&a.p, nv))) return rc;
+    for (int k = 0; k < 2; ++k)
+        if ((rc = m->alloc(&a.R[k], nv)) || (rc = m->alloc(&a.Q[k], nv))) return rc;
+    for (int k = 0; k < 3; ++k)
+        if ((rc = m->alloc(&a.W[k], nv))) return rc;
+    a.blocks = coarse_blocks(ne, p0);
+    for (int k = 0; k < 2; ++k)
+        if ((rc = m->alloc(&a.P[k], 2 * (size_t)a.blocks))) return rc;
+    if ((rc = m->alloc(&a.S, 2)) || (rc = m->alloc(&a.stat, 2))) return rc;
+    HIPCHK(hipMemset(a.S, 0, 2 * sizeof(CoarseState)));
+    HIPCHK(hipMemset(a.stat, 0, 2 * sizeof(int)));
     a.iters = m->d_coarse_iters;
+    // one chunk of COARSE_RING iteration launches as a graph
+    if (N0 > 0) {
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
+        for (int j = 0; j < COARSE_RING; ++j) {
+            hipError_t e = launch_coarse_iter(a, j, m->cap_stream);
+            if (e != hipSuccess) {
+                hipGraph_t junk = nullptr;
+                (void)hipStreamEndCapture(m->cap_stream, &junk);
+                if (junk) hipGraphDestroy(junk);
+                return fail(PMG_EHIP, std::string("coarse graph capture: ") + hipGetErrorString(e));
+            }
+        }
+        HIPCHK(hipStreamEndCapture(m->cap_stream, &g));
+        hipError_t e = hipGraphInstantiate(&lev.coarse_exec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(PMG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
     lev.has_ca = true;
     return 0;
 }
@@ -407,9 +417,10 @@ int build_mesh(pmg_mesh* m) {
     m->omega.assign(degs.size(), 1.0);
     int rc = check_lds(m->p);
     if (rc) return rc;
-    if ((rc = m->alloc(&m->d_coarse_iters, 1)) || (rc = m->alloc(&m->d_coarse_err, 1))) return rc;
+    if ((rc = m->alloc(&m->d_coarse_iters, 1))) return rc;
     HIPCHK(hipMemset(m->d_coarse_iters, 0, sizeof(int)));
-    HIPCHK(hipMemset(m->d_coarse_err, 0, sizeof(int)));
+    HIPCHK(hipHostMalloc((void**)&m->h_cstat, 2 * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
     for (size_t l = 0; l < degs.size(); ++l) {
         Level& L = m->lv[l];
         if ((rc = build_level(m, L, degs[l], l ? degs[l - 1] : 0, m->h))) return rc;
@@ -488,28 +499,46 @@ void smooth_add(Level& L, const T* r, T* u, hipStream_t st) {
     else launch_smoother_add<T>(Sel<T>::tabs(L), r, u, (T)L.omega, st);
 }
 
-// Jacobi-preconditioned CG on level 0 (FP64), x = 0 initially: one
-// persistent cooperative kernel.  b and x are level-0 skeleton arrays.
+// Jacobi-preconditioned CG on level 0 (FP64), x = 0 initially: the init
+// kernel, then chunks of COARSE_RING iteration launches (one graph each).
+// Launches after convergence return at once.  With a tolerance the stream
+// is synchronised once the expected number of chunks (from the previous
+// solve) is queued, and more chunks follow until the device reports
+// convergence or maxit; without one, enough chunks for maxit are queued
+// and nothing is synchronised.  b and x are level-0 skeleton arrays.
 int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st) {
     Level& L0 = *m->act[0];
-    HIPCHK(hipMemsetAsync(x, 0, L0.lay.len * sizeof(double), st));
-    if (L0.ca.N0 == 0) return 0;
-    HIPCHK(launch_coarse_cg(L0.ca, L0.coarse_blocks, b, x, m->coarse_maxit, m->coarse_rtol, st));
-    return 0;
+    CoarseArgs& a = L0.ca;
+    HIPCHK(launch_coarse_init(a, b, x, L0.lay.len, m->coarse_maxit, m->coarse_rtol, st));
+    if (a.N0 == 0) return 0;
+    const long need = (long)m->coarse_maxit + 2;  // launches for maxit updates
+    const long cmax = (need + COARSE_RING - 1) / COARSE_RING;
+    if (!(m->coarse_rtol > 0.0)) {
+        for (long c = 0; c < cmax; ++c) HIPCHK(hipGraphLaunch(L0.coarse_exec, st));
+        return 0;
+    }
+    long chunks = std::min(cmax, std::max(1L, ((long)m->coarse_last + 3 + COARSE_RING - 1) / COARSE_RING));
+    long launched = 0;
+    while (true) {
+        for (; launched < chunks; ++launched) HIPCHK(hipGraphLaunch(L0.coarse_exec, st));
+        HIPCHK(hipMemcpyAsync(m->h_cstat, a.stat, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (m->h_cstat[0]) {
+            m->coarse_last = m->h_cstat[1];
+            return 0;
+        }
+        if (launched >= cmax) return fail(PMG_EHIP, "coarse solver did not finish within maxit");
+        chunks = std::min(cmax, launched + std::max(1L, launched / 2));
+    }
 }
 
-// Read and reset the device-side coarse iteration counter and error flag.
+// Read and reset the device-side coarse iteration counter.
 int coarse_stats(pmg_mesh* m, hipStream_t st, int* iters) {
-    int h[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(&h[0], m->d_coarse_iters, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(&h[1], m->d_coarse_err, sizeof(int), hipMemcpyDeviceToHost, st));
+    int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, m->d_coarse_iters, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipMemsetAsync(m->d_coarse_iters, 0, sizeof(int), st));
-    if (h[1]) {
-        (void)hipMemsetAsync(m->d_coarse_err, 0, sizeof(int), st);
-        return fail(PMG_EHIP, "coarse solver: grid barrier wait timed out");
-    }
-    *iters = h[0];
+    *iters = h;
     return 0;
 }
 
@@ -660,8 +689,14 @@ int pmg_create_mesh_widths(int n1, int n2, int n3, int p, double lambda, const d
 void pmg_destroy_mesh(pmg_mesh* m) {
     if (!m) return;
     hipDeviceSynchronize();
+    for (Level& l : m->lv)
+        if (l.coarse_exec) (void)hipGraphExecDestroy(l.coarse_exec);
+    for (Level& l : m->hlv)
+        if (l.coarse_exec) (void)hipGraphExecDestroy(l.coarse_exec);
     for (void* q : m->allocs) hipFree(q);
     if (m->hscal) hipHostFree(m->hscal);
+    if (m->h_cstat) (void)hipHostFree(m->h_cstat);
+    if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
     delete m;
 }
 

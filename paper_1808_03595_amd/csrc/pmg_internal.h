@@ -98,25 +98,39 @@ void coarse_diagonal(const Layout& lay, double lam, const std::vector<double> h[
 
 namespace pmg {
 
-// Coarse-level (p_0 <= 2) problem in compact numbering, for the persistent
-// Jacobi-CG kernel.  Unknown i lives at plane-layout slot c_slot[i].
+// Coarse-level (p_0 <= 2) problem in compact numbering for the Jacobi-CG
+// iteration kernels.  Unknown i lives at plane-layout slot c_slot[i].
+//
+// Scalars of the coarse CG carried from one iteration launch to the next
+// (written by block 0 of each launch into the other ring slot).
+struct CoarseState {
+    double gamma, alpha, gamma0, rtol2;
+    double* out;     // skeleton array receiving the solution
+    int it;          // completed updates; -1 before the first launch
+    int done;
+    int maxit;
+    int pad;
+};
+
 struct CoarseArgs {
     int N0;          // unknowns
     int ne;          // elements
     int n[3];
     int p0;          // 1 or 2
     double lam;
-    const int* c_slot;    // [N0]
+    const int* c_slot;    // [N0] skeleton slot of each unknown
     const int* e_nodes;   // [ne][27] compact index of local node or -1
-    const int* r_adj;     // [N0][8]  e * 27 + local, or -1 (set-up check only)
     const double* diag;   // [N0]
     const double* el_m[3];  // level-0 element tables
     const double* el_L[3];
-    double *x, *r, *z, *p, *q, *E;  // work vectors [N0]; E accumulates w = A z
-    double* partials;     // [2 * blocks]
-    unsigned* bar;        // [2]: arrival counter, generation
-    int* err;             // set to 1 if a barrier wait timed out
+    double *x, *p;        // [N0], updated in place by the owning element
+    double *R[2], *Q[2];  // [N0] ping-pong residual and q = A p
+    double *W[3];         // [N0] rotating accumulators of w = A z
+    double *P[2];         // [2 * blocks] per-block partial sums (r.z, w.z)
+    CoarseState* S;       // [2]
+    int* stat;            // [2]: done flag and update count of the last solve
     int* iters;           // accumulated iteration count
+    int blocks;           // workgroups of one iteration launch
 };
 
 }  // namespace pmg

@@ -10,8 +10,13 @@ constexpr int REDUCE_BLOCKS = 512;
 hipError_t init_kernel_attributes();
 void set_mfma_min_degree(int p);
 void set_op_atomic(bool on);
-hipError_t launch_coarse_cg(const CoarseArgs& a, int blocks, const double* b, double* x, int maxit,
-                            double rtol, hipStream_t st);
+// Coarse CG (launch-per-iteration form): the init kernel, then iteration
+// launches with ring index j = 0, 1, ..., COARSE_RING - 1, 0, ...
+constexpr int COARSE_RING = 12;
+hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, double* out, int64_t len, int maxit,
+                              double rtol, hipStream_t st);
+hipError_t launch_coarse_iter(const CoarseArgs& a, int j, hipStream_t st);
+int coarse_blocks(int ne, int p0);
 
 template <typename T> void launch_grid_to_skel(const Layout&, const double*, T*, hipStream_t);
 template <typename T> void launch_skel_to_grid(const Layout&, const T*, double*, hipStream_t);

@@ -1310,379 +1310,214 @@ __global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ z, con
 }
 
 // ---------------------------------------------------------------------------
-// Coarse-grid solve (Sec. 4.1: CG on the condensed system at p_0 = 2) as one
-// persistent cooperative kernel: Jacobi-preconditioned CG in the
-// single-reduction (Chronopoulos-Gear) form, two grid barriers per
-// iteration.  Rows (compact unknowns) and elements are split into
-// contiguous chunks per workgroup; the condensed operator is applied element
-// by element into a per-element buffer E and gathered per row, so every
-// sum is taken in a fixed order and the result is deterministic.
+// Coarse-grid solve (Sec. 4.1: CG on the condensed system at p_0 = 2),
+// Jacobi-preconditioned, in the single-reduction (Chronopoulos-Gear) form.
+// One launch of k_coarse_iter is one CG iteration over the whole chip: the
+// launch boundary is the only global synchronisation (cheaper than a
+// software grid barrier across all CUs), the two dot products travel as
+// per-block partial sums that every block of the next launch adds up in the
+// same order, and the vector updates of an iteration are fused with the
+// element-wise application of the condensed operator: each element thread
+// recomputes the updated residual and preconditioned residual at its nodes
+// from the previous iteration's vectors.  Every unknown is owned by exactly
+// one element (the one whose lower corner is nearest), and only the owner
+// writes the updated p, x, r and q.
+//
+// Launch k uses ring index j = k mod COARSE_RING (a multiple of 2 and 3):
+//   reads  r = R[j%2], q = Q[j%2], w = W[j%3], partials P[j%2], state S[j%2]
+//   writes R, Q [(j+1)%2] (owners), W[(j+1)%3] += A z, W[(j+2)%3] = 0 (owners),
+//          P[(j+1)%2], S[(j+1)%2]; p and x in place (owners)
+// A chunk of COARSE_RING launches is captured once as a HIP graph.
 // ---------------------------------------------------------------------------
-// Data shared between workgroups inside the persistent kernel (z, E and the
-// partial sums) is written and read with device-coherent accesses (relaxed
-// agent-scope atomics: the sc1 loads and stores that bypass the
-// per-XCD L2), so the barrier itself needs no cache flushes: every thread
-// waits for its own stores to complete, then thread 0 arrives.
-template <typename T>
-__device__ __forceinline__ T ld_dev(const T* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// r = b (compact), all other vectors zero, the output array zero; state
+// "before the first launch".
+__global__ void k_coarse_init(CoarseArgs a, const double* __restrict__ b, double* __restrict__ out,
+                              int64_t len, int maxit, double rtol) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = t; s < len; s += stride) out[s] = 0.0;
+    for (int64_t i = t; i < a.N0; i += stride) {
+        a.R[0][i] = b[a.c_slot[i]];
+        a.Q[0][i] = 0.0;
+        a.W[0][i] = 0.0;
+        a.W[1][i] = 0.0;
+        a.W[2][i] = 0.0;
+        a.x[i] = 0.0;
+        a.p[i] = 0.0;
+    }
+    if (t == 0) {
+        CoarseState s0;
+        s0.gamma = s0.alpha = s0.gamma0 = 0.0;
+        s0.rtol2 = rtol * rtol;
+        s0.out = out;
+        s0.it = -1;
+        s0.done = 0;
+        s0.maxit = maxit;
+        s0.pad = 0;
+        a.S[0] = s0;
+        a.stat[0] = 0;
+        a.stat[1] = 0;
+    }
 }
-template <typename T>
-__device__ __forceinline__ void st_dev(T* p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0f70); }  // vmcnt(0)
 
-__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nb, int* err) {
-    wait_stores();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned g = ld_dev(bar + 1);
-        unsigned prev = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == nb - 1) {
-            st_dev(bar, 0u);
-            wait_stores();
-            __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Row of the level-0 element operator (condensed for p_0 = 2: one interior
+// node) at local node (a1, a2, a3), applied to the element vector u.
+// tb: m1[3] m2[3] m3[3] at 0, 3, 6; L1, L2, L3 (row-major nn x nn) at 9, 18, 27.
+template <int P0>
+__device__ inline double coarse_row(const double* tb, const double* u, double lam, int a1, int a2, int a3) {
+    constexpr int nn = P0 + 1;
+    const double *m1 = tb, *m2 = tb + 3, *m3 = tb + 6, *L1 = tb + 9, *L2 = tb + 18, *L3 = tb + 27;
+    double x1 = 0.0, x2 = 0.0, x3 = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < nn; ++jj) {
+        x1 += L1[a1 * nn + jj] * u[(a3 * nn + a2) * nn + jj];
+        x2 += L2[a2 * nn + jj] * u[(a3 * nn + jj) * nn + a1];
+        x3 += L3[a3 * nn + jj] * u[(jj * nn + a2) * nn + a1];
+    }
+    double y = lam * m1[a1] * m2[a2] * m3[a3] * u[(a3 * nn + a2) * nn + a1] + m3[a3] * m2[a2] * x1 +
+               m3[a3] * m1[a1] * x2 + m2[a2] * m1[a1] * x3;
+    if (P0 == 2) {
+        // Schur complement of the interior node (1,1,1): y -= H_BI s / H_II,
+        // s = H_IB u (only the six face centres couple to the interior)
+        const double s = m3[1] * m2[1] * (L1[3] * u[12] + L1[5] * u[14]) +
+                         m3[1] * m1[1] * (L2[3] * u[10] + L2[5] * u[16]) +
+                         m2[1] * m1[1] * (L3[3] * u[4] + L3[5] * u[22]);
+        const double hii = lam * m1[1] * m2[1] * m3[1] + m3[1] * m2[1] * L1[4] + m3[1] * m1[1] * L2[4] +
+                           m2[1] * m1[1] * L3[4];
+        double col = 0.0;
+        if (a2 == 1 && a3 == 1) col = m3[1] * m2[1] * L1[a1 * 3 + 1];
+        else if (a1 == 1 && a3 == 1) col = m3[1] * m1[1] * L2[a2 * 3 + 1];
+        else if (a1 == 1 && a2 == 1) col = m2[1] * m1[1] * L3[a3 * 3 + 1];
+        y -= (s / hii) * col;
+    }
+    return y;
+}
+
+template <int P0>
+struct CoarseShape {
+    static constexpr int nn = P0 + 1, nl = nn * nn * nn, epb = 256 / nl;
+};
+
+template <int P0>
+__global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j) {
+    using CS = CoarseShape<P0>;
+    constexpr int nn = CS::nn, nl = CS::nl, EPB = CS::epb;
+    __shared__ double tab[EPB][36];
+    __shared__ double zl[EPB][nl];
+    __shared__ double red[8];
+    __shared__ double sums[2];
+    const int jr = j & 1, jn = jr ^ 1;
+    const CoarseState si = a.S[jr];
+    if (si.done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.S[jn] = si;
+        return;
+    }
+    CoarseState so = si;
+    double alpha = 0.0, beta = 0.0;
+    bool finish = false;
+    if (si.it < 0) {
+        so.it = 0;                      // first launch: z_0 = D^-1 r_0, w_0 = A z_0
+    } else {
+        double g = 0.0, d = 0.0;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+            g += a.P[jr][2 * b];
+            d += a.P[jr][2 * b + 1];
+        }
+        g = block_sum(g, red);
+        __syncthreads();
+        d = block_sum(d, red);
+        if (threadIdx.x == 0) {
+            sums[0] = g;
+            sums[1] = d;
+        }
+        __syncthreads();
+        const double gnew = sums[0], delta = sums[1];
+        if (si.it == 0) {
+            so.gamma0 = gnew;
+            if (!(gnew > 0.0) || si.maxit <= 0) finish = true;
+            else alpha = gnew / delta;
+        } else if (si.it >= si.maxit || gnew <= si.rtol2 * si.gamma0) {
+            finish = true;
         } else {
-            // bounded wait: all blocks are co-resident (cooperative launch),
-            // the limit only guards against a broken launch
-            long spins = 0;
-            while (ld_dev(bar + 1) == g) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > (1L << 26)) {
-                    atomicExch(err, 1);
-                    break;
-                }
+            beta = gnew / si.gamma;
+            alpha = gnew / (delta - beta * gnew / si.alpha);
+        }
+        so.gamma = gnew;
+        so.alpha = alpha;
+        so.it = si.it + 1;
+    }
+    if (finish) {
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N0; i += stride)
+            si.out[a.c_slot[i]] = a.x[i];
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            so = si;
+            so.done = 1;
+            a.S[jn] = so;
+            a.stat[0] = 1;
+            a.stat[1] = si.it;
+            atomicAdd(a.iters, si.it);
+        }
+        return;
+    }
+    // 1D tables of this block's elements
+    for (int t = threadIdx.x; t < EPB * 36; t += blockDim.x) {
+        const int el = t / 36, o = t - el * 36, e = blockIdx.x * EPB + el;
+        double v = 0.0;
+        if (e < a.ne) {
+            const int c[3] = {e % a.n[0], (e / a.n[0]) % a.n[1], e / (a.n[0] * a.n[1])};
+            if (o < 9) {
+                const int d = o / 3, k = o % 3;
+                if (k < nn) v = a.el_m[d][c[d] * nn + k];
+            } else {
+                const int d = (o - 9) / 9, k = (o - 9) % 9;
+                if (k < nn * nn) v = a.el_L[d][c[d] * nn * nn + k];
             }
         }
+        tab[el][o] = v;
+    }
+    const int el = threadIdx.x / nl, l = threadIdx.x - el * nl;
+    const int e = blockIdx.x * EPB + el;
+    const bool act = el < EPB && e < a.ne;
+    const int a1 = l % nn, a2 = (l / nn) % nn, a3 = l / (nn * nn);
+    int gi = -1;
+    double zn = 0.0, gpart = 0.0, dpart = 0.0;
+    if (act) {
+        gi = a.e_nodes[e * 27 + l];
+        if (gi >= 0) {
+            const double dg = a.diag[gi], ro = a.R[jr][gi];
+            const double qn = a.W[j % 3][gi] + beta * a.Q[jr][gi];
+            const double rn = ro - alpha * qn;
+            zn = rn / dg;
+            const int c1 = e % a.n[0], c2 = (e / a.n[0]) % a.n[1], c3 = e / (a.n[0] * a.n[1]);
+            const bool own = (a1 < P0 || c1 == a.n[0] - 1) && (a2 < P0 || c2 == a.n[1] - 1) &&
+                             (a3 < P0 || c3 == a.n[2] - 1);
+            if (own) {
+                const double pn = ro / dg + beta * a.p[gi];
+                a.p[gi] = pn;
+                a.x[gi] += alpha * pn;
+                a.R[jn][gi] = rn;
+                a.Q[jn][gi] = qn;
+                a.W[(j + 2) % 3][gi] = 0.0;
+                gpart = rn * zn;
+            }
+        }
+        zl[el][l] = zn;
     }
     __syncthreads();
-}
-
-// Sum of per-block pairs partials[2*b + k] over all blocks, same order in
-// every block; result broadcast to all threads.
-__device__ inline void sum_partials(const double* partials, double& a, double& b) {
-    __shared__ double red[16];
-    __shared__ double res[2];
-    double va = 0.0, vb = 0.0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
-        va += __hip_atomic_load(partials + 2 * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        vb += __hip_atomic_load(partials + 2 * i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (gi >= 0) {
+        const double y = coarse_row<P0>(tab[el], zl[el], a.lam, a1, a2, a3);
+        unsafeAtomicAdd(a.W[(j + 1) % 3] + gi, y);
+        dpart = y * zn;
     }
-    double sa = block_sum(va, red);
+    gpart = block_sum(gpart, red);
     __syncthreads();
-    double sb = block_sum(vb, red);
+    dpart = block_sum(dpart, red);
     if (threadIdx.x == 0) {
-        res[0] = sa;
-        res[1] = sb;
+        a.P[jn][2 * blockIdx.x] = gpart;
+        a.P[jn][2 * blockIdx.x + 1] = dpart;
+        if (blockIdx.x == 0) a.S[jn] = so;
     }
-    __syncthreads();
-    a = res[0];
-    b = res[1];
-    __syncthreads();
-}
-
-__device__ inline void write_partials(double* partials, double a, double b) {
-    __shared__ double red[16];
-    double sa = block_sum(a, red);
-    __syncthreads();
-    double sb = block_sum(b, red);
-    if (threadIdx.x == 0) {
-        __hip_atomic_store(partials + 2 * blockIdx.x, sa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(partials + 2 * blockIdx.x + 1, sb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-// Level-0 1D element tables of all element indices, staged in LDS once per
-// kernel: per direction d, element e: m[3] then L[9] (p0 = 1 uses the first
-// 2 + 4 entries).
-constexpr int COARSE_MAXN = 256;  // elements per direction supported by the LDS table
-constexpr int COARSE_THREADS = 1024;
-constexpr int COARSE_SPLIT = 4;   // threads per element in the element phase
-
-// w += Hhat_e z_e for one quarter of the local nodes of the elements of this
-// block (hardware FP64 atomics into w); returns this thread's part of
-// sum_e (Hhat_e z_e) . z_e, which equals (w, z).
-template <int P0>
-__device__ double coarse_elements_t(const CoarseArgs& a, const double* tab, int e0, int e1) {
-    constexpr int nn = P0 + 1, nl = nn * nn * nn;
-    double part = 0.0;
-    for (int t = (int)threadIdx.x; t < (e1 - e0) * COARSE_SPLIT; t += blockDim.x) {
-        const int e = e0 + t / COARSE_SPLIT, sub = t % COARSE_SPLIT;
-        double u[nl];
-#pragma unroll
-        for (int l = 0; l < nl; ++l) {
-            int gi = a.e_nodes[e * 27 + l];
-            u[l] = gi >= 0 ? ld_dev(a.z + gi) : 0.0;
-        }
-        const int c1 = e % a.n[0], c2 = (e / a.n[0]) % a.n[1], c3 = e / (a.n[0] * a.n[1]);
-        const double* t1 = tab + (0 * COARSE_MAXN + c1) * 12;
-        const double* t2 = tab + (1 * COARSE_MAXN + c2) * 12;
-        const double* t3 = tab + (2 * COARSE_MAXN + c3) * 12;
-        const double *m1 = t1, *m2 = t2, *m3 = t3, *L1 = t1 + 3, *L2 = t2 + 3, *L3 = t3 + 3;
-        double sh = 0.0;
-        if (P0 == 2) {
-            // Schur complement of the single interior node (1,1,1):
-            // s = H_IB u_B, hii = H_II, sh = s / hii
-            double s = m3[1] * m2[1] * (L1[3] * u[12] + L1[5] * u[14]) +
-                       m3[1] * m1[1] * (L2[3] * u[10] + L2[5] * u[16]) +
-                       m2[1] * m1[1] * (L3[3] * u[4] + L3[5] * u[22]);
-            double hii = a.lam * m1[1] * m2[1] * m3[1] + m3[1] * m2[1] * L1[4] + m3[1] * m1[1] * L2[4] +
-                         m2[1] * m1[1] * L3[4];
-            sh = s / hii;
-        }
-#pragma unroll
-        for (int l = 0; l < nl; ++l) {
-            if (l % COARSE_SPLIT != sub) continue;
-            const int gi = a.e_nodes[e * 27 + l];
-            if (gi < 0) continue;
-            const int a1 = l % nn, a2 = (l / nn) % nn, a3 = l / (nn * nn);
-            double x1 = 0.0, x2 = 0.0, x3 = 0.0;
-#pragma unroll
-            for (int jj = 0; jj < nn; ++jj) {
-                x1 += L1[a1 * nn + jj] * u[(a3 * nn + a2) * nn + jj];
-                x2 += L2[a2 * nn + jj] * u[(a3 * nn + jj) * nn + a1];
-                x3 += L3[a3 * nn + jj] * u[(jj * nn + a2) * nn + a1];
-            }
-            double y = a.lam * m1[a1] * m2[a2] * m3[a3] * u[l] + m3[a3] * m2[a2] * x1 + m3[a3] * m1[a1] * x2 +
-                       m2[a2] * m1[a1] * x3;
-            if (P0 == 2) {
-                double col = 0.0;
-                if (a2 == 1 && a3 == 1) col = m3[1] * m2[1] * L1[a1 * 3 + 1];
-                else if (a1 == 1 && a3 == 1) col = m3[1] * m1[1] * L2[a2 * 3 + 1];
-                else if (a1 == 1 && a2 == 1) col = m2[1] * m1[1] * L3[a3 * 3 + 1];
-                y -= sh * col;
-            }
-            unsafeAtomicAdd(a.E + gi, y);
-            part += y * u[l];
-        }
-    }
-    return part;
-}
-
-__device__ inline double coarse_elements(const CoarseArgs& a, const double* tab, int e0, int e1) {
-    return a.p0 == 2 ? coarse_elements_t<2>(a, tab, e0, e1) : coarse_elements_t<1>(a, tab, e0, e1);
-}
-
-__global__ void __launch_bounds__(COARSE_THREADS) k_coarse_cg(CoarseArgs a, const double* __restrict__ b_in,
-                                                              double* __restrict__ x_out, int maxit, double rtol) {
-    __shared__ double tab[3 * COARSE_MAXN * 12];
-    const unsigned nb = gridDim.x;
-    const int nn = a.p0 + 1;
-    for (int d = 0; d < 3; ++d)
-        for (int i = threadIdx.x; i < a.n[d] * 12; i += blockDim.x) {
-            int e = i / 12, o = i % 12;
-            double v = 0.0;
-            if (o < nn) v = a.el_m[d][e * nn + o];
-            else if (o >= 3 && o - 3 < nn * nn) v = a.el_L[d][e * nn * nn + (o - 3)];
-            tab[(d * COARSE_MAXN + e) * 12 + o] = v;
-        }
-    __syncthreads();
-    // E holds the assembled w = A z (one value per unknown)
-    double* w = a.E;
-    const int R = (a.N0 + (int)nb - 1) / (int)nb;
-    const int r0 = blockIdx.x * R, r1 = min(a.N0, r0 + R);
-    const int EB = (a.ne + (int)nb - 1) / (int)nb;
-    const int e0 = min(a.ne, (int)blockIdx.x * EB), e1 = min(a.ne, e0 + EB);
-    // r = b, x = 0, z = D^-1 r, w = 0, gamma partial
-    double g_part = 0.0;
-    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-        double ri = b_in[a.c_slot[i]];
-        double zi = ri / a.diag[i];
-        a.x[i] = 0.0;
-        a.r[i] = ri;
-        st_dev(a.z + i, zi);
-        st_dev(w + i, 0.0);
-        g_part += ri * zi;
-    }
-    grid_barrier(a.bar, nb, a.err);
-    double d_part = coarse_elements(a, tab, e0, e1);
-    write_partials(a.partials, g_part, d_part);
-    grid_barrier(a.bar, nb, a.err);
-    double gamma, delta;
-    sum_partials(a.partials, gamma, delta);
-    const double gamma0 = gamma;
-    int it = 0;
-    if (gamma > 0.0 && maxit > 0) {
-        double alpha = gamma / delta, beta = 0.0;
-        bool first = true;
-        while (true) {
-            // rows: p = z + beta p; q = w + beta q; w = 0;
-            //       x += alpha p; r -= alpha q; z = D^-1 r; gamma partial
-            g_part = 0.0;
-            for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-                const double wi = ld_dev(w + i);
-                const double zo = ld_dev(a.z + i);
-                double pi = first ? zo : zo + beta * a.p[i];
-                double qi = first ? wi : wi + beta * a.q[i];
-                a.p[i] = pi;
-                a.q[i] = qi;
-                st_dev(w + i, 0.0);
-                double xi = a.x[i] + alpha * pi;
-                double ri = a.r[i] - alpha * qi;
-                a.x[i] = xi;
-                a.r[i] = ri;
-                double zi = ri / a.diag[i];
-                st_dev(a.z + i, zi);
-                g_part += ri * zi;
-            }
-            first = false;
-            ++it;
-            if (it >= maxit) break;
-            grid_barrier(a.bar, nb, a.err);
-            d_part = coarse_elements(a, tab, e0, e1);
-            write_partials(a.partials, g_part, d_part);
-            grid_barrier(a.bar, nb, a.err);
-            double gnew;
-            sum_partials(a.partials, gnew, delta);
-            if (gnew <= rtol * rtol * gamma0) break;
-            beta = gnew / gamma;
-            alpha = gnew / (delta - beta * gnew / alpha);
-            gamma = gnew;
-        }
-    }
-    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) x_out[a.c_slot[i]] = a.x[i];
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.iters, it);
-}
-
-// Single-workgroup variant for small coarse problems: the whole CG runs in
-// one workgroup of COARSE_THREADS threads on one CU, so workgroup barriers
-// replace grid barriers and plain cached memory accesses are coherent.  The
-// condensed operator is applied element by element into E[e][27] and
-// gathered per unknown through r_adj (fixed summation order).
-template <int P0>
-__device__ double coarse_elements_local(const CoarseArgs& a, const double* tab) {
-    constexpr int nn = P0 + 1, nl = nn * nn * nn;
-    double part = 0.0;
-    for (int t = (int)threadIdx.x; t < a.ne * COARSE_SPLIT; t += blockDim.x) {
-        const int e = t / COARSE_SPLIT, sub = t % COARSE_SPLIT;
-        double u[nl];
-#pragma unroll
-        for (int l = 0; l < nl; ++l) {
-            int gi = a.e_nodes[e * 27 + l];
-            u[l] = gi >= 0 ? a.z[gi] : 0.0;
-        }
-        const int c1 = e % a.n[0], c2 = (e / a.n[0]) % a.n[1], c3 = e / (a.n[0] * a.n[1]);
-        const double* t1 = tab + (0 * COARSE_MAXN + c1) * 12;
-        const double* t2 = tab + (1 * COARSE_MAXN + c2) * 12;
-        const double* t3 = tab + (2 * COARSE_MAXN + c3) * 12;
-        const double *m1 = t1, *m2 = t2, *m3 = t3, *L1 = t1 + 3, *L2 = t2 + 3, *L3 = t3 + 3;
-        double sh = 0.0;
-        if (P0 == 2) {
-            double s = m3[1] * m2[1] * (L1[3] * u[12] + L1[5] * u[14]) +
-                       m3[1] * m1[1] * (L2[3] * u[10] + L2[5] * u[16]) +
-                       m2[1] * m1[1] * (L3[3] * u[4] + L3[5] * u[22]);
-            double hii = a.lam * m1[1] * m2[1] * m3[1] + m3[1] * m2[1] * L1[4] + m3[1] * m1[1] * L2[4] +
-                         m2[1] * m1[1] * L3[4];
-            sh = s / hii;
-        }
-#pragma unroll
-        for (int l = 0; l < nl; ++l) {
-            if (l % COARSE_SPLIT != sub) continue;
-            if (a.e_nodes[e * 27 + l] < 0) continue;
-            const int a1 = l % nn, a2 = (l / nn) % nn, a3 = l / (nn * nn);
-            double x1 = 0.0, x2 = 0.0, x3 = 0.0;
-#pragma unroll
-            for (int jj = 0; jj < nn; ++jj) {
-                x1 += L1[a1 * nn + jj] * u[(a3 * nn + a2) * nn + jj];
-                x2 += L2[a2 * nn + jj] * u[(a3 * nn + jj) * nn + a1];
-                x3 += L3[a3 * nn + jj] * u[(jj * nn + a2) * nn + a1];
-            }
-            double y = a.lam * m1[a1] * m2[a2] * m3[a3] * u[l] + m3[a3] * m2[a2] * x1 + m3[a3] * m1[a1] * x2 +
-                       m2[a2] * m1[a1] * x3;
-            if (P0 == 2) {
-                double col = 0.0;
-                if (a2 == 1 && a3 == 1) col = m3[1] * m2[1] * L1[a1 * 3 + 1];
-                else if (a1 == 1 && a3 == 1) col = m3[1] * m1[1] * L2[a2 * 3 + 1];
-                else if (a1 == 1 && a2 == 1) col = m2[1] * m1[1] * L3[a3 * 3 + 1];
-                y -= sh * col;
-            }
-            a.E[(size_t)e * 27 + l] = y;
-            part += y * u[l];
-        }
-    }
-    return part;
-}
-
-__device__ inline double block_sum_all(double v) {
-    __shared__ double red[16];
-    __shared__ double res;
-    double s = block_sum(v, red);
-    if (threadIdx.x == 0) res = s;
-    __syncthreads();
-    double out = res;
-    __syncthreads();
-    return out;
-}
-
-__global__ void __launch_bounds__(COARSE_THREADS) k_coarse_cg_single(CoarseArgs a, const double* __restrict__ b_in,
-                                                                     double* __restrict__ x_out, int maxit,
-                                                                     double rtol) {
-    __shared__ double tab[3 * COARSE_MAXN * 12];
-    const int nn = a.p0 + 1;
-    for (int d = 0; d < 3; ++d)
-        for (int i = threadIdx.x; i < a.n[d] * 12; i += blockDim.x) {
-            int e = i / 12, o = i % 12;
-            double v = 0.0;
-            if (o < nn) v = a.el_m[d][e * nn + o];
-            else if (o >= 3 && o - 3 < nn * nn) v = a.el_L[d][e * nn * nn + (o - 3)];
-            tab[(d * COARSE_MAXN + e) * 12 + o] = v;
-        }
-    double g_part = 0.0;
-    for (int i = threadIdx.x; i < a.N0; i += blockDim.x) {
-        double ri = b_in[a.c_slot[i]];
-        double zi = ri / a.diag[i];
-        a.x[i] = 0.0;
-        a.r[i] = ri;
-        a.z[i] = zi;
-        g_part += ri * zi;
-    }
-    __syncthreads();
-    double d_part = a.p0 == 2 ? coarse_elements_local<2>(a, tab) : coarse_elements_local<1>(a, tab);
-    double gamma = block_sum_all(g_part);
-    double delta = block_sum_all(d_part);
-    const double gamma0 = gamma;
-    int it = 0;
-    if (gamma > 0.0 && maxit > 0) {
-        double alpha = gamma / delta, beta = 0.0;
-        bool first = true;
-        while (true) {
-            g_part = 0.0;
-            for (int i = threadIdx.x; i < a.N0; i += blockDim.x) {
-                const int4 adj0 = *reinterpret_cast<const int4*>(a.r_adj + (size_t)i * 8);
-                const int4 adj1 = *reinterpret_cast<const int4*>(a.r_adj + (size_t)i * 8 + 4);
-                const int adj[8] = {adj0.x, adj0.y, adj0.z, adj0.w, adj1.x, adj1.y, adj1.z, adj1.w};
-                double w = 0.0;
-#pragma unroll
-                for (int kk = 0; kk < 8; ++kk) w += adj[kk] >= 0 ? a.E[adj[kk]] : 0.0;
-                const double zo = a.z[i];
-                double pi = first ? zo : zo + beta * a.p[i];
-                double qi = first ? w : w + beta * a.q[i];
-                a.p[i] = pi;
-                a.q[i] = qi;
-                double ri = a.r[i] - alpha * qi;
-                a.x[i] += alpha * pi;
-                a.r[i] = ri;
-                double zi = ri / a.diag[i];
-                a.z[i] = zi;
-                g_part += ri * zi;
-            }
-            first = false;
-            ++it;
-            if (it >= maxit) break;
-            __syncthreads();
-            d_part = a.p0 == 2 ? coarse_elements_local<2>(a, tab) : coarse_elements_local<1>(a, tab);
-            double gnew = block_sum_all(g_part);
-            delta = block_sum_all(d_part);
-            if (gnew <= rtol * rtol * gamma0) break;
-            beta = gnew / gamma;
-            alpha = gnew / (delta - beta * gnew / alpha);
-            gamma = gnew;
-        }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < a.N0; i += blockDim.x) x_out[a.c_slot[i]] = a.x[i];
-    if (threadIdx.x == 0) atomicAdd(a.iters, it);
 }
 
 // ---------------------------------------------------------------------------
@@ -2030,17 +1865,25 @@ void launch_mlp_adam(float* prm, const float* g, float* m, float* v, int n, floa
     hipLaunchKernelGGL(k_mlp_adam, dim3(nblk(n)), dim3(256), 0, st, prm, g, m, v, n, lr, b1, b2, eps, c1, c2);
 }
 
-hipError_t launch_coarse_cg(const CoarseArgs& a, int blocks, const double* b, double* x, int maxit,
-                            double rtol, hipStream_t st) {
-    if (blocks <= 1) {
-        hipLaunchKernelGGL(k_coarse_cg_single, dim3(1), dim3(COARSE_THREADS), 0, st, a, b, x, maxit, rtol);
-        return hipGetLastError();
-    }
-    CoarseArgs aa = a;
-    const double* bb = b;
-    double* xx = x;
-    void* args[] = {&aa, &bb, &xx, &maxit, &rtol};
-    return hipLaunchCooperativeKernel((const void*)k_coarse_cg, dim3(blocks), dim3(COARSE_THREADS), args, 0, st);
+hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, double* out, int64_t len, int maxit,
+                              double rtol, hipStream_t st) {
+    const int64_t n = std::max<int64_t>(len, a.N0);
+    const int blocks = (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 1024);
+    hipLaunchKernelGGL(k_coarse_init, dim3(blocks), dim3(256), 0, st, a, b, out, len, maxit, rtol);
+    return hipGetLastError();
+}
+
+int coarse_blocks(int ne, int p0) {
+    const int epb = p0 == 2 ? CoarseShape<2>::epb : CoarseShape<1>::epb;
+    return std::max(1, (ne + epb - 1) / epb);
+}
+
+hipError_t launch_coarse_iter(const CoarseArgs& a, int j, hipStream_t st) {
+    if (a.p0 == 2)
+        hipLaunchKernelGGL(k_coarse_iter<2>, dim3(a.blocks), dim3(256), 0, st, a, j);
+    else
+        hipLaunchKernelGGL(k_coarse_iter<1>, dim3(a.blocks), dim3(256), 0, st, a, j);
+    return hipGetLastError();
 }
 
 hipError_t init_kernel_attributes() {

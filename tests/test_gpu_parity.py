@@ -173,6 +173,29 @@ def test_coarse_solve(gpu, case):
     assert rel(io.to_grid(x), ref) <= 1e-11
 
 
+@pytest.mark.parametrize("rtol,maxit", [(1e-6, 500), (1e-12, 25), (1e-3, 500)])
+def test_coarse_solve_to_tolerance(gpu, rtol, maxit):
+    """Coarse CG stopped by its tolerance (or maxit) over several launch
+    chunks: same update count and solution as the oracle, on repeated calls
+    (the second call starts from the first one's chunk estimate)."""
+    g, o = make_pair((8, 6, 5), 4, 1.0, 1.3)
+    io = LevelIO(g, 0)
+    o0 = o.with_degree(io.p)
+    g.set_cycle(0, rtol, maxit)
+    diag = matfree.condensed_diagonal(o0)
+    for seed in (43, 44):
+        b = synth.random_grid(o0.shape, seed) * o0.free_skeleton_mask()
+        log = []
+        ref = solver.jacobi_pcg(lambda v: matfree.condensed_op(o0, v), b, diag, rtol, maxit, log)
+        x = torch.full((io.len,), float("nan"), dtype=torch.float64, device=gpu)
+        it = g.coarse_solve(io.to_dev(b), x)
+        assert it == log[0]
+        assert rel(io.to_grid(x), ref) <= 1e-10
+    x = torch.full((io.len,), float("nan"), dtype=torch.float64, device=gpu)
+    assert g.coarse_solve(torch.zeros(io.len, dtype=torch.float64, device=gpu), x) == 0
+    assert float(x.abs().max()) == 0.0
+
+
 @pytest.mark.parametrize("method", ["kMG", "kvMG"])
 def test_pcg_solve_matches_oracle(gpu, method):
     """Alg. 5 end to end: same iteration count, residual history and solution."""
