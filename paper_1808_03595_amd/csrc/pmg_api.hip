@@ -61,7 +61,7 @@ struct Level {
     // coarse CG structures when this level is the bottom of the cycle
     CoarseArgs ca{};
     bool has_ca = false;
-    hipGraphExec_t coarse_exec = nullptr;  // COARSE_RING iteration launches
+    hipGraphExec_t coarse_exec[COARSE_GRAPHS] = {};  // COARSE_RING * 2^k iteration launches
 };
 
 template <typename T> struct Sel;
@@ -216,39 +216,21 @@ bool decode_slot(const Layout& L, int64_t s, int& i1, int& i2, int& i3) {
 int build_coarse(pmg_mesh* m, Level& lev) {
     if (lev.has_ca) return 0;
     const Layout& L0 = lev.lay;
-    const int p0 = L0.p, nn = p0 + 1;
+    const int p0 = L0.p;
     if (p0 > 2) return fail(PMG_EUNSUP, "coarse level degree must be 1 or 2");
-    std::vector<int> slot2c(L0.len, -1), cslot;
-    for (int64_t s = 0; s < L0.len; ++s) {
-        int i1, i2, i3;
-        if (decode_slot(L0, s, i1, i2, i3)) {
-            slot2c[s] = (int)cslot.size();
-            cslot.push_back((int)s);
-        }
-    }
-    const int N0 = (int)cslot.size();
-    const int* nl = L0.n;
-    const int ne = nl[0] * nl[1] * nl[2];
-    std::vector<int> enodes((size_t)ne * 27, -1);
-    for (int e = 0; e < ne; ++e) {
-        int c[3] = {e % nl[0], (e / nl[0]) % nl[1], e / (nl[0] * nl[1])};
-        for (int a3 = 0; a3 < nn; ++a3)
-            for (int a2 = 0; a2 < nn; ++a2)
-                for (int a1 = 0; a1 < nn; ++a1) {
-                    int i1 = c[0] * p0 + a1, i2 = c[1] * p0 + a2, i3 = c[2] * p0 + a3;
-                    bool on1 = i1 % p0 == 0, on2 = i2 % p0 == 0, on3 = i3 % p0 == 0;
-                    if (!(on1 || on2 || on3)) continue;
-                    if (i1 == 0 || i2 == 0 || i3 == 0 || i1 == L0.N[0] - 1 || i2 == L0.N[1] - 1 ||
-                        i3 == L0.N[2] - 1)
-                        continue;
-                    enodes[(size_t)e * 27 + (a3 * nn + a2) * nn + a1] = slot2c[L0.slot(i1, i2, i3, on1, on2)];
-                }
-    }
+    // diagonal at the unknowns, zero at every other slot of the plane layout
     std::vector<double> dg;
     coarse_diagonal(L0, m->lam, lev.h, dg);
-    std::vector<double> dc(std::max(N0, 1), 1.0);
-    for (int i = 0; i < N0; ++i) dc[i] = dg[cslot[i]];
+    int N0 = 0;
+    for (int64_t s = 0; s < L0.len; ++s) {
+        int i1, i2, i3;
+        if (decode_slot(L0, s, i1, i2, i3)) ++N0;
+        else dg[s] = 0.0;
+    }
+    const int* nl = L0.n;
+    const int ne = nl[0] * nl[1] * nl[2];
     CoarseArgs& a = lev.ca;
+    a.lay = L0;
     a.N0 = N0;
     a.ne = ne;
     for (int d = 0; d < 3; ++d) {
@@ -259,20 +241,9 @@ int build_coarse(pmg_mesh* m, Level& lev) {
     a.p0 = p0;
     a.lam = m->lam;
     int rc;
-    auto up_int = [&](const int** dst, const std::vector<int>& v) -> int {
-        int* d = nullptr;
-        int r = m->alloc(&d, v.size());
-        if (r) return r;
-        if (hipMemcpy(d, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
-            return fail(PMG_EHIP, "hipMemcpy coarse tables");
-        *dst = d;
-        return 0;
-    };
-    if ((rc = up_int(&a.c_slot, cslot.empty() ? std::vector<int>(1, 0) : cslot))) return rc;
-    if ((rc = up_int(&a.e_nodes, enodes))) return rc;
-    if ((rc = m->upload(&a.diag, dc))) return rc;
-    size_t nv = std::max(N0, 1);
-    if ((rc = m->alloc(&a.x, nv)) || (rc = m->alloc(&a.p, nv))) return rc;
+    if ((rc = m->upload(&a.diag, dg))) return rc;
+    const size_t nv = (size_t)L0.len;
+    if ((rc = m->alloc(&a.p, nv))) return rc;
     for (int k = 0; k < 2; ++k)
         if ((rc = m->alloc(&a.R[k], nv)) || (rc = m->alloc(&a.Q[k], nv))) return rc;
     for (int k = 0; k < 3; ++k)
@@ -284,22 +255,22 @@ int build_coarse(pmg_mesh* m, Level& lev) {
     HIPCHK(hipMemset(a.S, 0, 2 * sizeof(CoarseState)));
     HIPCHK(hipMemset(a.stat, 0, 2 * sizeof(int)));
     a.iters = m->d_coarse_iters;
-    // one chunk of COARSE_RING iteration launches as a graph
-    if (N0 > 0) {
+    // graphs of COARSE_RING * 2^k iteration launches
+    for (int k = 0; N0 > 0 && k < COARSE_GRAPHS; ++k) {
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
-        for (int j = 0; j < COARSE_RING; ++j) {
-            hipError_t e = launch_coarse_iter(a, j, m->cap_stream);
+        for (int j = 0; j < (COARSE_RING << k); ++j) {
+            hipError_t e = launch_coarse_iter(a, j % COARSE_RING, m->cap_stream);
             if (e != hipSuccess) {
                 hipGraph_t junk = nullptr;
                 (void)hipStreamEndCapture(m->cap_stream, &junk);
-                if (junk) hipGraphDestroy(junk);
+                if (junk) (void)hipGraphDestroy(junk);
                 return fail(PMG_EHIP, std::string("coarse graph capture: ") + hipGetErrorString(e));
             }
         }
         HIPCHK(hipStreamEndCapture(m->cap_stream, &g));
-        hipError_t e = hipGraphInstantiate(&lev.coarse_exec, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        hipError_t e = hipGraphInstantiate(&lev.coarse_exec[k], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
         if (e != hipSuccess) return fail(PMG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
     lev.has_ca = true;
@@ -322,6 +293,12 @@ int build_level(pmg_mesh* m, Level& L, int p, int pc, const std::vector<double> 
     if ((rc = m->alloc(&L.u64, n)) || (rc = m->alloc(&L.F64, n)) || (rc = m->alloc(&L.y64, n)) ||
         (rc = m->alloc(&L.u32, n)) || (rc = m->alloc(&L.F32, n)) || (rc = m->alloc(&L.y32, n)))
         return rc;
+    // condensed-operator workspace, shared by the FP64 and FP32 tables
+    double* ew = nullptr;
+    const size_t ne = (size_t)L.lay.n[0] * L.lay.n[1] * L.lay.n[2];
+    if ((rc = m->alloc(&ew, ne * 6 * (size_t)(p + 1) * (p + 1)))) return rc;
+    L.t64.opE = ew;
+    L.t32.opE = reinterpret_cast<float*>(ew);
     return 0;
 }
 
@@ -506,29 +483,39 @@ void smooth_add(Level& L, const T* r, T* u, hipStream_t st) {
 // solve) is queued, and more chunks follow until the device reports
 // convergence or maxit; without one, enough chunks for maxit are queued
 // and nothing is synchronised.  b and x are level-0 skeleton arrays.
+// Queue `units` * COARSE_RING iteration launches as a few graph launches.
+int coarse_launch_units(Level& L0, long units, hipStream_t st) {
+    while (units > 0) {
+        int k = COARSE_GRAPHS - 1;
+        while (k > 0 && (1L << k) > units) --k;
+        HIPCHK(hipGraphLaunch(L0.coarse_exec[k], st));
+        units -= 1L << k;
+    }
+    return 0;
+}
+
 int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st) {
     Level& L0 = *m->act[0];
     CoarseArgs& a = L0.ca;
-    HIPCHK(launch_coarse_init(a, b, x, L0.lay.len, m->coarse_maxit, m->coarse_rtol, st));
+    HIPCHK(launch_coarse_init(a, b, x, m->coarse_maxit, m->coarse_rtol, st));
     if (a.N0 == 0) return 0;
     const long need = (long)m->coarse_maxit + 2;  // launches for maxit updates
-    const long cmax = (need + COARSE_RING - 1) / COARSE_RING;
-    if (!(m->coarse_rtol > 0.0)) {
-        for (long c = 0; c < cmax; ++c) HIPCHK(hipGraphLaunch(L0.coarse_exec, st));
-        return 0;
-    }
-    long chunks = std::min(cmax, std::max(1L, ((long)m->coarse_last + 3 + COARSE_RING - 1) / COARSE_RING));
+    const long umax = (need + COARSE_RING - 1) / COARSE_RING;
+    int rc;
+    if (!(m->coarse_rtol > 0.0)) return coarse_launch_units(L0, umax, st);
+    long units = std::min(umax, std::max(1L, ((long)m->coarse_last + 3 + COARSE_RING - 1) / COARSE_RING));
     long launched = 0;
     while (true) {
-        for (; launched < chunks; ++launched) HIPCHK(hipGraphLaunch(L0.coarse_exec, st));
+        if ((rc = coarse_launch_units(L0, units - launched, st))) return rc;
+        launched = units;
         HIPCHK(hipMemcpyAsync(m->h_cstat, a.stat, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (m->h_cstat[0]) {
             m->coarse_last = m->h_cstat[1];
             return 0;
         }
-        if (launched >= cmax) return fail(PMG_EHIP, "coarse solver did not finish within maxit");
-        chunks = std::min(cmax, launched + std::max(1L, launched / 2));
+        if (launched >= umax) return fail(PMG_EHIP, "coarse solver did not finish within maxit");
+        units = std::min(umax, launched + std::max(1L, launched / 2));
     }
 }
 
@@ -689,10 +676,10 @@ int pmg_create_mesh_widths(int n1, int n2, int n3, int p, double lambda, const d
 void pmg_destroy_mesh(pmg_mesh* m) {
     if (!m) return;
     hipDeviceSynchronize();
-    for (Level& l : m->lv)
-        if (l.coarse_exec) (void)hipGraphExecDestroy(l.coarse_exec);
-    for (Level& l : m->hlv)
-        if (l.coarse_exec) (void)hipGraphExecDestroy(l.coarse_exec);
+    for (auto* v : {&m->lv, &m->hlv})
+        for (Level& l : *v)
+            for (hipGraphExec_t g : l.coarse_exec)
+                if (g) (void)hipGraphExecDestroy(g);
     for (void* q : m->allocs) hipFree(q);
     if (m->hscal) hipHostFree(m->hscal);
     if (m->h_cstat) (void)hipHostFree(m->h_cstat);

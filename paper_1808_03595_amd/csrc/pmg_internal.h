@@ -69,6 +69,9 @@ struct LevelTabs {
     // interpolation from the next coarser level: (p+1) x (pc+1), row-major
     const T* J;
     int pc;
+    // workspace of the condensed operator: per element, the six face tiles
+    // of its contribution, [e][6][(p+1)^2] (only canonical entries used)
+    T* opE;
 };
 
 struct HostTables {
@@ -98,14 +101,15 @@ void coarse_diagonal(const Layout& lay, double lam, const std::vector<double> h[
 
 namespace pmg {
 
-// Coarse-level (p_0 <= 2) problem in compact numbering for the Jacobi-CG
-// iteration kernels.  Unknown i lives at plane-layout slot c_slot[i].
+// Coarse-level (p_0 <= 2) problem for the Jacobi-CG iteration kernels; the
+// vectors live in the level's plane layout, so an element finds its nodes'
+// slots by arithmetic.
 //
 // Scalars of the coarse CG carried from one iteration launch to the next
 // (written by block 0 of each launch into the other ring slot).
 struct CoarseState {
     double gamma, alpha, gamma0, rtol2;
-    double* out;     // skeleton array receiving the solution
+    double* out;     // skeleton array holding the iterate x
     int it;          // completed updates; -1 before the first launch
     int done;
     int maxit;
@@ -113,21 +117,20 @@ struct CoarseState {
 };
 
 struct CoarseArgs {
-    int N0;          // unknowns
-    int ne;          // elements
+    Layout lay;           // level-0 plane layout: all vectors below have lay.len entries
+    int N0;               // unknowns
+    int ne;               // elements
     int n[3];
-    int p0;          // 1 or 2
+    int p0;               // 1 or 2
     double lam;
-    const int* c_slot;    // [N0] skeleton slot of each unknown
-    const int* e_nodes;   // [ne][27] compact index of local node or -1
-    const double* diag;   // [N0]
+    const double* diag;   // diagonal of the operator at unknowns, 0 at every other slot
     const double* el_m[3];  // level-0 element tables
     const double* el_L[3];
-    double *x, *p;        // [N0], updated in place by the owning element
-    double *R[2], *Q[2];  // [N0] ping-pong residual and q = A p
-    double *W[3];         // [N0] rotating accumulators of w = A z
+    double* p;            // search direction, updated in place by the owning element
+    double *R[2], *Q[2];  // ping-pong residual and q = A p
+    double *W[3];         // rotating accumulators of w = A z
     double *P[2];         // [2 * blocks] per-block partial sums (r.z, w.z)
-    CoarseState* S;       // [2]
+    CoarseState* S;       // [2]; S.out is the iterate x (the caller's output array)
     int* stat;            // [2]: done flag and update count of the last solve
     int* iters;           // accumulated iteration count
     int blocks;           // workgroups of one iteration launch

@@ -9,12 +9,12 @@ constexpr int REDUCE_BLOCKS = 512;
 
 hipError_t init_kernel_attributes();
 void set_mfma_min_degree(int p);
-void set_op_atomic(bool on);
 // Coarse CG (launch-per-iteration form): the init kernel, then iteration
 // launches with ring index j = 0, 1, ..., COARSE_RING - 1, 0, ...
-constexpr int COARSE_RING = 12;
-hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, double* out, int64_t len, int maxit,
-                              double rtol, hipStream_t st);
+constexpr int COARSE_RING = 6;
+constexpr int COARSE_GRAPHS = 5;   // graphs of COARSE_RING * 2^k launches
+hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, double* out, int maxit, double rtol,
+                              hipStream_t st);
 hipError_t launch_coarse_iter(const CoarseArgs& a, int j, hipStream_t st);
 int coarse_blocks(int ne, int p0);
 

@@ -36,6 +36,13 @@ __device__ inline void color_coords(int b, int color, const int n[3], int c[3]) 
     c[2] = p2 + 2 * (b / m1);
 }
 
+// Pick one of three pointers by a runtime index with selects (indexing a
+// pointer array of a kernel argument would load the pointer from memory).
+template <typename T>
+__device__ __forceinline__ T* pick3(int d, T* a0, T* a1, T* a2) {
+    return d == 0 ? a0 : (d == 1 ? a1 : a2);
+}
+
 template <typename T>
 __device__ inline void add_out(T* y, int64_t s, T v) {
     y[s] += v;
@@ -297,19 +304,17 @@ __device__ ElemPtrs<T> stage_elem_tables(const LevelTabs<T>& tb, const int e[3],
     return P;
 }
 
-// One element per workgroup, all elements in one launch; the contributions
-// of neighbouring elements meet in the shared face, edge and vertex slots
-// and are summed there with hardware atomics (ATOMIC) or, with ATOMIC
-// false, by eight parity-colour launches whose writes never overlap.
-template <typename T, bool ATOMIC>
-__global__ void __launch_bounds__(256) k_condensed_op(LevelTabs<T> tb, const T* __restrict__ u,
-                                                      T* __restrict__ y, int color) {
+// One element per workgroup (any degree); the element's result goes to the
+// workspace opE like that of k_condensed_op_w.
+template <typename T>
+__global__ void __launch_bounds__(256) k_condensed_op(LevelTabs<T> tb, const T* __restrict__ u) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
     const Layout& L = tb.lay;
     const int p = L.p, n1 = p + 1, t2 = n1 * n1, q = p - 1, q2 = q * q;
     int e[3];
-    color_coords(blockIdx.x, color, L.n, e);
+    color_coords(blockIdx.x, -1, L.n, e);
+    T* out = tb.opE + (size_t)blockIdx.x * 6 * t2;
     T* tile = sm;              // 6 t2
     T* G = tile + 6 * t2;      // 6 q2
     T* Tc = G + 6 * q2;        // 6 q2
@@ -328,12 +333,345 @@ __global__ void __launch_bounds__(256) k_condensed_op(LevelTabs<T> tb, const T* 
         if (!tile_canonical(p, f, r, c)) continue;
         int a1, a2, a3;
         tile_node(p, f, r, c, a1, a2, a3);
-        int i1 = e[0] * p + a1, i2 = e[1] * p + a2, i3 = e[2] * p + a3;
-        if (is_dir(L, i1, i2, i3)) continue;
         T v = hbb_at(P, p, tb.lam, tile, a1, a2, a3);
         if (r > 0 && r < p && c > 0 && c < p) v -= G[f * q2 + (r - 1) * q + (c - 1)];
-        if (ATOMIC) unsafeAtomicAdd(y + elem_slot(L, e, a1, a2, a3), v);
-        else add_out(y, elem_slot(L, e, a1, a2, a3), v);
+        out[i] = v;
+    }
+}
+
+// Assembly of the element contributions: every slot of the plane layout is
+// written once; a canonical, non-Dirichlet node receives the sum, in a fixed
+// order, of the canonical tile entries of the (up to eight) elements that
+// contain it, every other slot zero.  Deterministic, no atomics.
+// Grid: x over columns (64 per block), y over rows (4 per block, the plane's
+// padding rows included), z over the planes of all three families.
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restrict__ E, T* __restrict__ y) {
+    const int z = blockIdx.z;
+    const int d = z >= L.n[0] + L.n[1] + 2 ? 2 : (z >= L.n[0] + 1 ? 1 : 0);
+    const int j = z - (d == 0 ? 0 : (d == 1 ? L.n[0] + 1 : L.n[0] + L.n[1] + 2));
+    const int r = blockIdx.y * 4 + threadIdx.y, c = blockIdx.x * 64 + threadIdx.x;
+    const int pitch = L.pitch[d];
+    if (c >= pitch) return;
+    const int64_t within = (int64_t)r * pitch + c;
+    if (within >= L.pstride[d]) return;
+    const int64_t s = L.off[d] + (int64_t)j * L.pstride[d] + within;
+    const int p = P > 0 ? P : L.p, n1 = p + 1, t2 = n1 * n1;
+    int g[3];
+    bool canon = r < L.rows[d];
+    if (d == 0) { g[0] = j * p; g[2] = r; g[1] = c; canon = canon && c < L.N[1]; }
+    else if (d == 1) { g[1] = j * p; g[2] = r; g[0] = c; canon = canon && c < L.N[0] && c % p != 0; }
+    else { g[2] = j * p; g[1] = r; g[0] = c; canon = canon && c < L.N[0] && c % p != 0 && r % p != 0; }
+    if (!canon || is_dir(L, g[0], g[1], g[2])) {
+        y[s] = (T)0;
+        return;
+    }
+    // candidate (element index, local index) per direction
+    int ce[3][2], ca[3][2], nc[3];
+    for (int k = 0; k < 3; ++k) {
+        const int q = g[k] / p, a = g[k] - q * p;
+        if (a == 0) {   // element boundary: the elements on both sides
+            nc[k] = 0;
+            if (q > 0) { ce[k][nc[k]] = q - 1; ca[k][nc[k]] = p; ++nc[k]; }
+            if (q < L.n[k]) { ce[k][nc[k]] = q; ca[k][nc[k]] = 0; ++nc[k]; }
+        } else {
+            nc[k] = 1;
+            ce[k][0] = q;
+            ca[k][0] = a;
+        }
+    }
+    T acc = 0;
+    for (int z = 0; z < nc[2]; ++z)
+        for (int yy = 0; yy < nc[1]; ++yy)
+            for (int x = 0; x < nc[0]; ++x) {
+                const int a1 = ca[0][x], a2 = ca[1][yy], a3 = ca[2][z];
+                const int64_t e = ((int64_t)ce[2][z] * L.n[1] + ce[1][yy]) * L.n[0] + ce[0][x];
+                int f, tr, tc;
+                if (a1 == 0 || a1 == p) { f = a1 ? 1 : 0; tr = a3; tc = a2; }
+                else if (a2 == 0 || a2 == p) { f = a2 ? 3 : 2; tr = a3; tc = a1; }
+                else { f = a3 ? 5 : 4; tr = a2; tc = a1; }
+                acc += E[e * 6 * t2 + f * t2 + tr * n1 + tc];
+            }
+    y[s] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Condensed operator, one wavefront per element, compile-time degree P <= 8.
+// Same arithmetic as k_condensed_op, organised so that every stage keeps a
+// row or a line of its operand in registers: the two 2D transforms of each
+// face interior, the eigenspace expansion V = D^-1 sum_f c_f (x) G_f (one
+// lane per (k2, k3) line, which also yields the x1-contractions), the
+// x2/x3-contractions, the back-transforms and the shell part H_BB u_B.
+// A single-wave workgroup makes every barrier a no-op apart from the wait
+// for its own LDS accesses.  The element's result (canonical entries of its
+// six face tiles) goes to the workspace opE; k_gather_elem sums the
+// contributions of all elements at each skeleton node.
+// ---------------------------------------------------------------------------
+template <int P>
+struct K1Shape {
+    static constexpr int n1 = P + 1, q = P - 1, t2 = n1 * n1, q2 = q * q;
+    static constexpr int tab_d = n1 + n1 * n1 + 2 * q2 + 3 * q;       // one direction
+    static constexpr int tabs = 3 * tab_d;
+    // LDS layout (in elements of T)
+    static constexpr int o_tab = 0, o_tile = tabs, o_G = o_tile + 6 * t2, o_tmp = o_G + 6 * q2,
+                         o_V = o_tmp + 6 * q2, o_Tc = o_V + q * q2, total = o_Tc + 6 * q2;
+};
+
+template <typename T, int P>
+__global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T* __restrict__ u) {
+    using K = K1Shape<P>;
+    constexpr int n1 = K::n1, q = K::q, t2 = K::t2, q2 = K::q2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    T* tabs = sm + K::o_tab;
+    T* tile = sm + K::o_tile;
+    T* G = sm + K::o_G;
+    T* tmp = sm + K::o_tmp;
+    T* V = sm + K::o_V;
+    T* Tc = sm + K::o_Tc;
+    const Layout& L = tb.lay;
+    const int lane = threadIdx.x;
+    int e[3];
+    color_coords(blockIdx.x, -1, L.n, e);
+    const T lam = tb.lam;
+    T* out = tb.opE + (size_t)blockIdx.x * 6 * t2;
+    // 1D tables of this element (per direction m[n1] L[n1^2] Si[q^2] MS[q^2]
+    // lm[q] c0[q] cp[q]) and the six face tiles: all global loads are issued
+    // before the first LDS store, so their latencies overlap
+    constexpr int NT = (K::tabs + 63) / 64, NU = (6 * t2 + 63) / 64;
+    T tv[NT], uv[NU];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        const int i = lane + 64 * k;
+        T v = 0;
+        if (i < K::tabs) {
+            const int d = i / K::tab_d;
+            int o = i - d * K::tab_d;
+            const int ed = d == 0 ? e[0] : (d == 1 ? e[1] : e[2]);
+            const T* src;
+            if (o < n1) src = pick3(d, tb.el_m[0], tb.el_m[1], tb.el_m[2]) + ed * n1;
+            else if ((o -= n1) < n1 * n1) src = pick3(d, tb.el_L[0], tb.el_L[1], tb.el_L[2]) + ed * n1 * n1;
+            else if ((o -= n1 * n1) < q2) src = pick3(d, tb.el_Sinv[0], tb.el_Sinv[1], tb.el_Sinv[2]) + ed * q2;
+            else if ((o -= q2) < q2) src = pick3(d, tb.el_MS[0], tb.el_MS[1], tb.el_MS[2]) + ed * q2;
+            else if ((o -= q2) < q) src = pick3(d, tb.el_lam[0], tb.el_lam[1], tb.el_lam[2]) + ed * q;
+            else if ((o -= q) < q) src = pick3(d, tb.el_c0[0], tb.el_c0[1], tb.el_c0[2]) + ed * q;
+            else { o -= q; src = pick3(d, tb.el_cp[0], tb.el_cp[1], tb.el_cp[2]) + ed * q; }
+            v = src[o];
+        }
+        tv[k] = v;
+    }
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+        const int i = lane + 64 * k;
+        T v = 0;
+        if (i < 6 * t2) {
+            const int f = i / t2, rc = i - f * t2, r = rc / n1, c = rc - r * n1;
+            int a1, a2, a3;
+            tile_node(P, f, r, c, a1, a2, a3);
+            v = u[elem_slot(L, e, a1, a2, a3)];
+        }
+        uv[k] = v;
+    }
+#pragma unroll
+    for (int k = 0; k < NT; ++k)
+        if (lane + 64 * k < K::tabs) tabs[lane + 64 * k] = tv[k];
+#pragma unroll
+    for (int k = 0; k < NU; ++k)
+        if (lane + 64 * k < 6 * t2) tile[lane + 64 * k] = uv[k];
+    __syncthreads();
+    ElemPtrs<T> Pt;
+    for (int d = 0; d < 3; ++d) {
+        const T* b = tabs + d * K::tab_d;
+        Pt.m[d] = b;
+        Pt.L[d] = b + n1;
+        Pt.Si[d] = b + n1 + n1 * n1;
+        Pt.MS[d] = Pt.Si[d] + q2;
+        Pt.lm[d] = Pt.MS[d] + q2;
+        Pt.c0[d] = Pt.lm[d] + q;
+        Pt.cp[d] = Pt.c0[d] + q;
+    }
+    if (q > 0) {
+        // tmp_f = X_f Si_C^T (lane: face f, row r)
+        if (lane < 6 * q) {
+            const int f = lane / q, r = lane - f * q;
+            const T* Sc = Pt.Si[tile_cdir(f >> 1)];
+            T x[q > 0 ? q : 1];
+#pragma unroll
+            for (int c = 0; c < q; ++c) x[c] = tile[f * t2 + (r + 1) * n1 + c + 1];
+#pragma unroll
+            for (int kc = 0; kc < q; ++kc) {
+                T s = 0;
+#pragma unroll
+                for (int c = 0; c < q; ++c) s += x[c] * Sc[kc * q + c];
+                tmp[f * q2 + r * q + kc] = s;
+            }
+        }
+        __syncthreads();
+        // G_f = Si_R tmp_f (lane: face f, column kc)
+        if (lane < 6 * q) {
+            const int f = lane / q, kc = lane - f * q;
+            const T* Sr = Pt.Si[tile_rdir(f >> 1)];
+            T x[q > 0 ? q : 1];
+#pragma unroll
+            for (int r = 0; r < q; ++r) x[r] = tmp[f * q2 + r * q + kc];
+#pragma unroll
+            for (int kr = 0; kr < q; ++kr) {
+                T s = 0;
+#pragma unroll
+                for (int r = 0; r < q; ++r) s += Sr[kr * q + r] * x[r];
+                G[f * q2 + kr * q + kc] = s;
+            }
+        }
+        __syncthreads();
+        // V over the (k2, k3) line of lane; x1-contractions on the fly
+        if (lane < q2) {
+            const int k3 = lane / q, k2 = lane - k3 * q;
+            const T g0 = G[0 * q2 + k3 * q + k2], g1 = G[1 * q2 + k3 * q + k2];
+            const T a1 = Pt.c0[1][k2], b1 = Pt.cp[1][k2], a2 = Pt.c0[2][k3], b2 = Pt.cp[2][k3];
+            const T dd = lam + Pt.lm[1][k2] + Pt.lm[2][k3];
+            T s0 = 0, sp = 0;
+#pragma unroll
+            for (int k1 = 0; k1 < q; ++k1) {
+                T v = Pt.c0[0][k1] * g0 + Pt.cp[0][k1] * g1 + a1 * G[2 * q2 + k3 * q + k1] +
+                      b1 * G[3 * q2 + k3 * q + k1] + a2 * G[4 * q2 + k2 * q + k1] + b2 * G[5 * q2 + k2 * q + k1];
+                v = v / (dd + Pt.lm[0][k1]);
+                V[(k3 * q + k2) * q + k1] = v;
+                s0 += Pt.c0[0][k1] * v;
+                sp += Pt.cp[0][k1] * v;
+            }
+            Tc[0 * q2 + k3 * q + k2] = s0;
+            Tc[1 * q2 + k3 * q + k2] = sp;
+        }
+        __syncthreads();
+        // x2- and x3-contractions (lane: (d, r, c) with d in {1, 2})
+        for (int i = lane; i < 2 * q2; i += 64) {
+            const int dm = i / q2, rc = i - dm * q2, r = rc / q, c = rc - r * q;
+            T s0 = 0, sp = 0;
+            if (dm == 0) {          // d = 1: (r, c) = (k3, k1), sum over k2
+#pragma unroll
+                for (int k = 0; k < q; ++k) {
+                    const T v = V[(r * q + k) * q + c];
+                    s0 += Pt.c0[1][k] * v;
+                    sp += Pt.cp[1][k] * v;
+                }
+            } else {                // d = 2: (r, c) = (k2, k1), sum over k3
+#pragma unroll
+                for (int k = 0; k < q; ++k) {
+                    const T v = V[(k * q + r) * q + c];
+                    s0 += Pt.c0[2][k] * v;
+                    sp += Pt.cp[2][k] * v;
+                }
+            }
+            Tc[(2 + 2 * dm) * q2 + rc] = s0;
+            Tc[(3 + 2 * dm) * q2 + rc] = sp;
+        }
+        __syncthreads();
+        // tmp_f = Tc_f MS_C^T (lane: face f, row kr)
+        if (lane < 6 * q) {
+            const int f = lane / q, kr = lane - f * q;
+            const T* Mc = Pt.MS[tile_cdir(f >> 1)];
+            T x[q > 0 ? q : 1];
+#pragma unroll
+            for (int kc = 0; kc < q; ++kc) x[kc] = Tc[f * q2 + kr * q + kc];
+#pragma unroll
+            for (int c = 0; c < q; ++c) {
+                T s = 0;
+#pragma unroll
+                for (int kc = 0; kc < q; ++kc) s += x[kc] * Mc[c * q + kc];
+                tmp[f * q2 + kr * q + c] = s;
+            }
+        }
+        __syncthreads();
+        // corr_f = MS_R tmp_f, stored in G (lane: face f, column c)
+        if (lane < 6 * q) {
+            const int f = lane / q, c = lane - f * q;
+            const T* Mr = Pt.MS[tile_rdir(f >> 1)];
+            T x[q > 0 ? q : 1];
+#pragma unroll
+            for (int kr = 0; kr < q; ++kr) x[kr] = tmp[f * q2 + kr * q + c];
+#pragma unroll
+            for (int r = 0; r < q; ++r) {
+                T s = 0;
+#pragma unroll
+                for (int kr = 0; kr < q; ++kr) s += Mr[r * q + kr] * x[kr];
+                G[f * q2 + r * q + c] = s;
+            }
+        }
+        __syncthreads();
+    }
+    // face-interior nodes (lane: face f, row r): in-face lines stay in the
+    // tile, the normal line meets the shell only at the two opposite faces
+    if (lane < 6 * q) {
+        const int f = lane / q, r = lane - f * q + 1, d = f >> 1, s = f & 1;
+        {
+            const int dr = tile_rdir(d), dc = tile_cdir(d);
+            const T* Lr = Pt.L[dr] + r * n1;
+            const T* Lc = Pt.L[dc];
+            const T* Ln = Pt.L[d] + (s ? P : 0) * n1;
+            const T md = Pt.m[d][s ? P : 0], mr = Pt.m[dr][r];
+            const T* trow = tile + f * t2 + r * n1;
+            const T* t0 = tile + (2 * d) * t2 + r * n1;
+            const T* t1 = tile + (2 * d + 1) * t2 + r * n1;
+            T row[n1];
+#pragma unroll
+            for (int j = 0; j < n1; ++j) row[j] = trow[j];
+            for (int c = 1; c <= q; ++c) {
+                T xr = 0, xc = 0;
+#pragma unroll
+                for (int j = 0; j < n1; ++j) {
+                    xr += Lr[j] * tile[f * t2 + j * n1 + c];
+                    xc += Lc[c * n1 + j] * row[j];
+                }
+                const T mc = Pt.m[dc][c];
+                T v = lam * md * mr * mc * row[c] + md * mc * xr + md * mr * xc +
+                      mr * mc * (Ln[0] * t0[c] + Ln[P] * t1[c]);
+                v -= G[f * q2 + (r - 1) * q + (c - 1)];
+                out[f * t2 + r * n1 + c] = v;
+            }
+        }
+    }
+    // canonical edge and vertex nodes: rims of the x1-faces (4P each) and
+    // the two non-canonical-free rows of the x2-faces (P - 1 each)
+    constexpr int nrim0 = 4 * P, nrim1 = 2 * (P - 1), nrim = 2 * nrim0 + 2 * nrim1;
+    for (int i = lane; i < nrim; i += 64) {
+        int f, r, c;
+        if (i < 2 * nrim0) {
+            f = i / nrim0;
+            const int k = i - f * nrim0, side = k / P, t = k - side * P;
+            // walk the rim: r = 0 row, c = P column, r = P row, c = 0 column
+            if (side == 0) { r = 0; c = t; }
+            else if (side == 1) { r = t; c = P; }
+            else if (side == 2) { r = P; c = P - t; }
+            else { r = P - t; c = 0; }
+        } else {
+            const int k = i - 2 * nrim0, ff = k / nrim1, t = k - ff * nrim1;
+            f = 2 + ff;
+            r = t < P - 1 ? 0 : P;
+            c = 1 + (t < P - 1 ? t : t - (P - 1));
+        }
+        int a[3];
+        tile_node(P, f, r, c, a[0], a[1], a[2]);
+        // every line through an edge or vertex node lies in a face tile:
+        // take the face normal to the first other direction whose local
+        // coordinate is 0 or P, and walk its row or column
+        T acc = 0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+            const int dn = (a[o1] == 0 || a[o1] == P) ? o1 : o2;
+            const int ft = 2 * dn + (a[dn] == P ? 1 : 0);
+            const int rd = tile_rdir(dn), cd = tile_cdir(dn);
+            int base, stride;
+            if (d == rd) { base = ft * t2 + a[cd]; stride = n1; }
+            else { base = ft * t2 + a[rd] * n1; stride = 1; }
+            (void)cd;
+            const T* Ld = Pt.L[d] + a[d] * n1;
+            T x = 0;
+#pragma unroll
+            for (int j = 0; j < n1; ++j) x += Ld[j] * tile[base + j * stride];
+            acc += Pt.m[o1][a[o1]] * Pt.m[o2][a[o2]] * x;
+        }
+        out[f * t2 + r * n1 + c] = lam * Pt.m[0][a[0]] * Pt.m[1][a[1]] * Pt.m[2][a[2]] * tile[f * t2 + r * n1 + c] + acc;
     }
 }
 
@@ -1321,7 +1659,8 @@ __global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ z, con
 // recomputes the updated residual and preconditioned residual at its nodes
 // from the previous iteration's vectors.  Every unknown is owned by exactly
 // one element (the one whose lower corner is nearest), and only the owner
-// writes the updated p, x, r and q.
+// writes the updated p, x, r and q.  The vectors use the level's plane
+// layout, so every address is computed, none is looked up.
 //
 // Launch k uses ring index j = k mod COARSE_RING (a multiple of 2 and 3):
 //   reads  r = R[j%2], q = Q[j%2], w = W[j%3], partials P[j%2], state S[j%2]
@@ -1329,21 +1668,20 @@ __global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ z, con
 //          P[(j+1)%2], S[(j+1)%2]; p and x in place (owners)
 // A chunk of COARSE_RING launches is captured once as a HIP graph.
 // ---------------------------------------------------------------------------
-// r = b (compact), all other vectors zero, the output array zero; state
-// "before the first launch".
-__global__ void k_coarse_init(CoarseArgs a, const double* __restrict__ b, double* __restrict__ out,
-                              int64_t len, int maxit, double rtol) {
+// r = b at the unknowns, all other vectors and the iterate x = out zero;
+// state "before the first launch".
+__global__ void k_coarse_init(CoarseArgs a, const double* __restrict__ b, double* __restrict__ out, int maxit,
+                              double rtol) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t s = t; s < len; s += stride) out[s] = 0.0;
-    for (int64_t i = t; i < a.N0; i += stride) {
-        a.R[0][i] = b[a.c_slot[i]];
-        a.Q[0][i] = 0.0;
-        a.W[0][i] = 0.0;
-        a.W[1][i] = 0.0;
-        a.W[2][i] = 0.0;
-        a.x[i] = 0.0;
-        a.p[i] = 0.0;
+    for (int64_t s = t; s < a.lay.len; s += stride) {
+        a.R[0][s] = a.diag[s] != 0.0 ? b[s] : 0.0;
+        a.Q[0][s] = 0.0;
+        a.W[0][s] = 0.0;
+        a.W[1][s] = 0.0;
+        a.W[2][s] = 0.0;
+        a.p[s] = 0.0;
+        out[s] = 0.0;
     }
     if (t == 0) {
         CoarseState s0;
@@ -1407,7 +1745,49 @@ __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j) {
     __shared__ double red[8];
     __shared__ double sums[2];
     const int jr = j & 1, jn = jr ^ 1;
+    // loads that do not depend on this iteration's scalars go first, so
+    // their latency overlaps the reduction of the partial sums
+    const int el = threadIdx.x / nl, l = threadIdx.x - el * nl;
+    const int e = blockIdx.x * EPB + el;
+    const bool act = el < EPB && e < a.ne;
+    const int a1 = l % nn, a2 = (l / nn) % nn, a3 = l / (nn * nn);
+    const int c1 = e % a.n[0], c2 = (e / a.n[0]) % a.n[1], c3 = e / (a.n[0] * a.n[1]);
+    const int g1 = c1 * P0 + a1, g2 = c2 * P0 + a2, g3 = c3 * P0 + a3;
+    // unknown: a skeleton node (the p_0 = 2 element centre is not) off the boundary
+    const bool unk = act && (P0 == 1 || l != 13) && !(g1 == 0 || g2 == 0 || g3 == 0 || g1 == a.lay.N[0] - 1 ||
+                                                       g2 == a.lay.N[1] - 1 || g3 == a.lay.N[2] - 1);
+    const int ec[3] = {c1, c2, c3};
+    const int64_t gi = unk ? elem_slot(a.lay, ec, a1, a2, a3) : 0;
     const CoarseState si = a.S[jr];
+    double dg = 1.0, ro = 0.0, qo = 0.0, wo = 0.0, po = 0.0, xo = 0.0;
+    if (unk) {
+        dg = a.diag[gi];
+        ro = a.R[jr][gi];
+        qo = a.Q[jr][gi];
+        wo = a.W[j % 3][gi];
+        po = a.p[gi];
+        xo = si.out[gi];
+    }
+    constexpr int NTAB = (EPB * 36 + 255) / 256;
+    double tv[NTAB];
+#pragma unroll
+    for (int k = 0; k < NTAB; ++k) {
+        const int t = threadIdx.x + 256 * k, tel = t / 36, to = t - tel * 36, te = blockIdx.x * EPB + tel;
+        double v = 0.0;
+        if (tel < EPB && te < a.ne) {
+            const int c0 = te % a.n[0], c1 = (te / a.n[0]) % a.n[1], c2 = te / (a.n[0] * a.n[1]);
+            if (to < 9) {
+                const int d = to / 3, kk = to % 3;
+                const int cd = d == 0 ? c0 : (d == 1 ? c1 : c2);
+                if (kk < nn) v = pick3(d, a.el_m[0], a.el_m[1], a.el_m[2])[cd * nn + kk];
+            } else {
+                const int d = (to - 9) / 9, kk = (to - 9) % 9;
+                const int cd = d == 0 ? c0 : (d == 1 ? c1 : c2);
+                if (kk < nn * nn) v = pick3(d, a.el_L[0], a.el_L[1], a.el_L[2])[cd * nn * nn + kk];
+            }
+        }
+        tv[k] = v;
+    }
     if (si.done) {
         if (blockIdx.x == 0 && threadIdx.x == 0) a.S[jn] = si;
         return;
@@ -1447,9 +1827,6 @@ __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j) {
         so.it = si.it + 1;
     }
     if (finish) {
-        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.N0; i += stride)
-            si.out[a.c_slot[i]] = a.x[i];
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             so = si;
             so.done = 1;
@@ -1460,52 +1837,31 @@ __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j) {
         }
         return;
     }
-    // 1D tables of this block's elements
-    for (int t = threadIdx.x; t < EPB * 36; t += blockDim.x) {
-        const int el = t / 36, o = t - el * 36, e = blockIdx.x * EPB + el;
-        double v = 0.0;
-        if (e < a.ne) {
-            const int c[3] = {e % a.n[0], (e / a.n[0]) % a.n[1], e / (a.n[0] * a.n[1])};
-            if (o < 9) {
-                const int d = o / 3, k = o % 3;
-                if (k < nn) v = a.el_m[d][c[d] * nn + k];
-            } else {
-                const int d = (o - 9) / 9, k = (o - 9) % 9;
-                if (k < nn * nn) v = a.el_L[d][c[d] * nn * nn + k];
-            }
-        }
-        tab[el][o] = v;
+#pragma unroll
+    for (int k = 0; k < NTAB; ++k) {
+        const int t = threadIdx.x + 256 * k;
+        if (t < EPB * 36) tab[t / 36][t % 36] = tv[k];
     }
-    const int el = threadIdx.x / nl, l = threadIdx.x - el * nl;
-    const int e = blockIdx.x * EPB + el;
-    const bool act = el < EPB && e < a.ne;
-    const int a1 = l % nn, a2 = (l / nn) % nn, a3 = l / (nn * nn);
-    int gi = -1;
     double zn = 0.0, gpart = 0.0, dpart = 0.0;
-    if (act) {
-        gi = a.e_nodes[e * 27 + l];
-        if (gi >= 0) {
-            const double dg = a.diag[gi], ro = a.R[jr][gi];
-            const double qn = a.W[j % 3][gi] + beta * a.Q[jr][gi];
-            const double rn = ro - alpha * qn;
-            zn = rn / dg;
-            const int c1 = e % a.n[0], c2 = (e / a.n[0]) % a.n[1], c3 = e / (a.n[0] * a.n[1]);
-            const bool own = (a1 < P0 || c1 == a.n[0] - 1) && (a2 < P0 || c2 == a.n[1] - 1) &&
-                             (a3 < P0 || c3 == a.n[2] - 1);
-            if (own) {
-                const double pn = ro / dg + beta * a.p[gi];
-                a.p[gi] = pn;
-                a.x[gi] += alpha * pn;
-                a.R[jn][gi] = rn;
-                a.Q[jn][gi] = qn;
-                a.W[(j + 2) % 3][gi] = 0.0;
-                gpart = rn * zn;
-            }
+    if (unk) {
+        const double qn = wo + beta * qo;
+        const double rn = ro - alpha * qn;
+        zn = rn / dg;
+        const bool own = (a1 < P0 || c1 == a.n[0] - 1) && (a2 < P0 || c2 == a.n[1] - 1) &&
+                         (a3 < P0 || c3 == a.n[2] - 1);
+        if (own) {
+            const double pn = ro / dg + beta * po;
+            a.p[gi] = pn;
+            si.out[gi] = xo + alpha * pn;
+            a.R[jn][gi] = rn;
+            a.Q[jn][gi] = qn;
+            a.W[(j + 2) % 3][gi] = 0.0;
+            gpart = rn * zn;
         }
-        zl[el][l] = zn;
     }
+    if (act) zl[el][l] = zn;
     __syncthreads();
-    if (gi >= 0) {
+    if (unk) {
         const double y = coarse_row<P0>(tab[el], zl[el], a.lam, a1, a2, a3);
         unsafeAtomicAdd(a.W[(j + 1) % 3] + gi, y);
         dpart = y * zn;
@@ -1702,23 +2058,41 @@ void launch_skel_to_grid(const Layout& L, const T* s, double* g, hipStream_t st)
 }
 
 // assembly of the condensed operator: atomics (one launch) unless disabled
-bool g_op_atomic = true;
-void set_op_atomic(bool on) { g_op_atomic = on; }
+
+template <typename T>
+static void launch_gather_elem(const Layout& L, const T* E, T* y, hipStream_t st) {
+    int mp = 0, mr = 0;
+    for (int d = 0; d < 3; ++d) {
+        mp = std::max(mp, L.pitch[d]);
+        mr = std::max(mr, (int)((L.pstride[d] + L.pitch[d] - 1) / L.pitch[d]));
+    }
+    const int planes = L.n[0] + L.n[1] + L.n[2] + 3;
+    const dim3 grid((mp + 63) / 64, (mr + 3) / 4, planes), block(64, 4);
+    switch (L.p) {
+        case 1: hipLaunchKernelGGL((k_gather_elem<T, 1>), grid, block, 0, st, L, E, y); break;
+        case 2: hipLaunchKernelGGL((k_gather_elem<T, 2>), grid, block, 0, st, L, E, y); break;
+        case 4: hipLaunchKernelGGL((k_gather_elem<T, 4>), grid, block, 0, st, L, E, y); break;
+        case 8: hipLaunchKernelGGL((k_gather_elem<T, 8>), grid, block, 0, st, L, E, y); break;
+        case 16: hipLaunchKernelGGL((k_gather_elem<T, 16>), grid, block, 0, st, L, E, y); break;
+        default: hipLaunchKernelGGL((k_gather_elem<T, 0>), grid, block, 0, st, L, E, y);
+    }
+}
 
 template <typename T>
 void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t st) {
-    (void)hipMemsetAsync(y, 0, sizeof(T) * tb.lay.len, st);
-    size_t sm = smem_condensed_op<T>(tb.lay.p);
-    if (g_op_atomic) {
-        int ne = tb.lay.n[0] * tb.lay.n[1] * tb.lay.n[2];
-        hipLaunchKernelGGL((k_condensed_op<T, true>), dim3(ne), dim3(256), sm, st, tb, u, y, -1);
-        return;
+    const int ne = tb.lay.n[0] * tb.lay.n[1] * tb.lay.n[2];
+    switch (tb.lay.p) {
+#define PMG_K1W(PP)                                                                                       \
+    case PP:                                                                                              \
+        hipLaunchKernelGGL((k_condensed_op_w<T, PP>), dim3(ne), dim3(64), sizeof(T) * K1Shape<PP>::total, st, \
+                           tb, u);                                                                        \
+        break;
+        PMG_K1W(1) PMG_K1W(2) PMG_K1W(3) PMG_K1W(4) PMG_K1W(5) PMG_K1W(6) PMG_K1W(7) PMG_K1W(8)
+#undef PMG_K1W
+        default:
+            hipLaunchKernelGGL((k_condensed_op<T>), dim3(ne), dim3(256), smem_condensed_op<T>(tb.lay.p), st, tb, u);
     }
-    for (int c = 0; c < 8; ++c) {
-        int nb = color_count(tb.lay.n, c);
-        if (nb == 0) continue;
-        hipLaunchKernelGGL((k_condensed_op<T, false>), dim3(nb), dim3(256), sm, st, tb, u, y, c);
-    }
+    launch_gather_elem(tb.lay, (const T*)tb.opE, y, st);
 }
 
 constexpr int MFMA_WPB = 2;
@@ -1865,11 +2239,10 @@ void launch_mlp_adam(float* prm, const float* g, float* m, float* v, int n, floa
     hipLaunchKernelGGL(k_mlp_adam, dim3(nblk(n)), dim3(256), 0, st, prm, g, m, v, n, lr, b1, b2, eps, c1, c2);
 }
 
-hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, double* out, int64_t len, int maxit,
-                              double rtol, hipStream_t st) {
-    const int64_t n = std::max<int64_t>(len, a.N0);
-    const int blocks = (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 1024);
-    hipLaunchKernelGGL(k_coarse_init, dim3(blocks), dim3(256), 0, st, a, b, out, len, maxit, rtol);
+hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, double* out, int maxit, double rtol,
+                              hipStream_t st) {
+    const int blocks = (int)std::min<int64_t>(std::max<int64_t>((a.lay.len + 255) / 256, 1), 1024);
+    hipLaunchKernelGGL(k_coarse_init, dim3(blocks), dim3(256), 0, st, a, b, out, maxit, rtol);
     return hipGetLastError();
 }
 
@@ -1889,8 +2262,7 @@ hipError_t launch_coarse_iter(const CoarseArgs& a, int j, hipStream_t st) {
 hipError_t init_kernel_attributes() {
     const int lds = 160 * 1024;
     const void* fns[] = {
-        (const void*)k_condensed_op<double, true>, (const void*)k_condensed_op<float, true>,
-        (const void*)k_condensed_op<double, false>, (const void*)k_condensed_op<float, false>,
+        (const void*)k_condensed_op<double>, (const void*)k_condensed_op<float>,
         (const void*)k_smoother<double>,     (const void*)k_smoother<float>,
         (const void*)k_prolong_add<double>,  (const void*)k_prolong_add<float>,
         (const void*)k_restrict_planes<double>, (const void*)k_restrict_planes<float>,
