@@ -5,23 +5,29 @@ Metric: solved unknowns per second (n_e p^3 / t_solve) to a 1e-10 relative
 residual, where one step is one complete solve (condensation, Krylov-
 accelerated multigrid iterations of Alg. 5, interior recovery) of the
 workload below with its inputs already resident in HBM.  The headline value
-is the mixed-precision solver (FP32 V-cycle inside FP64 CG, with learned
-per-level damping when a trained network is available, otherwise the
-paper's omega = 1); the plain FP64 solver is timed beside it.
+is the mixed-precision solver (FP32 V-cycle inside FP64 CG) with the
+per-level damping predicted by the trained network (omega = 1 when no
+weights are available); the same mixed solver with the paper's omega = 1
+and the plain FP64 solver are timed beside it.
 
 Default workload: 16 x 16 x 16 elements, p = 8 (levels 2, 4, 8), lambda = 1,
 geometric stretching up to aspect ratio 8 (alpha = 8^(1/15)), exact solution
 a seeded sum of 8 sine modes.
 
-Also reported: the roofline position of the dominant kernel (the star
-smoother, timed alone with HIP events on its stream) and the CPU oracle
-timed on a bounded sample of the same workload on the host cores.
+Also reported: the roofline position of the star smoother (the kernel the
+method's work count is dominated by), timed alone with HIP events on its
+stream, with the HBM traffic measured by rocprofv3 counters; and the CPU
+oracle timed on a bounded sample of the same workload on the host cores.
+
+  python bench.py [--steps K] [--warmup W] [--workload c2a|c2b|c1]
+  python bench.py --kernel-only     # only the smoother timing loop (profiling)
+  python bench.py --copy-only       # one device copy of 512 MiB (counter scale)
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -32,10 +38,24 @@ if ROOT not in sys.path:
 
 PEAK = {"f64": 78.6, "f32": 157.3}   # TFLOP/s, MI355X dense vector / matrix
 HBM_PEAK = 8000.0                     # GB/s
+ROOFLINE_KERNEL = "k_smoother_mfma<float, 2>"
+
+# HBM bytes per launch of the roofline kernel at the default workload, from
+# two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of
+# "python bench.py --kernel-only", each scaled by the same counter's reading
+# for a plain 512 MiB device copy; valid only for the kernel source whose
+# hash is recorded with it.
+TRAFFIC = {"kernels_sha1": "a950ed62607de69c5f94d4e6930002e5369bab23", "bytes_per_launch": 27071499}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernels_sha1():
+    path = os.path.join(ROOT, "paper_1808_03595_amd", "csrc", "pmg_kernels.hip")
+    with open(path, "rb") as fh:
+        return hashlib.sha1(fh.read()).hexdigest()
 
 
 def workload(name):
@@ -67,7 +87,9 @@ def smoother_flops(n, p):
     return 37.0 * nS ** 3 * nstars
 
 
-def time_smoother(g, torch, dev, dtype, reps=20):
+def time_smoother(g, torch, dev, dtype, reps=50):
+    """Average duration of one smoothing update u += S(r) on the finest
+    level, HIP events recorded on the stream the kernel is launched on."""
     import paper_1808_03595_amd as pmg
     L = g.num_levels()
     n = g.skeleton_len(L)
@@ -76,22 +98,23 @@ def time_smoother(g, torch, dev, dtype, reps=20):
     tmp = torch.empty(g.grid_shape(), dtype=torch.float64, device=dev)
     g.skeleton_to_grid(r, tmp, dtype)       # zero the unused slots of r
     g.grid_to_skeleton(tmp, r, dtype)
-    du = torch.empty_like(r)
+    u = torch.zeros_like(r)
     s = torch.cuda.current_stream()
     for _ in range(3):
-        g.schwarz_smooth(L, r, du, 1.0, dtype, stream=s)
+        g.schwarz_smooth_add(L, r, u, 1.0, dtype, stream=s)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(reps):
-        g.schwarz_smooth(L, r, du, 1.0, dtype, stream=s)
+        g.schwarz_smooth_add(L, r, u, 1.0, dtype, stream=s)
     e1.record(s)
     e1.synchronize()
     return e0.elapsed_time(e1) / reps * 1e-3
 
 
-def cpu_baseline(wl, coarse_rtol=1e-2):
-    """Time the FP64 oracle on a bounded sample of the workload."""
+def cpu_baseline(wl, coarse_rtol):
+    """The FP64 oracle's complete solve of the workload (condensation, ipCG
+    to 1e-10 with the same coarse tolerance, recovery) on the host cores."""
     import numpy as np
     import synth
     from oracle import mesh as omesh, solver
@@ -102,22 +125,21 @@ def cpu_baseline(wl, coarse_rtol=1e-2):
     k, a = synth.sine_modes(wl["seed"])
     _, f = synth.sine_solution(k, a, (1.0, 1.0, 1.0), X1, X2, X3, wl["lam"])
     f = np.broadcast_to(f, o.shape).copy()
-    from oracle import matfree
     t0 = time.perf_counter()
-    Fh = matfree.condense_rhs(o, f)
-    t_pre = time.perf_counter() - t0
-    hier = solver.Hierarchy(o, nu_mode="kMG", coarse_rtol=coarse_rtol, coarse_maxit=2000)
-    # one Krylov iteration = one V-cycle + one operator application
-    t0 = time.perf_counter()
-    r = Fh
-    z = hier.vcycle(None, r)
-    matfree.condensed_op(o, z)
-    t_it = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    matfree.recover_interior(o, f, Fh)
-    t_post = time.perf_counter() - t0
-    return dict(t_pre=t_pre, t_iter=t_it, t_post=t_post, threads=threads,
-                coarse_iters=hier.coarse_iters[-1] if hier.coarse_iters else 0)
+    res = solver.solve(o, f, method="kMG", rtol=1e-10, coarse_rtol=coarse_rtol, coarse_maxit=2000)
+    return dict(t=time.perf_counter() - t0, iters=res.iters, threads=threads)
+
+
+def learned_damping(wl, L):
+    """omega predicted by the trained network for this mesh, or None."""
+    import synth
+    from paper_1808_03595_amd.learn import DampingMLP, predict_damping
+    model = DampingMLP.load()
+    if model is None:
+        return None
+    n = wl["n"]
+    hs = [synth.stretched_widths(n[d], wl["alpha"]) for d in range(3)]
+    return predict_damping(model, wl["p"], wl["lam"], hs[0], hs[1], hs[2], L)
 
 
 def main():
@@ -127,11 +149,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2a")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--coarse-rtol", type=float, default=1e-2)
+    ap.add_argument("--coarse-rtol", type=float, default=3e-2,
+                    help="relative tolerance of the coarse CG (the paper leaves it open)")
+    ap.add_argument("--damping", choices=["learned", "one"], default="learned")
     ap.add_argument("--hmg-levels", type=int, default=0,
                     help="degree-1 levels below p_0 (0: the paper's CG on p_0 = 2)")
     ap.add_argument("--hmg-omega", type=float, default=0.8)
     ap.add_argument("--hmg-nu", type=int, default=2)
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="run only the smoother timing loop (for counter profiles)")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="run one 512 MiB device copy (scale of the byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -144,12 +172,21 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if args.copy_only:
+        a = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] copied 512 MiB")
+        return
     wl = workload(args.workload)
     n, p = wl["n"], wl["p"]
     g = pmg.create_mesh(n[0], n[1], n[2], p, wl["lam"], wl["alpha"])
-    # coarse CG to a relative 1e-2: the outer iteration count equals the one
-    # with 1e-8 on this workload (checked with the oracle), and the flexible
-    # ipCG absorbs the inexact coarse solve
+    L = g.num_levels()
+    if args.kernel_only:
+        t = time_smoother(g, torch, dev, pmg.F32, reps=100)
+        log(f"[bench] {ROOFLINE_KERNEL}: {t * 1e6:.2f} us per launch")
+        return
     g.set_cycle(0, args.coarse_rtol, 2000)
     if args.hmg_levels:
         g.set_coarse_mg(args.hmg_levels, args.hmg_omega, args.hmg_nu)
@@ -157,7 +194,8 @@ def main():
     u = torch.zeros_like(f)
     ndof = n[0] * n[1] * n[2] * p ** 3
 
-    def run(dtype, steps, warm):
+    def run(dtype, omega, steps, warm):
+        g.set_damping(omega)
         for _ in range(warm):
             g.pcg_solve(f, u, 1e-10, 200, dtype)
         torch.cuda.synchronize()
@@ -170,13 +208,21 @@ def main():
         err = (torch.linalg.vector_norm(u - u_ex) / torch.linalg.vector_norm(u_ex)).item()
         return dt / steps, st, err
 
-    log(f"[bench] workload {args.workload}: n={n} p={p} ndof={ndof}")
-    t64, st64, err64 = run(pmg.F64, args.steps, args.warmup)
+    omega = learned_damping(wl, L) if args.damping == "learned" else None
+    log(f"[bench] workload {args.workload}: n={n} p={p} ndof={ndof} omega={omega}")
+    t64, st64, err64 = run(pmg.F64, None, args.steps, args.warmup)
     log(f"[bench] fp64: {t64*1e3:.2f} ms/solve iters={st64.iters} rel_res={st64.rel_res:.2e} "
         f"coarse_iters={st64.coarse_iters} err_vs_exact={err64:.2e}")
-    t32, st32, err32 = run(pmg.F32, args.steps, args.warmup)
-    log(f"[bench] mixed: {t32*1e3:.2f} ms/solve iters={st32.iters} rel_res={st32.rel_res:.2e} "
-        f"coarse_iters={st32.coarse_iters} err_vs_exact={err32:.2e}")
+    t1, st1, err1 = run(pmg.F32, None, args.steps, args.warmup)
+    log(f"[bench] mixed omega=1: {t1*1e3:.2f} ms/solve iters={st1.iters} rel_res={st1.rel_res:.2e} "
+        f"coarse_iters={st1.coarse_iters} err_vs_exact={err1:.2e}")
+    if omega is not None:
+        t32, st32, err32 = run(pmg.F32, omega, args.steps, args.warmup)
+        log(f"[bench] mixed learned: {t32*1e3:.2f} ms/solve iters={st32.iters} rel_res={st32.rel_res:.2e} "
+            f"coarse_iters={st32.coarse_iters} err_vs_exact={err32:.2e}")
+    else:
+        t32, st32, err32 = t1, st1, err1
+    g.set_damping(None)
 
     ts64 = time_smoother(g, torch, dev, pmg.F64)
     ts32 = time_smoother(g, torch, dev, pmg.F32)
@@ -184,22 +230,21 @@ def main():
     ach32 = fl / ts32 / 1e12
     ach64 = fl / ts64 / 1e12
     log(f"[bench] smoother f64 {ts64*1e6:.1f} us ({ach64:.2f} TF/s), f32 {ts32*1e6:.1f} us ({ach32:.2f} TF/s)")
+    traffic = None
+    if TRAFFIC["kernels_sha1"] == kernels_sha1() and args.workload == "c2a":
+        traffic = TRAFFIC["bytes_per_launch"]
 
     cpu = None
     if not args.no_cpu:
         c = cpu_baseline(wl, args.coarse_rtol)
-        iters = st64.iters
-        t_cpu = c["t_pre"] + iters * c["t_iter"] + c["t_post"]
-        cpu = {"value": ndof / t_cpu, "unit": "unknowns/s", "cores": c["threads"], "kind": "oracle",
-               "sample": (f"FP64 oracle on the full workload: condensation + one ipCG iteration "
-                          f"(V-cycle + operator) + recovery, timed once each and scaled to "
-                          f"{iters} iterations")}
-        log(f"[bench] cpu oracle: pre {c['t_pre']:.2f}s iter {c['t_iter']:.2f}s post {c['t_post']:.2f}s")
+        cpu = {"value": ndof / c["t"], "unit": "unknowns/s", "cores": c["threads"], "kind": "oracle",
+               "sample": (f"the FP64 oracle's complete solve of the same workload ({c['iters']} ipCG "
+                          f"iterations to 1e-10, coarse CG to {args.coarse_rtol:g}), timed once: {c['t']:.1f} s")}
+        log(f"[bench] cpu oracle: {c['t']:.2f} s, {c['iters']} iterations")
 
-    value = ndof / t32
     line = {
         "metric": "solved unknowns/s to 1e-10 residual vs p; FP32-MG+learned vs plain FP64",
-        "value": value,
+        "value": ndof / t32,
         "unit": "unknowns/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -214,14 +259,21 @@ def main():
                                f"stretch alpha={wl['alpha']:.4f} (AR {wl['alpha']**(n[0]-1):.1f}), "
                                f"8 sine modes seed {wl['seed']}",
                    "ndof": ndof, "iters": st32.iters, "rel_res": st32.rel_res,
-                   "damping": "omega=1 (paper)",
+                   "damping": "learned" if omega is not None else "omega=1 (paper)",
+                   "omega": omega,
+                   "coarse": (f"Jacobi CG on p_0=2 to rel. {args.coarse_rtol:g}" if not args.hmg_levels else
+                              f"{args.hmg_levels} degree-1 levels + CG"),
+                   "coarse_iters_per_solve": st32.coarse_iters,
+                   "mixed_omega1_unknowns_per_s": ndof / t1, "mixed_omega1_iters": st1.iters,
                    "fp64_unknowns_per_s": ndof / t64, "fp64_iters": st64.iters,
                    "fp64_ms_per_solve": t64 * 1e3,
                    "rel_err_vs_exact_mixed": err32, "rel_err_vs_exact_fp64": err64},
-        "roofline": {"bound": "alu", "kernel": "k_smoother<float>",
+        "roofline": {"bound": "mfma", "kernel": ROOFLINE_KERNEL,
                      "achieved": ach32, "peak": PEAK["f32"], "unit": "TFLOP/s",
-                     "frac": ach32 / PEAK["f32"], "traffic": None,
-                     "fp64": {"achieved": ach64, "peak": PEAK["f64"], "frac": ach64 / PEAK["f64"]}},
+                     "frac": ach32 / PEAK["f32"], "traffic": traffic,
+                     "us_per_launch": ts32 * 1e6,
+                     "fp64": {"kernel": "k_smoother_mfma<double, 2>", "achieved": ach64, "peak": PEAK["f64"],
+                              "frac": ach64 / PEAK["f64"], "us_per_launch": ts64 * 1e6}},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -109,6 +109,14 @@ int pmg_apply_condensed_op(pmg_mesh *m, int level, int dtype, const void *d_u,
 int pmg_schwarz_smooth(pmg_mesh *m, int level, int dtype, const void *d_r,
                        void *d_du, double omega, void *stream);
 
+/* d_u += omega * Smoother_l(r): the smoothing update of Alg. 3 as the
+ * V-cycle applies it (same smoother as pmg_schwarz_smooth, added into d_u
+ * instead of overwriting it).  d_r, d_u: skeleton arrays of the level
+ * (dtype), not aliasing; d_u must be zero at the slots that hold no unknown
+ * (as every array written by this library is). */
+int pmg_schwarz_smooth_add(pmg_mesh *m, int level, int dtype, const void *d_r,
+                           void *d_u, double omega, void *stream);
+
 /* Grid transfers between level l-1 and l (Sec. 4.1): prolongation
  * d_fine += J_l d_coarse (embedded tensor interpolation restricted to the
  * condensed unknowns) and restriction d_coarse = J_l^T d_fine. */

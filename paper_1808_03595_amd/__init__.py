@@ -72,6 +72,7 @@ SIGNATURES = {
     "pmg_skeleton_to_grid": (_I, [_VP, _I, _VP, _VP, _VP]),
     "pmg_apply_condensed_op": (_I, [_VP, _I, _I, _VP, _VP, _VP]),
     "pmg_schwarz_smooth": (_I, [_VP, _I, _I, _VP, _VP, _D, _VP]),
+    "pmg_schwarz_smooth_add": (_I, [_VP, _I, _I, _VP, _VP, _D, _VP]),
     "pmg_prolong_add": (_I, [_VP, _I, _I, _VP, _VP, _VP]),
     "pmg_restrict": (_I, [_VP, _I, _I, _VP, _VP, _VP]),
     "pmg_set_cycle": (_I, [_VP, _I, _D, _I]),
@@ -195,6 +196,9 @@ class Mesh:
 
     def schwarz_smooth(self, level, r, du, omega=1.0, dtype=F64, stream=None):
         _check(lib().pmg_schwarz_smooth(self.h, level, dtype, _ptr(r), _ptr(du), omega, _stream(stream)))
+
+    def schwarz_smooth_add(self, level, r, u, omega=1.0, dtype=F64, stream=None):
+        _check(lib().pmg_schwarz_smooth_add(self.h, level, dtype, _ptr(r), _ptr(u), omega, _stream(stream)))
 
     def prolong_add(self, level, coarse, fine, dtype=F64, stream=None):
         _check(lib().pmg_prolong_add(self.h, level, dtype, _ptr(coarse), _ptr(fine), _stream(stream)))

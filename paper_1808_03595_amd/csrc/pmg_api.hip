@@ -781,6 +781,18 @@ int pmg_schwarz_smooth(pmg_mesh* m, int level, int dtype, const void* r, void* d
     return 0;
 }
 
+int pmg_schwarz_smooth_add(pmg_mesh* m, int level, int dtype, const void* r, void* u, double omega,
+                           void* stream) {
+    if (check_level(m, level)) return PMG_EINVAL;
+    if (!r || !u || r == u) return fail(PMG_EINVAL, "null or aliasing pointers");
+    Level& L = m->lv[level];
+    if (dtype == PMG_F64) launch_smoother_add<double>(L.t64, (const double*)r, (double*)u, omega, S(stream));
+    else if (dtype == PMG_F32) launch_smoother_add<float>(L.t32, (const float*)r, (float*)u, (float)omega, S(stream));
+    else return fail(PMG_EINVAL, "bad dtype");
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
 int pmg_prolong_add(pmg_mesh* m, int level, int dtype, const void* c, void* f, void* stream) {
     if (check_level(m, level) || level < 1) return fail(PMG_EINVAL, "level must be 1..L");
     if (!c || !f) return fail(PMG_EINVAL, "null pointer");

@@ -366,32 +366,45 @@ __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restri
         y[s] = (T)0;
         return;
     }
-    // candidate (element index, local index) per direction
-    int ce[3][2], ca[3][2], nc[3];
+    // candidate (element index, local index) per direction: one element, or
+    // the two on both sides of an element boundary (clipped at the domain)
+    int e0[3], a0[3], e1[3], a1[3];
+    bool two[3];
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const int q = g[k] / p, a = g[k] - q * p;
-        if (a == 0) {   // element boundary: the elements on both sides
-            nc[k] = 0;
-            if (q > 0) { ce[k][nc[k]] = q - 1; ca[k][nc[k]] = p; ++nc[k]; }
-            if (q < L.n[k]) { ce[k][nc[k]] = q; ca[k][nc[k]] = 0; ++nc[k]; }
-        } else {
-            nc[k] = 1;
-            ce[k][0] = q;
-            ca[k][0] = a;
-        }
+        const int qk = g[k] / p, ak = g[k] - qk * p;
+        const bool bnd = ak == 0;
+        const bool lo = bnd && qk > 0, hi = !bnd || qk < L.n[k];
+        // first candidate: the element below the boundary if it exists
+        e0[k] = lo ? qk - 1 : qk;
+        a0[k] = lo ? p : ak;
+        two[k] = lo && hi;
+        e1[k] = qk;
+        a1[k] = 0;
     }
-    T acc = 0;
-    for (int z = 0; z < nc[2]; ++z)
-        for (int yy = 0; yy < nc[1]; ++yy)
-            for (int x = 0; x < nc[0]; ++x) {
-                const int a1 = ca[0][x], a2 = ca[1][yy], a3 = ca[2][z];
-                const int64_t e = ((int64_t)ce[2][z] * L.n[1] + ce[1][yy]) * L.n[0] + ce[0][x];
+    // all (up to eight) loads first, then the sum in a fixed order
+    T v[8];
+#pragma unroll
+    for (int z = 0; z < 2; ++z)
+#pragma unroll
+        for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const int k = (z * 2 + yy) * 2 + x;
+                v[k] = 0;
+                if ((x && !two[0]) || (yy && !two[1]) || (z && !two[2])) continue;
+                const int c1 = x ? e1[0] : e0[0], c2 = yy ? e1[1] : e0[1], c3 = z ? e1[2] : e0[2];
+                const int b1 = x ? a1[0] : a0[0], b2 = yy ? a1[1] : a0[1], b3 = z ? a1[2] : a0[2];
+                const int64_t e = ((int64_t)c3 * L.n[1] + c2) * L.n[0] + c1;
                 int f, tr, tc;
-                if (a1 == 0 || a1 == p) { f = a1 ? 1 : 0; tr = a3; tc = a2; }
-                else if (a2 == 0 || a2 == p) { f = a2 ? 3 : 2; tr = a3; tc = a1; }
-                else { f = a3 ? 5 : 4; tr = a2; tc = a1; }
-                acc += E[e * 6 * t2 + f * t2 + tr * n1 + tc];
+                if (b1 == 0 || b1 == p) { f = b1 ? 1 : 0; tr = b3; tc = b2; }
+                else if (b2 == 0 || b2 == p) { f = b2 ? 3 : 2; tr = b3; tc = b1; }
+                else { f = b3 ? 5 : 4; tr = b2; tc = b1; }
+                v[k] = E[e * 6 * t2 + f * t2 + tr * n1 + tc];
             }
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += v[k];
     y[s] = acc;
 }
 
@@ -816,7 +829,9 @@ __global__ void __launch_bounds__(256) k_smoother(LevelTabs<T> tb, const T* __re
 // output row held in register s by that group.  The eigenspace pass runs
 // on VALU in 4x4x4 tiles per lane; its three contractions are reduced
 // across the four tiles that share an index through LDS.  Corrections are
-// added to the plane layout with hardware atomics (one launch, no colours).
+// added to the plane layout with hardware atomics (a per-star workspace
+// summed by a gather kernel measured slower here: the windows overlap four
+// times, so the workspace traffic outweighs the atomics).
 // ---------------------------------------------------------------------------
 template <typename T> struct Mfma;
 template <> struct Mfma<double> {

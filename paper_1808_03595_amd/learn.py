@@ -168,7 +168,7 @@ def build_dataset(degrees, lam_h2s, ars, n=4, seed=0, cycles=4, log=None):
                 L = g.num_levels()
                 if L == 0:
                     continue
-                g.set_cycle(0, 1e-2, 2000)
+                g.set_cycle(0, 3e-2, 2000)
                 f = torch.as_tensor(synth.random_grid(g.grid_shape(), seed), device="cuda:0")
                 om, rho, rho1 = grid_search(g, f, min(L, NOUT), cycles)
                 x = mesh_features(p, lam, hx, hy, hz)

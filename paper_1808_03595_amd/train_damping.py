@@ -2,10 +2,11 @@
 
 python -m paper_1808_03595_amd.train_damping [--out PATH] [--report PATH]
 
-1. Training set: anisotropic brick meshes of 4^3 elements (Sec. 5.3 recipe,
+1. Training set: anisotropic brick meshes of 6^3 elements (Sec. 5.3 recipe,
    scaled) over p in {3, 4, 6, 8, 12, 16}, lambda h^2 in {0, 1e-2, 1, 1e2,
-   1e4}, AR in {1, 2, 4, 8, 16}; targets = per-level argmin of the MG
-   convergence factor over omega in 0.5 .. 1.5 (step 0.05).
+   1e4}, AR in {1, 2, 4, 8, 16}; targets = per-level argmin of the
+   convergence factor of the deployed solver over omega in 0.5 .. 1.5
+   (step 0.05), ties going to the value closest to 1.
 2. Training: full-batch Adam (lr 1e-3) on the masked MSE, GPU kernels only.
 3. Held-out evaluation: 24^3 elements, p = 12, AR in {3, 6, 12},
    lambda h^2 in {0.3, 30, 3e3}; iterations and time to a 1e-10 relative
@@ -28,7 +29,7 @@ def log(msg):
 
 
 def evaluate(model, ns=24, p=12, ars=(3.0, 6.0, 12.0), lam_h2s=(0.3, 30.0, 3e3), seed=0,
-             coarse_rtol=1e-2):
+             coarse_rtol=3e-2):
     import torch
     import synth
     from . import F32, create_mesh_widths
@@ -72,11 +73,13 @@ def main():
     ap.add_argument("--report", default=None)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--degrees", default="3,4,6,8,12,16")
+    ap.add_argument("--n", type=int, default=6, help="elements per direction of the training meshes")
     ap.add_argument("--skip-eval", action="store_true")
     args = ap.parse_args()
     degrees = [int(v) for v in args.degrees.split(",")]
     t0 = time.perf_counter()
-    X, T, M, rows = build_dataset(degrees, [0.0, 1e-2, 1.0, 1e2, 1e4], [1.0, 2.0, 4.0, 8.0, 16.0], log=log)
+    X, T, M, rows = build_dataset(degrees, [0.0, 1e-2, 1.0, 1e2, 1e4], [1.0, 2.0, 4.0, 8.0, 16.0], n=args.n,
+                                  log=log)
     t_data = time.perf_counter() - t0
     log(f"dataset: {len(X)} samples in {t_data:.1f} s")
     model = DampingMLP(seed=0)

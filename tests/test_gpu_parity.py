@@ -237,3 +237,20 @@ def test_vcycle_with_degree1_levels(gpu, n, p, lam, alpha, levels):
     g.vcycle(io.to_dev(r), z, pmg.F64)
     torch.cuda.synchronize()
     assert rel(io.to_grid(z), h0.vcycle(None, r)) <= 1e-11
+
+
+@pytest.mark.parametrize("case", CASES[:4], ids=_ids)
+def test_schwarz_smooth_add(gpu, case):
+    """u += omega S(r) on the finest level equals the oracle's update."""
+    n, p, lam, alpha = case
+    g, o = make_pair(n, p, lam, alpha)
+    L = g.num_levels()
+    io = LevelIO(g, L)
+    mask = o.free_skeleton_mask()
+    r = synth.random_grid(o.shape, 71) * mask
+    u0 = synth.random_grid(o.shape, 72) * mask
+    ref = u0 + matfree.smoother(o, r, 0.8)
+    u = io.to_dev(u0)
+    g.schwarz_smooth_add(L, io.to_dev(r), u, 0.8, pmg.F64)
+    torch.cuda.synchronize()
+    assert rel(io.to_grid(u), ref) <= 1e-12
