@@ -45,7 +45,7 @@ typedef struct pmg_mesh pmg_mesh;
 enum { PMG_F64 = 0, PMG_F32 = 1 };
 enum { PMG_OK = 0, PMG_EINVAL = -1, PMG_EHIP = -2, PMG_ENOMEM = -3,
        PMG_EUNSUP = -4, PMG_NOT_CONVERGED = 1, PMG_BREAKDOWN = 2 };
-enum { PMG_MAX_DEGREE = 32, PMG_MAX_HIST = 512 };
+enum { PMG_MAX_DEGREE = 48, PMG_MAX_HIST = 512 };
 
 typedef struct {
     int iters;                    /* outer iterations performed            */

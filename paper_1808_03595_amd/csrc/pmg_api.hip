@@ -181,17 +181,11 @@ int fill_tabs(pmg_mesh* m, LevelTabs<T>& tb, const HostTables& t, const Layout& 
     return rc;
 }
 
-const size_t kMaxLds = 160 * 1024;
 
 int check_lds(int p) {
-    size_t a = smem_condensed_op<double>(p), b = smem_smoother<double>(p);
-    int q = p - 1, n1 = p + 1;
-    size_t c = sizeof(double) * (size_t)(2 * q * q * q + 18 * q * q);
-    size_t r = sizeof(double) * (size_t)(6 * n1 * n1 + 2 * q * q * q + 12 * q * q);
-    size_t mx = std::max(std::max(a, b), std::max(c, r));
-    if (mx > kMaxLds)
-        return fail(PMG_EUNSUP, "degree " + std::to_string(p) + " needs " + std::to_string(mx) +
-                                    " bytes of LDS per workgroup (limit 160 KiB)");
+    // working sets beyond the LDS of a CU run from device scratch (see
+    // build_level); only the fixed-size kernels bound the degree
+    (void)p;
     return 0;
 }
 
@@ -299,6 +293,25 @@ int build_level(pmg_mesh* m, Level& L, int p, int pc, const std::vector<double> 
     if ((rc = m->alloc(&ew, ne * 6 * (size_t)(p + 1) * (p + 1)))) return rc;
     L.t64.opE = ew;
     L.t32.opE = reinterpret_cast<float*>(ew);
+    // device scratch of the general kernels whose working set exceeds the LDS
+    {
+        const int* n = L.lay.n;
+        const size_t nv = (size_t)(n[0] + 1) * (n[1] + 1) * (n[2] + 1);
+        const size_t col_e = (size_t)((n[0] + 1) / 2) * ((n[1] + 1) / 2) * ((n[2] + 1) / 2);
+        const size_t col_v = (size_t)((n[0] + 2) / 2) * ((n[1] + 2) / 2) * ((n[2] + 2) / 2);
+        auto over = [](size_t elems) { return elems * sizeof(double) > kLdsBytes; };
+        size_t need = 0;
+        if (over(ws_condensed_op(p))) need = std::max(need, ne * ws_condensed_op(p));
+        if (over(ws_smoother(p))) need = std::max(need, std::min(nv, col_v) * ws_smoother(p));
+        if (over(ws_condense(p))) need = std::max(need, std::min(ne, col_e) * ws_condense(p));
+        if (over(ws_recover(p))) need = std::max(need, ne * ws_recover(p));
+        if (need) {
+            double* g = nullptr;
+            if ((rc = m->alloc(&g, need))) return rc;
+            L.t64.gws = g;
+            L.t32.gws = reinterpret_cast<float*>(g);
+        }
+    }
     return 0;
 }
 

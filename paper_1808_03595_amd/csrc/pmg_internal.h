@@ -72,7 +72,34 @@ struct LevelTabs {
     // workspace of the condensed operator: per element, the six face tiles
     // of its contribution, [e][6][(p+1)^2] (only canonical entries used)
     T* opE;
+    // per-workgroup scratch in device memory for the general kernels when
+    // their working set exceeds the LDS of a CU (large p); null otherwise
+    T* gws;
 };
+
+// Working-set sizes (elements of T) of the general per-element / per-star
+// kernels: held in LDS when they fit, else in the level's device scratch.
+__host__ __device__ inline int elem_table_size(int p) {
+    const int n1 = p + 1, q = p - 1;
+    return 3 * (n1 + n1 * n1 + 2 * q * q + 3 * q);
+}
+__host__ __device__ inline size_t ws_condensed_op(int p) {
+    const size_t n1 = p + 1, q = p - 1;
+    return 6 * n1 * n1 + 18 * q * q + (size_t)elem_table_size(p);
+}
+__host__ __device__ inline size_t ws_smoother(int p) {
+    const size_t nS = 2 * p - 1;
+    return 9 * nS * nS;
+}
+__host__ __device__ inline size_t ws_condense(int p) {
+    const size_t q = p - 1;
+    return 2 * q * q * q + 18 * q * q;
+}
+__host__ __device__ inline size_t ws_recover(int p) {
+    const size_t n1 = p + 1, q = p - 1;
+    return 6 * n1 * n1 + 2 * q * q * q + 12 * q * q;
+}
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 
 struct HostTables {
     // per direction: concatenated element / star tables (FP64)

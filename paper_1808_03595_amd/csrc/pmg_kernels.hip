@@ -280,10 +280,6 @@ __device__ inline T hbb_at(const ElemPtrs<T>& P, int p, T lam, const T* tile, in
 
 // Copy the 1D tables of element e into LDS (`dst`, elem_table_size(p)
 // entries) and return pointers into the copy.
-__host__ __device__ inline int elem_table_size(int p) {
-    const int n1 = p + 1, q = p - 1;
-    return 3 * (n1 + n1 * n1 + 2 * q * q + 3 * q);
-}
 
 template <typename T>
 __device__ ElemPtrs<T> stage_elem_tables(const LevelTabs<T>& tb, const int e[3], T* dst) {
@@ -309,7 +305,7 @@ __device__ ElemPtrs<T> stage_elem_tables(const LevelTabs<T>& tb, const int e[3],
 template <typename T>
 __global__ void __launch_bounds__(256) k_condensed_op(LevelTabs<T> tb, const T* __restrict__ u) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* sm = reinterpret_cast<T*>(smem_raw);
+    T* sm = tb.gws ? tb.gws + (size_t)blockIdx.x * ws_condensed_op(tb.lay.p) : reinterpret_cast<T*>(smem_raw);
     const Layout& L = tb.lay;
     const int p = L.p, n1 = p + 1, t2 = n1 * n1, q = p - 1, q2 = q * q;
     int e[3];
@@ -705,7 +701,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_smoother(LevelTabs<T> tb, const T* __restrict__ r,
                                                   T* __restrict__ du, T omega, int color) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* sm = reinterpret_cast<T*>(smem_raw);
+    T* sm = tb.gws ? tb.gws + (size_t)blockIdx.x * ws_smoother(tb.lay.p) : reinterpret_cast<T*>(smem_raw);
     const Layout& L = tb.lay;
     const int p = L.p, nS = 2 * p - 1, s2 = nS * nS, c = p - 1;
     int nv[3] = {L.n[0] + 1, L.n[1] + 1, L.n[2] + 1};
@@ -1409,7 +1405,7 @@ __global__ void k_mass_skeleton(Layout L, const double* __restrict__ m1, const d
 __global__ void __launch_bounds__(256) k_condense(LevelTabs<double> tb, const double* __restrict__ f,
                                                   double* __restrict__ Fh, int color) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    double* sm = reinterpret_cast<double*>(smem_raw);
+    double* sm = tb.gws ? tb.gws + (size_t)blockIdx.x * ws_condense(tb.lay.p) : reinterpret_cast<double*>(smem_raw);
     const Layout& L = tb.lay;
     const int p = L.p, q = p - 1, q2 = q * q, q3 = q2 * q;
     if (q < 1) return;
@@ -1461,7 +1457,7 @@ __global__ void __launch_bounds__(256) k_condense(LevelTabs<double> tb, const do
 __global__ void __launch_bounds__(256) k_recover(LevelTabs<double> tb, const double* __restrict__ f,
                                                  const double* __restrict__ uh, double* __restrict__ ug) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    double* sm = reinterpret_cast<double*>(smem_raw);
+    double* sm = tb.gws ? tb.gws + (size_t)blockIdx.x * ws_recover(tb.lay.p) : reinterpret_cast<double*>(smem_raw);
     const Layout& L = tb.lay;
     const int p = L.p, n1 = p + 1, t2 = n1 * n1, q = p - 1, q2 = q * q, q3 = q2 * q;
     int e[3];
@@ -2053,13 +2049,19 @@ static int color_count(const int n[3], int color) {
 
 template <typename T>
 size_t smem_condensed_op(int p) {
-    int n1 = p + 1, q = p - 1;
-    return sizeof(T) * (size_t)(6 * n1 * n1 + 18 * q * q + elem_table_size(p));
+    return sizeof(T) * ws_condensed_op(p);
 }
 template <typename T>
 size_t smem_smoother(int p) {
-    int nS = 2 * p - 1;
-    return sizeof(T) * (size_t)(9 * nS * nS);
+    return sizeof(T) * ws_smoother(p);
+}
+
+// Launch helpers for the general kernels: LDS when the working set fits,
+// else the level's device scratch (a copy of the tables with gws set).
+template <typename T>
+static size_t pick_ws(LevelTabs<T>& t, size_t elems) {
+    if (sizeof(T) * elems <= kLdsBytes && t.gws) t.gws = nullptr;
+    return t.gws ? 0 : sizeof(T) * elems;
 }
 
 template <typename T>
@@ -2104,8 +2106,11 @@ void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t s
         break;
         PMG_K1W(1) PMG_K1W(2) PMG_K1W(3) PMG_K1W(4) PMG_K1W(5) PMG_K1W(6) PMG_K1W(7) PMG_K1W(8)
 #undef PMG_K1W
-        default:
-            hipLaunchKernelGGL((k_condensed_op<T>), dim3(ne), dim3(256), smem_condensed_op<T>(tb.lay.p), st, tb, u);
+        default: {
+            LevelTabs<T> t = tb;
+            const size_t sm = pick_ws(t, ws_condensed_op(tb.lay.p));
+            hipLaunchKernelGGL((k_condensed_op<T>), dim3(ne), dim3(256), sm, st, t, u);
+        }
     }
     launch_gather_elem(tb.lay, (const T*)tb.opE, y, st);
 }
@@ -2121,12 +2126,13 @@ void launch_smoother_add(const LevelTabs<T>& tb, const T* r, T* du, T omega, hip
                            dim3(64 * MFMA_WPB), smm, st, tb, r, du, omega);
         return;
     }
-    size_t sm = smem_smoother<T>(tb.lay.p);
+    LevelTabs<T> t = tb;
+    const size_t sm = pick_ws(t, ws_smoother(tb.lay.p));
     int nv[3] = {tb.lay.n[0] + 1, tb.lay.n[1] + 1, tb.lay.n[2] + 1};
     for (int c = 0; c < 8; ++c) {
         int nb = color_count(nv, c);
         if (nb == 0) continue;
-        hipLaunchKernelGGL(k_smoother<T>, dim3(nb), dim3(256), sm, st, tb, r, du, omega, c);
+        hipLaunchKernelGGL(k_smoother<T>, dim3(nb), dim3(256), sm, st, t, r, du, omega, c);
     }
 }
 
@@ -2171,19 +2177,20 @@ void launch_condense(const LevelTabs<double>& tb, const double* m1, const double
     hipLaunchKernelGGL(k_mass_skeleton, dim3(nblk(L.len)), dim3(256), 0, st, L, m1, m2, m3, f, Fh);
     int q = L.p - 1;
     if (q < 1) return;
-    size_t sm = sizeof(double) * (size_t)(2 * q * q * q + 18 * q * q);
+    LevelTabs<double> t = tb;
+    const size_t sm = pick_ws(t, ws_condense(L.p));
     for (int c = 0; c < 8; ++c) {
         int nb = color_count(L.n, c);
         if (nb == 0) continue;
-        hipLaunchKernelGGL(k_condense, dim3(nb), dim3(256), sm, st, tb, f, Fh, c);
+        hipLaunchKernelGGL(k_condense, dim3(nb), dim3(256), sm, st, t, f, Fh, c);
     }
 }
 
 void launch_recover(const LevelTabs<double>& tb, const double* f, const double* uh, double* ug, hipStream_t st) {
     const Layout& L = tb.lay;
-    int n1 = L.p + 1, q = L.p - 1;
-    size_t sm = sizeof(double) * (size_t)(6 * n1 * n1 + 2 * q * q * q + 12 * q * q);
-    hipLaunchKernelGGL(k_recover, dim3(L.n[0] * L.n[1] * L.n[2]), dim3(256), sm, st, tb, f, uh, ug);
+    LevelTabs<double> t = tb;
+    const size_t sm = pick_ws(t, ws_recover(L.p));
+    hipLaunchKernelGGL(k_recover, dim3(L.n[0] * L.n[1] * L.n[2]), dim3(256), sm, st, t, f, uh, ug);
 }
 
 template <typename T>

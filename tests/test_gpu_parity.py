@@ -31,6 +31,10 @@ CASES = [
     ((4, 3, 2), 6, 1.0, 1.7),
     ((2, 2, 2), 16, 1.0, 1.0),
     ((1, 2, 3), 5, 1.0, 1.0),
+    # large degrees: working sets beyond the LDS run from device scratch
+    ((2, 2, 2), 24, 1.0, 1.2),
+    ((2, 1, 2), 32, 10.0, 1.0),
+    ((1, 2, 1), 48, 1.0, 1.0),
 ]
 
 
@@ -254,3 +258,16 @@ def test_schwarz_smooth_add(gpu, case):
     g.schwarz_smooth_add(L, io.to_dev(r), u, 0.8, pmg.F64)
     torch.cuda.synchronize()
     assert rel(io.to_grid(u), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("n,p", [((2, 2, 2), 24), ((1, 2, 1), 48)])
+def test_pcg_solve_large_degree(gpu, n, p):
+    """Alg. 5 end to end at large p: same iterations and solution as the oracle."""
+    g, o = make_pair(n, p, 1.0, 1.2)
+    g.set_cycle(0, 1e-8, 500)
+    f = synth.random_grid(o.shape, 81)
+    res = solver.solve(o, f, method="kMG", rtol=1e-10, coarse_rtol=1e-8, coarse_maxit=500)
+    u = torch.zeros(o.shape, dtype=torch.float64, device=gpu)
+    st = g.pcg_solve(torch.as_tensor(f, device=gpu), u, 1e-10, 100, pmg.F64)
+    assert st.status == 0 and st.iters == res.iters
+    assert rel(u.cpu().numpy(), res.u) <= 1e-9
