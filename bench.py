@@ -142,6 +142,53 @@ def learned_damping(wl, L):
     return predict_damping(model, wl["p"], wl["lam"], hs[0], hs[1], hs[2], L)
 
 
+SWEEP = (2, 4, 8, 12, 16, 24, 32, 48)
+
+
+def p_sweep(torch, pmg, synth, dev, coarse_rtol, steps):
+    """Unknowns/s versus p at about 1e7 unknowns (n = round(215.44 / p)
+    elements per direction, uniform, lambda = 1, 8 sine modes), plain FP64
+    and mixed precision with the learned damping, one whole solve each after
+    one warm-up."""
+    out = []
+    for p in SWEEP:
+        nn = int(round(215.44 / p))
+        wl = dict(n=(nn, nn, nn), p=p, lam=1.0, alpha=1.0, seed=0)
+        g = pmg.create_mesh(nn, nn, nn, p, 1.0, 1.0)
+        g.set_cycle(0, coarse_rtol, 5000)
+        # at p <= 4 the coarse problem is most of the mesh: the CG on it grows
+        # like n_e^(4/3) (Sec. 4.2), so degree-1 levels go below it there
+        hmg = 6 if p <= 4 else 0
+        if hmg:
+            g.set_coarse_mg(hmg, 0.8, 2)
+        L = g.num_levels()
+        u_ex, f = make_rhs(g, wl, torch, synth, dev)
+        u = torch.zeros_like(f)
+        ndof = nn ** 3 * p ** 3
+        row = {"p": p, "n": nn, "ndof": ndof, "levels": L + 1,
+               "coarse": f"{hmg} degree-1 levels + CG" if hmg else "CG on p_0 = 2"}
+        omega = learned_damping(wl, L) if L > 0 else None
+        for name, dtype, om in (("fp64", pmg.F64, None), ("mixed_learned", pmg.F32, omega)):
+            g.set_damping(om)
+            g.pcg_solve(f, u, 1e-10, 300, dtype)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                st = g.pcg_solve(f, u, 1e-10, 300, dtype)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            err = (torch.linalg.vector_norm(u - u_ex) / torch.linalg.vector_norm(u_ex)).item()
+            row[name] = {"unknowns_per_s": ndof / dt, "ms": dt * 1e3, "iters": st.iters,
+                         "rel_res": st.rel_res, "rel_err_vs_exact": err, "status": st.status}
+        log(f"[bench] sweep p={p} n={nn}: fp64 {row['fp64']['ms']:.1f} ms ({row['fp64']['iters']} it), "
+            f"mixed+learned {row['mixed_learned']['ms']:.1f} ms ({row['mixed_learned']['iters']} it)")
+        out.append(row)
+        g.close()
+        del u, f, u_ex
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +207,7 @@ def main():
                     help="run only the smoother timing loop (for counter profiles)")
     ap.add_argument("--copy-only", action="store_true",
                     help="run one 512 MiB device copy (scale of the byte counters)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the p sweep at 1e7 unknowns")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -242,6 +290,11 @@ def main():
                           f"iterations to 1e-10, coarse CG to {args.coarse_rtol:g}), timed once: {c['t']:.1f} s")}
         log(f"[bench] cpu oracle: {c['t']:.2f} s, {c['iters']} iterations")
 
+    sweep = None
+    if not args.no_sweep:
+        g.close()
+        sweep = p_sweep(torch, pmg, synth, dev, args.coarse_rtol, 1)
+
     line = {
         "metric": "solved unknowns/s to 1e-10 residual vs p; FP32-MG+learned vs plain FP64",
         "value": ndof / t32,
@@ -275,6 +328,7 @@ def main():
                      "fp64": {"kernel": "k_smoother_mfma<double, 2>", "achieved": ach64, "peak": PEAK["f64"],
                               "frac": ach64 / PEAK["f64"], "us_per_launch": ts64 * 1e6}},
         "cpu_baseline": cpu,
+        "p_sweep": sweep,
     }
     print(json.dumps(line), flush=True)
 
