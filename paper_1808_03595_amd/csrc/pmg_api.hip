@@ -161,6 +161,7 @@ int fill_tabs(pmg_mesh* m, LevelTabs<T>& tb, const HostTables& t, const Layout& 
     tb.lay = lay;
     tb.lam = (T)m->lam;
     tb.pc = pc;
+    tb.np = t.np;
     int rc = 0;
     for (int d = 0; d < 3 && !rc; ++d) {
         if ((rc = m->upload(&tb.el_m[d], t.el_m[d]))) break;
@@ -172,10 +173,10 @@ int fill_tabs(pmg_mesh* m, LevelTabs<T>& tb, const HostTables& t, const Layout& 
         if ((rc = m->upload(&tb.el_cp[d], t.el_cp[d]))) break;
         if ((rc = m->upload(&tb.st_S[d], t.st_S[d]))) break;
         if ((rc = m->upload(&tb.st_lam[d], t.st_lam[d]))) break;
-        if ((rc = m->upload(&tb.st_S16[d], t.st_S16[d]))) break;
-        if ((rc = m->upload(&tb.st_lam16[d], t.st_lam16[d]))) break;
+        if ((rc = m->upload(&tb.st_SP[d], t.st_SP[d]))) break;
+        if ((rc = m->upload(&tb.st_lamP[d], t.st_lamP[d]))) break;
     }
-    if (!rc) rc = m->upload(&tb.st_w16, t.st_w16);
+    if (!rc) rc = m->upload(&tb.st_wP, t.st_wP);
     if (!rc) rc = m->upload(&tb.st_w, t.st_w);
     if (!rc) rc = m->upload(&tb.J, t.J);
     return rc;
@@ -293,6 +294,17 @@ int build_level(pmg_mesh* m, Level& L, int p, int pc, const std::vector<double> 
     if ((rc = m->alloc(&ew, ne * 6 * (size_t)(p + 1) * (p + 1)))) return rc;
     L.t64.opE = ew;
     L.t32.opE = reinterpret_cast<float*>(ew);
+    // workspaces of the batched star smoother (n_S > 16)
+    if (2 * p - 1 > 16) {
+        const int np = L.t64.np;
+        const size_t ns = (size_t)(L.lay.n[0] + 1) * (L.lay.n[1] + 1) * (L.lay.n[2] + 1);
+        for (int k = 0; k < 2; ++k) {
+            double* x = nullptr;
+            if ((rc = m->alloc(&x, ns * 3 * (size_t)np * np))) return rc;
+            L.t64.sbX[k] = x;
+            L.t32.sbX[k] = reinterpret_cast<float*>(x);
+        }
+    }
     // device scratch of the general kernels whose working set exceeds the LDS
     {
         const int* n = L.lay.n;
@@ -302,7 +314,7 @@ int build_level(pmg_mesh* m, Level& L, int p, int pc, const std::vector<double> 
         auto over = [](size_t elems) { return elems * sizeof(double) > kLdsBytes; };
         size_t need = 0;
         if (over(ws_condensed_op(p))) need = std::max(need, ne * ws_condensed_op(p));
-        if (over(ws_smoother(p))) need = std::max(need, std::min(nv, col_v) * ws_smoother(p));
+        if (over(ws_smoother(p)) && 2 * p - 1 <= 16) need = std::max(need, std::min(nv, col_v) * ws_smoother(p));
         if (over(ws_condense(p))) need = std::max(need, std::min(ne, col_e) * ws_condense(p));
         if (over(ws_recover(p))) need = std::max(need, ne * ws_recover(p));
         if (need) {

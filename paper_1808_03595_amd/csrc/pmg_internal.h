@@ -61,11 +61,12 @@ struct LevelTabs {
     const T* st_S[3];     // nS^2         [i][k], identity padded
     const T* st_lam[3];   // nS           padded eigenvalues = 1
     const T* st_w;        // nS           1D weights
-    // the same star tables padded to 16 x 16 (zeros; eigenvalue 1; weight 0)
-    // for the matrix-core smoother, present when nS <= 16
-    const T* st_S16[3];   // 256 per vertex
-    const T* st_lam16[3]; // 16 per vertex
-    const T* st_w16;      // 16
+    // the same star tables padded to np x np, np = 16 ceil(nS / 16) (zeros;
+    // eigenvalue 1; weight 0) for the matrix-core smoothers
+    const T* st_SP[3];   // np^2 per vertex
+    const T* st_lamP[3]; // np per vertex
+    const T* st_wP;      // np
+    int np;
     // interpolation from the next coarser level: (p+1) x (pc+1), row-major
     const T* J;
     int pc;
@@ -75,6 +76,8 @@ struct LevelTabs {
     // per-workgroup scratch in device memory for the general kernels when
     // their working set exceeds the LDS of a CU (large p); null otherwise
     T* gws;
+    // two [star][3][np][np] workspaces of the batched star smoother (nS > 16)
+    T* sbX[2];
 };
 
 // Working-set sizes (elements of T) of the general per-element / per-star
@@ -106,7 +109,8 @@ struct HostTables {
     std::vector<double> el_m[3], el_L[3], el_Sinv[3], el_MS[3], el_lam[3],
         el_c0[3], el_cp[3], st_S[3], st_lam[3];
     std::vector<double> st_w, J;
-    std::vector<double> st_S16[3], st_lam16[3], st_w16;
+    std::vector<double> st_SP[3], st_lamP[3], st_wP;
+    int np = 16;
 };
 
 // Host set-up (pmg_setup.cpp)

@@ -897,9 +897,9 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
         bool b1 = v1 == 0 || v1 == L.n[0], b2 = v2 == 0 || v2 == L.n[1], b3 = v3 == 0 || v3 == L.n[2];
         if (b1 && b2 && b3) active = false;  // corner: all three planes Dirichlet
     }
-    const T* S1 = tb.st_S16[0] + (size_t)v1 * 256;
-    const T* S2 = tb.st_S16[1] + (size_t)v2 * 256;
-    const T* S3 = tb.st_S16[2] + (size_t)v3 * 256;
+    const T* S1 = tb.st_SP[0] + (size_t)v1 * 256;
+    const T* S2 = tb.st_SP[1] + (size_t)v2 * 256;
+    const T* S3 = tb.st_SP[2] + (size_t)v3 * 256;
     const int c1 = v1 * p, c2 = v2 * p, c3 = v3 * p;
     // S in both operand patterns: Sb[s] = S[row(q,s)][j], Sa[s] = S[j][row(q,s)]
     T Sb1[4], Sb2[4], Sb3[4], Sa1[4], Sa2[4], Sa3[4];
@@ -952,9 +952,9 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
     T a1[4], a2[4], a3[4], l3[4], E12[4][4], G3r[4][4];
     T H1p[4][4], H2p[4][4], H3p[4][4];
     {
-        const T* L1 = tb.st_lam16[0] + v1 * 16;
-        const T* L2 = tb.st_lam16[1] + v2 * 16;
-        const T* L3 = tb.st_lam16[2] + v3 * 16;
+        const T* L1 = tb.st_lamP[0] + v1 * 16;
+        const T* L2 = tb.st_lamP[1] + v2 * 16;
+        const T* L3 = tb.st_lamP[2] + v3 * 16;
         T l1[4], l2[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -1029,7 +1029,7 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
     v4_to<T>(gemm16<T>(h3, Sa1), t);
     v4 u3 = gemm16<T>(Sa2, t);
     if (!active) return;
-    const T* w = tb.st_w16;
+    const T* w = tb.st_wP;
     const int ob = j - c;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -1051,6 +1051,189 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
             if (i1 >= 0 && i1 < L.N[0] && i2 >= 0 && i2 < L.N[1] && !is_dir(L, i1, i2, i3))
                 unsafeAtomicAdd(du + L.plane2(v3) + (int64_t)i2 * L.pitch[2] + i1, wt * u3[v]);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Star smoother for n_S = 2p - 1 > 16 (p >= 9).  The stars of a level are
+// processed together, one step of Alg. 1 per launch, with the np x np
+// matrices (np = 16 ceil(n_S / 16), zero padded) of every star and face in
+// a device workspace:
+//   k_star_gemm<FWD1>: gather of the three residual windows, F S_C
+//   k_star_gemm<FWD2>: G = S_R^T (F S_C)
+//   k_star_eigen:      H_d = sum_k a_d[k] (a1 G1 + a2 G2 + a3 G3) / D
+//   k_star_gemm<BWD1>: H S_C^T
+//   k_star_gemm<BWD2>: U = S_R (H S_C^T), weights, damping, atomic scatter
+// The four products run on MFMA, one wavefront per 16 x 16 output tile.
+// Face f uses (rows, columns) = (x3, x2), (x3, x1), (x2, x1).
+// ---------------------------------------------------------------------------
+enum { SG_FWD1 = 0, SG_FWD2 = 1, SG_BWD1 = 2, SG_BWD2 = 3 };
+
+__device__ inline bool star_vertex(const Layout& L, int s, int& v1, int& v2, int& v3) {
+    const int nv1 = L.n[0] + 1, nv2 = L.n[1] + 1;
+    v1 = s % nv1;
+    v2 = (s / nv1) % nv2;
+    v3 = s / (nv1 * nv2);
+    const bool b1 = v1 == 0 || v1 == L.n[0], b2 = v2 == 0 || v2 == L.n[1], b3 = v3 == 0 || v3 == L.n[2];
+    return !(b1 && b2 && b3);  // corner stars (all three planes Dirichlet) are empty
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(64) k_star_gemm(LevelTabs<T> tb, const T* __restrict__ r, const T* __restrict__ X,
+                                                  T* __restrict__ Y, T* __restrict__ du, T omega) {
+    typedef Mfma<T> M;
+    const Layout& L = tb.lay;
+    const int s = blockIdx.x, f = blockIdx.z;
+    int v1, v2, v3;
+    if (!star_vertex(L, s, v1, v2, v3)) return;
+    const int np = tb.np, nt = np / 16, nS = 2 * L.p - 1, c = L.p - 1;
+    const int tr = blockIdx.y / nt, tc = blockIdx.y - tr * nt;
+    const int lane = threadIdx.x, q = lane >> 4, j = lane & 15;
+    const int dR = f == 2 ? 1 : 2, dC = f == 0 ? 1 : 0;
+    const int vR = dR == 1 ? v2 : v3, vC = dC == 1 ? v2 : v1;
+    const T* SR = pick3(dR, tb.st_SP[0], tb.st_SP[1], tb.st_SP[2]) + (size_t)vR * np * np;
+    const T* SC = pick3(dC, tb.st_SP[0], tb.st_SP[1], tb.st_SP[2]) + (size_t)vC * np * np;
+    const size_t mo = ((size_t)s * 3 + f) * np * np;
+    const int row0 = tr * 16, col0 = tc * 16;
+    const int c1 = v1 * L.p, c2 = v2 * L.p, c3 = v3 * L.p;
+    // FWD1: the residual window of face f, row a = row0 + j
+    int64_t wbase = 0, wpitch = 0;
+    bool rowok = false;
+    int lo = 0, hi = 0;   // admissible column offsets b - c with the node inside the domain
+    if (MODE == SG_FWD1) {
+        const int a = row0 + j, oa = a - c;
+        int ir, nr, ncol, cbase;
+        if (f == 0) { ir = c3 + oa; nr = L.N[2]; ncol = L.N[1]; cbase = c2; wbase = L.plane0(v1); wpitch = L.pitch[0]; }
+        else if (f == 1) { ir = c3 + oa; nr = L.N[2]; ncol = L.N[0]; cbase = c1; wbase = L.plane1(v2); wpitch = L.pitch[1]; }
+        else { ir = c2 + oa; nr = L.N[1]; ncol = L.N[0]; cbase = c1; wbase = L.plane2(v3); wpitch = L.pitch[2]; }
+        rowok = a < nS && ir >= 0 && ir < nr;
+        wbase += (int64_t)ir * wpitch + cbase - c;   // + b gives the slot of column offset b - c
+        lo = c - cbase;                              // b >= lo keeps the column index >= 0
+        hi = ncol - 1 - cbase + c;                   // b <= hi keeps it < ncol
+    }
+    const T* Xm = X + mo;
+    typename M::v4 acc = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < np; k0 += 4) {
+        const int k = k0 + q;
+        T a, b;
+        if (MODE == SG_FWD1) {
+            a = (rowok && k < nS && k >= lo && k <= hi) ? r[wbase + k] : (T)0;
+            b = SC[k * np + col0 + j];
+        } else if (MODE == SG_FWD2) {
+            a = SR[k * np + row0 + j];
+            b = Xm[k * np + col0 + j];
+        } else if (MODE == SG_BWD1) {
+            a = Xm[(row0 + j) * np + k];
+            b = SC[(col0 + j) * np + k];
+        } else {
+            a = SR[(row0 + j) * np + k];
+            b = Xm[k * np + col0 + j];
+        }
+        acc = M::mma(a, b, acc);
+    }
+    if (MODE != SG_BWD2) {
+        T* Ym = Y + mo;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Ym[(row0 + M::row(q, v)) * np + col0 + j] = acc[v];
+        return;
+    }
+    const T* w = tb.st_wP;
+    const int bcol = col0 + j, ob = bcol - c;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int a = row0 + M::row(q, v), oa = a - c;
+        if (a >= nS || bcol >= nS) continue;
+        const T val = omega * w[a] * w[bcol] * acc[v];
+        int i1, i2, i3;
+        int64_t slot;
+        if (f == 0) {
+            i1 = c1; i2 = c2 + ob; i3 = c3 + oa;
+            slot = L.plane0(v1) + (int64_t)i3 * L.pitch[0] + i2;
+        } else if (f == 1) {
+            if (ob == 0) continue;   // x3-axis line: stored in family 0
+            i1 = c1 + ob; i2 = c2; i3 = c3 + oa;
+            slot = L.plane1(v2) + (int64_t)i3 * L.pitch[1] + i1;
+        } else {
+            if (ob == 0 || oa == 0) continue;   // axis lines: stored in families 0 and 1
+            i1 = c1 + ob; i2 = c2 + oa; i3 = c3;
+            slot = L.plane2(v3) + (int64_t)i2 * L.pitch[2] + i1;
+        }
+        if (i1 < 0 || i1 >= L.N[0] || i2 < 0 || i2 >= L.N[1] || i3 < 0 || i3 >= L.N[2] || is_dir(L, i1, i2, i3))
+            continue;
+        unsafeAtomicAdd(du + slot, val);
+    }
+}
+
+// Eigenspace pass of one star: H1[k3][k2] = sum_k1 a1 V, H2[k3][k1] =
+// sum_k2 a2 V, H3[k2][k1] = sum_k3 a3 V with V = (a1 G1[k3][k2] + a2
+// G2[k3][k1] + a3 G3[k2][k1]) / (lambda + l1 + l2 + l3), a_d = row c of S_d.
+// G staged in LDS when it fits (sm_elems > 0), else read from the workspace.
+template <typename T>
+__global__ void __launch_bounds__(256) k_star_eigen(LevelTabs<T> tb, const T* __restrict__ G, T* __restrict__ H,
+                                                    int stage) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    typedef Mfma<T> M;
+    const Layout& L = tb.lay;
+    const int s = blockIdx.x;
+    int v1, v2, v3;
+    if (!star_vertex(L, s, v1, v2, v3)) return;
+    const int np = tb.np, n2 = np * np, nS = 2 * L.p - 1, c = L.p - 1;
+    const T* Gs = G + (size_t)s * 3 * n2;
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    // a_d (row c of S_d) and l_d, then G if staged
+    T* A = sm;            // 3 np
+    T* Lm = A + 3 * np;   // 3 np
+    for (int i = threadIdx.x; i < 3 * np; i += blockDim.x) {
+        const int d = i / np, k = i - d * np;
+        const int vd = d == 0 ? v1 : (d == 1 ? v2 : v3);
+        A[i] = pick3(d, tb.st_SP[0], tb.st_SP[1], tb.st_SP[2])[((size_t)vd * np + c) * np + k];
+        Lm[i] = pick3(d, tb.st_lamP[0], tb.st_lamP[1], tb.st_lamP[2])[(size_t)vd * np + k];
+    }
+    const T* Gl = Gs;
+    if (stage) {
+        T* Gd = Lm + 3 * np;
+        for (int i = threadIdx.x; i < 3 * n2; i += blockDim.x) Gd[i] = Gs[i];
+        Gl = Gd;
+    }
+    __syncthreads();
+    const T* a1 = A;
+    const T* a2 = A + np;
+    const T* a3 = A + 2 * np;
+    const T* l1 = Lm;
+    const T* l2 = Lm + np;
+    const T* l3 = Lm + 2 * np;
+    const T* G1 = Gl;
+    const T* G2 = Gl + n2;
+    const T* G3 = Gl + 2 * n2;
+    T* Hs = H + (size_t)s * 3 * n2;
+    for (int i = threadIdx.x; i < 3 * n2; i += blockDim.x) {
+        const int d = i / n2, rc = i - d * n2, rr = rc / np, cc = rc - rr * np;
+        T acc = 0;
+        if (rr < nS && cc < nS) {
+            if (d == 0) {         // (rr, cc) = (k3, k2), sum over k1
+                const T g1 = G1[rr * np + cc], e0 = tb.lam + l2[cc] + l3[rr];
+                const T b2 = a2[cc], b3 = a3[rr];
+                for (int k = 0; k < nS; ++k) {
+                    const T e = a1[k] * g1 + b2 * G2[rr * np + k] + b3 * G3[cc * np + k];
+                    acc += a1[k] * (e * M::rcp(e0 + l1[k]));
+                }
+            } else if (d == 1) {  // (rr, cc) = (k3, k1), sum over k2
+                const T g2 = G2[rr * np + cc], e0 = tb.lam + l1[cc] + l3[rr];
+                const T b1 = a1[cc], b3 = a3[rr];
+                for (int k = 0; k < nS; ++k) {
+                    const T e = b1 * G1[rr * np + k] + a2[k] * g2 + b3 * G3[k * np + cc];
+                    acc += a2[k] * (e * M::rcp(e0 + l2[k]));
+                }
+            } else {              // (rr, cc) = (k2, k1), sum over k3
+                const T g3 = G3[rr * np + cc], e0 = tb.lam + l1[cc] + l2[rr];
+                const T b1 = a1[cc], b2 = a2[rr];
+                for (int k = 0; k < nS; ++k) {
+                    const T e = b1 * G1[k * np + rr] + b2 * G2[k * np + cc] + a3[k] * g3;
+                    acc += a3[k] * (e * M::rcp(e0 + l3[k]));
+                }
+            }
+        }
+        Hs[i] = acc;
     }
 }
 
@@ -2126,6 +2309,22 @@ void launch_smoother_add(const LevelTabs<T>& tb, const T* r, T* du, T omega, hip
                            dim3(64 * MFMA_WPB), smm, st, tb, r, du, omega);
         return;
     }
+    if (2 * tb.lay.p - 1 > 16 && tb.sbX[0]) {
+        const Layout& L = tb.lay;
+        const int ns = (L.n[0] + 1) * (L.n[1] + 1) * (L.n[2] + 1), nt = tb.np / 16;
+        const dim3 g(ns, nt * nt, 3);
+        T* X0 = tb.sbX[0];
+        T* X1 = tb.sbX[1];
+        hipLaunchKernelGGL((k_star_gemm<T, SG_FWD1>), g, dim3(64), 0, st, tb, r, (const T*)nullptr, X1, (T*)nullptr, omega);
+        hipLaunchKernelGGL((k_star_gemm<T, SG_FWD2>), g, dim3(64), 0, st, tb, r, (const T*)X1, X0, (T*)nullptr, omega);
+        const size_t full = sizeof(T) * (6 * (size_t)tb.np + 3 * (size_t)tb.np * tb.np);
+        const int stage = full <= kLdsBytes;
+        hipLaunchKernelGGL(k_star_eigen<T>, dim3(ns), dim3(256), stage ? full : sizeof(T) * 6 * tb.np, st, tb,
+                           (const T*)X0, X1, stage);
+        hipLaunchKernelGGL((k_star_gemm<T, SG_BWD1>), g, dim3(64), 0, st, tb, r, (const T*)X1, X0, (T*)nullptr, omega);
+        hipLaunchKernelGGL((k_star_gemm<T, SG_BWD2>), g, dim3(64), 0, st, tb, r, (const T*)X0, (T*)nullptr, du, omega);
+        return;
+    }
     LevelTabs<T> t = tb;
     const size_t sm = pick_ws(t, ws_smoother(tb.lay.p));
     int nv[3] = {tb.lay.n[0] + 1, tb.lay.n[1] + 1, tb.lay.n[2] + 1};
@@ -2289,7 +2488,8 @@ hipError_t init_kernel_attributes() {
         (const void*)k_prolong_add<double>,  (const void*)k_prolong_add<float>,
         (const void*)k_restrict_planes<double>, (const void*)k_restrict_planes<float>,
         (const void*)k_condense,             (const void*)k_recover,
-        (const void*)k_smoother_mfma<double, MFMA_WPB>, (const void*)k_smoother_mfma<float, MFMA_WPB>};
+        (const void*)k_smoother_mfma<double, MFMA_WPB>, (const void*)k_smoother_mfma<float, MFMA_WPB>,
+        (const void*)k_star_eigen<double>, (const void*)k_star_eigen<float>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;

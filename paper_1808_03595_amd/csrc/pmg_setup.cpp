@@ -279,23 +279,22 @@ void build_level_tables(int p, int pc, const std::vector<double> h[3], HostTable
     // weights at offsets -(p-1)..(p-1): t = (1 - x_|j|) / 2
     t.st_w.resize(nS);
     for (int j = -(p - 1); j <= p - 1; ++j) t.st_w[j + p - 1] = smoothstep(7, (1.0 - x[std::abs(j)]) / 2.0);
-    // 16-padded copies for the matrix-core smoother
+    // copies padded to np = 16 ceil(nS / 16) for the matrix-core smoothers
+    const int np = 16 * ((nS + 15) / 16);
+    t.np = np;
     for (int d = 0; d < 3; ++d) {
-        t.st_S16[d].clear();
-        t.st_lam16[d].clear();
-        if (nS > 16) continue;
         const int nv = (int)h[d].size() + 1;
-        t.st_S16[d].assign((size_t)nv * 256, 0.0);
-        t.st_lam16[d].assign((size_t)nv * 16, 1.0);
+        t.st_SP[d].assign((size_t)nv * np * np, 0.0);
+        t.st_lamP[d].assign((size_t)nv * np, 1.0);
         for (int v = 0; v < nv; ++v)
             for (int i = 0; i < nS; ++i) {
-                t.st_lam16[d][v * 16 + i] = t.st_lam[d][v * nS + i];
-                for (int k = 0; k < nS; ++k) t.st_S16[d][v * 256 + i * 16 + k] = t.st_S[d][(size_t)v * nS * nS + i * nS + k];
+                t.st_lamP[d][(size_t)v * np + i] = t.st_lam[d][(size_t)v * nS + i];
+                for (int k = 0; k < nS; ++k)
+                    t.st_SP[d][((size_t)v * np + i) * np + k] = t.st_S[d][(size_t)v * nS * nS + i * nS + k];
             }
     }
-    t.st_w16.assign(16, 0.0);
-    if (nS <= 16)
-        for (int i = 0; i < nS; ++i) t.st_w16[i] = t.st_w[i];
+    t.st_wP.assign(np, 0.0);
+    for (int i = 0; i < nS; ++i) t.st_wP[i] = t.st_w[i];
     t.J.clear();
     if (pc > 0) {
         std::vector<double> xc, wc;
