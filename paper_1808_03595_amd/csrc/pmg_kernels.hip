@@ -155,7 +155,16 @@ __device__ inline int tile_cdir(int d) { return d == 0 ? 1 : 0; }
 // ---------------------------------------------------------------------------
 template <typename T>
 struct ElemPtrs {
-    const T *m[3], *L[3], *Si[3], *MS[3], *lm[3], *c0[3], *cp[3];
+    // members indexed only with constants; the accessors pick by selects so
+    // that a runtime direction does not move the struct to private memory
+    const T *m_[3], *L_[3], *Si_[3], *MS_[3], *lm_[3], *c0_[3], *cp_[3];
+    __device__ const T* m(int d) const { return pick3(d, m_[0], m_[1], m_[2]); }
+    __device__ const T* L(int d) const { return pick3(d, L_[0], L_[1], L_[2]); }
+    __device__ const T* Si(int d) const { return pick3(d, Si_[0], Si_[1], Si_[2]); }
+    __device__ const T* MS(int d) const { return pick3(d, MS_[0], MS_[1], MS_[2]); }
+    __device__ const T* lm(int d) const { return pick3(d, lm_[0], lm_[1], lm_[2]); }
+    __device__ const T* c0(int d) const { return pick3(d, c0_[0], c0_[1], c0_[2]); }
+    __device__ const T* cp(int d) const { return pick3(d, cp_[0], cp_[1], cp_[2]); }
 };
 
 template <typename T>
@@ -163,13 +172,13 @@ __device__ inline ElemPtrs<T> elem_ptrs(const LevelTabs<T>& tb, const int e[3]) 
     const int p = tb.lay.p, n1 = p + 1, q = p - 1;
     ElemPtrs<T> P;
     for (int d = 0; d < 3; ++d) {
-        P.m[d] = tb.el_m[d] + e[d] * n1;
-        P.L[d] = tb.el_L[d] + e[d] * n1 * n1;
-        P.Si[d] = tb.el_Sinv[d] + e[d] * q * q;
-        P.MS[d] = tb.el_MS[d] + e[d] * q * q;
-        P.lm[d] = tb.el_lam[d] + e[d] * q;
-        P.c0[d] = tb.el_c0[d] + e[d] * q;
-        P.cp[d] = tb.el_cp[d] + e[d] * q;
+        P.m_[d] = tb.el_m[d] + e[d] * n1;
+        P.L_[d] = tb.el_L[d] + e[d] * n1 * n1;
+        P.Si_[d] = tb.el_Sinv[d] + e[d] * q * q;
+        P.MS_[d] = tb.el_MS[d] + e[d] * q * q;
+        P.lm_[d] = tb.el_lam[d] + e[d] * q;
+        P.c0_[d] = tb.el_c0[d] + e[d] * q;
+        P.cp_[d] = tb.el_cp[d] + e[d] * q;
     }
     return P;
 }
@@ -181,7 +190,7 @@ __device__ void faces_to_eigen(const ElemPtrs<T>& P, int p, const T* src, bool s
     const int q = p - 1, q2 = q * q, n1 = p + 1;
     for (int i = threadIdx.x; i < 6 * q2; i += blockDim.x) {
         int f = i / q2, rc = i - f * q2, r = rc / q, kc = rc - r * q;
-        const T* Sc = P.Si[tile_cdir(f >> 1)];
+        const T* Sc = P.Si(tile_cdir(f >> 1));
         T s = 0;
         if (src_q) {
             const T* X = src + f * q2 + r * q;
@@ -195,7 +204,7 @@ __device__ void faces_to_eigen(const ElemPtrs<T>& P, int p, const T* src, bool s
     __syncthreads();
     for (int i = threadIdx.x; i < 6 * q2; i += blockDim.x) {
         int f = i / q2, rc = i - f * q2, kr = rc / q, kc = rc - kr * q;
-        const T* Sr = P.Si[tile_rdir(f >> 1)];
+        const T* Sr = P.Si(tile_rdir(f >> 1));
         const T* X = tmp + f * q2;
         T s = 0;
         for (int r = 0; r < q; ++r) s += Sr[kr * q + r] * X[r * q + kc];
@@ -208,9 +217,9 @@ __device__ void faces_to_eigen(const ElemPtrs<T>& P, int p, const T* src, bool s
 template <typename T>
 __device__ inline T expand(const ElemPtrs<T>& P, const T* G, int q, int k1, int k2, int k3) {
     const int q2 = q * q;
-    return P.c0[0][k1] * G[0 * q2 + k3 * q + k2] + P.cp[0][k1] * G[1 * q2 + k3 * q + k2] +
-           P.c0[1][k2] * G[2 * q2 + k3 * q + k1] + P.cp[1][k2] * G[3 * q2 + k3 * q + k1] +
-           P.c0[2][k3] * G[4 * q2 + k2 * q + k1] + P.cp[2][k3] * G[5 * q2 + k2 * q + k1];
+    return P.c0(0)[k1] * G[0 * q2 + k3 * q + k2] + P.cp(0)[k1] * G[1 * q2 + k3 * q + k2] +
+           P.c0(1)[k2] * G[2 * q2 + k3 * q + k1] + P.cp(1)[k2] * G[3 * q2 + k3 * q + k1] +
+           P.c0(2)[k3] * G[4 * q2 + k2 * q + k1] + P.cp(2)[k3] * G[5 * q2 + k2 * q + k1];
 }
 
 // Contractions Tc_f = sum_{k_d} c_{d,s}[k_d] V with V = (expansion + extra) / D.
@@ -229,9 +238,9 @@ __device__ void eigen_contract(const ElemPtrs<T>& P, int p, T lam, const T* G, c
             else { k2 = r; k1 = c; k3 = k; }
             T v = expand(P, G, q, k1, k2, k3);
             if (extra) v = extra[(k3 * q + k2) * q + k1] + sign_extra * v;
-            v = v / (lam + P.lm[0][k1] + P.lm[1][k2] + P.lm[2][k3]);
-            s0 += P.c0[d][k] * v;
-            sp += P.cp[d][k] * v;
+            v = v / (lam + P.lm(0)[k1] + P.lm(1)[k2] + P.lm(2)[k3]);
+            s0 += P.c0(d)[k] * v;
+            sp += P.cp(d)[k] * v;
         }
         Tc[(2 * d) * q2 + rc] = s0;
         Tc[(2 * d + 1) * q2 + rc] = sp;
@@ -245,7 +254,7 @@ __device__ void eigen_to_faces(const ElemPtrs<T>& P, int p, const T* Tc, T* tmp,
     const int q = p - 1, q2 = q * q;
     for (int i = threadIdx.x; i < 6 * q2; i += blockDim.x) {
         int f = i / q2, rc = i - f * q2, kr = rc / q, c = rc - kr * q;
-        const T* Mc = P.MS[tile_cdir(f >> 1)];
+        const T* Mc = P.MS(tile_cdir(f >> 1));
         const T* X = Tc + f * q2 + kr * q;
         T s = 0;
         for (int kc = 0; kc < q; ++kc) s += X[kc] * Mc[c * q + kc];
@@ -254,7 +263,7 @@ __device__ void eigen_to_faces(const ElemPtrs<T>& P, int p, const T* Tc, T* tmp,
     __syncthreads();
     for (int i = threadIdx.x; i < 6 * q2; i += blockDim.x) {
         int f = i / q2, rc = i - f * q2, r = rc / q, c = rc - r * q;
-        const T* Mr = P.MS[tile_rdir(f >> 1)];
+        const T* Mr = P.MS(tile_rdir(f >> 1));
         const T* X = tmp + f * q2;
         T s = 0;
         for (int kr = 0; kr < q; ++kr) s += Mr[r * q + kr] * X[kr * q + c];
@@ -269,11 +278,11 @@ __device__ inline T hbb_at(const ElemPtrs<T>& P, int p, T lam, const T* tile, in
     const int n1 = p + 1;
     T x1 = 0, x2 = 0, x3 = 0;
     for (int j = 0; j <= p; ++j) {
-        x1 += P.L[0][a1 * n1 + j] * shell_value(tile, p, j, a2, a3);
-        x2 += P.L[1][a2 * n1 + j] * shell_value(tile, p, a1, j, a3);
-        x3 += P.L[2][a3 * n1 + j] * shell_value(tile, p, a1, a2, j);
+        x1 += P.L(0)[a1 * n1 + j] * shell_value(tile, p, j, a2, a3);
+        x2 += P.L(1)[a2 * n1 + j] * shell_value(tile, p, a1, j, a3);
+        x3 += P.L(2)[a3 * n1 + j] * shell_value(tile, p, a1, a2, j);
     }
-    const T m1 = P.m[0][a1], m2 = P.m[1][a2], m3 = P.m[2][a3];
+    const T m1 = P.m(0)[a1], m2 = P.m(1)[a2], m3 = P.m(2)[a3];
     return lam * m1 * m2 * m3 * shell_value(tile, p, a1, a2, a3) + m3 * m2 * x1 + m3 * m1 * x2 +
            m2 * m1 * x3;
 }
@@ -289,8 +298,8 @@ __device__ ElemPtrs<T> stage_elem_tables(const LevelTabs<T>& tb, const int e[3],
     const int sizes[7] = {n1, n1 * n1, q * q, q * q, q, q, q};
     T* o = dst;
     for (int d = 0; d < 3; ++d) {
-        const T* s[7] = {src.m[d], src.L[d], src.Si[d], src.MS[d], src.lm[d], src.c0[d], src.cp[d]};
-        const T** ptrs[7] = {&P.m[d], &P.L[d], &P.Si[d], &P.MS[d], &P.lm[d], &P.c0[d], &P.cp[d]};
+        const T* s[7] = {src.m_[d], src.L_[d], src.Si_[d], src.MS_[d], src.lm_[d], src.c0_[d], src.cp_[d]};
+        const T** ptrs[7] = {&P.m_[d], &P.L_[d], &P.Si_[d], &P.MS_[d], &P.lm_[d], &P.c0_[d], &P.cp_[d]};
         for (int t = 0; t < 7; ++t) {
             for (int i = threadIdx.x; i < sizes[t]; i += blockDim.x) o[i] = s[t][i];
             *ptrs[t] = o;
@@ -405,7 +414,7 @@ __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Condensed operator, one wavefront per element, compile-time degree P <= 8.
+// Condensed operator, one wavefront per element, compile-time degree P <= 16.
 // Same arithmetic as k_condensed_op, organised so that every stage keeps a
 // row or a line of its operand in registers: the two 2D transforms of each
 // face interior, the eigenspace expansion V = D^-1 sum_f c_f (x) G_f (one
@@ -488,22 +497,21 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
     for (int k = 0; k < NU; ++k)
         if (lane + 64 * k < 6 * t2) tile[lane + 64 * k] = uv[k];
     __syncthreads();
-    ElemPtrs<T> Pt;
-    for (int d = 0; d < 3; ++d) {
-        const T* b = tabs + d * K::tab_d;
-        Pt.m[d] = b;
-        Pt.L[d] = b + n1;
-        Pt.Si[d] = b + n1 + n1 * n1;
-        Pt.MS[d] = Pt.Si[d] + q2;
-        Pt.lm[d] = Pt.MS[d] + q2;
-        Pt.c0[d] = Pt.lm[d] + q;
-        Pt.cp[d] = Pt.c0[d] + q;
-    }
+    // table of direction d (runtime d: offsets, not a pointer array, so
+    // nothing is placed in private memory)
+    constexpr int TD = K::tab_d;
+    auto Tm = [&](int d) { return tabs + d * TD; };
+    auto TL = [&](int d) { return tabs + d * TD + n1; };
+    auto TSi = [&](int d) { return tabs + d * TD + n1 + n1 * n1; };
+    auto TMS = [&](int d) { return tabs + d * TD + n1 + n1 * n1 + q2; };
+    auto Tlm = [&](int d) { return tabs + d * TD + n1 + n1 * n1 + 2 * q2; };
+    auto Tc0 = [&](int d) { return tabs + d * TD + n1 + n1 * n1 + 2 * q2 + q; };
+    auto Tcp = [&](int d) { return tabs + d * TD + n1 + n1 * n1 + 2 * q2 + 2 * q; };
     if (q > 0) {
         // tmp_f = X_f Si_C^T (lane: face f, row r)
-        if (lane < 6 * q) {
-            const int f = lane / q, r = lane - f * q;
-            const T* Sc = Pt.Si[tile_cdir(f >> 1)];
+        for (int ii = lane; ii < 6 * q; ii += 64) {
+            const int f = ii / q, r = ii - f * q;
+            const T* Sc = TSi(tile_cdir(f >> 1));
             T x[q > 0 ? q : 1];
 #pragma unroll
             for (int c = 0; c < q; ++c) x[c] = tile[f * t2 + (r + 1) * n1 + c + 1];
@@ -517,9 +525,9 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
         }
         __syncthreads();
         // G_f = Si_R tmp_f (lane: face f, column kc)
-        if (lane < 6 * q) {
-            const int f = lane / q, kc = lane - f * q;
-            const T* Sr = Pt.Si[tile_rdir(f >> 1)];
+        for (int ii = lane; ii < 6 * q; ii += 64) {
+            const int f = ii / q, kc = ii - f * q;
+            const T* Sr = TSi(tile_rdir(f >> 1));
             T x[q > 0 ? q : 1];
 #pragma unroll
             for (int r = 0; r < q; ++r) x[r] = tmp[f * q2 + r * q + kc];
@@ -533,20 +541,20 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
         }
         __syncthreads();
         // V over the (k2, k3) line of lane; x1-contractions on the fly
-        if (lane < q2) {
-            const int k3 = lane / q, k2 = lane - k3 * q;
+        for (int ii = lane; ii < q2; ii += 64) {
+            const int k3 = ii / q, k2 = ii - k3 * q;
             const T g0 = G[0 * q2 + k3 * q + k2], g1 = G[1 * q2 + k3 * q + k2];
-            const T a1 = Pt.c0[1][k2], b1 = Pt.cp[1][k2], a2 = Pt.c0[2][k3], b2 = Pt.cp[2][k3];
-            const T dd = lam + Pt.lm[1][k2] + Pt.lm[2][k3];
+            const T a1 = Tc0(1)[k2], b1 = Tcp(1)[k2], a2 = Tc0(2)[k3], b2 = Tcp(2)[k3];
+            const T dd = lam + Tlm(1)[k2] + Tlm(2)[k3];
             T s0 = 0, sp = 0;
 #pragma unroll
             for (int k1 = 0; k1 < q; ++k1) {
-                T v = Pt.c0[0][k1] * g0 + Pt.cp[0][k1] * g1 + a1 * G[2 * q2 + k3 * q + k1] +
+                T v = Tc0(0)[k1] * g0 + Tcp(0)[k1] * g1 + a1 * G[2 * q2 + k3 * q + k1] +
                       b1 * G[3 * q2 + k3 * q + k1] + a2 * G[4 * q2 + k2 * q + k1] + b2 * G[5 * q2 + k2 * q + k1];
-                v = v / (dd + Pt.lm[0][k1]);
+                v = v / (dd + Tlm(0)[k1]);
                 V[(k3 * q + k2) * q + k1] = v;
-                s0 += Pt.c0[0][k1] * v;
-                sp += Pt.cp[0][k1] * v;
+                s0 += Tc0(0)[k1] * v;
+                sp += Tcp(0)[k1] * v;
             }
             Tc[0 * q2 + k3 * q + k2] = s0;
             Tc[1 * q2 + k3 * q + k2] = sp;
@@ -560,15 +568,15 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
 #pragma unroll
                 for (int k = 0; k < q; ++k) {
                     const T v = V[(r * q + k) * q + c];
-                    s0 += Pt.c0[1][k] * v;
-                    sp += Pt.cp[1][k] * v;
+                    s0 += Tc0(1)[k] * v;
+                    sp += Tcp(1)[k] * v;
                 }
             } else {                // d = 2: (r, c) = (k2, k1), sum over k3
 #pragma unroll
                 for (int k = 0; k < q; ++k) {
                     const T v = V[(k * q + r) * q + c];
-                    s0 += Pt.c0[2][k] * v;
-                    sp += Pt.cp[2][k] * v;
+                    s0 += Tc0(2)[k] * v;
+                    sp += Tcp(2)[k] * v;
                 }
             }
             Tc[(2 + 2 * dm) * q2 + rc] = s0;
@@ -576,9 +584,9 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
         }
         __syncthreads();
         // tmp_f = Tc_f MS_C^T (lane: face f, row kr)
-        if (lane < 6 * q) {
-            const int f = lane / q, kr = lane - f * q;
-            const T* Mc = Pt.MS[tile_cdir(f >> 1)];
+        for (int ii = lane; ii < 6 * q; ii += 64) {
+            const int f = ii / q, kr = ii - f * q;
+            const T* Mc = TMS(tile_cdir(f >> 1));
             T x[q > 0 ? q : 1];
 #pragma unroll
             for (int kc = 0; kc < q; ++kc) x[kc] = Tc[f * q2 + kr * q + kc];
@@ -592,9 +600,9 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
         }
         __syncthreads();
         // corr_f = MS_R tmp_f, stored in G (lane: face f, column c)
-        if (lane < 6 * q) {
-            const int f = lane / q, c = lane - f * q;
-            const T* Mr = Pt.MS[tile_rdir(f >> 1)];
+        for (int ii = lane; ii < 6 * q; ii += 64) {
+            const int f = ii / q, c = ii - f * q;
+            const T* Mr = TMS(tile_rdir(f >> 1));
             T x[q > 0 ? q : 1];
 #pragma unroll
             for (int kr = 0; kr < q; ++kr) x[kr] = tmp[f * q2 + kr * q + c];
@@ -610,14 +618,14 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
     }
     // face-interior nodes (lane: face f, row r): in-face lines stay in the
     // tile, the normal line meets the shell only at the two opposite faces
-    if (lane < 6 * q) {
-        const int f = lane / q, r = lane - f * q + 1, d = f >> 1, s = f & 1;
+    for (int ii = lane; ii < 6 * q; ii += 64) {
+        const int f = ii / q, r = ii - f * q + 1, d = f >> 1, s = f & 1;
         {
             const int dr = tile_rdir(d), dc = tile_cdir(d);
-            const T* Lr = Pt.L[dr] + r * n1;
-            const T* Lc = Pt.L[dc];
-            const T* Ln = Pt.L[d] + (s ? P : 0) * n1;
-            const T md = Pt.m[d][s ? P : 0], mr = Pt.m[dr][r];
+            const T* Lr = TL(dr) + r * n1;
+            const T* Lc = TL(dc);
+            const T* Ln = TL(d) + (s ? P : 0) * n1;
+            const T md = Tm(d)[s ? P : 0], mr = Tm(dr)[r];
             const T* trow = tile + f * t2 + r * n1;
             const T* t0 = tile + (2 * d) * t2 + r * n1;
             const T* t1 = tile + (2 * d + 1) * t2 + r * n1;
@@ -631,7 +639,7 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
                     xr += Lr[j] * tile[f * t2 + j * n1 + c];
                     xc += Lc[c * n1 + j] * row[j];
                 }
-                const T mc = Pt.m[dc][c];
+                const T mc = Tm(dc)[c];
                 T v = lam * md * mr * mc * row[c] + md * mc * xr + md * mr * xc +
                       mr * mc * (Ln[0] * t0[c] + Ln[P] * t1[c]);
                 v -= G[f * q2 + (r - 1) * q + (c - 1)];
@@ -658,8 +666,9 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
             r = t < P - 1 ? 0 : P;
             c = 1 + (t < P - 1 ? t : t - (P - 1));
         }
-        int a[3];
-        tile_node(P, f, r, c, a[0], a[1], a[2]);
+        int A0, A1, A2;
+        tile_node(P, f, r, c, A0, A1, A2);
+        auto av = [&](int d) { return d == 0 ? A0 : (d == 1 ? A1 : A2); };
         // every line through an edge or vertex node lies in a face tile:
         // take the face normal to the first other direction whose local
         // coordinate is 0 or P, and walk its row or column
@@ -667,20 +676,19 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
-            const int dn = (a[o1] == 0 || a[o1] == P) ? o1 : o2;
-            const int ft = 2 * dn + (a[dn] == P ? 1 : 0);
+            const int dn = (av(o1) == 0 || av(o1) == P) ? o1 : o2;
+            const int ft = 2 * dn + (av(dn) == P ? 1 : 0);
             const int rd = tile_rdir(dn), cd = tile_cdir(dn);
             int base, stride;
-            if (d == rd) { base = ft * t2 + a[cd]; stride = n1; }
-            else { base = ft * t2 + a[rd] * n1; stride = 1; }
-            (void)cd;
-            const T* Ld = Pt.L[d] + a[d] * n1;
+            if (d == rd) { base = ft * t2 + av(cd); stride = n1; }
+            else { base = ft * t2 + av(rd) * n1; stride = 1; }
+            const T* Ld = TL(d) + av(d) * n1;
             T x = 0;
 #pragma unroll
             for (int j = 0; j < n1; ++j) x += Ld[j] * tile[base + j * stride];
-            acc += Pt.m[o1][a[o1]] * Pt.m[o2][a[o2]] * x;
+            acc += Tm(o1)[av(o1)] * Tm(o2)[av(o2)] * x;
         }
-        out[f * t2 + r * n1 + c] = lam * Pt.m[0][a[0]] * Pt.m[1][a[1]] * Pt.m[2][a[2]] * tile[f * t2 + r * n1 + c] + acc;
+        out[f * t2 + r * n1 + c] = lam * Tm(0)[A0] * Tm(1)[A1] * Tm(2)[A2] * tile[f * t2 + r * n1 + c] + acc;
     }
 }
 
@@ -1508,21 +1516,21 @@ __device__ void interior_forward(const ElemPtrs<T>& P, int q, T* a, T* b) {
     for (int i = threadIdx.x; i < q3; i += blockDim.x) {
         int i1 = i % q, r = i / q;
         T s = 0;
-        for (int j = 0; j < q; ++j) s += P.Si[0][i1 * q + j] / P.m[0][j + 1] * a[r * q + j];
+        for (int j = 0; j < q; ++j) s += P.Si(0)[i1 * q + j] / P.m(0)[j + 1] * a[r * q + j];
         b[i] = s;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < q3; i += blockDim.x) {
         int k1 = i % q, k2 = (i / q) % q, k3 = i / (q * q);
         T s = 0;
-        for (int j = 0; j < q; ++j) s += P.Si[1][k2 * q + j] / P.m[1][j + 1] * b[(k3 * q + j) * q + k1];
+        for (int j = 0; j < q; ++j) s += P.Si(1)[k2 * q + j] / P.m(1)[j + 1] * b[(k3 * q + j) * q + k1];
         a[i] = s;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < q3; i += blockDim.x) {
         int k12 = i % (q * q), k3 = i / (q * q);
         T s = 0;
-        for (int j = 0; j < q; ++j) s += P.Si[2][k3 * q + j] / P.m[2][j + 1] * a[j * q * q + k12];
+        for (int j = 0; j < q; ++j) s += P.Si(2)[k3 * q + j] / P.m(2)[j + 1] * a[j * q * q + k12];
         b[i] = s;
     }
     __syncthreads();
@@ -1537,21 +1545,21 @@ __device__ void interior_backward(const ElemPtrs<T>& P, int q, T* a, T* b) {
     for (int i = threadIdx.x; i < q3; i += blockDim.x) {
         int i1 = i % q, r = i / q;
         T s = 0;
-        for (int k = 0; k < q; ++k) s += P.MS[0][i1 * q + k] / P.m[0][i1 + 1] * a[r * q + k];
+        for (int k = 0; k < q; ++k) s += P.MS(0)[i1 * q + k] / P.m(0)[i1 + 1] * a[r * q + k];
         b[i] = s;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < q3; i += blockDim.x) {
         int i1 = i % q, i2 = (i / q) % q, k3 = i / (q * q);
         T s = 0;
-        for (int k = 0; k < q; ++k) s += P.MS[1][i2 * q + k] / P.m[1][i2 + 1] * b[(k3 * q + k) * q + i1];
+        for (int k = 0; k < q; ++k) s += P.MS(1)[i2 * q + k] / P.m(1)[i2 + 1] * b[(k3 * q + k) * q + i1];
         a[i] = s;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < q3; i += blockDim.x) {
         int i12 = i % (q * q), i3 = i / (q * q);
         T s = 0;
-        for (int k = 0; k < q; ++k) s += P.MS[2][i3 * q + k] / P.m[2][i3 + 1] * a[k * q * q + i12];
+        for (int k = 0; k < q; ++k) s += P.MS(2)[i3 * q + k] / P.m(2)[i3 + 1] * a[k * q * q + i12];
         b[i] = s;
     }
     __syncthreads();
@@ -1603,7 +1611,7 @@ __global__ void __launch_bounds__(256) k_condense(LevelTabs<double> tb, const do
     for (int i = threadIdx.x; i < q3; i += blockDim.x) {
         int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
         int i1 = e[0] * p + 1 + k1, i2 = e[1] * p + 1 + k2, i3 = e[2] * p + 1 + k3;
-        a[i] = P.m[0][k1 + 1] * P.m[1][k2 + 1] * P.m[2][k3 + 1] *
+        a[i] = P.m(0)[k1 + 1] * P.m(1)[k2 + 1] * P.m(2)[k3 + 1] *
                f[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1];
     }
     __syncthreads();
@@ -1617,9 +1625,9 @@ __global__ void __launch_bounds__(256) k_condense(LevelTabs<double> tb, const do
             if (d == 0) { k3 = r; k2 = c; k1 = k; }
             else if (d == 1) { k3 = r; k1 = c; k2 = k; }
             else { k2 = r; k1 = c; k3 = k; }
-            double vv = a[(k3 * q + k2) * q + k1] / (tb.lam + P.lm[0][k1] + P.lm[1][k2] + P.lm[2][k3]);
-            s0 += P.c0[d][k] * vv;
-            sp += P.cp[d][k] * vv;
+            double vv = a[(k3 * q + k2) * q + k1] / (tb.lam + P.lm(0)[k1] + P.lm(1)[k2] + P.lm(2)[k3]);
+            s0 += P.c0(d)[k] * vv;
+            sp += P.cp(d)[k] * vv;
         }
         Tc[(2 * d) * q2 + rc] = s0;
         Tc[(2 * d + 1) * q2 + rc] = sp;
@@ -1655,7 +1663,7 @@ __global__ void __launch_bounds__(256) k_recover(LevelTabs<double> tb, const dou
     for (int i = threadIdx.x; i < q3; i += blockDim.x) {
         int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
         int i1 = e[0] * p + 1 + k1, i2 = e[1] * p + 1 + k2, i3 = e[2] * p + 1 + k3;
-        a[i] = P.m[0][k1 + 1] * P.m[1][k2 + 1] * P.m[2][k3 + 1] *
+        a[i] = P.m(0)[k1 + 1] * P.m(1)[k2 + 1] * P.m(2)[k3 + 1] *
                f[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1];
     }
     __syncthreads();
@@ -1678,7 +1686,7 @@ __global__ void __launch_bounds__(256) k_recover(LevelTabs<double> tb, const dou
     for (int i = threadIdx.x; i < q3; i += blockDim.x) {
         int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
         double v = a[i] - expand(P, G, q, k1, k2, k3);
-        a[i] = v / (tb.lam + P.lm[0][k1] + P.lm[1][k2] + P.lm[2][k3]);
+        a[i] = v / (tb.lam + P.lm(0)[k1] + P.lm(1)[k2] + P.lm(2)[k3]);
     }
     __syncthreads();
     interior_backward(P, q, a, b);
@@ -2288,6 +2296,7 @@ void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t s
                            tb, u);                                                                        \
         break;
         PMG_K1W(1) PMG_K1W(2) PMG_K1W(3) PMG_K1W(4) PMG_K1W(5) PMG_K1W(6) PMG_K1W(7) PMG_K1W(8)
+        PMG_K1W(12) PMG_K1W(16)
 #undef PMG_K1W
         default: {
             LevelTabs<T> t = tb;
@@ -2489,7 +2498,9 @@ hipError_t init_kernel_attributes() {
         (const void*)k_restrict_planes<double>, (const void*)k_restrict_planes<float>,
         (const void*)k_condense,             (const void*)k_recover,
         (const void*)k_smoother_mfma<double, MFMA_WPB>, (const void*)k_smoother_mfma<float, MFMA_WPB>,
-        (const void*)k_star_eigen<double>, (const void*)k_star_eigen<float>};
+        (const void*)k_star_eigen<double>, (const void*)k_star_eigen<float>,
+        (const void*)k_condensed_op_w<double, 16>, (const void*)k_condensed_op_w<float, 16>,
+        (const void*)k_condensed_op_w<double, 12>, (const void*)k_condensed_op_w<float, 12>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
