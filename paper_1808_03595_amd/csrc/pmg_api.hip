@@ -432,6 +432,17 @@ int build_mesh(pmg_mesh* m) {
         }
     }
     if ((rc = rebuild_active(m))) return rc;
+    // batched condensation / recovery workspaces on the finest level
+    if (m->p >= 9) {
+        Level& F = m->lv.back();
+        const int q = m->p - 1, n1 = m->p + 1, qp = 16 * ((q + 15) / 16);
+        const size_t ne = (size_t)m->n[0] * m->n[1] * m->n[2];
+        F.t64.qp = qp;
+        for (int k = 0; k < 2; ++k)
+            if ((rc = m->alloc(&F.t64.ixX[k], ne * qp * qp * qp))) return rc;
+        const size_t per = std::max<size_t>(18 * (size_t)q * q, 6 * (size_t)n1 * n1 + 12 * (size_t)q * q);
+        if (per * sizeof(double) > kLdsBytes && (rc = m->alloc(&F.t64.ixS, ne * per))) return rc;
+    }
     const Layout& Lf = m->lv.back().lay;
     int64_t nf = Lf.len;
     if ((rc = m->alloc(&m->w_u, nf)) || (rc = m->alloc(&m->w_r, nf)) || (rc = m->alloc(&m->w_s, nf)) ||

@@ -78,6 +78,12 @@ struct LevelTabs {
     T* gws;
     // two [star][3][np][np] workspaces of the batched star smoother (nS > 16)
     T* sbX[2];
+    // batched condensation / recovery (finest level, p >= 9): two
+    // [element][qp^3] arrays, qp = 16 ceil((p-1) / 16), and per-element
+    // scratch for the face parts when they exceed the LDS
+    double* ixX[2];
+    double* ixS;
+    int qp;
 };
 
 // Working-set sizes (elements of T) of the general per-element / per-star

@@ -1698,6 +1698,195 @@ __global__ void __launch_bounds__(256) k_recover(LevelTabs<double> tb, const dou
 }
 
 // ---------------------------------------------------------------------------
+// Condensation and recovery for p >= 9, batched over the elements: the
+// three 1D interior transforms (the O(p^4) part, Sec. 4.2) run as products
+// on FP64 MFMA over all elements at once, one wavefront per 16 x 16 output
+// tile, on qp^3 element arrays in a device workspace (qp = 16 ceil(q / 16),
+// zero padded); the remaining O(p^3) steps run per element.
+//   forward:  S^T[k][i] = Sinv[k][i] / m_i   (S^T M_I = Sinv)
+//   backward: S[i][k]   = (M_I S)[i][k] / m_i
+// ---------------------------------------------------------------------------
+template <int DIR, bool FWD>
+__global__ void __launch_bounds__(64) k_int_tx(LevelTabs<double> tb, int qp, const double* __restrict__ X,
+                                               double* __restrict__ Y) {
+    typedef Mfma<double> M;
+    const Layout& L = tb.lay;
+    const int q = L.p - 1, n1 = L.p + 1, nt = qp / 16;
+    const int eidx = blockIdx.x;
+    int e[3];
+    color_coords(eidx, -1, L.n, e);
+    const int lane = threadIdx.x, qg = lane >> 4, j = lane & 15;
+    const int ed = DIR == 0 ? e[0] : (DIR == 1 ? e[1] : e[2]);
+    const double* Mt = FWD ? pick3(DIR, tb.el_Sinv[0], tb.el_Sinv[1], tb.el_Sinv[2]) + (size_t)ed * q * q
+                           : pick3(DIR, tb.el_MS[0], tb.el_MS[1], tb.el_MS[2]) + (size_t)ed * q * q;
+    const double* md = pick3(DIR, tb.el_m[0], tb.el_m[1], tb.el_m[2]) + (size_t)ed * n1;
+    // M[i][k] of this direction (zero outside q x q)
+    auto Mv = [&](int i, int k) -> double {
+        if (i >= q || k >= q) return 0.0;
+        return FWD ? Mt[i * q + k] / md[k + 1] : Mt[i * q + k] / md[i + 1];
+    };
+    const size_t q2p = (size_t)qp * qp, base = (size_t)eidx * q2p * qp;
+    const double* Xe = X + base;
+    double* Ye = Y + base;
+    const int t = blockIdx.y;
+    typename M::v4 acc = {0, 0, 0, 0};
+    int row0, col0, slab = 0;
+    if (DIR == 0) {        // C[(k3,k2)][i] = sum_k X[(k3,k2)][k] M[i][k]
+        row0 = (t / nt) * 16;
+        col0 = (t % nt) * 16;
+        for (int k0 = 0; k0 < qp; k0 += 4) {
+            const int k = k0 + qg;
+            acc = M::mma(Xe[(size_t)(row0 + j) * qp + k], Mv(col0 + j, k), acc);
+        }
+    } else if (DIR == 1) { // for each k3: C[i][k1] = sum_k M[i][k] X[k3][k][k1]
+        slab = t / (nt * nt);
+        const int tt = t % (nt * nt);
+        row0 = (tt / nt) * 16;
+        col0 = (tt % nt) * 16;
+        const double* Xs = Xe + (size_t)slab * q2p;
+        for (int k0 = 0; k0 < qp; k0 += 4) {
+            const int k = k0 + qg;
+            acc = M::mma(Mv(row0 + j, k), Xs[(size_t)k * qp + col0 + j], acc);
+        }
+    } else {               // C[i][(k2,k1)] = sum_k M[i][k] X[k][(k2,k1)]
+        row0 = (t / (nt * qp)) * 16;
+        col0 = (t % (nt * qp)) * 16;
+        for (int k0 = 0; k0 < qp; k0 += 4) {
+            const int k = k0 + qg;
+            acc = M::mma(Mv(row0 + j, k), Xe[(size_t)k * q2p + col0 + j], acc);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = row0 + M::row(qg, v), c = col0 + j;
+        if (DIR == 0) Ye[(size_t)r * qp + c] = acc[v];
+        else if (DIR == 1) Ye[(size_t)slab * q2p + (size_t)r * qp + c] = acc[v];
+        else Ye[(size_t)r * q2p + c] = acc[v];
+    }
+}
+
+// X[e] = m1 m2 m3 f at the element's interior nodes (zero padded to qp^3)
+__global__ void k_int_load(LevelTabs<double> tb, int qp, const double* __restrict__ f, double* __restrict__ X) {
+    const Layout& L = tb.lay;
+    const int p = L.p, q = p - 1, n1 = p + 1;
+    const size_t per = (size_t)qp * qp * qp;
+    const size_t tot = per * L.n[0] * L.n[1] * L.n[2];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (size_t)gridDim.x * blockDim.x) {
+        const int eidx = (int)(i / per);
+        const int r = (int)(i - (size_t)eidx * per);
+        const int k1 = r % qp, k2 = (r / qp) % qp, k3 = r / (qp * qp);
+        double v = 0.0;
+        if (k1 < q && k2 < q && k3 < q) {
+            int e[3];
+            color_coords(eidx, -1, L.n, e);
+            const int i1 = e[0] * p + 1 + k1, i2 = e[1] * p + 1 + k2, i3 = e[2] * p + 1 + k3;
+            v = tb.el_m[0][e[0] * n1 + k1 + 1] * tb.el_m[1][e[1] * n1 + k2 + 1] * tb.el_m[2][e[2] * n1 + k3 + 1] *
+                f[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1];
+        }
+        X[i] = v;
+    }
+}
+
+// u at the interior nodes from X[e] (the recovered interior values)
+__global__ void k_int_store(LevelTabs<double> tb, int qp, const double* __restrict__ X, double* __restrict__ ug) {
+    const Layout& L = tb.lay;
+    const int p = L.p, q = p - 1;
+    const size_t per = (size_t)qp * qp * qp;
+    const size_t tot = per * L.n[0] * L.n[1] * L.n[2];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (size_t)gridDim.x * blockDim.x) {
+        const int eidx = (int)(i / per);
+        const int r = (int)(i - (size_t)eidx * per);
+        const int k1 = r % qp, k2 = (r / qp) % qp, k3 = r / (qp * qp);
+        if (k1 >= q || k2 >= q || k3 >= q) continue;
+        int e[3];
+        color_coords(eidx, -1, L.n, e);
+        const int i1 = e[0] * p + 1 + k1, i2 = e[1] * p + 1 + k2, i3 = e[2] * p + 1 + k3;
+        ug[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1] = X[i];
+    }
+}
+
+// Condensation, face part: with A = (S^T x S^T x S^T) M_I f_I in X,
+// Tc_{d,s} = sum_{k_d} c_{d,s}[k_d] A / D, corr_f = (MS_R x MS_C) Tc_f and
+// Fhat -= corr at the face-interior nodes (two elements meet at each: atomic).
+// Scratch: 3 x 6 q^2 per element (LDS when it fits).
+__global__ void __launch_bounds__(256) k_condense_faces(LevelTabs<double> tb, int qp, const double* __restrict__ X,
+                                                        double* __restrict__ Fh, double* __restrict__ scratch) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Layout& L = tb.lay;
+    const int p = L.p, q = p - 1, q2 = q * q;
+    double* sm = scratch ? scratch + (size_t)blockIdx.x * 18 * q2 : reinterpret_cast<double*>(smem_raw);
+    int e[3];
+    color_coords(blockIdx.x, -1, L.n, e);
+    ElemPtrs<double> P = elem_ptrs(tb, e);
+    const double* a = X + (size_t)blockIdx.x * qp * qp * qp;
+    double* Tc = sm;
+    double* tmp = Tc + 6 * q2;
+    double* cor = tmp + 6 * q2;
+    for (int i = threadIdx.x; i < 3 * q2; i += blockDim.x) {
+        const int d = i / q2, rc = i - d * q2, r = rc / q, c = rc - r * q;
+        double s0 = 0, sp = 0;
+        for (int k = 0; k < q; ++k) {
+            int k1, k2, k3;
+            if (d == 0) { k3 = r; k2 = c; k1 = k; }
+            else if (d == 1) { k3 = r; k1 = c; k2 = k; }
+            else { k2 = r; k1 = c; k3 = k; }
+            const double vv = a[((size_t)k3 * qp + k2) * qp + k1] /
+                              (tb.lam + P.lm(0)[k1] + P.lm(1)[k2] + P.lm(2)[k3]);
+            s0 += P.c0(d)[k] * vv;
+            sp += P.cp(d)[k] * vv;
+        }
+        Tc[(2 * d) * q2 + rc] = s0;
+        Tc[(2 * d + 1) * q2 + rc] = sp;
+    }
+    __syncthreads();
+    eigen_to_faces(P, p, Tc, tmp, cor);
+    for (int i = threadIdx.x; i < 6 * q2; i += blockDim.x) {
+        const int f = i / q2, rc = i - f * q2, r = rc / q + 1, c = rc % q + 1;
+        int a1, a2, a3;
+        tile_node(p, f, r, c, a1, a2, a3);
+        if (is_dir(L, e[0] * p + a1, e[1] * p + a2, e[2] * p + a3)) continue;
+        unsafeAtomicAdd(Fh + elem_slot(L, e, a1, a2, a3), -cor[i]);
+    }
+}
+
+// Recovery, middle part: writes the skeleton nodes of u owned by the
+// element, and replaces the forward-transformed right-hand side B in X by
+// V = (B - sum_f c_f (x) G_f) / D with G_f = (Sinv_R x Sinv_C) uhat_f.
+// Scratch: 6 (p+1)^2 + 12 q^2 per element (LDS when it fits).
+__global__ void __launch_bounds__(256) k_recover_mid(LevelTabs<double> tb, int qp, const double* __restrict__ uh,
+                                                     double* __restrict__ X, double* __restrict__ ug,
+                                                     double* __restrict__ scratch) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Layout& L = tb.lay;
+    const int p = L.p, n1 = p + 1, t2 = n1 * n1, q = p - 1, q2 = q * q;
+    double* sm = scratch ? scratch + (size_t)blockIdx.x * (6 * t2 + 12 * q2) : reinterpret_cast<double*>(smem_raw);
+    int e[3];
+    color_coords(blockIdx.x, -1, L.n, e);
+    ElemPtrs<double> P = elem_ptrs(tb, e);
+    double* tile = sm;
+    double* G = tile + 6 * t2;
+    double* tmp = G + 6 * q2;
+    load_tiles(L, e, uh, tile);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n1 * n1 * n1; i += blockDim.x) {
+        const int a1 = i % n1, a2 = (i / n1) % n1, a3 = i / t2;
+        const bool shell = a1 == 0 || a1 == p || a2 == 0 || a2 == p || a3 == 0 || a3 == p;
+        if (!shell) continue;
+        if ((a1 == p && e[0] != L.n[0] - 1) || (a2 == p && e[1] != L.n[1] - 1) || (a3 == p && e[2] != L.n[2] - 1))
+            continue;
+        const int i1 = e[0] * p + a1, i2 = e[1] * p + a2, i3 = e[2] * p + a3;
+        ug[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1] = is_dir(L, i1, i2, i3) ? 0.0 : shell_value(tile, p, a1, a2, a3);
+    }
+    faces_to_eigen(P, p, tile, false, tmp, G);
+    double* a = X + (size_t)blockIdx.x * qp * qp * qp;
+    for (int i = threadIdx.x; i < q2 * q; i += blockDim.x) {
+        const int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
+        double* v = a + ((size_t)k3 * qp + k2) * qp + k1;
+        *v = (*v - expand(P, G, q, k1, k2, k3)) / (tb.lam + P.lm(0)[k1] + P.lm(1)[k2] + P.lm(2)[k3]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // BLAS-1 on skeleton arrays.  Reductions write one partial per block and
 // the last block to finish sums the partials in a fixed order, so the
 // result is deterministic.  Scalars live in device memory.
@@ -2379,12 +2568,43 @@ void launch_point_smooth(const Layout& L, const T* dg, const T* r, T* u, T omega
     hipLaunchKernelGGL(k_point_smooth<T>, dim3(nblk(L.len)), dim3(256), 0, st, L.len, dg, r, u, omega);
 }
 
+static void int_forward(const LevelTabs<double>& tb, double* X0, double* X1, hipStream_t st) {
+    const int ne = tb.lay.n[0] * tb.lay.n[1] * tb.lay.n[2], qp = tb.qp;
+    const dim3 g(ne, qp * qp * qp / 256);
+    hipLaunchKernelGGL((k_int_tx<0, true>), g, dim3(64), 0, st, tb, qp, (const double*)X0, X1);
+    hipLaunchKernelGGL((k_int_tx<1, true>), g, dim3(64), 0, st, tb, qp, (const double*)X1, X0);
+    hipLaunchKernelGGL((k_int_tx<2, true>), g, dim3(64), 0, st, tb, qp, (const double*)X0, X1);
+}
+
+static void int_backward(const LevelTabs<double>& tb, double* X1, double* X0, hipStream_t st) {
+    const int ne = tb.lay.n[0] * tb.lay.n[1] * tb.lay.n[2], qp = tb.qp;
+    const dim3 g(ne, qp * qp * qp / 256);
+    hipLaunchKernelGGL((k_int_tx<0, false>), g, dim3(64), 0, st, tb, qp, (const double*)X1, X0);
+    hipLaunchKernelGGL((k_int_tx<1, false>), g, dim3(64), 0, st, tb, qp, (const double*)X0, X1);
+    hipLaunchKernelGGL((k_int_tx<2, false>), g, dim3(64), 0, st, tb, qp, (const double*)X1, X0);
+}
+
+static unsigned int_blocks(const LevelTabs<double>& tb) {
+    const size_t n = (size_t)tb.qp * tb.qp * tb.qp * tb.lay.n[0] * tb.lay.n[1] * tb.lay.n[2];
+    return (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+}
+
 void launch_condense(const LevelTabs<double>& tb, const double* m1, const double* m2, const double* m3,
                      const double* f, double* Fh, hipStream_t st) {
     const Layout& L = tb.lay;
     hipLaunchKernelGGL(k_mass_skeleton, dim3(nblk(L.len)), dim3(256), 0, st, L, m1, m2, m3, f, Fh);
     int q = L.p - 1;
     if (q < 1) return;
+    if (tb.ixX[0]) {
+        const int ne = L.n[0] * L.n[1] * L.n[2];
+        hipLaunchKernelGGL(k_int_load, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, f, tb.ixX[0]);
+        int_forward(tb, tb.ixX[0], tb.ixX[1], st);
+        const size_t need = sizeof(double) * 18 * (size_t)q * q;
+        double* scr = need > kLdsBytes ? tb.ixS : nullptr;
+        hipLaunchKernelGGL(k_condense_faces, dim3(ne), dim3(256), scr ? 0 : need, st, tb, tb.qp,
+                           (const double*)tb.ixX[1], Fh, scr);
+        return;
+    }
     LevelTabs<double> t = tb;
     const size_t sm = pick_ws(t, ws_condense(L.p));
     for (int c = 0; c < 8; ++c) {
@@ -2396,6 +2616,19 @@ void launch_condense(const LevelTabs<double>& tb, const double* m1, const double
 
 void launch_recover(const LevelTabs<double>& tb, const double* f, const double* uh, double* ug, hipStream_t st) {
     const Layout& L = tb.lay;
+    if (tb.ixX[0]) {
+        const int ne = L.n[0] * L.n[1] * L.n[2], n1 = L.p + 1, q = L.p - 1;
+        hipLaunchKernelGGL(k_int_load, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, f, tb.ixX[0]);
+        int_forward(tb, tb.ixX[0], tb.ixX[1], st);
+        const size_t need = sizeof(double) * (6 * (size_t)n1 * n1 + 12 * (size_t)q * q);
+        double* scr = need > kLdsBytes ? tb.ixS : nullptr;
+        hipLaunchKernelGGL(k_recover_mid, dim3(ne), dim3(256), scr ? 0 : need, st, tb, tb.qp, uh, tb.ixX[1], ug,
+                           scr);
+        int_backward(tb, tb.ixX[1], tb.ixX[0], st);
+        hipLaunchKernelGGL(k_int_store, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, (const double*)tb.ixX[0],
+                           ug);
+        return;
+    }
     LevelTabs<double> t = tb;
     const size_t sm = pick_ws(t, ws_recover(L.p));
     hipLaunchKernelGGL(k_recover, dim3(L.n[0] * L.n[1] * L.n[2]), dim3(256), sm, st, t, f, uh, ug);
@@ -2500,7 +2733,8 @@ hipError_t init_kernel_attributes() {
         (const void*)k_smoother_mfma<double, MFMA_WPB>, (const void*)k_smoother_mfma<float, MFMA_WPB>,
         (const void*)k_star_eigen<double>, (const void*)k_star_eigen<float>,
         (const void*)k_condensed_op_w<double, 16>, (const void*)k_condensed_op_w<float, 16>,
-        (const void*)k_condensed_op_w<double, 12>, (const void*)k_condensed_op_w<float, 12>};
+        (const void*)k_condensed_op_w<double, 12>, (const void*)k_condensed_op_w<float, 12>,
+        (const void*)k_condense_faces, (const void*)k_recover_mid};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
