@@ -312,7 +312,7 @@ __device__ ElemPtrs<T> stage_elem_tables(const LevelTabs<T>& tb, const int e[3],
 // One element per workgroup (any degree); the element's result goes to the
 // workspace opE like that of k_condensed_op_w.
 template <typename T>
-__global__ void __launch_bounds__(256) k_condensed_op(LevelTabs<T> tb, const T* __restrict__ u) {
+__global__ void __launch_bounds__(1024) k_condensed_op(LevelTabs<T> tb, const T* __restrict__ u) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = tb.gws ? tb.gws + (size_t)blockIdx.x * ws_condensed_op(tb.lay.p) : reinterpret_cast<T*>(smem_raw);
     const Layout& L = tb.lay;
@@ -325,12 +325,30 @@ __global__ void __launch_bounds__(256) k_condensed_op(LevelTabs<T> tb, const T* 
     T* Tc = G + 6 * q2;        // 6 q2
     T* tmp = Tc + 6 * q2;      // 6 q2
     T* tabs = tmp + 6 * q2;    // elem_table_size(p)
+    T* V = tabs + elem_table_size(p);  // q^3
     ElemPtrs<T> P = stage_elem_tables(tb, e, tabs);
     load_tiles(L, e, u, tile);
     __syncthreads();
     if (q > 0) {
         faces_to_eigen(P, p, tile, false, tmp, G);
-        eigen_contract(P, p, tb.lam, G, (const T*)nullptr, (T)1, Tc);
+        // V = D^-1 sum_f c_f (x) G_f once, then the three contractions
+        for (int i = threadIdx.x; i < q2 * q; i += blockDim.x) {
+            const int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
+            V[i] = expand(P, G, q, k1, k2, k3) / (tb.lam + P.lm(0)[k1] + P.lm(1)[k2] + P.lm(2)[k3]);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < 3 * q2; i += blockDim.x) {
+            const int d = i / q2, rc = i - d * q2, r = rc / q, c = rc - r * q;
+            T s0 = 0, sp = 0;
+            for (int k = 0; k < q; ++k) {
+                const int idx = d == 0 ? (r * q + c) * q + k : (d == 1 ? (r * q + k) * q + c : (k * q + r) * q + c);
+                s0 += P.c0(d)[k] * V[idx];
+                sp += P.cp(d)[k] * V[idx];
+            }
+            Tc[(2 * d) * q2 + rc] = s0;
+            Tc[(2 * d + 1) * q2 + rc] = sp;
+        }
+        __syncthreads();
         eigen_to_faces(P, p, Tc, tmp, G);  // corrections now in G
     }
     for (int i = threadIdx.x; i < 6 * t2; i += blockDim.x) {
@@ -2490,7 +2508,7 @@ void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t s
         default: {
             LevelTabs<T> t = tb;
             const size_t sm = pick_ws(t, ws_condensed_op(tb.lay.p));
-            hipLaunchKernelGGL((k_condensed_op<T>), dim3(ne), dim3(256), sm, st, t, u);
+            hipLaunchKernelGGL((k_condensed_op<T>), dim3(ne), dim3(tb.lay.p > 16 ? 1024 : 256), sm, st, t, u);
         }
     }
     launch_gather_elem(tb.lay, (const T*)tb.opE, y, st);
