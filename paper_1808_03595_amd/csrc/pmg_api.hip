@@ -371,7 +371,8 @@ int build_h_levels(pmg_mesh* m, int want) {
         gll_nodes_weights(p0.p, xf, wf);
         lagrange_interp(xc, xf, J);
         if ((rc = m->upload(&p0.Jlow64, J)) || (rc = m->upload(&p0.Jlow32, J))) return rc;
-        if ((rc = m->alloc(&p0.tb64, m->hlv[0].lay.len)) || (rc = m->alloc(&p0.tb32, m->hlv[0].lay.len))) return rc;
+        const int64_t wl = restrict_work_len(p0.lay, m->hlv[0].lay);
+        if ((rc = m->alloc(&p0.tb64, wl)) || (rc = m->alloc(&p0.tb32, wl))) return rc;
     }
     for (size_t k = 1; k < m->hlv.size(); ++k) {
         Level& f = m->hlv[k - 1];
@@ -427,7 +428,7 @@ int build_mesh(pmg_mesh* m) {
         Level& L = m->lv[l];
         if ((rc = build_level(m, L, degs[l], l ? degs[l - 1] : 0, m->h))) return rc;
         if (l > 0) {
-            int64_t nc = m->lv[l - 1].lay.len;
+            int64_t nc = restrict_work_len(L.lay, m->lv[l - 1].lay);
             if ((rc = m->alloc(&L.tb64, nc)) || (rc = m->alloc(&L.tb32, nc))) return rc;
         }
     }

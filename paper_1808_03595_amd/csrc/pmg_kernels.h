@@ -12,6 +12,8 @@ void set_mfma_min_degree(int p);
 // Coarse CG (launch-per-iteration form): the init kernel, then iteration
 // launches with ring index j = 0, 1, ..., COARSE_RING - 1, 0, ...
 constexpr int COARSE_RING = 6;
+// length of the restriction work buffer (coarse partial sums + row pass)
+int64_t restrict_work_len(const Layout& Lf, const Layout& Lc);
 constexpr int COARSE_GRAPHS = 5;   // graphs of COARSE_RING * 2^k launches
 hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, double* out, int maxit, double rtol,
                               hipStream_t st);

@@ -1267,135 +1267,116 @@ __global__ void __launch_bounds__(256) k_star_eigen(LevelTabs<T> tb, const T* __
 // Grid transfers (Sec. 4.1).  The fine condensed values are the tensor
 // Lagrange interpolation of the coarse ones; on a plane this is the 2D
 // interpolation of the coarse plane values (including its edge lines).
+// Transfers between p-levels run one thread per output node (compile-time
+// degrees PF / PC when known, 0 = runtime).  Along every plane direction the
+// 1D interpolation is element-local: fine node g of element E = min(g / pf,
+// n - 1) (local l = g - E pf) takes sum_R J[l][R] x(E pc + R).
 // ---------------------------------------------------------------------------
-// Coarse value at plane-local node of family d, plane j: (row index R, col C).
+// Coarse value at plane node (R, C) of family d, plane j, read from the
+// family that stores the node.
 template <typename T>
-__device__ inline T plane_value(const Layout& L, const T* x, int d, int j, int R, int C) {
-    const int p = L.p;
-    int i1, i2, i3;
-    if (d == 0) { i1 = j * p; i3 = R; i2 = C; }
-    else if (d == 1) { i2 = j * p; i3 = R; i1 = C; }
-    else { i3 = j * p; i2 = R; i1 = C; }
-    bool on1 = i1 % p == 0, on2 = i2 % p == 0;
-    return x[L.slot(i1, i2, i3, on1, on2)];
+__device__ inline T coarse_plane_value(const Layout& L, const T* x, int d, int j, int R, int C, int pc) {
+    if (d == 0) return x[L.plane0(j) + (int64_t)R * L.pitch[0] + C];
+    if (d == 1) {
+        if (C % pc == 0) return x[L.plane0(C / pc) + (int64_t)R * L.pitch[0] + j * pc];
+        return x[L.plane1(j) + (int64_t)R * L.pitch[1] + C];
+    }
+    if (C % pc == 0) return x[L.plane0(C / pc) + (int64_t)(j * pc) * L.pitch[0] + R];
+    if (R % pc == 0) return x[L.plane1(R / pc) + (int64_t)(j * pc) * L.pitch[1] + C];
+    return x[L.plane2(j) + (int64_t)R * L.pitch[2] + C];
 }
 
-// plane tile counts per family: rows run along rdir, columns along cdir
-__device__ inline int tiles_r(const Layout& L, int d) { return L.n[d == 2 ? 1 : 2]; }
-__device__ inline int tiles_c(const Layout& L, int d) { return L.n[d == 0 ? 1 : 0]; }
-
-__device__ inline void transfer_block(const Layout& L, int b, int& d, int& j, int& tr, int& tc) {
-    for (d = 0; d < 3; ++d) {
-        int cnt = (L.n[d] + 1) * tiles_r(L, d) * tiles_c(L, d);
-        if (b < cnt) break;
-        b -= cnt;
-    }
-    int ntc = tiles_c(L, d), ntr = tiles_r(L, d);
-    tc = b % ntc;
-    b /= ntc;
-    tr = b % ntr;
-    j = b / ntr;
+__device__ inline int plane_family(const Layout& L, int z, int& j) {
+    const int d = z >= L.n[0] + L.n[1] + 2 ? 2 : (z >= L.n[0] + 1 ? 1 : 0);
+    j = z - (d == 0 ? 0 : (d == 1 ? L.n[0] + 1 : L.n[0] + L.n[1] + 2));
+    return d;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_prolong_add(Layout Lc, Layout Lf, const T* __restrict__ J,
-                                                     const T* __restrict__ uc, T* __restrict__ uf) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* sm = reinterpret_cast<T*>(smem_raw);
-    const int pc = Lc.p, pf = Lf.p, nc1 = pc + 1;
-    int d, j, tr, tc;
-    transfer_block(Lf, blockIdx.x, d, j, tr, tc);
-    T* X = sm;                 // nc1 x nc1 coarse tile
-    T* Y = X + nc1 * nc1;      // pf x nc1
-    for (int i = threadIdx.x; i < nc1 * nc1; i += blockDim.x) {
-        int R = i / nc1, C = i - R * nc1;
-        X[i] = plane_value(Lc, uc, d, j, tr * pc + R, tc * pc + C);
+// uf += P uc on every canonical, non-Dirichlet fine node.
+template <typename T, int PF, int PC>
+__global__ void __launch_bounds__(256) k_prolong_direct(Layout Lc, Layout Lf, const T* __restrict__ J,
+                                                        const T* __restrict__ uc, T* __restrict__ uf) {
+    int j;
+    const int d = plane_family(Lf, blockIdx.z, j);
+    const int gr = blockIdx.y * 4 + threadIdx.y, gc = blockIdx.x * 64 + threadIdx.x;
+    const int pf = PF > 0 ? PF : Lf.p, pc = PC > 0 ? PC : Lc.p, nc1 = pc + 1;
+    const int dr = d == 2 ? 1 : 2, dc = d == 0 ? 1 : 0;
+    if (gr >= Lf.N[dr] || gc >= Lf.N[dc]) return;
+    int g[3];
+    bool canon = true;
+    g[d] = j * pf;
+    g[dr] = gr;
+    g[dc] = gc;
+    if (d == 1) canon = gc % pf != 0;
+    if (d == 2) canon = gc % pf != 0 && gr % pf != 0;
+    if (!canon || is_dir(Lf, g[0], g[1], g[2])) return;
+    const int Er = min(gr / pf, Lf.n[dr] - 1), lr = gr - Er * pf;
+    const int Ec = min(gc / pf, Lf.n[dc] - 1), lc = gc - Ec * pf;
+    T s = 0;
+    for (int R = 0; R < nc1; ++R) {
+        const T wr = J[lr * nc1 + R];
+        if (wr == (T)0) continue;
+        T t = 0;
+        for (int C = 0; C < nc1; ++C)
+            t += J[lc * nc1 + C] * coarse_plane_value(Lc, uc, d, j, Er * pc + R, Ec * pc + C, pc);
+        s += wr * t;
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < pf * nc1; i += blockDim.x) {
-        int r = i / nc1, C = i - r * nc1;
-        T s = 0;
-        for (int R = 0; R < nc1; ++R) s += J[r * nc1 + R] * X[R * nc1 + C];
-        Y[i] = s;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < pf * pf; i += blockDim.x) {
-        int r = i / pf, c = i - r * pf;
-        int gr = tr * pf + r, gc = tc * pf + c;
-        int i1, i2, i3;
-        bool canon;
-        if (d == 0) { i1 = j * pf; i3 = gr; i2 = gc; canon = true; }
-        else if (d == 1) { i2 = j * pf; i3 = gr; i1 = gc; canon = c != 0; }
-        else { i3 = j * pf; i2 = gr; i1 = gc; canon = c != 0 && r != 0; }
-        if (!canon || is_dir(Lf, i1, i2, i3)) continue;
-        T s = 0;
-        for (int C = 0; C < nc1; ++C) s += Y[r * nc1 + C] * J[c * nc1 + C];
-        int64_t slot = (d == 0) ? Lf.plane0(j) + (int64_t)i3 * Lf.pitch[0] + i2
-                     : (d == 1) ? Lf.plane1(j) + (int64_t)i3 * Lf.pitch[1] + i1
-                                : Lf.plane2(j) + (int64_t)i2 * Lf.pitch[2] + i1;
-        uf[slot] += s;
-    }
+    uf[Lf.off[d] + (int64_t)j * Lf.pstride[d] + (int64_t)gr * Lf.pitch[d] + gc] += s;
 }
 
-// 1D global interpolation weight P[g][G] between fine node g and coarse node G.
-template <typename T>
-__device__ inline T p1d(const T* J, int n, int pf, int pc, int g, int G) {
-    int e = g / pf;
-    if (e > n - 1) e = n - 1;
-    int R = G - e * pc;
-    if (R < 0 || R > pc) return (T)0;
-    return J[(g - e * pf) * (pc + 1) + R];
+// Transposed 1D interpolation: sum over the fine nodes g with a weight on
+// coarse node G of v(g) P[g][G] (the element-local support of G).
+template <typename T, int PF, int PC, typename F>
+__device__ inline T restrict_1d(const T* J, int n, int pf, int pc, int G, F v) {
+    const int nc1 = pc + 1, E = G / pc, l = G - E * pc;
+    T s = 0;
+    if (l != 0) {                     // interior coarse node of element E
+        for (int r = 1; r < pf; ++r) s += J[r * nc1 + l] * v(E * pf + r);
+        return s;
+    }
+    s = v(E * pf);                    // the shared vertex (weight 1)
+    if (E > 0)
+        for (int r = 1; r < pf; ++r) s += J[r * nc1 + pc] * v((E - 1) * pf + r);
+    if (E < n)
+        for (int r = 1; r < pf; ++r) s += J[r * nc1] * v(E * pf + r);
+    return s;
 }
 
-// Restriction pass A: T_d = (P^T x P^T) r_d on every coarse node of every
-// plane (holes included), written to `tb` in the coarse layout.
-template <typename T>
-__global__ void __launch_bounds__(256) k_restrict_planes(Layout Lc, Layout Lf, const T* __restrict__ J,
-                                                         const T* __restrict__ rf, T* __restrict__ tbuf) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* sm = reinterpret_cast<T*>(smem_raw);
-    const int pc = Lc.p, pf = Lf.p, w = 2 * pf - 1;
-    int d, j, tr, tc;
-    transfer_block(Lc, blockIdx.x, d, j, tr, tc);
-    const int nr = Lc.n[d == 2 ? 1 : 2], ncn = Lc.n[d == 0 ? 1 : 0];
-    const int Nr = Lf.N[d == 2 ? 1 : 2], Nc = Lf.N[d == 0 ? 1 : 0];
-    const int64_t base = (d == 0) ? Lf.plane0(j) : (d == 1) ? Lf.plane1(j) : Lf.plane2(j);
-    const int pitch = Lf.pitch[d];
-    T* W = sm;           // w x w fine window
-    T* Y = W + w * w;    // w x pc
-    const int gr0 = tr * pf - pf + 1, gc0 = tc * pf - pf + 1;
-    for (int i = threadIdx.x; i < w * w; i += blockDim.x) {
-        int a = i / w, b = i - a * w;
-        int gr = gr0 + a, gc = gc0 + b;
-        T v = 0;
-        if (gr >= 0 && gr < Nr && gc >= 0 && gc < Nc) v = rf[base + (int64_t)gr * pitch + gc];
-        W[i] = v;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < w * pc; i += blockDim.x) {
-        int a = i / pc, C = i - a * pc;
-        int G = tc * pc + C;
-        T s = 0;
-        for (int b = 0; b < w; ++b) {
-            int gc = gc0 + b;
-            if (gc < 0 || gc >= Nc) continue;
-            s += p1d(J, ncn, pf, pc, gc, G) * W[a * w + b];
-        }
-        Y[i] = s;
-    }
-    __syncthreads();
-    const int64_t cbase = (d == 0) ? Lc.plane0(j) : (d == 1) ? Lc.plane1(j) : Lc.plane2(j);
-    for (int i = threadIdx.x; i < pc * pc; i += blockDim.x) {
-        int R = i / pc, C = i - R * pc;
-        int G = tr * pc + R;
-        T s = 0;
-        for (int a = 0; a < w; ++a) {
-            int gr = gr0 + a;
-            if (gr < 0 || gr >= Nr) continue;
-            s += p1d(J, nr, pf, pc, gr, G) * Y[a * pc + C];
-        }
-        tbuf[cbase + (int64_t)(tr * pc + R) * Lc.pitch[d] + tc * pc + C] = s;
-    }
+// Restriction pass 1: Y[d][j][gr][C] = sum_gc P[gc][C] rf[d][j][gr][gc]
+// (fine plane values as stored: zero where another family holds the node).
+template <typename T, int PF, int PC>
+__global__ void __launch_bounds__(256) k_restrict_rows(Layout Lc, Layout Lf, const T* __restrict__ J,
+                                                       const T* __restrict__ rf, T* __restrict__ Y) {
+    int j;
+    const int d = plane_family(Lf, blockIdx.z, j);
+    const int gr = blockIdx.y * 4 + threadIdx.y, C = blockIdx.x * 64 + threadIdx.x;
+    const int dr = d == 2 ? 1 : 2, dc = d == 0 ? 1 : 0;
+    if (gr >= Lf.N[dr] || C >= Lc.N[dc]) return;
+    const int pf = PF > 0 ? PF : Lf.p, pc = PC > 0 ? PC : Lc.p;
+    const T* row = rf + Lf.off[d] + (int64_t)j * Lf.pstride[d] + (int64_t)gr * Lf.pitch[d];
+    const T s = restrict_1d<T, PF, PC>(J, Lf.n[dc], pf, pc, C, [&](int g) { return row[g]; });
+    int64_t ybase = 0;
+    for (int k = 0; k < d; ++k) ybase += (int64_t)(Lf.n[k] + 1) * Lf.rows[k] * Lc.pitch[k];
+    Y[ybase + ((int64_t)j * Lf.rows[d] + gr) * Lc.pitch[d] + C] = s;
+}
+
+// Restriction pass 2: T_d[j][R][C] = sum_gr P[gr][R] Y[d][j][gr][C] on every
+// coarse plane node (holes included), in the coarse plane layout.
+template <typename T, int PF, int PC>
+__global__ void __launch_bounds__(256) k_restrict_cols(Layout Lc, Layout Lf, const T* __restrict__ J,
+                                                       const T* __restrict__ Y, T* __restrict__ tbuf) {
+    int j;
+    const int d = plane_family(Lc, blockIdx.z, j);
+    const int R = blockIdx.y * 4 + threadIdx.y, C = blockIdx.x * 64 + threadIdx.x;
+    const int dr = d == 2 ? 1 : 2, dc = d == 0 ? 1 : 0;
+    if (R >= Lc.N[dr] || C >= Lc.N[dc]) return;
+    const int pf = PF > 0 ? PF : Lf.p, pc = PC > 0 ? PC : Lc.p;
+    int64_t ybase = 0;
+    for (int k = 0; k < d; ++k) ybase += (int64_t)(Lf.n[k] + 1) * Lf.rows[k] * Lc.pitch[k];
+    const T* col = Y + ybase + (int64_t)j * Lf.rows[d] * Lc.pitch[d] + C;
+    const int64_t pitch = Lc.pitch[d];
+    const T s = restrict_1d<T, PF, PC>(J, Lf.n[dr], pf, pc, R, [&](int g) { return col[(int64_t)g * pitch]; });
+    tbuf[Lc.off[d] + (int64_t)j * Lc.pstride[d] + (int64_t)R * Lc.pitch[d] + C] = s;
 }
 
 // Restriction pass B: coarse unknown = sum of T_d over the plane families
@@ -2551,24 +2532,47 @@ void launch_smoother_add(const LevelTabs<T>& tb, const T* r, T* du, T omega, hip
     }
 }
 
-static int transfer_blocks(const Layout& L) {
-    int tot = 0;
-    for (int d = 0; d < 3; ++d) tot += (L.n[d] + 1) * L.n[d == 2 ? 1 : 2] * L.n[d == 0 ? 1 : 0];
-    return tot;
+
+static dim3 plane_grid(const Layout& L, int cols, int rows) {
+    return dim3((cols + 63) / 64, (rows + 3) / 4, L.n[0] + L.n[1] + L.n[2] + 3);
+}
+
+static int max_cols(const Layout& L) { return std::max(L.N[0], L.N[1]); }
+static int max_rows(const Layout& L) { return std::max(L.N[1], L.N[2]); }
+
+int64_t restrict_work_len(const Layout& Lf, const Layout& Lc) {
+    int64_t y = 0;
+    for (int k = 0; k < 3; ++k) y += (int64_t)(Lf.n[k] + 1) * Lf.rows[k] * Lc.pitch[k];
+    return Lc.len + y;
 }
 
 template <typename T>
 void launch_prolong_add(const Layout& Lc, const Layout& Lf, const T* J, const T* uc, T* uf, hipStream_t st) {
-    size_t sm = sizeof(T) * (size_t)((Lc.p + 1) * (Lc.p + 1) + Lf.p * (Lc.p + 1));
-    hipLaunchKernelGGL(k_prolong_add<T>, dim3(transfer_blocks(Lf)), dim3(256), sm, st, Lc, Lf, J, uc, uf);
+    const dim3 g = plane_grid(Lf, max_cols(Lf), max_rows(Lf)), b(64, 4);
+#define PMG_PRO(A, B) hipLaunchKernelGGL((k_prolong_direct<T, A, B>), g, b, 0, st, Lc, Lf, J, uc, uf)
+    if (Lf.p == 4 && Lc.p == 2) PMG_PRO(4, 2);
+    else if (Lf.p == 8 && Lc.p == 4) PMG_PRO(8, 4);
+    else if (Lf.p == 16 && Lc.p == 8) PMG_PRO(16, 8);
+    else PMG_PRO(0, 0);
+#undef PMG_PRO
 }
 
 template <typename T>
 void launch_restrict(const Layout& Lf, const Layout& Lc, const T* J, const T* rf, T* rc, T* tbuf,
                      hipStream_t st) {
-    int w = 2 * Lf.p - 1;
-    size_t sm = sizeof(T) * (size_t)(w * w + w * Lc.p);
-    hipLaunchKernelGGL(k_restrict_planes<T>, dim3(transfer_blocks(Lc)), dim3(256), sm, st, Lc, Lf, J, rf, tbuf);
+    T* Y = tbuf + Lc.len;
+    const dim3 g1 = plane_grid(Lf, max_cols(Lc), max_rows(Lf)), g2 = plane_grid(Lc, max_cols(Lc), max_rows(Lc)),
+               b(64, 4);
+#define PMG_RES(A, B)                                                                                   \
+    do {                                                                                                \
+        hipLaunchKernelGGL((k_restrict_rows<T, A, B>), g1, b, 0, st, Lc, Lf, J, rf, Y);                 \
+        hipLaunchKernelGGL((k_restrict_cols<T, A, B>), g2, b, 0, st, Lc, Lf, J, (const T*)Y, tbuf);     \
+    } while (0)
+    if (Lf.p == 4 && Lc.p == 2) PMG_RES(4, 2);
+    else if (Lf.p == 8 && Lc.p == 4) PMG_RES(8, 4);
+    else if (Lf.p == 16 && Lc.p == 8) PMG_RES(16, 8);
+    else PMG_RES(0, 0);
+#undef PMG_RES
     hipLaunchKernelGGL(k_restrict_combine<T>, dim3(nblk(Lc.len)), dim3(256), 0, st, Lc, (const T*)tbuf, rc);
 }
 
@@ -2745,8 +2749,6 @@ hipError_t init_kernel_attributes() {
     const void* fns[] = {
         (const void*)k_condensed_op<double>, (const void*)k_condensed_op<float>,
         (const void*)k_smoother<double>,     (const void*)k_smoother<float>,
-        (const void*)k_prolong_add<double>,  (const void*)k_prolong_add<float>,
-        (const void*)k_restrict_planes<double>, (const void*)k_restrict_planes<float>,
         (const void*)k_condense,             (const void*)k_recover,
         (const void*)k_smoother_mfma<double, MFMA_WPB>, (const void*)k_smoother_mfma<float, MFMA_WPB>,
         (const void*)k_star_eigen<double>, (const void*)k_star_eigen<float>,
