@@ -104,6 +104,10 @@ struct pmg_mesh {
     int* d_coarse_iters = nullptr;
     int* h_cstat = nullptr;             // pinned copy of the coarse done flag and count
     hipStream_t cap_stream = nullptr;   // private stream for graph capture
+    // Alg. 5 iteration graphs per preconditioner precision: [2 pdt + 0] up to
+    // the coarse solve, [2 pdt + 1] after it; rebuilt after any change of
+    // the cycle
+    hipGraphExec_t solver_graphs[4] = {nullptr, nullptr, nullptr, nullptr};
     int coarse_last = 0;
     long coarse_total = 0;
     // finest-level solver vectors (FP64) and mixed-precision buffers
@@ -385,6 +389,11 @@ int build_h_levels(pmg_mesh* m, int want) {
 
 // Active cycle, coarsest level first: hlv[k-1..0] then the p-levels.
 int rebuild_active(pmg_mesh* m) {
+    for (auto& g : m->solver_graphs)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
     int nh = std::min(m->hmg_levels, (int)m->hlv.size());
     m->act.clear();
     for (int k = nh - 1; k >= 0; --k) m->act.push_back(&m->hlv[k]);
@@ -567,79 +576,121 @@ int coarse_stats(pmg_mesh* m, hipStream_t st, int* iters) {
 }
 
 // Alg. 3 over the active cycle (coarsest level first), with u_L = z (zero on
-// entry unless `nonzero_u`) and F_L = r.  The coarsest level is solved by the
-// persistent CG kernel in FP64.
+// entry unless `nonzero_u`) and F_L = r, in three phases: the down-sweep up
+// to the restricted right-hand side of the coarsest level (cast to FP64 for
+// an FP32 cycle), the coarse CG in FP64, and the up-sweep.  The down- and
+// up-sweeps contain kernel launches only (zero fills are kernels too), so
+// the solver can capture them as graphs.
 template <typename T>
-int vcycle_impl(pmg_mesh* m, const T* r, T* z, bool nonzero_u, hipStream_t st) {
+void vc_coarse_io(pmg_mesh* m, const T* r, T* z, const double*& b, double*& x) {
+    auto& A = m->act;
+    Level& l0 = *A[0];
+    const bool dbl = std::is_same<T, double>::value;
+    if (A.size() == 1) {
+        b = dbl ? reinterpret_cast<const double*>(r) : l0.F64;
+        x = dbl ? reinterpret_cast<double*>(z) : l0.u64;
+    } else {
+        b = dbl ? reinterpret_cast<const double*>(Sel<T>::F(l0)) : l0.F64;
+        x = l0.u64;
+    }
+}
+
+template <typename T>
+int vc_down(pmg_mesh* m, const T* r, T* z, bool nonzero_u, hipStream_t st) {
     auto& A = m->act;
     const int L = (int)A.size() - 1;
-    std::vector<T*> u(L + 1);
-    std::vector<const T*> F(L + 1);
-    u[L] = z;
-    F[L] = r;
-    if (!nonzero_u) HIPCHK(hipMemsetAsync(z, 0, A[L]->lay.len * sizeof(T), st));
+    Level& l0 = *A[0];
+    if (L == 0) {
+        if (!std::is_same<T, double>::value) launch_cast_scale<T, double>(r, l0.F64, nullptr, 0, l0.lay.len, st);
+        return 0;
+    }
+    if (!nonzero_u) launch_fill_zero<T>(z, A[L]->lay.len, st);
+    const T* F = r;
     for (int l = L; l >= 1; --l) {
         Level& lv = *A[l];
-        if (l != L) {
-            u[l] = Sel<T>::u(lv);
-            HIPCHK(hipMemsetAsync(u[l], 0, lv.lay.len * sizeof(T), st));
-        }
+        T* u = (l == L) ? z : Sel<T>::u(lv);
+        if (l != L) launch_fill_zero<T>(u, lv.lay.len, st);
         bool zero = (l != L) || !nonzero_u;
         T* y = Sel<T>::y(lv);
         for (int i = 0; i < lv.nu; ++i) {
-            const T* res = F[l];
+            const T* res = F;
             if (!zero) {
-                residual<T>(lv, F[l], u[l], y, st);
+                residual<T>(lv, F, u, y, st);
                 res = y;
             }
-            smooth_add<T>(lv, res, u[l], st);
+            smooth_add<T>(lv, res, u, st);
             zero = false;
         }
-        residual<T>(lv, F[l], u[l], y, st);
+        residual<T>(lv, F, u, y, st);
         Level& lc = *A[l - 1];
         T* Fc = Sel<T>::F(lc);
         if (lv.kind == 'p') launch_restrict<T>(lv.lay, lc.lay, jdown<T>(lv), y, Fc, Sel<T>::tb(lv), st);
         else launch_hrestrict<T>(lv.lay, lc.lay, hweights<T>(lv), y, Fc, st);
-        F[l - 1] = Fc;
+        F = Fc;
     }
-    // coarse solve in FP64
+    if (!std::is_same<T, double>::value) launch_cast_scale<T, double>(F, l0.F64, nullptr, 0, l0.lay.len, st);
+    return 0;
+}
+
+template <typename T>
+int vc_up(pmg_mesh* m, const T* r, T* z, hipStream_t st) {
+    auto& A = m->act;
+    const int L = (int)A.size() - 1;
     Level& l0 = *A[0];
+    const bool dbl = std::is_same<T, double>::value;
     if (L == 0) {
-        // the whole problem is the coarse problem
-        if (std::is_same<T, double>::value) return coarse_cg(m, reinterpret_cast<const double*>(r),
-                                                             reinterpret_cast<double*>(z), st);
-        launch_cast_scale<T, double>(r, l0.F64, nullptr, 0, l0.lay.len, st);
-        int rc = coarse_cg(m, l0.F64, l0.u64, st);
-        if (rc) return rc;
-        launch_cast_scale<double, T>(l0.u64, z, nullptr, 0, l0.lay.len, st);
+        if (!dbl) launch_cast_scale<double, T>(l0.u64, z, nullptr, 0, l0.lay.len, st);
         return 0;
     }
-    {
-        const double* b;
-        if (std::is_same<T, double>::value) b = reinterpret_cast<const double*>(F[0]);
-        else {
-            launch_cast_scale<T, double>(F[0], l0.F64, nullptr, 0, l0.lay.len, st);
-            b = l0.F64;
-        }
-        int rc = coarse_cg(m, b, l0.u64, st);
-        if (rc) return rc;
-        if (std::is_same<T, double>::value) u[0] = reinterpret_cast<T*>(l0.u64);
-        else {
-            launch_cast_scale<double, T>(l0.u64, Sel<T>::u(l0), nullptr, 0, l0.lay.len, st);
-            u[0] = Sel<T>::u(l0);
-        }
+    T* uc;
+    if (dbl) uc = reinterpret_cast<T*>(l0.u64);
+    else {
+        launch_cast_scale<double, T>(l0.u64, Sel<T>::u(l0), nullptr, 0, l0.lay.len, st);
+        uc = Sel<T>::u(l0);
     }
     for (int l = 1; l <= L; ++l) {
         Level& lv = *A[l];
         Level& lc = *A[l - 1];
-        if (lv.kind == 'p') launch_prolong_add<T>(lc.lay, lv.lay, jdown<T>(lv), u[l - 1], u[l], st);
-        else launch_hprolong_add<T>(lc.lay, lv.lay, hweights<T>(lv), u[l - 1], u[l], st);
+        T* u = (l == L) ? z : Sel<T>::u(lv);
+        const T* F = (l == L) ? r : Sel<T>::F(lv);
+        if (lv.kind == 'p') launch_prolong_add<T>(lc.lay, lv.lay, jdown<T>(lv), uc, u, st);
+        else launch_hprolong_add<T>(lc.lay, lv.lay, hweights<T>(lv), uc, u, st);
         T* y = Sel<T>::y(lv);
         for (int i = 0; i < lv.nu; ++i) {
-            residual<T>(lv, F[l], u[l], y, st);
-            smooth_add<T>(lv, y, u[l], st);
+            residual<T>(lv, F, u, y, st);
+            smooth_add<T>(lv, y, u, st);
         }
+        uc = u;
     }
+    return 0;
+}
+
+template <typename T>
+int vcycle_impl(pmg_mesh* m, const T* r, T* z, bool nonzero_u, hipStream_t st) {
+    int rc;
+    if ((rc = vc_down<T>(m, r, z, nonzero_u, st))) return rc;
+    const double* b;
+    double* x;
+    vc_coarse_io<T>(m, r, z, b, x);
+    if ((rc = coarse_cg(m, b, x, st))) return rc;
+    return vc_up<T>(m, r, z, st);
+}
+
+// Capture the launches `body` makes into an executable graph (on the
+// mesh's private stream; the graph is later launched on the caller's).
+template <typename F>
+int capture_graph(pmg_mesh* m, hipGraphExec_t* out, F body) {
+    HIPCHK(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = body(m->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(m->cap_stream, &g);
+    if (rc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : fail(PMG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(PMG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     return 0;
 }
 
@@ -717,6 +768,8 @@ void pmg_destroy_mesh(pmg_mesh* m) {
         for (Level& l : *v)
             for (hipGraphExec_t g : l.coarse_exec)
                 if (g) (void)hipGraphExecDestroy(g);
+    for (hipGraphExec_t g : m->solver_graphs)
+        if (g) (void)hipGraphExecDestroy(g);
     for (void* q : m->allocs) hipFree(q);
     if (m->hscal) hipHostFree(m->hscal);
     if (m->h_cstat) (void)hipHostFree(m->h_cstat);
@@ -982,23 +1035,42 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
             if ((rc = read_scalars(m, st))) return rc;
             rr = m->hscal[SC_RR];
         } else {
-            // Alg. 5
-            if (pdt == PMG_F64) {
-                if ((rc = vcycle_impl<double>(m, m->w_r, m->w_z, false, st))) return rc;
-            } else {
-                double nr = std::sqrt(rr);
-                HIPCHK(hipMemcpyAsync(m->scal + SC_N - 1, &nr, sizeof(double), hipMemcpyHostToDevice, st));
-                launch_cast_scale<double, float>(m->w_r, m->w_r32, m->scal + SC_N - 1, 1, n, st);
-                if ((rc = vcycle_impl<float>(m, m->w_r32, m->w_z32, false, st))) return rc;
-                launch_cast_scale<float, double>(m->w_z32, m->w_z, m->scal + SC_N - 1, 0, n, st);
+            // Alg. 5: z = MG(0, r) (FP64, or FP32 on r / |r| scaled back by
+            // |r|, the norm taken from the device), then the direction and
+            // the update.  Everything but the coarse CG is replayed from two
+            // graphs captured on first use.
+            const int gi = pdt == PMG_F64 ? 0 : 2;
+            if (!m->solver_graphs[gi]) {
+                auto part_a = [&](hipStream_t s) -> int {
+                    if (pdt == PMG_F64) return vc_down<double>(m, m->w_r, m->w_z, false, s);
+                    launch_cast_scale<double, float>(m->w_r, m->w_r32, m->scal + SC_RR, 2, n, s);
+                    return vc_down<float>(m, m->w_r32, m->w_z32, false, s);
+                };
+                auto part_b = [&](hipStream_t s) -> int {
+                    int r2 = pdt == PMG_F64 ? vc_up<double>(m, m->w_r, m->w_z, s)
+                                            : vc_up<float>(m, m->w_r32, m->w_z32, s);
+                    if (r2) return r2;
+                    if (pdt != PMG_F64)
+                        launch_cast_scale<float, double>(m->w_z32, m->w_z, m->scal + SC_RR, 3, n, s);
+                    launch_dot2<double>(m->w_z, m->w_r, m->w_s, n, m->partials, m->counter, m->scal + SC_GAMMA, s);
+                    launch_pcg_dir(m->w_p, m->w_z, m->scal, n, s);
+                    launch_condensed_op<double>(m->lv.back().t64, m->w_p, m->w_q, s);
+                    launch_dot2<double>(m->w_q, m->w_p, nullptr, n, m->partials, m->counter, m->scal + SC_QP, s);
+                    launch_pcg_update(m->w_u, m->w_r, m->w_s, m->w_p, m->w_q, m->scal + SC_GAMMA, m->scal + SC_QP,
+                                      n, m->partials, m->counter, m->scal + SC_RR, m->scal + SC_DELTA, s);
+                    return 0;
+                };
+                if ((rc = capture_graph(m, &m->solver_graphs[gi], part_a)) ||
+                    (rc = capture_graph(m, &m->solver_graphs[gi + 1], part_b)))
+                    return rc;
             }
-            launch_dot2<double>(m->w_z, m->w_r, m->w_s, n, m->partials, m->counter, m->scal + SC_GAMMA, st);
-            launch_pcg_dir(m->w_p, m->w_z, m->scal, n, st);
-            HIPCHK(hipMemcpyAsync(m->scal + SC_DELTA, m->scal + SC_GAMMA, sizeof(double), hipMemcpyDeviceToDevice, st));
-            launch_condensed_op<double>(m->lv.back().t64, m->w_p, m->w_q, st);
-            launch_dot2<double>(m->w_q, m->w_p, nullptr, n, m->partials, m->counter, m->scal + SC_QP, st);
-            launch_pcg_update(m->w_u, m->w_r, m->w_s, m->w_p, m->w_q, m->scal + SC_GAMMA, m->scal + SC_QP, n,
-                              m->partials, m->counter, m->scal + SC_RR, st);
+            const double* cb;
+            double* cx;
+            if (pdt == PMG_F64) vc_coarse_io<double>(m, m->w_r, m->w_z, cb, cx);
+            else vc_coarse_io<float>(m, m->w_r32, m->w_z32, cb, cx);
+            HIPCHK(hipGraphLaunch(m->solver_graphs[gi], st));
+            if ((rc = coarse_cg(m, cb, cx, st))) return rc;
+            HIPCHK(hipGraphLaunch(m->solver_graphs[gi + 1], st));
             if ((rc = read_scalars(m, st))) return rc;
             rr = m->hscal[SC_RR];
             double qp = m->hscal[SC_QP];

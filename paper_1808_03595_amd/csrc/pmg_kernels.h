@@ -50,7 +50,8 @@ void launch_recover(const LevelTabs<double>& tb, const double* f, const double* 
 void launch_pcg_dir(double* p, const double* z, const double* sc, int64_t n, hipStream_t);
 void launch_pcg_update(double* u, double* r, double* s, const double* p, const double* q, const double* gam,
                        const double* qp, int64_t n, double* partials, unsigned* counter, double* out,
-                       hipStream_t);
+                       double* delta_out, hipStream_t st);
+template <typename T> void launch_fill_zero(T* x, int64_t n, hipStream_t st);
 void launch_jacobi(const double* r, const double* dg, double* z, int64_t n, double* partials,
                    unsigned* counter, double* out, hipStream_t);
 void launch_cg_xr(double* x, double* r, const double* p, const double* q, const double* sc, int64_t n,

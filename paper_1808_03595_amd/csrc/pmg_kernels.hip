@@ -1962,9 +1962,11 @@ __global__ void __launch_bounds__(256) k_pcg_update(double* __restrict__ u, doub
                                                     double* __restrict__ s, const double* __restrict__ p,
                                                     const double* __restrict__ q, const double* sc_gamma,
                                                     const double* sc_qp, int64_t n, double* partials,
-                                                    unsigned* counter, double* out) {
+                                                    unsigned* counter, double* out, double* delta_out) {
     __shared__ double red[16];
     const double alpha = sc_gamma[0] / sc_qp[0];
+    // delta <- gamma for the next direction update (Alg. 5)
+    if (delta_out && blockIdx.x == 0 && threadIdx.x == 0) *delta_out = sc_gamma[0];
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double ri = r[i];
@@ -2001,7 +2003,12 @@ __global__ void k_cast_scale(const T* __restrict__ x, U* __restrict__ y, const d
                              int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double s = sc ? (invert ? 1.0 / sc[0] : sc[0]) : 1.0;
+    // invert: 0 y = x s, 1 y = x / s, 2 y = x / sqrt(s), 3 y = x sqrt(s)
+    double s = 1.0;
+    if (sc) {
+        const double v = sc[0];
+        s = invert == 0 ? v : (invert == 1 ? 1.0 / v : (invert == 2 ? 1.0 / sqrt(v) : sqrt(v)));
+    }
     y[i] = (U)((double)x[i] * s);
 }
 
@@ -2668,10 +2675,24 @@ void launch_pcg_dir(double* p, const double* z, const double* sc, int64_t n, hip
 
 void launch_pcg_update(double* u, double* r, double* s, const double* p, const double* q, const double* gam,
                        const double* qp, int64_t n, double* partials, unsigned* counter, double* out,
-                       hipStream_t st) {
+                       double* delta_out, hipStream_t st) {
     hipLaunchKernelGGL(k_pcg_update, dim3(REDUCE_BLOCKS), dim3(256), 0, st, u, r, s, p, q, gam, qp, n, partials,
-                       counter, out);
+                       counter, out, delta_out);
 }
+
+template <typename T>
+__global__ void k_fill_zero(T* __restrict__ x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = (T)0;
+}
+
+// zero fill as a kernel (graph-capturable, unlike a memset node)
+template <typename T>
+void launch_fill_zero(T* x, int64_t n, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_fill_zero<T>, dim3(nblk(n)), dim3(256), 0, st, x, n);
+}
+template void launch_fill_zero<double>(double*, int64_t, hipStream_t);
+template void launch_fill_zero<float>(float*, int64_t, hipStream_t);
 
 void launch_jacobi(const double* r, const double* dg, double* z, int64_t n, double* partials, unsigned* counter,
                    double* out, hipStream_t st) {

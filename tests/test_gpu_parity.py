@@ -271,3 +271,25 @@ def test_pcg_solve_large_degree(gpu, n, p):
     st = g.pcg_solve(torch.as_tensor(f, device=gpu), u, 1e-10, 100, pmg.F64)
     assert st.status == 0 and st.iters == res.iters
     assert rel(u.cpu().numpy(), res.u) <= 1e-9
+
+
+def test_pcg_solve_mixed_repeated(gpu):
+    """Mixed-precision Alg. 5 (FP32 cycle, FP64 CG) solved repeatedly, with
+    FP64 solves and damping changes in between: every solve reaches the
+    tolerance and agrees with the oracle's FP64 solution."""
+    n, p, lam, alpha = (3, 4, 2), 8, 1.0, 1.3
+    g, o = make_pair(n, p, lam, alpha)
+    g.set_cycle(0, 1e-8, 500)
+    f = synth.random_grid(o.shape, 91)
+    ref = solver.solve(o, f, method="kMG", rtol=1e-10, coarse_rtol=1e-8, coarse_maxit=500)
+    df = torch.as_tensor(f, device=gpu)
+    its = []
+    for k, (dt, om) in enumerate([(pmg.F32, None), (pmg.F64, None), (pmg.F32, None), (pmg.F32, [0.9, 1.1]),
+                                  (pmg.F32, None), (pmg.F64, None)]):
+        g.set_damping(om)
+        u = torch.zeros(o.shape, dtype=torch.float64, device=gpu)
+        st = g.pcg_solve(df, u, 1e-10, 100, dt)
+        assert st.status == 0 and st.rel_res <= 1e-10, (k, st.status, st.rel_res)
+        assert rel(u.cpu().numpy(), ref.u) <= 1e-8, k
+        its.append(st.iters)
+    assert its[1] == its[5] == ref.iters
