@@ -61,7 +61,7 @@ struct Level {
     // coarse CG structures when this level is the bottom of the cycle
     CoarseArgs ca{};
     bool has_ca = false;
-    hipGraphExec_t coarse_exec[COARSE_GRAPHS] = {};  // COARSE_RING * 2^k iteration launches
+    hipGraphExec_t coarse_exec[COARSE_GRAPHS + 1] = {};  // [k]: COARSE_RING * k iteration launches
 };
 
 template <typename T> struct Sel;
@@ -254,24 +254,6 @@ int build_coarse(pmg_mesh* m, Level& lev) {
     HIPCHK(hipMemset(a.S, 0, 2 * sizeof(CoarseState)));
     HIPCHK(hipMemset(a.stat, 0, 2 * sizeof(int)));
     a.iters = m->d_coarse_iters;
-    // graphs of COARSE_RING * 2^k iteration launches
-    for (int k = 0; N0 > 0 && k < COARSE_GRAPHS; ++k) {
-        hipGraph_t g = nullptr;
-        HIPCHK(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
-        for (int j = 0; j < (COARSE_RING << k); ++j) {
-            hipError_t e = launch_coarse_iter(a, j % COARSE_RING, m->cap_stream);
-            if (e != hipSuccess) {
-                hipGraph_t junk = nullptr;
-                (void)hipStreamEndCapture(m->cap_stream, &junk);
-                if (junk) (void)hipGraphDestroy(junk);
-                return fail(PMG_EHIP, std::string("coarse graph capture: ") + hipGetErrorString(e));
-            }
-        }
-        HIPCHK(hipStreamEndCapture(m->cap_stream, &g));
-        hipError_t e = hipGraphInstantiate(&lev.coarse_exec[k], g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return fail(PMG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    }
     lev.has_ca = true;
     return 0;
 }
@@ -529,13 +511,30 @@ void smooth_add(Level& L, const T* r, T* u, hipStream_t st) {
 // solve) is queued, and more chunks follow until the device reports
 // convergence or maxit; without one, enough chunks for maxit are queued
 // and nothing is synchronised.  b and x are level-0 skeleton arrays.
-// Queue `units` * COARSE_RING iteration launches as a few graph launches.
-int coarse_launch_units(Level& L0, long units, hipStream_t st) {
+// Queue `units` * COARSE_RING iteration launches: one graph of exactly that
+// many launches when units <= COARSE_GRAPHS (captured on first use; the
+// graph launches run back to back, separate graph launches do not).
+int coarse_launch_units(pmg_mesh* m, Level& L0, long units, hipStream_t st) {
     while (units > 0) {
-        int k = COARSE_GRAPHS - 1;
-        while (k > 0 && (1L << k) > units) --k;
+        const int k = (int)std::min<long>(units, COARSE_GRAPHS);
+        if (!L0.coarse_exec[k]) {
+            HIPCHK(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = hipSuccess;
+            for (int j = 0; j < k * COARSE_RING && e == hipSuccess; ++j)
+                e = launch_coarse_iter(L0.ca, j % COARSE_RING, m->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(m->cap_stream, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return fail(PMG_EHIP, std::string("coarse graph capture: ") +
+                                          hipGetErrorString(e != hipSuccess ? e : e2));
+            }
+            e = hipGraphInstantiate(&L0.coarse_exec[k], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return fail(PMG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
         HIPCHK(hipGraphLaunch(L0.coarse_exec[k], st));
-        units -= 1L << k;
+        units -= k;
     }
     return 0;
 }
@@ -548,11 +547,11 @@ int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st) {
     const long need = (long)m->coarse_maxit + 2;  // launches for maxit updates
     const long umax = (need + COARSE_RING - 1) / COARSE_RING;
     int rc;
-    if (!(m->coarse_rtol > 0.0)) return coarse_launch_units(L0, umax, st);
+    if (!(m->coarse_rtol > 0.0)) return coarse_launch_units(m, L0, umax, st);
     long units = std::min(umax, std::max(1L, ((long)m->coarse_last + 3 + COARSE_RING - 1) / COARSE_RING));
     long launched = 0;
     while (true) {
-        if ((rc = coarse_launch_units(L0, units - launched, st))) return rc;
+        if ((rc = coarse_launch_units(m, L0, units - launched, st))) return rc;
         launched = units;
         HIPCHK(hipMemcpyAsync(m->h_cstat, a.stat, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));

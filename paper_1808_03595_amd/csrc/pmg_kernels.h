@@ -14,7 +14,7 @@ void set_mfma_min_degree(int p);
 constexpr int COARSE_RING = 6;
 // length of the restriction work buffer (coarse partial sums + row pass)
 int64_t restrict_work_len(const Layout& Lf, const Layout& Lc);
-constexpr int COARSE_GRAPHS = 5;   // graphs of COARSE_RING * 2^k launches
+constexpr int COARSE_GRAPHS = 32;  // graphs of COARSE_RING * k launches, k = 1..32, built on first use
 hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, double* out, int maxit, double rtol,
                               hipStream_t st);
 hipError_t launch_coarse_iter(const CoarseArgs& a, int j, hipStream_t st);
