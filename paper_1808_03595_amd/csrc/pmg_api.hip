@@ -1,6 +1,9 @@
 // C ABI of the condensed p-multigrid solver: mesh handle, level
 // hierarchy, V-cycle (Alg. 3), MG (Alg. 4) and ipCG (Alg. 5) orchestration.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <immintrin.h>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -102,7 +105,6 @@ struct pmg_mesh {
     int hmg_nu = 1;
     // coarse CG counters shared by all bottom levels
     int* d_coarse_iters = nullptr;
-    int* h_cstat = nullptr;             // pinned copy of the coarse done flag and count
     hipStream_t cap_stream = nullptr;   // private stream for graph capture
     // Alg. 5 iteration graphs per preconditioner precision: [2 pdt + 0] up to
     // the coarse solve, [2 pdt + 1] after it; rebuilt after any change of
@@ -119,6 +121,14 @@ struct pmg_mesh {
     unsigned* counter = nullptr;
     double* scal = nullptr;
     double* hscal = nullptr;  // pinned host copy of the scalars
+    // notice block in mapped host memory (host and device addresses), the
+    // device-side publication counter and the host-side expectations
+    HostMail* hmail = nullptr;
+    HostMail* dmail = nullptr;
+    int64_t* d_pubcnt = nullptr;
+    int64_t pub_expected = 0;
+    int64_t coarse_id = 0;
+    int64_t mark_seq = 0;
     std::vector<void*> allocs;
 
     template <typename T>
@@ -254,6 +264,7 @@ int build_coarse(pmg_mesh* m, Level& lev) {
     HIPCHK(hipMemset(a.S, 0, 2 * sizeof(CoarseState)));
     HIPCHK(hipMemset(a.stat, 0, 2 * sizeof(int)));
     a.iters = m->d_coarse_iters;
+    a.mail = m->dmail;
     lev.has_ca = true;
     return 0;
 }
@@ -413,7 +424,6 @@ int build_mesh(pmg_mesh* m) {
     if (rc) return rc;
     if ((rc = m->alloc(&m->d_coarse_iters, 1))) return rc;
     HIPCHK(hipMemset(m->d_coarse_iters, 0, sizeof(int)));
-    HIPCHK(hipHostMalloc((void**)&m->h_cstat, 2 * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
     for (size_t l = 0; l < degs.size(); ++l) {
         Level& L = m->lv[l];
@@ -460,6 +470,13 @@ int build_mesh(pmg_mesh* m) {
     HIPCHK(hipMemset(m->counter, 0, 4 * sizeof(unsigned)));
     HIPCHK(hipMemset(m->scal, 0, SC_N * sizeof(double)));
     HIPCHK(hipHostMalloc((void**)&m->hscal, SC_N * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&m->hmail, sizeof(HostMail), hipHostMallocMapped | hipHostMallocCoherent));
+    std::memset((void*)m->hmail, 0, sizeof(HostMail));
+    HIPCHK(hipHostGetDevicePointer((void**)&m->dmail, m->hmail, 0));
+    if ((rc = m->alloc(&m->d_pubcnt, 1))) return rc;
+    HIPCHK(hipMemset(m->d_pubcnt, 0, sizeof(int64_t)));
+    for (auto* v : {&m->lv, &m->hlv})
+        for (Level& l : *v) l.ca.mail = m->dmail;
     // large dynamic LDS for the element / star kernels
     HIPCHK(init_kernel_attributes());
     HIPCHK(hipDeviceSynchronize());
@@ -468,9 +485,40 @@ int build_mesh(pmg_mesh* m) {
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-int read_scalars(pmg_mesh* m, hipStream_t st) {
-    HIPCHK(hipMemcpyAsync(m->hscal, m->scal, SC_N * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+// Wait until `ready()` holds, polling the mapped notice block; the stream
+// is queried now and then so that a device error or a stream that drained
+// without the notice ends the wait with an error instead of spinning.
+template <typename P>
+int host_wait(hipStream_t st, P ready) {
+    const auto t0 = std::chrono::steady_clock::now();
+    unsigned k = 0;
+    while (!ready()) {
+        _mm_pause();
+        if ((++k & 255) == 0) {
+            const hipError_t e = hipStreamQuery(st);
+            if (e != hipSuccess && e != hipErrorNotReady)
+                return fail(PMG_EHIP, std::string("device error while waiting: ") + hipGetErrorString(e));
+            if (e == hipSuccess) {
+                std::atomic_thread_fence(std::memory_order_acquire);
+                if (ready()) break;
+                return fail(PMG_EHIP, "stream finished without the expected device notice");
+            }
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(120))
+                return fail(PMG_EHIP, "timed out waiting for the device");
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return 0;
+}
+
+// Scalars of the outer solver on the host: the device publishes them to
+// the notice block (k_publish, queued here unless `queued`), the host polls.
+int read_scalars(pmg_mesh* m, hipStream_t st, bool queued = false) {
+    if (!queued) launch_publish(m->scal, SC_N, m->d_pubcnt, m->dmail, st);
+    const int64_t want = ++m->pub_expected;
+    int rc = host_wait(st, [&] { return m->hmail->seq >= want; });
+    if (rc) return rc;
+    for (int k = 0; k < SC_N; ++k) m->hscal[k] = m->hmail->sc[k];
     return 0;
 }
 
@@ -542,7 +590,8 @@ int coarse_launch_units(pmg_mesh* m, Level& L0, long units, hipStream_t st) {
 int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st) {
     Level& L0 = *m->act[0];
     CoarseArgs& a = L0.ca;
-    HIPCHK(launch_coarse_init(a, b, x, m->coarse_maxit, m->coarse_rtol, st));
+    const int64_t id = ++m->coarse_id;
+    HIPCHK(launch_coarse_init(a, b, x, m->coarse_maxit, m->coarse_rtol, id, st));
     if (a.N0 == 0) return 0;
     const long need = (long)m->coarse_maxit + 2;  // launches for maxit updates
     const long umax = (need + COARSE_RING - 1) / COARSE_RING;
@@ -553,10 +602,14 @@ int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st) {
     while (true) {
         if ((rc = coarse_launch_units(m, L0, units - launched, st))) return rc;
         launched = units;
-        HIPCHK(hipMemcpyAsync(m->h_cstat, a.stat, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (m->h_cstat[0]) {
-            m->coarse_last = m->h_cstat[1];
+        // the finishing launch reports (id, updates); a marker after the
+        // queued launches tells that they all ran without finishing
+        const int64_t mk = ++m->mark_seq;
+        launch_mark(m->dmail, mk, st);
+        HostMail* hm = m->hmail;
+        if ((rc = host_wait(st, [&] { return hm->cseq == id || hm->mseq >= mk; }))) return rc;
+        if (hm->cseq == id) {
+            m->coarse_last = hm->cit;
             return 0;
         }
         if (launched >= umax) return fail(PMG_EHIP, "coarse solver did not finish within maxit");
@@ -771,7 +824,7 @@ void pmg_destroy_mesh(pmg_mesh* m) {
         if (g) (void)hipGraphExecDestroy(g);
     for (void* q : m->allocs) hipFree(q);
     if (m->hscal) hipHostFree(m->hscal);
-    if (m->h_cstat) (void)hipHostFree(m->h_cstat);
+    if (m->hmail) (void)hipHostFree((void*)m->hmail);
     if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
     delete m;
 }
@@ -996,8 +1049,10 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
     std::memset(&stats, 0, sizeof(stats));
     {
         int dummy;
-        int rc0 = coarse_stats(m, st, &dummy);
+        int rc0 = coarse_stats(m, st, &dummy);  // synchronises the stream
         if (rc0) return rc0;
+        std::atomic_thread_fence(std::memory_order_acquire);
+        m->pub_expected = m->hmail->seq;          // resynchronise the notice count
     }
     hipEvent_t ev[4];
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
@@ -1057,6 +1112,7 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
                     launch_dot2<double>(m->w_q, m->w_p, nullptr, n, m->partials, m->counter, m->scal + SC_QP, s);
                     launch_pcg_update(m->w_u, m->w_r, m->w_s, m->w_p, m->w_q, m->scal + SC_GAMMA, m->scal + SC_QP,
                                       n, m->partials, m->counter, m->scal + SC_RR, m->scal + SC_DELTA, s);
+                    launch_publish(m->scal, SC_N, m->d_pubcnt, m->dmail, s);
                     return 0;
                 };
                 if ((rc = capture_graph(m, &m->solver_graphs[gi], part_a)) ||
@@ -1070,7 +1126,7 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
             HIPCHK(hipGraphLaunch(m->solver_graphs[gi], st));
             if ((rc = coarse_cg(m, cb, cx, st))) return rc;
             HIPCHK(hipGraphLaunch(m->solver_graphs[gi + 1], st));
-            if ((rc = read_scalars(m, st))) return rc;
+            if ((rc = read_scalars(m, st, true))) return rc;
             rr = m->hscal[SC_RR];
             double qp = m->hscal[SC_QP];
             if (!(qp > 0.0) || !std::isfinite(rr)) {

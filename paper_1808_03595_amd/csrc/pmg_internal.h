@@ -147,10 +147,22 @@ namespace pmg {
 struct CoarseState {
     double gamma, alpha, gamma0, rtol2;
     double* out;     // skeleton array holding the iterate x
+    int64_t id;      // coarse solve number (reported to the host when done)
     int it;          // completed updates; -1 before the first launch
     int done;
     int maxit;
     int pad;
+};
+
+// Mapped, coherent host memory the device writes completion notices to, so
+// the host can wait by polling instead of a stream synchronisation.
+struct HostMail {
+    volatile int64_t seq;    // number of scalar publications so far
+    volatile int64_t cseq;   // id of the last coarse solve that finished
+    volatile int64_t mseq;   // last marker written after queued coarse launches
+    volatile int cit;        // update count of that coarse solve
+    int pad;
+    double sc[16];           // the published scalars
 };
 
 struct CoarseArgs {
@@ -171,6 +183,7 @@ struct CoarseArgs {
     int* stat;            // [2]: done flag and update count of the last solve
     int* iters;           // accumulated iteration count
     int blocks;           // workgroups of one iteration launch
+    HostMail* mail;       // device address of the host notice block (or null)
 };
 
 }  // namespace pmg

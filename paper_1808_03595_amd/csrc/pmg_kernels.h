@@ -16,7 +16,9 @@ constexpr int COARSE_RING = 6;
 int64_t restrict_work_len(const Layout& Lf, const Layout& Lc);
 constexpr int COARSE_GRAPHS = 32;  // graphs of COARSE_RING * k launches, k = 1..32, built on first use
 hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, double* out, int maxit, double rtol,
-                              hipStream_t st);
+                              int64_t id, hipStream_t st);
+void launch_publish(const double* sc, int n, int64_t* cnt, HostMail* mail, hipStream_t st);
+void launch_mark(HostMail* mail, int64_t v, hipStream_t st);
 hipError_t launch_coarse_iter(const CoarseArgs& a, int j, hipStream_t st);
 int coarse_blocks(int ne, int p0);
 

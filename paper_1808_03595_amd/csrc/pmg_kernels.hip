@@ -2068,7 +2068,7 @@ __global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ z, con
 // r = b at the unknowns, all other vectors and the iterate x = out zero;
 // state "before the first launch".
 __global__ void k_coarse_init(CoarseArgs a, const double* __restrict__ b, double* __restrict__ out, int maxit,
-                              double rtol) {
+                              double rtol, int64_t id) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t s = t; s < a.lay.len; s += stride) {
@@ -2085,6 +2085,7 @@ __global__ void k_coarse_init(CoarseArgs a, const double* __restrict__ b, double
         s0.gamma = s0.alpha = s0.gamma0 = 0.0;
         s0.rtol2 = rtol * rtol;
         s0.out = out;
+        s0.id = id;
         s0.it = -1;
         s0.done = 0;
         s0.maxit = maxit;
@@ -2231,6 +2232,11 @@ __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j) {
             a.stat[0] = 1;
             a.stat[1] = si.it;
             atomicAdd(a.iters, si.it);
+            if (a.mail) {
+                a.mail->cit = si.it;
+                __threadfence_system();
+                a.mail->cseq = si.id;
+            }
         }
         return;
     }
@@ -2680,6 +2686,30 @@ void launch_pcg_update(double* u, double* r, double* s, const double* p, const d
                        counter, out, delta_out);
 }
 
+// Copy the solver scalars to the host notice block, then bump its sequence
+// number (the count kept in device memory at *cnt).
+__global__ void k_publish(const double* __restrict__ sc, int n, int64_t* cnt, HostMail* mail) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int k = 0; k < n; ++k) mail->sc[k] = sc[k];
+    const int64_t v = *cnt + 1;
+    *cnt = v;
+    __threadfence_system();
+    mail->seq = v;
+}
+
+__global__ void k_mark(HostMail* mail, int64_t v) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __threadfence_system();
+    mail->mseq = v;
+}
+
+void launch_publish(const double* sc, int n, int64_t* cnt, HostMail* mail, hipStream_t st) {
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, st, sc, n, cnt, mail);
+}
+void launch_mark(HostMail* mail, int64_t v, hipStream_t st) {
+    hipLaunchKernelGGL(k_mark, dim3(1), dim3(64), 0, st, mail, v);
+}
+
 template <typename T>
 __global__ void k_fill_zero(T* __restrict__ x, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2746,9 +2776,9 @@ void launch_mlp_adam(float* prm, const float* g, float* m, float* v, int n, floa
 }
 
 hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, double* out, int maxit, double rtol,
-                              hipStream_t st) {
+                              int64_t id, hipStream_t st) {
     const int blocks = (int)std::min<int64_t>(std::max<int64_t>((a.lay.len + 255) / 256, 1), 1024);
-    hipLaunchKernelGGL(k_coarse_init, dim3(blocks), dim3(256), 0, st, a, b, out, maxit, rtol);
+    hipLaunchKernelGGL(k_coarse_init, dim3(blocks), dim3(256), 0, st, a, b, out, maxit, rtol, id);
     return hipGetLastError();
 }
 
