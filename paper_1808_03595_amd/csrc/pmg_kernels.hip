@@ -928,7 +928,9 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
     const T* S3 = tb.st_SP[2] + (size_t)v3 * 256;
     const int c1 = v1 * p, c2 = v2 * p, c3 = v3 * p;
     // S in both operand patterns: Sb[s] = S[row(q,s)][j], Sa[s] = S[j][row(q,s)]
-    T Sb1[4], Sb2[4], Sb3[4], Sa1[4], Sa2[4], Sa3[4];
+    // (the A-pattern copies are loaded again for the back transforms, so
+    // that they do not occupy registers during the eigenspace pass)
+    T Sb1[4], Sb2[4], Sb3[4];
     T f1[4], f2[4], f3[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -936,9 +938,6 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
         Sb1[s] = S1[k * 16 + j];
         Sb2[s] = S2[k * 16 + j];
         Sb3[s] = S3[k * 16 + j];
-        Sa1[s] = S1[j * 16 + k];
-        Sa2[s] = S2[j * 16 + k];
-        Sa3[s] = S3[j * 16 + k];
         // face residuals as A operands: F[a = j][b = k]
         const int oa = j - c, ob = k - c;
         const bool ok = active && j < nS && k < nS;
@@ -975,19 +974,20 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
     // eigenspace pass on the 4x4x4 tile (t1, t2, t3) of this lane
     const int t1 = lane & 3, t2 = (lane >> 2) & 3, t3 = lane >> 4;
     const int k1b = 4 * t1, k2b = 4 * t2, k3b = 4 * t3;
-    T a1[4], a2[4], a3[4], l3[4], E12[4][4], G3r[4][4];
+    // (the lambda + l1 + l2 sums are formed on the fly and the G3 values
+    // read from LDS inside the loop, to keep the register count low)
+    T a1[4], a2[4], a3[4], l1[4], l2[4], l3[4];
     T H1p[4][4], H2p[4][4], H3p[4][4];
     {
         const T* L1 = tb.st_lamP[0] + v1 * 16;
         const T* L2 = tb.st_lamP[1] + v2 * 16;
         const T* L3 = tb.st_lamP[2] + v3 * 16;
-        T l1[4], l2[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             a1[i] = S1[c * 16 + k1b + i];
             a2[i] = S2[c * 16 + k2b + i];
             a3[i] = S3[c * 16 + k3b + i];
-            l1[i] = L1[k1b + i];
+            l1[i] = L1[k1b + i] + tb.lam;
             l2[i] = L2[k2b + i];
             l3[i] = L3[k3b + i];
         }
@@ -995,8 +995,6 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
         for (int b = 0; b < 4; ++b)
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
-                E12[b][a] = tb.lam + l2[b] + l1[a];
-                G3r[b][a] = sm[512 + (k2b + b) * 16 + k1b + a];
                 H1p[b][a] = 0;
                 H2p[b][a] = 0;
                 H3p[b][a] = 0;
@@ -1015,8 +1013,9 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
         for (int i2 = 0; i2 < 4; ++i2)
 #pragma unroll
             for (int i1 = 0; i1 < 4; ++i1) {
-                T e = a1[i1] * g1r[i2] + a2[i2] * g2r[i1] + a3[i3] * G3r[i2][i1];
-                T V = e * M::rcp(E12[i2][i1] + l3[i3]);
+                const T g3 = sm[512 + (k2b + i2) * 16 + k1b + i1];
+                T e = a1[i1] * g1r[i2] + a2[i2] * g2r[i1] + a3[i3] * g3;
+                T V = e * M::rcp(l1[i1] + l2[i2] + l3[i3]);
                 H1p[i3][i2] += a1[i1] * V;
                 H2p[i3][i1] += a2[i2] * V;
                 H3p[i2][i1] += a3[i3] * V;
@@ -1048,6 +1047,14 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
         h3[s] = z;  // H3[k2 = j][k1 = k]
     }
     // U1 = S3 (H1 S2^T), U2 = S3 (H2 S1^T), U3 = S2 (H3 S1^T)
+    T Sa1[4], Sa2[4], Sa3[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = M::row(q, s);
+        Sa1[s] = S1[j * 16 + k];
+        Sa2[s] = S2[j * 16 + k];
+        Sa3[s] = S3[j * 16 + k];
+    }
     v4_to<T>(gemm16<T>(h1, Sa2), t);
     v4 u1 = gemm16<T>(Sa3, t);
     v4_to<T>(gemm16<T>(h2, Sa1), t);
