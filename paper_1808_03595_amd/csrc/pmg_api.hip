@@ -252,6 +252,7 @@ int build_coarse(pmg_mesh* m, Level& lev) {
     int rc;
     if ((rc = m->upload(&a.diag, dg))) return rc;
     const size_t nv = (size_t)L0.len;
+    a.X = lev.u64;  // the V-cycle reads the coarse solution from there
     if ((rc = m->alloc(&a.p, nv))) return rc;
     for (int k = 0; k < 2; ++k)
         if ((rc = m->alloc(&a.R[k], nv)) || (rc = m->alloc(&a.Q[k], nv))) return rc;
@@ -591,12 +592,21 @@ int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st) {
     Level& L0 = *m->act[0];
     CoarseArgs& a = L0.ca;
     const int64_t id = ++m->coarse_id;
-    HIPCHK(launch_coarse_init(a, b, x, m->coarse_maxit, m->coarse_rtol, id, st));
-    if (a.N0 == 0) return 0;
+    // the iterations update the level's own array a.X; a copy follows for
+    // any other destination
+    auto deliver = [&]() -> int {
+        if (x != a.X) HIPCHK(hipMemcpyAsync(x, a.X, (size_t)a.lay.len * sizeof(double), hipMemcpyDeviceToDevice, st));
+        return 0;
+    };
+    HIPCHK(launch_coarse_init(a, b, m->coarse_maxit, m->coarse_rtol, id, st));
+    if (a.N0 == 0) return deliver();
     const long need = (long)m->coarse_maxit + 2;  // launches for maxit updates
     const long umax = (need + COARSE_RING - 1) / COARSE_RING;
     int rc;
-    if (!(m->coarse_rtol > 0.0)) return coarse_launch_units(m, L0, umax, st);
+    if (!(m->coarse_rtol > 0.0)) {
+        if ((rc = coarse_launch_units(m, L0, umax, st))) return rc;
+        return deliver();
+    }
     long units = std::min(umax, std::max(1L, ((long)m->coarse_last + 3 + COARSE_RING - 1) / COARSE_RING));
     long launched = 0;
     while (true) {
@@ -610,7 +620,7 @@ int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st) {
         if ((rc = host_wait(st, [&] { return hm->cseq == id || hm->mseq >= mk; }))) return rc;
         if (hm->cseq == id) {
             m->coarse_last = hm->cit;
-            return 0;
+            return deliver();
         }
         if (launched >= umax) return fail(PMG_EHIP, "coarse solver did not finish within maxit");
         units = std::min(umax, launched + std::max(1L, launched / 2));

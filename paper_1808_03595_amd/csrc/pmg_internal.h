@@ -146,7 +146,6 @@ namespace pmg {
 // (written by block 0 of each launch into the other ring slot).
 struct CoarseState {
     double gamma, alpha, gamma0, rtol2;
-    double* out;     // skeleton array holding the iterate x
     int64_t id;      // coarse solve number (reported to the host when done)
     int it;          // completed updates; -1 before the first launch
     int done;
@@ -175,11 +174,12 @@ struct CoarseArgs {
     const double* diag;   // diagonal of the operator at unknowns, 0 at every other slot
     const double* el_m[3];  // level-0 element tables
     const double* el_L[3];
+    double* X;            // the iterate x (level-0 skeleton array, fixed per mesh)
     double* p;            // search direction, updated in place by the owning element
     double *R[2], *Q[2];  // ping-pong residual and q = A p
     double *W[3];         // rotating accumulators of w = A z
     double *P[2];         // [2 * blocks] per-block partial sums (r.z, w.z)
-    CoarseState* S;       // [2]; S.out is the iterate x (the caller's output array)
+    CoarseState* S;       // [2] scalar state, ping-pong
     int* stat;            // [2]: done flag and update count of the last solve
     int* iters;           // accumulated iteration count
     int blocks;           // workgroups of one iteration launch

@@ -8,15 +8,14 @@ namespace pmg {
 constexpr int REDUCE_BLOCKS = 512;
 
 hipError_t init_kernel_attributes();
-void set_mfma_min_degree(int p);
 // Coarse CG (launch-per-iteration form): the init kernel, then iteration
 // launches with ring index j = 0, 1, ..., COARSE_RING - 1, 0, ...
 constexpr int COARSE_RING = 6;
 // length of the restriction work buffer (coarse partial sums + row pass)
 int64_t restrict_work_len(const Layout& Lf, const Layout& Lc);
 constexpr int COARSE_GRAPHS = 32;  // graphs of COARSE_RING * k launches, k = 1..32, built on first use
-hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, double* out, int maxit, double rtol,
-                              int64_t id, hipStream_t st);
+hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, int maxit, double rtol, int64_t id,
+                              hipStream_t st);
 void launch_publish(const double* sc, int n, int64_t* cnt, HostMail* mail, hipStream_t st);
 void launch_mark(HostMail* mail, int64_t v, hipStream_t st);
 hipError_t launch_coarse_iter(const CoarseArgs& a, int j, hipStream_t st);

@@ -1088,6 +1088,178 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
 }
 
 // ---------------------------------------------------------------------------
+// Star smoother for small stars, n_S = 2p - 1 <= 8 (p <= 4).  The star
+// matrices are padded to NSP x NSP (NSP = 4 for p <= 2, else 8; identity S,
+// eigenvalue 1, zero faces and a = 0 in the padding, so the padding carries
+// zeros through every step), which wastes far less than the 16 x 16 tiles
+// of the matrix-core kernel.  Every step of Alg. 1 runs on VALU with its
+// operands in LDS.  A group of NSP^2 lanes handles one star (64 / NSP^2
+// stars per wavefront): lane (i, j) of a group computes entry (i, j) of
+// the three faces in each 2D transform and, in the eigenspace pass, the
+// line k2 = i, k1 = j over all k3 (so the k3-contraction H3 stays in the
+// lane and H1, H2 are read back from the stored V).
+// ---------------------------------------------------------------------------
+template <int NSP>
+struct SmallStar {
+    static constexpr int G = NSP * NSP;                 // lanes per star
+    static constexpr int SPB = 256 / G;                 // stars per workgroup
+    static constexpr int PER = 12 * G + NSP * G + 3 * NSP;  // LDS entries per star
+};
+
+template <typename T, int NSP>
+__global__ void __launch_bounds__(256) k_smoother_small(LevelTabs<T> tb, const T* __restrict__ r,
+                                                        T* __restrict__ du, T omega) {
+    typedef SmallStar<NSP> SS;
+    constexpr int G = SS::G;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sS = reinterpret_cast<T*>(smem_raw) + (threadIdx.x / G) * SS::PER;  // S_d, [d][i][k]
+    T* sF = sS + 3 * G;       // faces, later H_d
+    T* sX = sS + 6 * G;       // F S_C, later H S_C^T
+    T* sY = sS + 9 * G;       // G_d
+    T* sV = sS + 12 * G;      // V[k3][k2][k1]
+    T* sL = sV + NSP * G;     // eigenvalues l_d[k]
+    const int ls = threadIdx.x % G, i = ls / NSP, j = ls % NSP;
+    const Layout& L = tb.lay;
+    const int p = L.p, nS = 2 * p - 1, c = p - 1;
+    const int nv1 = L.n[0] + 1, nv2 = L.n[1] + 1, nv3 = L.n[2] + 1;
+    const int star = blockIdx.x * SS::SPB + (int)(threadIdx.x / G);
+    bool active = star < nv1 * nv2 * nv3;
+    int v1 = 0, v2 = 0, v3 = 0;
+    if (active) {
+        v1 = star % nv1;
+        v2 = (star / nv1) % nv2;
+        v3 = star / (nv1 * nv2);
+        bool b1 = v1 == 0 || v1 == L.n[0], b2 = v2 == 0 || v2 == L.n[1], b3 = v3 == 0 || v3 == L.n[2];
+        if (b1 && b2 && b3) active = false;  // corner: all three planes Dirichlet
+    }
+    const int c1 = v1 * p, c2 = v2 * p, c3 = v3 * p;
+    const bool in = i < nS && j < nS;
+    const int oa = i - c, ob = j - c;
+    {
+        T s1 = (i == j) ? T(1) : T(0), s2 = s1, s3 = s1;
+        if (in) {
+            const int o = i * nS + j;
+            s1 = tb.st_S[0][(size_t)v1 * nS * nS + o];
+            s2 = tb.st_S[1][(size_t)v2 * nS * nS + o];
+            s3 = tb.st_S[2][(size_t)v3 * nS * nS + o];
+        }
+        sS[ls] = s1;
+        sS[G + ls] = s2;
+        sS[2 * G + ls] = s3;
+        if (ls < 3 * NSP) {
+            const int d = ls / NSP, k = ls - d * NSP;
+            const int vd = d == 0 ? v1 : (d == 1 ? v2 : v3);
+            sL[ls] = k < nS ? pick3(d, tb.st_lam[0], tb.st_lam[1], tb.st_lam[2])[(size_t)vd * nS + k] : T(1);
+        }
+        // faces: F1[a][b] at (c1, c2 + ob, c3 + oa), F2 at (c1 + ob, c2, c3 + oa),
+        // F3 at (c1 + ob, c2 + oa, c3); a = i, b = j
+        T x1 = 0, x2 = 0, x3 = 0;
+        if (active && in) {
+            const int i1 = c1 + ob, i2 = c2 + ob, i3 = c3 + oa, i2a = c2 + oa;
+            if (i2 >= 0 && i2 < L.N[1] && i3 >= 0 && i3 < L.N[2])
+                x1 = r[L.plane0(v1) + (int64_t)i3 * L.pitch[0] + i2];
+            if (i1 >= 0 && i1 < L.N[0] && i3 >= 0 && i3 < L.N[2])
+                x2 = r[L.plane1(v2) + (int64_t)i3 * L.pitch[1] + i1];
+            if (i1 >= 0 && i1 < L.N[0] && i2a >= 0 && i2a < L.N[1])
+                x3 = r[L.plane2(v3) + (int64_t)i2a * L.pitch[2] + i1];
+        }
+        sF[ls] = x1;
+        sF[G + ls] = x2;
+        sF[2 * G + ls] = x3;
+    }
+    __syncthreads();
+    // face f: (row matrix S_R, column matrix S_C) = (S3, S2), (S3, S1), (S2, S1)
+    // X_f = F_f S_C
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const T* Fr = sF + f * G + i * NSP;
+        const T* Sc = sS + (f == 0 ? G : 0);
+        T acc = 0;
+#pragma unroll
+        for (int b = 0; b < NSP; ++b) acc += Fr[b] * Sc[b * NSP + j];
+        sX[f * G + ls] = acc;
+    }
+    __syncthreads();
+    // G_f = S_R^T X_f
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const T* Sr = sS + (f == 2 ? G : 2 * G);
+        const T* X = sX + f * G;
+        T acc = 0;
+#pragma unroll
+        for (int a = 0; a < NSP; ++a) acc += Sr[a * NSP + i] * X[a * NSP + j];
+        sY[f * G + ls] = acc;
+    }
+    __syncthreads();
+    // eigenspace pass on the line (k1, k2) = (j, i): V = (a1 G1 + a2 G2 + a3 G3) / D
+    {
+        const T a1 = sS[c * NSP + j], a2 = sS[G + c * NSP + i];
+        const T l12 = tb.lam + sL[j] + sL[NSP + i];
+        const T g3 = sY[2 * G + ls];
+        T h3 = 0;
+#pragma unroll
+        for (int k3 = 0; k3 < NSP; ++k3) {
+            const T a3 = sS[2 * G + c * NSP + k3];
+            const T e = a1 * sY[k3 * NSP + i] + a2 * sY[G + k3 * NSP + j] + a3 * g3;
+            const T V = e * Mfma<T>::rcp(l12 + sL[2 * NSP + k3]);
+            sV[k3 * G + ls] = V;
+            h3 += a3 * V;
+        }
+        __syncthreads();
+        // H1[k3 = i][k2 = j] = sum_k1 a1 V, H2[k3 = i][k1 = j] = sum_k2 a2 V
+        T h1 = 0, h2 = 0;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) {
+            h1 += sS[c * NSP + k] * sV[i * G + j * NSP + k];
+            h2 += sS[G + c * NSP + k] * sV[i * G + k * NSP + j];
+        }
+        sF[ls] = h1;
+        sF[G + ls] = h2;
+        sF[2 * G + ls] = h3;  // H3[k2 = i][k1 = j]
+    }
+    __syncthreads();
+    // X_f = H_f S_C^T
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const T* Hr = sF + f * G + i * NSP;
+        const T* Sc = sS + (f == 0 ? G : 0);
+        T acc = 0;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) acc += Hr[k] * Sc[j * NSP + k];
+        sX[f * G + ls] = acc;
+    }
+    __syncthreads();
+    if (!active || !in) return;
+    // U_f = S_R X_f, weights, damping, scatter
+    T u[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const T* Sr = sS + (f == 2 ? G : 2 * G) + i * NSP;
+        const T* X = sX + f * G;
+        T acc = 0;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) acc += Sr[k] * X[k * NSP + j];
+        u[f] = acc;
+    }
+    const T wt = omega * tb.st_w[i] * tb.st_w[j];
+    {
+        const int i1 = c1, i2 = c2 + ob, i3 = c3 + oa;
+        if (i2 >= 0 && i2 < L.N[1] && i3 >= 0 && i3 < L.N[2] && !is_dir(L, i1, i2, i3))
+            unsafeAtomicAdd(du + L.plane0(v1) + (int64_t)i3 * L.pitch[0] + i2, wt * u[0]);
+    }
+    if (ob != 0) {  // without the x3-axis line (stored in family 0)
+        const int i1 = c1 + ob, i2 = c2, i3 = c3 + oa;
+        if (i1 >= 0 && i1 < L.N[0] && i3 >= 0 && i3 < L.N[2] && !is_dir(L, i1, i2, i3))
+            unsafeAtomicAdd(du + L.plane1(v2) + (int64_t)i3 * L.pitch[1] + i1, wt * u[1]);
+    }
+    if (ob != 0 && oa != 0) {  // without both axis lines
+        const int i1 = c1 + ob, i2 = c2 + oa, i3 = c3;
+        if (i1 >= 0 && i1 < L.N[0] && i2 >= 0 && i2 < L.N[1] && !is_dir(L, i1, i2, i3))
+            unsafeAtomicAdd(du + L.plane2(v3) + (int64_t)i2 * L.pitch[2] + i1, wt * u[2]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Star smoother for n_S = 2p - 1 > 16 (p >= 9).  The stars of a level are
 // processed together, one step of Alg. 1 per launch, with the np x np
 // matrices (np = 16 ceil(n_S / 16), zero padded) of every star and face in
@@ -2072,10 +2244,9 @@ __global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ z, con
 //          P[(j+1)%2], S[(j+1)%2]; p and x in place (owners)
 // A chunk of COARSE_RING launches is captured once as a HIP graph.
 // ---------------------------------------------------------------------------
-// r = b at the unknowns, all other vectors and the iterate x = out zero;
-// state "before the first launch".
-__global__ void k_coarse_init(CoarseArgs a, const double* __restrict__ b, double* __restrict__ out, int maxit,
-                              double rtol, int64_t id) {
+// r = b at the unknowns, all other vectors and the iterate x zero; state
+// "before the first launch".
+__global__ void k_coarse_init(CoarseArgs a, const double* __restrict__ b, int maxit, double rtol, int64_t id) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t s = t; s < a.lay.len; s += stride) {
@@ -2085,13 +2256,12 @@ __global__ void k_coarse_init(CoarseArgs a, const double* __restrict__ b, double
         a.W[1][s] = 0.0;
         a.W[2][s] = 0.0;
         a.p[s] = 0.0;
-        out[s] = 0.0;
+        a.X[s] = 0.0;
     }
     if (t == 0) {
         CoarseState s0;
         s0.gamma = s0.alpha = s0.gamma0 = 0.0;
         s0.rtol2 = rtol * rtol;
-        s0.out = out;
         s0.id = id;
         s0.it = -1;
         s0.done = 0;
@@ -2141,6 +2311,28 @@ struct CoarseShape {
     static constexpr int nn = P0 + 1, nl = nn * nn * nn, epb = 256 / nl;
 };
 
+// Sum of (x, y) over the block, returned to every thread (each adds the
+// per-wave totals in the same order, so all hold the same bits).
+__device__ inline void block_sum2_all(double& x, double& y, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        x += __shfl_xor(x, o, 64);
+        y += __shfl_xor(y, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) {
+        red[2 * wid] = x;
+        red[2 * wid + 1] = y;
+    }
+    __syncthreads();
+    x = 0.0;
+    y = 0.0;
+    for (int k = 0; k < nw; ++k) {
+        x += red[2 * k];
+        y += red[2 * k + 1];
+    }
+}
+
 template <int P0>
 __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j) {
     using CS = CoarseShape<P0>;
@@ -2148,10 +2340,11 @@ __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j) {
     __shared__ double tab[EPB][36];
     __shared__ double zl[EPB][nl];
     __shared__ double red[8];
-    __shared__ double sums[2];
+    __shared__ double red2[8];
     const int jr = j & 1, jn = jr ^ 1;
-    // loads that do not depend on this iteration's scalars go first, so
-    // their latency overlaps the reduction of the partial sums
+    // every load that does not depend on this iteration's scalars is issued
+    // first (the previous launch's partial sums included), so that their
+    // latencies overlap
     const int el = threadIdx.x / nl, l = threadIdx.x - el * nl;
     const int e = blockIdx.x * EPB + el;
     const bool act = el < EPB && e < a.ne;
@@ -2163,6 +2356,11 @@ __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j) {
                                                        g2 == a.lay.N[1] - 1 || g3 == a.lay.N[2] - 1);
     const int ec[3] = {c1, c2, c3};
     const int64_t gi = unk ? elem_slot(a.lay, ec, a1, a2, a3) : 0;
+    double g = 0.0, d = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+        g += a.P[jr][2 * b];
+        d += a.P[jr][2 * b + 1];
+    }
     const CoarseState si = a.S[jr];
     double dg = 1.0, ro = 0.0, qo = 0.0, wo = 0.0, po = 0.0, xo = 0.0;
     if (unk) {
@@ -2171,7 +2369,7 @@ __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j) {
         qo = a.Q[jr][gi];
         wo = a.W[j % 3][gi];
         po = a.p[gi];
-        xo = si.out[gi];
+        xo = a.X[gi];
     }
     constexpr int NTAB = (EPB * 36 + 255) / 256;
     double tv[NTAB];
@@ -2203,20 +2401,8 @@ __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j) {
     if (si.it < 0) {
         so.it = 0;                      // first launch: z_0 = D^-1 r_0, w_0 = A z_0
     } else {
-        double g = 0.0, d = 0.0;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
-            g += a.P[jr][2 * b];
-            d += a.P[jr][2 * b + 1];
-        }
-        g = block_sum(g, red);
-        __syncthreads();
-        d = block_sum(d, red);
-        if (threadIdx.x == 0) {
-            sums[0] = g;
-            sums[1] = d;
-        }
-        __syncthreads();
-        const double gnew = sums[0], delta = sums[1];
+        block_sum2_all(g, d, red);
+        const double gnew = g, delta = d;
         if (si.it == 0) {
             so.gamma0 = gnew;
             if (!(gnew > 0.0) || si.maxit <= 0) finish = true;
@@ -2262,7 +2448,7 @@ __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j) {
         if (own) {
             const double pn = ro / dg + beta * po;
             a.p[gi] = pn;
-            si.out[gi] = xo + alpha * pn;
+            a.X[gi] = xo + alpha * pn;
             a.R[jn][gi] = rn;
             a.Q[jn][gi] = qn;
             a.W[(j + 2) % 3][gi] = 0.0;
@@ -2276,9 +2462,7 @@ __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j) {
         unsafeAtomicAdd(a.W[(j + 1) % 3] + gi, y);
         dpart = y * zn;
     }
-    gpart = block_sum(gpart, red);
-    __syncthreads();
-    dpart = block_sum(dpart, red);
+    block_sum2_all(gpart, dpart, red2);
     if (threadIdx.x == 0) {
         a.P[jn][2 * blockIdx.x] = gpart;
         a.P[jn][2 * blockIdx.x + 1] = dpart;
@@ -2436,8 +2620,6 @@ __global__ void k_mlp_adam(float* __restrict__ prm, const float* __restrict__ g,
 // launchers
 // ---------------------------------------------------------------------------
 // smallest degree that uses the matrix-core smoother (settable for tests)
-int g_mfma_min_p = 3;
-void set_mfma_min_degree(int p) { g_mfma_min_p = p; }
 
 static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
@@ -2519,7 +2701,20 @@ constexpr int MFMA_WPB = 2;
 
 template <typename T>
 void launch_smoother_add(const LevelTabs<T>& tb, const T* r, T* du, T omega, hipStream_t st) {
-    if (2 * tb.lay.p - 1 <= 16 && tb.lay.p >= g_mfma_min_p) {
+    const int nstars = (tb.lay.n[0] + 1) * (tb.lay.n[1] + 1) * (tb.lay.n[2] + 1);
+    if (2 * tb.lay.p - 1 <= 4) {
+        typedef SmallStar<4> SS;
+        hipLaunchKernelGGL((k_smoother_small<T, 4>), dim3((nstars + SS::SPB - 1) / SS::SPB), dim3(256),
+                           sizeof(T) * SS::PER * SS::SPB, st, tb, r, du, omega);
+        return;
+    }
+    if (2 * tb.lay.p - 1 <= 8) {
+        typedef SmallStar<8> SS;
+        hipLaunchKernelGGL((k_smoother_small<T, 8>), dim3((nstars + SS::SPB - 1) / SS::SPB), dim3(256),
+                           sizeof(T) * SS::PER * SS::SPB, st, tb, r, du, omega);
+        return;
+    }
+    if (2 * tb.lay.p - 1 <= 16) {
         int ns = (tb.lay.n[0] + 1) * (tb.lay.n[1] + 1) * (tb.lay.n[2] + 1);
         size_t smm = sizeof(T) * SM_MFMA_PER_WAVE * MFMA_WPB;
         hipLaunchKernelGGL((k_smoother_mfma<T, MFMA_WPB>), dim3((ns + MFMA_WPB - 1) / MFMA_WPB),
@@ -2782,10 +2977,10 @@ void launch_mlp_adam(float* prm, const float* g, float* m, float* v, int n, floa
     hipLaunchKernelGGL(k_mlp_adam, dim3(nblk(n)), dim3(256), 0, st, prm, g, m, v, n, lr, b1, b2, eps, c1, c2);
 }
 
-hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, double* out, int maxit, double rtol,
-                              int64_t id, hipStream_t st) {
+hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, int maxit, double rtol, int64_t id,
+                              hipStream_t st) {
     const int blocks = (int)std::min<int64_t>(std::max<int64_t>((a.lay.len + 255) / 256, 1), 1024);
-    hipLaunchKernelGGL(k_coarse_init, dim3(blocks), dim3(256), 0, st, a, b, out, maxit, rtol, id);
+    hipLaunchKernelGGL(k_coarse_init, dim3(blocks), dim3(256), 0, st, a, b, maxit, rtol, id);
     return hipGetLastError();
 }
 
