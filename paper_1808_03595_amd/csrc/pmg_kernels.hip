@@ -899,7 +899,9 @@ __device__ __forceinline__ void v4_to(const typename Mfma<T>::v4& c, T o[4]) {
     o[3] = c[3];
 }
 
-constexpr int SM_MFMA_PER_WAVE = 3072;
+// LDS entries per wavefront of the matrix-core smoother
+template <typename T>
+constexpr int sm_mfma_per_wave() { return sizeof(T) == 4 ? 3072 : 1024; }
 
 template <typename T, int WPB>
 __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, const T* __restrict__ r,
@@ -909,7 +911,7 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int q = lane >> 4, j = lane & 15;
-    T* sm = reinterpret_cast<T*>(smem_raw) + wv * SM_MFMA_PER_WAVE;
+    T* sm = reinterpret_cast<T*>(smem_raw) + wv * sm_mfma_per_wave<T>();
     const Layout& L = tb.lay;
     const int p = L.p, nS = 2 * p - 1, c = p - 1;
     const int nv1 = L.n[0] + 1, nv2 = L.n[1] + 1, nv3 = L.n[2] + 1;
@@ -927,10 +929,40 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
     const T* S2 = tb.st_SP[1] + (size_t)v2 * 256;
     const T* S3 = tb.st_SP[2] + (size_t)v3 * 256;
     const int c1 = v1 * p, c2 = v2 * p, c3 = v3 * p;
+    // the eigenspace pass works on the 4x4x4 tile (t1, t2, t3) of this lane;
+    // its vectors a_d (row c of S_d), the eigenvalues, the weights and the
+    // A-pattern copies of S for the back transforms are loaded with the
+    // operands in FP32, so that no later step waits on memory for them; FP64
+    // lacks the registers and loads each set where it is needed
+    constexpr bool early = sizeof(T) == 4;
+    const int t1 = lane & 3, t2 = (lane >> 2) & 3, t3 = lane >> 4;
+    const int k1b = 4 * t1, k2b = 4 * t2, k3b = 4 * t3;
+    T a1[4], a2[4], a3[4], l1[4], l2[4], l3[4], wr[4], wj;
+    auto load_eig = [&]() {
+        const T* L1 = tb.st_lamP[0] + v1 * 16;
+        const T* L2 = tb.st_lamP[1] + v2 * 16;
+        const T* L3 = tb.st_lamP[2] + v3 * 16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            a1[i] = S1[c * 16 + k1b + i];
+            a2[i] = S2[c * 16 + k2b + i];
+            a3[i] = S3[c * 16 + k3b + i];
+            l1[i] = L1[k1b + i] + tb.lam;
+            l2[i] = L2[k2b + i];
+            l3[i] = L3[k3b + i];
+        }
+    };
+    auto load_w = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) wr[i] = tb.st_wP[M::row(q, i)];
+        wj = omega * tb.st_wP[j];
+    };
+    if (early) {
+        load_eig();
+        load_w();
+    }
     // S in both operand patterns: Sb[s] = S[row(q,s)][j], Sa[s] = S[j][row(q,s)]
-    // (the A-pattern copies are loaded again for the back transforms, so
-    // that they do not occupy registers during the eigenspace pass)
-    T Sb1[4], Sb2[4], Sb3[4];
+    T Sb1[4], Sb2[4], Sb3[4], Sa1[4], Sa2[4], Sa3[4];
     T f1[4], f2[4], f3[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -970,36 +1002,28 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
         sm[256 + rr * 16 + j] = g2[v];  // G2[k3][k1]
         sm[512 + rr * 16 + j] = g3[v];  // G3[k2][k1]
     }
-    __syncthreads();
-    // eigenspace pass on the 4x4x4 tile (t1, t2, t3) of this lane
-    const int t1 = lane & 3, t2 = (lane >> 2) & 3, t3 = lane >> 4;
-    const int k1b = 4 * t1, k2b = 4 * t2, k3b = 4 * t3;
-    // (the lambda + l1 + l2 sums are formed on the fly and the G3 values
-    // read from LDS inside the loop, to keep the register count low)
-    T a1[4], a2[4], a3[4], l1[4], l2[4], l3[4];
-    T H1p[4][4], H2p[4][4], H3p[4][4];
-    {
-        const T* L1 = tb.st_lamP[0] + v1 * 16;
-        const T* L2 = tb.st_lamP[1] + v2 * 16;
-        const T* L3 = tb.st_lamP[2] + v3 * 16;
+    if (early) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            a1[i] = S1[c * 16 + k1b + i];
-            a2[i] = S2[c * 16 + k2b + i];
-            a3[i] = S3[c * 16 + k3b + i];
-            l1[i] = L1[k1b + i] + tb.lam;
-            l2[i] = L2[k2b + i];
-            l3[i] = L3[k3b + i];
+        for (int s = 0; s < 4; ++s) {
+            const int k = M::row(q, s);
+            Sa1[s] = S1[j * 16 + k];
+            Sa2[s] = S2[j * 16 + k];
+            Sa3[s] = S3[j * 16 + k];
         }
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                H1p[b][a] = 0;
-                H2p[b][a] = 0;
-                H3p[b][a] = 0;
-            }
     }
+    __syncthreads();
+    // eigenspace pass on this lane's tile: V = (a1 G1 + a2 G2 + a3 G3) /
+    // (lambda + l1 + l2 + l3), the three contractions accumulated in registers
+    T H1p[4][4], H2p[4][4], H3p[4][4];
+    if (!early) load_eig();
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            H1p[b][a] = 0;
+            H2p[b][a] = 0;
+            H3p[b][a] = 0;
+        }
 #pragma unroll
     for (int i3 = 0; i3 < 4; ++i3) {
         const int k3 = k3b + i3;
@@ -1021,39 +1045,63 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
                 H3p[i2][i1] += a3[i3] * V;
             }
     }
-    __syncthreads();  // all G reads done; reuse the region for the partials
+    // the three contractions are summed over the four tiles that share an
+    // index through LDS: P1[t1][k3][k2], P2[t2][k3][k1], P3[t3][k2][k1]; FP32
+    // stages all three at once, FP64 one after the other (a third of the LDS,
+    // so that LDS does not limit its occupancy)
+    auto stage = [&](int d, T* P) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            sm[(t1 * 16 + k3b + b) * 16 + k2b + a] = H1p[b][a];          // P1[t1][k3][k2]
-            sm[1024 + (t2 * 16 + k3b + b) * 16 + k1b + a] = H2p[b][a];   // P2[t2][k3][k1]
-            sm[2048 + (t3 * 16 + k2b + b) * 16 + k1b + a] = H3p[b][a];   // P3[t3][k2][k1]
+            for (int a = 0; a < 4; ++a) {
+                if (d == 0) P[(t1 * 16 + k3b + b) * 16 + k2b + a] = H1p[b][a];
+                else if (d == 1) P[(t2 * 16 + k3b + b) * 16 + k1b + a] = H2p[b][a];
+                else P[(t3 * 16 + k2b + b) * 16 + k1b + a] = H3p[b][a];
+            }
+    };
+    // hd[s] = H_d[j][row(q, s)]: H1[k3][k2], H2[k3][k1], H3[k2][k1]
+    auto reduce = [&](const T* P, T hd[4]) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = M::row(q, s);
+            T x = 0;
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) x += P[(tt * 16 + j) * 16 + k];
+            hd[s] = x;
         }
-    __syncthreads();
+    };
     T h1[4], h2[4], h3[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int k = M::row(q, s);
-        T x = 0, y = 0, z = 0;
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-            x += sm[(tt * 16 + j) * 16 + k];
-            y += sm[1024 + (tt * 16 + j) * 16 + k];
-            z += sm[2048 + (tt * 16 + j) * 16 + k];
-        }
-        h1[s] = x;  // H1[k3 = j][k2 = k]
-        h2[s] = y;  // H2[k3 = j][k1 = k]
-        h3[s] = z;  // H3[k2 = j][k1 = k]
+    __syncthreads();  // all G reads done; reuse the region for the partials
+    if (early) {
+        stage(0, sm);
+        stage(1, sm + 1024);
+        stage(2, sm + 2048);
+        __syncthreads();
+        reduce(sm, h1);
+        reduce(sm + 1024, h2);
+        reduce(sm + 2048, h3);
+    } else {
+        stage(0, sm);
+        __syncthreads();
+        reduce(sm, h1);
+        __syncthreads();
+        stage(1, sm);
+        __syncthreads();
+        reduce(sm, h2);
+        __syncthreads();
+        stage(2, sm);
+        __syncthreads();
+        reduce(sm, h3);
     }
     // U1 = S3 (H1 S2^T), U2 = S3 (H2 S1^T), U3 = S2 (H3 S1^T)
-    T Sa1[4], Sa2[4], Sa3[4];
+    if (!early) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int k = M::row(q, s);
-        Sa1[s] = S1[j * 16 + k];
-        Sa2[s] = S2[j * 16 + k];
-        Sa3[s] = S3[j * 16 + k];
+        for (int s = 0; s < 4; ++s) {
+            const int k = M::row(q, s);
+            Sa1[s] = S1[j * 16 + k];
+            Sa2[s] = S2[j * 16 + k];
+            Sa3[s] = S3[j * 16 + k];
+        }
     }
     v4_to<T>(gemm16<T>(h1, Sa2), t);
     v4 u1 = gemm16<T>(Sa3, t);
@@ -1062,13 +1110,13 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
     v4_to<T>(gemm16<T>(h3, Sa1), t);
     v4 u3 = gemm16<T>(Sa2, t);
     if (!active) return;
-    const T* w = tb.st_wP;
+    if (!early) load_w();
     const int ob = j - c;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int a = M::row(q, v), oa = a - c;
         if (a >= nS || j >= nS) continue;
-        const T wt = omega * w[a] * w[j];
+        const T wt = wj * wr[v];
         {   // face normal to x1: (i1, i2, i3) = (c1, c2 + ob, c3 + oa)
             int i1 = c1, i2 = c2 + ob, i3 = c3 + oa;
             if (i2 >= 0 && i2 < L.N[1] && i3 >= 0 && i3 < L.N[2] && !is_dir(L, i1, i2, i3))
@@ -2716,7 +2764,7 @@ void launch_smoother_add(const LevelTabs<T>& tb, const T* r, T* du, T omega, hip
     }
     if (2 * tb.lay.p - 1 <= 16) {
         int ns = (tb.lay.n[0] + 1) * (tb.lay.n[1] + 1) * (tb.lay.n[2] + 1);
-        size_t smm = sizeof(T) * SM_MFMA_PER_WAVE * MFMA_WPB;
+        size_t smm = sizeof(T) * sm_mfma_per_wave<T>() * MFMA_WPB;
         hipLaunchKernelGGL((k_smoother_mfma<T, MFMA_WPB>), dim3((ns + MFMA_WPB - 1) / MFMA_WPB),
                            dim3(64 * MFMA_WPB), smm, st, tb, r, du, omega);
         return;
