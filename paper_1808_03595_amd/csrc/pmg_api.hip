@@ -64,7 +64,9 @@ struct Level {
     // coarse CG structures when this level is the bottom of the cycle
     CoarseArgs ca{};
     bool has_ca = false;
-    hipGraphExec_t coarse_exec[COARSE_GRAPHS + 1] = {};  // [k]: COARSE_RING * k iteration launches
+    // graphs of n iteration launches with ring indices j0 .. j0 + n - 1,
+    // [(n - 1) * COARSE_RING + j0 % COARSE_RING], captured on first use
+    std::vector<hipGraphExec_t> coarse_exec;
 };
 
 template <typename T> struct Sel;
@@ -111,6 +113,8 @@ struct pmg_mesh {
     // the cycle
     hipGraphExec_t solver_graphs[4] = {nullptr, nullptr, nullptr, nullptr};
     int coarse_last = 0;
+    int coarse_recent[4] = {0, 0, 0, 0};  // update counts of the last coarse solves
+    int coarse_nrec = 0;
     long coarse_total = 0;
     // finest-level solver vectors (FP64) and mixed-precision buffers
     double *w_u = nullptr, *w_r = nullptr, *w_s = nullptr, *w_p = nullptr, *w_q = nullptr, *w_z = nullptr,
@@ -554,23 +558,29 @@ void smooth_add(Level& L, const T* r, T* u, hipStream_t st) {
 }
 
 // Jacobi-preconditioned CG on level 0 (FP64), x = 0 initially: the init
-// kernel, then chunks of COARSE_RING iteration launches (one graph each).
-// Launches after convergence return at once.  With a tolerance the stream
-// is synchronised once the expected number of chunks (from the previous
-// solve) is queued, and more chunks follow until the device reports
-// convergence or maxit; without one, enough chunks for maxit are queued
-// and nothing is synchronised.  b and x are level-0 skeleton arrays.
-// Queue `units` * COARSE_RING iteration launches: one graph of exactly that
-// many launches when units <= COARSE_GRAPHS (captured on first use; the
-// graph launches run back to back, separate graph launches do not).
-int coarse_launch_units(pmg_mesh* m, Level& L0, long units, hipStream_t st) {
-    while (units > 0) {
-        const int k = (int)std::min<long>(units, COARSE_GRAPHS);
-        if (!L0.coarse_exec[k]) {
+// kernel, then iteration launches (k updates take k + 2 launches: the first
+// forms z_0 and w_0, the last finds convergence; launches after convergence
+// return at once).  With a tolerance, as many launches are queued as the
+// largest update count of the last few solves needs, the host waits for
+// the device's completion notice, and further launches follow only if the
+// solve has not finished by then; without one, exactly maxit + 2 launches
+// are queued and nothing is waited for.  b and x are level-0 skeleton
+// arrays.
+//
+// Queue n iteration launches with ring indices j0 .. j0 + n - 1 as graphs
+// of up to COARSE_GRAPH_MAXN launches (captured on first use; the launches
+// of one graph run back to back).
+int coarse_launch_range(pmg_mesh* m, Level& L0, long j0, long n, hipStream_t st) {
+    if (L0.coarse_exec.empty()) L0.coarse_exec.assign((size_t)COARSE_GRAPH_MAXN * COARSE_RING, nullptr);
+    while (n > 0) {
+        const int k = (int)std::min<long>(n, COARSE_GRAPH_MAXN);
+        const int r0 = (int)(j0 % COARSE_RING);
+        hipGraphExec_t& ex = L0.coarse_exec[(size_t)(k - 1) * COARSE_RING + r0];
+        if (!ex) {
             HIPCHK(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
             hipError_t e = hipSuccess;
-            for (int j = 0; j < k * COARSE_RING && e == hipSuccess; ++j)
-                e = launch_coarse_iter(L0.ca, j % COARSE_RING, m->cap_stream);
+            for (int j = 0; j < k && e == hipSuccess; ++j)
+                e = launch_coarse_iter(L0.ca, (r0 + j) % COARSE_RING, m->cap_stream);
             hipGraph_t g = nullptr;
             hipError_t e2 = hipStreamEndCapture(m->cap_stream, &g);
             if (e != hipSuccess || e2 != hipSuccess) {
@@ -578,12 +588,13 @@ int coarse_launch_units(pmg_mesh* m, Level& L0, long units, hipStream_t st) {
                 return fail(PMG_EHIP, std::string("coarse graph capture: ") +
                                           hipGetErrorString(e != hipSuccess ? e : e2));
             }
-            e = hipGraphInstantiate(&L0.coarse_exec[k], g, nullptr, nullptr, 0);
+            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) return fail(PMG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
         }
-        HIPCHK(hipGraphLaunch(L0.coarse_exec[k], st));
-        units -= k;
+        HIPCHK(hipGraphLaunch(ex, st));
+        j0 += k;
+        n -= k;
     }
     return 0;
 }
@@ -600,18 +611,17 @@ int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st) {
     };
     HIPCHK(launch_coarse_init(a, b, m->coarse_maxit, m->coarse_rtol, id, st));
     if (a.N0 == 0) return deliver();
-    const long need = (long)m->coarse_maxit + 2;  // launches for maxit updates
-    const long umax = (need + COARSE_RING - 1) / COARSE_RING;
+    const long need = (long)std::max(m->coarse_maxit, 0) + 2;  // launches for maxit updates
     int rc;
     if (!(m->coarse_rtol > 0.0)) {
-        if ((rc = coarse_launch_units(m, L0, umax, st))) return rc;
+        if ((rc = coarse_launch_range(m, L0, 0, need, st))) return rc;
         return deliver();
     }
-    long units = std::min(umax, std::max(1L, ((long)m->coarse_last + 3 + COARSE_RING - 1) / COARSE_RING));
-    long launched = 0;
+    int est = m->coarse_last;
+    for (int i = 0; i < std::min(m->coarse_nrec, 4); ++i) est = std::max(est, m->coarse_recent[i]);
+    long launched = std::min(need, (long)est + 2);
+    if ((rc = coarse_launch_range(m, L0, 0, launched, st))) return rc;
     while (true) {
-        if ((rc = coarse_launch_units(m, L0, units - launched, st))) return rc;
-        launched = units;
         // the finishing launch reports (id, updates); a marker after the
         // queued launches tells that they all ran without finishing
         const int64_t mk = ++m->mark_seq;
@@ -620,10 +630,13 @@ int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st) {
         if ((rc = host_wait(st, [&] { return hm->cseq == id || hm->mseq >= mk; }))) return rc;
         if (hm->cseq == id) {
             m->coarse_last = hm->cit;
+            m->coarse_recent[m->coarse_nrec++ % 4] = hm->cit;
             return deliver();
         }
-        if (launched >= umax) return fail(PMG_EHIP, "coarse solver did not finish within maxit");
-        units = std::min(umax, launched + std::max(1L, launched / 2));
+        if (launched >= need) return fail(PMG_EHIP, "coarse solver did not finish within maxit");
+        const long more = std::min(need - launched, std::max(2L * COARSE_RING, launched / 8));
+        if ((rc = coarse_launch_range(m, L0, launched, more, st))) return rc;
+        launched += more;
     }
 }
 

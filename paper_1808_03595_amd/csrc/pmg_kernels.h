@@ -13,7 +13,7 @@ hipError_t init_kernel_attributes();
 constexpr int COARSE_RING = 6;
 // length of the restriction work buffer (coarse partial sums + row pass)
 int64_t restrict_work_len(const Layout& Lf, const Layout& Lc);
-constexpr int COARSE_GRAPHS = 32;  // graphs of COARSE_RING * k launches, k = 1..32, built on first use
+constexpr int COARSE_GRAPH_MAXN = 256;  // longest captured chain of coarse iteration launches
 hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, int maxit, double rtol, int64_t id,
                               hipStream_t st);
 void launch_publish(const double* sc, int n, int64_t* cnt, HostMail* mail, hipStream_t st);
