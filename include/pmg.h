@@ -45,7 +45,7 @@ typedef struct pmg_mesh pmg_mesh;
 enum { PMG_F64 = 0, PMG_F32 = 1 };
 enum { PMG_OK = 0, PMG_EINVAL = -1, PMG_EHIP = -2, PMG_ENOMEM = -3,
        PMG_EUNSUP = -4, PMG_NOT_CONVERGED = 1, PMG_BREAKDOWN = 2 };
-enum { PMG_MAX_DEGREE = 48, PMG_MAX_HIST = 512 };
+enum { PMG_MAX_DEGREE = 48, PMG_MAX_HIST = 512, PMG_MAX_COARSE_IT = 1000000 };
 
 typedef struct {
     int iters;                    /* outer iterations performed            */
@@ -129,7 +129,8 @@ int pmg_restrict(pmg_mesh *m, int level, int dtype, const void *d_fine,
  * level ("kMG"), 1 = 2^(L-l) steps on level l ("kvMG") (Sec. 4.1).  The
  * coarse problem (p_0 = 2) is solved by Jacobi-preconditioned CG to the
  * relative tolerance coarse_rtol (D^-1-weighted residual norm) or
- * coarse_maxit iterations; coarse_rtol = 0 runs exactly coarse_maxit. */
+ * coarse_maxit iterations; coarse_rtol = 0 runs exactly coarse_maxit.
+ * 0 <= coarse_maxit <= PMG_MAX_COARSE_IT, else PMG_EINVAL. */
 int pmg_set_cycle(pmg_mesh *m, int nu_mode, double coarse_rtol,
                   int coarse_maxit);
 

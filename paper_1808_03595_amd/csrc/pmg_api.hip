@@ -131,8 +131,8 @@ struct pmg_mesh {
     HostMail* dmail = nullptr;
     int64_t* d_pubcnt = nullptr;
     int64_t pub_expected = 0;
-    int64_t coarse_id = 0;
-    int64_t mark_seq = 0;
+    int64_t coarse_id = 0;    // coarse solves queued (the device numbers them alike)
+    int* hcit = nullptr;      // pinned host copy of the coarse iteration counter
     std::vector<void*> allocs;
 
     template <typename T>
@@ -270,6 +270,8 @@ int build_coarse(pmg_mesh* m, Level& lev) {
     HIPCHK(hipMemset(a.stat, 0, 2 * sizeof(int)));
     a.iters = m->d_coarse_iters;
     a.mail = m->dmail;
+    if ((rc = m->alloc(&a.seq, 1))) return rc;
+    HIPCHK(hipMemset(a.seq, 0, sizeof(int64_t)));
     lev.has_ca = true;
     return 0;
 }
@@ -387,6 +389,7 @@ int build_h_levels(pmg_mesh* m, int want) {
 
 // Active cycle, coarsest level first: hlv[k-1..0] then the p-levels.
 int rebuild_active(pmg_mesh* m) {
+    m->coarse_nrec = 0;  // the coarse update counts of another cycle do not carry over
     for (auto& g : m->solver_graphs)
         if (g) {
             (void)hipGraphExecDestroy(g);
@@ -475,6 +478,7 @@ int build_mesh(pmg_mesh* m) {
     HIPCHK(hipMemset(m->counter, 0, 4 * sizeof(unsigned)));
     HIPCHK(hipMemset(m->scal, 0, SC_N * sizeof(double)));
     HIPCHK(hipHostMalloc((void**)&m->hscal, SC_N * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&m->hcit, sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&m->hmail, sizeof(HostMail), hipHostMallocMapped | hipHostMallocCoherent));
     std::memset((void*)m->hmail, 0, sizeof(HostMail));
     HIPCHK(hipHostGetDevicePointer((void**)&m->dmail, m->hmail, 0));
@@ -580,7 +584,7 @@ int coarse_launch_range(pmg_mesh* m, Level& L0, long j0, long n, hipStream_t st)
             HIPCHK(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
             hipError_t e = hipSuccess;
             for (int j = 0; j < k && e == hipSuccess; ++j)
-                e = launch_coarse_iter(L0.ca, (r0 + j) % COARSE_RING, m->cap_stream);
+                e = launch_coarse_iter(L0.ca, (r0 + j) % COARSE_RING, j == k - 1, m->cap_stream);
             hipGraph_t g = nullptr;
             hipError_t e2 = hipStreamEndCapture(m->cap_stream, &g);
             if (e != hipSuccess || e2 != hipSuccess) {
@@ -599,17 +603,17 @@ int coarse_launch_range(pmg_mesh* m, Level& L0, long j0, long n, hipStream_t st)
     return 0;
 }
 
-int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st) {
+int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st, bool init_queued = false) {
     Level& L0 = *m->act[0];
     CoarseArgs& a = L0.ca;
-    const int64_t id = ++m->coarse_id;
     // the iterations update the level's own array a.X; a copy follows for
     // any other destination
     auto deliver = [&]() -> int {
         if (x != a.X) HIPCHK(hipMemcpyAsync(x, a.X, (size_t)a.lay.len * sizeof(double), hipMemcpyDeviceToDevice, st));
         return 0;
     };
-    HIPCHK(launch_coarse_init(a, b, m->coarse_maxit, m->coarse_rtol, id, st));
+    if (!init_queued) HIPCHK(launch_coarse_init(a, b, m->coarse_maxit, m->coarse_rtol, st));
+    const int64_t id = ++m->coarse_id;
     if (a.N0 == 0) return deliver();
     const long need = (long)std::max(m->coarse_maxit, 0) + 2;  // launches for maxit updates
     int rc;
@@ -621,13 +625,12 @@ int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st) {
     for (int i = 0; i < std::min(m->coarse_nrec, 4); ++i) est = std::max(est, m->coarse_recent[i]);
     long launched = std::min(need, (long)est + 2);
     if ((rc = coarse_launch_range(m, L0, 0, launched, st))) return rc;
+    HostMail* hm = m->hmail;
     while (true) {
-        // the finishing launch reports (id, updates); a marker after the
-        // queued launches tells that they all ran without finishing
-        const int64_t mk = ++m->mark_seq;
-        launch_mark(m->dmail, mk, st);
-        HostMail* hm = m->hmail;
-        if ((rc = host_wait(st, [&] { return hm->cseq == id || hm->mseq >= mk; }))) return rc;
+        // the finishing launch reports (id, updates); the last queued launch
+        // reports (id, updates so far) if the solve goes on
+        const int64_t ran_out = (id << 20) | (int64_t)(launched - 1);
+        if ((rc = host_wait(st, [&] { return hm->cseq == id || hm->rseq == ran_out; }))) return rc;
         if (hm->cseq == id) {
             m->coarse_last = hm->cit;
             m->coarse_recent[m->coarse_nrec++ % 4] = hm->cit;
@@ -847,6 +850,7 @@ void pmg_destroy_mesh(pmg_mesh* m) {
         if (g) (void)hipGraphExecDestroy(g);
     for (void* q : m->allocs) hipFree(q);
     if (m->hscal) hipHostFree(m->hscal);
+    if (m->hcit) hipHostFree(m->hcit);
     if (m->hmail) (void)hipHostFree((void*)m->hmail);
     if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
     delete m;
@@ -987,7 +991,8 @@ int pmg_restrict(pmg_mesh* m, int level, int dtype, const void* f, void* c, void
 int pmg_set_cycle(pmg_mesh* m, int nu_mode, double coarse_rtol, int coarse_maxit) {
     if (check_mesh(m)) return PMG_EINVAL;
     if (nu_mode != 0 && nu_mode != 1) return fail(PMG_EINVAL, "nu_mode must be 0 or 1");
-    if (!(coarse_rtol >= 0.0) || coarse_maxit < 0) return fail(PMG_EINVAL, "bad coarse parameters");
+    if (!(coarse_rtol >= 0.0) || coarse_maxit < 0 || coarse_maxit > PMG_MAX_COARSE_IT)
+        return fail(PMG_EINVAL, "bad coarse parameters");
     m->nu_mode = nu_mode;
     m->coarse_rtol = coarse_rtol;
     m->coarse_maxit = coarse_maxit;
@@ -1070,13 +1075,10 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
     const int64_t n = Lf.len;
     pmg_stats stats;
     std::memset(&stats, 0, sizeof(stats));
-    {
-        int dummy;
-        int rc0 = coarse_stats(m, st, &dummy);  // synchronises the stream
-        if (rc0) return rc0;
-        std::atomic_thread_fence(std::memory_order_acquire);
-        m->pub_expected = m->hmail->seq;          // resynchronise the notice count
-    }
+    HIPCHK(hipStreamSynchronize(st));
+    std::atomic_thread_fence(std::memory_order_acquire);
+    m->pub_expected = m->hmail->seq;  // resynchronise the notice count
+    launch_fill_zero<int>(m->d_coarse_iters, 1, st);
     hipEvent_t ev[4];
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
     HIPCHK(hipEventRecord(ev[0], st));
@@ -1084,14 +1086,7 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
     HIPCHK(hipEventRecord(ev[1], st));
     int rc = 0, status = 0;
     // r = F, u = 0, s = r, p = 0, delta = 1
-    HIPCHK(hipMemsetAsync(m->w_u, 0, n * sizeof(double), st));
-    HIPCHK(hipMemcpyAsync(m->w_r, m->w_F, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(m->w_s, m->w_F, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemsetAsync(m->w_p, 0, n * sizeof(double), st));
-    {
-        double one = 1.0;
-        HIPCHK(hipMemcpyAsync(m->scal + SC_DELTA, &one, sizeof(double), hipMemcpyHostToDevice, st));
-    }
+    launch_pcg_start(m->w_F, m->w_r, m->w_s, m->w_u, m->w_p, m->scal + SC_DELTA, n, st);
     launch_dot2<double>(m->w_r, m->w_r, nullptr, n, m->partials, m->counter, m->scal + SC_RR, st);
     if ((rc = read_scalars(m, st))) return rc;
     double rr0 = m->hscal[SC_RR], rr = rr0;
@@ -1114,14 +1109,26 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
         } else {
             // Alg. 5: z = MG(0, r) (FP64, or FP32 on r / |r| scaled back by
             // |r|, the norm taken from the device), then the direction and
-            // the update.  Everything but the coarse CG is replayed from two
-            // graphs captured on first use.
+            // the update.  Everything but the coarse CG iterations is
+            // replayed from two graphs captured on first use (the first ends
+            // with the coarse CG's initialisation).
             const int gi = pdt == PMG_F64 ? 0 : 2;
+            const double* cb;
+            double* cx;
+            if (pdt == PMG_F64) vc_coarse_io<double>(m, m->w_r, m->w_z, cb, cx);
+            else vc_coarse_io<float>(m, m->w_r32, m->w_z32, cb, cx);
             if (!m->solver_graphs[gi]) {
                 auto part_a = [&](hipStream_t s) -> int {
-                    if (pdt == PMG_F64) return vc_down<double>(m, m->w_r, m->w_z, false, s);
-                    launch_cast_scale<double, float>(m->w_r, m->w_r32, m->scal + SC_RR, 2, n, s);
-                    return vc_down<float>(m, m->w_r32, m->w_z32, false, s);
+                    int r2;
+                    if (pdt == PMG_F64) {
+                        r2 = vc_down<double>(m, m->w_r, m->w_z, false, s);
+                    } else {
+                        launch_cast_scale<double, float>(m->w_r, m->w_r32, m->scal + SC_RR, 2, n, s);
+                        r2 = vc_down<float>(m, m->w_r32, m->w_z32, false, s);
+                    }
+                    if (r2) return r2;
+                    HIPCHK(launch_coarse_init(m->act[0]->ca, cb, m->coarse_maxit, m->coarse_rtol, s));
+                    return 0;
                 };
                 auto part_b = [&](hipStream_t s) -> int {
                     int r2 = pdt == PMG_F64 ? vc_up<double>(m, m->w_r, m->w_z, s)
@@ -1142,12 +1149,8 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
                     (rc = capture_graph(m, &m->solver_graphs[gi + 1], part_b)))
                     return rc;
             }
-            const double* cb;
-            double* cx;
-            if (pdt == PMG_F64) vc_coarse_io<double>(m, m->w_r, m->w_z, cb, cx);
-            else vc_coarse_io<float>(m, m->w_r32, m->w_z32, cb, cx);
             HIPCHK(hipGraphLaunch(m->solver_graphs[gi], st));
-            if ((rc = coarse_cg(m, cb, cx, st))) return rc;
+            if ((rc = coarse_cg(m, cb, cx, st, true))) return rc;
             HIPCHK(hipGraphLaunch(m->solver_graphs[gi + 1], st));
             if ((rc = read_scalars(m, st, true))) return rc;
             rr = m->hscal[SC_RR];
@@ -1170,6 +1173,7 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
     HIPCHK(hipEventRecord(ev[2], st));
     launch_recover(m->lv.back().t64, f, m->w_u, ug, st);
     HIPCHK(hipEventRecord(ev[3], st));
+    HIPCHK(hipMemcpyAsync(m->hcit, m->d_coarse_iters, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     float t0 = 0, t1 = 0, t2 = 0;
     hipEventElapsedTime(&t0, ev[0], ev[1]);
@@ -1179,12 +1183,7 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
     stats.iters = it;
     stats.status = status;
     stats.rel_res = stats.res0 > 0 ? std::sqrt(rr) / stats.res0 : 0.0;
-    {
-        int cit = 0;
-        int rc1 = coarse_stats(m, st, &cit);
-        if (rc1) return rc1;
-        stats.coarse_iters = cit;
-    }
+    stats.coarse_iters = *m->hcit;
     stats.t_pre_ms = t0;
     stats.t_iter_ms = t1;
     stats.t_post_ms = t2;

@@ -158,7 +158,7 @@ struct CoarseState {
 struct HostMail {
     volatile int64_t seq;    // number of scalar publications so far
     volatile int64_t cseq;   // id of the last coarse solve that finished
-    volatile int64_t mseq;   // last marker written after queued coarse launches
+    volatile int64_t rseq;   // (id << 20) | updates: a coarse solve whose queued launches ran out
     volatile int cit;        // update count of that coarse solve
     int pad;
     double sc[16];           // the published scalars
@@ -184,6 +184,7 @@ struct CoarseArgs {
     int* iters;           // accumulated iteration count
     int blocks;           // workgroups of one iteration launch
     HostMail* mail;       // device address of the host notice block (or null)
+    int64_t* seq;         // number of coarse solves started (device counter)
 };
 
 }  // namespace pmg

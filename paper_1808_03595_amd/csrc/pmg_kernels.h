@@ -14,11 +14,11 @@ constexpr int COARSE_RING = 6;
 // length of the restriction work buffer (coarse partial sums + row pass)
 int64_t restrict_work_len(const Layout& Lf, const Layout& Lc);
 constexpr int COARSE_GRAPH_MAXN = 256;  // longest captured chain of coarse iteration launches
-hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, int maxit, double rtol, int64_t id,
-                              hipStream_t st);
+hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, int maxit, double rtol, hipStream_t st);
 void launch_publish(const double* sc, int n, int64_t* cnt, HostMail* mail, hipStream_t st);
-void launch_mark(HostMail* mail, int64_t v, hipStream_t st);
-hipError_t launch_coarse_iter(const CoarseArgs& a, int j, hipStream_t st);
+void launch_pcg_start(const double* F, double* r, double* s, double* u, double* p, double* delta, int64_t n,
+                      hipStream_t st);
+hipError_t launch_coarse_iter(const CoarseArgs& a, int j, bool last, hipStream_t st);
 int coarse_blocks(int ne, int p0);
 
 template <typename T> void launch_grid_to_skel(const Layout&, const double*, T*, hipStream_t);

@@ -2177,6 +2177,19 @@ __global__ void __launch_bounds__(256) k_dot2(const T* __restrict__ x, const T* 
 
 // ipCG direction update (Alg. 5): beta = (gamma - gamma0) / delta,
 // p = beta p + z.  sc[0] = gamma, sc[1] = gamma0, sc[2] = delta (old).
+// Start of Alg. 5: r = s = F, u = p = 0, delta = 1.
+__global__ void k_pcg_start(const double* __restrict__ F, double* __restrict__ r, double* __restrict__ s,
+                            double* __restrict__ u, double* __restrict__ p, double* delta, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *delta = 1.0;
+    if (i >= n) return;
+    const double f = F[i];
+    r[i] = f;
+    s[i] = f;
+    u[i] = 0.0;
+    p[i] = 0.0;
+}
+
 __global__ void k_pcg_dir(double* __restrict__ p, const double* __restrict__ z, const double* sc, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -2294,7 +2307,7 @@ __global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ z, con
 // ---------------------------------------------------------------------------
 // r = b at the unknowns, all other vectors and the iterate x zero; state
 // "before the first launch".
-__global__ void k_coarse_init(CoarseArgs a, const double* __restrict__ b, int maxit, double rtol, int64_t id) {
+__global__ void k_coarse_init(CoarseArgs a, const double* __restrict__ b, int maxit, double rtol) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t s = t; s < a.lay.len; s += stride) {
@@ -2307,6 +2320,10 @@ __global__ void k_coarse_init(CoarseArgs a, const double* __restrict__ b, int ma
         a.X[s] = 0.0;
     }
     if (t == 0) {
+        // solves are numbered on the device, in stream order, so that this
+        // launch can be part of a replayed graph
+        const int64_t id = *a.seq + 1;
+        *a.seq = id;
         CoarseState s0;
         s0.gamma = s0.alpha = s0.gamma0 = 0.0;
         s0.rtol2 = rtol * rtol;
@@ -2382,7 +2399,7 @@ __device__ inline void block_sum2_all(double& x, double& y, double* red) {
 }
 
 template <int P0>
-__global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j) {
+__global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j, int last) {
     using CS = CoarseShape<P0>;
     constexpr int nn = CS::nn, nl = CS::nl, EPB = CS::epb;
     __shared__ double tab[EPB][36];
@@ -2514,7 +2531,11 @@ __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j) {
     if (threadIdx.x == 0) {
         a.P[jn][2 * blockIdx.x] = gpart;
         a.P[jn][2 * blockIdx.x + 1] = dpart;
-        if (blockIdx.x == 0) a.S[jn] = so;
+        if (blockIdx.x == 0) {
+            a.S[jn] = so;
+            // the last queued launch tells the host that the solve goes on
+            if (last && a.mail) a.mail->rseq = (so.id << 20) | (int64_t)so.it;
+        }
     }
 }
 
@@ -2947,17 +2968,13 @@ __global__ void k_publish(const double* __restrict__ sc, int n, int64_t* cnt, Ho
     mail->seq = v;
 }
 
-__global__ void k_mark(HostMail* mail, int64_t v) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    __threadfence_system();
-    mail->mseq = v;
+void launch_pcg_start(const double* F, double* r, double* s, double* u, double* p, double* delta, int64_t n,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_start, dim3(nblk(std::max<int64_t>(n, 1))), dim3(256), 0, st, F, r, s, u, p, delta, n);
 }
 
 void launch_publish(const double* sc, int n, int64_t* cnt, HostMail* mail, hipStream_t st) {
     hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, st, sc, n, cnt, mail);
-}
-void launch_mark(HostMail* mail, int64_t v, hipStream_t st) {
-    hipLaunchKernelGGL(k_mark, dim3(1), dim3(64), 0, st, mail, v);
 }
 
 template <typename T>
@@ -2973,6 +2990,7 @@ void launch_fill_zero(T* x, int64_t n, hipStream_t st) {
 }
 template void launch_fill_zero<double>(double*, int64_t, hipStream_t);
 template void launch_fill_zero<float>(float*, int64_t, hipStream_t);
+template void launch_fill_zero<int>(int*, int64_t, hipStream_t);
 
 void launch_jacobi(const double* r, const double* dg, double* z, int64_t n, double* partials, unsigned* counter,
                    double* out, hipStream_t st) {
@@ -3025,10 +3043,9 @@ void launch_mlp_adam(float* prm, const float* g, float* m, float* v, int n, floa
     hipLaunchKernelGGL(k_mlp_adam, dim3(nblk(n)), dim3(256), 0, st, prm, g, m, v, n, lr, b1, b2, eps, c1, c2);
 }
 
-hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, int maxit, double rtol, int64_t id,
-                              hipStream_t st) {
+hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, int maxit, double rtol, hipStream_t st) {
     const int blocks = (int)std::min<int64_t>(std::max<int64_t>((a.lay.len + 255) / 256, 1), 1024);
-    hipLaunchKernelGGL(k_coarse_init, dim3(blocks), dim3(256), 0, st, a, b, maxit, rtol, id);
+    hipLaunchKernelGGL(k_coarse_init, dim3(blocks), dim3(256), 0, st, a, b, maxit, rtol);
     return hipGetLastError();
 }
 
@@ -3037,11 +3054,11 @@ int coarse_blocks(int ne, int p0) {
     return std::max(1, (ne + epb - 1) / epb);
 }
 
-hipError_t launch_coarse_iter(const CoarseArgs& a, int j, hipStream_t st) {
+hipError_t launch_coarse_iter(const CoarseArgs& a, int j, bool last, hipStream_t st) {
     if (a.p0 == 2)
-        hipLaunchKernelGGL(k_coarse_iter<2>, dim3(a.blocks), dim3(256), 0, st, a, j);
+        hipLaunchKernelGGL(k_coarse_iter<2>, dim3(a.blocks), dim3(256), 0, st, a, j, (int)last);
     else
-        hipLaunchKernelGGL(k_coarse_iter<1>, dim3(a.blocks), dim3(256), 0, st, a, j);
+        hipLaunchKernelGGL(k_coarse_iter<1>, dim3(a.blocks), dim3(256), 0, st, a, j, (int)last);
     return hipGetLastError();
 }
 
