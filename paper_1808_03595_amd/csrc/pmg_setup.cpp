@@ -7,6 +7,7 @@
 // transfer matrix (Sec. 4.1).
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <numeric>
 #include <stdexcept>
 
@@ -95,68 +96,78 @@ void stiffness_std(int p, const std::vector<double>& x, const std::vector<double
 }
 
 // Cyclic Jacobi rotations for a symmetric n x n matrix A (destroyed).
-// Q[i][k] column k is the eigenvector of lam[k]; ascending order.
-void sym_eig_jacobi(int n, std::vector<double>& A, std::vector<double>& Q,
-                    std::vector<double>& lam) {
-    Q.assign(n * n, 0.0);
-    for (int i = 0; i < n; ++i) Q[i * n + i] = 1.0;
+// Q[i][k] column k is the eigenvector of lam[k]; ascending order.  The
+// rotations run in extended precision (long double; the matrix is given in
+// it) and skip an entry once
+// it is negligible relative to its two diagonal entries, so that even the
+// smallest eigenvalues come out correct to the last FP64 bit at large p
+// (their absolute size is ~p^-4 of the largest one).
+static void jacobi_ext(int n, std::vector<long double>& A, std::vector<double>& Q_out, std::vector<double>& lam) {
+    typedef long double R;
+    std::vector<R> Q((size_t)n * n, 0.0L);
+    for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0L;
+    const R tol = 4.0L * std::numeric_limits<R>::epsilon();
     for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) {
-                tot += A[i * n + j] * A[i * n + j];
-                if (i != j) off += A[i * n + j] * A[i * n + j];
-            }
-        if (off <= 1e-32 * tot || off == 0.0) break;
+        bool rotated = false;
         for (int pq = 0; pq < n; ++pq)
             for (int qq = pq + 1; qq < n; ++qq) {
-                double apq = A[pq * n + qq];
-                if (apq == 0.0) continue;
-                double app = A[pq * n + pq], aqq = A[qq * n + qq];
-                double theta = (aqq - app) / (2.0 * apq);
-                double t = (theta >= 0 ? 1.0 : -1.0) /
-                           (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-                double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                const R apq = A[(size_t)pq * n + qq];
+                const R app = A[(size_t)pq * n + pq], aqq = A[(size_t)qq * n + qq];
+                if (std::fabs(apq) <= tol * std::sqrt(std::fabs(app * aqq))) continue;
+                rotated = true;
+                const R theta = (aqq - app) / (2.0L * apq);
+                const R t = (theta >= 0 ? 1.0L : -1.0L) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0L));
+                const R c = 1.0L / std::sqrt(t * t + 1.0L), s = t * c;
                 for (int k = 0; k < n; ++k) {
-                    double akp = A[k * n + pq], akq = A[k * n + qq];
-                    A[k * n + pq] = c * akp - s * akq;
-                    A[k * n + qq] = s * akp + c * akq;
+                    const R akp = A[(size_t)k * n + pq], akq = A[(size_t)k * n + qq];
+                    A[(size_t)k * n + pq] = c * akp - s * akq;
+                    A[(size_t)k * n + qq] = s * akp + c * akq;
                 }
                 for (int k = 0; k < n; ++k) {
-                    double apk = A[pq * n + k], aqk = A[qq * n + k];
-                    A[pq * n + k] = c * apk - s * aqk;
-                    A[qq * n + k] = s * apk + c * aqk;
+                    const R apk = A[(size_t)pq * n + k], aqk = A[(size_t)qq * n + k];
+                    A[(size_t)pq * n + k] = c * apk - s * aqk;
+                    A[(size_t)qq * n + k] = s * apk + c * aqk;
                 }
                 for (int k = 0; k < n; ++k) {
-                    double qkp = Q[k * n + pq], qkq = Q[k * n + qq];
-                    Q[k * n + pq] = c * qkp - s * qkq;
-                    Q[k * n + qq] = s * qkp + c * qkq;
+                    const R qkp = Q[(size_t)k * n + pq], qkq = Q[(size_t)k * n + qq];
+                    Q[(size_t)k * n + pq] = c * qkp - s * qkq;
+                    Q[(size_t)k * n + qq] = s * qkp + c * qkq;
                 }
             }
+        if (!rotated) break;
     }
     std::vector<int> ord(n);
     std::iota(ord.begin(), ord.end(), 0);
-    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return A[a * n + a] < A[b * n + b]; });
-    std::vector<double> Qs(n * n);
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return A[(size_t)a * n + a] < A[(size_t)b * n + b]; });
+    Q_out.assign((size_t)n * n, 0.0);
     lam.resize(n);
     for (int k = 0; k < n; ++k) {
-        lam[k] = A[ord[k] * n + ord[k]];
-        for (int i = 0; i < n; ++i) Qs[i * n + k] = Q[i * n + ord[k]];
+        lam[k] = (double)A[(size_t)ord[k] * n + ord[k]];
+        for (int i = 0; i < n; ++i) Q_out[(size_t)i * n + k] = (double)Q[(size_t)i * n + ord[k]];
     }
-    Q.swap(Qs);
+}
+
+void sym_eig_jacobi(int n, std::vector<double>& A_in, std::vector<double>& Q_out, std::vector<double>& lam) {
+    std::vector<long double> A(A_in.begin(), A_in.end());
+    jacobi_ext(n, A, Q_out, lam);
 }
 
 // Generalized eigenpairs of (L, diag(m)): S^T L S = diag(lam), S^T M S = I,
-// via the symmetric matrix M^-1/2 L M^-1/2 = Q diag(lam) Q^T, S = M^-1/2 Q.
+// via the symmetric matrix M^-1/2 L M^-1/2 = Q diag(lam) Q^T, S = M^-1/2 Q
+// (scaling and back-scaling in extended precision as well).
 void gen_eig_diag(int n, const double* L, const double* m, std::vector<double>& S,
                   std::vector<double>& lam) {
-    std::vector<double> A(n * n), Q;
+    typedef long double R;
+    std::vector<R> ms(n);
+    for (int i = 0; i < n; ++i) ms[i] = std::sqrt((R)m[i]);
+    std::vector<R> A((size_t)n * n);
+    std::vector<double> Q;
     for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) A[i * n + j] = L[i * n + j] / std::sqrt(m[i] * m[j]);
-    sym_eig_jacobi(n, A, Q, lam);
-    S.resize(n * n);
+        for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = (R)L[(size_t)i * n + j] / (ms[i] * ms[j]);
+    jacobi_ext(n, A, Q, lam);
+    S.resize((size_t)n * n);
     for (int i = 0; i < n; ++i)
-        for (int k = 0; k < n; ++k) S[i * n + k] = Q[i * n + k] / std::sqrt(m[i]);
+        for (int k = 0; k < n; ++k) S[(size_t)i * n + k] = (double)((R)Q[(size_t)i * n + k] / ms[i]);
 }
 
 // J[i][j] = l_j(xt[i]) by the barycentric formula on the nodes xf.
