@@ -55,10 +55,13 @@ def glorot(nout=NOUT, seed=0):
 class DampingMLP:
     """FP32 network 3 -> 64 -> 64 -> NOUT held in device memory."""
 
-    def __init__(self, params=None, nout=NOUT, seed=0):
+    def __init__(self, params=None, nout=NOUT, seed=0, trained=None):
         import torch
         self.torch = torch
         self.nout = nout
+        # outputs that had training targets; the others are never used (the
+        # paper's omega = 1 stands in for them)
+        self.trained = np.ones(nout, dtype=bool) if trained is None else np.asarray(trained, dtype=bool)
         self.dev = torch.device("cuda:0")
         p = glorot(nout, seed) if params is None else np.asarray(params, dtype=np.float32)
         assert p.size == mlp_nparams(nout)
@@ -69,12 +72,13 @@ class DampingMLP:
         if not os.path.exists(path):
             return None
         with np.load(path, allow_pickle=False) as z:
-            return cls(z["params"], int(z["nout"]))
+            trained = z["trained"] if "trained" in z.files else None
+            return cls(z["params"], int(z["nout"]), trained=trained)
 
     def save(self, path, **meta):
         os.makedirs(os.path.dirname(path), exist_ok=True)
         np.savez(path, params=self.params.cpu().numpy(), nout=np.int32(self.nout),
-                 meta=np.array(json.dumps(meta)))
+                 trained=self.trained.astype(np.int8), meta=np.array(json.dumps(meta)))
 
     def predict(self, X):
         torch = self.torch
@@ -110,9 +114,11 @@ class DampingMLP:
         return hist
 
 
-def convergence_factor(mesh, f, omega, cycles=4):
-    """rho over `cycles` iterations of the deployed solver (mixed-precision
-    Krylov-accelerated MG, Alg. 5) with damping `omega` (finest first)."""
+def convergence_factor(mesh, f, omega, cycles=2):
+    """rho over the first `cycles` iterations of the deployed solver
+    (mixed-precision Krylov-accelerated MG, Alg. 5) with damping `omega`
+    (finest first).  Two iterations keep the residual well above rounding
+    level even where one iteration gains 1e-6."""
     torch = __import__("torch")
     mesh.set_damping(list(omega))
     u = torch.zeros_like(f)
@@ -123,11 +129,12 @@ def convergence_factor(mesh, f, omega, cycles=4):
     return (h[-1] / h[0]) ** (1.0 / (len(h) - 1))
 
 
-def grid_search(mesh, f, L, cycles=4, grid=OMEGA_GRID, tie=0.03):
+def grid_search(mesh, f, L, cycles=2, grid=OMEGA_GRID, tie=0.25):
     """Coordinate search over omega, finest level first.  Among the values
     whose rho is within a factor (1 + tie) of the best, the one closest to 1
-    is taken, so flat directions keep the paper's omega = 1.  Returns (omega
-    list of length L, rho at the result, rho at omega = 1)."""
+    is taken, so that only a clear gain moves a level away from the paper's
+    omega = 1.  Returns (omega list of length L, rho at the result, rho at
+    omega = 1)."""
     om = [1.0] * L
     rho1 = convergence_factor(mesh, f, om, cycles)
     best = rho1
@@ -155,7 +162,7 @@ def sample_mesh(p, lam_h2, ar, n=4):
     return hx, hy, hz, lam
 
 
-def build_dataset(degrees, lam_h2s, ars, n=4, seed=0, cycles=4, log=None):
+def build_dataset(degrees, lam_h2s, ars, n=4, seed=0, cycles=2, log=None):
     """Solver-measured targets for every (p, lambda h^2, AR) sample."""
     import torch
     import synth
@@ -187,8 +194,9 @@ def build_dataset(degrees, lam_h2s, ars, n=4, seed=0, cycles=4, log=None):
 
 
 def predict_damping(model, p, lam, hx, hy, hz, L):
-    """omega for the finest min(L, NOUT) levels; None without a model."""
+    """omega for the finest min(L, NOUT) levels; None without a model.  A
+    level whose output had no training target keeps omega = 1."""
     if model is None or L == 0:
         return None
     y = model.predict(mesh_features(p, lam, hx, hy, hz)[None, :])[0]
-    return [float(v) for v in y[:min(L, model.nout)]]
+    return [float(v) if model.trained[j] else 1.0 for j, v in enumerate(y[:min(L, model.nout)])]

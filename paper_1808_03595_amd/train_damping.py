@@ -3,10 +3,12 @@
 python -m paper_1808_03595_amd.train_damping [--out PATH] [--report PATH]
 
 1. Training set: anisotropic brick meshes of 6^3 elements (Sec. 5.3 recipe,
-   scaled) over p in {3, 4, 6, 8, 12, 16}, lambda h^2 in {0, 1e-2, 1, 1e2,
-   1e4}, AR in {1, 2, 4, 8, 16}; targets = per-level argmin of the
-   convergence factor of the deployed solver over omega in 0.5 .. 1.5
-   (step 0.05), ties going to the value closest to 1.
+   scaled) over p in {3, 4, 6, 8, 12, 16, 24, 32} (so that all four outputs,
+   the finest four smoothed levels, get targets), lambda h^2 in {0, 1e-2, 1,
+   1e2, 1e4}, AR in {1, 2, 4, 8, 16}; targets = per-level argmin of the
+   convergence factor of the deployed solver (first two iterations) over
+   omega in 0.5 .. 1.5 (step 0.05); values within 25 % of the best count as
+   ties, which go to the value closest to 1.
 2. Training: full-batch Adam (lr 1e-3) on the masked MSE, GPU kernels only.
 3. Held-out evaluation: 24^3 elements, p = 12, AR in {3, 6, 12},
    lambda h^2 in {0.3, 30, 3e3}; iterations and time to a 1e-10 relative
@@ -72,7 +74,7 @@ def main():
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--report", default=None)
     ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--degrees", default="3,4,6,8,12,16")
+    ap.add_argument("--degrees", default="3,4,6,8,12,16,24,32")
     ap.add_argument("--n", type=int, default=6, help="elements per direction of the training meshes")
     ap.add_argument("--skip-eval", action="store_true")
     args = ap.parse_args()
@@ -82,7 +84,7 @@ def main():
                                   log=log)
     t_data = time.perf_counter() - t0
     log(f"dataset: {len(X)} samples in {t_data:.1f} s")
-    model = DampingMLP(seed=0)
+    model = DampingMLP(seed=0, trained=np.asarray(M).any(axis=0))
     t0 = time.perf_counter()
     hist = model.train(X, T, M, steps=args.steps, lr=1e-3)
     t_train = time.perf_counter() - t0

@@ -79,3 +79,22 @@ def test_training_on_gpu_reduces_loss(gpu):
     assert hist[-1][1] < 0.05 * hist[0][1]
     pred = model.predict(X)
     assert np.sqrt(np.mean((pred[:, :3] - T[:, :3]) ** 2)) < 0.05
+
+
+def test_trained_network_against_omega1(gpu):
+    """The committed network on the held-out meshes (24^3 elements, p = 12,
+    anisotropic AR in {3, 6, 12}, lambda h^2 in {0.3, 30, 3e3}): the
+    mixed-precision solver with its damping needs in total no more outer
+    iterations to 1e-10 than with the paper's omega = 1, and no case more
+    than one iteration more (a case at the edge of 1e-10 may flip with the
+    order of the atomic sums)."""
+    from paper_1808_03595_amd.learn import DampingMLP
+    from paper_1808_03595_amd.train_damping import evaluate
+    model = DampingMLP.load()
+    assert model is not None and model.trained.all()
+    rows = evaluate(model)
+    it1 = [r["omega1"]["iters"] for r in rows]
+    itl = [r["learned"]["iters"] for r in rows]
+    assert all(r["omega1"]["status"] == 0 and r["learned"]["status"] == 0 for r in rows)
+    assert sum(itl) <= sum(it1), (itl, it1)
+    assert all(a <= b + 1 for a, b in zip(itl, it1)), (itl, it1)
