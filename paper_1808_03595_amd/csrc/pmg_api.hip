@@ -533,8 +533,7 @@ int read_scalars(pmg_mesh* m, hipStream_t st, bool queued = false) {
 
 template <typename T>
 void residual(Level& L, const T* F, const T* u, T* y, hipStream_t st) {
-    launch_condensed_op<T>(Sel<T>::tabs(L), u, y, st);
-    launch_sub_from<T>(F, y, L.lay.len, st);
+    launch_condensed_op<T>(Sel<T>::tabs(L), u, y, st, F);
 }
 
 template <typename T>

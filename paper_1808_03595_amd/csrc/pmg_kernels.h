@@ -5,7 +5,8 @@
 
 namespace pmg {
 
-constexpr int REDUCE_BLOCKS = 512;
+constexpr int REDUCE_BLOCKS = 128;   // workgroups of the reduction kernels
+constexpr int REDUCE_THREADS = 1024;
 
 hipError_t init_kernel_attributes();
 // Coarse CG (launch-per-iteration form): the init kernel, then iteration
@@ -23,7 +24,8 @@ int coarse_blocks(int ne, int p0);
 
 template <typename T> void launch_grid_to_skel(const Layout&, const double*, T*, hipStream_t);
 template <typename T> void launch_skel_to_grid(const Layout&, const T*, double*, hipStream_t);
-template <typename T> void launch_condensed_op(const LevelTabs<T>&, const T*, T*, hipStream_t);
+// y = H_hat u, or y = F - H_hat u (the residual) when F is given
+template <typename T> void launch_condensed_op(const LevelTabs<T>&, const T*, T*, hipStream_t, const T* F = nullptr);
 template <typename T> void launch_smoother_add(const LevelTabs<T>&, const T*, T*, T, hipStream_t);
 template <typename T>
 void launch_prolong_add(const Layout& Lc, const Layout& Lf, const T* J, const T* uc, T* uf, hipStream_t);

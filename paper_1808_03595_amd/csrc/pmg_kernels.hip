@@ -365,11 +365,13 @@ __global__ void __launch_bounds__(1024) k_condensed_op(LevelTabs<T> tb, const T*
 // Assembly of the element contributions: every slot of the plane layout is
 // written once; a canonical, non-Dirichlet node receives the sum, in a fixed
 // order, of the canonical tile entries of the (up to eight) elements that
-// contain it, every other slot zero.  Deterministic, no atomics.
+// contain it (or F minus that sum, the residual, when F is given), every
+// other slot zero.  Deterministic, no atomics.
 // Grid: x over columns (64 per block), y over rows (4 per block, the plane's
 // padding rows included), z over the planes of all three families.
 template <typename T, int P>
-__global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restrict__ E, T* __restrict__ y) {
+__global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restrict__ E, const T* __restrict__ F,
+                                                     T* __restrict__ y) {
     const int z = blockIdx.z;
     const int d = z >= L.n[0] + L.n[1] + 2 ? 2 : (z >= L.n[0] + 1 ? 1 : 0);
     const int j = z - (d == 0 ? 0 : (d == 1 ? L.n[0] + 1 : L.n[0] + L.n[1] + 2));
@@ -428,7 +430,7 @@ __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restri
     T acc = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc += v[k];
-    y[s] = acc;
+    y[s] = F ? F[s] - acc : acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -2158,7 +2160,7 @@ __device__ inline void finish_reduce(double* partials, const double* mine, int n
 
 // out[0] = x . y ; out[1] = x . z (if z non-null)
 template <typename T>
-__global__ void __launch_bounds__(256) k_dot2(const T* __restrict__ x, const T* __restrict__ y,
+__global__ void __launch_bounds__(REDUCE_THREADS) k_dot2(const T* __restrict__ x, const T* __restrict__ y,
                                               const T* __restrict__ z, int64_t n, double* partials,
                                               unsigned* counter, double* out) {
     __shared__ double red[16];
@@ -2198,7 +2200,7 @@ __global__ void k_pcg_dir(double* __restrict__ p, const double* __restrict__ z, 
 }
 
 // alpha = gamma / (q . p); s = r; u += alpha p; r -= alpha q; partial r.r
-__global__ void __launch_bounds__(256) k_pcg_update(double* __restrict__ u, double* __restrict__ r,
+__global__ void __launch_bounds__(REDUCE_THREADS) k_pcg_update(double* __restrict__ u, double* __restrict__ r,
                                                     double* __restrict__ s, const double* __restrict__ p,
                                                     const double* __restrict__ q, const double* sc_gamma,
                                                     const double* sc_qp, int64_t n, double* partials,
@@ -2223,7 +2225,7 @@ __global__ void __launch_bounds__(256) k_pcg_update(double* __restrict__ u, doub
 
 // Jacobi-PCG pieces for the coarse solve (FP64).
 // z = r / diag; partial (r . z)
-__global__ void __launch_bounds__(256) k_jacobi(const double* __restrict__ r, const double* __restrict__ dg,
+__global__ void __launch_bounds__(REDUCE_THREADS) k_jacobi(const double* __restrict__ r, const double* __restrict__ dg,
                                                 double* __restrict__ z, int64_t n, double* partials,
                                                 unsigned* counter, double* out) {
     __shared__ double red[16];
@@ -2727,7 +2729,7 @@ void launch_skel_to_grid(const Layout& L, const T* s, double* g, hipStream_t st)
 // assembly of the condensed operator: atomics (one launch) unless disabled
 
 template <typename T>
-static void launch_gather_elem(const Layout& L, const T* E, T* y, hipStream_t st) {
+static void launch_gather_elem(const Layout& L, const T* E, const T* F, T* y, hipStream_t st) {
     int mp = 0, mr = 0;
     for (int d = 0; d < 3; ++d) {
         mp = std::max(mp, L.pitch[d]);
@@ -2736,17 +2738,17 @@ static void launch_gather_elem(const Layout& L, const T* E, T* y, hipStream_t st
     const int planes = L.n[0] + L.n[1] + L.n[2] + 3;
     const dim3 grid((mp + 63) / 64, (mr + 3) / 4, planes), block(64, 4);
     switch (L.p) {
-        case 1: hipLaunchKernelGGL((k_gather_elem<T, 1>), grid, block, 0, st, L, E, y); break;
-        case 2: hipLaunchKernelGGL((k_gather_elem<T, 2>), grid, block, 0, st, L, E, y); break;
-        case 4: hipLaunchKernelGGL((k_gather_elem<T, 4>), grid, block, 0, st, L, E, y); break;
-        case 8: hipLaunchKernelGGL((k_gather_elem<T, 8>), grid, block, 0, st, L, E, y); break;
-        case 16: hipLaunchKernelGGL((k_gather_elem<T, 16>), grid, block, 0, st, L, E, y); break;
-        default: hipLaunchKernelGGL((k_gather_elem<T, 0>), grid, block, 0, st, L, E, y);
+        case 1: hipLaunchKernelGGL((k_gather_elem<T, 1>), grid, block, 0, st, L, E, F, y); break;
+        case 2: hipLaunchKernelGGL((k_gather_elem<T, 2>), grid, block, 0, st, L, E, F, y); break;
+        case 4: hipLaunchKernelGGL((k_gather_elem<T, 4>), grid, block, 0, st, L, E, F, y); break;
+        case 8: hipLaunchKernelGGL((k_gather_elem<T, 8>), grid, block, 0, st, L, E, F, y); break;
+        case 16: hipLaunchKernelGGL((k_gather_elem<T, 16>), grid, block, 0, st, L, E, F, y); break;
+        default: hipLaunchKernelGGL((k_gather_elem<T, 0>), grid, block, 0, st, L, E, F, y);
     }
 }
 
 template <typename T>
-void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t st) {
+void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t st, const T* F) {
     const int ne = tb.lay.n[0] * tb.lay.n[1] * tb.lay.n[2];
     switch (tb.lay.p) {
 #define PMG_K1W(PP)                                                                                       \
@@ -2763,7 +2765,7 @@ void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t s
             hipLaunchKernelGGL((k_condensed_op<T>), dim3(ne), dim3(tb.lay.p > 16 ? 1024 : 256), sm, st, t, u);
         }
     }
-    launch_gather_elem(tb.lay, (const T*)tb.opE, y, st);
+    launch_gather_elem(tb.lay, (const T*)tb.opE, F, y, st);
 }
 
 constexpr int MFMA_WPB = 2;
@@ -2943,7 +2945,7 @@ void launch_recover(const LevelTabs<double>& tb, const double* f, const double* 
 template <typename T>
 void launch_dot2(const T* x, const T* y, const T* z, int64_t n, double* partials, unsigned* counter,
                  double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_dot2<T>, dim3(REDUCE_BLOCKS), dim3(256), 0, st, x, y, z, n, partials, counter, out);
+    hipLaunchKernelGGL(k_dot2<T>, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, st, x, y, z, n, partials, counter, out);
 }
 
 void launch_pcg_dir(double* p, const double* z, const double* sc, int64_t n, hipStream_t st) {
@@ -2953,7 +2955,7 @@ void launch_pcg_dir(double* p, const double* z, const double* sc, int64_t n, hip
 void launch_pcg_update(double* u, double* r, double* s, const double* p, const double* q, const double* gam,
                        const double* qp, int64_t n, double* partials, unsigned* counter, double* out,
                        double* delta_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_update, dim3(REDUCE_BLOCKS), dim3(256), 0, st, u, r, s, p, q, gam, qp, n, partials,
+    hipLaunchKernelGGL(k_pcg_update, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, st, u, r, s, p, q, gam, qp, n, partials,
                        counter, out, delta_out);
 }
 
@@ -2994,7 +2996,7 @@ template void launch_fill_zero<int>(int*, int64_t, hipStream_t);
 
 void launch_jacobi(const double* r, const double* dg, double* z, int64_t n, double* partials, unsigned* counter,
                    double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_jacobi, dim3(REDUCE_BLOCKS), dim3(256), 0, st, r, dg, z, n, partials, counter, out);
+    hipLaunchKernelGGL(k_jacobi, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, st, r, dg, z, n, partials, counter, out);
 }
 
 void launch_cg_xr(double* x, double* r, const double* p, const double* q, const double* sc, int64_t n,
@@ -3084,7 +3086,7 @@ hipError_t init_kernel_attributes() {
 #define INST(T)                                                                                            \
     template void launch_grid_to_skel<T>(const Layout&, const double*, T*, hipStream_t);                    \
     template void launch_skel_to_grid<T>(const Layout&, const T*, double*, hipStream_t);                    \
-    template void launch_condensed_op<T>(const LevelTabs<T>&, const T*, T*, hipStream_t);                  \
+    template void launch_condensed_op<T>(const LevelTabs<T>&, const T*, T*, hipStream_t, const T*);        \
     template void launch_smoother_add<T>(const LevelTabs<T>&, const T*, T*, T, hipStream_t);               \
     template void launch_prolong_add<T>(const Layout&, const Layout&, const T*, const T*, T*, hipStream_t); \
     template void launch_restrict<T>(const Layout&, const Layout&, const T*, const T*, T*, T*, hipStream_t); \
