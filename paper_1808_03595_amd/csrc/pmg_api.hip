@@ -257,9 +257,7 @@ int build_coarse(pmg_mesh* m, Level& lev) {
     if ((rc = m->upload(&a.diag, dg))) return rc;
     const size_t nv = (size_t)L0.len;
     a.X = lev.u64;  // the V-cycle reads the coarse solution from there
-    if ((rc = m->alloc(&a.p, nv))) return rc;
-    for (int k = 0; k < 2; ++k)
-        if ((rc = m->alloc(&a.R[k], nv)) || (rc = m->alloc(&a.Q[k], nv))) return rc;
+    if ((rc = m->alloc(&a.rec, 8 * nv))) return rc;
     for (int k = 0; k < 3; ++k)
         if ((rc = m->alloc(&a.W[k], nv))) return rc;
     a.blocks = coarse_blocks(ne, p0);
@@ -602,15 +600,16 @@ int coarse_launch_range(pmg_mesh* m, Level& L0, long j0, long n, hipStream_t st)
     return 0;
 }
 
-int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st, bool init_queued = false) {
+// With `in_graphs` the caller's graphs hold the initialisation (before) and
+// the extraction of x (after); otherwise both are launched here.
+int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st, bool in_graphs = false) {
     Level& L0 = *m->act[0];
     CoarseArgs& a = L0.ca;
-    // the iterations update the level's own array a.X; a copy follows for
-    // any other destination
     auto deliver = [&]() -> int {
-        if (x != a.X) HIPCHK(hipMemcpyAsync(x, a.X, (size_t)a.lay.len * sizeof(double), hipMemcpyDeviceToDevice, st));
+        if (!in_graphs) HIPCHK(launch_coarse_extract(a, x, st));
         return 0;
     };
+    const bool init_queued = in_graphs;
     if (!init_queued) HIPCHK(launch_coarse_init(a, b, m->coarse_maxit, m->coarse_rtol, st));
     const int64_t id = ++m->coarse_id;
     if (a.N0 == 0) return deliver();
@@ -1110,7 +1109,8 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
             // |r|, the norm taken from the device), then the direction and
             // the update.  Everything but the coarse CG iterations is
             // replayed from two graphs captured on first use (the first ends
-            // with the coarse CG's initialisation).
+            // with the coarse CG's initialisation, the second starts with the
+            // extraction of its solution).
             const int gi = pdt == PMG_F64 ? 0 : 2;
             const double* cb;
             double* cx;
@@ -1130,6 +1130,7 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
                     return 0;
                 };
                 auto part_b = [&](hipStream_t s) -> int {
+                    HIPCHK(launch_coarse_extract(m->act[0]->ca, cx, s));
                     int r2 = pdt == PMG_F64 ? vc_up<double>(m, m->w_r, m->w_z, s)
                                             : vc_up<float>(m, m->w_r32, m->w_z32, s);
                     if (r2) return r2;

@@ -174,9 +174,10 @@ struct CoarseArgs {
     const double* diag;   // diagonal of the operator at unknowns, 0 at every other slot
     const double* el_m[3];  // level-0 element tables
     const double* el_L[3];
-    double* X;            // the iterate x (level-0 skeleton array, fixed per mesh)
-    double* p;            // search direction, updated in place by the owning element
-    double *R[2], *Q[2];  // ping-pong residual and q = A p
+    double* X;            // level-0 skeleton array that receives the solution x
+    // per slot one 64-byte record, so that a node's CG state is one cache
+    // line: [diag, -, r0, q0, r1, q1, p, x] (r and q = A p ping-pong)
+    double* rec;
     double *W[3];         // rotating accumulators of w = A z
     double *P[2];         // [2 * blocks] per-block partial sums (r.z, w.z)
     CoarseState* S;       // [2] scalar state, ping-pong

@@ -20,6 +20,8 @@ void launch_publish(const double* sc, int n, int64_t* cnt, HostMail* mail, hipSt
 void launch_pcg_start(const double* F, double* r, double* s, double* u, double* p, double* delta, int64_t n,
                       hipStream_t st);
 hipError_t launch_coarse_iter(const CoarseArgs& a, int j, bool last, hipStream_t st);
+// x of the finished coarse CG into the plane-layout array x
+hipError_t launch_coarse_extract(const CoarseArgs& a, double* x, hipStream_t st);
 int coarse_blocks(int ne, int p0);
 
 template <typename T> void launch_grid_to_skel(const Layout&, const double*, T*, hipStream_t);

@@ -2313,13 +2313,15 @@ __global__ void k_coarse_init(CoarseArgs a, const double* __restrict__ b, int ma
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t s = t; s < a.lay.len; s += stride) {
-        a.R[0][s] = a.diag[s] != 0.0 ? b[s] : 0.0;
-        a.Q[0][s] = 0.0;
+        const double dg = a.diag[s];
+        double2* rc = reinterpret_cast<double2*>(a.rec + 8 * s);
+        rc[0] = make_double2(dg, 0.0);
+        rc[1] = make_double2(dg != 0.0 ? b[s] : 0.0, 0.0);  // r0, q0
+        rc[2] = make_double2(0.0, 0.0);                       // r1, q1
+        rc[3] = make_double2(0.0, 0.0);                       // p, x
         a.W[0][s] = 0.0;
         a.W[1][s] = 0.0;
         a.W[2][s] = 0.0;
-        a.p[s] = 0.0;
-        a.X[s] = 0.0;
     }
     if (t == 0) {
         // solves are numbered on the device, in stream order, so that this
@@ -2373,9 +2375,11 @@ __device__ inline double coarse_row(const double* tb, const double* u, double la
     return y;
 }
 
+constexpr int COARSE_THREADS = 256;  // threads per workgroup of the coarse iteration (1024 measured slower)
+
 template <int P0>
 struct CoarseShape {
-    static constexpr int nn = P0 + 1, nl = nn * nn * nn, epb = 256 / nl;
+    static constexpr int nn = P0 + 1, nl = nn * nn * nn, epb = COARSE_THREADS / nl;
 };
 
 // Sum of (x, y) over the block, returned to every thread (each adds the
@@ -2401,13 +2405,13 @@ __device__ inline void block_sum2_all(double& x, double& y, double* red) {
 }
 
 template <int P0>
-__global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j, int last) {
+__global__ void __launch_bounds__(COARSE_THREADS) k_coarse_iter(CoarseArgs a, int j, int last) {
     using CS = CoarseShape<P0>;
     constexpr int nn = CS::nn, nl = CS::nl, EPB = CS::epb;
     __shared__ double tab[EPB][36];
     __shared__ double zl[EPB][nl];
-    __shared__ double red[8];
-    __shared__ double red2[8];
+    __shared__ double red[2 * COARSE_THREADS / 64];
+    __shared__ double red2[2 * COARSE_THREADS / 64];
     const int jr = j & 1, jn = jr ^ 1;
     // every load that does not depend on this iteration's scalars is issued
     // first (the previous launch's partial sums included), so that their
@@ -2430,19 +2434,21 @@ __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j, int la
     }
     const CoarseState si = a.S[jr];
     double dg = 1.0, ro = 0.0, qo = 0.0, wo = 0.0, po = 0.0, xo = 0.0;
+    double2* rc = reinterpret_cast<double2*>(a.rec + 8 * gi);
     if (unk) {
-        dg = a.diag[gi];
-        ro = a.R[jr][gi];
-        qo = a.Q[jr][gi];
+        const double2 v0 = rc[0], v1 = rc[1], v2 = rc[2], v3 = rc[3];
+        dg = v0.x;
+        ro = jr ? v2.x : v1.x;
+        qo = jr ? v2.y : v1.y;
+        po = v3.x;
+        xo = v3.y;
         wo = a.W[j % 3][gi];
-        po = a.p[gi];
-        xo = a.X[gi];
     }
-    constexpr int NTAB = (EPB * 36 + 255) / 256;
+    constexpr int NTAB = (EPB * 36 + COARSE_THREADS - 1) / COARSE_THREADS;
     double tv[NTAB];
 #pragma unroll
     for (int k = 0; k < NTAB; ++k) {
-        const int t = threadIdx.x + 256 * k, tel = t / 36, to = t - tel * 36, te = blockIdx.x * EPB + tel;
+        const int t = threadIdx.x + COARSE_THREADS * k, tel = t / 36, to = t - tel * 36, te = blockIdx.x * EPB + tel;
         double v = 0.0;
         if (tel < EPB && te < a.ne) {
             const int c0 = te % a.n[0], c1 = (te / a.n[0]) % a.n[1], c2 = te / (a.n[0] * a.n[1]);
@@ -2502,7 +2508,7 @@ __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j, int la
     }
 #pragma unroll
     for (int k = 0; k < NTAB; ++k) {
-        const int t = threadIdx.x + 256 * k;
+        const int t = threadIdx.x + COARSE_THREADS * k;
         if (t < EPB * 36) tab[t / 36][t % 36] = tv[k];
     }
     double zn = 0.0, gpart = 0.0, dpart = 0.0;
@@ -2514,10 +2520,8 @@ __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j, int la
                          (a3 < P0 || c3 == a.n[2] - 1);
         if (own) {
             const double pn = ro / dg + beta * po;
-            a.p[gi] = pn;
-            a.X[gi] = xo + alpha * pn;
-            a.R[jn][gi] = rn;
-            a.Q[jn][gi] = qn;
+            rc[1 + jn] = make_double2(rn, qn);
+            rc[3] = make_double2(pn, xo + alpha * pn);
             a.W[(j + 2) % 3][gi] = 0.0;
             gpart = rn * zn;
         }
@@ -2539,6 +2543,12 @@ __global__ void __launch_bounds__(256) k_coarse_iter(CoarseArgs a, int j, int la
             if (last && a.mail) a.mail->rseq = (so.id << 20) | (int64_t)so.it;
         }
     }
+}
+
+// x of the coarse CG records into a plane-layout array
+__global__ void k_coarse_extract(CoarseArgs a, double* __restrict__ x) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < a.lay.len) x[s] = a.rec[8 * s + 7];
 }
 
 // ---------------------------------------------------------------------------
@@ -3051,6 +3061,11 @@ hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, int maxit, d
     return hipGetLastError();
 }
 
+hipError_t launch_coarse_extract(const CoarseArgs& a, double* x, hipStream_t st) {
+    hipLaunchKernelGGL(k_coarse_extract, dim3(nblk(std::max<int64_t>(a.lay.len, 1))), dim3(256), 0, st, a, x);
+    return hipGetLastError();
+}
+
 int coarse_blocks(int ne, int p0) {
     const int epb = p0 == 2 ? CoarseShape<2>::epb : CoarseShape<1>::epb;
     return std::max(1, (ne + epb - 1) / epb);
@@ -3058,9 +3073,9 @@ int coarse_blocks(int ne, int p0) {
 
 hipError_t launch_coarse_iter(const CoarseArgs& a, int j, bool last, hipStream_t st) {
     if (a.p0 == 2)
-        hipLaunchKernelGGL(k_coarse_iter<2>, dim3(a.blocks), dim3(256), 0, st, a, j, (int)last);
+        hipLaunchKernelGGL(k_coarse_iter<2>, dim3(a.blocks), dim3(COARSE_THREADS), 0, st, a, j, (int)last);
     else
-        hipLaunchKernelGGL(k_coarse_iter<1>, dim3(a.blocks), dim3(256), 0, st, a, j, (int)last);
+        hipLaunchKernelGGL(k_coarse_iter<1>, dim3(a.blocks), dim3(COARSE_THREADS), 0, st, a, j, (int)last);
     return hipGetLastError();
 }
 
