@@ -38,14 +38,14 @@ if ROOT not in sys.path:
 
 PEAK = {"f64": 78.6, "f32": 157.3}   # TFLOP/s, MI355X dense vector / matrix
 HBM_PEAK = 8000.0                     # GB/s
-ROOFLINE_KERNEL = "k_smoother_mfma<float, 2>"
+ROOFLINE_KERNEL = "k_smoother_mfma<float, 1>"
 
 # HBM bytes per launch of the roofline kernel at the default workload, from
 # two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of
 # "python bench.py --kernel-only", each scaled by the same counter's reading
 # for a plain 512 MiB device copy; valid only for the kernel source whose
 # hash is recorded with it.
-TRAFFIC = {"kernels_sha1": "75f570bd457893260a57cd11e2a79f5cc62c434f", "bytes_per_launch": 27083806}
+TRAFFIC = {"kernels_sha1": "e469eb185fd70e471248006f1c1e6c9d82bc5281", "bytes_per_launch": 19026903}
 
 
 def log(msg):
@@ -325,7 +325,7 @@ def main():
                      "achieved": ach32, "peak": PEAK["f32"], "unit": "TFLOP/s",
                      "frac": ach32 / PEAK["f32"], "traffic": traffic,
                      "us_per_launch": ts32 * 1e6,
-                     "fp64": {"kernel": "k_smoother_mfma<double, 2>", "achieved": ach64, "peak": PEAK["f64"],
+                     "fp64": {"kernel": "k_smoother_mfma<double, 1>", "achieved": ach64, "peak": PEAK["f64"],
                               "frac": ach64 / PEAK["f64"], "us_per_launch": ts64 * 1e6}},
         "cpu_baseline": cpu,
         "p_sweep": sweep,

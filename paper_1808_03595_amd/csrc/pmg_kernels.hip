@@ -43,6 +43,15 @@ __device__ __forceinline__ T* pick3(int d, T* a0, T* a1, T* a2) {
     return d == 0 ? a0 : (d == 1 ? a1 : a2);
 }
 
+// Workgroups are dispatched to the eight XCDs (each with its own L2) round
+// robin, b -> b % 8.  Work item of workgroup b such that every XCD gets one
+// contiguous range of items (neighbouring stars and elements share data).
+// A bijection of [0, G); only locality depends on the dispatch order.
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+    const int x = b & 7, i = b >> 3, q = G >> 3, r = G & 7;
+    return x * q + (x < r ? x : r) + i;
+}
+
 template <typename T>
 __device__ inline void add_out(T* y, int64_t s, T v) {
     y[s] += v;
@@ -469,10 +478,11 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
     T* Tc = sm + K::o_Tc;
     const Layout& L = tb.lay;
     const int lane = threadIdx.x;
+    const int eid = xcd_remap(blockIdx.x, gridDim.x);
     int e[3];
-    color_coords(blockIdx.x, -1, L.n, e);
+    color_coords(eid, -1, L.n, e);
     const T lam = tb.lam;
-    T* out = tb.opE + (size_t)blockIdx.x * 6 * t2;
+    T* out = tb.opE + (size_t)eid * 6 * t2;
     // 1D tables of this element (per direction m[n1] L[n1^2] Si[q^2] MS[q^2]
     // lm[q] c0[q] cp[q]) and the six face tiles: all global loads are issued
     // before the first LDS store, so their latencies overlap
@@ -917,7 +927,7 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
     const Layout& L = tb.lay;
     const int p = L.p, nS = 2 * p - 1, c = p - 1;
     const int nv1 = L.n[0] + 1, nv2 = L.n[1] + 1, nv3 = L.n[2] + 1;
-    const int star = blockIdx.x * WPB + wv;
+    const int star = xcd_remap(blockIdx.x, gridDim.x) * WPB + wv;
     bool active = star < nv1 * nv2 * nv3;
     int v1 = 0, v2 = 0, v3 = 0;
     if (active) {
@@ -1172,7 +1182,7 @@ __global__ void __launch_bounds__(256) k_smoother_small(LevelTabs<T> tb, const T
     const Layout& L = tb.lay;
     const int p = L.p, nS = 2 * p - 1, c = p - 1;
     const int nv1 = L.n[0] + 1, nv2 = L.n[1] + 1, nv3 = L.n[2] + 1;
-    const int star = blockIdx.x * SS::SPB + (int)(threadIdx.x / G);
+    const int star = xcd_remap(blockIdx.x, gridDim.x) * SS::SPB + (int)(threadIdx.x / G);
     bool active = star < nv1 * nv2 * nv3;
     int v1 = 0, v2 = 0, v3 = 0;
     if (active) {
@@ -2778,7 +2788,7 @@ void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t s
     launch_gather_elem(tb.lay, (const T*)tb.opE, F, y, st);
 }
 
-constexpr int MFMA_WPB = 2;
+constexpr int MFMA_WPB = 1;  // wavefronts (stars) per workgroup: 2 and 4 measured slower in FP64
 
 template <typename T>
 void launch_smoother_add(const LevelTabs<T>& tb, const T* r, T* du, T omega, hipStream_t st) {
