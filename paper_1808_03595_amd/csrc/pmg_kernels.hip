@@ -2427,7 +2427,8 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_coarse_iter(CoarseArgs a, in
     // first (the previous launch's partial sums included), so that their
     // latencies overlap
     const int el = threadIdx.x / nl, l = threadIdx.x - el * nl;
-    const int e = blockIdx.x * EPB + el;
+    const int e0 = xcd_remap(blockIdx.x, gridDim.x) * EPB;  // first element of this workgroup
+    const int e = e0 + el;
     const bool act = el < EPB && e < a.ne;
     const int a1 = l % nn, a2 = (l / nn) % nn, a3 = l / (nn * nn);
     const int c1 = e % a.n[0], c2 = (e / a.n[0]) % a.n[1], c3 = e / (a.n[0] * a.n[1]);
@@ -2458,7 +2459,7 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_coarse_iter(CoarseArgs a, in
     double tv[NTAB];
 #pragma unroll
     for (int k = 0; k < NTAB; ++k) {
-        const int t = threadIdx.x + COARSE_THREADS * k, tel = t / 36, to = t - tel * 36, te = blockIdx.x * EPB + tel;
+        const int t = threadIdx.x + COARSE_THREADS * k, tel = t / 36, to = t - tel * 36, te = e0 + tel;
         double v = 0.0;
         if (tel < EPB && te < a.ne) {
             const int c0 = te % a.n[0], c1 = (te / a.n[0]) % a.n[1], c2 = te / (a.n[0] * a.n[1]);
