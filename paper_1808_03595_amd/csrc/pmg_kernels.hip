@@ -459,9 +459,11 @@ struct K1Shape {
     static constexpr int n1 = P + 1, q = P - 1, t2 = n1 * n1, q2 = q * q;
     static constexpr int tab_d = n1 + n1 * n1 + 2 * q2 + 3 * q;       // one direction
     static constexpr int tabs = 3 * tab_d;
-    // LDS layout (in elements of T)
-    static constexpr int o_tab = 0, o_tile = tabs, o_G = o_tile + 6 * t2, o_tmp = o_G + 6 * q2,
-                         o_V = o_tmp + 6 * q2, o_Tc = o_V + q * q2, total = o_Tc + 6 * q2;
+    // LDS layout (in elements of T); tmp shares V's region (the forward tmp
+    // is dead before V is written, V before the backward tmp)
+    static constexpr int vt = q * q2 > 6 * q2 ? q * q2 : 6 * q2;
+    static constexpr int o_tab = 0, o_tile = tabs, o_G = o_tile + 6 * t2, o_V = o_G + 6 * q2, o_tmp = o_V,
+                         o_Tc = o_V + vt, total = o_Tc + 6 * q2;
 };
 
 template <typename T, int P>
