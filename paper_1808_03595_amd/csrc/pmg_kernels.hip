@@ -378,7 +378,7 @@ __global__ void __launch_bounds__(1024) k_condensed_op(LevelTabs<T> tb, const T*
 // other slot zero.  Deterministic, no atomics.
 // Grid: x over columns (64 per block), y over rows (4 per block, the plane's
 // padding rows included), z over the planes of all three families.
-template <typename T, int P>
+template <typename T, int P, bool NODES = false>
 __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restrict__ E, const T* __restrict__ F,
                                                      T* __restrict__ y) {
     const int z = blockIdx.z;
@@ -430,6 +430,10 @@ __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restri
                 const int c1 = x ? e1[0] : e0[0], c2 = yy ? e1[1] : e0[1], c3 = z ? e1[2] : e0[2];
                 const int b1 = x ? a1[0] : a0[0], b2 = yy ? a1[1] : a0[1], b3 = z ? a1[2] : a0[2];
                 const int64_t e = ((int64_t)c3 * L.n[1] + c2) * L.n[0] + c1;
+                if (NODES) {  // workspace: (p+1)^3 node block per element
+                    v[k] = E[e * n1 * n1 * n1 + (b3 * n1 + b2) * n1 + b1];
+                    continue;
+                }
                 int f, tr, tc;
                 if (b1 == 0 || b1 == p) { f = b1 ? 1 : 0; tr = b3; tc = b2; }
                 else if (b2 == 0 || b2 == p) { f = b2 ? 3 : 2; tr = b3; tc = b1; }
@@ -1833,6 +1837,106 @@ __global__ void k_mass_skeleton(Layout L, const double* __restrict__ m1, const d
 }
 
 // Fhat -= H_BI H_II^-1 F_I, element by element (colour launches).
+// Condensation and recovery for p <= 2 (Alg. 4, first and last steps).  A
+// degree-2 element has a single interior node (the centre, local index 1);
+// with a diagonal M it couples only to the six face centres, through the
+// three lines that cross it: H_IB[face (d, a)] = (product of the other two
+// m[1]) L_d[a][1].  Degree 1 has no interior.
+//   s_e = F_I / H_II,  F_I = m1 m2 m3 f(centre)
+//   F_hat(face centre) -= sum over its two elements of H_BI s_e
+//   u_I = (F_I - sum over the six face centres of H_IB u_hat) / H_II
+struct TinyElem {
+    double m[3][3];   // m_d[k]
+    double l[3][3];   // L_d[k][1]
+};
+__device__ inline TinyElem tiny_elem(const LevelTabs<double>& tb, int c0, int c1, int c2) {
+    TinyElem t;
+    const int c[3] = {c0, c1, c2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double* m = pick3(d, tb.el_m[0], tb.el_m[1], tb.el_m[2]) + c[d] * 3;
+        const double* L = pick3(d, tb.el_L[0], tb.el_L[1], tb.el_L[2]) + c[d] * 9;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            t.m[d][k] = m[k];
+            t.l[d][k] = L[k * 3 + 1];
+        }
+    }
+    return t;
+}
+__device__ inline double tiny_hii(const TinyElem& t, double lam) {
+    const double m0 = t.m[0][1], m1 = t.m[1][1], m2 = t.m[2][1];
+    return lam * m0 * m1 * m2 + m1 * m2 * t.l[0][1] + m0 * m2 * t.l[1][1] + m0 * m1 * t.l[2][1];
+}
+// coupling of the centre to the face centre at local coordinate a (0 or 2) in direction d
+__device__ inline double tiny_hib(const TinyElem& t, int d, int a) {
+    const double mo = d == 0 ? t.m[1][1] * t.m[2][1] : (d == 1 ? t.m[0][1] * t.m[2][1] : t.m[0][1] * t.m[1][1]);
+    return mo * t.l[d][a];
+}
+__device__ inline double tiny_fi(const LevelTabs<double>& tb, const TinyElem& t, const double* f, int c0, int c1,
+                                 int c2) {
+    const Layout& L = tb.lay;
+    return t.m[0][1] * t.m[1][1] * t.m[2][1] *
+           f[((int64_t)(2 * c2 + 1) * L.N[1] + (2 * c1 + 1)) * L.N[0] + (2 * c0 + 1)];
+}
+
+// p = 2: one thread per element corrects the three face centres on its
+// lower faces (each face centre belongs to one element below and one above;
+// on the domain boundary it is a Dirichlet node), with both elements' terms
+// in a fixed order: deterministic, no atomics.
+__global__ void k_condense_tiny(LevelTabs<double> tb, const double* __restrict__ f, double* __restrict__ Fh) {
+    const Layout& L = tb.lay;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= L.n[0] * L.n[1] * L.n[2]) return;
+    const int c0 = e % L.n[0], c1 = (e / L.n[0]) % L.n[1], c2 = e / (L.n[0] * L.n[1]);
+    const TinyElem te = tiny_elem(tb, c0, c1, c2);
+    const double se = tiny_fi(tb, te, f, c0, c1, c2) / tiny_hii(te, tb.lam);
+    const int ec[3] = {c0, c1, c2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int cd = d == 0 ? c0 : (d == 1 ? c1 : c2);
+        if (cd == 0) continue;
+        const int n0 = d == 0 ? c0 - 1 : c0, n1 = d == 1 ? c1 - 1 : c1, n2 = d == 2 ? c2 - 1 : c2;
+        const TinyElem tn = tiny_elem(tb, n0, n1, n2);
+        const double sn = tiny_fi(tb, tn, f, n0, n1, n2) / tiny_hii(tn, tb.lam);
+        const int64_t slot = elem_slot(L, ec, d == 0 ? 0 : 1, d == 1 ? 0 : 1, d == 2 ? 0 : 1);
+        Fh[slot] -= tiny_hib(tn, d, 2) * sn + tiny_hib(te, d, 0) * se;
+    }
+}
+
+// p <= 2: one thread per element node writes the nodes the element owns
+// (a_d < p, or a_d = p on the last element): shell values copied from
+// u_hat (zero at Dirichlet nodes), the degree-2 centre recovered.
+template <int P>
+__global__ void __launch_bounds__(256) k_recover_tiny(LevelTabs<double> tb, const double* __restrict__ f,
+                                                      const double* __restrict__ uh, double* __restrict__ ug) {
+    constexpr int nn = P + 1, nl = nn * nn * nn, EPB = 256 / nl;
+    const Layout& L = tb.lay;
+    const int el = threadIdx.x / nl, l = threadIdx.x - el * nl;
+    const int e = blockIdx.x * EPB + el;
+    if (el >= EPB || e >= L.n[0] * L.n[1] * L.n[2]) return;
+    const int a1 = l % nn, a2 = (l / nn) % nn, a3 = l / (nn * nn);
+    const int c0 = e % L.n[0], c1 = (e / L.n[0]) % L.n[1], c2 = e / (L.n[0] * L.n[1]);
+    if ((a1 == P && c0 != L.n[0] - 1) || (a2 == P && c1 != L.n[1] - 1) || (a3 == P && c2 != L.n[2] - 1)) return;
+    const int i1 = c0 * P + a1, i2 = c1 * P + a2, i3 = c2 * P + a3;
+    const int ec[3] = {c0, c1, c2};
+    double v;
+    if (P == 2 && l == 13) {
+        const TinyElem te = tiny_elem(tb, c0, c1, c2);
+        double r = tiny_fi(tb, te, f, c0, c1, c2);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int a = 0; a <= 2; a += 2)
+                r -= tiny_hib(te, d, a) *
+                     uh[elem_slot(L, ec, d == 0 ? a : 1, d == 1 ? a : 1, d == 2 ? a : 1)];
+        v = r / tiny_hii(te, tb.lam);
+    } else {
+        v = is_dir(L, i1, i2, i3) ? 0.0 : uh[elem_slot(L, ec, a1, a2, a3)];
+    }
+    ug[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1] = v;
+}
+
 __global__ void __launch_bounds__(256) k_condense(LevelTabs<double> tb, const double* __restrict__ f,
                                                   double* __restrict__ Fh, int color) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -2357,28 +2461,28 @@ __global__ void k_coarse_init(CoarseArgs a, const double* __restrict__ b, int ma
 // Row of the level-0 element operator (condensed for p_0 = 2: one interior
 // node) at local node (a1, a2, a3), applied to the element vector u.
 // tb: m1[3] m2[3] m3[3] at 0, 3, 6; L1, L2, L3 (row-major nn x nn) at 9, 18, 27.
-template <int P0>
-__device__ inline double coarse_row(const double* tb, const double* u, double lam, int a1, int a2, int a3) {
+template <int P0, typename T>
+__device__ inline T coarse_row(const T* tb, const T* u, T lam, int a1, int a2, int a3) {
     constexpr int nn = P0 + 1;
-    const double *m1 = tb, *m2 = tb + 3, *m3 = tb + 6, *L1 = tb + 9, *L2 = tb + 18, *L3 = tb + 27;
-    double x1 = 0.0, x2 = 0.0, x3 = 0.0;
+    const T *m1 = tb, *m2 = tb + 3, *m3 = tb + 6, *L1 = tb + 9, *L2 = tb + 18, *L3 = tb + 27;
+    T x1 = 0, x2 = 0, x3 = 0;
 #pragma unroll
     for (int jj = 0; jj < nn; ++jj) {
         x1 += L1[a1 * nn + jj] * u[(a3 * nn + a2) * nn + jj];
         x2 += L2[a2 * nn + jj] * u[(a3 * nn + jj) * nn + a1];
         x3 += L3[a3 * nn + jj] * u[(jj * nn + a2) * nn + a1];
     }
-    double y = lam * m1[a1] * m2[a2] * m3[a3] * u[(a3 * nn + a2) * nn + a1] + m3[a3] * m2[a2] * x1 +
+    T y = lam * m1[a1] * m2[a2] * m3[a3] * u[(a3 * nn + a2) * nn + a1] + m3[a3] * m2[a2] * x1 +
                m3[a3] * m1[a1] * x2 + m2[a2] * m1[a1] * x3;
     if (P0 == 2) {
         // Schur complement of the interior node (1,1,1): y -= H_BI s / H_II,
         // s = H_IB u (only the six face centres couple to the interior)
-        const double s = m3[1] * m2[1] * (L1[3] * u[12] + L1[5] * u[14]) +
+        const T s = m3[1] * m2[1] * (L1[3] * u[12] + L1[5] * u[14]) +
                          m3[1] * m1[1] * (L2[3] * u[10] + L2[5] * u[16]) +
                          m2[1] * m1[1] * (L3[3] * u[4] + L3[5] * u[22]);
-        const double hii = lam * m1[1] * m2[1] * m3[1] + m3[1] * m2[1] * L1[4] + m3[1] * m1[1] * L2[4] +
+        const T hii = lam * m1[1] * m2[1] * m3[1] + m3[1] * m2[1] * L1[4] + m3[1] * m1[1] * L2[4] +
                            m2[1] * m1[1] * L3[4];
-        double col = 0.0;
+        T col = 0;
         if (a2 == 1 && a3 == 1) col = m3[1] * m2[1] * L1[a1 * 3 + 1];
         else if (a1 == 1 && a3 == 1) col = m3[1] * m1[1] * L2[a2 * 3 + 1];
         else if (a1 == 1 && a2 == 1) col = m2[1] * m1[1] * L3[a3 * 3 + 1];
@@ -2393,6 +2497,59 @@ template <int P0>
 struct CoarseShape {
     static constexpr int nn = P0 + 1, nl = nn * nn * nn, epb = COARSE_THREADS / nl;
 };
+
+// Condensed operator for degrees 1 and 2 (the lowest p-level and the
+// degree-1 levels): one thread per element node, several elements per
+// workgroup; a thread forms its node's row of the element operator (p = 2:
+// including the Schur term of the element's single interior node) from the
+// element's 1D tables and shell values and stores it in the element's
+// (p+1)^3 node block of the workspace, which k_gather_elem<T, P, true> sums
+// per node.
+template <typename T, int P>
+__global__ void __launch_bounds__(COARSE_THREADS) k_condensed_op_tiny(LevelTabs<T> tb, const T* __restrict__ u) {
+    using CS = CoarseShape<P>;
+    constexpr int nn = CS::nn, nl = CS::nl, EPB = CS::epb;
+    __shared__ T tab[EPB][36];
+    __shared__ T ul[EPB][nl];
+    const Layout& L = tb.lay;
+    const int ne = L.n[0] * L.n[1] * L.n[2];
+    const int el = threadIdx.x / nl, l = threadIdx.x - el * nl;
+    const int e0 = xcd_remap(blockIdx.x, gridDim.x) * EPB;
+    const int e = e0 + el;
+    const bool act = el < EPB && e < ne;
+    const int a1 = l % nn, a2 = (l / nn) % nn, a3 = l / (nn * nn);
+    const int c1 = e % L.n[0], c2 = (e / L.n[0]) % L.n[1], c3 = e / (L.n[0] * L.n[1]);
+    const int g1 = c1 * P + a1, g2 = c2 * P + a2, g3 = c3 * P + a3;
+    // unknown: a shell node (the p = 2 element centre is interior) off the boundary
+    const bool unk = act && (P == 1 || l != 13) && !(g1 == 0 || g2 == 0 || g3 == 0 || g1 == L.N[0] - 1 ||
+                                                       g2 == L.N[1] - 1 || g3 == L.N[2] - 1);
+    const int ec[3] = {c1, c2, c3};
+    const int64_t gi = unk ? elem_slot(L, ec, a1, a2, a3) : 0;
+    const T uv = unk ? u[gi] : T(0);
+    constexpr int NTAB = (EPB * 36 + COARSE_THREADS - 1) / COARSE_THREADS;
+#pragma unroll
+    for (int k = 0; k < NTAB; ++k) {
+        const int t = threadIdx.x + COARSE_THREADS * k, tel = t / 36, to = t - tel * 36, te = e0 + tel;
+        if (tel >= EPB) continue;
+        T v = 0;
+        if (te < ne) {
+            const int d0 = te % L.n[0], d1 = (te / L.n[0]) % L.n[1], d2 = te / (L.n[0] * L.n[1]);
+            if (to < 9) {
+                const int d = to / 3, kk = to % 3;
+                const int cd = d == 0 ? d0 : (d == 1 ? d1 : d2);
+                if (kk < nn) v = pick3(d, tb.el_m[0], tb.el_m[1], tb.el_m[2])[cd * nn + kk];
+            } else {
+                const int d = (to - 9) / 9, kk = (to - 9) % 9;
+                const int cd = d == 0 ? d0 : (d == 1 ? d1 : d2);
+                if (kk < nn * nn) v = pick3(d, tb.el_L[0], tb.el_L[1], tb.el_L[2])[cd * nn * nn + kk];
+            }
+        }
+        tab[tel][to] = v;
+    }
+    if (act) ul[el][l] = uv;
+    __syncthreads();
+    if (unk) tb.opE[(size_t)e * nl + l] = coarse_row<P, T>(tab[el], ul[el], tb.lam, a1, a2, a3);
+}
 
 // Sum of (x, y) over the block, returned to every thread (each adds the
 // per-wave totals in the same order, so all hold the same bits).
@@ -2542,7 +2699,7 @@ __global__ void __launch_bounds__(COARSE_THREADS) k_coarse_iter(CoarseArgs a, in
     if (act) zl[el][l] = zn;
     __syncthreads();
     if (unk) {
-        const double y = coarse_row<P0>(tab[el], zl[el], a.lam, a1, a2, a3);
+        const double y = coarse_row<P0, double>(tab[el], zl[el], a.lam, a1, a2, a3);
         unsafeAtomicAdd(a.W[(j + 1) % 3] + gi, y);
         dpart = y * zn;
     }
@@ -2761,8 +2918,8 @@ static void launch_gather_elem(const Layout& L, const T* E, const T* F, T* y, hi
     const int planes = L.n[0] + L.n[1] + L.n[2] + 3;
     const dim3 grid((mp + 63) / 64, (mr + 3) / 4, planes), block(64, 4);
     switch (L.p) {
-        case 1: hipLaunchKernelGGL((k_gather_elem<T, 1>), grid, block, 0, st, L, E, F, y); break;
-        case 2: hipLaunchKernelGGL((k_gather_elem<T, 2>), grid, block, 0, st, L, E, F, y); break;
+        case 1: hipLaunchKernelGGL((k_gather_elem<T, 1, true>), grid, block, 0, st, L, E, F, y); break;
+        case 2: hipLaunchKernelGGL((k_gather_elem<T, 2, true>), grid, block, 0, st, L, E, F, y); break;
         case 4: hipLaunchKernelGGL((k_gather_elem<T, 4>), grid, block, 0, st, L, E, F, y); break;
         case 8: hipLaunchKernelGGL((k_gather_elem<T, 8>), grid, block, 0, st, L, E, F, y); break;
         case 16: hipLaunchKernelGGL((k_gather_elem<T, 16>), grid, block, 0, st, L, E, F, y); break;
@@ -2773,13 +2930,23 @@ static void launch_gather_elem(const Layout& L, const T* E, const T* F, T* y, hi
 template <typename T>
 void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t st, const T* F) {
     const int ne = tb.lay.n[0] * tb.lay.n[1] * tb.lay.n[2];
+    if (tb.lay.p <= 2) {
+        if (tb.lay.p == 2)
+            hipLaunchKernelGGL((k_condensed_op_tiny<T, 2>), dim3((ne + CoarseShape<2>::epb - 1) / CoarseShape<2>::epb),
+                               dim3(COARSE_THREADS), 0, st, tb, u);
+        else
+            hipLaunchKernelGGL((k_condensed_op_tiny<T, 1>), dim3((ne + CoarseShape<1>::epb - 1) / CoarseShape<1>::epb),
+                               dim3(COARSE_THREADS), 0, st, tb, u);
+        launch_gather_elem(tb.lay, (const T*)tb.opE, F, y, st);
+        return;
+    }
     switch (tb.lay.p) {
 #define PMG_K1W(PP)                                                                                       \
     case PP:                                                                                              \
         hipLaunchKernelGGL((k_condensed_op_w<T, PP>), dim3(ne), dim3(64), sizeof(T) * K1Shape<PP>::total, st, \
                            tb, u);                                                                        \
         break;
-        PMG_K1W(1) PMG_K1W(2) PMG_K1W(3) PMG_K1W(4) PMG_K1W(5) PMG_K1W(6) PMG_K1W(7) PMG_K1W(8)
+        PMG_K1W(3) PMG_K1W(4) PMG_K1W(5) PMG_K1W(6) PMG_K1W(7) PMG_K1W(8)
         PMG_K1W(12) PMG_K1W(16)
 #undef PMG_K1W
         default: {
@@ -2926,6 +3093,10 @@ void launch_condense(const LevelTabs<double>& tb, const double* m1, const double
     hipLaunchKernelGGL(k_mass_skeleton, dim3(nblk(L.len)), dim3(256), 0, st, L, m1, m2, m3, f, Fh);
     int q = L.p - 1;
     if (q < 1) return;
+    if (L.p == 2) {
+        hipLaunchKernelGGL(k_condense_tiny, dim3(nblk((int64_t)L.n[0] * L.n[1] * L.n[2])), dim3(256), 0, st, tb, f, Fh);
+        return;
+    }
     if (tb.ixX[0]) {
         const int ne = L.n[0] * L.n[1] * L.n[2];
         hipLaunchKernelGGL(k_int_load, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, f, tb.ixX[0]);
@@ -2947,6 +3118,14 @@ void launch_condense(const LevelTabs<double>& tb, const double* m1, const double
 
 void launch_recover(const LevelTabs<double>& tb, const double* f, const double* uh, double* ug, hipStream_t st) {
     const Layout& L = tb.lay;
+    if (L.p <= 2) {
+        const int64_t ne = (int64_t)L.n[0] * L.n[1] * L.n[2];
+        if (L.p == 2)
+            hipLaunchKernelGGL(k_recover_tiny<2>, dim3((unsigned)((ne + 8) / 9)), dim3(256), 0, st, tb, f, uh, ug);
+        else
+            hipLaunchKernelGGL(k_recover_tiny<1>, dim3((unsigned)((ne + 31) / 32)), dim3(256), 0, st, tb, f, uh, ug);
+        return;
+    }
     if (tb.ixX[0]) {
         const int ne = L.n[0] * L.n[1] * L.n[2], n1 = L.p + 1, q = L.p - 1;
         hipLaunchKernelGGL(k_int_load, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, f, tb.ixX[0]);
