@@ -107,6 +107,9 @@ struct pmg_mesh {
     int hmg_nu = 1;
     // coarse CG counters shared by all bottom levels
     int* d_coarse_iters = nullptr;
+    // number of coarse solves started, counted on the device by every coarse
+    // level's initialisation (one counter per mesh, like coarse_id)
+    int64_t* d_coarse_seq = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream for graph capture
     // Alg. 5 iteration graphs per preconditioner precision: [2 pdt + 0] up to
     // the coarse solve, [2 pdt + 1] after it; rebuilt after any change of
@@ -268,8 +271,7 @@ int build_coarse(pmg_mesh* m, Level& lev) {
     HIPCHK(hipMemset(a.stat, 0, 2 * sizeof(int)));
     a.iters = m->d_coarse_iters;
     a.mail = m->dmail;
-    if ((rc = m->alloc(&a.seq, 1))) return rc;
-    HIPCHK(hipMemset(a.seq, 0, sizeof(int64_t)));
+    a.seq = m->d_coarse_seq;
     lev.has_ca = true;
     return 0;
 }
@@ -428,8 +430,9 @@ int build_mesh(pmg_mesh* m) {
     m->omega.assign(degs.size(), 1.0);
     int rc = check_lds(m->p);
     if (rc) return rc;
-    if ((rc = m->alloc(&m->d_coarse_iters, 1))) return rc;
+    if ((rc = m->alloc(&m->d_coarse_iters, 1)) || (rc = m->alloc(&m->d_coarse_seq, 1))) return rc;
     HIPCHK(hipMemset(m->d_coarse_iters, 0, sizeof(int)));
+    HIPCHK(hipMemset(m->d_coarse_seq, 0, sizeof(int64_t)));
     HIPCHK(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
     for (size_t l = 0; l < degs.size(); ++l) {
         Level& L = m->lv[l];

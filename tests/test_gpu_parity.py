@@ -293,3 +293,23 @@ def test_pcg_solve_mixed_repeated(gpu):
         assert rel(u.cpu().numpy(), ref.u) <= 1e-8, k
         its.append(st.iters)
     assert its[1] == its[5] == ref.iters
+
+
+def test_solves_across_coarse_level_changes(gpu):
+    """Solves with a coarse tolerance (the host waits for the device's
+    completion notices), then with degree-1 levels below p_0 (another coarse
+    level), then without them again: every solve finishes and reaches the
+    tolerance, and the solutions agree with the oracle's."""
+    n, p, lam, alpha = (4, 4, 4), 4, 1.0, 1.2
+    g, o = make_pair(n, p, lam, alpha)
+    g.set_cycle(0, 1e-6, 500)
+    f = synth.random_grid(o.shape, 95)
+    ref = solver.solve(o, f, method="kMG", rtol=1e-10, coarse_rtol=1e-6, coarse_maxit=500)
+    df = torch.as_tensor(f, device=gpu)
+    for levels in (0, 2, 0, 1):
+        g.set_coarse_mg(levels, 0.8, 2)
+        for dt in (pmg.F64, pmg.F32):
+            u = torch.zeros(o.shape, dtype=torch.float64, device=gpu)
+            st = g.pcg_solve(df, u, 1e-10, 100, dt)
+            assert st.status == 0 and st.rel_res <= 1e-10, (levels, dt, st.status, st.rel_res)
+            assert rel(u.cpu().numpy(), ref.u) <= 1e-8, (levels, dt)
