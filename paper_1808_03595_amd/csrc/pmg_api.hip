@@ -941,10 +941,10 @@ int pmg_schwarz_smooth(pmg_mesh* m, int level, int dtype, const void* r, void* d
     if (!r || !du || r == du) return fail(PMG_EINVAL, "null or aliasing pointers");
     Level& L = m->lv[level];
     if (dtype == PMG_F64) {
-        HIPCHK(hipMemsetAsync(du, 0, L.lay.len * sizeof(double), S(stream)));
+        launch_fill_zero<double>((double*)du, L.lay.len, S(stream));  // a kernel: capturable
         launch_smoother_add<double>(L.t64, (const double*)r, (double*)du, omega, S(stream));
     } else if (dtype == PMG_F32) {
-        HIPCHK(hipMemsetAsync(du, 0, L.lay.len * sizeof(float), S(stream)));
+        launch_fill_zero<float>((float*)du, L.lay.len, S(stream));
         launch_smoother_add<float>(L.t32, (const float*)r, (float*)du, (float)omega, S(stream));
     } else return fail(PMG_EINVAL, "bad dtype");
     HIPCHK(hipGetLastError());
