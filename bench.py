@@ -44,8 +44,8 @@ ROOFLINE_KERNEL = "k_smoother_mfma<float, 1>"
 # two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of
 # "python bench.py --kernel-only", each scaled by the same counter's reading
 # for a plain 512 MiB device copy; valid only for the kernel source whose
-# hash is recorded with it.
-TRAFFIC = {"kernels_sha1": "8828731f5a756643eea5a864ee069f5ad57a19d0", "bytes_per_launch": 19026913}
+# hash (kernels_sha1 below) is recorded with it.
+TRAFFIC = {"kernels_sha1": "ae5cb0e76caa24277f67d2386022436f6d5fd787", "bytes_per_launch": 19026913}
 
 
 def log(msg):
@@ -53,9 +53,22 @@ def log(msg):
 
 
 def kernels_sha1():
-    path = os.path.join(ROOT, "paper_1808_03595_amd", "csrc", "pmg_kernels.hip")
-    with open(path, "rb") as fh:
-        return hashlib.sha1(fh.read()).hexdigest()
+    """Hash of the source the roofline kernel is built from: the shared
+    helpers at the top of the kernel file, the matrix-core smoother itself,
+    the internal header and the compiler flags (edits elsewhere in the
+    kernel file leave its traffic record valid)."""
+    csrc = os.path.join(ROOT, "paper_1808_03595_amd", "csrc")
+    with open(os.path.join(csrc, "pmg_kernels.hip")) as fh:
+        src = fh.read()
+    head = src[:src.index("template <typename T>\n__device__ inline void add_out")]
+    body = src[src.index("// Matrix-core star smoother for n_S"):src.index("// Star smoother for small stars")]
+    with open(os.path.join(csrc, "pmg_internal.h")) as fh:
+        hdr = fh.read()
+    from paper_1808_03595_amd import build as pbuild
+    h = hashlib.sha1()
+    for part in (head, body, hdr, " ".join(pbuild.FLAGS)):
+        h.update(part.encode())
+    return h.hexdigest()
 
 
 def workload(name):
@@ -65,6 +78,10 @@ def workload(name):
         return dict(n=(8, 8, 8), p=16, lam=1.0, alpha=8.0 ** (1.0 / 7.0), seed=0)
     if name == "c1":
         return dict(n=(4, 4, 4), p=4, lam=1.0, alpha=1.0, seed=0)
+    if name.startswith("c3p") and name[3:].isdigit():  # one point of the p sweep
+        p = int(name[3:])
+        nn = int(round(215.44 / p))
+        return dict(n=(nn, nn, nn), p=p, lam=1.0, alpha=1.0, seed=0)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -85,6 +102,18 @@ def smoother_flops(n, p):
     nS = 2 * p - 1
     nstars = (n[0] + 1) * (n[1] + 1) * (n[2] + 1) - 8
     return 37.0 * nS ** 3 * nstars
+
+
+def smoother_kernel(p, t):
+    """The smoother kernel that degree p runs (t: "float" or "double")."""
+    nS = 2 * p - 1
+    if nS <= 4:
+        return f"k_smoother_small<{t}, 4>"
+    if nS <= 8:
+        return f"k_smoother_small<{t}, 8>"
+    if nS <= 16:
+        return f"k_smoother_mfma<{t}, 1>"
+    return f"k_star_gemm<{t}, ...> + k_star_eigen<{t}> (batched)"
 
 
 def time_smoother(g, torch, dev, dtype, reps=50):
@@ -199,8 +228,9 @@ def main():
     ap.add_argument("--coarse-rtol", type=float, default=3e-2,
                     help="relative tolerance of the coarse CG (the paper leaves it open)")
     ap.add_argument("--damping", choices=["learned", "one"], default="learned")
-    ap.add_argument("--hmg-levels", type=int, default=0,
-                    help="degree-1 levels below p_0 (0: the paper's CG on p_0 = 2)")
+    ap.add_argument("--hmg-levels", type=int, default=None,
+                    help="degree-1 levels below p_0 (0: the paper's CG on p_0 = 2; "
+                         "default 6 at p <= 4 as in the p sweep, else 0)")
     ap.add_argument("--hmg-omega", type=float, default=0.8)
     ap.add_argument("--hmg-nu", type=int, default=2)
     ap.add_argument("--kernel-only", action="store_true",
@@ -236,8 +266,9 @@ def main():
         log(f"[bench] {ROOFLINE_KERNEL}: {t * 1e6:.2f} us per launch")
         return
     g.set_cycle(0, args.coarse_rtol, 2000)
-    if args.hmg_levels:
-        g.set_coarse_mg(args.hmg_levels, args.hmg_omega, args.hmg_nu)
+    hmg = args.hmg_levels if args.hmg_levels is not None else (6 if p <= 4 else 0)
+    if hmg:
+        g.set_coarse_mg(hmg, args.hmg_omega, args.hmg_nu)
     u_ex, f = make_rhs(g, wl, torch, synth, dev)
     u = torch.zeros_like(f)
     ndof = n[0] * n[1] * n[2] * p ** 3
@@ -272,15 +303,23 @@ def main():
         t32, st32, err32 = t1, st1, err1
     g.set_damping(None)
 
-    ts64 = time_smoother(g, torch, dev, pmg.F64)
-    ts32 = time_smoother(g, torch, dev, pmg.F32)
-    fl = smoother_flops(n, p)
-    ach32 = fl / ts32 / 1e12
-    ach64 = fl / ts64 / 1e12
-    log(f"[bench] smoother f64 {ts64*1e6:.1f} us ({ach64:.2f} TF/s), f32 {ts32*1e6:.1f} us ({ach32:.2f} TF/s)")
-    traffic = None
-    if TRAFFIC["kernels_sha1"] == kernels_sha1() and args.workload == "c2a":
-        traffic = TRAFFIC["bytes_per_launch"]
+    roof = None
+    if L > 0:   # p_0 = 2 alone has no smoothed level
+        ts64 = time_smoother(g, torch, dev, pmg.F64)
+        ts32 = time_smoother(g, torch, dev, pmg.F32)
+        fl = smoother_flops(n, p)
+        ach32 = fl / ts32 / 1e12
+        ach64 = fl / ts64 / 1e12
+        log(f"[bench] smoother f64 {ts64*1e6:.1f} us ({ach64:.2f} TF/s), f32 {ts32*1e6:.1f} us ({ach32:.2f} TF/s)")
+        traffic = None
+        if TRAFFIC["kernels_sha1"] == kernels_sha1() and args.workload == "c2a":
+            traffic = TRAFFIC["bytes_per_launch"]
+        roof = {"bound": "mfma", "kernel": smoother_kernel(p, "float"),
+                "achieved": ach32, "peak": PEAK["f32"], "unit": "TFLOP/s",
+                "frac": ach32 / PEAK["f32"], "traffic": traffic,
+                "us_per_launch": ts32 * 1e6,
+                "fp64": {"kernel": smoother_kernel(p, "double"), "achieved": ach64, "peak": PEAK["f64"],
+                         "frac": ach64 / PEAK["f64"], "us_per_launch": ts64 * 1e6}}
 
     cpu = None
     if not args.no_cpu:
@@ -314,19 +353,14 @@ def main():
                    "ndof": ndof, "iters": st32.iters, "rel_res": st32.rel_res,
                    "damping": "learned" if omega is not None else "omega=1 (paper)",
                    "omega": omega,
-                   "coarse": (f"Jacobi CG on p_0=2 to rel. {args.coarse_rtol:g}" if not args.hmg_levels else
-                              f"{args.hmg_levels} degree-1 levels + CG"),
+                   "coarse": (f"Jacobi CG on p_0=2 to rel. {args.coarse_rtol:g}" if not hmg else
+                              f"{hmg} degree-1 levels + CG"),
                    "coarse_iters_per_solve": st32.coarse_iters,
                    "mixed_omega1_unknowns_per_s": ndof / t1, "mixed_omega1_iters": st1.iters,
                    "fp64_unknowns_per_s": ndof / t64, "fp64_iters": st64.iters,
                    "fp64_ms_per_solve": t64 * 1e3,
                    "rel_err_vs_exact_mixed": err32, "rel_err_vs_exact_fp64": err64},
-        "roofline": {"bound": "mfma", "kernel": ROOFLINE_KERNEL,
-                     "achieved": ach32, "peak": PEAK["f32"], "unit": "TFLOP/s",
-                     "frac": ach32 / PEAK["f32"], "traffic": traffic,
-                     "us_per_launch": ts32 * 1e6,
-                     "fp64": {"kernel": "k_smoother_mfma<double, 1>", "achieved": ach64, "peak": PEAK["f64"],
-                              "frac": ach64 / PEAK["f64"], "us_per_launch": ts64 * 1e6}},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "p_sweep": sweep,
     }

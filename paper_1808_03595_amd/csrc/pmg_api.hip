@@ -196,6 +196,7 @@ int fill_tabs(pmg_mesh* m, LevelTabs<T>& tb, const HostTables& t, const Layout& 
         if ((rc = m->upload(&tb.st_lam[d], t.st_lam[d]))) break;
         if ((rc = m->upload(&tb.st_SP[d], t.st_SP[d]))) break;
         if ((rc = m->upload(&tb.st_lamP[d], t.st_lamP[d]))) break;
+        if (!t.ax[d].empty() && (rc = m->upload(&tb.ax[d], t.ax[d]))) break;
     }
     if (!rc) rc = m->upload(&tb.st_wP, t.st_wP);
     if (!rc) rc = m->upload(&tb.st_w, t.st_w);
@@ -293,11 +294,19 @@ int build_level(pmg_mesh* m, Level& L, int p, int pc, const std::vector<double> 
         (rc = m->alloc(&L.u32, n)) || (rc = m->alloc(&L.F32, n)) || (rc = m->alloc(&L.y32, n)))
         return rc;
     // condensed-operator workspace, shared by the FP64 and FP32 tables
-    double* ew = nullptr;
+    // (degrees 1 and 2 form the operator per node, without one)
     const size_t ne = (size_t)L.lay.n[0] * L.lay.n[1] * L.lay.n[2];
-    if ((rc = m->alloc(&ew, ne * 6 * (size_t)(p + 1) * (p + 1)))) return rc;
-    L.t64.opE = ew;
-    L.t32.opE = reinterpret_cast<float*>(ew);
+    if (p > 2) {
+        double* ew = nullptr;
+        if ((rc = m->alloc(&ew, ne * 6 * (size_t)(p + 1) * (p + 1)))) return rc;
+        L.t64.opE = ew;
+        L.t32.opE = reinterpret_cast<float*>(ew);
+    } else if (p == 2) {  // one value per element (its interior node)
+        double* tw = nullptr;
+        if ((rc = m->alloc(&tw, ne))) return rc;
+        L.t64.tc = tw;
+        L.t32.tc = reinterpret_cast<float*>(tw);
+    }
     // workspaces of the batched star smoother (n_S > 16)
     if (2 * p - 1 > 16) {
         const int np = L.t64.np;

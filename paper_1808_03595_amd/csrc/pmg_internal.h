@@ -70,6 +70,11 @@ struct LevelTabs {
     // interpolation from the next coarser level: (p+1) x (pc+1), row-major
     const T* J;
     int pc;
+    // p <= 2: assembled 1D matrices per direction, one record of AXW entries
+    // per global node index i: [M~(i,i), L~(i,i-p) .. L~(i,i+p), 0...]
+    const T* ax[3];
+    // p = 2: per element, (H_IB u)_e / (H_II)_e of the condensed operator
+    T* tc;
     // workspace of the condensed operator: per element, the six face tiles
     // of its contribution, [e][6][(p+1)^2] (only canonical entries used)
     T* opE;
@@ -116,8 +121,10 @@ struct HostTables {
         el_c0[3], el_cp[3], st_S[3], st_lam[3];
     std::vector<double> st_w, J;
     std::vector<double> st_SP[3], st_lamP[3], st_wP;
+    std::vector<double> ax[3];  // p <= 2 only
     int np = 16;
 };
+constexpr int AXW = 8;  // entries per record of the assembled 1D tables
 
 // Host set-up (pmg_setup.cpp)
 void gll_nodes_weights(int p, std::vector<double>& x, std::vector<double>& w);

@@ -375,12 +375,13 @@ __global__ void __launch_bounds__(1024) k_condensed_op(LevelTabs<T> tb, const T*
 // written once; a canonical, non-Dirichlet node receives the sum, in a fixed
 // order, of the canonical tile entries of the (up to eight) elements that
 // contain it (or F minus that sum, the residual, when F is given), every
-// other slot zero.  Deterministic, no atomics.
+// other slot zero.  With `sub`, y -= sum at those nodes and every other
+// slot is left as it is.  Deterministic, no atomics.
 // Grid: x over columns (64 per block), y over rows (4 per block, the plane's
 // padding rows included), z over the planes of all three families.
-template <typename T, int P, bool NODES = false>
+template <typename T, int P>
 __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restrict__ E, const T* __restrict__ F,
-                                                     T* __restrict__ y) {
+                                                     T* __restrict__ y, int sub) {
     const int z = blockIdx.z;
     const int d = z >= L.n[0] + L.n[1] + 2 ? 2 : (z >= L.n[0] + 1 ? 1 : 0);
     const int j = z - (d == 0 ? 0 : (d == 1 ? L.n[0] + 1 : L.n[0] + L.n[1] + 2));
@@ -397,7 +398,7 @@ __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restri
     else if (d == 1) { g[1] = j * p; g[2] = r; g[0] = c; canon = canon && c < L.N[0] && c % p != 0; }
     else { g[2] = j * p; g[1] = r; g[0] = c; canon = canon && c < L.N[0] && c % p != 0 && r % p != 0; }
     if (!canon || is_dir(L, g[0], g[1], g[2])) {
-        y[s] = (T)0;
+        if (!sub) y[s] = (T)0;
         return;
     }
     // candidate (element index, local index) per direction: one element, or
@@ -430,10 +431,6 @@ __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restri
                 const int c1 = x ? e1[0] : e0[0], c2 = yy ? e1[1] : e0[1], c3 = z ? e1[2] : e0[2];
                 const int b1 = x ? a1[0] : a0[0], b2 = yy ? a1[1] : a0[1], b3 = z ? a1[2] : a0[2];
                 const int64_t e = ((int64_t)c3 * L.n[1] + c2) * L.n[0] + c1;
-                if (NODES) {  // workspace: (p+1)^3 node block per element
-                    v[k] = E[e * n1 * n1 * n1 + (b3 * n1 + b2) * n1 + b1];
-                    continue;
-                }
                 int f, tr, tc;
                 if (b1 == 0 || b1 == p) { f = b1 ? 1 : 0; tr = b3; tc = b2; }
                 else if (b2 == 0 || b2 == p) { f = b2 ? 3 : 2; tr = b3; tc = b1; }
@@ -443,7 +440,8 @@ __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restri
     T acc = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc += v[k];
-    y[s] = F ? F[s] - acc : acc;
+    if (sub) y[s] -= acc;
+    else y[s] = F ? F[s] - acc : acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -1938,7 +1936,7 @@ __global__ void __launch_bounds__(256) k_recover_tiny(LevelTabs<double> tb, cons
 }
 
 __global__ void __launch_bounds__(256) k_condense(LevelTabs<double> tb, const double* __restrict__ f,
-                                                  double* __restrict__ Fh, int color) {
+                                                  double* __restrict__ Fh, int color, double* __restrict__ ws) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* sm = tb.gws ? tb.gws + (size_t)blockIdx.x * ws_condense(tb.lay.p) : reinterpret_cast<double*>(smem_raw);
     const Layout& L = tb.lay;
@@ -1978,6 +1976,15 @@ __global__ void __launch_bounds__(256) k_condense(LevelTabs<double> tb, const do
     }
     __syncthreads();
     eigen_to_faces(P, p, Tc, tmp, cor);
+    if (ws) {   // the element's six face tiles (zero off the face interiors), summed by k_gather_elem
+        const int n1 = p + 1, t2 = n1 * n1;
+        double* out = ws + (size_t)blockIdx.x * 6 * t2;
+        for (int i = threadIdx.x; i < 6 * t2; i += blockDim.x) {
+            const int f = i / t2, rc = i - f * t2, r = rc / n1, c = rc - r * n1;
+            out[i] = (r > 0 && r < p && c > 0 && c < p) ? cor[f * q2 + (r - 1) * q + (c - 1)] : 0.0;
+        }
+        return;
+    }
     for (int i = threadIdx.x; i < 6 * q2; i += blockDim.x) {
         int f = i / q2, rc = i - f * q2, r = rc / q + 1, c = rc % q + 1;
         int a1, a2, a3;
@@ -2499,56 +2506,150 @@ struct CoarseShape {
 };
 
 // Condensed operator for degrees 1 and 2 (the lowest p-level and the
-// degree-1 levels): one thread per element node, several elements per
-// workgroup; a thread forms its node's row of the element operator (p = 2:
-// including the Schur term of the element's single interior node) from the
-// element's 1D tables and shell values and stores it in the element's
-// (p+1)^3 node block of the workspace, which k_gather_elem<T, P, true> sums
-// per node.
+// degree-1 levels), one thread per slot of the plane layout, no workspace.
+//
+// With a diagonal mass matrix the element interior couples only to the
+// face-interior nodes (Sec. 2.2); for p <= 2 an element has at most one
+// interior node, its centre, which couples to the six face centres alone.
+// The boundary block H_BB of the assembled operator on a tensor-product
+// mesh is the sum of Kronecker products of the assembled 1D matrices,
+//   lam M3 (x) M2 (x) M1 + M3 (x) M2 (x) L1 + M3 (x) L2 (x) M1 + L3 (x) M2 (x) M1,
+// so (H_BB u)_i is an axis stencil of width 2p + 1 per direction with the
+// skeleton values (element centres taken as zero).  The Schur term
+// H_BI H_II^-1 H_IB u (p = 2) only changes face centres: each subtracts,
+// for the two elements that share its face, its coupling to the element
+// centre times t_e = (H_IB u)_e / (H_II)_e, formed beforehand from the six
+// face centres of each element (k_centre_t).
+// ---------------------------------------------------------------------------
+
+// Slot of the skeleton value at global node (i1, i2, i3); `ok` is false
+// (and the slot `dflt`) outside the node grid, at Dirichlet nodes and at
+// element interiors, whose value counts as zero.
+template <int P>
+__device__ __forceinline__ int64_t skel_slot(const Layout& L, int i1, int i2, int i3, int64_t dflt, bool& ok) {
+    const bool in = i1 > 0 && i2 > 0 && i3 > 0 && i1 < L.N[0] - 1 && i2 < L.N[1] - 1 && i3 < L.N[2] - 1;
+    const bool on1 = i1 % P == 0, on2 = i2 % P == 0, on3 = i3 % P == 0;
+    ok = in && (on1 || on2 || on3);
+    return ok ? L.slot(i1, i2, i3, on1, on2) : dflt;
+}
+
 template <typename T, int P>
-__global__ void __launch_bounds__(COARSE_THREADS) k_condensed_op_tiny(LevelTabs<T> tb, const T* __restrict__ u) {
-    using CS = CoarseShape<P>;
-    constexpr int nn = CS::nn, nl = CS::nl, EPB = CS::epb;
-    __shared__ T tab[EPB][36];
-    __shared__ T ul[EPB][nl];
+__device__ __forceinline__ T skel_load(const Layout& L, const T* __restrict__ u, int i1, int i2, int i3) {
+    bool ok;
+    const int64_t sl = skel_slot<P>(L, i1, i2, i3, 0, ok);
+    const T v = u[sl];
+    return ok ? v : T(0);
+}
+
+// t_e = (H_IB u)_e / (H_II)_e for every element of a degree-2 level: the
+// element centre row of the element operator restricted to its six face
+// centres, over the centre's diagonal entry.  One thread per element.
+template <typename T>
+__global__ void __launch_bounds__(256) k_centre_t(LevelTabs<T> tb, const T* __restrict__ u) {
     const Layout& L = tb.lay;
     const int ne = L.n[0] * L.n[1] * L.n[2];
-    const int el = threadIdx.x / nl, l = threadIdx.x - el * nl;
-    const int e0 = xcd_remap(blockIdx.x, gridDim.x) * EPB;
-    const int e = e0 + el;
-    const bool act = el < EPB && e < ne;
-    const int a1 = l % nn, a2 = (l / nn) % nn, a3 = l / (nn * nn);
-    const int c1 = e % L.n[0], c2 = (e / L.n[0]) % L.n[1], c3 = e / (L.n[0] * L.n[1]);
-    const int g1 = c1 * P + a1, g2 = c2 * P + a2, g3 = c3 * P + a3;
-    // unknown: a shell node (the p = 2 element centre is interior) off the boundary
-    const bool unk = act && (P == 1 || l != 13) && !(g1 == 0 || g2 == 0 || g3 == 0 || g1 == L.N[0] - 1 ||
-                                                       g2 == L.N[1] - 1 || g3 == L.N[2] - 1);
-    const int ec[3] = {c1, c2, c3};
-    const int64_t gi = unk ? elem_slot(L, ec, a1, a2, a3) : 0;
-    const T uv = unk ? u[gi] : T(0);
-    constexpr int NTAB = (EPB * 36 + COARSE_THREADS - 1) / COARSE_THREADS;
+    const int e = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (e >= ne) return;
+    const int e1 = e % L.n[0], e2 = (e / L.n[0]) % L.n[1], e3 = e / (L.n[0] * L.n[1]);
+    const int c1 = 2 * e1 + 1, c2 = 2 * e2 + 1, c3 = 2 * e3 + 1;
+    const T u1m = skel_load<T, 2>(L, u, c1 - 1, c2, c3), u1p = skel_load<T, 2>(L, u, c1 + 1, c2, c3);
+    const T u2m = skel_load<T, 2>(L, u, c1, c2 - 1, c3), u2p = skel_load<T, 2>(L, u, c1, c2 + 1, c3);
+    const T u3m = skel_load<T, 2>(L, u, c1, c2, c3 - 1), u3p = skel_load<T, 2>(L, u, c1, c2, c3 + 1);
+    const T m1 = tb.el_m[0][e1 * 3 + 1], m2 = tb.el_m[1][e2 * 3 + 1], m3 = tb.el_m[2][e3 * 3 + 1];
+    const T* L1 = tb.el_L[0] + e1 * 9 + 3;  // row 1 (the centre) of each element matrix
+    const T* L2 = tb.el_L[1] + e2 * 9 + 3;
+    const T* L3 = tb.el_L[2] + e3 * 9 + 3;
+    const T s = m2 * m3 * (L1[0] * u1m + L1[2] * u1p) + m1 * m3 * (L2[0] * u2m + L2[2] * u2p) +
+                m1 * m2 * (L3[0] * u3m + L3[2] * u3p);
+    const T hii = tb.lam * m1 * m2 * m3 + m2 * m3 * L1[1] + m1 * m3 * L2[1] + m1 * m2 * L3[1];
+    tb.tc[e] = s / hii;
+}
+
+// Assembled 1D mass entry and stiffness row at global index i of one
+// direction: c[o + P] = L~(i, i + o), o = -P..P (zero where uncoupled).
+template <typename T, int P>
+__device__ __forceinline__ void axis_rec(const T* __restrict__ ax, int i, T& mm, T c[2 * P + 1]) {
+    const T* r = static_cast<const T*>(__builtin_assume_aligned(ax + (size_t)i * AXW, AXW * sizeof(T)));
+    mm = r[0];
 #pragma unroll
-    for (int k = 0; k < NTAB; ++k) {
-        const int t = threadIdx.x + COARSE_THREADS * k, tel = t / 36, to = t - tel * 36, te = e0 + tel;
-        if (tel >= EPB) continue;
-        T v = 0;
-        if (te < ne) {
-            const int d0 = te % L.n[0], d1 = (te / L.n[0]) % L.n[1], d2 = te / (L.n[0] * L.n[1]);
-            if (to < 9) {
-                const int d = to / 3, kk = to % 3;
-                const int cd = d == 0 ? d0 : (d == 1 ? d1 : d2);
-                if (kk < nn) v = pick3(d, tb.el_m[0], tb.el_m[1], tb.el_m[2])[cd * nn + kk];
-            } else {
-                const int d = (to - 9) / 9, kk = (to - 9) % 9;
-                const int cd = d == 0 ? d0 : (d == 1 ? d1 : d2);
-                if (kk < nn * nn) v = pick3(d, tb.el_L[0], tb.el_L[1], tb.el_L[2])[cd * nn * nn + kk];
-            }
-        }
-        tab[tel][to] = v;
+    for (int k = 0; k <= 2 * P; ++k) c[k] = r[1 + k];
+}
+
+// Grid: one workgroup of 64 x 4 threads per (64-column, 4-row) tile of a
+// plane, over the planes of all three families (1D grid, XCD-aware order);
+// every slot is written once (zero off the unknowns), y = H u or F - H u.
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_condensed_op_low(LevelTabs<T> tb, const T* __restrict__ u,
+                                                          const T* __restrict__ F, T* __restrict__ y, int bx,
+                                                          int by) {
+    const Layout& L = tb.lay;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int z = b / (bx * by), rem = b - z * bx * by, byi = rem / bx, bxi = rem - byi * bx;
+    const int d = z >= L.n[0] + L.n[1] + 2 ? 2 : (z >= L.n[0] + 1 ? 1 : 0);
+    const int j = z - (d == 0 ? 0 : (d == 1 ? L.n[0] + 1 : L.n[0] + L.n[1] + 2));
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int r = byi * 4 + ty, c = bxi * 64 + tx;
+    const int pitch = L.pitch[d];
+    if (c >= pitch) return;
+    const int64_t within = (int64_t)r * pitch + c;
+    if (within >= L.pstride[d]) return;
+    const int64_t s = L.off[d] + (int64_t)j * L.pstride[d] + within;
+    int g1, g2, g3;
+    bool canon = r < L.rows[d];
+    if (d == 0) { g1 = j * P; g3 = r; g2 = c; canon = canon && c < L.N[1]; }
+    else if (d == 1) { g2 = j * P; g3 = r; g1 = c; canon = canon && c < L.N[0] && c % P != 0; }
+    else { g3 = j * P; g2 = r; g1 = c; canon = canon && c < L.N[0] && c % P != 0 && r % P != 0; }
+    if (!canon || is_dir(L, g1, g2, g3)) {
+        y[s] = T(0);
+        return;
     }
-    if (act) ul[el][l] = uv;
-    __syncthreads();
-    if (unk) tb.opE[(size_t)e * nl + l] = coarse_row<P, T>(tab[el], ul[el], tb.lam, a1, a2, a3);
+    // all neighbour values first (masked, never a branch around a load)
+    T v1[2 * P], v2[2 * P], v3[2 * P];
+#pragma unroll
+    for (int k = 0; k < 2 * P; ++k) {
+        const int o = k < P ? k - P : k - P + 1;  // -P..-1, 1..P
+        bool ok1, ok2, ok3;
+        const int64_t s1 = skel_slot<P>(L, g1 + o, g2, g3, s, ok1);
+        const int64_t s2 = skel_slot<P>(L, g1, g2 + o, g3, s, ok2);
+        const int64_t s3 = skel_slot<P>(L, g1, g2, g3 + o, s, ok3);
+        const T a1 = u[s1], a2 = u[s2], a3 = u[s3];
+        v1[k] = ok1 ? a1 : T(0);
+        v2[k] = ok2 ? a2 : T(0);
+        v3[k] = ok3 ? a3 : T(0);
+    }
+    const T u0 = u[s];
+    T m1, m2, m3, c1[2 * P + 1], c2[2 * P + 1], c3[2 * P + 1];
+    axis_rec<T, P>(tb.ax[0], g1, m1, c1);
+    axis_rec<T, P>(tb.ax[1], g2, m2, c2);
+    axis_rec<T, P>(tb.ax[2], g3, m3, c3);
+    T x1 = c1[P] * u0, x2 = c2[P] * u0, x3 = c3[P] * u0;
+#pragma unroll
+    for (int k = 0; k < 2 * P; ++k) {
+        const int ci = k < P ? k : k + 1;
+        x1 += c1[ci] * v1[k];
+        x2 += c2[ci] * v2[k];
+        x3 += c3[ci] * v3[k];
+    }
+    T acc = tb.lam * m1 * m2 * m3 * u0 + m2 * m3 * x1 + m1 * m3 * x2 + m1 * m2 * x3;
+    if constexpr (P == 2) {
+        // face centre: exactly one index on an element boundary, the other
+        // two at element midpoints; its coupling to the centre of the element
+        // below (above) the face is the assembled L~(i, i -+ 1) in that
+        // direction times the two midpoint masses
+        const bool b1 = (g1 & 1) == 0, b2 = (g2 & 1) == 0, b3 = (g3 & 1) == 0;
+        if ((int)b1 + (int)b2 + (int)b3 == 1) {
+            const int dd = b1 ? 0 : (b2 ? 1 : 2);
+            const int f1 = g1 >> 1, f2 = g2 >> 1, f3 = g3 >> 1;  // element above the face
+            const int64_t eh = ((int64_t)f3 * L.n[1] + f2) * L.n[0] + f1;
+            const int64_t el = eh - (dd == 0 ? 1 : (dd == 1 ? L.n[0] : (int64_t)L.n[0] * L.n[1]));
+            const T tl = tb.tc[el], th = tb.tc[eh];
+            const T mo = dd == 0 ? m2 * m3 : (dd == 1 ? m1 * m3 : m1 * m2);
+            const T cl = dd == 0 ? c1[1] : (dd == 1 ? c2[1] : c3[1]);
+            const T ch = dd == 0 ? c1[3] : (dd == 1 ? c2[3] : c3[3]);
+            acc -= mo * (cl * tl + ch * th);
+        }
+    }
+    y[s] = F ? F[s] - acc : acc;
 }
 
 // Sum of (x, y) over the block, returned to every thread (each adds the
@@ -2906,10 +3007,10 @@ void launch_skel_to_grid(const Layout& L, const T* s, double* g, hipStream_t st)
     hipLaunchKernelGGL(k_skel_to_grid<T>, dim3(nblk(tot)), dim3(256), 0, st, L, s, g);
 }
 
-// assembly of the condensed operator: atomics (one launch) unless disabled
+// assembly of the per-element face tiles of the condensed operator (p >= 3)
 
 template <typename T>
-static void launch_gather_elem(const Layout& L, const T* E, const T* F, T* y, hipStream_t st) {
+static void launch_gather_elem(const Layout& L, const T* E, const T* F, T* y, hipStream_t st, int sub = 0) {
     int mp = 0, mr = 0;
     for (int d = 0; d < 3; ++d) {
         mp = std::max(mp, L.pitch[d]);
@@ -2918,12 +3019,10 @@ static void launch_gather_elem(const Layout& L, const T* E, const T* F, T* y, hi
     const int planes = L.n[0] + L.n[1] + L.n[2] + 3;
     const dim3 grid((mp + 63) / 64, (mr + 3) / 4, planes), block(64, 4);
     switch (L.p) {
-        case 1: hipLaunchKernelGGL((k_gather_elem<T, 1, true>), grid, block, 0, st, L, E, F, y); break;
-        case 2: hipLaunchKernelGGL((k_gather_elem<T, 2, true>), grid, block, 0, st, L, E, F, y); break;
-        case 4: hipLaunchKernelGGL((k_gather_elem<T, 4>), grid, block, 0, st, L, E, F, y); break;
-        case 8: hipLaunchKernelGGL((k_gather_elem<T, 8>), grid, block, 0, st, L, E, F, y); break;
-        case 16: hipLaunchKernelGGL((k_gather_elem<T, 16>), grid, block, 0, st, L, E, F, y); break;
-        default: hipLaunchKernelGGL((k_gather_elem<T, 0>), grid, block, 0, st, L, E, F, y);
+        case 4: hipLaunchKernelGGL((k_gather_elem<T, 4>), grid, block, 0, st, L, E, F, y, sub); break;
+        case 8: hipLaunchKernelGGL((k_gather_elem<T, 8>), grid, block, 0, st, L, E, F, y, sub); break;
+        case 16: hipLaunchKernelGGL((k_gather_elem<T, 16>), grid, block, 0, st, L, E, F, y, sub); break;
+        default: hipLaunchKernelGGL((k_gather_elem<T, 0>), grid, block, 0, st, L, E, F, y, sub);
     }
 }
 
@@ -2931,13 +3030,21 @@ template <typename T>
 void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t st, const T* F) {
     const int ne = tb.lay.n[0] * tb.lay.n[1] * tb.lay.n[2];
     if (tb.lay.p <= 2) {
-        if (tb.lay.p == 2)
-            hipLaunchKernelGGL((k_condensed_op_tiny<T, 2>), dim3((ne + CoarseShape<2>::epb - 1) / CoarseShape<2>::epb),
-                               dim3(COARSE_THREADS), 0, st, tb, u);
-        else
-            hipLaunchKernelGGL((k_condensed_op_tiny<T, 1>), dim3((ne + CoarseShape<1>::epb - 1) / CoarseShape<1>::epb),
-                               dim3(COARSE_THREADS), 0, st, tb, u);
-        launch_gather_elem(tb.lay, (const T*)tb.opE, F, y, st);
+        const Layout& L = tb.lay;
+        int mp = 0, mr = 0;
+        for (int d = 0; d < 3; ++d) {
+            mp = std::max(mp, L.pitch[d]);
+            mr = std::max(mr, (int)((L.pstride[d] + L.pitch[d] - 1) / L.pitch[d]));
+        }
+        const int bx = (mp + 63) / 64, by = (mr + 3) / 4, planes = L.n[0] + L.n[1] + L.n[2] + 3;
+        const dim3 grid((unsigned)((int64_t)bx * by * planes));
+        if (L.p == 2) {
+            const int ne = L.n[0] * L.n[1] * L.n[2];
+            hipLaunchKernelGGL(k_centre_t<T>, dim3((ne + 255) / 256), dim3(256), 0, st, tb, u);
+            hipLaunchKernelGGL((k_condensed_op_low<T, 2>), grid, dim3(256), 0, st, tb, u, F, y, bx, by);
+        } else {
+            hipLaunchKernelGGL((k_condensed_op_low<T, 1>), grid, dim3(256), 0, st, tb, u, F, y, bx, by);
+        }
         return;
     }
     switch (tb.lay.p) {
@@ -3109,10 +3216,20 @@ void launch_condense(const LevelTabs<double>& tb, const double* m1, const double
     }
     LevelTabs<double> t = tb;
     const size_t sm = pick_ws(t, ws_condense(L.p));
+    if (tb.opE && L.p <= 8 && !t.gws) {
+        // one launch over all elements into the operator's face-tile
+        // workspace, then the deterministic per-node sum; up to p = 5 a
+        // wavefront per element (cheap barriers, more elements per CU;
+        // measured 2.1x faster at p = 4, slower at p = 8)
+        const int ne = L.n[0] * L.n[1] * L.n[2];
+        hipLaunchKernelGGL(k_condense, dim3(ne), dim3(L.p <= 5 ? 64 : 256), sm, st, t, f, Fh, -1, tb.opE);
+        launch_gather_elem(L, (const double*)tb.opE, (const double*)nullptr, Fh, st, 1);
+        return;
+    }
     for (int c = 0; c < 8; ++c) {
         int nb = color_count(L.n, c);
         if (nb == 0) continue;
-        hipLaunchKernelGGL(k_condense, dim3(nb), dim3(256), sm, st, t, f, Fh, c);
+        hipLaunchKernelGGL(k_condense, dim3(nb), dim3(256), sm, st, t, f, Fh, c, (double*)nullptr);
     }
 }
 
@@ -3141,7 +3258,9 @@ void launch_recover(const LevelTabs<double>& tb, const double* f, const double* 
     }
     LevelTabs<double> t = tb;
     const size_t sm = pick_ws(t, ws_recover(L.p));
-    hipLaunchKernelGGL(k_recover, dim3(L.n[0] * L.n[1] * L.n[2]), dim3(256), sm, st, t, f, uh, ug);
+    // a wavefront per element up to p = 5 (cheap barriers, more elements per
+    // CU: 1.9x faster at p = 4; at p = 8 256 threads are faster)
+    hipLaunchKernelGGL(k_recover, dim3(L.n[0] * L.n[1] * L.n[2]), dim3(L.p <= 5 ? 64 : 256), sm, st, t, f, uh, ug);
 }
 
 template <typename T>

@@ -312,6 +312,20 @@ void build_level_tables(int p, int pc, const std::vector<double> h[3], HostTable
         gll_nodes_weights(pc, xc, wc);
         lagrange_interp(xc, x, t.J);
     }
+    // p <= 2: the assembled 1D mass (diagonal) and stiffness (band of
+    // half-width p) per direction, one record per global node index
+    for (int d = 0; d < 3; ++d) {
+        t.ax[d].clear();
+        if (p > 2) continue;
+        const int ne = (int)h[d].size(), N = ne * p + 1;
+        t.ax[d].assign((size_t)N * AXW, 0.0);
+        for (int e = 0; e < ne; ++e)
+            for (int a = 0; a < n1; ++a) {
+                double* rec = &t.ax[d][(size_t)(e * p + a) * AXW];
+                rec[0] += t.el_m[d][(size_t)e * n1 + a];
+                for (int b = 0; b < n1; ++b) rec[1 + p + (b - a)] += t.el_L[d][(size_t)e * n1 * n1 + a * n1 + b];
+            }
+    }
 }
 
 // Diagonal of the assembled condensed operator on a level, stored in the

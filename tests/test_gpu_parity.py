@@ -75,6 +75,27 @@ def test_condensed_op_all_levels(gpu, case, dtype):
         assert err <= (TOL64 if dtype == "f64" else TOL32), (level, err)
 
 
+@pytest.mark.parametrize("n,p,lam,alpha", [((5, 3, 4), 1, 1.0, 1.3), ((1, 2, 7), 1, 0.0, 1.0),
+                                            ((6, 5, 3), 2, 10.0, 1.25), ((1, 1, 3), 2, 0.0, 1.0),
+                                            ((33, 2, 2), 2, 1.0, 1.05)])
+def test_condensed_op_degrees_1_2(gpu, n, p, lam, alpha):
+    """Degrees 1 and 2 (per-node axis stencil plus the face-centre Schur
+    term): meshes whose planes span several 64 x 4 tiles, ragged counts."""
+    g, o = make_pair(n, p, lam, alpha)
+    io = LevelIO(g, 0)
+    u = synth.random_grid(o.shape, 17) * o.free_skeleton_mask()
+    ref = matfree.condensed_op(o, u)
+    for dt, tdt, tol in ((pmg.F64, torch.float64, TOL64), (pmg.F32, torch.float32, TOL32)):
+        du = io.to_dev(u, tdt)
+        y = torch.full_like(du, float("nan"))
+        g.apply_condensed_op(0, du, y, dt)
+        torch.cuda.synchronize()
+        # every slot written: zero off the unknowns
+        assert not torch.isnan(y).any()
+        assert rel(io.to_grid(y), ref) <= tol
+    g.close()
+
+
 @pytest.mark.parametrize("case", CASES, ids=_ids)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_smoother_all_levels(gpu, case, dtype):
