@@ -76,6 +76,29 @@ def test_operator_and_smoother_full_size(gpu, case):
     g.close()
 
 
+def test_degree2_operator_and_smoother_large(gpu):
+    """p = 2 on 81 x 80 x 82 elements (551k stars): the smoother runs as
+    eight launches of stars with disjoint windows and plain adds (taken from
+    2^19 stars on), the operator as the per-node axis stencil; both against
+    the oracle over whole vectors."""
+    g, o = make_pair((81, 80, 82), 2, 1.0, 1.01)
+    io = LevelIO(g, 0)
+    mask = o.free_skeleton_mask()
+    u = synth.random_grid(o.shape, 23) * mask
+    ref_op = matfree.condensed_op(o, u)
+    ref_sm = matfree.smoother(o, u, 0.7)
+    for dt, tdt, tol in ((pmg.F64, torch.float64, TOL64), (pmg.F32, torch.float32, TOL32)):
+        du = io.to_dev(u, tdt)
+        y = torch.full_like(du, float("nan"))
+        g.apply_condensed_op(0, du, y, dt)
+        z = torch.full_like(du, float("nan"))
+        g.schwarz_smooth(0, du, z, 0.7, dt)
+        torch.cuda.synchronize()
+        assert rel(io.to_grid(y), ref_op) <= tol, dt
+        assert rel(io.to_grid(z), ref_sm) <= tol, dt
+    g.close()
+
+
 def _check_solution(o, f, u, F_hat, tol_res):
     """Residual of the returned skeleton values and consistency of the
     interior, both recomputed by the oracle."""
