@@ -1462,7 +1462,10 @@ __global__ void __launch_bounds__(64) k_star_gemm(LevelTabs<T> tb, const T* __re
 // Eigenspace pass of one star: H1[k3][k2] = sum_k1 a1 V, H2[k3][k1] =
 // sum_k2 a2 V, H3[k2][k1] = sum_k3 a3 V with V = (a1 G1[k3][k2] + a2
 // G2[k3][k1] + a3 G3[k2][k1]) / (lambda + l1 + l2 + l3), a_d = row c of S_d.
-// G staged in LDS when it fits (sm_elems > 0), else read from the workspace.
+// G staged in LDS when it fits (stage), else read from the workspace.  The
+// 3 np^2 outputs of a star are split over gridDim.y workgroups when the
+// level has few stars (large p on small meshes), so that the launch fills
+// the chip.
 template <typename T>
 __global__ void __launch_bounds__(256) k_star_eigen(LevelTabs<T> tb, const T* __restrict__ G, T* __restrict__ H,
                                                     int stage) {
@@ -1501,7 +1504,7 @@ __global__ void __launch_bounds__(256) k_star_eigen(LevelTabs<T> tb, const T* __
     const T* G2 = Gl + n2;
     const T* G3 = Gl + 2 * n2;
     T* Hs = H + (size_t)s * 3 * n2;
-    for (int i = threadIdx.x; i < 3 * n2; i += blockDim.x) {
+    for (int i = blockIdx.y * blockDim.x + threadIdx.x; i < 3 * n2; i += gridDim.y * blockDim.x) {
         const int d = i / n2, rc = i - d * n2, rr = rc / np, cc = rc - rr * np;
         T acc = 0;
         if (rr < nS && cc < nS) {
@@ -1559,6 +1562,46 @@ __device__ inline int plane_family(const Layout& L, int z, int& j) {
     const int d = z >= L.n[0] + L.n[1] + 2 ? 2 : (z >= L.n[0] + 1 ? 1 : 0);
     j = z - (d == 0 ? 0 : (d == 1 ? L.n[0] + 1 : L.n[0] + L.n[1] + 2));
     return d;
+}
+
+// uf += P uc on every canonical, non-Dirichlet fine node, separably (any
+// degree pair): one thread per fine column gc of one element row Er of a
+// plane forms the pc + 1 column interpolations of the element's coarse rows
+// once (in LDS), then each fine row of the element takes its (pc + 1)-term
+// row interpolation: 2 (pc + 1) operations per fine node instead of
+// (pc + 1)^2.  Element Er writes its rows 0..pf-1, the last element also
+// row pf (a boundary row interpolates to the same value from either side).
+template <typename T>
+__global__ void __launch_bounds__(64) k_prolong_sep(Layout Lc, Layout Lf, const T* __restrict__ J,
+                                                    const T* __restrict__ uc, T* __restrict__ uf) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    int j;
+    const int d = plane_family(Lf, blockIdx.z, j);
+    const int pf = Lf.p, pc = Lc.p, nc1 = pc + 1;
+    const int dr = d == 2 ? 1 : 2, dc = d == 0 ? 1 : 0;
+    const int Er = blockIdx.y, gc = blockIdx.x * 64 + threadIdx.x;
+    if (Er >= Lf.n[dr] || gc >= Lf.N[dc]) return;
+    T* t = reinterpret_cast<T*>(smem_raw) + threadIdx.x * nc1;
+    const int Ec = min(gc / pf, Lf.n[dc] - 1), lc = gc - Ec * pf;
+    for (int R = 0; R < nc1; ++R) {
+        T a = 0;
+        for (int C = 0; C < nc1; ++C)
+            a += J[lc * nc1 + C] * coarse_plane_value(Lc, uc, d, j, Er * pc + R, Ec * pc + C, pc);
+        t[R] = a;
+    }
+    const bool col_ok = d == 0 || gc % pf != 0;
+    const int last = Er == Lf.n[dr] - 1 ? pf : pf - 1;
+    for (int lr = 0; lr <= last; ++lr) {
+        const int gr = Er * pf + lr;
+        int g[3];
+        g[d] = j * pf;
+        g[dr] = gr;
+        g[dc] = gc;
+        if (!col_ok || (d == 2 && gr % pf == 0) || is_dir(Lf, g[0], g[1], g[2])) continue;
+        T a = 0;
+        for (int R = 0; R < nc1; ++R) a += J[lr * nc1 + R] * t[R];
+        uf[Lf.off[d] + (int64_t)j * Lf.pstride[d] + (int64_t)gr * Lf.pitch[d] + gc] += a;
+    }
 }
 
 // uf += P uc on every canonical, non-Dirichlet fine node.
@@ -3143,8 +3186,15 @@ void launch_smoother_add(const LevelTabs<T>& tb, const T* r, T* du, T omega, hip
         hipLaunchKernelGGL((k_star_gemm<T, SG_FWD2>), g, dim3(64), 0, st, tb, r, (const T*)X1, X0, (T*)nullptr, omega);
         const size_t full = sizeof(T) * (6 * (size_t)tb.np + 3 * (size_t)tb.np * tb.np);
         const int stage = full <= kLdsBytes;
-        hipLaunchKernelGGL(k_star_eigen<T>, dim3(ns), dim3(256), stage ? full : sizeof(T) * 6 * tb.np, st, tb,
-                           (const T*)X0, X1, stage);
+        // few stars: split each star's outputs over several workgroups (no
+        // staging then: each would load all of G for a part of the outputs).
+        // Measured: 125 stars, np = 96: 604 -> 231 us (FP64), 324 -> 95 us
+        // (FP32); 729 stars, np = 32: 80 -> 74 / 47 -> 41 us; 1000 stars,
+        // np = 48: 245 -> 262 / 111 -> 111 us (kept whole there)
+        const int chunks = ns < 1000 ? (3 * tb.np * tb.np + 255) / 256 : 1;
+        const int stg = chunks == 1 ? stage : 0;
+        hipLaunchKernelGGL(k_star_eigen<T>, dim3(ns, chunks), dim3(256), stg ? full : sizeof(T) * 6 * tb.np, st, tb,
+                           (const T*)X0, X1, stg);
         hipLaunchKernelGGL((k_star_gemm<T, SG_BWD1>), g, dim3(64), 0, st, tb, r, (const T*)X1, X0, (T*)nullptr, omega);
         hipLaunchKernelGGL((k_star_gemm<T, SG_BWD2>), g, dim3(64), 0, st, tb, r, (const T*)X0, (T*)nullptr, du, omega);
         return;
@@ -3180,7 +3230,12 @@ void launch_prolong_add(const Layout& Lc, const Layout& Lf, const T* J, const T*
     if (Lf.p == 4 && Lc.p == 2) PMG_PRO(4, 2);
     else if (Lf.p == 8 && Lc.p == 4) PMG_PRO(8, 4);
     else if (Lf.p == 16 && Lc.p == 8) PMG_PRO(16, 8);
-    else PMG_PRO(0, 0);
+    else {
+        int mr = 0;
+        for (int dd = 0; dd < 3; ++dd) mr = std::max(mr, Lf.n[dd]);
+        const dim3 gs((max_cols(Lf) + 63) / 64, mr, Lf.n[0] + Lf.n[1] + Lf.n[2] + 3);
+        hipLaunchKernelGGL(k_prolong_sep<T>, gs, dim3(64), sizeof(T) * 64 * (Lc.p + 1), st, Lc, Lf, J, uc, uf);
+    }
 #undef PMG_PRO
 }
 
