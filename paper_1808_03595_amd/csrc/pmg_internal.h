@@ -99,7 +99,12 @@ __host__ __device__ inline int elem_table_size(int p) {
 }
 __host__ __device__ inline size_t ws_condensed_op(int p) {
     const size_t n1 = p + 1, q = p - 1;
-    return 6 * n1 * n1 + 18 * q * q + (size_t)elem_table_size(p) + q * q * q;
+    return 6 * n1 * n1 + 18 * q * q + (size_t)elem_table_size(p);
+}
+// in device scratch the q^3 eigenspace array V is formed once as well
+__host__ __device__ inline size_t ws_condensed_op_v(int p) {
+    const size_t q = p - 1;
+    return ws_condensed_op(p) + q * q * q;
 }
 __host__ __device__ inline size_t ws_smoother(int p) {
     const size_t nS = 2 * p - 1;

@@ -331,7 +331,7 @@ __device__ ElemPtrs<T> stage_elem_tables(const LevelTabs<T>& tb, const int e[3],
 template <typename T>
 __global__ void __launch_bounds__(1024) k_condensed_op(LevelTabs<T> tb, const T* __restrict__ u) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* sm = tb.gws ? tb.gws + (size_t)blockIdx.x * ws_condensed_op(tb.lay.p) : reinterpret_cast<T*>(smem_raw);
+    T* sm = tb.gws ? tb.gws + (size_t)blockIdx.x * ws_condensed_op_v(tb.lay.p) : reinterpret_cast<T*>(smem_raw);
     const Layout& L = tb.lay;
     const int p = L.p, n1 = p + 1, t2 = n1 * n1, q = p - 1, q2 = q * q;
     int e[3];
@@ -342,30 +342,39 @@ __global__ void __launch_bounds__(1024) k_condensed_op(LevelTabs<T> tb, const T*
     T* Tc = G + 6 * q2;        // 6 q2
     T* tmp = Tc + 6 * q2;      // 6 q2
     T* tabs = tmp + 6 * q2;    // elem_table_size(p)
-    T* V = tabs + elem_table_size(p);  // q^3
     ElemPtrs<T> P = stage_elem_tables(tb, e, tabs);
     load_tiles(L, e, u, tile);
     __syncthreads();
     if (q > 0) {
         faces_to_eigen(P, p, tile, false, tmp, G);
-        // V = D^-1 sum_f c_f (x) G_f once, then the three contractions
-        for (int i = threadIdx.x; i < q2 * q; i += blockDim.x) {
-            const int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
-            V[i] = expand(P, G, q, k1, k2, k3) / (tb.lam + P.lm(0)[k1] + P.lm(1)[k2] + P.lm(2)[k3]);
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < 3 * q2; i += blockDim.x) {
-            const int d = i / q2, rc = i - d * q2, r = rc / q, c = rc - r * q;
-            T s0 = 0, sp = 0;
-            for (int k = 0; k < q; ++k) {
-                const int idx = d == 0 ? (r * q + c) * q + k : (d == 1 ? (r * q + k) * q + c : (k * q + r) * q + c);
-                s0 += P.c0(d)[k] * V[idx];
-                sp += P.cp(d)[k] * V[idx];
+        if (!tb.gws) {
+            // in LDS: the contractions with V = D^-1 sum_f c_f (x) G_f formed
+            // on the fly (three times the expansion work, but no q^3 array,
+            // so the working set stays in LDS up to p = 24 in FP64 and p = 32
+            // in FP32: p = 24 FP64 691 -> 604 us at 9^3 elements)
+            eigen_contract(P, p, tb.lam, G, (const T*)nullptr, (T)0, Tc);
+        } else {
+            // in device scratch: V once, then the three contractions (the
+            // on-the-fly form measured 11 % slower there)
+            T* V = tabs + elem_table_size(p);  // q^3
+            for (int i = threadIdx.x; i < q2 * q; i += blockDim.x) {
+                const int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
+                V[i] = expand(P, G, q, k1, k2, k3) / (tb.lam + P.lm(0)[k1] + P.lm(1)[k2] + P.lm(2)[k3]);
             }
-            Tc[(2 * d) * q2 + rc] = s0;
-            Tc[(2 * d + 1) * q2 + rc] = sp;
+            __syncthreads();
+            for (int i = threadIdx.x; i < 3 * q2; i += blockDim.x) {
+                const int d = i / q2, rc = i - d * q2, r = rc / q, c = rc - r * q;
+                T s0 = 0, sp = 0;
+                for (int k = 0; k < q; ++k) {
+                    const int idx = d == 0 ? (r * q + c) * q + k : (d == 1 ? (r * q + k) * q + c : (k * q + r) * q + c);
+                    s0 += P.c0(d)[k] * V[idx];
+                    sp += P.cp(d)[k] * V[idx];
+                }
+                Tc[(2 * d) * q2 + rc] = s0;
+                Tc[(2 * d + 1) * q2 + rc] = sp;
+            }
+            __syncthreads();
         }
-        __syncthreads();
         eigen_to_faces(P, p, Tc, tmp, G);  // corrections now in G
     }
     for (int i = threadIdx.x; i < 6 * t2; i += blockDim.x) {
@@ -375,6 +384,188 @@ __global__ void __launch_bounds__(1024) k_condensed_op(LevelTabs<T> tb, const T*
         tile_node(p, f, r, c, a1, a2, a3);
         T v = hbb_at(P, p, tb.lam, tile, a1, a2, a3);
         if (r > 0 && r < p && c > 0 && c < p) v -= G[f * q2 + (r - 1) * q + (c - 1)];
+        out[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Condensed operator for p > 16: the steps of the element kernel above as
+// three launches over all elements with many workgroups each (one element
+// per workgroup left most CUs idle on the small meshes these degrees run
+// on, 64 workgroups at 4^3 elements, and its working set exceeds the LDS
+// from p = 25 in FP64).  Per element and face f:
+//   fwd:      G_f = (Sinv_R x Sinv_C) X_f on the face interior,
+//   contract: Tc_{d,s} = sum_{k_d} c_{d,s}[k_d] V with V = D^-1 sum_f c_f (x) G_f
+//             formed on the fly, one thread per output,
+//   bwd:      corr_f = (MS_R x MS_C) Tc_f, then every canonical entry of the
+//             face tile: H_BB u_B minus corr_f (face interior) into opE.
+// G and Tc live in the level's two star-smoother workspaces (n_v 3 np^2 >=
+// n_e 6 (p-1)^2 entries each; the smoother does not run meanwhile).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_op_big_fwd(LevelTabs<T> tb, const T* __restrict__ u) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Layout& L = tb.lay;
+    const int p = L.p, q = p - 1, q2 = q * q;
+    const int el = blockIdx.x, f = blockIdx.y, d = f >> 1, rd = tile_rdir(d), cd = tile_cdir(d);
+    int e[3];
+    color_coords(el, -1, L.n, e);
+    const ElemPtrs<T> P = elem_ptrs(tb, e);
+    T* X = reinterpret_cast<T*>(smem_raw);
+    T* tmp = X + q2;
+    T* Sc = tmp + q2;
+    T* Sr = Sc + q2;
+    for (int i = threadIdx.x; i < q2; i += blockDim.x) {
+        const int r = i / q, c = i - r * q;
+        int a1, a2, a3;
+        tile_node(p, f, r + 1, c + 1, a1, a2, a3);
+        X[i] = u[elem_slot(L, e, a1, a2, a3)];
+        Sc[i] = P.Si(cd)[i];
+        Sr[i] = P.Si(rd)[i];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < q2; i += blockDim.x) {
+        const int r = i / q, kc = i - r * q;
+        T a = 0;
+        for (int c = 0; c < q; ++c) a += X[r * q + c] * Sc[kc * q + c];
+        tmp[i] = a;
+    }
+    __syncthreads();
+    T* G = tb.sbX[0] + ((size_t)el * 6 + f) * q2;
+    for (int i = threadIdx.x; i < q2; i += blockDim.x) {
+        const int kr = i / q, kc = i - kr * q;
+        T a = 0;
+        for (int r = 0; r < q; ++r) a += Sr[kr * q + r] * tmp[r * q + kc];
+        G[i] = a;
+    }
+}
+
+// One workgroup per (element, chunk of BIG_CHUNK outputs); the element's G
+// is staged in LDS (each output reads 6 q values of it).
+constexpr int BIG_CHUNK = 1024;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_op_big_contract(LevelTabs<T> tb) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Layout& L = tb.lay;
+    const int p = L.p, q = p - 1, q2 = q * q;
+    const int el = blockIdx.x;
+    int e[3];
+    color_coords(el, -1, L.n, e);
+    const ElemPtrs<T> P = elem_ptrs(tb, e);
+    T* G = reinterpret_cast<T*>(smem_raw);
+    const T* Gg = tb.sbX[0] + (size_t)el * 6 * q2;
+    for (int i = threadIdx.x; i < 6 * q2; i += blockDim.x) G[i] = Gg[i];
+    __syncthreads();
+    T* Tc = tb.sbX[1] + (size_t)el * 6 * q2;
+    const int i0 = blockIdx.y * BIG_CHUNK, i1 = min(i0 + BIG_CHUNK, 3 * q2);
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        const int d = i / q2, rc = i - d * q2, r = rc / q, c = rc - r * q;
+        T s0 = 0, sp = 0;
+        for (int k = 0; k < q; ++k) {
+            int k1, k2, k3;
+            if (d == 0) { k3 = r; k2 = c; k1 = k; }
+            else if (d == 1) { k3 = r; k1 = c; k2 = k; }
+            else { k2 = r; k1 = c; k3 = k; }
+            const T v = expand(P, G, q, k1, k2, k3) / (tb.lam + P.lm(0)[k1] + P.lm(1)[k2] + P.lm(2)[k3]);
+            s0 += P.c0(d)[k] * v;
+            sp += P.cp(d)[k] * v;
+        }
+        Tc[(2 * d) * q2 + rc] = s0;
+        Tc[(2 * d + 1) * q2 + rc] = sp;
+    }
+}
+
+// Shell value of element-local node (b1, b2, b3), zero at interior nodes.
+template <typename T>
+__device__ __forceinline__ T shell_u(const Layout& L, const T* __restrict__ u, const int e[3], int b1, int b2,
+                                     int b3) {
+    const int p = L.p;
+    if (b1 > 0 && b1 < p && b2 > 0 && b2 < p && b3 > 0 && b3 < p) return T(0);
+    return u[elem_slot(L, e, b1, b2, b3)];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_op_big_bwd(LevelTabs<T> tb, const T* __restrict__ u) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Layout& L = tb.lay;
+    const int p = L.p, n1 = p + 1, t2 = n1 * n1, q = p - 1, q2 = q * q;
+    const int el = blockIdx.x, f = blockIdx.y, d = f >> 1, rd = tile_rdir(d), cd = tile_cdir(d);
+    const int side = (f & 1) ? p : 0;
+    int e[3];
+    color_coords(el, -1, L.n, e);
+    const ElemPtrs<T> P = elem_ptrs(tb, e);
+    T* Tf = reinterpret_cast<T*>(smem_raw);   // Tc_f, later corr_f
+    T* tmp = Tf + q2;
+    T* Mc = tmp + q2;
+    T* Mr = Mc + q2;
+    T* tile = Mr + q2;                         // the face's (p+1)^2 shell values
+    const T* Tc = tb.sbX[1] + ((size_t)el * 6 + f) * q2;
+    for (int i = threadIdx.x; i < q2; i += blockDim.x) {
+        Tf[i] = Tc[i];
+        Mc[i] = P.MS(cd)[i];
+        Mr[i] = P.MS(rd)[i];
+    }
+    for (int i = threadIdx.x; i < t2; i += blockDim.x) {
+        const int r = i / n1, c = i - r * n1;
+        int a1, a2, a3;
+        tile_node(p, f, r, c, a1, a2, a3);
+        tile[i] = u[elem_slot(L, e, a1, a2, a3)];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < q2; i += blockDim.x) {
+        const int kr = i / q, c = i - kr * q;
+        T a = 0;
+        for (int kc = 0; kc < q; ++kc) a += Tf[kr * q + kc] * Mc[c * q + kc];
+        tmp[i] = a;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < q2; i += blockDim.x) {
+        const int r = i / q, c = i - r * q;
+        T a = 0;
+        for (int kr = 0; kr < q; ++kr) a += Mr[r * q + kr] * tmp[kr * q + c];
+        Tf[i] = a;   // corr_f
+    }
+    __syncthreads();
+    T* out = tb.opE + ((size_t)el * 6 + f) * t2;
+    for (int i = threadIdx.x; i < t2; i += blockDim.x) {
+        const int r = i / n1, c = i - r * n1;
+        if (!tile_canonical(p, f, r, c)) continue;
+        int a[3];
+        tile_node(p, f, r, c, a[0], a[1], a[2]);
+        // H_BB u_B: the two in-face lines from the tile; the line along the
+        // face normal crosses the interior (two shell values) unless the node
+        // lies on an edge of the face, where that line runs in another face
+        T x[3];
+        {
+            const T* Lr = P.L(rd) + a[rd] * n1;
+            const T* Lc = P.L(cd) + a[cd] * n1;
+            T xr = 0, xc = 0;
+            for (int j = 0; j <= p; ++j) {
+                xr += Lr[j] * tile[j * n1 + c];
+                xc += Lc[j] * tile[r * n1 + j];
+            }
+            const T* Ln = P.L(d) + a[d] * n1;
+            T xn;
+            if (r > 0 && r < p && c > 0 && c < p) {
+                int b[3] = {a[0], a[1], a[2]};
+                b[d] = p - side;
+                xn = Ln[side] * tile[i] + Ln[p - side] * u[elem_slot(L, e, b[0], b[1], b[2])];
+            } else {
+                xn = 0;
+                for (int j = 0; j <= p; ++j) {
+                    int b[3] = {a[0], a[1], a[2]};
+                    b[d] = j;
+                    xn += Ln[j] * shell_u(L, u, e, b[0], b[1], b[2]);
+                }
+            }
+            x[rd] = xr;
+            x[cd] = xc;
+            x[d] = xn;
+        }
+        const T m1 = P.m(0)[a[0]], m2 = P.m(1)[a[1]], m3 = P.m(2)[a[2]];
+        T v = tb.lam * m1 * m2 * m3 * tile[i] + m3 * m2 * x[0] + m3 * m1 * x[1] + m2 * m1 * x[2];
+        if (r > 0 && r < p && c > 0 && c < p) v -= Tf[(r - 1) * q + (c - 1)];
         out[i] = v;
     }
 }
@@ -3132,7 +3323,17 @@ void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t s
         default: {
             LevelTabs<T> t = tb;
             const size_t sm = pick_ws(t, ws_condensed_op(tb.lay.p));
-            hipLaunchKernelGGL((k_condensed_op<T>), dim3(ne), dim3(tb.lay.p > 16 ? 1024 : 256), sm, st, t, u);
+            if (tb.lay.p > 16 && tb.sbX[0] && tb.sbX[1]) {
+                // large p: the three batched launches
+                const int q = tb.lay.p - 1, q2 = q * q, n1 = tb.lay.p + 1;
+                hipLaunchKernelGGL(k_op_big_fwd<T>, dim3(ne, 6), dim3(256), sizeof(T) * 4 * q2, st, tb, u);
+                hipLaunchKernelGGL(k_op_big_contract<T>, dim3(ne, (3 * q2 + BIG_CHUNK - 1) / BIG_CHUNK), dim3(256),
+                                   sizeof(T) * 6 * q2, st, tb);
+                hipLaunchKernelGGL(k_op_big_bwd<T>, dim3(ne, 6), dim3(256), sizeof(T) * (4 * q2 + n1 * n1), st, tb,
+                                   u);
+            } else {
+                hipLaunchKernelGGL((k_condensed_op<T>), dim3(ne), dim3(tb.lay.p > 16 ? 1024 : 256), sm, st, t, u);
+            }
         }
     }
     launch_gather_elem(tb.lay, (const T*)tb.opE, F, y, st);
@@ -3190,7 +3391,9 @@ void launch_smoother_add(const LevelTabs<T>& tb, const T* r, T* du, T omega, hip
         // staging then: each would load all of G for a part of the outputs).
         // Measured: 125 stars, np = 96: 604 -> 231 us (FP64), 324 -> 95 us
         // (FP32); 729 stars, np = 32: 80 -> 74 / 47 -> 41 us; 1000 stars,
-        // np = 48: 245 -> 262 / 111 -> 111 us (kept whole there)
+        // np = 48: 245 -> 262 / 111 -> 111 us (kept whole there).  Staging G
+        // in every split workgroup (rows of G3 padded against bank
+        // conflicts) measured 1.1-3.8x slower.
         const int chunks = ns < 1000 ? (3 * tb.np * tb.np + 255) / 256 : 1;
         const int stg = chunks == 1 ? stage : 0;
         hipLaunchKernelGGL(k_star_eigen<T>, dim3(ns, chunks), dim3(256), stg ? full : sizeof(T) * 6 * tb.np, st, tb,
@@ -3493,6 +3696,9 @@ hipError_t init_kernel_attributes() {
     const int lds = 160 * 1024;
     const void* fns[] = {
         (const void*)k_condensed_op<double>, (const void*)k_condensed_op<float>,
+        (const void*)k_op_big_fwd<double>,   (const void*)k_op_big_fwd<float>,
+        (const void*)k_op_big_bwd<double>,   (const void*)k_op_big_bwd<float>,
+        (const void*)k_op_big_contract<double>, (const void*)k_op_big_contract<float>,
         (const void*)k_smoother<double>,     (const void*)k_smoother<float>,
         (const void*)k_condense,             (const void*)k_recover,
         (const void*)k_smoother_mfma<double, MFMA_WPB>, (const void*)k_smoother_mfma<float, MFMA_WPB>,
