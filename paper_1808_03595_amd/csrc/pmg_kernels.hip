@@ -570,6 +570,117 @@ __global__ void __launch_bounds__(256) k_op_big_bwd(LevelTabs<T> tb, const T* __
     }
 }
 
+// Condensation and recovery for p >= 9 (the batched interior transforms
+// above), their per-element middle steps spread over many workgroups like
+// the large-p operator (one element per workgroup left most CUs idle).
+// Condensation, after the forward interior transform (eigen-space F_I in X):
+//   k_cond_big_contract: Tc_{d,s} = sum_{k_d} c_{d,s}[k_d] X / D per output,
+//   k_cond_big_back:     corr_f = (MS_R x MS_C) Tc_f as a face tile of the
+//                        operator's workspace (zero off the face interior),
+//                        subtracted from F_B by the in-place gather.
+// Recovery, between the forward and backward interior transforms:
+//   k_op_big_fwd (G_f of the skeleton values), k_rec_big_update: X = (X -
+//   sum_f c_f (x) G_f) / D per eigen-index, k_rec_big_shell: the skeleton
+//   values into the grid.
+template <typename T>
+__global__ void __launch_bounds__(256) k_cond_big_contract(LevelTabs<T> tb, int qp, const T* __restrict__ X) {
+    const Layout& L = tb.lay;
+    const int p = L.p, q = p - 1, q2 = q * q;
+    const int el = blockIdx.x, i = blockIdx.y * blockDim.x + threadIdx.x;
+    if (i >= 3 * q2) return;
+    int e[3];
+    color_coords(el, -1, L.n, e);
+    const ElemPtrs<T> P = elem_ptrs(tb, e);
+    const T* a = X + (size_t)el * qp * qp * qp;
+    const int d = i / q2, rc = i - d * q2, r = rc / q, c = rc - r * q;
+    T s0 = 0, sp = 0;
+    for (int k = 0; k < q; ++k) {
+        int k1, k2, k3;
+        if (d == 0) { k3 = r; k2 = c; k1 = k; }
+        else if (d == 1) { k3 = r; k1 = c; k2 = k; }
+        else { k2 = r; k1 = c; k3 = k; }
+        const T vv = a[((size_t)k3 * qp + k2) * qp + k1] / (tb.lam + P.lm(0)[k1] + P.lm(1)[k2] + P.lm(2)[k3]);
+        s0 += P.c0(d)[k] * vv;
+        sp += P.cp(d)[k] * vv;
+    }
+    T* Tc = tb.sbX[1] + (size_t)el * 6 * q2;
+    Tc[(2 * d) * q2 + rc] = s0;
+    Tc[(2 * d + 1) * q2 + rc] = sp;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cond_big_back(LevelTabs<T> tb) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Layout& L = tb.lay;
+    const int p = L.p, n1 = p + 1, t2 = n1 * n1, q = p - 1, q2 = q * q;
+    const int el = blockIdx.x, f = blockIdx.y, d = f >> 1, rd = tile_rdir(d), cd = tile_cdir(d);
+    int e[3];
+    color_coords(el, -1, L.n, e);
+    const ElemPtrs<T> P = elem_ptrs(tb, e);
+    T* Tf = reinterpret_cast<T*>(smem_raw);
+    T* tmp = Tf + q2;
+    T* Mc = tmp + q2;
+    T* Mr = Mc + q2;
+    const T* Tc = tb.sbX[1] + ((size_t)el * 6 + f) * q2;
+    for (int i = threadIdx.x; i < q2; i += blockDim.x) {
+        Tf[i] = Tc[i];
+        Mc[i] = P.MS(cd)[i];
+        Mr[i] = P.MS(rd)[i];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < q2; i += blockDim.x) {
+        const int kr = i / q, c = i - kr * q;
+        T a = 0;
+        for (int kc = 0; kc < q; ++kc) a += Tf[kr * q + kc] * Mc[c * q + kc];
+        tmp[i] = a;
+    }
+    __syncthreads();
+    T* out = tb.opE + ((size_t)el * 6 + f) * t2;
+    for (int i = threadIdx.x; i < t2; i += blockDim.x) {
+        const int r = i / n1, c = i - r * n1;
+        T a = 0;
+        if (r > 0 && r < p && c > 0 && c < p)
+            for (int kr = 0; kr < q; ++kr) a += Mr[(r - 1) * q + kr] * tmp[kr * q + (c - 1)];
+        out[i] = a;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_rec_big_update(LevelTabs<T> tb, int qp, T* __restrict__ X) {
+    const Layout& L = tb.lay;
+    const int p = L.p, q = p - 1, q2 = q * q;
+    const int el = blockIdx.x, i = blockIdx.y * blockDim.x + threadIdx.x;
+    if (i >= q2 * q) return;
+    int e[3];
+    color_coords(el, -1, L.n, e);
+    const ElemPtrs<T> P = elem_ptrs(tb, e);
+    const T* G = tb.sbX[0] + (size_t)el * 6 * q2;
+    const int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
+    T* v = X + (size_t)el * qp * qp * qp + ((size_t)k3 * qp + k2) * qp + k1;
+    *v = (*v - expand(P, G, q, k1, k2, k3)) / (tb.lam + P.lm(0)[k1] + P.lm(1)[k2] + P.lm(2)[k3]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_rec_big_shell(LevelTabs<T> tb, const T* __restrict__ uh,
+                                                       double* __restrict__ ug) {
+    const Layout& L = tb.lay;
+    const int p = L.p, n1 = p + 1, t2 = n1 * n1;
+    const int el = blockIdx.x, i = blockIdx.y * blockDim.x + threadIdx.x;
+    if (i >= 6 * t2) return;
+    int e[3];
+    color_coords(el, -1, L.n, e);
+    const int f = i / t2, rc = i - f * t2, r = rc / n1, c = rc - r * n1;
+    // each shell node once: its canonical tile entry, on the element that
+    // owns it (a_d = p only on the last element in direction d)
+    if (!tile_canonical(p, f, r, c)) return;
+    int a1, a2, a3;
+    tile_node(p, f, r, c, a1, a2, a3);
+    if ((a1 == p && e[0] != L.n[0] - 1) || (a2 == p && e[1] != L.n[1] - 1) || (a3 == p && e[2] != L.n[2] - 1))
+        return;
+    const int i1 = e[0] * p + a1, i2 = e[1] * p + a2, i3 = e[2] * p + a3;
+    ug[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1] = is_dir(L, i1, i2, i3) ? 0.0 : (double)uh[elem_slot(L, e, a1, a2, a3)];
+}
+
 // Assembly of the element contributions: every slot of the plane layout is
 // written once; a canonical, non-Dirichlet node receives the sum, in a fixed
 // order, of the canonical tile entries of the (up to eight) elements that
@@ -3506,6 +3617,16 @@ void launch_condense(const LevelTabs<double>& tb, const double* m1, const double
         hipLaunchKernelGGL(k_condense_tiny, dim3(nblk((int64_t)L.n[0] * L.n[1] * L.n[2])), dim3(256), 0, st, tb, f, Fh);
         return;
     }
+    if (tb.ixX[0] && tb.sbX[0] && tb.sbX[1] && tb.opE) {
+        const int ne = L.n[0] * L.n[1] * L.n[2], q2 = q * q;
+        hipLaunchKernelGGL(k_int_load, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, f, tb.ixX[0]);
+        int_forward(tb, tb.ixX[0], tb.ixX[1], st);
+        hipLaunchKernelGGL(k_cond_big_contract<double>, dim3(ne, (3 * q2 + 255) / 256), dim3(256), 0, st, tb, tb.qp,
+                           (const double*)tb.ixX[1]);
+        hipLaunchKernelGGL(k_cond_big_back<double>, dim3(ne, 6), dim3(256), sizeof(double) * 4 * q2, st, tb);
+        launch_gather_elem(L, (const double*)tb.opE, (const double*)nullptr, Fh, st, 1);
+        return;
+    }
     if (tb.ixX[0]) {
         const int ne = L.n[0] * L.n[1] * L.n[2];
         hipLaunchKernelGGL(k_int_load, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, f, tb.ixX[0]);
@@ -3543,6 +3664,19 @@ void launch_recover(const LevelTabs<double>& tb, const double* f, const double* 
             hipLaunchKernelGGL(k_recover_tiny<2>, dim3((unsigned)((ne + 8) / 9)), dim3(256), 0, st, tb, f, uh, ug);
         else
             hipLaunchKernelGGL(k_recover_tiny<1>, dim3((unsigned)((ne + 31) / 32)), dim3(256), 0, st, tb, f, uh, ug);
+        return;
+    }
+    if (tb.ixX[0] && tb.sbX[0]) {
+        const int ne = L.n[0] * L.n[1] * L.n[2], n1 = L.p + 1, q = L.p - 1, q2 = q * q;
+        hipLaunchKernelGGL(k_int_load, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, f, tb.ixX[0]);
+        int_forward(tb, tb.ixX[0], tb.ixX[1], st);
+        hipLaunchKernelGGL(k_op_big_fwd<double>, dim3(ne, 6), dim3(256), sizeof(double) * 4 * q2, st, tb, uh);
+        hipLaunchKernelGGL(k_rec_big_update<double>, dim3(ne, (q2 * q + 255) / 256), dim3(256), 0, st, tb, tb.qp,
+                           tb.ixX[1]);
+        hipLaunchKernelGGL(k_rec_big_shell<double>, dim3(ne, (6 * n1 * n1 + 255) / 256), dim3(256), 0, st, tb, uh, ug);
+        int_backward(tb, tb.ixX[1], tb.ixX[0], st);
+        hipLaunchKernelGGL(k_int_store, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, (const double*)tb.ixX[0],
+                           ug);
         return;
     }
     if (tb.ixX[0]) {
@@ -3699,6 +3833,7 @@ hipError_t init_kernel_attributes() {
         (const void*)k_op_big_fwd<double>,   (const void*)k_op_big_fwd<float>,
         (const void*)k_op_big_bwd<double>,   (const void*)k_op_big_bwd<float>,
         (const void*)k_op_big_contract<double>, (const void*)k_op_big_contract<float>,
+        (const void*)k_cond_big_back<double>,
         (const void*)k_smoother<double>,     (const void*)k_smoother<float>,
         (const void*)k_condense,             (const void*)k_recover,
         (const void*)k_smoother_mfma<double, MFMA_WPB>, (const void*)k_smoother_mfma<float, MFMA_WPB>,
