@@ -460,8 +460,7 @@ int build_mesh(pmg_mesh* m) {
         F.t64.qp = qp;
         for (int k = 0; k < 2; ++k)
             if ((rc = m->alloc(&F.t64.ixX[k], ne * qp * qp * qp))) return rc;
-        const size_t per = std::max<size_t>(18 * (size_t)q * q, 6 * (size_t)n1 * n1 + 12 * (size_t)q * q);
-        if (per * sizeof(double) > kLdsBytes && (rc = m->alloc(&F.t64.ixS, ne * per))) return rc;
+        (void)n1;   // the per-element middle steps run batched over faces (no face scratch: ixS stays null)
     }
     const Layout& Lf = m->lv.back().lay;
     int64_t nf = Lf.len;

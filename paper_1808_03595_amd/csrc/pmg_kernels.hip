@@ -2527,86 +2527,7 @@ __global__ void k_int_store(LevelTabs<double> tb, int qp, const double* __restri
     }
 }
 
-// Condensation, face part: with A = (S^T x S^T x S^T) M_I f_I in X,
-// Tc_{d,s} = sum_{k_d} c_{d,s}[k_d] A / D, corr_f = (MS_R x MS_C) Tc_f and
-// Fhat -= corr at the face-interior nodes (two elements meet at each: atomic).
-// Scratch: 3 x 6 q^2 per element (LDS when it fits).
-__global__ void __launch_bounds__(256) k_condense_faces(LevelTabs<double> tb, int qp, const double* __restrict__ X,
-                                                        double* __restrict__ Fh, double* __restrict__ scratch) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const Layout& L = tb.lay;
-    const int p = L.p, q = p - 1, q2 = q * q;
-    double* sm = scratch ? scratch + (size_t)blockIdx.x * 18 * q2 : reinterpret_cast<double*>(smem_raw);
-    int e[3];
-    color_coords(blockIdx.x, -1, L.n, e);
-    ElemPtrs<double> P = elem_ptrs(tb, e);
-    const double* a = X + (size_t)blockIdx.x * qp * qp * qp;
-    double* Tc = sm;
-    double* tmp = Tc + 6 * q2;
-    double* cor = tmp + 6 * q2;
-    for (int i = threadIdx.x; i < 3 * q2; i += blockDim.x) {
-        const int d = i / q2, rc = i - d * q2, r = rc / q, c = rc - r * q;
-        double s0 = 0, sp = 0;
-        for (int k = 0; k < q; ++k) {
-            int k1, k2, k3;
-            if (d == 0) { k3 = r; k2 = c; k1 = k; }
-            else if (d == 1) { k3 = r; k1 = c; k2 = k; }
-            else { k2 = r; k1 = c; k3 = k; }
-            const double vv = a[((size_t)k3 * qp + k2) * qp + k1] /
-                              (tb.lam + P.lm(0)[k1] + P.lm(1)[k2] + P.lm(2)[k3]);
-            s0 += P.c0(d)[k] * vv;
-            sp += P.cp(d)[k] * vv;
-        }
-        Tc[(2 * d) * q2 + rc] = s0;
-        Tc[(2 * d + 1) * q2 + rc] = sp;
-    }
-    __syncthreads();
-    eigen_to_faces(P, p, Tc, tmp, cor);
-    for (int i = threadIdx.x; i < 6 * q2; i += blockDim.x) {
-        const int f = i / q2, rc = i - f * q2, r = rc / q + 1, c = rc % q + 1;
-        int a1, a2, a3;
-        tile_node(p, f, r, c, a1, a2, a3);
-        if (is_dir(L, e[0] * p + a1, e[1] * p + a2, e[2] * p + a3)) continue;
-        unsafeAtomicAdd(Fh + elem_slot(L, e, a1, a2, a3), -cor[i]);
-    }
-}
 
-// Recovery, middle part: writes the skeleton nodes of u owned by the
-// element, and replaces the forward-transformed right-hand side B in X by
-// V = (B - sum_f c_f (x) G_f) / D with G_f = (Sinv_R x Sinv_C) uhat_f.
-// Scratch: 6 (p+1)^2 + 12 q^2 per element (LDS when it fits).
-__global__ void __launch_bounds__(256) k_recover_mid(LevelTabs<double> tb, int qp, const double* __restrict__ uh,
-                                                     double* __restrict__ X, double* __restrict__ ug,
-                                                     double* __restrict__ scratch) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const Layout& L = tb.lay;
-    const int p = L.p, n1 = p + 1, t2 = n1 * n1, q = p - 1, q2 = q * q;
-    double* sm = scratch ? scratch + (size_t)blockIdx.x * (6 * t2 + 12 * q2) : reinterpret_cast<double*>(smem_raw);
-    int e[3];
-    color_coords(blockIdx.x, -1, L.n, e);
-    ElemPtrs<double> P = elem_ptrs(tb, e);
-    double* tile = sm;
-    double* G = tile + 6 * t2;
-    double* tmp = G + 6 * q2;
-    load_tiles(L, e, uh, tile);
-    __syncthreads();
-    for (int i = threadIdx.x; i < n1 * n1 * n1; i += blockDim.x) {
-        const int a1 = i % n1, a2 = (i / n1) % n1, a3 = i / t2;
-        const bool shell = a1 == 0 || a1 == p || a2 == 0 || a2 == p || a3 == 0 || a3 == p;
-        if (!shell) continue;
-        if ((a1 == p && e[0] != L.n[0] - 1) || (a2 == p && e[1] != L.n[1] - 1) || (a3 == p && e[2] != L.n[2] - 1))
-            continue;
-        const int i1 = e[0] * p + a1, i2 = e[1] * p + a2, i3 = e[2] * p + a3;
-        ug[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1] = is_dir(L, i1, i2, i3) ? 0.0 : shell_value(tile, p, a1, a2, a3);
-    }
-    faces_to_eigen(P, p, tile, false, tmp, G);
-    double* a = X + (size_t)blockIdx.x * qp * qp * qp;
-    for (int i = threadIdx.x; i < q2 * q; i += blockDim.x) {
-        const int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
-        double* v = a + ((size_t)k3 * qp + k2) * qp + k1;
-        *v = (*v - expand(P, G, q, k1, k2, k3)) / (tb.lam + P.lm(0)[k1] + P.lm(1)[k2] + P.lm(2)[k3]);
-    }
-}
 
 // ---------------------------------------------------------------------------
 // BLAS-1 on skeleton arrays.  Reductions write one partial per block and
@@ -3617,7 +3538,7 @@ void launch_condense(const LevelTabs<double>& tb, const double* m1, const double
         hipLaunchKernelGGL(k_condense_tiny, dim3(nblk((int64_t)L.n[0] * L.n[1] * L.n[2])), dim3(256), 0, st, tb, f, Fh);
         return;
     }
-    if (tb.ixX[0] && tb.sbX[0] && tb.sbX[1] && tb.opE) {
+    if (tb.ixX[0]) {   // p >= 9 (the star-smoother workspaces and opE exist too)
         const int ne = L.n[0] * L.n[1] * L.n[2], q2 = q * q;
         hipLaunchKernelGGL(k_int_load, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, f, tb.ixX[0]);
         int_forward(tb, tb.ixX[0], tb.ixX[1], st);
@@ -3625,16 +3546,6 @@ void launch_condense(const LevelTabs<double>& tb, const double* m1, const double
                            (const double*)tb.ixX[1]);
         hipLaunchKernelGGL(k_cond_big_back<double>, dim3(ne, 6), dim3(256), sizeof(double) * 4 * q2, st, tb);
         launch_gather_elem(L, (const double*)tb.opE, (const double*)nullptr, Fh, st, 1);
-        return;
-    }
-    if (tb.ixX[0]) {
-        const int ne = L.n[0] * L.n[1] * L.n[2];
-        hipLaunchKernelGGL(k_int_load, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, f, tb.ixX[0]);
-        int_forward(tb, tb.ixX[0], tb.ixX[1], st);
-        const size_t need = sizeof(double) * 18 * (size_t)q * q;
-        double* scr = need > kLdsBytes ? tb.ixS : nullptr;
-        hipLaunchKernelGGL(k_condense_faces, dim3(ne), dim3(256), scr ? 0 : need, st, tb, tb.qp,
-                           (const double*)tb.ixX[1], Fh, scr);
         return;
     }
     LevelTabs<double> t = tb;
@@ -3666,7 +3577,7 @@ void launch_recover(const LevelTabs<double>& tb, const double* f, const double* 
             hipLaunchKernelGGL(k_recover_tiny<1>, dim3((unsigned)((ne + 31) / 32)), dim3(256), 0, st, tb, f, uh, ug);
         return;
     }
-    if (tb.ixX[0] && tb.sbX[0]) {
+    if (tb.ixX[0]) {   // p >= 9
         const int ne = L.n[0] * L.n[1] * L.n[2], n1 = L.p + 1, q = L.p - 1, q2 = q * q;
         hipLaunchKernelGGL(k_int_load, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, f, tb.ixX[0]);
         int_forward(tb, tb.ixX[0], tb.ixX[1], st);
@@ -3674,19 +3585,6 @@ void launch_recover(const LevelTabs<double>& tb, const double* f, const double* 
         hipLaunchKernelGGL(k_rec_big_update<double>, dim3(ne, (q2 * q + 255) / 256), dim3(256), 0, st, tb, tb.qp,
                            tb.ixX[1]);
         hipLaunchKernelGGL(k_rec_big_shell<double>, dim3(ne, (6 * n1 * n1 + 255) / 256), dim3(256), 0, st, tb, uh, ug);
-        int_backward(tb, tb.ixX[1], tb.ixX[0], st);
-        hipLaunchKernelGGL(k_int_store, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, (const double*)tb.ixX[0],
-                           ug);
-        return;
-    }
-    if (tb.ixX[0]) {
-        const int ne = L.n[0] * L.n[1] * L.n[2], n1 = L.p + 1, q = L.p - 1;
-        hipLaunchKernelGGL(k_int_load, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, f, tb.ixX[0]);
-        int_forward(tb, tb.ixX[0], tb.ixX[1], st);
-        const size_t need = sizeof(double) * (6 * (size_t)n1 * n1 + 12 * (size_t)q * q);
-        double* scr = need > kLdsBytes ? tb.ixS : nullptr;
-        hipLaunchKernelGGL(k_recover_mid, dim3(ne), dim3(256), scr ? 0 : need, st, tb, tb.qp, uh, tb.ixX[1], ug,
-                           scr);
         int_backward(tb, tb.ixX[1], tb.ixX[0], st);
         hipLaunchKernelGGL(k_int_store, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, (const double*)tb.ixX[0],
                            ug);
@@ -3839,8 +3737,7 @@ hipError_t init_kernel_attributes() {
         (const void*)k_smoother_mfma<double, MFMA_WPB>, (const void*)k_smoother_mfma<float, MFMA_WPB>,
         (const void*)k_star_eigen<double>, (const void*)k_star_eigen<float>,
         (const void*)k_condensed_op_w<double, 16>, (const void*)k_condensed_op_w<float, 16>,
-        (const void*)k_condensed_op_w<double, 12>, (const void*)k_condensed_op_w<float, 12>,
-        (const void*)k_condense_faces, (const void*)k_recover_mid};
+        (const void*)k_condensed_op_w<double, 12>, (const void*)k_condensed_op_w<float, 12>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
