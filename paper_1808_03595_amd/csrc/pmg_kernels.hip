@@ -2948,6 +2948,111 @@ __global__ void __launch_bounds__(256) k_condensed_op_low(LevelTabs<T> tb, const
     y[s] = F ? F[s] - acc : acc;
 }
 
+// Degree 2 with the skeleton values of a box of nodes staged in LDS: the
+// x1-neighbours of a node lie in the other plane families, so reading them
+// per node (k_condensed_op_low) scatters every load over up to 64 planes.
+// Here a workgroup loads a box of BX x BY x BZ nodes plus a halo of 2 in
+// every direction into LDS, the nodes on family-0 planes (even i1) with i2
+// fastest and the others with i1 fastest (both contiguous in the layout),
+// evaluates the same axis stencil and face-centre term for the box's nodes
+// from LDS, stages the results in LDS and writes them back the same two
+// ways.  Only canonical unknowns are written; the caller zeroes y first.
+constexpr int BOX_X = 32, BOX_Y = 8, BOX_Z = 4;
+constexpr int BOX_HX = BOX_X + 4, BOX_HY = BOX_Y + 4, BOX_HZ = BOX_Z + 4;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_condensed_op_box2(LevelTabs<T> tb, const T* __restrict__ u,
+                                                           const T* __restrict__ F, T* __restrict__ y, int nbx,
+                                                           int nby) {
+    __shared__ T U[BOX_HZ * BOX_HY * BOX_HX];
+    __shared__ T Yb[BOX_Z * BOX_Y * BOX_X];
+    const Layout& L = tb.lay;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bxi = b % nbx, byi = (b / nbx) % nby, bzi = b / (nbx * nby);
+    const int X0 = bxi * BOX_X, Y0 = byi * BOX_Y, Z0 = bzi * BOX_Z;   // X0 even
+    // halo box: g = (X0 - 2 + lx, Y0 - 2 + ly, Z0 - 2 + lz)
+    constexpr int NE = (BOX_HX / 2) * BOX_HY * BOX_HZ;   // entries with even (resp. odd) lx
+    for (int t = threadIdx.x; t < NE; t += blockDim.x) {   // even g1: family 0, i2 fastest
+        const int ly = t % BOX_HY, lz = (t / BOX_HY) % BOX_HZ, lx = 2 * (t / (BOX_HY * BOX_HZ));
+        bool ok;
+        const int64_t sl = skel_slot<2>(L, X0 - 2 + lx, Y0 - 2 + ly, Z0 - 2 + lz, 0, ok);
+        const T v = u[sl];
+        U[(lz * BOX_HY + ly) * BOX_HX + lx] = ok ? v : T(0);
+    }
+    for (int t = threadIdx.x; t < NE; t += blockDim.x) {   // odd g1: families 1 and 2, i1 fastest
+        const int lx = 2 * (t % (BOX_HX / 2)) + 1, ly = (t / (BOX_HX / 2)) % BOX_HY, lz = t / ((BOX_HX / 2) * BOX_HY);
+        bool ok;
+        const int64_t sl = skel_slot<2>(L, X0 - 2 + lx, Y0 - 2 + ly, Z0 - 2 + lz, 0, ok);
+        const T v = u[sl];
+        U[(lz * BOX_HY + ly) * BOX_HX + lx] = ok ? v : T(0);
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % BOX_X, ty = threadIdx.x / BOX_X;   // 32 x 8
+    const int g1 = X0 + tx, g2 = Y0 + ty;
+    T m1 = 0, m2 = 0, c1[5] = {0, 0, 0, 0, 0}, c2[5] = {0, 0, 0, 0, 0};
+    const bool in12 = g1 > 0 && g1 < L.N[0] - 1 && g2 > 0 && g2 < L.N[1] - 1;
+    if (in12) {
+        axis_rec<T, 2>(tb.ax[0], g1, m1, c1);
+        axis_rec<T, 2>(tb.ax[1], g2, m2, c2);
+    }
+    for (int tz = 0; tz < BOX_Z; ++tz) {
+        const int g3 = Z0 + tz;
+        const int lx = tx + 2, ly = ty + 2, lz = tz + 2;
+        T out = 0;
+        const bool unk = in12 && g3 > 0 && g3 < L.N[2] - 1 && !((g1 & 1) && (g2 & 1) && (g3 & 1));
+        if (unk) {
+            T m3, c3[5];
+            axis_rec<T, 2>(tb.ax[2], g3, m3, c3);
+            const T* Uc = U + (lz * BOX_HY + ly) * BOX_HX + lx;
+            const T u0 = Uc[0];
+            T x1 = c1[2] * u0, x2 = c2[2] * u0, x3 = c3[2] * u0;
+#pragma unroll
+            for (int o = -2; o <= 2; ++o) {
+                if (o == 0) continue;
+                x1 += c1[o + 2] * Uc[o];
+                x2 += c2[o + 2] * Uc[o * BOX_HX];
+                x3 += c3[o + 2] * Uc[o * BOX_HX * BOX_HY];
+            }
+            out = tb.lam * m1 * m2 * m3 * u0 + m2 * m3 * x1 + m1 * m3 * x2 + m1 * m2 * x3;
+            const bool b1 = (g1 & 1) == 0, b2 = (g2 & 1) == 0, b3 = (g3 & 1) == 0;
+            if ((int)b1 + (int)b2 + (int)b3 == 1) {   // face centre (as in k_condensed_op_low)
+                const int dd = b1 ? 0 : (b2 ? 1 : 2);
+                const int64_t eh = ((int64_t)(g3 >> 1) * L.n[1] + (g2 >> 1)) * L.n[0] + (g1 >> 1);
+                const int64_t el = eh - (dd == 0 ? 1 : (dd == 1 ? L.n[0] : (int64_t)L.n[0] * L.n[1]));
+                const T tl = tb.tc[el], th = tb.tc[eh];
+                const T mo = dd == 0 ? m2 * m3 : (dd == 1 ? m1 * m3 : m1 * m2);
+                const T cl = dd == 0 ? c1[1] : (dd == 1 ? c2[1] : c3[1]);
+                const T ch = dd == 0 ? c1[3] : (dd == 1 ? c2[3] : c3[3]);
+                out -= mo * (cl * tl + ch * th);
+            }
+        }
+        Yb[(tz * BOX_Y + ty) * BOX_X + tx] = out;
+    }
+    __syncthreads();
+    // write back: canonical unknowns only
+    constexpr int NO = (BOX_X / 2) * BOX_Y * BOX_Z;
+    for (int t = threadIdx.x; t < NO; t += blockDim.x) {   // even g1 (family 0), i2 fastest
+        const int ty2 = t % BOX_Y, tz = (t / BOX_Y) % BOX_Z, tx2 = 2 * (t / (BOX_Y * BOX_Z));
+        const int h1 = X0 + tx2, h2 = Y0 + ty2, h3 = Z0 + tz;
+        bool ok;
+        const int64_t sl = skel_slot<2>(L, h1, h2, h3, 0, ok);
+        if (ok) {
+            const T v = Yb[(tz * BOX_Y + ty2) * BOX_X + tx2];
+            y[sl] = F ? F[sl] - v : v;
+        }
+    }
+    for (int t = threadIdx.x; t < NO; t += blockDim.x) {   // odd g1, i1 fastest
+        const int tx2 = 2 * (t % (BOX_X / 2)) + 1, ty2 = (t / (BOX_X / 2)) % BOX_Y, tz = t / ((BOX_X / 2) * BOX_Y);
+        const int h1 = X0 + tx2, h2 = Y0 + ty2, h3 = Z0 + tz;
+        bool ok;
+        const int64_t sl = skel_slot<2>(L, h1, h2, h3, 0, ok);
+        if (ok) {
+            const T v = Yb[(tz * BOX_Y + ty2) * BOX_X + tx2];
+            y[sl] = F ? F[sl] - v : v;
+        }
+    }
+}
+
 // Sum of (x, y) over the block, returned to every thread (each adds the
 // per-wave totals in the same order, so all hold the same bits).
 __device__ inline void block_sum2_all(double& x, double& y, double* red) {
@@ -3337,7 +3442,11 @@ void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t s
         if (L.p == 2) {
             const int ne = L.n[0] * L.n[1] * L.n[2];
             hipLaunchKernelGGL(k_centre_t<T>, dim3((ne + 255) / 256), dim3(256), 0, st, tb, u);
-            hipLaunchKernelGGL((k_condensed_op_low<T, 2>), grid, dim3(256), 0, st, tb, u, F, y, bx, by);
+            const int nbx = (L.N[0] + BOX_X - 1) / BOX_X, nby = (L.N[1] + BOX_Y - 1) / BOX_Y,
+                      nbz = (L.N[2] + BOX_Z - 1) / BOX_Z;
+            launch_fill_zero<T>(y, L.len, st);
+            hipLaunchKernelGGL(k_condensed_op_box2<T>, dim3((unsigned)((int64_t)nbx * nby * nbz)), dim3(256), 0, st,
+                               tb, u, F, y, nbx, nby);
         } else {
             hipLaunchKernelGGL((k_condensed_op_low<T, 1>), grid, dim3(256), 0, st, tb, u, F, y, bx, by);
         }
