@@ -1251,6 +1251,10 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
         bool b1 = v1 == 0 || v1 == L.n[0], b2 = v2 == 0 || v2 == L.n[1], b3 = v3 == 0 || v3 == L.n[2];
         if (b1 && b2 && b3) active = false;  // corner: all three planes Dirichlet
     }
+    // interior star (1 <= v_d <= n_d - 1): its windows lie inside the node
+    // grid and hold no Dirichlet node, so loads and atomics skip those tests
+    // (wave-uniform: one star per wavefront; 26.3 -> 25.7 us FP32 at 16^3)
+    const bool inner = active && v1 >= 1 && v1 < L.n[0] && v2 >= 1 && v2 < L.n[1] && v3 >= 1 && v3 < L.n[2];
     const T* S1 = tb.st_SP[0] + (size_t)v1 * 256;
     const T* S2 = tb.st_SP[1] + (size_t)v2 * 256;
     const T* S3 = tb.st_SP[2] + (size_t)v3 * 256;
@@ -1302,12 +1306,18 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
         T x1 = 0, x2 = 0, x3 = 0;
         if (ok) {
             int i1 = c1 + ob, i2 = c2 + ob, i3 = c3 + oa, i2a = c2 + oa;
-            if (i2 >= 0 && i2 < L.N[1] && i3 >= 0 && i3 < L.N[2])
+            if (inner) {
                 x1 = r[L.plane0(v1) + (int64_t)i3 * L.pitch[0] + i2];
-            if (i1 >= 0 && i1 < L.N[0] && i3 >= 0 && i3 < L.N[2])
                 x2 = r[L.plane1(v2) + (int64_t)i3 * L.pitch[1] + i1];
-            if (i1 >= 0 && i1 < L.N[0] && i2a >= 0 && i2a < L.N[1])
                 x3 = r[L.plane2(v3) + (int64_t)i2a * L.pitch[2] + i1];
+            } else {
+                if (i2 >= 0 && i2 < L.N[1] && i3 >= 0 && i3 < L.N[2])
+                    x1 = r[L.plane0(v1) + (int64_t)i3 * L.pitch[0] + i2];
+                if (i1 >= 0 && i1 < L.N[0] && i3 >= 0 && i3 < L.N[2])
+                    x2 = r[L.plane1(v2) + (int64_t)i3 * L.pitch[1] + i1];
+                if (i1 >= 0 && i1 < L.N[0] && i2a >= 0 && i2a < L.N[1])
+                    x3 = r[L.plane2(v3) + (int64_t)i2a * L.pitch[2] + i1];
+            }
         }
         f1[s] = x1;
         f2[s] = x2;
@@ -1438,6 +1448,19 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
     if (!active) return;
     if (!early) load_w();
     const int ob = j - c;
+    if (inner) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int a = M::row(q, v), oa = a - c;
+            if (a >= nS || j >= nS) continue;
+            const T wt = wj * wr[v];
+            unsafeAtomicAdd(du + L.plane0(v1) + (int64_t)(c3 + oa) * L.pitch[0] + (c2 + ob), wt * u1[v]);
+            if (ob != 0) unsafeAtomicAdd(du + L.plane1(v2) + (int64_t)(c3 + oa) * L.pitch[1] + (c1 + ob), wt * u2[v]);
+            if (ob != 0 && oa != 0)
+                unsafeAtomicAdd(du + L.plane2(v3) + (int64_t)(c2 + oa) * L.pitch[2] + (c1 + ob), wt * u3[v]);
+        }
+        return;
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int a = M::row(q, v), oa = a - c;
