@@ -2834,7 +2834,9 @@ struct CoarseShape {
 // H_BI H_II^-1 H_IB u (p = 2) only changes face centres: each subtracts,
 // for the two elements that share its face, its coupling to the element
 // centre times t_e = (H_IB u)_e / (H_II)_e, formed beforehand from the six
-// face centres of each element (k_centre_t).
+// face centres of each element (k_centre_t).  Degree 1 runs the per-slot
+// kernel k_condensed_op_low below; degree 2 runs k_condensed_op_box2, which
+// evaluates the same stencil from a box of nodes staged in LDS.
 // ---------------------------------------------------------------------------
 
 // Slot of the skeleton value at global node (i1, i2, i3); `ok` is false
