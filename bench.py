@@ -108,9 +108,9 @@ def smoother_flops(n, p):
 def smoother_kernel(p, t):
     """The smoother kernel that degree p runs (t: "float" or "double")."""
     nS = 2 * p - 1
-    if nS <= 4:
-        return f"k_smoother_small<{t}, 4>"
-    if nS <= 8:
+    if nS <= 3:
+        return f"k_smoother_small<{t}, 3>"
+    if nS <= 7:
         return f"k_smoother_small<{t}, 8>"
     if nS <= 16:
         return f"k_smoother_mfma<{t}, 1>"

@@ -1,0 +1,47 @@
+"""Host-side checks of bench.py's contract (no GPU needed)."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_multi_gpu_request_exits_with_message():
+    """The build measures one GPU; --gpus N > 1 must stop with a message
+    (before touching a device)."""
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+
+
+def test_workload_recipes():
+    """The benchmark workload and the p-sweep points: element counts,
+    degrees and the stretching that gives aspect ratio 8."""
+    wl = bench.workload("c2a")
+    assert wl["n"] == (16, 16, 16) and wl["p"] == 8
+    assert abs(wl["alpha"] ** 15 - 8.0) < 1e-12
+    wl = bench.workload("c2b")
+    assert wl["n"] == (8, 8, 8) and wl["p"] == 16
+    assert abs(wl["alpha"] ** 7 - 8.0) < 1e-12
+    for p in bench.SWEEP:
+        w = bench.workload(f"c3p{p}")
+        assert w["p"] == p and w["n"][0] == int(round(215.44 / p)) and w["alpha"] == 1.0
+
+
+def test_smoother_flop_count():
+    """37 n_S^3 flop per star (Alg. 1 count), corners excluded: 0.612 GFLOP
+    at 16^3, p = 8."""
+    fl = bench.smoother_flops((16, 16, 16), 8)
+    assert fl == 37.0 * 15 ** 3 * (17 ** 3 - 8)
+    assert abs(fl - 0.612e9) < 0.001e9
+
+
+def test_smoother_kernel_names():
+    assert bench.smoother_kernel(2, "float") == "k_smoother_small<float, 3>"
+    assert bench.smoother_kernel(4, "double") == "k_smoother_small<double, 8>"
+    assert bench.smoother_kernel(8, "float") == "k_smoother_mfma<float, 1>"
