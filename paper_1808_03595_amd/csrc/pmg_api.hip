@@ -682,6 +682,19 @@ void vc_coarse_io(pmg_mesh* m, const T* r, T* z, const double*& b, double*& x) {
     }
 }
 
+// One grid transfer between active levels lv (fine) and lc (coarse); the
+// coarse-side array may be FP64 below an FP32 fine level.
+template <typename T, typename TC>
+void restrict_to(Level& lv, Level& lc, const T* y, TC* Fc, hipStream_t st) {
+    if (lv.kind == 'p') launch_restrict<T>(lv.lay, lc.lay, jdown<T>(lv), y, Fc, Sel<T>::tb(lv), st);
+    else launch_hrestrict<T>(lv.lay, lc.lay, hweights<T>(lv), y, Fc, st);
+}
+template <typename T, typename TC>
+void prolong_from(Level& lc, Level& lv, const TC* uc, T* u, hipStream_t st) {
+    if (lv.kind == 'p') launch_prolong_add<T>(lc.lay, lv.lay, jdown<T>(lv), uc, u, st);
+    else launch_hprolong_add<T>(lc.lay, lv.lay, hweights<T>(lv), uc, u, st);
+}
+
 template <typename T>
 int vc_down(pmg_mesh* m, const T* r, T* z, bool nonzero_u, hipStream_t st) {
     auto& A = m->act;
@@ -710,12 +723,13 @@ int vc_down(pmg_mesh* m, const T* r, T* z, bool nonzero_u, hipStream_t st) {
         }
         residual<T>(lv, F, u, y, st);
         Level& lc = *A[l - 1];
-        T* Fc = Sel<T>::F(lc);
-        if (lv.kind == 'p') launch_restrict<T>(lv.lay, lc.lay, jdown<T>(lv), y, Fc, Sel<T>::tb(lv), st);
-        else launch_hrestrict<T>(lv.lay, lc.lay, hweights<T>(lv), y, Fc, st);
-        F = Fc;
+        if (l == 1) {   // into the FP64 right-hand side of the coarse solve
+            restrict_to<T, double>(lv, lc, y, l0.F64, st);
+            break;
+        }
+        restrict_to<T, T>(lv, lc, y, Sel<T>::F(lc), st);
+        F = Sel<T>::F(lc);
     }
-    if (!std::is_same<T, double>::value) launch_cast_scale<T, double>(F, l0.F64, nullptr, 0, l0.lay.len, st);
     return 0;
 }
 
@@ -729,19 +743,14 @@ int vc_up(pmg_mesh* m, const T* r, T* z, hipStream_t st) {
         if (!dbl) launch_cast_scale<double, T>(l0.u64, z, nullptr, 0, l0.lay.len, st);
         return 0;
     }
-    T* uc;
-    if (dbl) uc = reinterpret_cast<T*>(l0.u64);
-    else {
-        launch_cast_scale<double, T>(l0.u64, Sel<T>::u(l0), nullptr, 0, l0.lay.len, st);
-        uc = Sel<T>::u(l0);
-    }
+    const T* uc = nullptr;
     for (int l = 1; l <= L; ++l) {
         Level& lv = *A[l];
         Level& lc = *A[l - 1];
         T* u = (l == L) ? z : Sel<T>::u(lv);
         const T* F = (l == L) ? r : Sel<T>::F(lv);
-        if (lv.kind == 'p') launch_prolong_add<T>(lc.lay, lv.lay, jdown<T>(lv), uc, u, st);
-        else launch_hprolong_add<T>(lc.lay, lv.lay, hweights<T>(lv), uc, u, st);
+        if (l == 1) prolong_from<T, double>(lc, lv, l0.u64, u, st);   // the FP64 coarse solution
+        else prolong_from<T, T>(lc, lv, uc, u, st);
         T* y = Sel<T>::y(lv);
         for (int i = 0; i < lv.nu; ++i) {
             residual<T>(lv, F, u, y, st);
@@ -850,16 +859,16 @@ int pmg_create_mesh_widths(int n1, int n2, int n3, int p, double lambda, const d
 
 void pmg_destroy_mesh(pmg_mesh* m) {
     if (!m) return;
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     for (auto* v : {&m->lv, &m->hlv})
         for (Level& l : *v)
             for (hipGraphExec_t g : l.coarse_exec)
                 if (g) (void)hipGraphExecDestroy(g);
     for (hipGraphExec_t g : m->solver_graphs)
         if (g) (void)hipGraphExecDestroy(g);
-    for (void* q : m->allocs) hipFree(q);
-    if (m->hscal) hipHostFree(m->hscal);
-    if (m->hcit) hipHostFree(m->hcit);
+    for (void* q : m->allocs) (void)hipFree(q);
+    if (m->hscal) (void)hipHostFree(m->hscal);
+    if (m->hcit) (void)hipHostFree(m->hcit);
     if (m->hmail) (void)hipHostFree((void*)m->hmail);
     if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
     delete m;
@@ -1187,10 +1196,10 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
     HIPCHK(hipMemcpyAsync(m->hcit, m->d_coarse_iters, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     float t0 = 0, t1 = 0, t2 = 0;
-    hipEventElapsedTime(&t0, ev[0], ev[1]);
-    hipEventElapsedTime(&t1, ev[1], ev[2]);
-    hipEventElapsedTime(&t2, ev[2], ev[3]);
-    for (int i = 0; i < 4; ++i) hipEventDestroy(ev[i]);
+    (void)hipEventElapsedTime(&t0, ev[0], ev[1]);   // a failed query leaves 0
+    (void)hipEventElapsedTime(&t1, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&t2, ev[2], ev[3]);
+    for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
     stats.iters = it;
     stats.status = status;
     stats.rel_res = stats.res0 > 0 ? std::sqrt(rr) / stats.res0 : 0.0;

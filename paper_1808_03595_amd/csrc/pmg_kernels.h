@@ -29,10 +29,11 @@ template <typename T> void launch_skel_to_grid(const Layout&, const T*, double*,
 // y = H_hat u, or y = F - H_hat u (the residual) when F is given
 template <typename T> void launch_condensed_op(const LevelTabs<T>&, const T*, T*, hipStream_t, const T* F = nullptr);
 template <typename T> void launch_smoother_add(const LevelTabs<T>&, const T*, T*, T, hipStream_t);
-template <typename T>
-void launch_prolong_add(const Layout& Lc, const Layout& Lf, const T* J, const T* uc, T* uf, hipStream_t);
-template <typename T>
-void launch_restrict(const Layout& Lf, const Layout& Lc, const T* J, const T* rf, T* rc, T* tbuf, hipStream_t);
+// The coarse-side array (uc, rc) may be of a wider type TC than the level's T.
+template <typename T, typename TC>
+void launch_prolong_add(const Layout& Lc, const Layout& Lf, const T* J, const TC* uc, T* uf, hipStream_t);
+template <typename T, typename TC>
+void launch_restrict(const Layout& Lf, const Layout& Lc, const T* J, const T* rf, TC* rc, T* tbuf, hipStream_t);
 template <typename T>
 void launch_dot2(const T* x, const T* y, const T* z, int64_t n, double* partials, unsigned* counter,
                  double* out, hipStream_t);
@@ -40,10 +41,10 @@ template <typename T> void launch_sub_from(const T* x, T* y, int64_t n, hipStrea
 template <typename T> void launch_axpy(T a, const T* x, T* y, int64_t n, hipStream_t);
 template <typename T, typename U>
 void launch_cast_scale(const T* x, U* y, const double* sc, int invert, int64_t n, hipStream_t);
-template <typename T>
-void launch_hprolong_add(const Layout& Lc, const Layout& Lf, const T* const* t, const T* uc, T* uf, hipStream_t);
-template <typename T>
-void launch_hrestrict(const Layout& Lf, const Layout& Lc, const T* const* t, const T* rf, T* rc, hipStream_t);
+template <typename T, typename TC>
+void launch_hprolong_add(const Layout& Lc, const Layout& Lf, const T* const* t, const TC* uc, T* uf, hipStream_t);
+template <typename T, typename TC>
+void launch_hrestrict(const Layout& Lf, const Layout& Lc, const T* const* t, const T* rf, TC* rc, hipStream_t);
 template <typename T>
 void launch_point_smooth(const Layout& L, const T* dg, const T* r, T* u, T omega, hipStream_t);
 template <typename T> size_t smem_condensed_op(int p);

@@ -1871,16 +1871,16 @@ __global__ void __launch_bounds__(256) k_star_eigen(LevelTabs<T> tb, const T* __
 // ---------------------------------------------------------------------------
 // Coarse value at plane node (R, C) of family d, plane j, read from the
 // family that stores the node.
-template <typename T>
-__device__ inline T coarse_plane_value(const Layout& L, const T* x, int d, int j, int R, int C, int pc) {
-    if (d == 0) return x[L.plane0(j) + (int64_t)R * L.pitch[0] + C];
+template <typename T, typename TC>
+__device__ inline T coarse_plane_value(const Layout& L, const TC* x, int d, int j, int R, int C, int pc) {
+    if (d == 0) return (T)x[L.plane0(j) + (int64_t)R * L.pitch[0] + C];
     if (d == 1) {
-        if (C % pc == 0) return x[L.plane0(C / pc) + (int64_t)R * L.pitch[0] + j * pc];
-        return x[L.plane1(j) + (int64_t)R * L.pitch[1] + C];
+        if (C % pc == 0) return (T)x[L.plane0(C / pc) + (int64_t)R * L.pitch[0] + j * pc];
+        return (T)x[L.plane1(j) + (int64_t)R * L.pitch[1] + C];
     }
-    if (C % pc == 0) return x[L.plane0(C / pc) + (int64_t)(j * pc) * L.pitch[0] + R];
-    if (R % pc == 0) return x[L.plane1(R / pc) + (int64_t)(j * pc) * L.pitch[1] + C];
-    return x[L.plane2(j) + (int64_t)R * L.pitch[2] + C];
+    if (C % pc == 0) return (T)x[L.plane0(C / pc) + (int64_t)(j * pc) * L.pitch[0] + R];
+    if (R % pc == 0) return (T)x[L.plane1(R / pc) + (int64_t)(j * pc) * L.pitch[1] + C];
+    return (T)x[L.plane2(j) + (int64_t)R * L.pitch[2] + C];
 }
 
 __device__ inline int plane_family(const Layout& L, int z, int& j) {
@@ -1896,9 +1896,9 @@ __device__ inline int plane_family(const Layout& L, int z, int& j) {
 // row interpolation: 2 (pc + 1) operations per fine node instead of
 // (pc + 1)^2.  Element Er writes its rows 0..pf-1, the last element also
 // row pf (a boundary row interpolates to the same value from either side).
-template <typename T>
+template <typename T, typename TC>
 __global__ void __launch_bounds__(64) k_prolong_sep(Layout Lc, Layout Lf, const T* __restrict__ J,
-                                                    const T* __restrict__ uc, T* __restrict__ uf) {
+                                                    const TC* __restrict__ uc, T* __restrict__ uf) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int j;
     const int d = plane_family(Lf, blockIdx.z, j);
@@ -1911,7 +1911,7 @@ __global__ void __launch_bounds__(64) k_prolong_sep(Layout Lc, Layout Lf, const 
     for (int R = 0; R < nc1; ++R) {
         T a = 0;
         for (int C = 0; C < nc1; ++C)
-            a += J[lc * nc1 + C] * coarse_plane_value(Lc, uc, d, j, Er * pc + R, Ec * pc + C, pc);
+            a += J[lc * nc1 + C] * coarse_plane_value<T>(Lc, uc, d, j, Er * pc + R, Ec * pc + C, pc);
         t[R] = a;
     }
     const bool col_ok = d == 0 || gc % pf != 0;
@@ -1930,9 +1930,9 @@ __global__ void __launch_bounds__(64) k_prolong_sep(Layout Lc, Layout Lf, const 
 }
 
 // uf += P uc on every canonical, non-Dirichlet fine node.
-template <typename T, int PF, int PC>
+template <typename T, typename TC, int PF, int PC>
 __global__ void __launch_bounds__(256) k_prolong_direct(Layout Lc, Layout Lf, const T* __restrict__ J,
-                                                        const T* __restrict__ uc, T* __restrict__ uf) {
+                                                        const TC* __restrict__ uc, T* __restrict__ uf) {
     int j;
     const int d = plane_family(Lf, blockIdx.z, j);
     const int gr = blockIdx.y * 4 + threadIdx.y, gc = blockIdx.x * 64 + threadIdx.x;
@@ -1955,7 +1955,7 @@ __global__ void __launch_bounds__(256) k_prolong_direct(Layout Lc, Layout Lf, co
         if (wr == (T)0) continue;
         T t = 0;
         for (int C = 0; C < nc1; ++C)
-            t += J[lc * nc1 + C] * coarse_plane_value(Lc, uc, d, j, Er * pc + R, Ec * pc + C, pc);
+            t += J[lc * nc1 + C] * coarse_plane_value<T>(Lc, uc, d, j, Er * pc + R, Ec * pc + C, pc);
         s += wr * t;
     }
     uf[Lf.off[d] + (int64_t)j * Lf.pstride[d] + (int64_t)gr * Lf.pitch[d] + gc] += s;
@@ -2018,8 +2018,8 @@ __global__ void __launch_bounds__(256) k_restrict_cols(Layout Lc, Layout Lf, con
 
 // Restriction pass B: coarse unknown = sum of T_d over the plane families
 // that contain it.
-template <typename T>
-__global__ void k_restrict_combine(Layout L, const T* __restrict__ tbuf, T* __restrict__ rc) {
+template <typename T, typename TC>
+__global__ void k_restrict_combine(Layout L, const T* __restrict__ tbuf, TC* __restrict__ rc) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L.len) return;
     int d = (i >= L.off[2]) ? 2 : (i >= L.off[1] ? 1 : 0);
@@ -2041,7 +2041,7 @@ __global__ void k_restrict_combine(Layout L, const T* __restrict__ tbuf, T* __re
             if (d == 0 && i2 % p == 0) v += tbuf[L.plane1(i2 / p) + (int64_t)i3 * L.pitch[1] + i1];
         }
     }
-    rc[i] = v;
+    rc[i] = (TC)v;
 }
 
 // ---------------------------------------------------------------------------
@@ -2056,9 +2056,9 @@ __device__ inline T* p1_at(const Layout& L, T* x, int i1, int i2, int i3) {
     return x + L.plane0(i1) + (int64_t)i3 * L.pitch[0] + i2;
 }
 
-template <typename T>
+template <typename T, typename TC>
 __global__ void k_hprolong_add(Layout Lc, Layout Lf, const T* __restrict__ t1, const T* __restrict__ t2,
-                               const T* __restrict__ t3, const T* __restrict__ uc, T* __restrict__ uf) {
+                               const T* __restrict__ t3, const TC* __restrict__ uc, T* __restrict__ uf) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tot = (int64_t)Lf.N[0] * Lf.N[1] * Lf.N[2];
     if (i >= tot) return;
@@ -2087,14 +2087,14 @@ __global__ void k_hprolong_add(Layout Lc, Layout Lf, const T* __restrict__ t1, c
         for (int b = 0; b < 2; ++b)
             for (int cc = 0; cc < 2; ++cc) {
                 T wt = w[0][a] * w[1][b] * w[2][cc];
-                if (wt != (T)0) s += wt * *p1_at(Lc, uc, c[0][a], c[1][b], c[2][cc]);
+                if (wt != (T)0) s += wt * (T)*p1_at(Lc, uc, c[0][a], c[1][b], c[2][cc]);
             }
     *p1_at(Lf, uf, f1, f2, f3) += s;
 }
 
-template <typename T>
+template <typename T, typename TC>
 __global__ void k_hrestrict(Layout Lf, Layout Lc, const T* __restrict__ t1, const T* __restrict__ t2,
-                            const T* __restrict__ t3, const T* __restrict__ rf, T* __restrict__ rc) {
+                            const T* __restrict__ t3, const T* __restrict__ rf, TC* __restrict__ rc) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= Lc.len) return;
     // every slot of the coarse array is written (zero outside the unknowns)
@@ -2128,7 +2128,7 @@ __global__ void k_hrestrict(Layout Lf, Layout Lc, const T* __restrict__ t1, cons
                     }
         }
     }
-    rc[i] = s;
+    rc[i] = (TC)s;
 }
 
 // u += omega r / diag on every slot (diag = 1 and r = 0 outside the unknowns)
@@ -3592,10 +3592,10 @@ int64_t restrict_work_len(const Layout& Lf, const Layout& Lc) {
     return Lc.len + y;
 }
 
-template <typename T>
-void launch_prolong_add(const Layout& Lc, const Layout& Lf, const T* J, const T* uc, T* uf, hipStream_t st) {
+template <typename T, typename TC>
+void launch_prolong_add(const Layout& Lc, const Layout& Lf, const T* J, const TC* uc, T* uf, hipStream_t st) {
     const dim3 g = plane_grid(Lf, max_cols(Lf), max_rows(Lf)), b(64, 4);
-#define PMG_PRO(A, B) hipLaunchKernelGGL((k_prolong_direct<T, A, B>), g, b, 0, st, Lc, Lf, J, uc, uf)
+#define PMG_PRO(A, B) hipLaunchKernelGGL((k_prolong_direct<T, TC, A, B>), g, b, 0, st, Lc, Lf, J, uc, uf)
     if (Lf.p == 4 && Lc.p == 2) PMG_PRO(4, 2);
     else if (Lf.p == 8 && Lc.p == 4) PMG_PRO(8, 4);
     else if (Lf.p == 16 && Lc.p == 8) PMG_PRO(16, 8);
@@ -3603,13 +3603,13 @@ void launch_prolong_add(const Layout& Lc, const Layout& Lf, const T* J, const T*
         int mr = 0;
         for (int dd = 0; dd < 3; ++dd) mr = std::max(mr, Lf.n[dd]);
         const dim3 gs((max_cols(Lf) + 63) / 64, mr, Lf.n[0] + Lf.n[1] + Lf.n[2] + 3);
-        hipLaunchKernelGGL(k_prolong_sep<T>, gs, dim3(64), sizeof(T) * 64 * (Lc.p + 1), st, Lc, Lf, J, uc, uf);
+        hipLaunchKernelGGL((k_prolong_sep<T, TC>), gs, dim3(64), sizeof(T) * 64 * (Lc.p + 1), st, Lc, Lf, J, uc, uf);
     }
 #undef PMG_PRO
 }
 
-template <typename T>
-void launch_restrict(const Layout& Lf, const Layout& Lc, const T* J, const T* rf, T* rc, T* tbuf,
+template <typename T, typename TC>
+void launch_restrict(const Layout& Lf, const Layout& Lc, const T* J, const T* rf, TC* rc, T* tbuf,
                      hipStream_t st) {
     T* Y = tbuf + Lc.len;
     const dim3 g1 = plane_grid(Lf, max_cols(Lc), max_rows(Lf)), g2 = plane_grid(Lc, max_cols(Lc), max_rows(Lc)),
@@ -3624,17 +3624,17 @@ void launch_restrict(const Layout& Lf, const Layout& Lc, const T* J, const T* rf
     else if (Lf.p == 16 && Lc.p == 8) PMG_RES(16, 8);
     else PMG_RES(0, 0);
 #undef PMG_RES
-    hipLaunchKernelGGL(k_restrict_combine<T>, dim3(nblk(Lc.len)), dim3(256), 0, st, Lc, (const T*)tbuf, rc);
+    hipLaunchKernelGGL((k_restrict_combine<T, TC>), dim3(nblk(Lc.len)), dim3(256), 0, st, Lc, (const T*)tbuf, rc);
 }
 
-template <typename T>
-void launch_hprolong_add(const Layout& Lc, const Layout& Lf, const T* const* t, const T* uc, T* uf, hipStream_t st) {
+template <typename T, typename TC>
+void launch_hprolong_add(const Layout& Lc, const Layout& Lf, const T* const* t, const TC* uc, T* uf, hipStream_t st) {
     int64_t tot = (int64_t)Lf.N[0] * Lf.N[1] * Lf.N[2];
-    hipLaunchKernelGGL(k_hprolong_add<T>, dim3(nblk(tot)), dim3(256), 0, st, Lc, Lf, t[0], t[1], t[2], uc, uf);
+    hipLaunchKernelGGL((k_hprolong_add<T, TC>), dim3(nblk(tot)), dim3(256), 0, st, Lc, Lf, t[0], t[1], t[2], uc, uf);
 }
-template <typename T>
-void launch_hrestrict(const Layout& Lf, const Layout& Lc, const T* const* t, const T* rf, T* rc, hipStream_t st) {
-    hipLaunchKernelGGL(k_hrestrict<T>, dim3(nblk(Lc.len)), dim3(256), 0, st, Lf, Lc, t[0], t[1], t[2], rf, rc);
+template <typename T, typename TC>
+void launch_hrestrict(const Layout& Lf, const Layout& Lc, const T* const* t, const T* rf, TC* rc, hipStream_t st) {
+    hipLaunchKernelGGL((k_hrestrict<T, TC>), dim3(nblk(Lc.len)), dim3(256), 0, st, Lf, Lc, t[0], t[1], t[2], rf, rc);
 }
 template <typename T>
 void launch_point_smooth(const Layout& L, const T* dg, const T* r, T* u, T omega, hipStream_t st) {
@@ -3885,21 +3885,31 @@ hipError_t init_kernel_attributes() {
     template void launch_skel_to_grid<T>(const Layout&, const T*, double*, hipStream_t);                    \
     template void launch_condensed_op<T>(const LevelTabs<T>&, const T*, T*, hipStream_t, const T*);        \
     template void launch_smoother_add<T>(const LevelTabs<T>&, const T*, T*, T, hipStream_t);               \
-    template void launch_prolong_add<T>(const Layout&, const Layout&, const T*, const T*, T*, hipStream_t); \
-    template void launch_restrict<T>(const Layout&, const Layout&, const T*, const T*, T*, T*, hipStream_t); \
+    template void launch_prolong_add<T, T>(const Layout&, const Layout&, const T*, const T*, T*, hipStream_t); \
+    template void launch_restrict<T, T>(const Layout&, const Layout&, const T*, const T*, T*, T*, hipStream_t); \
     template void launch_dot2<T>(const T*, const T*, const T*, int64_t, double*, unsigned*, double*,        \
                                  hipStream_t);                                                             \
     template void launch_sub_from<T>(const T*, T*, int64_t, hipStream_t);                                  \
     template void launch_axpy<T>(T, const T*, T*, int64_t, hipStream_t);                                   \
     template size_t smem_condensed_op<T>(int);                                                             \
     template size_t smem_smoother<T>(int);                                                                 \
-    template void launch_hprolong_add<T>(const Layout&, const Layout&, const T* const*, const T*, T*,       \
+    template void launch_hprolong_add<T, T>(const Layout&, const Layout&, const T* const*, const T*, T*,    \
                                          hipStream_t);                                                     \
-    template void launch_hrestrict<T>(const Layout&, const Layout&, const T* const*, const T*, T*,          \
+    template void launch_hrestrict<T, T>(const Layout&, const Layout&, const T* const*, const T*, T*,       \
                                       hipStream_t);                                                        \
     template void launch_point_smooth<T>(const Layout&, const T*, const T*, T*, T, hipStream_t);
 INST(double)
 INST(float)
+// FP32 V-cycle around the FP64 coarse solve: the last restriction writes,
+// the first prolongation reads, the coarse level's FP64 arrays directly.
+template void launch_prolong_add<float, double>(const Layout&, const Layout&, const float*, const double*, float*,
+                                                hipStream_t);
+template void launch_restrict<float, double>(const Layout&, const Layout&, const float*, const float*, double*,
+                                             float*, hipStream_t);
+template void launch_hprolong_add<float, double>(const Layout&, const Layout&, const float* const*, const double*,
+                                                 float*, hipStream_t);
+template void launch_hrestrict<float, double>(const Layout&, const Layout&, const float* const*, const float*,
+                                              double*, hipStream_t);
 template void launch_cast_scale<double, float>(const double*, float*, const double*, int, int64_t, hipStream_t);
 template void launch_cast_scale<float, double>(const float*, double*, const double*, int, int64_t, hipStream_t);
 template void launch_cast_scale<double, double>(const double*, double*, const double*, int, int64_t, hipStream_t);
