@@ -23,6 +23,9 @@ Layout of the package:
 * ``solver``  -- V-cycle (Alg. 3), MG solver (Alg. 4), ipCG (Alg. 5), the
                  coarse CG, the mixed-precision preconditioner form.
 * ``mlp``     -- the damping-weight MLP: forward, analytic backward, Adam.
+* ``dirichlet`` -- inhomogeneous Dirichlet data by lifting (Sec. 3.4
+                 boundary treatment, Sec. 5.2 test problem) and its dense
+                 brute-force solve.
 
 Every array in this package is float64 unless a function says otherwise.
 Global node grids are numpy arrays of shape (N3, N2, N1), x1 fastest,
