@@ -189,6 +189,32 @@ int pmg_pcg_solve(pmg_mesh *m, const double *d_f, double *d_u, double rtol,
 int pmg_mg_solve(pmg_mesh *m, const double *d_f, double *d_u, double rtol,
                  int maxit, pmg_stats *h_stats, void *stream);
 
+/* ---- inhomogeneous Dirichlet data (Sec. 3.4, Sec. 5.2) ------------------
+ * The paper's boundary treatment keeps Dirichlet values fixed while every
+ * correction vanishes there, and its runtime test problem prescribes them
+ * on the whole boundary.  They enter by lifting: with G = g on the boundary
+ * nodes and 0 inside, u = u0 + G, where u0 vanishes on the boundary and
+ * solves the homogeneous problem with f' = f - M^-1 H G (M the diagonal
+ * GLL-lumped mass, H the assembled Helmholtz operator of Sec. 2.1).  Only
+ * the boundary entries of d_g are read.  All arrays are FP64 grids. */
+
+/* d_out = f - M^-1 H G on the inner grid nodes, 0 on the boundary nodes.
+ * d_out may alias d_f but not d_g.  Stream-ordered. */
+int pmg_lift_dirichlet(pmg_mesh *m, const double *d_f, const double *d_g,
+                       double *d_out, void *stream);
+
+/* d_u = d_g on the boundary nodes; inner nodes untouched.  Stream-ordered. */
+int pmg_set_boundary(pmg_mesh *m, const double *d_g, double *d_u, void *stream);
+
+/* pmg_pcg_solve with u = g on the boundary: lifts f into a grid-sized
+ * workspace the mesh allocates on the first call (and keeps), solves, and
+ * writes the boundary values of g into d_u.  d_u must not alias d_g.  Same
+ * return values and synchronization as pmg_pcg_solve. */
+int pmg_pcg_solve_dirichlet(pmg_mesh *m, const double *d_f, const double *d_g,
+                            double *d_u, double rtol, int maxit,
+                            int precond_dtype, pmg_stats *h_stats,
+                            void *stream);
+
 /* ---- learned damping: FP32 MLP 3 -> 64 -> 64 -> nout ------------------
  * Parameter vector (nparams = 64*3+64 + 64*64+64 + nout*64+nout floats):
  * W1[64][3], b1[64], W2[64][64], b2[64], W3[nout][64], b3[nout].

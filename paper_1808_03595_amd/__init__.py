@@ -84,6 +84,9 @@ SIGNATURES = {
     "pmg_recover_interior": (_I, [_VP, _VP, _VP, _VP, _VP]),
     "pmg_pcg_solve": (_I, [_VP, _VP, _VP, _D, _I, _I, ctypes.POINTER(Stats), _VP]),
     "pmg_mg_solve": (_I, [_VP, _VP, _VP, _D, _I, ctypes.POINTER(Stats), _VP]),
+    "pmg_lift_dirichlet": (_I, [_VP, _VP, _VP, _VP, _VP]),
+    "pmg_set_boundary": (_I, [_VP, _VP, _VP, _VP]),
+    "pmg_pcg_solve_dirichlet": (_I, [_VP, _VP, _VP, _VP, _D, _I, _I, ctypes.POINTER(Stats), _VP]),
     "pmg_mlp_nparams": (_I, [_I]),
     "pmg_mlp_forward": (_I, [_VP, _VP, _VP, _VP, _I, _I, _VP]),
     "pmg_mlp_loss": (_I, [_VP, _VP, _VP, _VP, _VP, _I, _I, _VP]),
@@ -243,6 +246,19 @@ class Mesh:
         st = Stats()
         _check(lib().pmg_mg_solve(self.h, _ptr(f), _ptr(u), rtol, maxit, ctypes.byref(st),
                                   _stream(stream)), allow_status=True)
+        return st
+
+    def lift_dirichlet(self, f, g, out, stream=None):
+        _check(lib().pmg_lift_dirichlet(self.h, _ptr(f), _ptr(g), _ptr(out), _stream(stream)))
+
+    def set_boundary(self, g, u, stream=None):
+        _check(lib().pmg_set_boundary(self.h, _ptr(g), _ptr(u), _stream(stream)))
+
+    def pcg_solve_dirichlet(self, f, g, u, rtol=1e-10, maxit=200, precond_dtype=F64, stream=None):
+        st = Stats()
+        _check(lib().pmg_pcg_solve_dirichlet(self.h, _ptr(f), _ptr(g), _ptr(u), rtol, maxit,
+                                             precond_dtype, ctypes.byref(st), _stream(stream)),
+               allow_status=True)
         return st
 
 

@@ -124,6 +124,8 @@ struct pmg_mesh {
            *w_F = nullptr;
     float *w_r32 = nullptr, *w_z32 = nullptr;
     double* m1d[3] = {nullptr, nullptr, nullptr};
+    double* lift_tab = nullptr;   // [3][2][p + 1] Dirichlet lifting couplings (finest level)
+    double* w_lift = nullptr;     // lifted right-hand side on the grid, allocated on first use
     double* partials = nullptr;
     unsigned* counter = nullptr;
     double* scal = nullptr;
@@ -480,6 +482,25 @@ int build_mesh(pmg_mesh* m) {
             if ((rc = m->upload(&dd, ma))) return rc;
             m->m1d[d] = const_cast<double*>(dd);
         }
+        // lifting of Dirichlet data: coupling of node k of the first (last)
+        // element with the line's end node 0 (N - 1), over the assembled mass
+        std::vector<double> Ls, tab(6 * (m->p + 1), 0.0);
+        stiffness_std(m->p, x, w, Ls);
+        const int n1 = m->p + 1;
+        for (int d = 0; d < 3; ++d) {
+            std::vector<double> ma(Lf.N[d], 0.0);
+            for (int e = 0; e < m->n[d]; ++e)
+                for (int i = 0; i <= m->p; ++i) ma[e * m->p + i] += 0.5 * m->h[d][e] * w[i];
+            const double h0 = m->h[d][0], hl = m->h[d][m->n[d] - 1];
+            const int off = Lf.N[d] - 1 - m->p;
+            for (int k = 0; k <= m->p; ++k) {
+                tab[(2 * d) * n1 + k] = (2.0 / h0) * Ls[k * n1 + 0] / ma[k];
+                tab[(2 * d + 1) * n1 + k] = (2.0 / hl) * Ls[k * n1 + m->p] / ma[off + k];
+            }
+        }
+        const double* dt = nullptr;
+        if ((rc = m->upload(&dt, tab))) return rc;
+        m->lift_tab = const_cast<double*>(dt);
     }
     if ((rc = m->alloc(&m->partials, 2 * REDUCE_BLOCKS)) || (rc = m->alloc(&m->counter, 4)) ||
         (rc = m->alloc(&m->scal, SC_N)))
@@ -1219,6 +1240,42 @@ int pmg_pcg_solve(pmg_mesh* m, const double* f, double* u, double rtol, int maxi
 
 int pmg_mg_solve(pmg_mesh* m, const double* f, double* u, double rtol, int maxit, pmg_stats* st, void* stream) {
     return solve_common(m, f, u, rtol, maxit, 1, PMG_F64, st, S(stream));
+}
+
+int pmg_lift_dirichlet(pmg_mesh* m, const double* f, const double* g, double* out, void* stream) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (!f || !g || !out) return fail(PMG_EINVAL, "null pointer");
+    if (out == g) return fail(PMG_EINVAL, "out must not alias g");
+    launch_lift_dirichlet(m->lv.back().lay.N, m->p, m->lift_tab, f, g, out, S(stream));
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int pmg_set_boundary(pmg_mesh* m, const double* g, double* u, void* stream) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (!g || !u) return fail(PMG_EINVAL, "null pointer");
+    launch_set_boundary(m->lv.back().lay.N, g, u, S(stream));
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+int pmg_pcg_solve_dirichlet(pmg_mesh* m, const double* f, const double* g, double* u, double rtol, int maxit,
+                            int pdt, pmg_stats* st, void* stream) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (!f || !g || !u) return fail(PMG_EINVAL, "null pointer");
+    if (u == g) return fail(PMG_EINVAL, "u must not alias g");
+    const int* N = m->lv.back().lay.N;
+    int rc;
+    if (!m->w_lift && (rc = m->alloc(&m->w_lift, (size_t)N[0] * N[1] * N[2]))) return rc;
+    const hipStream_t s = S(stream);
+    launch_lift_dirichlet(N, m->p, m->lift_tab, f, g, m->w_lift, s);
+    HIPCHK(hipGetLastError());
+    rc = solve_common(m, m->w_lift, u, rtol, maxit, 0, pdt, st, s);
+    if (rc < 0) return rc;
+    launch_set_boundary(N, g, u, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return rc;
 }
 
 int pmg_mlp_nparams(int nout) { return 64 * 3 + 64 + 64 * 64 + 64 + nout * 64 + nout; }

@@ -53,6 +53,11 @@ template <typename T> size_t smem_smoother(int p);
 void launch_condense(const LevelTabs<double>& tb, const double* m1, const double* m2, const double* m3,
                      const double* f, double* Fh, hipStream_t);
 void launch_recover(const LevelTabs<double>& tb, const double* f, const double* uh, double* ug, hipStream_t);
+// out = f - M^-1 H G on inner grid nodes, 0 on the boundary (G = g on the
+// boundary, 0 inside); tab: [3][2][p + 1] 1D end couplings over the mass
+void launch_lift_dirichlet(const int N[3], int p, const double* tab, const double* f, const double* g,
+                           double* out, hipStream_t);
+void launch_set_boundary(const int N[3], const double* g, double* u, hipStream_t);
 void launch_pcg_dir(double* p, const double* z, const double* sc, int64_t n, hipStream_t);
 void launch_pcg_update(double* u, double* r, double* s, const double* p, const double* q, const double* gam,
                        const double* qp, int64_t n, double* partials, unsigned* counter, double* out,

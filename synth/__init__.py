@@ -16,6 +16,7 @@ inhomogeneous Dirichlet data on (0, 2 pi)^3):
 """
 from __future__ import annotations
 
+import itertools
 import math
 
 import numpy as np
@@ -55,6 +56,37 @@ def sine_solution(k, a, lengths, x1, x2, x3, lam, xp=np):
         u = u + float(a[m]) * s
         f = f + float(a[m]) * (lam + kk) * s
     return u, f
+
+
+def paper_test_solution(k, lam, x1, x2, x3):
+    """Manufactured solution of the paper's runtime tests (Sec. 5.2) and its
+    right-hand side f = lam u - Laplace u, on broadcastable coordinates.
+
+    u = cos(k(x1 - 3x2 + 2x3)) sin(k(1 + x1)) sin(k(1 - x2)) sin(k(2x1 + x2))
+        sin(k(3x1 - 2x2 + 2x3)); the paper poses it on (0, 2 pi)^3 with k = 5,
+    lam = 0 and its values as Dirichlet data on the whole boundary.  Each
+    factor is written as two complex exponentials, so u is a sum of 32
+    plane waves exp(i (K.x + B)) and Laplace u multiplies each by -|K|^2.
+    """
+    # (wave vector / k, phase / k, cosine?) of the five factors
+    factors = [((1.0, -3.0, 2.0), 0.0, True), ((1.0, 0.0, 0.0), 1.0, False),
+               ((0.0, -1.0, 0.0), 1.0, False), ((2.0, 1.0, 0.0), 0.0, False),
+               ((3.0, -2.0, 2.0), 0.0, False)]
+    u = 0.0
+    lap = 0.0
+    for signs in itertools.product((1.0, -1.0), repeat=5):
+        K = np.zeros(3)
+        B = 0.0
+        c = 1.0 + 0.0j
+        for (a, b, is_cos), s in zip(factors, signs):
+            K = K + s * k * np.asarray(a)
+            B += s * k * b
+            c *= 0.5 if is_cos else s / 2.0j
+        wave = c * np.exp(1j * (K[0] * x1 + K[1] * x2 + K[2] * x3 + B))
+        u = u + wave
+        lap = lap - float(K @ K) * wave
+    u, lap = np.real(u), np.real(lap)
+    return u, lam * u - lap
 
 
 def stretched_widths(n, alpha, length=1.0):

@@ -98,3 +98,29 @@ def test_spectral_convergence_trig_solution():
         errs.append(np.max(np.abs(res.u - u)))
     assert errs[0] > 20 * errs[1] > 400 * errs[2]
     assert errs[2] < 1e-5
+
+
+def test_paper_test_solution_generator():
+    """The manufactured solution of Sec. 5.2: the plane-wave sum equals the
+    product of the five factors, and its Laplacian matches a fourth-order
+    finite-difference Laplacian at random points."""
+    import synth
+    rng = np.random.default_rng(8)
+    x = rng.uniform(0.0, 2 * np.pi, size=(3, 50))
+    for k in (1.0, 5.0):
+        u, f = synth.paper_test_solution(k, 0.0, x[0], x[1], x[2])
+        prod = (np.cos(k * (x[0] - 3 * x[1] + 2 * x[2])) * np.sin(k * (1 + x[0]))
+                * np.sin(k * (1 - x[1])) * np.sin(k * (2 * x[0] + x[1]))
+                * np.sin(k * (3 * x[0] - 2 * x[1] + 2 * x[2])))
+        assert np.max(np.abs(u - prod)) < 1e-13
+        h = 1e-3 / k
+        lap = 0.0
+        for d in range(3):
+            def at(s):
+                y = x.copy()
+                y[d] += s * h
+                return synth.paper_test_solution(k, 0.0, y[0], y[1], y[2])[0]
+            lap = lap + (-at(2) + 16 * at(1) - 30 * u + 16 * at(-1) - at(-2)) / (12 * h * h)
+        assert np.max(np.abs(-lap - f)) < 1e-6 * np.max(np.abs(f))
+        _, f2 = synth.paper_test_solution(k, 3.0, x[0], x[1], x[2])
+        assert np.allclose(f2, 3.0 * u + f, rtol=0, atol=1e-12 * np.max(np.abs(f)))
