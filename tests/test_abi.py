@@ -63,6 +63,9 @@ def test_null_handles_and_pointers(lib):
     assert lib.pmg_schwarz_smooth(None, 0, 0, None, None, 1.0, None) == -1
     assert lib.pmg_vcycle(None, 0, None, None, None) == -1
     assert lib.pmg_pcg_solve(None, None, None, 1e-10, 10, 0, None, None) == -1
+    assert lib.pmg_pcg_solve_dirichlet(None, None, None, None, 1e-10, 10, 0, None, None) == -1
+    assert lib.pmg_lift_dirichlet(None, None, None, None, None) == -1
+    assert lib.pmg_set_boundary(None, None, None, None) == -1
     assert lib.pmg_set_cycle(None, 0, 1e-8, 10) == -1
     lib.pmg_destroy_mesh(None)                    # no-op
 
