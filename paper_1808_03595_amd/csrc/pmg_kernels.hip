@@ -3596,7 +3596,8 @@ template <typename T, typename TC>
 void launch_prolong_add(const Layout& Lc, const Layout& Lf, const T* J, const TC* uc, T* uf, hipStream_t st) {
     const dim3 g = plane_grid(Lf, max_cols(Lf), max_rows(Lf)), b(64, 4);
 #define PMG_PRO(A, B) hipLaunchKernelGGL((k_prolong_direct<T, TC, A, B>), g, b, 0, st, Lc, Lf, J, uc, uf)
-    if (Lf.p == 4 && Lc.p == 2) PMG_PRO(4, 2);
+    if (Lf.p == 2 && Lc.p == 1) PMG_PRO(2, 1);
+    else if (Lf.p == 4 && Lc.p == 2) PMG_PRO(4, 2);
     else if (Lf.p == 8 && Lc.p == 4) PMG_PRO(8, 4);
     else if (Lf.p == 16 && Lc.p == 8) PMG_PRO(16, 8);
     else {
@@ -3619,7 +3620,8 @@ void launch_restrict(const Layout& Lf, const Layout& Lc, const T* J, const T* rf
         hipLaunchKernelGGL((k_restrict_rows<T, A, B>), g1, b, 0, st, Lc, Lf, J, rf, Y);                 \
         hipLaunchKernelGGL((k_restrict_cols<T, A, B>), g2, b, 0, st, Lc, Lf, J, (const T*)Y, tbuf);     \
     } while (0)
-    if (Lf.p == 4 && Lc.p == 2) PMG_RES(4, 2);
+    if (Lf.p == 2 && Lc.p == 1) PMG_RES(2, 1);
+    else if (Lf.p == 4 && Lc.p == 2) PMG_RES(4, 2);
     else if (Lf.p == 8 && Lc.p == 4) PMG_RES(8, 4);
     else if (Lf.p == 16 && Lc.p == 8) PMG_RES(16, 8);
     else PMG_RES(0, 0);
