@@ -28,6 +28,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -219,6 +220,55 @@ def p_sweep(torch, pmg, synth, dev, coarse_rtol, steps):
     return out
 
 
+NSWEEP = (8, 16, 24, 32, 40)
+
+
+def n_sweep(torch, pmg, synth, dev, coarse_rtol, steps):
+    """Runtime versus the number of unknowns (the linear-scaling claim,
+    Sec. 5.2): the paper's runtime test problem on (0, 2 pi)^3 (manufactured
+    solution with k = 5, lambda = 0, its values as inhomogeneous Dirichlet
+    data on the whole boundary), p = 8 on n^3 uniform elements, plain FP64
+    and mixed precision with the learned damping, one whole solve each after
+    one warm-up."""
+    out = []
+    p = 8
+    for nn in NSWEEP:
+        h = [2.0 * math.pi / nn] * nn
+        g = pmg.create_mesh_widths(h, h, h, p, 0.0)
+        g.set_cycle(0, coarse_rtol, 5000)
+        L = g.num_levels()
+        x1, x2, x3 = (torch.tensor(c, dtype=torch.float64, device=dev) for c in g.grid_coords())
+        u_ex, f = synth.paper_test_solution(5.0, 0.0, x1[None, None, :], x2[None, :, None],
+                                            x3[:, None, None], xp=torch)
+        u_ex, f = u_ex.contiguous(), f.contiguous()
+        u = torch.zeros_like(f)
+        ndof = nn ** 3 * p ** 3
+        row = {"n": nn, "p": p, "ndof": ndof}
+        omega = learned_damping(dict(n=(nn, nn, nn), p=p, lam=0.0, alpha=1.0), L)
+        for name, dtype, om in (("fp64", pmg.F64, None), ("mixed_learned", pmg.F32, omega)):
+            g.set_damping(om)
+            g.pcg_solve_dirichlet(f, u_ex, u, 1e-10, 300, dtype)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                st = g.pcg_solve_dirichlet(f, u_ex, u, 1e-10, 300, dtype)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            err = (u - u_ex).abs().max().item()
+            row[name] = {"ms": dt * 1e3, "iters": st.iters, "ns_per_unknown": dt * 1e9 / ndof,
+                         "ns_per_unknown_iter": dt * 1e9 / ndof / max(st.iters, 1),
+                         "coarse_iters": st.coarse_iters, "rel_res": st.rel_res,
+                         "max_err_vs_exact": err, "status": st.status}
+        log(f"[bench] n sweep n={nn} ({ndof / 1e6:.1f}M unknowns): fp64 {row['fp64']['ms']:.1f} ms "
+            f"({row['fp64']['iters']} it), mixed+learned {row['mixed_learned']['ms']:.1f} ms "
+            f"({row['mixed_learned']['iters']} it)")
+        out.append(row)
+        g.close()
+        del u, f, u_ex
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +289,8 @@ def main():
     ap.add_argument("--copy-only", action="store_true",
                     help="run one 512 MiB device copy (scale of the byte counters)")
     ap.add_argument("--no-sweep", action="store_true", help="skip the p sweep at 1e7 unknowns")
+    ap.add_argument("--no-nsweep", action="store_true",
+                    help="skip the sweep over the unknown count (the paper's test problem, p = 8)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -334,6 +386,9 @@ def main():
     if not args.no_sweep:
         g.close()
         sweep = p_sweep(torch, pmg, synth, dev, args.coarse_rtol, 1)
+    nsweep = None
+    if not args.no_nsweep and not args.no_sweep:
+        nsweep = n_sweep(torch, pmg, synth, dev, args.coarse_rtol, 1)
 
     line = {
         "metric": "solved unknowns/s to 1e-10 residual vs p; FP32-MG+learned vs plain FP64",
@@ -364,6 +419,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "p_sweep": sweep,
+        "n_sweep": nsweep,
     }
     print(json.dumps(line), flush=True)
 

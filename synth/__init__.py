@@ -58,15 +58,19 @@ def sine_solution(k, a, lengths, x1, x2, x3, lam, xp=np):
     return u, f
 
 
-def paper_test_solution(k, lam, x1, x2, x3):
+def paper_test_solution(k, lam, x1, x2, x3, xp=np):
     """Manufactured solution of the paper's runtime tests (Sec. 5.2) and its
-    right-hand side f = lam u - Laplace u, on broadcastable coordinates.
+    right-hand side f = lam u - Laplace u, on broadcastable coordinates
+    (``xp`` is numpy or torch).
 
     u = cos(k(x1 - 3x2 + 2x3)) sin(k(1 + x1)) sin(k(1 - x2)) sin(k(2x1 + x2))
         sin(k(3x1 - 2x2 + 2x3)); the paper poses it on (0, 2 pi)^3 with k = 5,
-    lam = 0 and its values as Dirichlet data on the whole boundary.  Each
-    factor is written as two complex exponentials, so u is a sum of 32
-    plane waves exp(i (K.x + B)) and Laplace u multiplies each by -|K|^2.
+    lam = 0 and its values as Dirichlet data on the whole boundary.  Writing
+    each factor as two complex exponentials makes u a sum of 32 plane waves
+    c_s exp(i (K_s.x + B_s)) over the sign choices s; the coefficients
+    c_s = prod(sine signs) / 32 are real and s, -s give conjugate waves, so
+    u = sum over 16 sign choices of 2 c_s cos(K_s.x + B_s), and Laplace u
+    multiplies each term by -|K_s|^2.
     """
     # (wave vector / k, phase / k, cosine?) of the five factors
     factors = [((1.0, -3.0, 2.0), 0.0, True), ((1.0, 0.0, 0.0), 1.0, False),
@@ -74,18 +78,19 @@ def paper_test_solution(k, lam, x1, x2, x3):
                ((3.0, -2.0, 2.0), 0.0, False)]
     u = 0.0
     lap = 0.0
-    for signs in itertools.product((1.0, -1.0), repeat=5):
-        K = np.zeros(3)
+    for rest in itertools.product((1.0, -1.0), repeat=4):
+        signs = (1.0,) + rest
+        K = [0.0, 0.0, 0.0]
         B = 0.0
-        c = 1.0 + 0.0j
+        c = 2.0 / 32.0
         for (a, b, is_cos), s in zip(factors, signs):
-            K = K + s * k * np.asarray(a)
+            K = [K[i] + s * k * a[i] for i in range(3)]
             B += s * k * b
-            c *= 0.5 if is_cos else s / 2.0j
-        wave = c * np.exp(1j * (K[0] * x1 + K[1] * x2 + K[2] * x3 + B))
+            if not is_cos:
+                c *= s
+        wave = c * xp.cos(K[0] * x1 + K[1] * x2 + K[2] * x3 + B)
         u = u + wave
-        lap = lap - float(K @ K) * wave
-    u, lap = np.real(u), np.real(lap)
+        lap = lap - (K[0] ** 2 + K[1] ** 2 + K[2] ** 2) * wave
     return u, lam * u - lap
 
 
