@@ -4,6 +4,8 @@
  *
  *        lambda u - Laplace(u) = f   on a box,  u = 0 on the boundary,
  *
+ * (inhomogeneous boundary values u = g by lifting: pmg_pcg_solve_dirichlet),
+ *
  * after Huismann, Stiller & Froehlich, "Scaling to the stars -- a linearly
  * scaling elliptic solver for p-multigrid" (arXiv 1808.03595).
  *
