@@ -457,12 +457,11 @@ int build_mesh(pmg_mesh* m) {
     // batched condensation / recovery workspaces on the finest level
     if (m->p >= 9) {
         Level& F = m->lv.back();
-        const int q = m->p - 1, n1 = m->p + 1, qp = 16 * ((q + 15) / 16);
+        const int q = m->p - 1, qp = 16 * ((q + 15) / 16);
         const size_t ne = (size_t)m->n[0] * m->n[1] * m->n[2];
         F.t64.qp = qp;
         for (int k = 0; k < 2; ++k)
             if ((rc = m->alloc(&F.t64.ixX[k], ne * qp * qp * qp))) return rc;
-        (void)n1;   // the per-element middle steps run batched over faces (no face scratch: ixS stays null)
     }
     const Layout& Lf = m->lv.back().lay;
     int64_t nf = Lf.len;

@@ -84,10 +84,8 @@ struct LevelTabs {
     // two [star][3][np][np] workspaces of the batched star smoother (nS > 16)
     T* sbX[2];
     // batched condensation / recovery (finest level, p >= 9): two
-    // [element][qp^3] arrays, qp = 16 ceil((p-1) / 16), and per-element
-    // scratch for the face parts when they exceed the LDS
+    // [element][qp^3] arrays, qp = 16 ceil((p-1) / 16)
     double* ixX[2];
-    double* ixS;
     int qp;
 };
 
