@@ -1890,33 +1890,38 @@ __device__ inline int plane_family(const Layout& L, int z, int& j) {
 }
 
 // uf += P uc on every canonical, non-Dirichlet fine node, separably (any
-// degree pair): one thread per fine column gc of one element row Er of a
-// plane forms the pc + 1 column interpolations of the element's coarse rows
-// once (in LDS), then each fine row of the element takes its (pc + 1)-term
-// row interpolation: 2 (pc + 1) operations per fine node instead of
-// (pc + 1)^2.  Element Er writes its rows 0..pf-1, the last element also
+// degree pair): four threads per fine column gc of one element row Er of a
+// plane form the pc + 1 column interpolations of the element's coarse rows
+// once (in LDS, split over the four), then each fine row of the element
+// (rows split over the four) takes its (pc + 1)-term row interpolation:
+// 2 (pc + 1) operations per fine node instead of (pc + 1)^2.  Element Er writes its rows 0..pf-1, the last element also
 // row pf (a boundary row interpolates to the same value from either side).
 template <typename T, typename TC>
-__global__ void __launch_bounds__(64) k_prolong_sep(Layout Lc, Layout Lf, const T* __restrict__ J,
-                                                    const TC* __restrict__ uc, T* __restrict__ uf) {
+__global__ void __launch_bounds__(256) k_prolong_sep(Layout Lc, Layout Lf, const T* __restrict__ J,
+                                                     const TC* __restrict__ uc, T* __restrict__ uf) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int j;
     const int d = plane_family(Lf, blockIdx.z, j);
     const int pf = Lf.p, pc = Lc.p, nc1 = pc + 1;
     const int dr = d == 2 ? 1 : 2, dc = d == 0 ? 1 : 0;
-    const int Er = blockIdx.y, gc = blockIdx.x * 64 + threadIdx.x;
-    if (Er >= Lf.n[dr] || gc >= Lf.N[dc]) return;
-    T* t = reinterpret_cast<T*>(smem_raw) + threadIdx.x * nc1;
-    const int Ec = min(gc / pf, Lf.n[dc] - 1), lc = gc - Ec * pf;
-    for (int R = 0; R < nc1; ++R) {
-        T a = 0;
-        for (int C = 0; C < nc1; ++C)
-            a += J[lc * nc1 + C] * coarse_plane_value<T>(Lc, uc, d, j, Er * pc + R, Ec * pc + C, pc);
-        t[R] = a;
-    }
+    const int Er = blockIdx.y, tx = threadIdx.x, ty = threadIdx.y, gc = blockIdx.x * 64 + tx;
+    if (Er >= Lf.n[dr]) return;   // uniform over the workgroup
+    const bool col = gc < Lf.N[dc];
+    // the four threads (ty) of a column share its pc + 1 column interpolations
+    T* t = reinterpret_cast<T*>(smem_raw) + tx * nc1;
+    const int Ec = col ? min(gc / pf, Lf.n[dc] - 1) : 0, lc = gc - Ec * pf;
+    if (col)
+        for (int R = ty; R < nc1; R += 4) {
+            T a = 0;
+            for (int C = 0; C < nc1; ++C)
+                a += J[lc * nc1 + C] * coarse_plane_value<T>(Lc, uc, d, j, Er * pc + R, Ec * pc + C, pc);
+            t[R] = a;
+        }
+    __syncthreads();
+    if (!col) return;
     const bool col_ok = d == 0 || gc % pf != 0;
     const int last = Er == Lf.n[dr] - 1 ? pf : pf - 1;
-    for (int lr = 0; lr <= last; ++lr) {
+    for (int lr = ty; lr <= last; lr += 4) {
         const int gr = Er * pf + lr;
         int g[3];
         g[d] = j * pf;
@@ -3604,7 +3609,8 @@ void launch_prolong_add(const Layout& Lc, const Layout& Lf, const T* J, const TC
         int mr = 0;
         for (int dd = 0; dd < 3; ++dd) mr = std::max(mr, Lf.n[dd]);
         const dim3 gs((max_cols(Lf) + 63) / 64, mr, Lf.n[0] + Lf.n[1] + Lf.n[2] + 3);
-        hipLaunchKernelGGL((k_prolong_sep<T, TC>), gs, dim3(64), sizeof(T) * 64 * (Lc.p + 1), st, Lc, Lf, J, uc, uf);
+        hipLaunchKernelGGL((k_prolong_sep<T, TC>), gs, dim3(64, 4), sizeof(T) * 64 * (Lc.p + 1), st, Lc, Lf, J, uc,
+                           uf);
     }
 #undef PMG_PRO
 }
