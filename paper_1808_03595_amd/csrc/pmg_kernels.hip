@@ -3774,8 +3774,8 @@ __global__ void k_lift_dirichlet(int N1, int N2, int N3, int p, const double* __
     out[i] = f[i] - acc;   // f may alias out: each thread reads only its own f[i]
 }
 
-// u = g on the boundary nodes; inner nodes untouched.
-__global__ void k_set_boundary(int N1, int N2, int N3, const double* __restrict__ g, double* __restrict__ u) {
+// u = g on the boundary nodes; inner nodes untouched (g may alias u).
+__global__ void k_set_boundary(int N1, int N2, int N3, const double* g, double* u) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)N1 * N2 * N3) return;
     const int i1 = (int)(i % N1);
