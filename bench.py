@@ -161,6 +161,23 @@ def cpu_baseline(wl, coarse_rtol):
     return dict(t=time.perf_counter() - t0, iters=res.iters, threads=threads)
 
 
+def coarse_levels(p, alpha, ne):
+    """Degree-1 levels below p_0 = 2 (Sec. 4.2's low-order coarse grid) for
+    degree p, stretching alpha and ne elements.
+
+    Measured on one MI355X (whole solves to 1e-10): at p <= 4 the coarse
+    problem is most of the mesh and six levels win.  At p = 8 one level wins
+    on uniform meshes of 16^3 elements or more (the paper's test problem at
+    16^3..40^3 elements: 1.2-2.1x; the p = 8 sweep point: 1.28x) and loses on
+    8^3 elements and on the stretched default workload (aspect ratio 8: 7 ->
+    10 outer iterations).  At p >= 12 (meshes of 18^3 elements or fewer in
+    the sweep, deeper p-hierarchies) it loses 0-25 %.
+    """
+    if p <= 4:
+        return 6
+    return 1 if (p <= 8 and alpha == 1.0 and ne >= 16 ** 3) else 0
+
+
 def learned_damping(wl, L):
     """omega predicted by the trained network for this mesh, or None."""
     import synth
@@ -187,9 +204,9 @@ def p_sweep(torch, pmg, synth, dev, coarse_rtol, steps):
         wl = dict(n=(nn, nn, nn), p=p, lam=1.0, alpha=1.0, seed=0)
         g = pmg.create_mesh(nn, nn, nn, p, 1.0, 1.0)
         g.set_cycle(0, coarse_rtol, 5000)
-        # at p <= 4 the coarse problem is most of the mesh: the CG on it grows
-        # like n_e^(4/3) (Sec. 4.2), so degree-1 levels go below it there
-        hmg = 6 if p <= 4 else 0
+        # the CG on the coarse problem grows like n_e^(4/3) (Sec. 4.2), so
+        # degree-1 levels go below it
+        hmg = coarse_levels(p, 1.0, nn ** 3)
         if hmg:
             g.set_coarse_mg(hmg, 0.8, 2)
         L = g.num_levels()
@@ -236,6 +253,8 @@ def n_sweep(torch, pmg, synth, dev, coarse_rtol, steps):
         h = [2.0 * math.pi / nn] * nn
         g = pmg.create_mesh_widths(h, h, h, p, 0.0)
         g.set_cycle(0, coarse_rtol, 5000)
+        hmg = coarse_levels(p, 1.0, nn ** 3)
+        g.set_coarse_mg(hmg, 0.8, 2)
         L = g.num_levels()
         x1, x2, x3 = (torch.tensor(c, dtype=torch.float64, device=dev) for c in g.grid_coords())
         u_ex, f = synth.paper_test_solution(5.0, 0.0, x1[None, None, :], x2[None, :, None],
@@ -243,7 +262,8 @@ def n_sweep(torch, pmg, synth, dev, coarse_rtol, steps):
         u_ex, f = u_ex.contiguous(), f.contiguous()
         u = torch.zeros_like(f)
         ndof = nn ** 3 * p ** 3
-        row = {"n": nn, "p": p, "ndof": ndof}
+        row = {"n": nn, "p": p, "ndof": ndof,
+               "coarse": f"{hmg} degree-1 level(s) + CG" if hmg else "CG on p_0 = 2"}
         omega = learned_damping(dict(n=(nn, nn, nn), p=p, lam=0.0, alpha=1.0), L)
         for name, dtype, om in (("fp64", pmg.F64, None), ("mixed_learned", pmg.F32, omega)):
             g.set_damping(om)
@@ -281,7 +301,7 @@ def main():
     ap.add_argument("--damping", choices=["learned", "one"], default="learned")
     ap.add_argument("--hmg-levels", type=int, default=None,
                     help="degree-1 levels below p_0 (0: the paper's CG on p_0 = 2; "
-                         "default 6 at p <= 4 as in the p sweep, else 0)")
+                         "default: 6 at p <= 4; 1 at p <= 8 on uniform meshes of >= 16^3 elements; else 0)")
     ap.add_argument("--hmg-omega", type=float, default=0.8)
     ap.add_argument("--hmg-nu", type=int, default=2)
     ap.add_argument("--kernel-only", action="store_true",
@@ -319,7 +339,7 @@ def main():
         log(f"[bench] {ROOFLINE_KERNEL}: {t * 1e6:.2f} us per launch")
         return
     g.set_cycle(0, args.coarse_rtol, 2000)
-    hmg = args.hmg_levels if args.hmg_levels is not None else (6 if p <= 4 else 0)
+    hmg = args.hmg_levels if args.hmg_levels is not None else coarse_levels(p, wl["alpha"], n[0] * n[1] * n[2])
     if hmg:
         g.set_coarse_mg(hmg, args.hmg_omega, args.hmg_nu)
     u_ex, f = make_rhs(g, wl, torch, synth, dev)

@@ -45,3 +45,14 @@ def test_smoother_kernel_names():
     assert bench.smoother_kernel(2, "float") == "k_smoother_small<float, 3>"
     assert bench.smoother_kernel(4, "double") == "k_smoother_small<double, 8>"
     assert bench.smoother_kernel(8, "float") == "k_smoother_mfma<float, 1>"
+
+
+def test_coarse_level_policy():
+    """Degree-1 levels below p_0: six at p <= 4; one at 4 < p <= 8 on uniform
+    meshes of at least 16^3 elements; none otherwise (the default stretched
+    workload, small meshes, p >= 12)."""
+    assert bench.coarse_levels(2, 1.0, 8) == 6 and bench.coarse_levels(4, 1.3, 4096) == 6
+    assert bench.coarse_levels(8, 1.0, 16 ** 3) == 1 and bench.coarse_levels(8, 1.0, 40 ** 3) == 1
+    assert bench.coarse_levels(8, 1.0, 8 ** 3) == 0 and bench.coarse_levels(12, 1.0, 40 ** 3) == 0
+    wl = bench.workload("c2a")
+    assert bench.coarse_levels(8, wl["alpha"], 16 ** 3) == 0
