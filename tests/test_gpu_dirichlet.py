@@ -161,3 +161,28 @@ def test_paper_test_problem_full_size(gpu):
     assert st.status == 0 and st.rel_res <= 1e-10
     err = np.max(np.abs(u.cpu().numpy() - u_ex))
     assert err <= 1e-6, err
+
+
+@pytest.mark.parametrize("precond", ["f64", "f32"])
+def test_dirichlet_solve_with_degree1_coarse_level(gpu, precond):
+    """The sweep's configuration at p = 8 on uniform meshes (one degree-1
+    level below p_0 = 2, CG on it): the lifted solve reaches the same discrete
+    solution as with the CG on p_0 = 2, on the paper's test problem."""
+    n, p = 16, 8
+    widths = tuple(np.full(n, 2 * np.pi / n) for _ in range(3))
+    o = omesh.Mesh(widths[0], widths[1], widths[2], p, 0.0)
+    X3, X2, X1 = o.coords()
+    u_ex, f = synth.paper_test_solution(5.0, 0.0, X1, X2, X3)
+    fd, gd = _dev(f, gpu), _dev(u_ex, gpu)
+    dt = pmg.F64 if precond == "f64" else pmg.F32
+    sols = []
+    for levels in (0, 1):
+        g = pmg.create_mesh_widths(widths[0], widths[1], widths[2], p, 0.0)
+        g.set_cycle(0, 3e-2, 5000)
+        g.set_coarse_mg(levels, 0.8, 2)
+        u = torch.zeros(o.shape, dtype=torch.float64, device=gpu)
+        st = g.pcg_solve_dirichlet(fd, gd, u, 1e-11, 100, dt)
+        assert st.status == 0 and st.rel_res <= 1e-11
+        sols.append(u.cpu().numpy())
+        g.close()
+    assert rel(sols[1], sols[0]) <= 1e-9
