@@ -106,7 +106,7 @@ int pmg_apply_condensed_op(pmg_mesh *m, int level, int dtype, const void *d_u,
 
 /* du = omega * Smoother_l(r): the additive Schwarz star smoother of Alg. 2
  * with the star inverse of Alg. 1 and the degree-7 weight functions of
- * Sec. 3.3; omega = 1 is the paper's method.  d_r, d_du: skeleton arrays of
+ * Sec. 3.2; omega = 1 is the paper's method.  d_r, d_du: skeleton arrays of
  * the level (dtype), not aliasing.  d_du is overwritten. */
 int pmg_schwarz_smooth(pmg_mesh *m, int level, int dtype, const void *d_r,
                        void *d_du, double omega, void *stream);
@@ -191,7 +191,7 @@ int pmg_pcg_solve(pmg_mesh *m, const double *d_f, double *d_u, double rtol,
 int pmg_mg_solve(pmg_mesh *m, const double *d_f, double *d_u, double rtol,
                  int maxit, pmg_stats *h_stats, void *stream);
 
-/* ---- inhomogeneous Dirichlet data (Sec. 3.4, Sec. 5.2) ------------------
+/* ---- inhomogeneous Dirichlet data (Sec. 3.3, Sec. 5.2) ------------------
  * The paper's boundary treatment keeps Dirichlet values fixed while every
  * correction vanishes there, and its runtime test problem prescribes them
  * on the whole boundary.  They enter by lifting: with G = g on the boundary

@@ -13,7 +13,7 @@ Layout of the package:
 
 * ``sem1d``   -- GLL basis, 1D mass/stiffness, generalized eigenpairs,
                  Lagrange interpolation, the degree-7 weight polynomial
-                 (Sec. 2.1, eq. (helmholtzop); Sec. 3.4 weight functions).
+                 (Sec. 2.1, eq. (helmholtzop); Sec. 3.2 weight functions).
 * ``mesh``    -- Cartesian element meshes, node grids, skeleton index sets.
 * ``dense``   -- dense assembly of H, its Schur complement and the star
                  operators on tiny meshes (plain definitions, Sec. 2.2/2.3).
@@ -23,7 +23,7 @@ Layout of the package:
 * ``solver``  -- V-cycle (Alg. 3), MG solver (Alg. 4), ipCG (Alg. 5), the
                  coarse CG, the mixed-precision preconditioner form.
 * ``mlp``     -- the damping-weight MLP: forward, analytic backward, Adam.
-* ``dirichlet`` -- inhomogeneous Dirichlet data by lifting (Sec. 3.4
+* ``dirichlet`` -- inhomogeneous Dirichlet data by lifting (Sec. 3.3
                  boundary treatment, Sec. 5.2 test problem) and its dense
                  brute-force solve.
 

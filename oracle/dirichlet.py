@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY, like the rest of this package.
 
 The paper's runtime test problem (Sec. 5.2, the manufactured solution on
 (0, 2 pi)^3) prescribes inhomogeneous Dirichlet values on the whole
-boundary, and its boundary treatment (Sec. 3.4) keeps Dirichlet values
+boundary, and its boundary treatment (Sec. 3.3) keeps Dirichlet values
 fixed while every correction vanishes there.  The discrete problem is:
 u = g on the boundary nodes D, and on the free nodes f the rows of
 H u = M f hold, i.e.

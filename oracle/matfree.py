@@ -12,8 +12,8 @@ Passages followed:
 * star inverse, Alg. 1 (Sec. 3.2) -- the tensor-product inverse in the
   condensed system (TPC) -- together with the full-star fast
   diagonalization (TPF, eq. fast_diagonalization) as a second route;
-* Schwarz smoother, Alg. 2 with the weight functions of Sec. 3.3 and the
-  boundary treatment by identity padding of Sec. 3.4;
+* Schwarz smoother, Alg. 2 with the weight functions of Sec. 3.2 and the
+  boundary treatment by identity padding of Sec. 3.3;
 * grid transfers: embedded tensor-product interpolation restricted to the
   condensed system, restriction = transpose (Sec. 4.1);
 * static condensation of the right-hand side and interior recovery
@@ -197,7 +197,7 @@ def star_tables_1d(hs, p, v):
     the outer ends +-p are dropped (homogeneous local problem), leaving
     n_S = 2p-1 positions.  Positions outside the domain (ghost element) and
     a Dirichlet vertex are decoupled: S = identity and eigenvalue 1 there,
-    the eigenpairs of the remaining block fill the rest (Sec. 3.4).
+    the eigenpairs of the remaining block fill the rest (Sec. 3.3).
     Returns (S, lam, coupled mask) with S^T M S = I, S^T L S = diag(lam) on
     the coupled block.
     """

@@ -6,7 +6,7 @@ Paper passages followed:
   on an element of width h the physical matrices are (h/2) M and (2/h) L.
 * Sec. 3.2 (fast diagonalization): generalized eigenpairs S^T L S = Lambda,
   S^T M S = I.
-* Sec. 3.3 (weight functions): polynomials of degree p_W that are one at the
+* Sec. 3.2 (weight functions): polynomials of degree p_W that are one at the
   star vertex, zero at the other vertex and have vanishing higher
   derivatives there (p_W = 7 in the paper).
 * Sec. 4.1: interpolation between polynomial degrees for the p-multigrid.
@@ -96,7 +96,9 @@ def standard_matrices(p: int):
     x, w = gll(p)
     D = diff_matrix(x)
     L = D.T @ np.diag(w) @ D
-    return w, L
+    # L is symmetric by definition; the FP64 product is so only to ~1e-14,
+    # and eigen solvers read one triangle of it
+    return w, 0.5 * (L + L.T)
 
 
 def element_matrices(p: int, h: float):
@@ -105,15 +107,53 @@ def element_matrices(p: int, h: float):
     return 0.5 * h * w, (2.0 / h) * L
 
 
+def _two_sum(a, b):
+    """s + e = a + b exactly (Knuth's TwoSum)."""
+    s = a + b
+    bb = s - a
+    return s, (a - (s - bb)) + (b - bb)
+
+
+def _two_prod(a, b):
+    """x + e = a b exactly (Dekker's TwoProduct, 64-bit significand)."""
+    f = np.longdouble(4294967297.0)          # 2^32 + 1 splits a longdouble
+    x = a * b
+    c = f * a
+    ah = c - (c - a)
+    al = a - ah
+    c = f * b
+    bh = c - (c - b)
+    bl = b - bh
+    return x, al * bl - (((x - ah * bh) - al * bh) - ah * bl)
+
+
+def _matmul2(A, B):
+    """A @ B with every entry summed as if in twice the working precision
+    (compensated dot product, Dot2 of Ogita, Rump & Oishi 2005)."""
+    S = np.zeros((A.shape[0], B.shape[1]), dtype=A.dtype)
+    C = np.zeros_like(S)
+    for k in range(A.shape[1]):
+        p, pe = _two_prod(A[:, k, None], B[None, k, :])
+        S, se = _two_sum(S, p)
+        C = C + (pe + se)
+    return S + C
+
+
 def gen_eig(L, M):
     """S, lam with S^T L S = diag(lam), S^T M S = I (M diagonal, positive).
 
-    The pairs are those of the symmetric A = M^-1/2 L M^-1/2 (S = M^-1/2 Q):
-    a LAPACK eigendecomposition of A in FP64, then cyclic Jacobi sweeps in
-    extended precision (numpy longdouble) on Q^T A Q until every
-    off-diagonal entry is negligible against its two diagonal entries.  At
-    large p the smallest eigenvalues are ~p^-4 of the largest, and an FP64
-    solver alone leaves them with relative errors near 1e-12.
+    The pairs are those of the symmetric A = M^-1/2 L M^-1/2 (S = M^-1/2 Q).
+    Route: a LAPACK eigendecomposition of A in FP64, then iterative
+    refinement of the whole decomposition by the method of Ogita & Aishima
+    (2018) in extended precision (numpy longdouble).  One step maps an
+    approximate eigenvector matrix X to X (I + E), where, with R = I - X^T X
+    and T = X^T A X, the eigenvalue estimates are t_ii / (1 - r_ii) and E
+    has diagonal r_ii / 2 and off-diagonal (t_ij + lam_j r_ij) /
+    (lam_j - lam_i); the error contracts quadratically.  The last step and
+    the final Rayleigh quotients form R and T with compensated products, so
+    that the small eigenvalues (~p^-4 of the largest at large p) come out
+    with relative, not only absolute, accuracy; an FP64 solver alone leaves
+    them with relative errors up to ~1e-11.
     """
     L = np.asarray(L, dtype=np.float64)
     M = np.asarray(M, dtype=np.float64)
@@ -126,29 +166,20 @@ def gen_eig(L, M):
     A = L.astype(X) / (ms[:, None] * ms[None, :])
     _, Q0 = scipy.linalg.eigh(A.astype(np.float64))
     Q = Q0.astype(X)
-    B = Q.T @ A @ Q
-    tol = 4 * np.finfo(X).eps
-    for _ in range(50):
-        rotated = False
-        for i in range(n - 1):
-            for j in range(i + 1, n):
-                bij = B[i, j]
-                if abs(bij) <= tol * np.sqrt(abs(B[i, i] * B[j, j])):
-                    continue
-                rotated = True
-                theta = (B[j, j] - B[i, i]) / (2 * bij)
-                t = (1 if theta >= 0 else -1) / (abs(theta) + np.sqrt(theta * theta + 1))
-                c = 1 / np.sqrt(t * t + 1)
-                s = t * c
-                bi, bj = B[i, :].copy(), B[j, :].copy()
-                B[i, :], B[j, :] = c * bi - s * bj, s * bi + c * bj
-                bi, bj = B[:, i].copy(), B[:, j].copy()
-                B[:, i], B[:, j] = c * bi - s * bj, s * bi + c * bj
-                qi, qj = Q[:, i].copy(), Q[:, j].copy()
-                Q[:, i], Q[:, j] = c * qi - s * qj, s * qi + c * qj
-        if not rotated:
-            break
-    lam = np.diag(B).copy()
+    eye = np.eye(n, dtype=X)
+    for step in range(3):
+        mm = _matmul2 if step == 2 else np.matmul
+        R = eye - mm(Q.T, Q)
+        T = mm(Q.T, mm(A, Q))
+        lam = np.diag(T) / (1 - np.diag(R))
+        gap = lam[None, :] - lam[:, None]            # lam_j - lam_i
+        np.fill_diagonal(gap, 1)
+        E = (T + lam[None, :] * R) / gap
+        np.fill_diagonal(E, np.diag(R) / 2)
+        Q = Q + Q @ E
+    AQ = _matmul2(A, Q)
+    lam = np.array([_matmul2(Q[:, i:i + 1].T, AQ[:, i:i + 1])[0, 0]
+                    / _matmul2(Q[:, i:i + 1].T, Q[:, i:i + 1])[0, 0] for i in range(n)])
     order = np.argsort(lam)
     S = Q[:, order] / ms[:, None]
     return S.astype(np.float64), lam[order].astype(np.float64)

@@ -158,42 +158,32 @@ class Hierarchy:
 
 
 def jacobi_pcg(apply, b, diag, rtol, maxit, log=None):
-    """Jacobi-preconditioned CG from x = 0 (Chronopoulos-Gear form).
+    """Jacobi-preconditioned conjugate gradients from x = 0 (textbook form).
 
-    The single-reduction form of preconditioned CG: per iteration one
-    operator application w = A z and the two inner products (r, z) and
-    (w, z) taken together; p and q = A p follow by recurrences.  In exact
-    arithmetic it produces the iterates of standard PCG.  Stops when
-    (r, D^-1 r) <= rtol^2 (b, D^-1 b) or after ``maxit`` updates of x.
+    Per iteration: q = A p, alpha = (r, z) / (p, q), x += alpha p,
+    r -= alpha q, z = D^-1 r, beta = (r, z)_new / (r, z)_old,
+    p = z + beta p.  Stops when (r, D^-1 r) <= rtol^2 (b, D^-1 b) or after
+    ``maxit`` updates of x.
     """
     x = np.zeros_like(b)
     r = np.array(b, dtype=np.float64)
     z = r / diag
-    w = apply(z)
-    gamma = dot(r, z)
-    delta = dot(w, z)
-    gamma0 = gamma
+    rz = dot(r, z)
+    rz0 = rz
+    p = z.copy()
     it = 0
-    if gamma > 0.0 and maxit > 0:
-        p, q = z.copy(), w.copy()
-        alpha = gamma / delta
-        while True:
-            x = x + alpha * p
-            r = r - alpha * q
-            it += 1
-            if it >= maxit:
-                break
-            z = r / diag
-            w = apply(z)
-            gamma_new = dot(r, z)
-            delta = dot(w, z)
-            if gamma_new <= (rtol * rtol) * gamma0:
-                break
-            beta = gamma_new / gamma
-            alpha = gamma_new / (delta - beta * gamma_new / alpha)
-            gamma = gamma_new
-            p = z + beta * p
-            q = w + beta * q
+    while rz > 0.0 and it < maxit:
+        q = apply(p)
+        alpha = rz / dot(p, q)
+        x = x + alpha * p
+        r = r - alpha * q
+        it += 1
+        z = r / diag
+        rz_new = dot(r, z)
+        if rz_new <= (rtol * rtol) * rz0:
+            break
+        p = z + (rz_new / rz) * p
+        rz = rz_new
     if log is not None:
         log.append(it)
     return x
@@ -259,23 +249,6 @@ def mg_solve(mesh: Mesh, Fhat, rtol=1e-10, maxit=200, hier=None, **hkw):
         hist.append(norm(r))
         it += 1
     return u, it, hist
-
-
-def mixed_precond(hier: Hierarchy):
-    """Mixed-precision preconditioner form: z = |r| up(M(down(r / |r|))).
-
-    The oracle rounds the scaled residual and the correction to float32
-    around an FP64 V-cycle; it reproduces the data flow, not the float32
-    arithmetic inside the cycle.
-    """
-    def M(r):
-        nr = norm(r)
-        if nr == 0.0:
-            return np.zeros_like(r)
-        r32 = (r / nr).astype(np.float32).astype(np.float64)
-        z = hier.vcycle(None, r32)
-        return nr * z.astype(np.float32).astype(np.float64)
-    return M
 
 
 def solve(mesh: Mesh, f_grid, method="kMG", rtol=1e-10, maxit=200, **hkw):

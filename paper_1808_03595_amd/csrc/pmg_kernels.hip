@@ -3740,7 +3740,7 @@ void launch_recover(const LevelTabs<double>& tb, const double* f, const double* 
 }
 
 // ---------------------------------------------------------------------------
-// Inhomogeneous Dirichlet data by lifting (Sec. 3.4 keeps boundary values
+// Inhomogeneous Dirichlet data by lifting (Sec. 3.3 keeps boundary values
 // fixed; the runtime test problem of Sec. 5.2 prescribes them on the whole
 // boundary).  With G = g on the boundary and 0 inside, u = u0 + G and u0
 // solves the homogeneous problem with f' = f - M^-1 H G.  On a Cartesian

@@ -3,7 +3,7 @@
 // GLL nodes/weights, the standard stiffness matrix, generalized eigenpairs
 // of (L, M) with a diagonal M, Lagrange interpolation and the weight
 // polynomial; then the per-level tables of elements (condensed operator,
-// Sec. 2.2), stars (Alg. 1, with the identity padding of Sec. 3.4) and the
+// Sec. 2.2), stars (Alg. 1, with the identity padding of Sec. 3.3) and the
 // transfer matrix (Sec. 4.1).
 #include <algorithm>
 #include <cmath>

@@ -27,10 +27,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "data", "damping_mlp.npz")
 
 
+def mlp_features(p, lam, hmin, ar):
+    """Scaled network inputs: (p/32, log10(1 + lambda h_min^2)/4, log2(AR)/4)."""
+    return np.array([p / 32.0, math.log10(1.0 + lam * hmin * hmin) / 4.0,
+                     math.log2(max(ar, 1.0)) / 4.0], dtype=np.float32)
+
+
 def mesh_features(p, lam, hx, hy, hz):
     """(p, lambda h_min^2, AR): h_min over all element widths, AR the largest
     element aspect ratio max(h) / min(h)."""
-    import synth
     hs = [np.asarray(h, dtype=np.float64) for h in (hx, hy, hz)]
     hmin = min(float(h.min()) for h in hs)
     ar = 1.0
@@ -38,7 +43,7 @@ def mesh_features(p, lam, hx, hy, hz):
         for b in hs[1]:
             for c in hs[2]:
                 ar = max(ar, max(a, b, c) / min(a, b, c))
-    return synth.mlp_features(p, lam, hmin, ar)
+    return mlp_features(p, lam, hmin, ar)
 
 
 def glorot(nout=NOUT, seed=0):

@@ -103,9 +103,3 @@ def anisotropic_widths(n, ar):
     """Uniform bricks on (0, AR) x (0, ceil(AR/2)/2) x (0, 1), n per direction."""
     lx, ly, lz = float(ar), math.ceil(ar / 2.0) / 2.0, 1.0
     return (np.full(n, lx / n), np.full(n, ly / n), np.full(n, lz / n)), (lx, ly, lz)
-
-
-def mlp_features(p, lam, hmin, ar):
-    """Scaled inputs of the damping MLP: (p/32, log10(1+lam h^2)/4, log2(AR)/4)."""
-    return np.array([p / 32.0, math.log10(1.0 + lam * hmin * hmin) / 4.0,
-                     math.log2(max(ar, 1.0)) / 4.0], dtype=np.float32)

@@ -195,14 +195,20 @@ def test_coarse_solve(gpu, case):
     assert it == 9
     diag = matfree.condensed_diagonal(o0)
     ref = solver.jacobi_pcg(lambda v: matfree.condensed_op(o0, v), b, diag, 0.0, 9)
-    assert rel(io.to_grid(x), ref) <= 1e-11
+    # the kernel runs the single-reduction recurrence of CG, the oracle the
+    # textbook one: the same iterates in exact arithmetic, rounding apart
+    assert rel(io.to_grid(x), ref) <= 1e-10
 
 
 @pytest.mark.parametrize("rtol,maxit", [(1e-6, 500), (1e-12, 25), (1e-3, 500)])
 def test_coarse_solve_to_tolerance(gpu, rtol, maxit):
     """Coarse CG stopped by its tolerance (or maxit) over several launch
-    chunks: same update count and solution as the oracle, on repeated calls
-    (the second call starts from the first one's chunk estimate)."""
+    chunks, on repeated calls (the second call starts from the first one's
+    chunk estimate).  The kernel's single-reduction recurrence and the
+    oracle's textbook CG take the same steps in exact arithmetic, so the
+    update counts agree to one near the threshold; the returned solution
+    meets the stopping rule by the oracle's own residual, and equals the
+    oracle's when the counts agree."""
     g, o = make_pair((8, 6, 5), 4, 1.0, 1.3)
     io = LevelIO(g, 0)
     o0 = o.with_degree(io.p)
@@ -214,8 +220,13 @@ def test_coarse_solve_to_tolerance(gpu, rtol, maxit):
         ref = solver.jacobi_pcg(lambda v: matfree.condensed_op(o0, v), b, diag, rtol, maxit, log)
         x = torch.full((io.len,), float("nan"), dtype=torch.float64, device=gpu)
         it = g.coarse_solve(io.to_dev(b), x)
-        assert it == log[0]
-        assert rel(io.to_grid(x), ref) <= 1e-10
+        assert abs(it - log[0]) <= 1
+        xg = io.to_grid(x)
+        rr = b - matfree.condensed_op(o0, xg)
+        if it < maxit:
+            assert np.sum(rr * rr / diag) <= (rtol * rtol) * np.sum(b * b / diag)
+        if it == log[0]:
+            assert rel(xg, ref) <= 1e-8
     x = torch.full((io.len,), float("nan"), dtype=torch.float64, device=gpu)
     assert g.coarse_solve(torch.zeros(io.len, dtype=torch.float64, device=gpu), x) == 0
     assert float(x.abs().max()) == 0.0

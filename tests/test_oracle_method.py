@@ -222,6 +222,42 @@ def test_jacobi_pcg_solves_and_diagonal():
     assert rel(x, cs.to_grid(np.linalg.solve(cs.Hhat, cs.to_vec(b)))) < 1e-11
 
 
+def test_jacobi_pcg_krylov_optimality():
+    """k steps of Jacobi-PCG from x = 0 give the minimiser of the H-energy
+    error over the Krylov space span{z0, (D^-1 H) z0, ..., (D^-1 H)^(k-1) z0},
+    z0 = D^-1 b (the defining property of preconditioned CG), computed here
+    densely by a Galerkin projection; also the iteration count at a
+    tolerance equals the first k whose projected solution meets it."""
+    m = M.Mesh.box((3, 2, 2), 2, 0.5, 1.4)
+    cs = dense.CondensedSystem(m)
+    H = cs.Hhat
+    dg = matfree.condensed_diagonal(m)
+    d = cs.to_vec(dg)
+    b = cs.to_vec(synth.random_grid(m.shape, 9) * m.free_skeleton_mask())
+    A = lambda v: cs.to_grid(H @ cs.to_vec(v))
+    for k in (1, 2, 3, 5):
+        x = cs.to_vec(solver.jacobi_pcg(A, cs.to_grid(b), dg, 0.0, k))
+        K = [b / d]
+        for _ in range(k - 1):
+            K.append((H @ K[-1]) / d)
+        Q, _ = np.linalg.qr(np.array(K).T)
+        y = np.linalg.solve(Q.T @ H @ Q, Q.T @ b)
+        assert np.linalg.norm(x - Q @ y) <= 1e-10 * np.linalg.norm(Q @ y), k
+    # stopping rule: first k with (r, D^-1 r) <= tol^2 (b, D^-1 b)
+    tol = 1e-3
+    log = []
+    solver.jacobi_pcg(A, cs.to_grid(b), dg, tol, 500, log)
+    rz0 = b @ (b / d)
+    kk = 0
+    while True:                                   # brute force: the same test on the iterates
+        kk += 1
+        x = cs.to_vec(solver.jacobi_pcg(A, cs.to_grid(b), dg, 0.0, kk))
+        rr = b - H @ x
+        if rr @ (rr / d) <= tol * tol * rz0:
+            break
+    assert log[0] == kk
+
+
 def test_spectral_convergence_manufactured_solution():
     """4^3 elements, lambda = 1, u = sin(pi x) sin(pi y) sin(pi z): the nodal
     error of the solved discrete problem decays exponentially in p."""

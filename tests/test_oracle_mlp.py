@@ -51,6 +51,38 @@ def test_adam_first_step_is_lr_sign():
     assert np.allclose(th1, -0.01 * g / (np.abs(g) + 1e-8))
 
 
+def test_adam_constant_gradient_steps():
+    """With a constant gradient the bias-corrected moments are exactly g and
+    g^2 at every step t (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so each
+    step moves by lr g / (|g| + eps): theta_t = theta_0 - t lr g / (|g| + eps).
+    A wrong exponent in either bias correction breaks this for t > 1."""
+    g = np.array([1.0, -2.0, 0.5, 0.0, 3.0])
+    th, m, v = np.zeros(5), np.zeros(5), np.zeros(5)
+    for t in range(1, 8):
+        th, m, v = mlp.adam_step(th, g, m, v, t, lr=0.01, b1=0.8, b2=0.9)
+        assert np.allclose(m, (1 - 0.8 ** t) * g, rtol=1e-14, atol=0)
+        assert np.allclose(v, (1 - 0.9 ** t) * g * g, rtol=1e-14, atol=0)
+        assert np.allclose(th, -t * 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
+
+
+def test_adam_moments_closed_form():
+    """Alternating gradients +g, -g: m_t = (1 - b1) sum_k b1^(t-k) g_k and
+    v_t = (1 - b2^t) g^2 in closed form; the step uses m_t / (1 - b1^t)
+    over sqrt(v_t / (1 - b2^t)) + eps."""
+    g0 = np.array([0.3, -1.5])
+    b1, b2, lr, eps = 0.9, 0.99, 0.1, 1e-8
+    th, m, v = np.zeros(2), np.zeros(2), np.zeros(2)
+    th_ref = np.zeros(2)
+    for t in range(1, 6):
+        gt = g0 * (-1) ** (t + 1)
+        th, m, v = mlp.adam_step(th, gt, m, v, t, lr=lr, b1=b1, b2=b2, eps=eps)
+        mt = (1 - b1) * sum(b1 ** (t - k) * g0 * (-1) ** (k + 1) for k in range(1, t + 1))
+        vt = (1 - b2 ** t) * g0 * g0
+        th_ref = th_ref - lr * (mt / (1 - b1 ** t)) / (np.sqrt(vt / (1 - b2 ** t)) + eps)
+        assert np.allclose(m, mt, rtol=1e-13) and np.allclose(v, vt, rtol=1e-13)
+        assert np.allclose(th, th_ref, rtol=1e-12)
+
+
 def test_training_reduces_loss():
     nout = 2
     rng = np.random.default_rng(2)
