@@ -235,6 +235,19 @@ int pmg_mlp_loss(const float *d_y, const float *d_t, const float *d_mask,
 int pmg_mlp_backward(const float *d_params, const float *d_x,
                      const float *d_cache, const float *d_dy,
                      float *d_grad, int batch, int nout, void *stream);
+/* The same gradient as pmg_mlp_backward, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid allocation): no allocation of any kind.  The per-sample
+ * deltas live in a fixed array of 2^21 floats (8 MiB) that the library
+ * holds on each GPU it runs on until the process ends; batch * (128 + nout)
+ * above 2^21 returns PMG_EUNSUP.  Every call on one GPU shares that GPU's
+ * array, so calls that overlap on one GPU (other streams, other threads)
+ * race and must be serialised by the caller.  The stream must belong to
+ * the current device. */
+int pmg_mlp_backward_noalloc(const float *d_params, const float *d_x,
+                             const float *d_cache, const float *d_dy,
+                             float *d_grad, int batch, int nout,
+                             void *stream);
 /* One Adam step (Kingma & Ba) at step t >= 1 on n parameters. */
 int pmg_mlp_adam(float *d_params, const float *d_grad, float *d_m,
                  float *d_v, int n, float lr, float beta1, float beta2,

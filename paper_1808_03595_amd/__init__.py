@@ -91,6 +91,7 @@ SIGNATURES = {
     "pmg_mlp_forward": (_I, [_VP, _VP, _VP, _VP, _I, _I, _VP]),
     "pmg_mlp_loss": (_I, [_VP, _VP, _VP, _VP, _VP, _I, _I, _VP]),
     "pmg_mlp_backward": (_I, [_VP, _VP, _VP, _VP, _VP, _I, _I, _VP]),
+    "pmg_mlp_backward_noalloc": (_I, [_VP, _VP, _VP, _VP, _VP, _I, _I, _VP]),
     "pmg_mlp_adam": (_I, [_VP, _VP, _VP, _VP, _I, _F, _F, _F, _F, _I, _VP]),
     "pmg_last_error": (ctypes.c_char_p, []),
 }
@@ -294,6 +295,11 @@ def mlp_loss(y, t, mask, dy, loss, batch, nout, stream=None):
 def mlp_backward(params, x, cache, dy, grad, batch, nout, stream=None):
     _check(lib().pmg_mlp_backward(_ptr(params), _ptr(x), _ptr(cache), _ptr(dy), _ptr(grad), batch,
                                   nout, _stream(stream)))
+
+
+def mlp_backward_noalloc(params, x, cache, dy, grad, batch, nout, stream=None):
+    _check(lib().pmg_mlp_backward_noalloc(_ptr(params), _ptr(x), _ptr(cache), _ptr(dy), _ptr(grad),
+                                          batch, nout, _stream(stream)))
 
 
 def mlp_adam(params, grad, m, v, n, lr, beta1, beta2, eps, t, stream=None):

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <string>
@@ -1304,6 +1305,47 @@ int pmg_mlp_backward(const float* prm, const float* x, const float* cache, const
     HIPCHK(hipMallocAsync((void**)&work, bytes, S(stream)));
     launch_mlp_backward(prm, x, cache, dy, work, grad, batch, nout, S(stream));
     HIPCHK(hipFreeAsync(work, S(stream)));
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+// Allocation-free backward pass: the per-sample deltas go to a fixed device
+// array instead of a stream-ordered allocation.  Every call on one GPU uses
+// that GPU's copy of the array, so calls that overlap on one GPU race.
+constexpr size_t kMlpScratchFloats = size_t(1) << 21;  // 8 MiB per GPU
+static __device__ __align__(256) float scratch[kMlpScratchFloats];
+static std::mutex g_scratch_mu;
+static std::vector<float*> g_scratch_dev;  // device address of `scratch`, per device
+
+// Device address of the current device's `scratch` (looked up once per device).
+static int scratch_address(float** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(PMG_EHIP, "hipGetSymbolAddress returned a null address for the MLP scratch");
+        g_scratch_dev[dev] = static_cast<float*>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return 0;
+}
+
+int pmg_mlp_backward_noalloc(const float* prm, const float* x, const float* cache, const float* dy, float* grad,
+                             int batch, int nout, void* stream) {
+    if (!prm || !x || !cache || !dy || !grad || batch < 0 || nout < 1) return fail(PMG_EINVAL, "bad MLP arguments");
+    const size_t need = (size_t)std::max(batch, 1) * (128 + (size_t)nout);
+    if (need > kMlpScratchFloats)
+        return fail(PMG_EUNSUP, "pmg_mlp_backward_noalloc: batch * (128 + nout) = " + std::to_string(need) +
+                                    " floats exceeds the fixed scratch of " + std::to_string(kMlpScratchFloats));
+    float* work = nullptr;
+    int rc = scratch_address(&work);
+    if (rc) return rc;
+    // every delta the parameter pass reads is written first by the per-sample
+    // pass of the same call, so the scratch needs no clearing
+    launch_mlp_backward(prm, x, cache, dy, work, grad, batch, nout, S(stream));
     HIPCHK(hipGetLastError());
     return 0;
 }

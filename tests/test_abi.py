@@ -75,6 +75,13 @@ def test_mlp_arguments(lib):
     assert lib.pmg_mlp_forward(None, None, None, None, 1, 4, None) == -1
     assert lib.pmg_mlp_adam(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None) == -1
     assert lib.pmg_mlp_adam(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == -1
+    # the allocation-free backward pass: null pointers, then a batch whose
+    # deltas exceed its fixed scratch (rejected before any device call)
+    assert lib.pmg_mlp_backward_noalloc(None, None, None, None, None, 1, 4, None) == -1
+    fake = ctypes.c_void_p(0x1000)
+    big = (1 << 21) // (128 + 4) + 1
+    assert lib.pmg_mlp_backward_noalloc(fake, fake, fake, fake, fake, big, 4, None) == -4
+    assert b"scratch" in lib.pmg_last_error()
 
 
 def test_binding_names_match_c_abi():
