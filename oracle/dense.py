@@ -162,6 +162,54 @@ class CondensedSystem:
         return omega * Smat
 
 
+def block_nodes(cs: CondensedSystem, e):
+    """Free skeleton nodes of the element-centred block of element e.
+
+    The block covers the open region ((e_d - 1) p, (e_d + 2) p) in every
+    direction (3 x 3 x 3 elements around e, Sec. 3.4); its condensed
+    unknowns are all free skeleton nodes inside.  Returns (flat grid
+    indices, positions (k, 3) as (o1, o2, o3) with o_d = i_d - (e_d - 1) p - 1).
+    """
+    m = cs.mesh
+    p = m.p
+    lo = [(e[d] - 1) * p for d in range(3)]
+    out, offs = [], []
+    for i3 in range(max(lo[2] + 1, 0), min(lo[2] + 3 * p, m.N[2])):
+        for i2 in range(max(lo[1] + 1, 0), min(lo[1] + 3 * p, m.N[1])):
+            for i1 in range(max(lo[0] + 1, 0), min(lo[0] + 3 * p, m.N[0])):
+                g = (i3 * m.N[1] + i2) * m.N[0] + i1
+                if g in cs.pos:
+                    out.append(g)
+                    offs.append((i1 - lo[0] - 1, i2 - lo[1] - 1, i3 - lo[2] - 1))
+    return np.array(out, dtype=np.int64), np.array(offs).reshape(-1, 3)
+
+
+def block_smoother_matrix(cs: CondensedSystem, omega=1.0, weights="smooth", unit_weights=False):
+    """Dense sum_e W_e R_e^T Hhat_e^-1 R_e over all element-centred blocks,
+    with Hhat_e = R_e Hhat R_e^T inverted by dense LU."""
+    from .blocks import block_weights_1d
+    m = cs.mesh
+    p = m.p
+    nB = len(cs.B)
+    Smat = np.zeros((nB, nB))
+    for e3 in range(m.n[2]):
+        for e2 in range(m.n[1]):
+            for e1 in range(m.n[0]):
+                e = (e1, e2, e3)
+                g, offs = block_nodes(cs, e)
+                if len(g) == 0:
+                    continue
+                k = np.array([cs.pos[x] for x in g], dtype=np.int64)
+                Hi_inv = scipy.linalg.inv(cs.Hhat[np.ix_(k, k)])
+                if unit_weights:
+                    W = np.ones(len(k))
+                else:
+                    w = [block_weights_1d(m.n[d], p, e[d], weights) for d in range(3)]
+                    W = w[0][offs[:, 0]] * w[1][offs[:, 1]] * w[2][offs[:, 2]]
+                Smat[np.ix_(k, k)] += W[:, None] * Hi_inv
+    return omega * Smat
+
+
 def interp_1d_global(hs, pc, pf):
     """Global 1D interpolation from degree pc to pf on elements ``hs``.
 

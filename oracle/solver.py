@@ -32,7 +32,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import matfree
+from . import blocks, matfree
 from .mesh import Mesh, level_degrees
 
 
@@ -50,7 +50,8 @@ class Hierarchy:
     def __init__(self, mesh: Mesh, nu_mode: str = "kMG", omega=None,
                  coarse_rtol: float = 1e-8, coarse_maxit: int = 2000,
                  exact_coarse: bool = False, hmg_levels: int = 0,
-                 hmg_omega: float = 0.6, hmg_nu: int = 1):
+                 hmg_omega: float = 0.6, hmg_nu: int = 1,
+                 smoother: str = "star", block_weights: str = "smooth"):
         self.degs = level_degrees(mesh.p)
         Lp = len(self.degs) - 1
         pmeshes = [mesh.with_degree(q) for q in self.degs]
@@ -98,6 +99,10 @@ class Hierarchy:
         self._diag0 = None
         self._dense0 = None
         self.coarse_iters = []
+        if smoother not in ("star", "element"):
+            raise ValueError(smoother)
+        self.smoother = smoother
+        self.block_weights = block_weights
 
     def _prolong(self, l, uc):
         if self.kind[l] == "h":
@@ -139,7 +144,11 @@ class Hierarchy:
             return Fs[l] - matfree.condensed_op(ms[l], us[l])
 
         def smooth(l):
-            du = matfree.smoother(ms[l], residual(l), self.omega[l])
+            if self.smoother == "element" and ms[l].p >= 2:
+                du = blocks.block_smoother(ms[l], residual(l), self.omega[l],
+                                           weights=self.block_weights)
+            else:
+                du = matfree.smoother(ms[l], residual(l), self.omega[l])
             us[l] = du if us[l] is None else us[l] + du
 
         for l in range(L, 0, -1):
