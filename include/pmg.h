@@ -147,6 +147,25 @@ int pmg_set_cycle(pmg_mesh *m, int nu_mode, double coarse_rtol,
  * Jacobi CG then runs on the smallest mesh.  Synchronizes the device. */
 int pmg_set_coarse_mg(pmg_mesh *m, int levels, double omega, int nu);
 
+/* Smoother of every level of degree >= 2 (pmg_schwarz_smooth(_add) and the
+ * V-cycle): kind 0 = the vertex-centred star smoother of Alg. 2 (default);
+ * kind 1 = the element-centred block smoother of Sec. 3.4: one subdomain
+ * per element, the 3 x 3 x 3 element block around it (full overlap),
+ * condensed to the six faces of the centre element extended over the block
+ * (n_S = 3p - 1 nodes per direction), inverted by the six-face form of the
+ * star algorithm (2D transforms into the block's 1D eigenbases, expansion,
+ * inverse eigenvalue sums, contraction, back transforms; 73 n_S^3
+ * operations), with the boundary treatment of Sec. 3.3 (identity padding of
+ * ghost elements and Dirichlet vertices).  Block weights: the distance
+ * functions q(t)/2, 1/2, q(1-t)/2 on the block's left, centre and right
+ * element (q the degree-7 weight polynomial), normalised over the blocks
+ * covering a node so that they sum to one.  Degree-1 levels keep their
+ * point smoother.  The first switch to kind 1 builds the block tables and
+ * two workspaces of n_e * 6 * np^2 FP64 values per level (np =
+ * 16 ceil((3p - 1) / 16)); PMG_ENOMEM if they do not fit.  Synchronizes the
+ * device. */
+int pmg_set_smoother(pmg_mesh *m, int kind);
+
 /* Per-level damping of the smoother correction, u_l += omega_l S_l(r_l).
  * h_omega[j] applies to level L - j (j = 0 is the finest); n <= L values;
  * NULL or n = 0 restores omega = 1 (the paper's method). */

@@ -76,6 +76,7 @@ SIGNATURES = {
     "pmg_prolong_add": (_I, [_VP, _I, _I, _VP, _VP, _VP]),
     "pmg_restrict": (_I, [_VP, _I, _I, _VP, _VP, _VP]),
     "pmg_set_cycle": (_I, [_VP, _I, _D, _I]),
+    "pmg_set_smoother": (_I, [_VP, _I]),
     "pmg_set_damping": (_I, [_VP, _FP, _I]),
     "pmg_set_coarse_mg": (_I, [_VP, _I, _D, _I]),
     "pmg_vcycle": (_I, [_VP, _I, _VP, _VP, _VP]),
@@ -215,6 +216,10 @@ class Mesh:
 
     def set_coarse_mg(self, levels=0, omega=0.6, nu=1):
         _check(lib().pmg_set_coarse_mg(self.h, levels, omega, nu))
+
+    def set_smoother(self, kind=0):
+        """0: star smoother (Alg. 2); 1: element-centred blocks (Sec. 3.4)."""
+        _check(lib().pmg_set_smoother(self.h, kind))
 
     def set_damping(self, omega=None):
         if omega is None or len(omega) == 0:

@@ -65,6 +65,8 @@ struct Level {
     // coarse CG structures when this level is the bottom of the cycle
     CoarseArgs ca{};
     bool has_ca = false;
+    // smoothed by the element-centred block smoother (Sec. 3.4) instead of stars
+    bool blocks = false;
     // graphs of n iteration launches with ring indices j0 .. j0 + n - 1,
     // [(n - 1) * COARSE_RING + j0 % COARSE_RING], captured on first use
     std::vector<hipGraphExec_t> coarse_exec;
@@ -106,6 +108,7 @@ struct pmg_mesh {
     int hmg_levels = 0;
     double hmg_omega = 0.6;
     int hmg_nu = 1;
+    int smoother_kind = 0;      // 0: star smoother (Alg. 2), 1: element-centred blocks (Sec. 3.4)
     // coarse CG counters shared by all bottom levels
     int* d_coarse_iters = nullptr;
     // number of coarse solves started, counted on the device by every coarse
@@ -585,9 +588,40 @@ template <> const float* const* hweights<float>(const Level& L) { return L.ht32;
 // degree-1 levels its equivalent point form (each star is a single vertex,
 // so the local solve is a division by the diagonal).
 template <typename T>
+void schwarz_add(Level& L, const T* r, T* u, T omega, hipStream_t st) {
+    if (L.blocks && L.p >= 2) launch_block_smoother_add<T>(Sel<T>::tabs(L), r, u, omega, st);
+    else launch_smoother_add<T>(Sel<T>::tabs(L), r, u, omega, st);
+}
+
+template <typename T>
 void smooth_add(Level& L, const T* r, T* u, hipStream_t st) {
     if (L.p == 1 && jdiag<T>(L)) launch_point_smooth<T>(L.lay, jdiag<T>(L), r, u, (T)L.omega, st);
-    else launch_smoother_add<T>(Sel<T>::tabs(L), r, u, (T)L.omega, st);
+    else schwarz_add<T>(L, r, u, (T)L.omega, st);
+}
+
+// Tables and workspaces of the element-centred block smoother on one level
+// (built on first request; the FP32 tables share the FP64 workspaces).
+int setup_blocks(pmg_mesh* m, Level& L) {
+    if (L.t64.bnp || L.p < 2) return 0;
+    const int p = L.p, nS = 3 * p - 1, np = 16 * ((nS + 15) / 16);
+    int rc;
+    for (int d = 0; d < 3; ++d) {
+        std::vector<double> S, lam, w;
+        build_block_tables(p, L.h[d], np, S, lam, w);
+        if ((rc = m->upload(&L.t64.bl_S[d], S)) || (rc = m->upload(&L.t32.bl_S[d], S)) ||
+            (rc = m->upload(&L.t64.bl_lam[d], lam)) || (rc = m->upload(&L.t32.bl_lam[d], lam)) ||
+            (rc = m->upload(&L.t64.bl_w[d], w)) || (rc = m->upload(&L.t32.bl_w[d], w)))
+            return rc;
+    }
+    const size_t ws = (size_t)L.lay.n[0] * L.lay.n[1] * L.lay.n[2] * 6 * np * np;
+    for (int k = 0; k < 2; ++k) {
+        double* X = nullptr;
+        if ((rc = m->alloc(&X, ws))) return rc;
+        L.t64.bwX[k] = X;
+        L.t32.bwX[k] = reinterpret_cast<float*>(X);
+    }
+    L.t64.bnp = L.t32.bnp = np;
+    return 0;
 }
 
 // Jacobi-preconditioned CG on level 0 (FP64), x = 0 initially: the init
@@ -980,10 +1014,10 @@ int pmg_schwarz_smooth(pmg_mesh* m, int level, int dtype, const void* r, void* d
     Level& L = m->lv[level];
     if (dtype == PMG_F64) {
         launch_fill_zero<double>((double*)du, L.lay.len, S(stream));  // a kernel: capturable
-        launch_smoother_add<double>(L.t64, (const double*)r, (double*)du, omega, S(stream));
+        schwarz_add<double>(L, (const double*)r, (double*)du, omega, S(stream));
     } else if (dtype == PMG_F32) {
         launch_fill_zero<float>((float*)du, L.lay.len, S(stream));
-        launch_smoother_add<float>(L.t32, (const float*)r, (float*)du, (float)omega, S(stream));
+        schwarz_add<float>(L, (const float*)r, (float*)du, (float)omega, S(stream));
     } else return fail(PMG_EINVAL, "bad dtype");
     HIPCHK(hipGetLastError());
     return 0;
@@ -994,8 +1028,8 @@ int pmg_schwarz_smooth_add(pmg_mesh* m, int level, int dtype, const void* r, voi
     if (check_level(m, level)) return PMG_EINVAL;
     if (!r || !u || r == u) return fail(PMG_EINVAL, "null or aliasing pointers");
     Level& L = m->lv[level];
-    if (dtype == PMG_F64) launch_smoother_add<double>(L.t64, (const double*)r, (double*)u, omega, S(stream));
-    else if (dtype == PMG_F32) launch_smoother_add<float>(L.t32, (const float*)r, (float*)u, (float)omega, S(stream));
+    if (dtype == PMG_F64) schwarz_add<double>(L, (const double*)r, (double*)u, omega, S(stream));
+    else if (dtype == PMG_F32) schwarz_add<float>(L, (const float*)r, (float*)u, (float)omega, S(stream));
     else return fail(PMG_EINVAL, "bad dtype");
     HIPCHK(hipGetLastError());
     return 0;
@@ -1048,6 +1082,20 @@ int pmg_set_coarse_mg(pmg_mesh* m, int levels, double omega, int nu) {
     m->hmg_levels = levels;
     m->hmg_omega = omega;
     m->hmg_nu = nu;
+    if ((rc = rebuild_active(m))) return rc;
+    HIPCHK(hipDeviceSynchronize());
+    return 0;
+}
+
+int pmg_set_smoother(pmg_mesh* m, int kind) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (kind != 0 && kind != 1) return fail(PMG_EINVAL, "smoother kind must be 0 (star) or 1 (element-centred)");
+    int rc;
+    if (kind == 1)
+        for (auto& L : m->lv)
+            if ((rc = setup_blocks(m, L))) return rc;
+    for (auto& L : m->lv) L.blocks = kind == 1;
+    m->smoother_kind = kind;
     if ((rc = rebuild_active(m))) return rc;
     HIPCHK(hipDeviceSynchronize());
     return 0;
@@ -1133,7 +1181,8 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
     stats.res_hist[0] = stats.res0;
     const double eps = rtol * stats.res0;
     int it = 0;
-    while (std::sqrt(rr) > eps && it < maxit) {
+    if (!std::isfinite(rr0)) status = PMG_BREAKDOWN;  // NaN or Inf in the condensed right-hand side
+    while (!status && std::sqrt(rr) > eps && it < maxit) {
         if (mode == 1) {
             // Alg. 4: u <- MultigridCycle(u, F); r = F - H u
             if (m->act.size() == 1) {
@@ -1210,7 +1259,7 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
             break;
         }
     }
-    if (!status && std::sqrt(rr) > eps) status = PMG_NOT_CONVERGED;
+    if (!status && !(std::sqrt(rr) <= eps)) status = PMG_NOT_CONVERGED;
     HIPCHK(hipEventRecord(ev[2], st));
     launch_recover(m->lv.back().t64, f, m->w_u, ug, st);
     HIPCHK(hipEventRecord(ev[3], st));

@@ -87,6 +87,16 @@ struct LevelTabs {
     // [element][qp^3] arrays, qp = 16 ceil((p-1) / 16)
     double* ixX[2];
     int qp;
+    // element-centred block smoother (Sec. 3.4), set up on request: per
+    // direction d and element index e, the block's 1D eigenvectors [i][k]
+    // (bnp x bnp, identity padded), eigenvalues (bnp, padding 1) and weights
+    // (bnp, padding 0), bnp = 16 ceil((3p - 1) / 16); two
+    // [element][6][bnp][bnp] workspaces
+    const T* bl_S[3];
+    const T* bl_lam[3];
+    const T* bl_w[3];
+    int bnp;
+    T* bwX[2];
 };
 
 // Working-set sizes (elements of T) of the general per-element / per-star
@@ -141,6 +151,8 @@ void lagrange_interp(const std::vector<double>& xf, const std::vector<double>& x
                      std::vector<double>& J);
 double smoothstep(int pw, double t);
 void build_level_tables(int p, int pc, const std::vector<double> h[3], HostTables& t);
+void build_block_tables(int p, const std::vector<double>& h, int np, std::vector<double>& S,
+                        std::vector<double>& lam, std::vector<double>& w);
 void coarse_diagonal(const Layout& lay, double lam, const std::vector<double> h[3],
                      std::vector<double>& diag);
 

@@ -29,6 +29,8 @@ template <typename T> void launch_skel_to_grid(const Layout&, const T*, double*,
 // y = H_hat u, or y = F - H_hat u (the residual) when F is given
 template <typename T> void launch_condensed_op(const LevelTabs<T>&, const T*, T*, hipStream_t, const T* F = nullptr);
 template <typename T> void launch_smoother_add(const LevelTabs<T>&, const T*, T*, T, hipStream_t);
+// element-centred block smoother (Sec. 3.4), p >= 2, tables set up
+template <typename T> void launch_block_smoother_add(const LevelTabs<T>&, const T*, T*, T, hipStream_t);
 // The coarse-side array (uc, rc) may be of a wider type TC than the level's T.
 template <typename T, typename TC>
 void launch_prolong_add(const Layout& Lc, const Layout& Lf, const T* J, const TC* uc, T* uf, hipStream_t);

@@ -1861,6 +1861,191 @@ __global__ void __launch_bounds__(256) k_star_eigen(LevelTabs<T> tb, const T* __
 }
 
 // ---------------------------------------------------------------------------
+// Element-centred block smoother (Sec. 3.4).  The block of element
+// e = (e1, e2, e3) is the 3 x 3 x 3 element cube around it; in the residual
+// form its outer boundary is homogeneous, so it has n_S = 3p - 1 positions per
+// direction (position o <-> global node index (e_d - 1) p + 1 + o), and after
+// condensation it keeps six faces: the two element-boundary planes of e in
+// every direction (positions c_0 = p - 1 and c_1 = 2p - 1), each an n_S x n_S
+// window.  Its inverse is Alg. 1 with six faces: 2D transforms into the 1D
+// eigenbases of the block, expansion with the rows c_s of the eigenvector
+// matrices, the inverse eigenvalue sums, contraction onto the six faces and
+// the 2D back transforms.  The blocks of a level are processed together, one
+// step per launch, as for the large stars:
+//   k_blk_gemm<FWD1>: gather of the six residual windows, F S_C
+//   k_blk_gemm<FWD2>: G = S_R^T (F S_C)
+//   k_blk_eigen:      H_{d,s} = sum_k a_{d,s}[k] (sum_{d',s'} a_{d',s'} G_{d',s'}) / D
+//   k_blk_gemm<BWD1>: H S_C^T
+//   k_blk_gemm<BWD2>: U = S_R (H S_C^T), weights, damping, atomic scatter
+// Face f = 2d + s lies on plane e_d + s of family d; (rows, columns) =
+// (x3, x2), (x3, x1), (x2, x1) for d = 0, 1, 2.  The plane layout stores
+// every unknown once, so the gathered windows hold each block unknown once
+// (zeros in the other copies) and the scatter writes only the owning copy.
+// ---------------------------------------------------------------------------
+__device__ inline void block_element(const Layout& L, int b, int& e1, int& e2, int& e3) {
+    e1 = b % L.n[0];
+    e2 = (b / L.n[0]) % L.n[1];
+    e3 = b / (L.n[0] * L.n[1]);
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(64) k_blk_gemm(LevelTabs<T> tb, const T* __restrict__ r, const T* __restrict__ X,
+                                                 T* __restrict__ Y, T* __restrict__ du, T omega) {
+    typedef Mfma<T> M;
+    const Layout& L = tb.lay;
+    const int b = blockIdx.x, f = blockIdx.z, d = f >> 1, sf = f & 1;
+    int e[3];
+    block_element(L, b, e[0], e[1], e[2]);
+    const int np = tb.bnp, nt = np / 16, p = L.p, nS = 3 * p - 1;
+    const int tr = blockIdx.y / nt, tc = blockIdx.y - tr * nt;
+    const int lane = threadIdx.x, q = lane >> 4, j = lane & 15;
+    const int dR = d == 2 ? 1 : 2, dC = d == 0 ? 1 : 0;
+    const T* SR = pick3(dR, tb.bl_S[0], tb.bl_S[1], tb.bl_S[2]) + (size_t)e[dR] * np * np;
+    const T* SC = pick3(dC, tb.bl_S[0], tb.bl_S[1], tb.bl_S[2]) + (size_t)e[dC] * np * np;
+    const size_t mo = ((size_t)b * 6 + f) * np * np;
+    const int row0 = tr * 16, col0 = tc * 16;
+    const int gR = (e[dR] - 1) * p + 1, gC = (e[dC] - 1) * p + 1;   // global index of position 0
+    const int NR = L.N[dR], NC = L.N[dC];
+    const int64_t pbase = d == 0 ? L.plane0(e[0] + sf) : (d == 1 ? L.plane1(e[1] + sf) : L.plane2(e[2] + sf));
+    const int pitch = L.pitch[d];
+    int64_t wbase = 0;
+    bool rowok = false;
+    int lo = 0, hi = 0;   // admissible column positions: global column index inside the grid
+    if (MODE == SG_FWD1) {
+        const int a = row0 + j, ir = gR + a;
+        rowok = a < nS && ir >= 0 && ir < NR;
+        wbase = pbase + (int64_t)ir * pitch + gC;   // + k gives the slot of column position k
+        lo = -gC;
+        hi = NC - 1 - gC;
+    }
+    const T* Xm = X + mo;
+    typename M::v4 acc = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < np; k0 += 4) {
+        const int k = k0 + q;
+        T a, bb;
+        if (MODE == SG_FWD1) {
+            a = (rowok && k < nS && k >= lo && k <= hi) ? r[wbase + k] : (T)0;
+            bb = SC[k * np + col0 + j];
+        } else if (MODE == SG_FWD2) {
+            a = SR[k * np + row0 + j];
+            bb = Xm[k * np + col0 + j];
+        } else if (MODE == SG_BWD1) {
+            a = Xm[(row0 + j) * np + k];
+            bb = SC[(col0 + j) * np + k];
+        } else {
+            a = SR[(row0 + j) * np + k];
+            bb = Xm[k * np + col0 + j];
+        }
+        acc = M::mma(a, bb, acc);
+    }
+    if (MODE != SG_BWD2) {
+        T* Ym = Y + mo;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Ym[(row0 + M::row(q, v)) * np + col0 + j] = acc[v];
+        return;
+    }
+    const int c0 = p - 1, c1 = 2 * p - 1, cs = sf ? c1 : c0;
+    const T* wR = pick3(dR, tb.bl_w[0], tb.bl_w[1], tb.bl_w[2]) + (size_t)e[dR] * np;
+    const T* wC = pick3(dC, tb.bl_w[0], tb.bl_w[1], tb.bl_w[2]) + (size_t)e[dC] * np;
+    const T wN = pick3(d, tb.bl_w[0], tb.bl_w[1], tb.bl_w[2])[(size_t)e[d] * np + cs];
+    const int bc = col0 + j;
+    const bool col_line = bc == c0 || bc == c1;   // column on a plane of a lower family
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int a = row0 + M::row(q, v);
+        if (a >= nS || bc >= nS) continue;
+        const bool row_line = a == c0 || a == c1;
+        // the owning copy: family 1 skips x1-planes (columns); family 2 skips
+        // x1-planes (columns) and x2-planes (rows)
+        if ((d >= 1 && col_line) || (d == 2 && row_line)) continue;
+        const int ir = gR + a, ic = gC + bc;
+        if (ir < 0 || ir >= NR || ic < 0 || ic >= NC) continue;
+        int i[3];
+        i[d] = (e[d] + sf) * p;
+        i[dR] = ir;
+        i[dC] = ic;
+        if (is_dir(L, i[0], i[1], i[2])) continue;
+        unsafeAtomicAdd(du + pbase + (int64_t)ir * pitch + ic, omega * wN * wR[a] * wC[bc] * acc[v]);
+    }
+}
+
+// Eigenspace pass of one block: H_{0,s}[k3][k2] = sum_k1 a_{0,s} V,
+// H_{1,s}[k3][k1] = sum_k2 a_{1,s} V, H_{2,s}[k2][k1] = sum_k3 a_{2,s} V with
+// V = sum_{d,s} a_{d,s} G_{d,s} / (lambda + l1 + l2 + l3) and a_{d,s} = row c_s
+// of S_d.  G staged in LDS when it fits; the 6 np^2 outputs of a block are
+// split over gridDim.y workgroups when the level has few blocks.
+template <typename T>
+__global__ void __launch_bounds__(256) k_blk_eigen(LevelTabs<T> tb, const T* __restrict__ G, T* __restrict__ H,
+                                                   int stage) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    typedef Mfma<T> M;
+    const Layout& L = tb.lay;
+    const int b = blockIdx.x;
+    int e[3];
+    block_element(L, b, e[0], e[1], e[2]);
+    const int np = tb.bnp, n2 = np * np, p = L.p, nS = 3 * p - 1;
+    const T* Gs = G + (size_t)b * 6 * n2;
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    T* A = sm;            // [d][s][np]: rows c_s of S_d
+    T* Lm = A + 6 * np;   // [d][np]
+    for (int i = threadIdx.x; i < 6 * np; i += blockDim.x) {
+        const int f = i / np, k = i - f * np, d = f >> 1, c = (f & 1) ? 2 * p - 1 : p - 1;
+        A[i] = pick3(d, tb.bl_S[0], tb.bl_S[1], tb.bl_S[2])[((size_t)e[d] * np + c) * np + k];
+    }
+    for (int i = threadIdx.x; i < 3 * np; i += blockDim.x) {
+        const int d = i / np, k = i - d * np;
+        Lm[i] = pick3(d, tb.bl_lam[0], tb.bl_lam[1], tb.bl_lam[2])[(size_t)e[d] * np + k];
+    }
+    const T* Gl = Gs;
+    if (stage) {
+        T* Gd = Lm + 3 * np;
+        for (int i = threadIdx.x; i < 6 * n2; i += blockDim.x) Gd[i] = Gs[i];
+        Gl = Gd;
+    }
+    __syncthreads();
+    const T *a10 = A, *a11 = A + np, *a20 = A + 2 * np, *a21 = A + 3 * np, *a30 = A + 4 * np, *a31 = A + 5 * np;
+    const T *l1 = Lm, *l2 = Lm + np, *l3 = Lm + 2 * np;
+    const T *G10 = Gl, *G11 = Gl + n2, *G20 = Gl + 2 * n2, *G21 = Gl + 3 * n2, *G30 = Gl + 4 * n2,
+            *G31 = Gl + 5 * n2;
+    T* Hs = H + (size_t)b * 6 * n2;
+    for (int i = blockIdx.y * blockDim.x + threadIdx.x; i < 6 * n2; i += gridDim.y * blockDim.x) {
+        const int f = i / n2, rc = i - f * n2, rr = rc / np, cc = rc - rr * np, d = f >> 1;
+        T acc = 0;
+        if (rr < nS && cc < nS) {
+            if (d == 0) {         // (rr, cc) = (k3, k2), sum over k1
+                const T* af = (f & 1) ? a11 : a10;
+                const T g10 = G10[rr * np + cc], g11 = G11[rr * np + cc], e0 = tb.lam + l2[cc] + l3[rr];
+                const T b20 = a20[cc], b21 = a21[cc], b30 = a30[rr], b31 = a31[rr];
+                for (int k = 0; k < nS; ++k) {
+                    const T ev = a10[k] * g10 + a11[k] * g11 + b20 * G20[rr * np + k] + b21 * G21[rr * np + k] +
+                                 b30 * G30[cc * np + k] + b31 * G31[cc * np + k];
+                    acc += af[k] * (ev * M::rcp(e0 + l1[k]));
+                }
+            } else if (d == 1) {  // (rr, cc) = (k3, k1), sum over k2
+                const T* af = (f & 1) ? a21 : a20;
+                const T g20 = G20[rr * np + cc], g21 = G21[rr * np + cc], e0 = tb.lam + l1[cc] + l3[rr];
+                const T b10 = a10[cc], b11 = a11[cc], b30 = a30[rr], b31 = a31[rr];
+                for (int k = 0; k < nS; ++k) {
+                    const T ev = b10 * G10[rr * np + k] + b11 * G11[rr * np + k] + a20[k] * g20 + a21[k] * g21 +
+                                 b30 * G30[k * np + cc] + b31 * G31[k * np + cc];
+                    acc += af[k] * (ev * M::rcp(e0 + l2[k]));
+                }
+            } else {              // (rr, cc) = (k2, k1), sum over k3
+                const T* af = (f & 1) ? a31 : a30;
+                const T g30 = G30[rr * np + cc], g31 = G31[rr * np + cc], e0 = tb.lam + l1[cc] + l2[rr];
+                const T b10 = a10[cc], b11 = a11[cc], b20 = a20[rr], b21 = a21[rr];
+                for (int k = 0; k < nS; ++k) {
+                    const T ev = b10 * G10[k * np + rr] + b11 * G11[k * np + rr] + b20 * G20[k * np + cc] +
+                                 b21 * G21[k * np + cc] + a30[k] * g30 + a31[k] * g31;
+                    acc += af[k] * (ev * M::rcp(e0 + l3[k]));
+                }
+            }
+        }
+        Hs[i] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Grid transfers (Sec. 4.1).  The fine condensed values are the tensor
 // Lagrange interpolation of the coarse ones; on a plane this is the 2D
 // interpolation of the coarse plane values (including its edge lines).
@@ -3583,6 +3768,26 @@ void launch_smoother_add(const LevelTabs<T>& tb, const T* r, T* du, T omega, hip
     }
 }
 
+// du += omega * (element-centred block smoother)(r) on one level (p >= 2);
+// the block tables and workspaces must have been set up.
+template <typename T>
+void launch_block_smoother_add(const LevelTabs<T>& tb, const T* r, T* du, T omega, hipStream_t st) {
+    const Layout& L = tb.lay;
+    const int nb = L.n[0] * L.n[1] * L.n[2], nt = tb.bnp / 16;
+    const dim3 g(nb, nt * nt, 6);
+    T* X0 = tb.bwX[0];
+    T* X1 = tb.bwX[1];
+    hipLaunchKernelGGL((k_blk_gemm<T, SG_FWD1>), g, dim3(64), 0, st, tb, r, (const T*)nullptr, X1, (T*)nullptr, omega);
+    hipLaunchKernelGGL((k_blk_gemm<T, SG_FWD2>), g, dim3(64), 0, st, tb, r, (const T*)X1, X0, (T*)nullptr, omega);
+    const size_t full = sizeof(T) * (9 * (size_t)tb.bnp + 6 * (size_t)tb.bnp * tb.bnp);
+    const int chunks = nb < 1000 ? (6 * tb.bnp * tb.bnp + 255) / 256 : 1;
+    const int stg = chunks == 1 && full <= kLdsBytes;
+    hipLaunchKernelGGL(k_blk_eigen<T>, dim3(nb, chunks), dim3(256), stg ? full : sizeof(T) * 9 * tb.bnp, st, tb,
+                       (const T*)X0, X1, stg);
+    hipLaunchKernelGGL((k_blk_gemm<T, SG_BWD1>), g, dim3(64), 0, st, tb, r, (const T*)X1, X0, (T*)nullptr, omega);
+    hipLaunchKernelGGL((k_blk_gemm<T, SG_BWD2>), g, dim3(64), 0, st, tb, r, (const T*)X0, (T*)nullptr, du, omega);
+}
+
 
 static dim3 plane_grid(const Layout& L, int cols, int rows) {
     return dim3((cols + 63) / 64, (rows + 3) / 4, L.n[0] + L.n[1] + L.n[2] + 3);
@@ -3949,6 +4154,7 @@ hipError_t init_kernel_attributes() {
     template void launch_skel_to_grid<T>(const Layout&, const T*, double*, hipStream_t);                    \
     template void launch_condensed_op<T>(const LevelTabs<T>&, const T*, T*, hipStream_t, const T*);        \
     template void launch_smoother_add<T>(const LevelTabs<T>&, const T*, T*, T, hipStream_t);               \
+    template void launch_block_smoother_add<T>(const LevelTabs<T>&, const T*, T*, T, hipStream_t);         \
     template void launch_prolong_add<T, T>(const Layout&, const Layout&, const T*, const T*, T*, hipStream_t); \
     template void launch_restrict<T, T>(const Layout&, const Layout&, const T*, const T*, T*, T*, hipStream_t); \
     template void launch_dot2<T>(const T*, const T*, const T*, int64_t, double*, unsigned*, double*,        \

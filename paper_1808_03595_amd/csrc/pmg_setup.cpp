@@ -209,6 +209,82 @@ double smoothstep(int pw, double t) {
     return std::pow(t, m + 1) * s;
 }
 
+// Element-centred blocks (Sec. 3.4) along one direction: for every element
+// e of the widths h, the 1D matrices of elements e-1, e, e+1 assembled on
+// positions 0..3p with both ends dropped (n_S = 3p - 1 positions), the
+// generalized eigenpairs of the coupled part, identity padding (eigenvalue 1)
+// at positions in ghost elements and at Dirichlet boundary vertices
+// (Sec. 3.3), and the block's 1D weights.  Weights: the block's distance
+// function is q(t)/2 on its left element, 1/2 on the centre and q(1-t)/2 on
+// the right element (q the degree-7 weight polynomial, t the element
+// reference coordinate); a position's weight is the block's value divided by
+// the sum over all blocks of the mesh that cover it, so the weights of the
+// covering blocks add up to one.  Outputs padded to np per block: S [e][i][k]
+// (np x np), lam [e][np], w [e][np] (zero on padding and ghost positions).
+void build_block_tables(int p, const std::vector<double>& h, int np, std::vector<double>& Sout,
+                        std::vector<double>& lamout, std::vector<double>& wout) {
+    std::vector<double> x, w, Ls;
+    gll_nodes_weights(p, x, w);
+    stiffness_std(p, x, w, Ls);
+    const int n1 = p + 1, nS = 3 * p - 1, nb = (int)h.size(), W = 3 * p + 1;
+    Sout.assign((size_t)nb * np * np, 0.0);
+    lamout.assign((size_t)nb * np, 1.0);
+    wout.assign((size_t)nb * np, 0.0);
+    // distance function of block b at global position g it covers
+    auto phi = [&](int b, int g) -> double {
+        int m = g / p, j = g - m * p;
+        if (m >= nb) { m = nb - 1; j = p; }
+        const double t = 0.5 * (x[j] + 1.0);
+        if (m == b) return 0.5;
+        if (m == b - 1) return 0.5 * smoothstep(7, t);
+        if (m == b + 1) return 0.5 * smoothstep(7, 1.0 - t);
+        return 0.0;
+    };
+    for (int e = 0; e < nb; ++e) {
+        std::vector<double> M(W, 0.0), L((size_t)W * W, 0.0);
+        std::vector<char> cpl(W, 0);
+        for (int j = 0; j < 3; ++j) {
+            const int el = e - 1 + j;
+            if (el < 0 || el >= nb) continue;
+            const double he = h[el];
+            for (int a = 0; a < n1; ++a) {
+                M[j * p + a] += 0.5 * he * w[a];
+                cpl[j * p + a] = 1;
+                for (int b = 0; b < n1; ++b) L[(size_t)(j * p + a) * W + j * p + b] += (2.0 / he) * Ls[a * n1 + b];
+            }
+        }
+        if (e == 0) cpl[p] = 0;            // domain boundary at the block's left face
+        if (e == nb - 1) cpl[2 * p] = 0;   // domain boundary at the block's right face
+        std::vector<int> c;
+        for (int i = 1; i < 3 * p; ++i)
+            if (cpl[i]) c.push_back(i);
+        double* S = &Sout[(size_t)e * np * np];
+        double* lam = &lamout[(size_t)e * np];
+        for (int i = 0; i < np; ++i) S[(size_t)i * np + i] = i < nS ? 1.0 : 0.0;
+        const int nc = (int)c.size();
+        if (nc > 0) {
+            std::vector<double> Lc((size_t)nc * nc), mc(nc), Sc, lc;
+            for (int a = 0; a < nc; ++a) {
+                mc[a] = M[c[a]];
+                for (int b = 0; b < nc; ++b) Lc[(size_t)a * nc + b] = L[(size_t)c[a] * W + c[b]];
+            }
+            gen_eig_diag(nc, Lc.data(), mc.data(), Sc, lc);
+            for (int a = 0; a < nc; ++a) {
+                lam[c[a] - 1] = lc[a];
+                for (int b = 0; b < nc; ++b) S[(size_t)(c[a] - 1) * np + (c[b] - 1)] = Sc[(size_t)a * nc + b];
+            }
+        }
+        for (int o = 0; o < nS; ++o) {
+            const int g = (e - 1) * p + 1 + o;
+            if (g < 0 || g > nb * p) continue;
+            double tot = 0.0;
+            for (int b = std::max(0, g / p - 2); b <= std::min(nb - 1, g / p + 1); ++b)
+                if ((b - 1) * p < g && g < (b + 2) * p) tot += phi(b, g);
+            wout[(size_t)e * np + o] = tot > 0.0 ? phi(e, g) / tot : 0.0;
+        }
+    }
+}
+
 void build_level_tables(int p, int pc, const std::vector<double> h[3], HostTables& t) {
     std::vector<double> x, w, Ls;
     gll_nodes_weights(p, x, w);
