@@ -87,5 +87,20 @@ class LevelIO:
 
 
 def rel(a, b):
-    nb = np.linalg.norm(np.ravel(b))
-    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / (nb if nb > 0 else 1.0)
+    """Relative difference of a from the reference b that every parity check
+    compares with its tolerance tol: the larger of the norm-wise difference
+    ||a - b||_2 / ||b||_2 and one fifth of the largest element difference
+    relative to the largest reference magnitude, max|a - b| / (5 max|b|).
+    So `rel(a, b) <= tol` also bounds every single element,
+    max|a - b| <= 5 tol max|b|: one wrong entry of a long vector cannot hide
+    in the norm."""
+    a = np.ravel(np.asarray(a, dtype=np.float64))
+    b = np.ravel(np.asarray(b, dtype=np.float64))
+    d = a - b
+    nb = np.linalg.norm(b)
+    mb = np.max(np.abs(b)) if b.size else 0.0
+    norm_wise = np.linalg.norm(d) / (nb if nb > 0 else 1.0)
+    if not d.size:
+        return norm_wise
+    elem = np.max(np.abs(d)) / (5.0 * (mb if mb > 0 else 1.0))
+    return max(norm_wise, elem)

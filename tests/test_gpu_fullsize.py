@@ -136,7 +136,7 @@ def test_benchmark_workload_solves(gpu):
     g.close()
 
 
-@pytest.mark.parametrize("ar,lam", [(16, 1e4), (16, 0.0), (4, 1e2), (1, 0.0)])
+@pytest.mark.parametrize("ar,lam", [(16, 1e4), (16, 0.0), (8, 1e2), (4, 1e2), (2, 0.0), (1, 0.0)])
 def test_mixed_precision_32cubed(gpu, ar, lam):
     """32^3 elements, p = 8 (16.8M unknowns) on the anisotropic box: the FP32
     cycle inside FP64 CG reaches 1e-10, its solution agrees with the FP64
