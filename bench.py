@@ -585,8 +585,13 @@ def main():
                     help="run only the condensed-operator timing loop (for counter profiles)")
     ap.add_argument("--sweep-kernels", action="store_true",
                     help="time only the smoother and the operator at every p of the sweep")
+    ap.add_argument("--sweep-p", type=int, default=None,
+                    help="with --sweep-kernels: only this degree of the sweep")
     ap.add_argument("--copy-only", action="store_true",
                     help="run one 512 MiB device copy (scale of the byte counters)")
+    ap.add_argument("--profile-solve", action="store_true",
+                    help="run only the headline solver (mixed precision, learned damping): warm-up and timed "
+                         "solves, for kernel-share profiles")
     ap.add_argument("--no-sweep", action="store_true", help="skip the p and n sweeps")
     ap.add_argument("--no-grids", action="store_true", help="skip the 32^3 and the learned-damping grids")
     args = ap.parse_args()
@@ -609,7 +614,7 @@ def main():
         log("[bench] copied 512 MiB")
         return
     if args.sweep_kernels:
-        for p in SWEEP:
+        for p in (SWEEP if args.sweep_p is None else (args.sweep_p,)):
             wl = workload(f"c3p{p}")
             g = create(pmg, wl)
             if g.num_levels() > 0:
@@ -631,6 +636,12 @@ def main():
     hmg = args.hmg_levels if args.hmg_levels is not None else coarse_levels(p, is_uniform(wl), ne)
     g.set_coarse_mg(hmg, 0.8, 2)
     log(f"[bench] workload {args.workload}: {wl['desc']}")
+    if args.profile_solve:
+        u_ex, f = make_rhs(g, wl, torch, synth, dev)
+        u = torch.zeros_like(f)
+        mean, best, st = timed_solves(g, f, u, pmg.F32, learned_damping(wl, L), args.steps, args.warmup, torch)
+        log(f"[bench] mixed learned: {mean * 1e3:.2f} ms/solve iters={st.iters} rel_res={st.rel_res:.2e}")
+        return
     head, ndof, f_head, sols = solver_row(g, wl, torch, synth, dev, args.steps, args.warmup,
                                           with_omega1=True, keep=not args.no_cpu)
     for k in ("fp64", "mixed_omega1", "mixed_learned"):

@@ -2633,6 +2633,338 @@ __global__ void __launch_bounds__(256) k_recover(LevelTabs<double> tb, const dou
 }
 
 // ---------------------------------------------------------------------------
+// Condensation F_hat -= H_BI H_II^-1 F_I and recovery u_I = H_II^-1 (F_I -
+// H_IB u_hat) (Alg. 4, first and last steps) for 3 <= p <= 8: one wavefront
+// per element, compile-time degree.  The element's 1D tables go to LDS
+// once, with the interior eigenvector matrices in both orientations (S^T =
+// Sinv M_I^-1 for the forward and S = (M_I S) M_I^-1 for the backward
+// transform), so that no division is left in the transforms; each 1D pass of
+// the three-dimensional transforms gives one lane one line of the element
+// and keeps the line in registers.
+// ---------------------------------------------------------------------------
+template <int P>
+struct CRShape {
+    static constexpr int n1 = P + 1, q = P - 1, q2 = q * q, q3 = q2 * q, t2 = n1 * n1;
+    // one direction: m[n1] ST[q2] SS[q2] Si[q2] MS[q2] lm[q] c0[q] cp[q]
+    static constexpr int o_m = 0, o_ST = n1, o_SS = o_ST + q2, o_Si = o_SS + q2, o_MS = o_Si + q2,
+                         o_lm = o_MS + q2, o_c0 = o_lm + q, o_cp = o_c0 + q, tab_d = o_cp + q;
+    static constexpr int tabs = 3 * tab_d;
+    // LDS: tables | a[q3] | b[q3] | G[6 q2] | tmp[6 q2] | tile[6 t2] (recovery)
+    static constexpr int o_a = tabs, o_b = o_a + q3, o_G = o_b + q3, o_tmp = o_G + 6 * q2, o_tile = o_tmp + 6 * q2,
+                         cond_total = o_tile, rec_total = o_tile + 6 * t2;
+};
+
+// Stage the tables of element e (CRShape layout) into LDS.
+template <int P>
+__device__ inline void cr_stage_tables(const LevelTabs<double>& tb, const int e[3], double* tabs) {
+    using K = CRShape<P>;
+    constexpr int n1 = K::n1, q = K::q, q2 = K::q2;
+    const int lane = threadIdx.x;
+    for (int i = lane; i < K::tabs; i += 64) {
+        const int d = i / K::tab_d, o = i - d * K::tab_d;
+        const int ed = d == 0 ? e[0] : (d == 1 ? e[1] : e[2]);
+        double v = 0.0;
+        if (o < K::o_ST) v = pick3(d, tb.el_m[0], tb.el_m[1], tb.el_m[2])[ed * n1 + o];
+        else if (o >= K::o_Si && o < K::o_MS) v = pick3(d, tb.el_Sinv[0], tb.el_Sinv[1], tb.el_Sinv[2])[ed * q2 + o - K::o_Si];
+        else if (o >= K::o_MS && o < K::o_lm) v = pick3(d, tb.el_MS[0], tb.el_MS[1], tb.el_MS[2])[ed * q2 + o - K::o_MS];
+        else if (o >= K::o_lm && o < K::o_c0) v = pick3(d, tb.el_lam[0], tb.el_lam[1], tb.el_lam[2])[ed * q + o - K::o_lm];
+        else if (o >= K::o_c0 && o < K::o_cp) v = pick3(d, tb.el_c0[0], tb.el_c0[1], tb.el_c0[2])[ed * q + o - K::o_c0];
+        else if (o >= K::o_cp) v = pick3(d, tb.el_cp[0], tb.el_cp[1], tb.el_cp[2])[ed * q + o - K::o_cp];
+        tabs[i] = v;
+    }
+    __syncthreads();
+    // ST[k][i] = Si[k][i] / m[i+1];  SS[i][k] = MS[i][k] / m[i+1]
+    for (int i = lane; i < 3 * 2 * q2; i += 64) {
+        const int d = i / (2 * q2), w = i - d * 2 * q2, which = w / q2, rc = w - which * q2;
+        double* t = tabs + d * K::tab_d;
+        const int col = which == 0 ? rc % q : rc / q;   // the interior index i
+        const double mi = t[K::o_m + col + 1];
+        if (which == 0) t[K::o_ST + rc] = t[K::o_Si + rc] / mi;
+        else t[K::o_SS + rc] = t[K::o_MS + rc] / mi;
+    }
+    __syncthreads();
+}
+
+// Three 1D passes of a separable transform of the q^3 array x (layout
+// [i3][i2][i1]) with the matrices A_d (row-major q x q, out[k] = sum_i
+// A_d[k][i] in[i]) at offset `off` in each direction's table; x is
+// overwritten, y is scratch.  The result ends in x.
+template <int P>
+__device__ inline void cr_transform3(const double* tabs, int off, double* x, double* y) {
+    using K = CRShape<P>;
+    constexpr int q = K::q, q2 = K::q2;
+    const int lane = threadIdx.x;
+    if (lane < q2) {   // x1 lines: (i2, i3) = (lane % q, lane / q)
+        const double* A = tabs + 0 * K::tab_d + off;
+        double v[q], w[q];
+#pragma unroll
+        for (int i = 0; i < q; ++i) v[i] = x[lane * q + i];
+#pragma unroll
+        for (int k = 0; k < q; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < q; ++i) s += A[k * q + i] * v[i];
+            w[k] = s;
+        }
+#pragma unroll
+        for (int k = 0; k < q; ++k) y[lane * q + k] = w[k];
+    }
+    __syncthreads();
+    if (lane < q2) {   // x2 lines: (i1, i3) = (lane % q, lane / q)
+        const int i1 = lane % q, i3 = lane / q;
+        const double* A = tabs + 1 * K::tab_d + off;
+        double v[q], w[q];
+#pragma unroll
+        for (int i = 0; i < q; ++i) v[i] = y[(i3 * q + i) * q + i1];
+#pragma unroll
+        for (int k = 0; k < q; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < q; ++i) s += A[k * q + i] * v[i];
+            w[k] = s;
+        }
+#pragma unroll
+        for (int k = 0; k < q; ++k) x[(i3 * q + k) * q + i1] = w[k];
+    }
+    __syncthreads();
+    if (lane < q2) {   // x3 lines: (i1, i2) = (lane % q, lane / q)
+        const double* A = tabs + 2 * K::tab_d + off;
+        double v[q], w[q];
+#pragma unroll
+        for (int i = 0; i < q; ++i) v[i] = x[i * q2 + lane];
+#pragma unroll
+        for (int k = 0; k < q; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < q; ++i) s += A[k * q + i] * v[i];
+            w[k] = s;
+        }
+#pragma unroll
+        for (int k = 0; k < q; ++k) x[k * q2 + lane] = w[k];
+    }
+    __syncthreads();
+}
+
+// a[q3] = m1 m2 m3 f at the element's interior nodes
+template <int P>
+__device__ inline void cr_load_interior(const Layout& L, const int e[3], const double* tabs,
+                                        const double* __restrict__ f, double* a) {
+    using K = CRShape<P>;
+    constexpr int q = K::q, q2 = K::q2;
+    for (int i = threadIdx.x; i < K::q3; i += 64) {
+        const int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
+        const int i1 = e[0] * P + 1 + k1, i2 = e[1] * P + 1 + k2, i3 = e[2] * P + 1 + k3;
+        a[i] = tabs[K::o_m + k1 + 1] * tabs[K::tab_d + K::o_m + k2 + 1] * tabs[2 * K::tab_d + K::o_m + k3 + 1] *
+               f[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1];
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(64) k_condense_w(LevelTabs<double> tb, const double* __restrict__ f) {
+    using K = CRShape<P>;
+    constexpr int n1 = K::n1, q = K::q, q2 = K::q2, t2 = K::t2, TD = K::tab_d;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* sm = reinterpret_cast<double*>(smem_raw);
+    double* tabs = sm;
+    double* a = sm + K::o_a;
+    double* b = sm + K::o_b;
+    double* Tc = sm + K::o_G;
+    double* tmp = sm + K::o_tmp;
+    const Layout& L = tb.lay;
+    const int lane = threadIdx.x;
+    const int eid = xcd_remap(blockIdx.x, gridDim.x);
+    int e[3];
+    color_coords(eid, -1, L.n, e);
+    cr_stage_tables<P>(tb, e, tabs);
+    cr_load_interior<P>(L, e, tabs, f, a);
+    __syncthreads();
+    cr_transform3<P>(tabs, K::o_ST, a, b);          // a = (S x S x S)^T F_I
+    const double lam = tb.lam;
+    auto lm = [&](int d) { return tabs + d * TD + K::o_lm; };
+    auto c0 = [&](int d) { return tabs + d * TD + K::o_c0; };
+    auto cp = [&](int d) { return tabs + d * TD + K::o_cp; };
+    // V = a / D, in place, with the x1-contractions on the fly (lane: (k2, k3))
+    if (lane < q2) {
+        const int k2 = lane % q, k3 = lane / q;
+        const double dd = lam + lm(1)[k2] + lm(2)[k3];
+        double s0 = 0.0, sp = 0.0;
+#pragma unroll
+        for (int k1 = 0; k1 < q; ++k1) {
+            const double v = a[lane * q + k1] / (dd + lm(0)[k1]);
+            a[lane * q + k1] = v;
+            s0 += c0(0)[k1] * v;
+            sp += cp(0)[k1] * v;
+        }
+        Tc[0 * q2 + k3 * q + k2] = s0;
+        Tc[1 * q2 + k3 * q + k2] = sp;
+    }
+    __syncthreads();
+    // x2- and x3-contractions
+    for (int i = lane; i < 2 * q2; i += 64) {
+        const int dm = i / q2, rc = i - dm * q2, r = rc / q, c = rc - r * q;
+        double s0 = 0.0, sp = 0.0;
+        if (dm == 0) {          // (r, c) = (k3, k1), sum over k2
+#pragma unroll
+            for (int k = 0; k < q; ++k) {
+                const double v = a[(r * q + k) * q + c];
+                s0 += c0(1)[k] * v;
+                sp += cp(1)[k] * v;
+            }
+        } else {                // (r, c) = (k2, k1), sum over k3
+#pragma unroll
+            for (int k = 0; k < q; ++k) {
+                const double v = a[(k * q + r) * q + c];
+                s0 += c0(2)[k] * v;
+                sp += cp(2)[k] * v;
+            }
+        }
+        Tc[(2 + 2 * dm) * q2 + rc] = s0;
+        Tc[(3 + 2 * dm) * q2 + rc] = sp;
+    }
+    __syncthreads();
+    // corr_f = MS_R Tc_f MS_C^T (lane: face f, row kr, then face f, column c)
+    for (int ii = lane; ii < 6 * q; ii += 64) {
+        const int f = ii / q, kr = ii - f * q;
+        const double* Mc = tabs + tile_cdir(f >> 1) * TD + K::o_MS;
+        double x[q];
+#pragma unroll
+        for (int kc = 0; kc < q; ++kc) x[kc] = Tc[f * q2 + kr * q + kc];
+#pragma unroll
+        for (int c = 0; c < q; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int kc = 0; kc < q; ++kc) s += x[kc] * Mc[c * q + kc];
+            tmp[f * q2 + kr * q + c] = s;
+        }
+    }
+    __syncthreads();
+    double* out = tb.opE + (size_t)eid * 6 * t2;
+    for (int ii = lane; ii < 6 * q; ii += 64) {
+        const int f = ii / q, c = ii - f * q;
+        const double* Mr = tabs + tile_rdir(f >> 1) * TD + K::o_MS;
+        double x[q];
+#pragma unroll
+        for (int kr = 0; kr < q; ++kr) x[kr] = tmp[f * q2 + kr * q + c];
+#pragma unroll
+        for (int r = 0; r < q; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int kr = 0; kr < q; ++kr) s += Mr[r * q + kr] * x[kr];
+            out[f * t2 + (r + 1) * n1 + c + 1] = s;
+        }
+    }
+    // the rims of the six tiles carry no correction
+    constexpr int nrim = 6 * 4 * P;
+    for (int i = lane; i < nrim; i += 64) {
+        const int f = i / (4 * P), k = i - f * 4 * P, side = k / P, t = k - side * P;
+        int r, c;
+        if (side == 0) { r = 0; c = t; }
+        else if (side == 1) { r = t; c = P; }
+        else if (side == 2) { r = P; c = P - t; }
+        else { r = P - t; c = 0; }
+        out[f * t2 + r * n1 + c] = 0.0;
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(64) k_recover_w(LevelTabs<double> tb, const double* __restrict__ f,
+                                                  const double* __restrict__ uh, double* __restrict__ ug) {
+    using K = CRShape<P>;
+    constexpr int n1 = K::n1, q = K::q, q2 = K::q2, t2 = K::t2, TD = K::tab_d;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* sm = reinterpret_cast<double*>(smem_raw);
+    double* tabs = sm;
+    double* a = sm + K::o_a;
+    double* b = sm + K::o_b;
+    double* G = sm + K::o_G;
+    double* tmp = sm + K::o_tmp;
+    double* tile = sm + K::o_tile;
+    const Layout& L = tb.lay;
+    const int lane = threadIdx.x;
+    const int eid = xcd_remap(blockIdx.x, gridDim.x);
+    int e[3];
+    color_coords(eid, -1, L.n, e);
+    for (int i = lane; i < 6 * t2; i += 64) {
+        const int fc = i / t2, rc = i - fc * t2, r = rc / n1, c = rc - r * n1;
+        int a1, a2, a3;
+        tile_node(P, fc, r, c, a1, a2, a3);
+        tile[i] = uh[elem_slot(L, e, a1, a2, a3)];
+    }
+    cr_stage_tables<P>(tb, e, tabs);   // ends with a barrier: the tiles are in place too
+    cr_load_interior<P>(L, e, tabs, f, a);
+    // shell nodes owned by this element: a_d < p, or a_d = p on the last element
+    for (int i = lane; i < n1 * n1 * n1; i += 64) {
+        const int a1 = i % n1, a2 = (i / n1) % n1, a3 = i / t2;
+        const bool shell = a1 == 0 || a1 == P || a2 == 0 || a2 == P || a3 == 0 || a3 == P;
+        if (!shell) continue;
+        if ((a1 == P && e[0] != L.n[0] - 1) || (a2 == P && e[1] != L.n[1] - 1) || (a3 == P && e[2] != L.n[2] - 1))
+            continue;
+        const int i1 = e[0] * P + a1, i2 = e[1] * P + a2, i3 = e[2] * P + a3;
+        ug[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1] =
+            is_dir(L, i1, i2, i3) ? 0.0 : shell_value(tile, P, a1, a2, a3);
+    }
+    __syncthreads();
+    cr_transform3<P>(tabs, K::o_ST, a, b);          // a = (S x S x S)^T F_I
+    // G_f = Si_R X_f Si_C^T on the face interiors
+    for (int ii = lane; ii < 6 * q; ii += 64) {
+        const int fc = ii / q, r = ii - fc * q;
+        const double* Sc = tabs + tile_cdir(fc >> 1) * TD + K::o_Si;
+        double x[q];
+#pragma unroll
+        for (int c = 0; c < q; ++c) x[c] = tile[fc * t2 + (r + 1) * n1 + c + 1];
+#pragma unroll
+        for (int kc = 0; kc < q; ++kc) {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < q; ++c) s += x[c] * Sc[kc * q + c];
+            tmp[fc * q2 + r * q + kc] = s;
+        }
+    }
+    __syncthreads();
+    for (int ii = lane; ii < 6 * q; ii += 64) {
+        const int fc = ii / q, kc = ii - fc * q;
+        const double* Sr = tabs + tile_rdir(fc >> 1) * TD + K::o_Si;
+        double x[q];
+#pragma unroll
+        for (int r = 0; r < q; ++r) x[r] = tmp[fc * q2 + r * q + kc];
+#pragma unroll
+        for (int kr = 0; kr < q; ++kr) {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < q; ++r) s += Sr[kr * q + r] * x[r];
+            G[fc * q2 + kr * q + kc] = s;
+        }
+    }
+    __syncthreads();
+    // V = (a - sum_f c_f (x) G_f) / D in place (lane: (k2, k3) line)
+    const double lam = tb.lam;
+    if (lane < q2) {
+        const int k2 = lane % q, k3 = lane / q;
+        const double* lm0 = tabs + K::o_lm;
+        const double* c00 = tabs + K::o_c0;
+        const double* cp0 = tabs + K::o_cp;
+        const double g0 = G[0 * q2 + k3 * q + k2], g1 = G[1 * q2 + k3 * q + k2];
+        const double a1 = tabs[TD + K::o_c0 + k2], b1 = tabs[TD + K::o_cp + k2];
+        const double a2 = tabs[2 * TD + K::o_c0 + k3], b2 = tabs[2 * TD + K::o_cp + k3];
+        const double dd = lam + tabs[TD + K::o_lm + k2] + tabs[2 * TD + K::o_lm + k3];
+#pragma unroll
+        for (int k1 = 0; k1 < q; ++k1) {
+            const double ex = c00[k1] * g0 + cp0[k1] * g1 + a1 * G[2 * q2 + k3 * q + k1] +
+                              b1 * G[3 * q2 + k3 * q + k1] + a2 * G[4 * q2 + k2 * q + k1] +
+                              b2 * G[5 * q2 + k2 * q + k1];
+            a[lane * q + k1] = (a[lane * q + k1] - ex) / (dd + lm0[k1]);
+        }
+    }
+    __syncthreads();
+    cr_transform3<P>(tabs, K::o_SS, a, b);          // u_I = (S x S x S) V
+    for (int i = lane; i < K::q3; i += 64) {
+        const int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
+        const int i1 = e[0] * P + 1 + k1, i2 = e[1] * P + 1 + k2, i3 = e[2] * P + 1 + k3;
+        ug[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1] = a[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Condensation and recovery for p >= 9, batched over the elements: the
 // three 1D interior transforms (the O(p^4) part, Sec. 4.2) run as products
 // on FP64 MFMA over all elements at once, one wavefront per 16 x 16 output
@@ -3895,6 +4227,21 @@ void launch_condense(const LevelTabs<double>& tb, const double* m1, const double
         launch_gather_elem(L, (const double*)tb.opE, (const double*)nullptr, Fh, st, 1);
         return;
     }
+    if (tb.opE && L.p >= 3 && L.p <= 8) {
+        // one wavefront per element into the operator's face-tile workspace,
+        // then the deterministic per-node sum
+        const int ne = L.n[0] * L.n[1] * L.n[2];
+        switch (L.p) {
+#define PMG_CW(PP)                                                                                        \
+    case PP:                                                                                              \
+        hipLaunchKernelGGL(k_condense_w<PP>, dim3(ne), dim3(64), sizeof(double) * CRShape<PP>::cond_total, st, tb, f); \
+        break;
+            PMG_CW(3) PMG_CW(4) PMG_CW(5) PMG_CW(6) PMG_CW(7) PMG_CW(8)
+#undef PMG_CW
+        }
+        launch_gather_elem(L, (const double*)tb.opE, (const double*)nullptr, Fh, st, 1);
+        return;
+    }
     LevelTabs<double> t = tb;
     const size_t sm = pick_ws(t, ws_condense(L.p));
     if (tb.opE && L.p <= 8 && !t.gws) {
@@ -3935,6 +4282,19 @@ void launch_recover(const LevelTabs<double>& tb, const double* f, const double* 
         int_backward(tb, tb.ixX[1], tb.ixX[0], st);
         hipLaunchKernelGGL(k_int_store, dim3(int_blocks(tb)), dim3(256), 0, st, tb, tb.qp, (const double*)tb.ixX[0],
                            ug);
+        return;
+    }
+    if (L.p <= 8) {
+        const int ne = L.n[0] * L.n[1] * L.n[2];
+        switch (L.p) {
+#define PMG_RW(PP)                                                                                        \
+    case PP:                                                                                              \
+        hipLaunchKernelGGL(k_recover_w<PP>, dim3(ne), dim3(64), sizeof(double) * CRShape<PP>::rec_total, st, tb, f, \
+                           uh, ug);                                                                       \
+        break;
+            PMG_RW(3) PMG_RW(4) PMG_RW(5) PMG_RW(6) PMG_RW(7) PMG_RW(8)
+#undef PMG_RW
+        }
         return;
     }
     LevelTabs<double> t = tb;
