@@ -32,7 +32,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import blocks, matfree
+from . import blocks, coarse_fd, matfree
 from .mesh import Mesh, level_degrees
 
 
@@ -51,7 +51,7 @@ class Hierarchy:
                  coarse_rtol: float = 1e-8, coarse_maxit: int = 2000,
                  exact_coarse: bool = False, hmg_levels: int = 0,
                  hmg_omega: float = 0.6, hmg_nu: int = 1,
-                 smoother: str = "star", block_weights: str = "smooth"):
+                 smoother: str = "star", block_weights: str = "smooth", coarse: str = "cg"):
         self.degs = level_degrees(mesh.p)
         Lp = len(self.degs) - 1
         pmeshes = [mesh.with_degree(q) for q in self.degs]
@@ -103,6 +103,9 @@ class Hierarchy:
             raise ValueError(smoother)
         self.smoother = smoother
         self.block_weights = block_weights
+        if coarse not in ("cg", "fd"):
+            raise ValueError(coarse)
+        self.coarse = coarse
 
     def _prolong(self, l, uc):
         if self.kind[l] == "h":
@@ -117,6 +120,8 @@ class Hierarchy:
     # ---- coarse grid ----------------------------------------------------
     def coarse_solve(self, F0):
         m0 = self.meshes[0]
+        if self.coarse == "fd":
+            return coarse_fd.fd_condensed_solve(m0, F0)
         if self.exact_coarse:
             if self._dense0 is None:
                 from .dense import CondensedSystem
