@@ -170,6 +170,31 @@ def coarse_levels(p, uniform, ne):
     return 1 if (p <= 8 and uniform and ne >= 16 ** 3) else 0
 
 
+# coarse solver of every solve: "fd" (exact solve by fast diagonalization of
+# the whole coarse mesh) or "cg" (the paper's Jacobi CG on p_0 = 2, with the
+# degree-1 levels of coarse_levels below it)
+COARSE = {"kind": "fd"}
+
+
+def configure_coarse(g, wl, coarse_rtol):
+    """Set up the coarse solver of mesh g for workload wl; returns its
+    description and the oracle's matching keyword arguments."""
+    g.set_cycle(0, coarse_rtol, 5000)
+    if COARSE["kind"] == "fd":
+        g.set_coarse_mg(0, 0.8, 2)
+        g.set_coarse_solver(1)
+        return "exact (fast diagonalization)", {"coarse": "fd"}
+    g.set_coarse_solver(0)
+    n = wl["n"]
+    hmg = coarse_levels(wl["p"], is_uniform(wl), n[0] * n[1] * n[2])
+    g.set_coarse_mg(hmg, 0.8, 2)
+    desc = (f"{hmg} degree-1 level(s) + " if hmg else "") + f"Jacobi CG to rel. {coarse_rtol:g}"
+    kw = {"coarse_rtol": coarse_rtol, "coarse_maxit": 5000}
+    if hmg:
+        kw.update(hmg_levels=hmg, hmg_omega=0.8, hmg_nu=2)
+    return desc, kw
+
+
 def learned_damping(wl, L):
     """omega predicted by the trained network for this mesh, or None."""
     from paper_1808_03595_amd.learn import DampingMLP, predict_damping
@@ -357,12 +382,9 @@ def c4_grid(torch, pmg, synth, dev, coarse_rtol, steps, warm):
         for ar in (1, 2, 4, 8, 16):
             wl = brick(32, 8, lam, ar)
             g = create(pmg, wl)
-            g.set_cycle(0, coarse_rtol, 5000)
-            hmg = coarse_levels(8, True, 32 ** 3)
-            g.set_coarse_mg(hmg, 0.8, 2)
+            cdesc, _ = configure_coarse(g, wl, coarse_rtol)
             row, ndof, _, _ = solver_row(g, wl, torch, synth, dev, steps, warm)
-            row.update({"lambda": lam, "ar": ar, "ndof": ndof,
-                        "coarse": f"{hmg} degree-1 level(s) + CG" if hmg else "CG on p_0 = 2",
+            row.update({"lambda": lam, "ar": ar, "ndof": ndof, "coarse": cdesc,
                         "parity": "rel_res recomputed by the solver; oracle check at the headline only"})
             log(f"[bench] c4 grid lambda={lam:g} AR={ar}: fp64 {row['fp64']['ms']:.2f} ms "
                 f"({row['fp64']['iters']} it), mixed+learned {row['mixed_learned']['ms']:.2f} ms "
@@ -385,9 +407,9 @@ def c5_grid(torch, pmg, synth, dev, coarse_rtol, steps, warm):
             hmin = min(float(np.min(h)) for h in w0["widths"])
             wl = brick(24, 12, lh2 / hmin ** 2, ar)
             g = create(pmg, wl)
-            g.set_cycle(0, coarse_rtol, 5000)
+            cdesc, _ = configure_coarse(g, wl, coarse_rtol)
             row, ndof, _, _ = solver_row(g, wl, torch, synth, dev, steps, warm, with_omega1=True)
-            row.update({"ar": ar, "lambda_h2": lh2, "lambda": wl["lam"], "ndof": ndof})
+            row.update({"ar": ar, "lambda_h2": lh2, "lambda": wl["lam"], "ndof": ndof, "coarse": cdesc})
             log(f"[bench] c5 AR={ar} lambda h^2={lh2:g}: mixed omega=1 {row['mixed_omega1']['ms']:.2f} ms "
                 f"({row['mixed_omega1']['iters']} it), learned {row['mixed_learned']['ms']:.2f} ms "
                 f"({row['mixed_learned']['iters']} it)")
@@ -412,15 +434,10 @@ def p_sweep(torch, pmg, synth, dev, coarse_rtol, steps, warm):
         wl = workload(f"c3p{p}")
         nn = wl["n"][0]
         g = create(pmg, wl)
-        g.set_cycle(0, coarse_rtol, 5000)
-        # the CG on the coarse problem grows like n_e^(4/3) (Sec. 4.2), so
-        # degree-1 levels go below it
-        hmg = coarse_levels(p, True, nn ** 3)
-        g.set_coarse_mg(hmg, 0.8, 2)
+        cdesc, _ = configure_coarse(g, wl, coarse_rtol)
         L = g.num_levels()
         row, ndof, _, _ = solver_row(g, wl, torch, synth, dev, steps, warm)
-        row.update({"p": p, "n": nn, "ndof": ndof, "levels": L + 1,
-                    "coarse": f"{hmg} degree-1 levels + CG" if hmg else "CG on p_0 = 2",
+        row.update({"p": p, "n": nn, "ndof": ndof, "levels": L + 1, "coarse": cdesc,
                     "parity": "parity unpinned at this size (no oracle solve); rel_res from the solver"})
         if L > 0:
             row["kernels"] = kernel_rooflines(g, torch, dev, wl["n"], p)
@@ -446,9 +463,8 @@ def n_sweep(torch, pmg, synth, dev, coarse_rtol, steps, warm):
     for nn in NSWEEP:
         h = [2.0 * math.pi / nn] * nn
         g = pmg.create_mesh_widths(h, h, h, p, 0.0)
-        g.set_cycle(0, coarse_rtol, 5000)
-        hmg = coarse_levels(p, True, nn ** 3)
-        g.set_coarse_mg(hmg, 0.8, 2)
+        wln = dict(n=(nn, nn, nn), p=p, lam=0.0, widths=(h, h, h))
+        cdesc, _ = configure_coarse(g, wln, coarse_rtol)
         L = g.num_levels()
         x1, x2, x3 = (torch.tensor(c, dtype=torch.float64, device=dev) for c in g.grid_coords())
         u_ex, f = synth.paper_test_solution(5.0, 0.0, x1[None, None, :], x2[None, :, None],
@@ -456,10 +472,9 @@ def n_sweep(torch, pmg, synth, dev, coarse_rtol, steps, warm):
         u_ex, f = u_ex.contiguous(), f.contiguous()
         u = torch.zeros_like(f)
         ndof = nn ** 3 * p ** 3
-        row = {"n": nn, "p": p, "ndof": ndof,
-               "coarse": f"{hmg} degree-1 level(s) + CG" if hmg else "CG on p_0 = 2",
+        row = {"n": nn, "p": p, "ndof": ndof, "coarse": cdesc,
                "parity": "parity unpinned at this size (no oracle solve); rel_res from the solver"}
-        omega = learned_damping(dict(n=(nn, nn, nn), p=p, lam=0.0, widths=(h, h, h)), L)
+        omega = learned_damping(wln, L)
         for name, dtype, om in (("fp64", pmg.F64, None), ("mixed_learned", pmg.F32, omega)):
             g.set_damping(om)
             for _ in range(warm):
@@ -519,14 +534,13 @@ def oracle_check(wl, f, sols):
     return out
 
 
-def oracle_solve(wl, f, coarse_rtol, hmg):
+def oracle_solve(wl, f, ckw):
     """The FP64 oracle's complete solve (condensation, ipCG to 1e-10 with the
-    same coarse tolerance and coarse levels, recovery); returns (u, iters, s)."""
+    same coarse solver, recovery); returns (u, iters, s)."""
     from oracle import solver
     o = oracle_mesh(wl)
     t0 = time.perf_counter()
-    kw = {"hmg_levels": hmg, "hmg_omega": 0.8, "hmg_nu": 2} if hmg else {}
-    res = solver.solve(o, f, method="kMG", rtol=1e-10, coarse_rtol=coarse_rtol, coarse_maxit=5000, **kw)
+    res = solver.solve(o, f, method="kMG", rtol=1e-10, **ckw)
     return res.u, res.iters, time.perf_counter() - t0
 
 
@@ -538,13 +552,10 @@ def cpu_parity_and_baseline(wl_sample, wl_small, torch, pmg, synth, dev, coarse_
     from threadpoolctl import threadpool_limits
     threads = len(os.sched_getaffinity(0))
     g = create(pmg, wl_sample)
-    g.set_cycle(0, coarse_rtol, 5000)
-    ne = wl_sample["n"][0] * wl_sample["n"][1] * wl_sample["n"][2]
-    hmg = coarse_levels(wl_sample["p"], is_uniform(wl_sample), ne)
-    g.set_coarse_mg(hmg, 0.8, 2)
+    _, ckw = configure_coarse(g, wl_sample, coarse_rtol)
     row, ndof, f, sols = solver_row(g, wl_sample, torch, synth, dev, steps, warm, with_omega1=True, keep=True)
     g.close()
-    u_or, it_or, t_or = oracle_solve(wl_sample, f, coarse_rtol, hmg)
+    u_or, it_or, t_or = oracle_solve(wl_sample, f, ckw)
     nr = float(np.linalg.norm(u_or))
     errs = {k: float(np.linalg.norm(v - u_or)) / nr for k, v in sols.items()}
     log(f"[bench] oracle sample solve: {t_or:.1f} s on {threads} threads, {it_or} iterations; "
@@ -552,11 +563,11 @@ def cpu_parity_and_baseline(wl_sample, wl_small, torch, pmg, synth, dev, coarse_
     g = create(pmg, wl_small)
     _, fs = make_rhs(g, wl_small, torch, synth, dev)
     fs = fs.cpu().numpy()
+    _, ckw_s = configure_coarse(g, wl_small, coarse_rtol)
     g.close()
     ne_s = wl_small["n"][0] * wl_small["n"][1] * wl_small["n"][2]
-    hmg_s = coarse_levels(wl_small["p"], is_uniform(wl_small), ne_s)
     with threadpool_limits(limits=1):
-        _, it1, t1 = oracle_solve(wl_small, fs, coarse_rtol, hmg_s)
+        _, it1, t1 = oracle_solve(wl_small, fs, ckw_s)
     ndof_s = ne_s * wl_small["p"] ** 3
     log(f"[bench] oracle 1-thread solve of {wl_small['desc']}: {t1:.1f} s, {it1} iterations")
     return {
@@ -576,9 +587,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle parity checks and CPU baseline")
     ap.add_argument("--coarse-rtol", type=float, default=3e-2,
                     help="relative tolerance of the coarse CG (the paper leaves it open)")
-    ap.add_argument("--hmg-levels", type=int, default=None,
-                    help="degree-1 levels below p_0 (0: the paper's CG on p_0 = 2; default: 6 at p <= 4; "
-                         "1 at p <= 8 on uniform meshes of >= 16^3 elements; else 0)")
+    ap.add_argument("--coarse", choices=["fd", "cg"], default="fd",
+                    help="coarse solver: exact fast-diagonalization solve (default) or the paper's Jacobi CG "
+                         "(with degree-1 levels below p_0 = 2: 6 at p <= 4; 1 at p <= 8 on uniform meshes of "
+                         ">= 16^3 elements; else none)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the smoother timing loop (for counter profiles)")
     ap.add_argument("--op-only", action="store_true",
@@ -632,10 +644,9 @@ def main():
         t = fn(g, torch, dev, pmg.F32, reps=100)
         log(f"[bench] {'smoother' if args.kernel_only else 'operator'} f32: {t * 1e6:.2f} us per launch")
         return
-    g.set_cycle(0, args.coarse_rtol, 5000)
-    hmg = args.hmg_levels if args.hmg_levels is not None else coarse_levels(p, is_uniform(wl), ne)
-    g.set_coarse_mg(hmg, 0.8, 2)
-    log(f"[bench] workload {args.workload}: {wl['desc']}")
+    COARSE["kind"] = args.coarse
+    cdesc, _ = configure_coarse(g, wl, args.coarse_rtol)
+    log(f"[bench] workload {args.workload}: {wl['desc']}; coarse solver: {cdesc}")
     if args.profile_solve:
         u_ex, f = make_rhs(g, wl, torch, synth, dev)
         u = torch.zeros_like(f)
@@ -705,8 +716,7 @@ def main():
         "config": {"workload": wl["desc"], "ndof": ndof, "iters": mixed["iters"], "rel_res": mixed["rel_res"],
                    "damping": "learned" if head["omega"] is not None else "omega=1 (paper)",
                    "omega": head["omega"],
-                   "coarse": (f"Jacobi CG on p_0=2 to rel. {args.coarse_rtol:g}" if not hmg else
-                              f"{hmg} degree-1 level(s) + Jacobi CG to rel. {args.coarse_rtol:g}"),
+                   "coarse": cdesc,
                    "coarse_iters_per_solve": mixed["coarse_iters"],
                    "solvers": {k: head[k] for k in ("fp64", "mixed_omega1", "mixed_learned")}},
         "roofline": roof,

@@ -147,6 +147,21 @@ int pmg_set_cycle(pmg_mesh *m, int nu_mode, double coarse_rtol,
  * Jacobi CG then runs on the smallest mesh.  Synchronizes the device. */
 int pmg_set_coarse_mg(pmg_mesh *m, int levels, double omega, int nu);
 
+/* Solver of the coarsest level of the active cycle: kind 0 = the
+ * Jacobi-preconditioned CG of pmg_set_cycle (Sec. 4.1; default); kind 1 =
+ * an exact solve by fast diagonalization of the whole coarse mesh: on a
+ * Cartesian mesh the assembled operator is the tensor sum of eq.
+ * helmholtzop, so its inverse is (S3 x S2 x S1) diag(1 / (lambda + mu1 +
+ * mu2 + mu3)) (S3 x S2 x S1)^T with the generalized eigenpairs of the
+ * assembled 1D matrices (eq. fast_diagonalization on the whole mesh), and
+ * the condensed solution is the skeleton part of the full solution with
+ * zero interior right-hand side.  Six 1D passes of m_d = n_d p - 1 per
+ * direction; no iteration, no tolerance, no host synchronisation (the
+ * solvers capture it in their graphs); coarse iteration counts report 0.
+ * Tables of 3 m_d^2 values and two work grids of m1 m2 m3 values on the
+ * bottom level.  Synchronizes the device. */
+int pmg_set_coarse_solver(pmg_mesh *m, int kind);
+
 /* Smoother of every level of degree >= 2 (pmg_schwarz_smooth(_add) and the
  * V-cycle): kind 0 = the vertex-centred star smoother of Alg. 2 (default);
  * kind 1 = the element-centred block smoother of Sec. 3.4: one subdomain

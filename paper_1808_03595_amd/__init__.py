@@ -77,6 +77,7 @@ SIGNATURES = {
     "pmg_restrict": (_I, [_VP, _I, _I, _VP, _VP, _VP]),
     "pmg_set_cycle": (_I, [_VP, _I, _D, _I]),
     "pmg_set_smoother": (_I, [_VP, _I]),
+    "pmg_set_coarse_solver": (_I, [_VP, _I]),
     "pmg_set_damping": (_I, [_VP, _FP, _I]),
     "pmg_set_coarse_mg": (_I, [_VP, _I, _D, _I]),
     "pmg_vcycle": (_I, [_VP, _I, _VP, _VP, _VP]),
@@ -216,6 +217,10 @@ class Mesh:
 
     def set_coarse_mg(self, levels=0, omega=0.6, nu=1):
         _check(lib().pmg_set_coarse_mg(self.h, levels, omega, nu))
+
+    def set_coarse_solver(self, kind=0):
+        """0: Jacobi CG (Sec. 4.1); 1: exact solve by fast diagonalization."""
+        _check(lib().pmg_set_coarse_solver(self.h, kind))
 
     def set_smoother(self, kind=0):
         """0: star smoother (Alg. 2); 1: element-centred blocks (Sec. 3.4)."""

@@ -67,6 +67,9 @@ struct Level {
     bool has_ca = false;
     // smoothed by the element-centred block smoother (Sec. 3.4) instead of stars
     bool blocks = false;
+    // exact coarse solve by fast diagonalization when this level is the bottom
+    FdTabs fd{};
+    bool has_fd = false;
     // graphs of n iteration launches with ring indices j0 .. j0 + n - 1,
     // [(n - 1) * COARSE_RING + j0 % COARSE_RING], captured on first use
     std::vector<hipGraphExec_t> coarse_exec;
@@ -109,6 +112,7 @@ struct pmg_mesh {
     double hmg_omega = 0.6;
     int hmg_nu = 1;
     int smoother_kind = 0;      // 0: star smoother (Alg. 2), 1: element-centred blocks (Sec. 3.4)
+    int coarse_kind = 0;        // 0: Jacobi CG (Sec. 4.1), 1: exact solve by fast diagonalization
     // coarse CG counters shared by all bottom levels
     int* d_coarse_iters = nullptr;
     // number of coarse solves started, counted on the device by every coarse
@@ -403,6 +407,23 @@ int build_h_levels(pmg_mesh* m, int want) {
 }
 
 // Active cycle, coarsest level first: hlv[k-1..0] then the p-levels.
+// Tables and work arrays of the exact coarse solve on one level.
+int setup_fd(pmg_mesh* m, Level& L) {
+    if (L.has_fd) return 0;
+    int rc;
+    for (int d = 0; d < 3; ++d) {
+        std::vector<double> Af, Ab, mu;
+        build_fd_tables(L.p, L.h[d], Af, Ab, mu);
+        L.fd.m[d] = (int)mu.size();
+        if ((rc = m->upload(&L.fd.Af[d], Af)) || (rc = m->upload(&L.fd.Ab[d], Ab)) || (rc = m->upload(&L.fd.mu[d], mu)))
+            return rc;
+    }
+    const size_t M = (size_t)L.fd.m[0] * L.fd.m[1] * L.fd.m[2];
+    if ((rc = m->alloc(&L.fd.X, M)) || (rc = m->alloc(&L.fd.Y, M))) return rc;
+    L.has_fd = true;
+    return 0;
+}
+
 int rebuild_active(pmg_mesh* m) {
     m->coarse_nrec = 0;  // the coarse update counts of another cycle do not carry over
     for (auto& g : m->solver_graphs)
@@ -434,6 +455,7 @@ int rebuild_active(pmg_mesh* m) {
             }
         }
     }
+    if (m->coarse_kind == 1) return setup_fd(m, *m->act[0]);
     return build_coarse(m, *m->act[0]);
 }
 
@@ -707,6 +729,18 @@ int coarse_cg(pmg_mesh* m, const double* b, double* x, hipStream_t st, bool in_g
     }
 }
 
+// The coarse solve of the active cycle: the Jacobi CG, or the exact solve by
+// fast diagonalization (kernel launches only, so capturable in a graph).
+int coarse_solve(pmg_mesh* m, const double* b, double* x, hipStream_t st) {
+    if (m->coarse_kind == 1) {
+        Level& L0 = *m->act[0];
+        launch_fd_solve(L0.lay, L0.fd, m->lam, b, x, st);
+        HIPCHK(hipGetLastError());
+        return 0;
+    }
+    return coarse_cg(m, b, x, st);
+}
+
 // Read and reset the device-side coarse iteration counter.
 int coarse_stats(pmg_mesh* m, hipStream_t st, int* iters) {
     int h = 0;
@@ -823,7 +857,7 @@ int vcycle_impl(pmg_mesh* m, const T* r, T* z, bool nonzero_u, hipStream_t st) {
     const double* b;
     double* x;
     vc_coarse_io<T>(m, r, z, b, x);
-    if ((rc = coarse_cg(m, b, x, st))) return rc;
+    if ((rc = coarse_solve(m, b, x, st))) return rc;
     return vc_up<T>(m, r, z, st);
 }
 
@@ -1087,6 +1121,16 @@ int pmg_set_coarse_mg(pmg_mesh* m, int levels, double omega, int nu) {
     return 0;
 }
 
+int pmg_set_coarse_solver(pmg_mesh* m, int kind) {
+    if (check_mesh(m)) return PMG_EINVAL;
+    if (kind != 0 && kind != 1) return fail(PMG_EINVAL, "coarse solver kind must be 0 (CG) or 1 (exact)");
+    m->coarse_kind = kind;
+    int rc;
+    if ((rc = rebuild_active(m))) return rc;
+    HIPCHK(hipDeviceSynchronize());
+    return 0;
+}
+
 int pmg_set_smoother(pmg_mesh* m, int kind) {
     if (check_mesh(m)) return PMG_EINVAL;
     if (kind != 0 && kind != 1) return fail(PMG_EINVAL, "smoother kind must be 0 (star) or 1 (element-centred)");
@@ -1129,7 +1173,7 @@ int pmg_coarse_solve(pmg_mesh* m, const double* F0, double* u0, int* iters, void
     if (!F0 || !u0) return fail(PMG_EINVAL, "null pointer");
     int it = 0, rc;
     if ((rc = coarse_stats(m, S(stream), &it))) return rc;
-    if ((rc = coarse_cg(m, F0, u0, S(stream)))) return rc;
+    if ((rc = coarse_solve(m, F0, u0, S(stream)))) return rc;
     if ((rc = coarse_stats(m, S(stream), &it))) return rc;
     m->coarse_last = it;
     if (iters) *iters = it;
@@ -1216,11 +1260,16 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
                         r2 = vc_down<float>(m, m->w_r32, m->w_z32, false, s);
                     }
                     if (r2) return r2;
+                    if (m->coarse_kind == 1) {   // the exact coarse solve, inside the graph
+                        Level& L0 = *m->act[0];
+                        launch_fd_solve(L0.lay, L0.fd, m->lam, cb, cx, s);
+                        return 0;
+                    }
                     HIPCHK(launch_coarse_init(m->act[0]->ca, cb, m->coarse_maxit, m->coarse_rtol, s));
                     return 0;
                 };
                 auto part_b = [&](hipStream_t s) -> int {
-                    HIPCHK(launch_coarse_extract(m->act[0]->ca, cx, s));
+                    if (m->coarse_kind != 1) HIPCHK(launch_coarse_extract(m->act[0]->ca, cx, s));
                     int r2 = pdt == PMG_F64 ? vc_up<double>(m, m->w_r, m->w_z, s)
                                             : vc_up<float>(m, m->w_r32, m->w_z32, s);
                     if (r2) return r2;
@@ -1240,7 +1289,7 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
                     return rc;
             }
             HIPCHK(hipGraphLaunch(m->solver_graphs[gi], st));
-            if ((rc = coarse_cg(m, cb, cx, st, true))) return rc;
+            if (m->coarse_kind != 1 && (rc = coarse_cg(m, cb, cx, st, true))) return rc;
             HIPCHK(hipGraphLaunch(m->solver_graphs[gi + 1], st));
             if ((rc = read_scalars(m, st, true))) return rc;
             rr = m->hscal[SC_RR];

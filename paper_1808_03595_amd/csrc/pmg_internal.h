@@ -128,6 +128,20 @@ __host__ __device__ inline size_t ws_recover(int p) {
 }
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 
+// Exact solve of a level's condensed system by fast diagonalization of the
+// whole mesh (the full system with zero interior right-hand side): per
+// direction m_d = n_d p - 1 unknowns, the forward (S^T) and backward (S)
+// transform matrices, row-major, and the eigenvalues; two [m3][m2][m1] work
+// arrays.
+struct FdTabs {
+    int m[3];
+    const double* Af[3];
+    const double* Ab[3];
+    const double* mu[3];
+    double* X;
+    double* Y;
+};
+
 struct HostTables {
     // per direction: concatenated element / star tables (FP64)
     std::vector<double> el_m[3], el_L[3], el_Sinv[3], el_MS[3], el_lam[3],
@@ -151,6 +165,8 @@ void lagrange_interp(const std::vector<double>& xf, const std::vector<double>& x
                      std::vector<double>& J);
 double smoothstep(int pw, double t);
 void build_level_tables(int p, int pc, const std::vector<double> h[3], HostTables& t);
+void build_fd_tables(int p, const std::vector<double>& h, std::vector<double>& Af, std::vector<double>& Ab,
+                     std::vector<double>& mu);
 void build_block_tables(int p, const std::vector<double>& h, int np, std::vector<double>& S,
                         std::vector<double>& lam, std::vector<double>& w);
 void coarse_diagonal(const Layout& lay, double lam, const std::vector<double> h[3],

@@ -16,6 +16,8 @@ constexpr int COARSE_RING = 6;
 int64_t restrict_work_len(const Layout& Lf, const Layout& Lc);
 constexpr int COARSE_GRAPH_MAXN = 256;  // longest captured chain of coarse iteration launches
 hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, int maxit, double rtol, hipStream_t st);
+// exact solve of the level's condensed system by fast diagonalization: x = Hhat^-1 b
+void launch_fd_solve(const Layout& L, const FdTabs& fd, double lam, const double* b, double* x, hipStream_t st);
 void launch_publish(const double* sc, int n, int64_t* cnt, HostMail* mail, hipStream_t st);
 void launch_pcg_start(const double* F, double* r, double* s, double* u, double* p, double* delta, int64_t n,
                       hipStream_t st);

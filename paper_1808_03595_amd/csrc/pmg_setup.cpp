@@ -285,6 +285,38 @@ void build_block_tables(int p, const std::vector<double>& h, int np, std::vector
     }
 }
 
+// Exact coarse solve by fast diagonalization of the whole mesh: along one
+// direction, the assembled 1D GLL mass (diagonal) and stiffness on the
+// n p + 1 nodes, the two Dirichlet end nodes removed, and their generalized
+// eigenpairs S^T L S = diag(mu), S^T M S = I.  Outputs (m = n p - 1):
+// Af[k][i] = S[i][k] (forward transform), Ab[i][k] = S[i][k] (backward), mu.
+void build_fd_tables(int p, const std::vector<double>& h, std::vector<double>& Af, std::vector<double>& Ab,
+                     std::vector<double>& mu) {
+    std::vector<double> x, w, Ls;
+    gll_nodes_weights(p, x, w);
+    stiffness_std(p, x, w, Ls);
+    const int n = (int)h.size(), N = n * p + 1, m = N - 2, n1 = p + 1;
+    std::vector<double> M(N, 0.0), L((size_t)N * N, 0.0);
+    for (int e = 0; e < n; ++e)
+        for (int a = 0; a < n1; ++a) {
+            M[e * p + a] += 0.5 * h[e] * w[a];
+            for (int b = 0; b < n1; ++b) L[(size_t)(e * p + a) * N + e * p + b] += (2.0 / h[e]) * Ls[a * n1 + b];
+        }
+    std::vector<double> Li((size_t)m * m), Mi(m), S;
+    for (int a = 0; a < m; ++a) {
+        Mi[a] = M[a + 1];
+        for (int b = 0; b < m; ++b) Li[(size_t)a * m + b] = L[(size_t)(a + 1) * N + b + 1];
+    }
+    gen_eig_diag(m, Li.data(), Mi.data(), S, mu);
+    Af.assign((size_t)m * m, 0.0);
+    Ab.assign((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i)
+        for (int k = 0; k < m; ++k) {
+            Af[(size_t)k * m + i] = S[(size_t)i * m + k];
+            Ab[(size_t)i * m + k] = S[(size_t)i * m + k];
+        }
+}
+
 void build_level_tables(int p, int pc, const std::vector<double> h[3], HostTables& t) {
     std::vector<double> x, w, Ls;
     gll_nodes_weights(p, x, w);
