@@ -213,7 +213,9 @@ int pmg_recover_interior(pmg_mesh *m, const double *d_f, const double *d_uhat,
 /* Whole solve of Alg. 5 (Krylov-accelerated MG, inexact preconditioned
  * CG): condense, iterate until |r| <= rtol |r_0| or maxit, recover.
  * precond_dtype PMG_F32 uses the mixed-precision cycle (FP32 V-cycle on
- * r/|r| inside FP64 CG; FP64 residuals, dots and coarse solve).  d_f, d_u:
+ * r/|r| inside FP64 CG; FP64 residuals, dots and coarse solve); with no
+ * smoothed level (p <= 2 and no degree-1 levels) the cycle is the FP64
+ * coarse solve alone and runs in FP64 for either value.  d_f, d_u:
  * grids (FP64).  Synchronizes the stream before filling *h_stats (may be
  * NULL).  Returns 0, PMG_NOT_CONVERGED or PMG_BREAKDOWN, or an error. */
 int pmg_pcg_solve(pmg_mesh *m, const double *d_f, double *d_u, double rtol,

@@ -207,6 +207,17 @@ int fill_tabs(pmg_mesh* m, LevelTabs<T>& tb, const HostTables& t, const Layout& 
         if ((rc = m->upload(&tb.st_SP[d], t.st_SP[d]))) break;
         if ((rc = m->upload(&tb.st_lamP[d], t.st_lamP[d]))) break;
         if (!t.ax[d].empty() && (rc = m->upload(&tb.ax[d], t.ax[d]))) break;
+        // per element: m, L, Sinv, MS, lam, c0, cp contiguous
+        const int p = lay.p, n1 = p + 1, q = p - 1, ne = lay.n[d];
+        const std::vector<double>* src[7] = {&t.el_m[d], &t.el_L[d], &t.el_Sinv[d], &t.el_MS[d],
+                                             &t.el_lam[d], &t.el_c0[d], &t.el_cp[d]};
+        const size_t sz[7] = {(size_t)n1, (size_t)n1 * n1, (size_t)q * q, (size_t)q * q, (size_t)q, (size_t)q, (size_t)q};
+        std::vector<double> pack;
+        for (int e = 0; e < ne; ++e)
+            for (int k = 0; k < 7; ++k)
+                if (sz[k] && src[k]->size() >= (e + 1) * sz[k])
+                    pack.insert(pack.end(), src[k]->begin() + e * sz[k], src[k]->begin() + (e + 1) * sz[k]);
+        if ((rc = m->upload(&tb.el_pack[d], pack))) break;
     }
     if (!rc) rc = m->upload(&tb.st_wP, t.st_wP);
     if (!rc) rc = m->upload(&tb.st_w, t.st_w);
@@ -1202,6 +1213,9 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
     if (!f || !ug) return fail(PMG_EINVAL, "null pointer");
     if (!(rtol >= 0.0) || maxit < 0) return fail(PMG_EINVAL, "bad tolerance or iteration limit");
     if (pdt != PMG_F64 && pdt != PMG_F32) return fail(PMG_EINVAL, "bad dtype");
+    // with no smoothed level the cycle is the coarse solve alone, which runs
+    // in FP64 either way: an FP32 cycle would only round r and z
+    if (m->act.size() == 1) pdt = PMG_F64;
     const Layout& Lf = m->lv.back().lay;
     const int64_t n = Lf.len;
     pmg_stats stats;

@@ -57,6 +57,10 @@ struct LevelTabs {
     const T* el_lam[3];   // (p-1)        interior eigenvalues
     const T* el_c0[3];    // (p-1)        S^T L[I,0]
     const T* el_cp[3];    // (p-1)        S^T L[I,p]
+    // the seven tables above packed per element, in that order (m, L, Sinv,
+    // MS, lam, c0, cp): one contiguous block of elem_table_size(p) / 3
+    // entries per direction and element
+    const T* el_pack[3];
     // star tables, direction d, vertex v: offsets v * size
     const T* st_S[3];     // nS^2         [i][k], identity padded
     const T* st_lam[3];   // nS           padded eigenvalues = 1

@@ -47,6 +47,16 @@ __device__ __forceinline__ T* pick3(int d, T* a0, T* a1, T* a2) {
 // robin, b -> b % 8.  Work item of workgroup b such that every XCD gets one
 // contiguous range of items (neighbouring stars and elements share data).
 // A bijection of [0, G); only locality depends on the dispatch order.
+// Reciprocal without the full division sequence: the hardware estimate
+// (FP32: within 1 ulp; FP64: relative error ~5e-8) refined in FP64 by one
+// Newton step, d > 0.
+__device__ __forceinline__ float recip(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double recip(double d) {
+    const double r = __builtin_amdgcn_rcp(d);
+    const double e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int G) {
     const int x = b & 7, i = b >> 3, q = G >> 3, r = G & 7;
     return x * q + (x < r ? x : r) + i;
@@ -766,6 +776,82 @@ __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restri
 // six face tiles) goes to the workspace opE; k_gather_elem sums the
 // contributions of all elements at each skeleton node.
 // ---------------------------------------------------------------------------
+// One wavefront per element, compile-time degree P: the element's 1D tables
+// (per direction one contiguous block m[n1] L[n1^2] Sinv[q^2] MS[q^2] lm[q]
+// c0[q] cp[q], tab_d entries) into `tabs`, and its six face tiles of u into
+// `tile` ([f][r][c], (p+1)^2 each; f = 2d + s, rows / columns along
+// tile_rdir(d) / tile_cdir(d)).  All global loads are issued before the first
+// LDS store, so their latencies overlap.  A tile is the (p+1) x (p+1) window
+// of its own plane (wave-uniform base, plain row-major addressing); its rim
+// nodes that a lower plane family stores hold 0 there and are copied from
+// the tiles of that family afterwards.  Ends with a barrier.
+template <typename T, int P>
+__device__ inline void stage_elem_pack_and_tiles(const LevelTabs<T>& tb, const int e[3], const T* __restrict__ u,
+                                                 T* tabs, T* tile) {
+    constexpr int n1 = P + 1, q = P - 1, t2 = n1 * n1;
+    constexpr int TD0 = n1 + n1 * n1 + 2 * q * q + 3 * q, NTD = (TD0 + 63) / 64, NU = (t2 + 63) / 64;
+    const Layout& L = tb.lay;
+    const int lane = threadIdx.x;
+    T tv[3][NTD], uv[6][NU];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T* src = tb.el_pack[d] + (size_t)e[d] * TD0;
+#pragma unroll
+        for (int k = 0; k < NTD; ++k) {
+            const int i = lane + 64 * k;
+            tv[d][k] = i < TD0 ? src[i] : (T)0;
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1, s = f & 1, dr = tile_rdir(d), dc = tile_cdir(d);
+        const int64_t base = (d == 0 ? L.plane0(e[0] + s) : (d == 1 ? L.plane1(e[1] + s) : L.plane2(e[2] + s))) +
+                             (int64_t)(e[dr] * P) * L.pitch[d] + e[dc] * P;
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+            const int i = lane + 64 * k, r = i / n1, c = i - r * n1;
+            uv[f][k] = i < t2 ? u[base + (int64_t)r * L.pitch[d] + c] : (T)0;
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int k = 0; k < NTD; ++k)
+            if (lane + 64 * k < TD0) tabs[d * TD0 + lane + 64 * k] = tv[d][k];
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+#pragma unroll
+        for (int k = 0; k < NU; ++k)
+            if (lane + 64 * k < t2) tile[f * t2 + lane + 64 * k] = uv[f][k];
+    __syncthreads();
+    // rims stored by a lower family: x2-face columns 0, P (x1-planes) from the
+    // x1-faces; x3-face columns 0, P from the x1-faces, rows 0, P (x2-planes)
+    // from the x2-faces
+    constexpr int n2r = 2 * 2 * n1, n3r = 2 * (2 * n1 + 2 * (n1 - 2));
+    for (int i = lane; i < n2r + n3r; i += 64) {
+        int f, r, c, src;
+        if (i < n2r) {
+            const int s2 = i / (2 * n1), k = i - s2 * 2 * n1, side = k / n1;
+            f = 2 + s2; r = k - side * n1; c = side * P;
+            src = side * t2 + r * n1 + s2 * P;               // face (0, side): [x3][x2]
+        } else {
+            const int k0 = i - n2r, s3 = k0 / (n3r / 2), k = k0 - s3 * (n3r / 2);
+            f = 4 + s3;
+            if (k < 2 * n1) {                                // columns 0, P: x1-planes
+                const int side = k / n1;
+                r = k - side * n1; c = side * P;
+                src = side * t2 + (s3 * P) * n1 + r;          // face (0, side): [x3][x2]
+            } else {                                         // rows 0, P without the corners: x2-planes
+                const int kk = k - 2 * n1, side = kk / (n1 - 2);
+                r = side * P; c = 1 + kk - side * (n1 - 2);
+                src = (2 + side) * t2 + (s3 * P) * n1 + c;   // face (1, side): [x3][x1]
+            }
+        }
+        tile[f * t2 + r * n1 + c] = tile[src];
+    }
+    __syncthreads();
+}
+
 template <int P>
 struct K1Shape {
     static constexpr int n1 = P + 1, q = P - 1, t2 = n1 * n1, q2 = q * q;
@@ -797,50 +883,7 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
     color_coords(eid, -1, L.n, e);
     const T lam = tb.lam;
     T* out = tb.opE + (size_t)eid * 6 * t2;
-    // 1D tables of this element (per direction m[n1] L[n1^2] Si[q^2] MS[q^2]
-    // lm[q] c0[q] cp[q]) and the six face tiles: all global loads are issued
-    // before the first LDS store, so their latencies overlap
-    constexpr int NT = (K::tabs + 63) / 64, NU = (6 * t2 + 63) / 64;
-    T tv[NT], uv[NU];
-#pragma unroll
-    for (int k = 0; k < NT; ++k) {
-        const int i = lane + 64 * k;
-        T v = 0;
-        if (i < K::tabs) {
-            const int d = i / K::tab_d;
-            int o = i - d * K::tab_d;
-            const int ed = d == 0 ? e[0] : (d == 1 ? e[1] : e[2]);
-            const T* src;
-            if (o < n1) src = pick3(d, tb.el_m[0], tb.el_m[1], tb.el_m[2]) + ed * n1;
-            else if ((o -= n1) < n1 * n1) src = pick3(d, tb.el_L[0], tb.el_L[1], tb.el_L[2]) + ed * n1 * n1;
-            else if ((o -= n1 * n1) < q2) src = pick3(d, tb.el_Sinv[0], tb.el_Sinv[1], tb.el_Sinv[2]) + ed * q2;
-            else if ((o -= q2) < q2) src = pick3(d, tb.el_MS[0], tb.el_MS[1], tb.el_MS[2]) + ed * q2;
-            else if ((o -= q2) < q) src = pick3(d, tb.el_lam[0], tb.el_lam[1], tb.el_lam[2]) + ed * q;
-            else if ((o -= q) < q) src = pick3(d, tb.el_c0[0], tb.el_c0[1], tb.el_c0[2]) + ed * q;
-            else { o -= q; src = pick3(d, tb.el_cp[0], tb.el_cp[1], tb.el_cp[2]) + ed * q; }
-            v = src[o];
-        }
-        tv[k] = v;
-    }
-#pragma unroll
-    for (int k = 0; k < NU; ++k) {
-        const int i = lane + 64 * k;
-        T v = 0;
-        if (i < 6 * t2) {
-            const int f = i / t2, rc = i - f * t2, r = rc / n1, c = rc - r * n1;
-            int a1, a2, a3;
-            tile_node(P, f, r, c, a1, a2, a3);
-            v = u[elem_slot(L, e, a1, a2, a3)];
-        }
-        uv[k] = v;
-    }
-#pragma unroll
-    for (int k = 0; k < NT; ++k)
-        if (lane + 64 * k < K::tabs) tabs[lane + 64 * k] = tv[k];
-#pragma unroll
-    for (int k = 0; k < NU; ++k)
-        if (lane + 64 * k < 6 * t2) tile[lane + 64 * k] = uv[k];
-    __syncthreads();
+    stage_elem_pack_and_tiles<T, P>(tb, e, u, tabs, tile);
     // table of direction d (runtime d: offsets, not a pointer array, so
     // nothing is placed in private memory)
     constexpr int TD = K::tab_d;
@@ -895,7 +938,7 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
             for (int k1 = 0; k1 < q; ++k1) {
                 T v = Tc0(0)[k1] * g0 + Tcp(0)[k1] * g1 + a1 * G[2 * q2 + k3 * q + k1] +
                       b1 * G[3 * q2 + k3 * q + k1] + a2 * G[4 * q2 + k2 * q + k1] + b2 * G[5 * q2 + k2 * q + k1];
-                v = v / (dd + Tlm(0)[k1]);
+                v = v * recip(dd + Tlm(0)[k1]);
                 V[(k3 * q + k2) * q + k1] = v;
                 s0 += Tc0(0)[k1] * v;
                 sp += Tcp(0)[k1] * v;
@@ -2062,41 +2105,35 @@ __global__ void k_fd_scatter(Layout L, const double* __restrict__ b, double* __r
     X[t] = (on1 || on2 || on3) ? b[L.slot(i1, i2, i3, on1, on2)] : 0.0;
 }
 
-// Y[o][k][c] = sum_i A[k][i] X[o][i][c] for an m x m matrix A: one thread per
-// line (o, c) and a block of 16 outputs k; A staged in LDS in chunks of
-// 128 columns.
-constexpr int FD_KB = 16, FD_IC = 128;
-__global__ void __launch_bounds__(256) k_fd_pass(const double* __restrict__ A, const double* __restrict__ X,
-                                                 double* __restrict__ Y, int m, int64_t outer, int64_t inner) {
-    __shared__ double As[FD_KB * FD_IC];
-    const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int kb = blockIdx.y * FD_KB;
-    const bool ok = line < outer * inner;
-    const int64_t o = ok ? line / inner : 0, c = ok ? line - o * inner : 0;
-    const double* x = X + o * m * inner + c;
-    double acc[FD_KB];
-#pragma unroll
-    for (int k = 0; k < FD_KB; ++k) acc[k] = 0.0;
-    for (int i0 = 0; i0 < m; i0 += FD_IC) {
-        const int ni = min(FD_IC, m - i0);
-        for (int t = threadIdx.x; t < FD_KB * FD_IC; t += blockDim.x) {
-            const int k = t / FD_IC, i = t - k * FD_IC;
-            As[t] = (kb + k < m && i < ni) ? A[(int64_t)(kb + k) * m + i0 + i] : 0.0;
-        }
-        __syncthreads();
-        if (ok)
-            for (int i = 0; i < ni; ++i) {
-                const double xv = x[(int64_t)(i0 + i) * inner];
-#pragma unroll
-                for (int k = 0; k < FD_KB; ++k) acc[k] += As[k * FD_IC + i] * xv;
-            }
-        __syncthreads();
+// One 1D pass as a (batched) product on FP64 matrix cores: C[b][r][c] =
+// sum_k P[b][r][k] Q[b][k][c] with general strides, one wavefront per 16 x 16
+// tile of C (v_mfma_f64_16x16x4: lane (q, j) supplies P[j][k] and Q[k][j]
+// for k = k0 + q and receives C[q + 4 v][j]).
+struct FdMat {
+    const double* p;
+    int64_t rs, cs, bs;   // row, column and batch strides
+};
+__global__ void __launch_bounds__(64) k_fd_gemm(FdMat P, FdMat Q, double* __restrict__ C, int64_t c_rs, int64_t c_cs,
+                                                int64_t c_bs, int M, int N, int K, int tiles_n) {
+    typedef Mfma<double> MF;
+    const int lane = threadIdx.x, q = lane >> 4, j = lane & 15;
+    const int tr = blockIdx.x / tiles_n, tc = blockIdx.x - tr * tiles_n, b = blockIdx.y;
+    const int row = tr * 16 + j, col = tc * 16 + j;
+    const double* pp = P.p + b * P.bs + (int64_t)row * P.rs;
+    const double* qq = Q.p + b * Q.bs + (int64_t)col * Q.cs;
+    MF::v4 acc = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const int k = k0 + q;
+        const double a = (row < M && k < K) ? pp[(int64_t)k * P.cs] : 0.0;
+        const double bq = (col < N && k < K) ? qq[(int64_t)k * Q.rs] : 0.0;
+        acc = MF::mma(a, bq, acc);
     }
-    if (!ok) return;
-    double* y = Y + o * m * inner + c;
+    double* cc = C + b * c_bs;
 #pragma unroll
-    for (int k = 0; k < FD_KB; ++k)
-        if (kb + k < m) y[(int64_t)(kb + k) * inner] = acc[k];
+    for (int v = 0; v < 4; ++v) {
+        const int r = tr * 16 + MF::row(q, v);
+        if (r < M && col < N) cc[(int64_t)r * c_rs + (int64_t)col * c_cs] = acc[v];
+    }
 }
 
 __global__ void k_fd_scale(double* __restrict__ X, const double* __restrict__ mu1, const double* __restrict__ mu2,
@@ -2135,13 +2172,35 @@ void launch_fd_solve(const Layout& L, const FdTabs& fd, double lam, const double
     const int m1 = fd.m[0], m2 = fd.m[1], m3 = fd.m[2];
     const int64_t M = (int64_t)m1 * m2 * m3;
     hipLaunchKernelGGL(k_fd_scatter, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, L, b, fd.X, m1, m2, m3);
-    // direction d: outer / inner extents of the [m3][m2][m1] array
+    // direction d of the [m3][m2][m1] array X with the m x m matrix A
+    // (out[.., k, ..] = sum_i A[k][i] in[.., i, ..]):
+    //   d = 0: out[o][k] = sum_i in[o][i] A[k][i]        (o over m2 m3)
+    //   d = 1: out[o][k][c] = sum_i A[k][i] in[o][i][c]  (batch o over m3)
+    //   d = 2: out[k][c] = sum_i A[k][i] in[i][c]        (c over m1 m2)
     auto pass = [&](int d, const double* A, const double* in, double* out) {
         const int m = fd.m[d];
-        const int64_t inner = d == 0 ? 1 : (d == 1 ? m1 : (int64_t)m1 * m2);
-        const int64_t outer = M / ((int64_t)m * inner);
-        const dim3 g((unsigned)((outer * inner + 255) / 256), (unsigned)((m + FD_KB - 1) / FD_KB));
-        hipLaunchKernelGGL(k_fd_pass, g, dim3(256), 0, st, A, in, out, m, outer, inner);
+        int Mr, Nc, nb;
+        FdMat P, Q;
+        int64_t crs, ccs, cbs;
+        if (d == 0) {
+            Mr = m2 * m3; Nc = m1; nb = 1;
+            P = {in, m1, 1, 0};
+            Q = {A, 1, m, 0};
+            crs = m1; ccs = 1; cbs = 0;
+        } else if (d == 1) {
+            Mr = m2; Nc = m1; nb = m3;
+            P = {A, m, 1, 0};
+            Q = {in, m1, 1, (int64_t)m1 * m2};
+            crs = m1; ccs = 1; cbs = (int64_t)m1 * m2;
+        } else {
+            Mr = m3; Nc = m1 * m2; nb = 1;
+            P = {A, m, 1, 0};
+            Q = {in, (int64_t)m1 * m2, 1, 0};
+            crs = (int64_t)m1 * m2; ccs = 1; cbs = 0;
+        }
+        const int tn = (Nc + 15) / 16, tm = (Mr + 15) / 16;
+        hipLaunchKernelGGL(k_fd_gemm, dim3((unsigned)(tm * tn), (unsigned)nb), dim3(64), 0, st, P, Q, out, crs, ccs,
+                           cbs, Mr, Nc, m, tn);
     };
     pass(0, fd.Af[0], fd.X, fd.Y);
     pass(1, fd.Af[1], fd.Y, fd.X);
@@ -2755,42 +2814,50 @@ __global__ void __launch_bounds__(256) k_recover(LevelTabs<double> tb, const dou
 template <int P>
 struct CRShape {
     static constexpr int n1 = P + 1, q = P - 1, q2 = q * q, q3 = q2 * q, t2 = n1 * n1;
-    // one direction: m[n1] ST[q2] SS[q2] Si[q2] MS[q2] lm[q] c0[q] cp[q]
-    static constexpr int o_m = 0, o_ST = n1, o_SS = o_ST + q2, o_Si = o_SS + q2, o_MS = o_Si + q2,
-                         o_lm = o_MS + q2, o_c0 = o_lm + q, o_cp = o_c0 + q, tab_d = o_cp + q;
+    // per direction the packed tables m[n1] L[n1^2] Si[q2] MS[q2] lm[q] c0[q] cp[q]
+    static constexpr int o_m = 0, o_L = n1, o_Si = o_L + n1 * n1, o_MS = o_Si + q2, o_lm = o_MS + q2,
+                         o_c0 = o_lm + q, o_cp = o_c0 + q, tab_d = o_cp + q;
     static constexpr int tabs = 3 * tab_d;
-    // LDS: tables | a[q3] | b[q3] | G[6 q2] | tmp[6 q2] | tile[6 t2] (recovery)
-    static constexpr int o_a = tabs, o_b = o_a + q3, o_G = o_b + q3, o_tmp = o_G + 6 * q2, o_tile = o_tmp + 6 * q2,
-                         cond_total = o_tile, rec_total = o_tile + 6 * t2;
+    // then per direction ST[q2] SS[q2] (offsets from `tabs` of direction d: o_ST(d))
+    static constexpr int o_STS = tabs, sts = 3 * 2 * q2;
+    __host__ __device__ static constexpr int o_ST(int d) { return o_STS + d * 2 * q2; }
+    __host__ __device__ static constexpr int o_SS(int d) { return o_STS + d * 2 * q2 + q2; }
+    // LDS: tables | ST/SS | a[q3] | b[q3] | G[6 q2] | tmp[6 q2] | tile[6 t2] (recovery)
+    static constexpr int o_a = o_STS + sts, o_b = o_a + q3, o_G = o_b + q3, o_tmp = o_G + 6 * q2,
+                         o_tile = o_tmp + 6 * q2, cond_total = o_tile, rec_total = o_tile + 6 * t2;
 };
 
-// Stage the tables of element e (CRShape layout) into LDS.
+// The packed tables of element e into LDS (CRShape layout), then the interior
+// eigenvector matrices in both orientations: ST[k][i] = Sinv[k][i] / m[i+1],
+// SS[i][k] = MS[i][k] / m[i+1].  Ends with a barrier.
 template <int P>
-__device__ inline void cr_stage_tables(const LevelTabs<double>& tb, const int e[3], double* tabs) {
+__device__ inline void cr_stage_tables(const LevelTabs<double>& tb, const int e[3], double* sm) {
     using K = CRShape<P>;
-    constexpr int n1 = K::n1, q = K::q, q2 = K::q2;
+    constexpr int q = K::q, q2 = K::q2, TD0 = K::tab_d, NTD = (TD0 + 63) / 64;
     const int lane = threadIdx.x;
-    for (int i = lane; i < K::tabs; i += 64) {
-        const int d = i / K::tab_d, o = i - d * K::tab_d;
-        const int ed = d == 0 ? e[0] : (d == 1 ? e[1] : e[2]);
-        double v = 0.0;
-        if (o < K::o_ST) v = pick3(d, tb.el_m[0], tb.el_m[1], tb.el_m[2])[ed * n1 + o];
-        else if (o >= K::o_Si && o < K::o_MS) v = pick3(d, tb.el_Sinv[0], tb.el_Sinv[1], tb.el_Sinv[2])[ed * q2 + o - K::o_Si];
-        else if (o >= K::o_MS && o < K::o_lm) v = pick3(d, tb.el_MS[0], tb.el_MS[1], tb.el_MS[2])[ed * q2 + o - K::o_MS];
-        else if (o >= K::o_lm && o < K::o_c0) v = pick3(d, tb.el_lam[0], tb.el_lam[1], tb.el_lam[2])[ed * q + o - K::o_lm];
-        else if (o >= K::o_c0 && o < K::o_cp) v = pick3(d, tb.el_c0[0], tb.el_c0[1], tb.el_c0[2])[ed * q + o - K::o_c0];
-        else if (o >= K::o_cp) v = pick3(d, tb.el_cp[0], tb.el_cp[1], tb.el_cp[2])[ed * q + o - K::o_cp];
-        tabs[i] = v;
+    double tv[3][NTD];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double* src = tb.el_pack[d] + (size_t)e[d] * TD0;
+#pragma unroll
+        for (int k = 0; k < NTD; ++k) {
+            const int i = lane + 64 * k;
+            tv[d][k] = i < TD0 ? src[i] : 0.0;
+        }
     }
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int k = 0; k < NTD; ++k)
+            if (lane + 64 * k < TD0) sm[d * TD0 + lane + 64 * k] = tv[d][k];
     __syncthreads();
-    // ST[k][i] = Si[k][i] / m[i+1];  SS[i][k] = MS[i][k] / m[i+1]
     for (int i = lane; i < 3 * 2 * q2; i += 64) {
         const int d = i / (2 * q2), w = i - d * 2 * q2, which = w / q2, rc = w - which * q2;
-        double* t = tabs + d * K::tab_d;
+        const double* t = sm + d * TD0;
         const int col = which == 0 ? rc % q : rc / q;   // the interior index i
         const double mi = t[K::o_m + col + 1];
-        if (which == 0) t[K::o_ST + rc] = t[K::o_Si + rc] / mi;
-        else t[K::o_SS + rc] = t[K::o_MS + rc] / mi;
+        if (which == 0) sm[K::o_ST(d) + rc] = t[K::o_Si + rc] / mi;
+        else sm[K::o_SS(d) + rc] = t[K::o_MS + rc] / mi;
     }
     __syncthreads();
 }
@@ -2799,13 +2866,13 @@ __device__ inline void cr_stage_tables(const LevelTabs<double>& tb, const int e[
 // [i3][i2][i1]) with the matrices A_d (row-major q x q, out[k] = sum_i
 // A_d[k][i] in[i]) at offset `off` in each direction's table; x is
 // overwritten, y is scratch.  The result ends in x.
-template <int P>
-__device__ inline void cr_transform3(const double* tabs, int off, double* x, double* y) {
+template <int P, bool FWD>
+__device__ inline void cr_transform3(const double* tabs, double* x, double* y) {
     using K = CRShape<P>;
     constexpr int q = K::q, q2 = K::q2;
     const int lane = threadIdx.x;
     if (lane < q2) {   // x1 lines: (i2, i3) = (lane % q, lane / q)
-        const double* A = tabs + 0 * K::tab_d + off;
+        const double* A = tabs + (FWD ? K::o_ST(0) : K::o_SS(0));
         double v[q], w[q];
 #pragma unroll
         for (int i = 0; i < q; ++i) v[i] = x[lane * q + i];
@@ -2822,7 +2889,7 @@ __device__ inline void cr_transform3(const double* tabs, int off, double* x, dou
     __syncthreads();
     if (lane < q2) {   // x2 lines: (i1, i3) = (lane % q, lane / q)
         const int i1 = lane % q, i3 = lane / q;
-        const double* A = tabs + 1 * K::tab_d + off;
+        const double* A = tabs + (FWD ? K::o_ST(1) : K::o_SS(1));
         double v[q], w[q];
 #pragma unroll
         for (int i = 0; i < q; ++i) v[i] = y[(i3 * q + i) * q + i1];
@@ -2838,7 +2905,7 @@ __device__ inline void cr_transform3(const double* tabs, int off, double* x, dou
     }
     __syncthreads();
     if (lane < q2) {   // x3 lines: (i1, i2) = (lane % q, lane / q)
-        const double* A = tabs + 2 * K::tab_d + off;
+        const double* A = tabs + (FWD ? K::o_ST(2) : K::o_SS(2));
         double v[q], w[q];
 #pragma unroll
         for (int i = 0; i < q; ++i) v[i] = x[i * q2 + lane];
@@ -2885,10 +2952,10 @@ __global__ void __launch_bounds__(64) k_condense_w(LevelTabs<double> tb, const d
     const int eid = xcd_remap(blockIdx.x, gridDim.x);
     int e[3];
     color_coords(eid, -1, L.n, e);
-    cr_stage_tables<P>(tb, e, tabs);
+    cr_stage_tables<P>(tb, e, sm);
     cr_load_interior<P>(L, e, tabs, f, a);
     __syncthreads();
-    cr_transform3<P>(tabs, K::o_ST, a, b);          // a = (S x S x S)^T F_I
+    cr_transform3<P, true>(sm, a, b);          // a = (S x S x S)^T F_I
     const double lam = tb.lam;
     auto lm = [&](int d) { return tabs + d * TD + K::o_lm; };
     auto c0 = [&](int d) { return tabs + d * TD + K::o_c0; };
@@ -2900,7 +2967,7 @@ __global__ void __launch_bounds__(64) k_condense_w(LevelTabs<double> tb, const d
         double s0 = 0.0, sp = 0.0;
 #pragma unroll
         for (int k1 = 0; k1 < q; ++k1) {
-            const double v = a[lane * q + k1] / (dd + lm(0)[k1]);
+            const double v = a[lane * q + k1] * recip(dd + lm(0)[k1]);
             a[lane * q + k1] = v;
             s0 += c0(0)[k1] * v;
             sp += cp(0)[k1] * v;
@@ -2994,13 +3061,15 @@ __global__ void __launch_bounds__(64) k_recover_w(LevelTabs<double> tb, const do
     const int eid = xcd_remap(blockIdx.x, gridDim.x);
     int e[3];
     color_coords(eid, -1, L.n, e);
-    for (int i = lane; i < 6 * t2; i += 64) {
-        const int fc = i / t2, rc = i - fc * t2, r = rc / n1, c = rc - r * n1;
-        int a1, a2, a3;
-        tile_node(P, fc, r, c, a1, a2, a3);
-        tile[i] = uh[elem_slot(L, e, a1, a2, a3)];
+    stage_elem_pack_and_tiles<double, P>(tb, e, uh, tabs, tile);
+    for (int i = lane; i < 3 * 2 * q2; i += 64) {   // ST and SS (cr_stage_tables without the loads)
+        const int d = i / (2 * q2), w = i - d * 2 * q2, which = w / q2, rc = w - which * q2;
+        const double* t = tabs + d * TD;
+        const int col = which == 0 ? rc % q : rc / q;
+        const double mi = t[K::o_m + col + 1];
+        if (which == 0) sm[K::o_ST(d) + rc] = t[K::o_Si + rc] / mi;
+        else sm[K::o_SS(d) + rc] = t[K::o_MS + rc] / mi;
     }
-    cr_stage_tables<P>(tb, e, tabs);   // ends with a barrier: the tiles are in place too
     cr_load_interior<P>(L, e, tabs, f, a);
     // shell nodes owned by this element: a_d < p, or a_d = p on the last element
     for (int i = lane; i < n1 * n1 * n1; i += 64) {
@@ -3014,7 +3083,7 @@ __global__ void __launch_bounds__(64) k_recover_w(LevelTabs<double> tb, const do
             is_dir(L, i1, i2, i3) ? 0.0 : shell_value(tile, P, a1, a2, a3);
     }
     __syncthreads();
-    cr_transform3<P>(tabs, K::o_ST, a, b);          // a = (S x S x S)^T F_I
+    cr_transform3<P, true>(sm, a, b);          // a = (S x S x S)^T F_I
     // G_f = Si_R X_f Si_C^T on the face interiors
     for (int ii = lane; ii < 6 * q; ii += 64) {
         const int fc = ii / q, r = ii - fc * q;
@@ -3062,11 +3131,11 @@ __global__ void __launch_bounds__(64) k_recover_w(LevelTabs<double> tb, const do
             const double ex = c00[k1] * g0 + cp0[k1] * g1 + a1 * G[2 * q2 + k3 * q + k1] +
                               b1 * G[3 * q2 + k3 * q + k1] + a2 * G[4 * q2 + k2 * q + k1] +
                               b2 * G[5 * q2 + k2 * q + k1];
-            a[lane * q + k1] = (a[lane * q + k1] - ex) / (dd + lm0[k1]);
+            a[lane * q + k1] = (a[lane * q + k1] - ex) * recip(dd + lm0[k1]);
         }
     }
     __syncthreads();
-    cr_transform3<P>(tabs, K::o_SS, a, b);          // u_I = (S x S x S) V
+    cr_transform3<P, false>(sm, a, b);          // u_I = (S x S x S) V
     for (int i = lane; i < K::q3; i += 64) {
         const int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
         const int i1 = e[0] * P + 1 + k1, i2 = e[1] * P + 1 + k2, i3 = e[2] * P + 1 + k3;
