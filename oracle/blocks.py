@@ -213,6 +213,8 @@ class _Blocks:
     """Block index maps and gathered 1D tables for a mesh."""
 
     def __init__(self, mesh: Mesh, weights="smooth"):
+        if not mesh.all_dirichlet():
+            raise NotImplementedError("element-centred blocks: Dirichlet boundaries only")
         p = mesh.p
         nS = 3 * p - 1
         n1, n2, n3 = mesh.n

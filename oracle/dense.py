@@ -95,19 +95,21 @@ class CondensedSystem:
         return u.reshape(self.mesh.shape)
 
     def full_solve(self, F_grid):
-        """u* = H^-1 F on the non-Dirichlet nodes (brute force)."""
-        free = np.flatnonzero(~self.mesh.dirichlet_mask().ravel())
+        """u* = H^-1 F on the unknowns (brute force); mirror entries of a
+        periodic direction repeat the first layer."""
+        free = np.flatnonzero(self.mesh.free_mask().ravel())
         F = np.asarray(F_grid).ravel()
         u = np.zeros(F.size)
         u[free] = np.linalg.solve(self.H[np.ix_(free, free)], F[free])
-        return u.reshape(self.mesh.shape)
+        return self.mesh.expand_periodic(u.reshape(self.mesh.shape))
 
     # ---- stars ---------------------------------------------------------
     def star_nodes(self, v):
         """Free skeleton nodes of the star around vertex v = (v1, v2, v3).
 
         The star consists of the three planes through the vertex, restricted
-        to the window of offsets -(p-1)..(p-1) in every direction.
+        to the window of offsets -(p-1)..(p-1) in every direction; in a
+        periodic direction the window continues across the seam.
         Returns (flat grid indices, offsets (k, 3) as (o1, o2, o3)).
         """
         m = self.mesh
@@ -121,6 +123,8 @@ class CondensedSystem:
                     if o1 != 0 and o2 != 0 and o3 != 0:
                         continue
                     i1, i2, i3 = ctr[0] + o1, ctr[1] + o2, ctr[2] + o3
+                    i1, i2, i3 = (int(m.wrap(0, i1)), int(m.wrap(1, i2)),
+                                  int(m.wrap(2, i3)))
                     if not (0 <= i1 < m.N[0] and 0 <= i2 < m.N[1]
                             and 0 <= i3 < m.N[2]):
                         continue
@@ -131,9 +135,10 @@ class CondensedSystem:
         return np.array(out, dtype=np.int64), np.array(offs).reshape(-1, 3)
 
     def vertices(self):
-        n1, n2, n3 = self.mesh.n
-        return [(a, b, c) for c in range(n3 + 1) for b in range(n2 + 1)
-                for a in range(n1 + 1)]
+        m = self.mesh
+        n1, n2, n3 = (m.n[d] + (0 if m.periodic[d] else 1) for d in range(3))
+        return [(a, b, c) for c in range(n3) for b in range(n2)
+                for a in range(n1)]
 
     def star_operator(self, v):
         g, _ = self.star_nodes(v)
@@ -172,6 +177,8 @@ def block_nodes(cs: CondensedSystem, e):
     """
     m = cs.mesh
     p = m.p
+    if not m.all_dirichlet():
+        raise NotImplementedError("element-centred blocks: Dirichlet boundaries only")
     lo = [(e[d] - 1) * p for d in range(3)]
     out, offs = [], []
     for i3 in range(max(lo[2] + 1, 0), min(lo[2] + 3 * p, m.N[2])):
@@ -233,6 +240,15 @@ def prolongation_matrix(mesh_c: Mesh, mesh_f: Mesh):
     P2 = interp_1d_global(mesh_c.h[1], mesh_c.p, mesh_f.p)
     P3 = interp_1d_global(mesh_c.h[2], mesh_c.p, mesh_f.p)
     full = np.kron(P3, np.kron(P2, P1))
+    # periodic: the value at a coarse mirror node is the value at the node
+    # it repeats, so its column adds to that node's column
+    Nc = mesh_c.N
+    i3, i2, i1 = np.meshgrid(np.arange(Nc[2]), np.arange(Nc[1]), np.arange(Nc[0]), indexing="ij")
+    j1, j2, j3 = mesh_c.wrap(0, i1), mesh_c.wrap(1, i2), mesh_c.wrap(2, i3)
+    canon = ((j3 * Nc[1] + j2) * Nc[0] + j1).ravel()
+    folded = np.zeros_like(full)
+    for col in range(full.shape[1]):
+        folded[:, canon[col]] += full[:, col]
     rows = np.flatnonzero(mesh_f.free_skeleton_mask().ravel())
     cols = np.flatnonzero(mesh_c.free_skeleton_mask().ravel())
-    return full[np.ix_(rows, cols)]
+    return folded[np.ix_(rows, cols)]

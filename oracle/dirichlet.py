@@ -37,6 +37,8 @@ def apply_H(mesh: Mesh, u_grid):
 def lift_rhs(mesh: Mesh, f_grid, g_grid):
     """f' = f - M^-1 H G on the free nodes and 0 on the boundary, where G
     takes the boundary values of g and is zero inside."""
+    if not mesh.all_dirichlet():
+        raise NotImplementedError("lifting: Dirichlet data on every side")
     D = mesh.dirichlet_mask()
     G = np.where(D, np.asarray(g_grid, dtype=np.float64), 0.0)
     fp = np.asarray(f_grid, dtype=np.float64) - apply_H(mesh, G) / mesh.assembled_mass()
@@ -52,6 +54,8 @@ def solve(mesh: Mesh, f_grid, g_grid, method="kMG", rtol=1e-10, maxit=200, **hkw
 
 
 def exact_solve(mesh: Mesh, f_grid, g_grid):
+    if not mesh.all_dirichlet():
+        raise NotImplementedError("lifting: Dirichlet data on every side")
     """Brute force on tiny meshes: u_D = g_D and
     u_f = H_ff^-1 ((M f)_f - H_fD g_D) with the dense assembled H."""
     H = dense.assemble_H(mesh)

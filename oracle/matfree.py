@@ -176,7 +176,7 @@ def recover_interior(mesh: Mesh, f_grid, uhat_grid):
     p = mesh.p
     u = np.where(el.free, np.asarray(uhat_grid), 0.0)
     if p < 2:
-        return u
+        return mesh.expand_periodic(u)
     F = mesh.assembled_mass() * np.asarray(f_grid)
     ue = el.gather(u)
     ue = np.where(el.inner[None], 0.0, ue)
@@ -184,30 +184,33 @@ def recover_interior(mesh: Mesh, f_grid, uhat_grid):
     uI = el.HII_inv(w)
     out = u.ravel().copy()
     out[el.idx[:, 1:p, 1:p, 1:p].ravel()] = uI.ravel()
-    return out.reshape(mesh.shape)
+    return mesh.expand_periodic(out.reshape(mesh.shape))
 
 
 # --------------------------------------------------------------------------
 # stars (Sec. 3)
 # --------------------------------------------------------------------------
-def star_tables_1d(hs, p, v):
+def star_tables_1d(hs, p, v, bc=("D", "D")):
     """1D star matrices for vertex index v on the element widths ``hs``.
 
     The 2-element block around the vertex is assembled on positions -p..p,
     the outer ends +-p are dropped (homogeneous local problem), leaving
-    n_S = 2p-1 positions.  Positions outside the domain (ghost element) and
-    a Dirichlet vertex are decoupled: S = identity and eigenvalue 1 there,
-    the eigenpairs of the remaining block fill the rest (Sec. 3.3).
-    Returns (S, lam, coupled mask) with S^T M S = I, S^T L S = diag(lam) on
-    the coupled block.
+    n_S = 2p-1 positions.  Sec. 3.3: positions outside the domain (ghost
+    element beyond a Dirichlet or Neumann side) are decoupled, and so is a
+    Dirichlet vertex: S = identity and eigenvalue 1 there, the eigenpairs of
+    the remaining block fill the rest.  A Neumann vertex stays coupled; in a
+    periodic direction the ghost element is element n-1 (v = 0) and nothing
+    is decoupled.  Returns (S, lam, coupled mask) with S^T M S = I,
+    S^T L S = diag(lam) on the coupled block.
     """
     n = len(hs)
     nS = 2 * p - 1
+    per = bc[0] == "P"
     M = np.zeros(2 * p + 1)
     L = np.zeros((2 * p + 1, 2 * p + 1))
     coupled = np.zeros(2 * p + 1, dtype=bool)
-    if v >= 1:
-        m, Le = sem1d.element_matrices(p, hs[v - 1])
+    if v >= 1 or per:
+        m, Le = sem1d.element_matrices(p, hs[(v - 1) % n])
         M[0:p + 1] += m
         L[0:p + 1, 0:p + 1] += Le
         coupled[0:p + 1] = True
@@ -216,7 +219,7 @@ def star_tables_1d(hs, p, v):
         M[p:2 * p + 1] += m
         L[p:2 * p + 1, p:2 * p + 1] += Le
         coupled[p:2 * p + 1] = True
-    if v == 0 or v == n:
+    if (v == 0 and bc[0] == "D") or (v == n and bc[1] == "D"):
         coupled[p] = False          # Dirichlet vertex
     M, L, coupled = M[1:2 * p], L[1:2 * p, 1:2 * p], coupled[1:2 * p]
     S = np.eye(nS)
@@ -308,16 +311,18 @@ class _Stars:
         nS = 2 * p - 1
         n1, n2, n3 = mesh.n
         N1, N2, N3 = mesh.N
+        # one star per vertex; in a periodic direction vertex n_d is vertex 0
+        nv = [mesh.n[d] + (0 if mesh.periodic[d] else 1) for d in range(3)]
         tabs = []
         for d in range(3):
             Ss, ls = [], []
-            for v in range(mesh.n[d] + 1):
-                S, lam, _ = star_tables_1d(mesh.h[d], p, v)
+            for v in range(nv[d]):
+                S, lam, _ = star_tables_1d(mesh.h[d], p, v, mesh.bc[d])
                 Ss.append(S)
                 ls.append(lam)
             tabs.append((np.array(Ss), np.array(ls)))
-        v3, v2, v1 = np.meshgrid(np.arange(n3 + 1), np.arange(n2 + 1),
-                                 np.arange(n1 + 1), indexing="ij")
+        v3, v2, v1 = np.meshgrid(np.arange(nv[2]), np.arange(nv[1]),
+                                 np.arange(nv[0]), indexing="ij")
         v1, v2, v3 = v1.ravel(), v2.ravel(), v3.ravel()
         self.v = (v1, v2, v3)
         self.S = [tabs[0][0][v1], tabs[1][0][v2], tabs[2][0][v3]]
@@ -327,6 +332,7 @@ class _Stars:
         self.sentinel = sentinel
 
         def flat(i1, i2, i3):
+            i1, i2, i3 = mesh.wrap(0, i1), mesh.wrap(1, i2), mesh.wrap(2, i3)
             ok = ((i1 >= 0) & (i1 < N1) & (i2 >= 0) & (i2 < N2)
                   & (i3 >= 0) & (i3 < N3))
             return np.where(ok, (i3 * N2 + i2) * N1 + i1, sentinel)
@@ -395,7 +401,11 @@ def smoother(mesh: Mesh, r_grid, omega: float = 1.0, route: str = "tpc",
 # --------------------------------------------------------------------------
 # grid transfers (Sec. 4.1)
 # --------------------------------------------------------------------------
-def _interp_1d(hs, pc, pf):
+def _interp_1d(hs, pc, pf, periodic=False):
+    """Element-wise Lagrange interpolation from degree pc to pf along one
+    direction (rows fine nodes, columns coarse nodes).  Periodic: the last
+    coarse node is the first one, so its column is added to the first, and
+    the last fine node (a mirror) gets no row."""
     n = len(hs)
     xc, _ = sem1d.gll(pc)
     xf, _ = sem1d.gll(pf)
@@ -403,12 +413,16 @@ def _interp_1d(hs, pc, pf):
     P = np.zeros((n * pf + 1, n * pc + 1))
     for e in range(n):
         P[e * pf: e * pf + pf + 1, e * pc: e * pc + pc + 1] = J
+    if periodic:
+        P[:, 0] += P[:, -1]
+        P[:, -1] = 0.0
+        P[-1, :] = 0.0
     return P
 
 
 def prolong(mesh_c: Mesh, mesh_f: Mesh, uc_grid):
     """Fine condensed values = 3D tensor interpolation of the coarse ones."""
-    P = [_interp_1d(mesh_c.h[d], mesh_c.p, mesh_f.p) for d in range(3)]
+    P = [_interp_1d(mesh_c.h[d], mesh_c.p, mesh_f.p, mesh_c.periodic[d]) for d in range(3)]
     u = np.where(mesh_c.free_skeleton_mask(), np.asarray(uc_grid), 0.0)
     u = np.einsum("ia,cba->cbi", P[0], u, optimize=True)
     u = np.einsum("ib,cba->cia", P[1], u, optimize=True)
@@ -418,7 +432,7 @@ def prolong(mesh_c: Mesh, mesh_f: Mesh, uc_grid):
 
 def restrict(mesh_f: Mesh, mesh_c: Mesh, rf_grid):
     """Exact transpose of ``prolong`` on the condensed unknowns."""
-    P = [_interp_1d(mesh_c.h[d], mesh_c.p, mesh_f.p) for d in range(3)]
+    P = [_interp_1d(mesh_c.h[d], mesh_c.p, mesh_f.p, mesh_c.periodic[d]) for d in range(3)]
     r = np.where(mesh_f.free_skeleton_mask(), np.asarray(rf_grid), 0.0)
     r = np.einsum("ia,cbi->cba", P[0], r, optimize=True)
     r = np.einsum("ib,cia->cba", P[1], r, optimize=True)
@@ -453,8 +467,11 @@ def _h_interp_1d(hf):
 
 
 def h_prolong(mesh_c: Mesh, mesh_f: Mesh, uc_grid):
-    """Trilinear interpolation of degree-1 nodal values from the merged mesh."""
+    """Trilinear interpolation of degree-1 nodal values from the merged mesh
+    (homogeneous Dirichlet boundaries only)."""
     assert mesh_c.p == 1 and mesh_f.p == 1
+    if not (mesh_c.all_dirichlet() and mesh_f.all_dirichlet()):
+        raise NotImplementedError("degree-1 h-levels: Dirichlet boundaries only")
     P = [_h_interp_1d(mesh_f.h[d]) for d in range(3)]
     u = np.where(mesh_c.free_skeleton_mask(), np.asarray(uc_grid), 0.0)
     u = np.einsum("ia,cba->cbi", P[0], u, optimize=True)
@@ -465,6 +482,8 @@ def h_prolong(mesh_c: Mesh, mesh_f: Mesh, uc_grid):
 
 def h_restrict(mesh_f: Mesh, mesh_c: Mesh, rf_grid):
     """Exact transpose of ``h_prolong``."""
+    if not (mesh_c.all_dirichlet() and mesh_f.all_dirichlet()):
+        raise NotImplementedError("degree-1 h-levels: Dirichlet boundaries only")
     P = [_h_interp_1d(mesh_f.h[d]) for d in range(3)]
     r = np.where(mesh_f.free_skeleton_mask(), np.asarray(rf_grid), 0.0)
     r = np.einsum("ia,cbi->cba", P[0], r, optimize=True)

@@ -3,11 +3,19 @@
 Sec. 2.1: elements are cuboids of dimensions h_{1,e} x h_{2,e} x h_{3,e};
 Sec. 5.4: geometrically stretched meshes with a constant expansion factor
 alpha (h_{k+1} = alpha h_k, maximum aspect ratio alpha^(n-1));
-Sec. 5.3: anisotropic brick meshes.  Homogeneous Dirichlet conditions on the
-whole boundary.
+Sec. 5.3: anisotropic brick meshes.
+
+Boundary conditions (Sec. 3.3) are set per direction and side: homogeneous
+Dirichlet ("D", the default on every side), homogeneous Neumann ("N": the
+boundary nodes are unknowns and the natural condition holds), or periodic
+("P", both sides of a direction).  In a periodic direction the last node
+layer i_d = N_d - 1 is the first one again: the grid keeps it as a mirror
+entry that holds no unknown, and the element-to-node map wraps onto the
+first layer, so the two neighbours of the seam are coupled by assembly.
 
 Node grids have shape (N3, N2, N1), N_d = n_d p + 1, x1 fastest.  Element
-e = (e1, e2, e3) owns the nodes i_d in [e_d p, e_d p + p].
+e = (e1, e2, e3) owns the nodes i_d in [e_d p, e_d p + p] (taken modulo
+N_d - 1 in a periodic direction).
 """
 from __future__ import annotations
 
@@ -26,10 +34,33 @@ def stretched_widths(n: int, alpha: float, length: float = 1.0):
     return h * (length / h.sum())
 
 
-class Mesh:
-    """Element widths per direction, polynomial degree and Helmholtz lambda."""
+def parse_bc(bc):
+    """Normalise a boundary specification to ((lo, hi), ...) per direction.
 
-    def __init__(self, hx, hy, hz, p: int, lam: float):
+    ``bc`` is None (Dirichlet everywhere) or three entries, each "P"
+    (periodic), a single kind "D"/"N" for both sides, or a pair (lo, hi) of
+    kinds; a six-letter string "DNPPDD" lists (lo, hi) for x1, x2, x3.
+    """
+    if bc is None:
+        return (("D", "D"),) * 3
+    if isinstance(bc, str) and len(bc) == 6:
+        bc = [bc[0:2], bc[2:4], bc[4:6]]
+    out = []
+    for b in bc:
+        if isinstance(b, str) and len(b) == 1:
+            b = (b, b)
+        lo, hi = b[0], b[1]
+        if lo not in "DNP" or hi not in "DNP" or (("P" in (lo, hi)) and lo != hi):
+            raise ValueError(f"bad boundary specification {bc!r}")
+        out.append((lo, hi))
+    return tuple(out)
+
+
+class Mesh:
+    """Element widths per direction, polynomial degree, Helmholtz lambda and
+    boundary conditions."""
+
+    def __init__(self, hx, hy, hz, p: int, lam: float, bc=None):
         self.h = [np.asarray(hx, dtype=np.float64),
                   np.asarray(hy, dtype=np.float64),
                   np.asarray(hz, dtype=np.float64)]
@@ -38,16 +69,52 @@ class Mesh:
         self.lam = float(lam)
         self.N = [nd * self.p + 1 for nd in self.n]
         self.shape = (self.N[2], self.N[1], self.N[0])
+        self.bc = parse_bc(bc)
+        self.periodic = [self.bc[d][0] == "P" for d in range(3)]
+        if not any("D" in b for b in self.bc) and self.lam <= 0.0:
+            raise ValueError("without a Dirichlet side the operator is singular for lambda <= 0")
+        for d in range(3):
+            if self.periodic[d] and self.n[d] < 3:
+                raise ValueError("a periodic direction needs at least 3 elements")
 
     @classmethod
-    def box(cls, n, p, lam, alpha=1.0, lengths=(1.0, 1.0, 1.0)):
+    def box(cls, n, p, lam, alpha=1.0, lengths=(1.0, 1.0, 1.0), bc=None):
         if np.isscalar(n):
             n = (n, n, n)
         ws = [stretched_widths(n[d], alpha, lengths[d]) for d in range(3)]
-        return cls(ws[0], ws[1], ws[2], p, lam)
+        return cls(ws[0], ws[1], ws[2], p, lam, bc)
 
     def with_degree(self, p: int) -> "Mesh":
-        return Mesh(self.h[0], self.h[1], self.h[2], p, self.lam)
+        return Mesh(self.h[0], self.h[1], self.h[2], p, self.lam, self.bc)
+
+    def all_dirichlet(self) -> bool:
+        return all(b == ("D", "D") for b in self.bc)
+
+    # ---- index maps -----------------------------------------------------
+    def global_1d(self, d: int):
+        """(n_d, p+1) node index of local node a of element e in direction d:
+        e p + a, wrapped modulo N_d - 1 in a periodic direction."""
+        g = np.arange(self.n[d])[:, None] * self.p + np.arange(self.p + 1)[None, :]
+        if self.periodic[d]:
+            g = g % (self.N[d] - 1)
+        return g
+
+    def wrap(self, d: int, i):
+        """Node index i (possibly outside 0..N_d-1) taken onto the node grid:
+        modulo N_d - 1 in a periodic direction, unchanged otherwise."""
+        return np.mod(i, self.N[d] - 1) if self.periodic[d] else i
+
+    def expand_periodic(self, grid):
+        """Copy of a node grid with each periodic direction's last layer set
+        to its first (the mirror entries repeat the unknowns they stand for)."""
+        g = np.array(grid, dtype=np.float64, copy=True)
+        if self.periodic[0]:
+            g[:, :, -1] = g[:, :, 0]
+        if self.periodic[1]:
+            g[:, -1, :] = g[:, 0, :]
+        if self.periodic[2]:
+            g[-1, :, :] = g[0, :, :]
+        return g
 
     # ---- coordinates --------------------------------------------------
     def coords_1d(self, d: int):
@@ -68,9 +135,30 @@ class Mesh:
     # ---- node classes -------------------------------------------------
     def dirichlet_mask(self):
         m = np.zeros(self.shape, dtype=bool)
-        m[0, :, :] = m[-1, :, :] = True
-        m[:, 0, :] = m[:, -1, :] = True
-        m[:, :, 0] = m[:, :, -1] = True
+        (a1, b1), (a2, b2), (a3, b3) = self.bc
+        if a3 == "D":
+            m[0, :, :] = True
+        if b3 == "D":
+            m[-1, :, :] = True
+        if a2 == "D":
+            m[:, 0, :] = True
+        if b2 == "D":
+            m[:, -1, :] = True
+        if a1 == "D":
+            m[:, :, 0] = True
+        if b1 == "D":
+            m[:, :, -1] = True
+        return m
+
+    def mirror_mask(self):
+        """Last node layer of each periodic direction (no unknown of its own)."""
+        m = np.zeros(self.shape, dtype=bool)
+        if self.periodic[0]:
+            m[:, :, -1] = True
+        if self.periodic[1]:
+            m[:, -1, :] = True
+        if self.periodic[2]:
+            m[-1, :, :] = True
         return m
 
     def skeleton_mask(self):
@@ -81,8 +169,13 @@ class Mesh:
         return (i1 % p == 0) | (i2 % p == 0) | (i3 % p == 0)
 
     def free_skeleton_mask(self):
-        """Unknowns of the condensed system: skeleton minus Dirichlet nodes."""
-        return self.skeleton_mask() & ~self.dirichlet_mask()
+        """Unknowns of the condensed system: skeleton minus Dirichlet and
+        mirror nodes."""
+        return self.skeleton_mask() & ~self.dirichlet_mask() & ~self.mirror_mask()
+
+    def free_mask(self):
+        """All unknowns of the full system (interior included)."""
+        return ~self.dirichlet_mask() & ~self.mirror_mask()
 
     def interior_mask(self):
         return ~self.skeleton_mask()
@@ -102,10 +195,9 @@ class Mesh:
         e3, e2, e1 = np.meshgrid(np.arange(n3), np.arange(n2), np.arange(n1),
                                  indexing="ij")
         e1, e2, e3 = e1.ravel(), e2.ravel(), e3.ravel()
-        loc = np.arange(p + 1)
-        g3 = e3[:, None] * p + loc[None, :]
-        g2 = e2[:, None] * p + loc[None, :]
-        g1 = e1[:, None] * p + loc[None, :]
+        g3 = self.global_1d(2)[e3]
+        g2 = self.global_1d(1)[e2]
+        g1 = self.global_1d(0)[e1]
         idx = (g3[:, :, None, None] * N2 + g2[:, None, :, None]) * N1 \
             + g1[:, None, None, :]
         return idx, e1, e2, e3
@@ -114,9 +206,10 @@ class Mesh:
         """Diagonal of the assembled GLL mass matrix on the node grid."""
         m = [np.zeros(self.N[d]) for d in range(3)]
         for d in range(3):
+            g = self.global_1d(d)
             for e, h in enumerate(self.h[d]):
                 me, _ = sem1d.element_matrices(self.p, h)
-                m[d][e * self.p: e * self.p + self.p + 1] += me
+                np.add.at(m[d], g[e], me)
         return m[2][:, None, None] * m[1][None, :, None] * m[0][None, None, :]
 
     def n_dof(self):

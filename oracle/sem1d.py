@@ -149,7 +149,11 @@ def gen_eig(L, M):
     approximate eigenvector matrix X to X (I + E), where, with R = I - X^T X
     and T = X^T A X, the eigenvalue estimates are t_ii / (1 - r_ii) and E
     has diagonal r_ii / 2 and off-diagonal (t_ij + lam_j r_ij) /
-    (lam_j - lam_i); the error contracts quadratically.  The last step and
+    (lam_j - lam_i); the error contracts quadratically.  Pairs whose
+    estimates lie within delta = 2 (||T - diag(lam)|| + ||A|| ||R||) of each
+    other are treated as one cluster, E_ij = r_ij / 2 (the same paper's rule
+    for multiple eigenvalues: periodic 1D problems have double ones), which
+    only re-orthonormalises the basis of the cluster.  The last step and
     the final Rayleigh quotients form R and T with compensated products, so
     that the small eigenvalues (~p^-4 of the largest at large p) come out
     with relative, not only absolute, accuracy; an FP64 solver alone leaves
@@ -174,7 +178,10 @@ def gen_eig(L, M):
         lam = np.diag(T) / (1 - np.diag(R))
         gap = lam[None, :] - lam[:, None]            # lam_j - lam_i
         np.fill_diagonal(gap, 1)
-        E = (T + lam[None, :] * R) / gap
+        delta = 2 * (np.linalg.norm((T - np.diag(lam)).astype(np.float64), 2)
+                     + np.linalg.norm(A.astype(np.float64), 2) * np.linalg.norm(R.astype(np.float64), 2))
+        near = np.abs(gap) <= delta
+        E = np.where(near, R / 2, (T + lam[None, :] * R) / np.where(near, 1, gap))
         np.fill_diagonal(E, np.diag(R) / 2)
         Q = Q + Q @ E
     AQ = _matmul2(A, Q)

@@ -59,6 +59,8 @@ class Hierarchy:
         # levels below p_0: degree 1 on the same mesh, then merged meshes
         hmeshes = []
         if hmg_levels > 0 and self.degs[0] >= 2:
+            if not mesh.all_dirichlet():
+                raise NotImplementedError("degree-1 h-levels: Dirichlet boundaries only")
             cur = mesh.with_degree(1)
             hmeshes.append(cur)
             for _ in range(hmg_levels - 1):
