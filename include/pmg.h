@@ -4,7 +4,8 @@
  *
  *        lambda u - Laplace(u) = f   on a box,  u = 0 on the boundary,
  *
- * (inhomogeneous boundary values u = g by lifting: pmg_pcg_solve_dirichlet),
+ * (inhomogeneous boundary values u = g by lifting: pmg_pcg_solve_dirichlet;
+ * homogeneous Neumann and periodic sides: pmg_create_mesh_bc),
  *
  * after Huismann, Stiller & Froehlich, "Scaling to the stars -- a linearly
  * scaling elliptic solver for p-multigrid" (arXiv 1808.03595).
@@ -30,6 +31,12 @@
  *    unknown is stored exactly once (edges and vertices in the first plane
  *    family that contains them); all other slots, and Dirichlet nodes, hold
  *    0.  Hence plain sums over a skeleton array are sums over the unknowns.
+ *    On a mesh with a periodic direction d (pmg_create_mesh_bc) the node
+ *    layer i_d = N_d - 1 repeats the layer i_d = 0: its skeleton slots carry
+ *    no unknown and are 0 between calls (calls that read element data fill
+ *    them for their duration and clear them again, also in inputs), and in
+ *    grid arrays that layer is written as a copy of the first and ignored on
+ *    input.
  *    Its length is pmg_skeleton_len(); the element type is FP64 (dtype
  *    PMG_F64) or FP32 (PMG_F32) as the call states.
  */
@@ -48,6 +55,7 @@ enum { PMG_F64 = 0, PMG_F32 = 1 };
 enum { PMG_OK = 0, PMG_EINVAL = -1, PMG_EHIP = -2, PMG_ENOMEM = -3,
        PMG_EUNSUP = -4, PMG_NOT_CONVERGED = 1, PMG_BREAKDOWN = 2 };
 enum { PMG_MAX_DEGREE = 48, PMG_MAX_HIST = 512, PMG_MAX_COARSE_IT = 1000000 };
+enum { PMG_BC_DIRICHLET = 0, PMG_BC_NEUMANN = 1, PMG_BC_PERIODIC = 2 };
 
 typedef struct {
     int iters;                    /* outer iterations performed            */
@@ -73,6 +81,24 @@ int pmg_create_mesh(int n1, int n2, int n3, int p, double lambda,
 int pmg_create_mesh_widths(int n1, int n2, int n3, int p, double lambda,
                            const double *h_hx, const double *h_hy,
                            const double *h_hz, pmg_mesh **out);
+
+/* As pmg_create_mesh_widths with a boundary kind per side (Sec. 3.3):
+ * h_bc[6] = (x1 low, x1 high, x2 low, x2 high, x3 low, x3 high), each
+ * PMG_BC_DIRICHLET (homogeneous, u = 0), PMG_BC_NEUMANN (homogeneous, zero
+ * normal derivative: the boundary nodes are unknowns, a flux enters through
+ * the right-hand side) or PMG_BC_PERIODIC (on both sides of a direction,
+ * which then needs n_d >= 3 elements).  The star of a boundary vertex keeps
+ * its size: the 1D star matrices are padded with identity where the ghost
+ * element lies outside the domain and at a Dirichlet vertex; in a periodic
+ * direction the ghost element is the last element.  Without a Dirichlet
+ * side lambda must be > 0 (else the operator is singular): PMG_EINVAL.
+ * Such a mesh always uses the exact coarse solve; pmg_set_coarse_solver(0),
+ * pmg_set_coarse_mg with levels > 0, pmg_set_smoother(1) and the lifting
+ * calls (pmg_lift_dirichlet, pmg_set_boundary, pmg_pcg_solve_dirichlet)
+ * return PMG_EUNSUP on it unless every side is Dirichlet. */
+int pmg_create_mesh_bc(int n1, int n2, int n3, int p, double lambda,
+                       const double *h_hx, const double *h_hy,
+                       const double *h_hz, const int *h_bc, pmg_mesh **out);
 
 void pmg_destroy_mesh(pmg_mesh *m);
 

@@ -22,6 +22,8 @@ F32 = 1
 MAX_HIST = 512
 NOT_CONVERGED = 1
 BREAKDOWN = 2
+EINVAL = -1
+EUNSUP = -4
 
 _lib = None
 
@@ -62,6 +64,7 @@ _FP = ctypes.POINTER(ctypes.c_float)
 SIGNATURES = {
     "pmg_create_mesh": (_I, [_I, _I, _I, _I, _D, _D, ctypes.POINTER(_VP)]),
     "pmg_create_mesh_widths": (_I, [_I, _I, _I, _I, _D, _DP, _DP, _DP, ctypes.POINTER(_VP)]),
+    "pmg_create_mesh_bc": (_I, [_I, _I, _I, _I, _D, _DP, _DP, _DP, _IP, ctypes.POINTER(_VP)]),
     "pmg_destroy_mesh": (None, [_VP]),
     "pmg_num_levels": (_I, [_VP, _IP]),
     "pmg_level_degree": (_I, [_VP, _I, _IP]),
@@ -284,6 +287,32 @@ def create_mesh_widths(hx, hy, hz, p, lam):
     h = _VP()
     _check(lib().pmg_create_mesh_widths(len(hx), len(hy), len(hz), p, lam, arrs[0], arrs[1],
                                         arrs[2], ctypes.byref(h)))
+    return Mesh(h, (len(hx), len(hy), len(hz)), p, lam)
+
+
+BC_DIRICHLET, BC_NEUMANN, BC_PERIODIC = 0, 1, 2
+_BC_CODE = {"D": BC_DIRICHLET, "N": BC_NEUMANN, "P": BC_PERIODIC}
+
+
+def bc_codes(bc):
+    """Six side kinds (x1 low, x1 high, x2 low, ..., x3 high) from a string
+    such as "DNPPDD", or three per-direction entries each "D"/"N"/"P" or a
+    (low, high) pair."""
+    if isinstance(bc, str) and len(bc) == 6:
+        sides = list(bc)
+    else:
+        sides = []
+        for b in bc:
+            sides += [b, b] if isinstance(b, str) and len(b) == 1 else [b[0], b[1]]
+    return [_BC_CODE[s] if isinstance(s, str) else int(s) for s in sides]
+
+
+def create_mesh_bc(hx, hy, hz, p, lam, bc):
+    arrs = [(ctypes.c_double * len(a))(*[float(v) for v in a]) for a in (hx, hy, hz)]
+    codes = (ctypes.c_int * 6)(*bc_codes(bc))
+    h = _VP()
+    _check(lib().pmg_create_mesh_bc(len(hx), len(hy), len(hz), p, lam, arrs[0], arrs[1], arrs[2], codes,
+                                    ctypes.byref(h)))
     return Mesh(h, (len(hx), len(hy), len(hz)), p, lam)
 
 

@@ -112,6 +112,8 @@ struct pmg_mesh {
     double hmg_omega = 0.6;
     int hmg_nu = 1;
     int smoother_kind = 0;      // 0: star smoother (Alg. 2), 1: element-centred blocks (Sec. 3.4)
+    int bc = BC_ALL_DIRICHLET;  // boundary kinds, as Layout::bc
+    double* w_fgrid = nullptr;  // periodic meshes: right-hand side grid with its seam layers equal
     int coarse_kind = 0;        // 0: Jacobi CG (Sec. 4.1), 1: exact solve by fast diagonalization
     // coarse CG counters shared by all bottom levels
     int* d_coarse_iters = nullptr;
@@ -304,9 +306,9 @@ int build_level(pmg_mesh* m, Level& L, int p, int pc, const std::vector<double> 
     L.p = p;
     L.pc = pc;
     for (int d = 0; d < 3; ++d) L.h[d] = h[d];
-    L.lay = make_layout((int)h[0].size(), (int)h[1].size(), (int)h[2].size(), p);
+    L.lay = make_layout((int)h[0].size(), (int)h[1].size(), (int)h[2].size(), p, m->bc);
     HostTables t;
-    build_level_tables(p, pc, h, t);
+    build_level_tables(p, pc, h, t, m->bc);
     int rc;
     if ((rc = fill_tabs(m, L.t64, t, L.lay, pc))) return rc;
     if ((rc = fill_tabs(m, L.t32, t, L.lay, pc))) return rc;
@@ -424,7 +426,8 @@ int setup_fd(pmg_mesh* m, Level& L) {
     int rc;
     for (int d = 0; d < 3; ++d) {
         std::vector<double> Af, Ab, mu;
-        build_fd_tables(L.p, L.h[d], Af, Ab, mu);
+        const int bcd = (L.lay.dlo(d) ? 1 : 0) | (L.lay.dhi(d) ? 2 : 0) | (L.lay.per(d) ? 4 : 0);
+        build_fd_tables(L.p, L.h[d], bcd, Af, Ab, mu, L.fd.o[d]);
         L.fd.m[d] = (int)mu.size();
         if ((rc = m->upload(&L.fd.Af[d], Af)) || (rc = m->upload(&L.fd.Ab[d], Ab)) || (rc = m->upload(&L.fd.mu[d], mu)))
             return rc;
@@ -502,6 +505,7 @@ int build_mesh(pmg_mesh* m) {
     }
     const Layout& Lf = m->lv.back().lay;
     int64_t nf = Lf.len;
+    if (Lf.any_per() && (rc = m->alloc(&m->w_fgrid, (size_t)Lf.N[0] * Lf.N[1] * Lf.N[2]))) return rc;
     if ((rc = m->alloc(&m->w_u, nf)) || (rc = m->alloc(&m->w_r, nf)) || (rc = m->alloc(&m->w_s, nf)) ||
         (rc = m->alloc(&m->w_p, nf)) || (rc = m->alloc(&m->w_q, nf)) || (rc = m->alloc(&m->w_z, nf)) ||
         (rc = m->alloc(&m->w_F, nf)) || (rc = m->alloc(&m->w_r32, nf)) || (rc = m->alloc(&m->w_z32, nf)))
@@ -901,18 +905,61 @@ int check_level(const pmg_mesh* m, int level) {
     return 0;
 }
 
+// Boundary kinds of the six sides (x1 low, x1 high, x2 low, ..., x3 high;
+// PMG_BC_*) as Layout::bc; -1 if invalid.
+int encode_bc(const int* kinds, const int n[3], double lambda, std::string& why) {
+    if (!kinds) return BC_ALL_DIRICHLET;
+    int bc = 0;
+    bool any_dir = false;
+    for (int d = 0; d < 3; ++d) {
+        const int lo = kinds[2 * d], hi = kinds[2 * d + 1];
+        for (int k : {lo, hi})
+            if (k != PMG_BC_DIRICHLET && k != PMG_BC_NEUMANN && k != PMG_BC_PERIODIC) {
+                why = "boundary kind must be PMG_BC_DIRICHLET, PMG_BC_NEUMANN or PMG_BC_PERIODIC";
+                return -1;
+            }
+        if ((lo == PMG_BC_PERIODIC) != (hi == PMG_BC_PERIODIC)) {
+            why = "a periodic direction is periodic on both sides";
+            return -1;
+        }
+        if (lo == PMG_BC_PERIODIC) {
+            if (n[d] < 3) {
+                why = "a periodic direction needs at least 3 elements";
+                return -1;
+            }
+            bc |= 1 << (6 + d);
+        }
+        if (lo == PMG_BC_DIRICHLET) bc |= 1 << d;
+        if (hi == PMG_BC_DIRICHLET) bc |= 1 << (3 + d);
+        any_dir = any_dir || lo == PMG_BC_DIRICHLET || hi == PMG_BC_DIRICHLET;
+    }
+    if (!any_dir && !(lambda > 0.0)) {
+        why = "without a Dirichlet side the operator is singular unless lambda > 0";
+        return -1;
+    }
+    return bc;
+}
+
 int create(int n1, int n2, int n3, int p, double lambda, const double* hx, const double* hy, const double* hz,
-           double stretch, pmg_mesh** out) {
+           double stretch, const int* kinds, pmg_mesh** out) {
     if (!out) return fail(PMG_EINVAL, "out is null");
     *out = nullptr;
     if (n1 < 1 || n2 < 1 || n3 < 1) return fail(PMG_EINVAL, "element counts must be >= 1");
     if (p < 1 || p > PMG_MAX_DEGREE) return fail(PMG_EINVAL, "degree out of range");
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(PMG_EINVAL, "lambda must be finite and >= 0");
+    const int nn0[3] = {n1, n2, n3};
+    std::string why;
+    const int bc = encode_bc(kinds, nn0, lambda, why);
+    if (bc < 0) return fail(PMG_EINVAL, why);
     pmg_mesh* m = new (std::nothrow) pmg_mesh();
     if (!m) return fail(PMG_ENOMEM, "host allocation");
     m->n[0] = n1; m->n[1] = n2; m->n[2] = n3;
     m->p = p;
     m->lam = lambda;
+    m->bc = bc;
+    // other boundaries than Dirichlet: the exact coarse solve (the Jacobi CG
+    // coarse solver and the degree-1 levels assume Dirichlet sides)
+    if (bc != BC_ALL_DIRICHLET) m->coarse_kind = 1;
     const int nn[3] = {n1, n2, n3};
     const double* hs[3] = {hx, hy, hz};
     for (int d = 0; d < 3; ++d) {
@@ -948,13 +995,20 @@ const char* pmg_last_error(void) { return g_err.c_str(); }
 
 int pmg_create_mesh(int n1, int n2, int n3, int p, double lambda, double stretch, pmg_mesh** out) {
     if (!(stretch >= 1.0) || !std::isfinite(stretch)) return fail(PMG_EINVAL, "stretch must be >= 1");
-    return create(n1, n2, n3, p, lambda, nullptr, nullptr, nullptr, stretch, out);
+    return create(n1, n2, n3, p, lambda, nullptr, nullptr, nullptr, stretch, nullptr, out);
 }
 
 int pmg_create_mesh_widths(int n1, int n2, int n3, int p, double lambda, const double* hx, const double* hy,
                            const double* hz, pmg_mesh** out) {
     if (!hx || !hy || !hz) return fail(PMG_EINVAL, "width arrays must not be null");
-    return create(n1, n2, n3, p, lambda, hx, hy, hz, 1.0, out);
+    return create(n1, n2, n3, p, lambda, hx, hy, hz, 1.0, nullptr, out);
+}
+
+int pmg_create_mesh_bc(int n1, int n2, int n3, int p, double lambda, const double* hx, const double* hy,
+                       const double* hz, const int* bc, pmg_mesh** out) {
+    if (!hx || !hy || !hz) return fail(PMG_EINVAL, "width arrays must not be null");
+    if (!bc) return fail(PMG_EINVAL, "boundary kinds must not be null");
+    return create(n1, n2, n3, p, lambda, hx, hy, hz, 1.0, bc, out);
 }
 
 void pmg_destroy_mesh(pmg_mesh* m) {
@@ -1122,6 +1176,8 @@ int pmg_set_coarse_mg(pmg_mesh* m, int levels, double omega, int nu) {
     if (levels < 0 || levels > 16 || !(omega > 0.0) || !std::isfinite(omega) || nu < 1 || nu > 16)
         return fail(PMG_EINVAL, "bad coarse multigrid parameters");
     if (levels > 0 && m->lv[0].p < 2) return fail(PMG_EUNSUP, "degree-1 levels need p_0 = 2");
+    if (levels > 0 && m->bc != BC_ALL_DIRICHLET)
+        return fail(PMG_EUNSUP, "degree-1 levels are built for Dirichlet sides only");
     int rc;
     if ((rc = build_h_levels(m, levels))) return rc;
     m->hmg_levels = levels;
@@ -1135,6 +1191,8 @@ int pmg_set_coarse_mg(pmg_mesh* m, int levels, double omega, int nu) {
 int pmg_set_coarse_solver(pmg_mesh* m, int kind) {
     if (check_mesh(m)) return PMG_EINVAL;
     if (kind != 0 && kind != 1) return fail(PMG_EINVAL, "coarse solver kind must be 0 (CG) or 1 (exact)");
+    if (kind == 0 && m->bc != BC_ALL_DIRICHLET)
+        return fail(PMG_EUNSUP, "the coarse CG is built for Dirichlet sides only; this mesh keeps the exact solve");
     m->coarse_kind = kind;
     int rc;
     if ((rc = rebuild_active(m))) return rc;
@@ -1145,6 +1203,8 @@ int pmg_set_coarse_solver(pmg_mesh* m, int kind) {
 int pmg_set_smoother(pmg_mesh* m, int kind) {
     if (check_mesh(m)) return PMG_EINVAL;
     if (kind != 0 && kind != 1) return fail(PMG_EINVAL, "smoother kind must be 0 (star) or 1 (element-centred)");
+    if (kind == 1 && m->bc != BC_ALL_DIRICHLET)
+        return fail(PMG_EUNSUP, "the element-centred smoother is built for Dirichlet sides only");
     int rc;
     if (kind == 1)
         for (auto& L : m->lv)
@@ -1191,10 +1251,20 @@ int pmg_coarse_solve(pmg_mesh* m, const double* F0, double* u0, int* iters, void
     return 0;
 }
 
+// The right-hand side grid as the element kernels read it: on a mesh with a
+// periodic direction a copy whose last layers repeat the first ones (the
+// values given there are ignored).
+static const double* rhs_grid(pmg_mesh* m, const double* f, hipStream_t st) {
+    const Layout& L = m->lv.back().lay;
+    if (!L.any_per()) return f;
+    launch_grid_seam_copy(L, f, m->w_fgrid, st);
+    return m->w_fgrid;
+}
+
 int pmg_condense_rhs(pmg_mesh* m, const double* f, double* Fh, void* stream) {
     if (check_mesh(m)) return PMG_EINVAL;
     if (!f || !Fh) return fail(PMG_EINVAL, "null pointer");
-    launch_condense(m->lv.back().t64, m->m1d[0], m->m1d[1], m->m1d[2], f, Fh, S(stream));
+    launch_condense(m->lv.back().t64, m->m1d[0], m->m1d[1], m->m1d[2], rhs_grid(m, f, S(stream)), Fh, S(stream));
     HIPCHK(hipGetLastError());
     return 0;
 }
@@ -1202,7 +1272,7 @@ int pmg_condense_rhs(pmg_mesh* m, const double* f, double* Fh, void* stream) {
 int pmg_recover_interior(pmg_mesh* m, const double* f, const double* uh, double* u, void* stream) {
     if (check_mesh(m)) return PMG_EINVAL;
     if (!f || !uh || !u) return fail(PMG_EINVAL, "null pointer");
-    launch_recover(m->lv.back().t64, f, uh, u, S(stream));
+    launch_recover(m->lv.back().t64, rhs_grid(m, f, S(stream)), uh, u, S(stream));
     HIPCHK(hipGetLastError());
     return 0;
 }
@@ -1227,7 +1297,8 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
     hipEvent_t ev[4];
     for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
     HIPCHK(hipEventRecord(ev[0], st));
-    launch_condense(m->lv.back().t64, m->m1d[0], m->m1d[1], m->m1d[2], f, m->w_F, st);
+    const double* fg = rhs_grid(m, f, st);
+    launch_condense(m->lv.back().t64, m->m1d[0], m->m1d[1], m->m1d[2], fg, m->w_F, st);
     HIPCHK(hipEventRecord(ev[1], st));
     int rc = 0, status = 0;
     // r = F, u = 0, s = r, p = 0, delta = 1
@@ -1324,7 +1395,7 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
     }
     if (!status && !(std::sqrt(rr) <= eps)) status = PMG_NOT_CONVERGED;
     HIPCHK(hipEventRecord(ev[2], st));
-    launch_recover(m->lv.back().t64, f, m->w_u, ug, st);
+    launch_recover(m->lv.back().t64, fg, m->w_u, ug, st);
     HIPCHK(hipEventRecord(ev[3], st));
     HIPCHK(hipMemcpyAsync(m->hcit, m->d_coarse_iters, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1356,6 +1427,7 @@ int pmg_mg_solve(pmg_mesh* m, const double* f, double* u, double rtol, int maxit
 
 int pmg_lift_dirichlet(pmg_mesh* m, const double* f, const double* g, double* out, void* stream) {
     if (check_mesh(m)) return PMG_EINVAL;
+    if (m->bc != BC_ALL_DIRICHLET) return fail(PMG_EUNSUP, "Dirichlet data by lifting needs Dirichlet sides only");
     if (!f || !g || !out) return fail(PMG_EINVAL, "null pointer");
     if (out == g) return fail(PMG_EINVAL, "out must not alias g");
     launch_lift_dirichlet(m->lv.back().lay.N, m->p, m->lift_tab, f, g, out, S(stream));
@@ -1365,6 +1437,7 @@ int pmg_lift_dirichlet(pmg_mesh* m, const double* f, const double* g, double* ou
 
 int pmg_set_boundary(pmg_mesh* m, const double* g, double* u, void* stream) {
     if (check_mesh(m)) return PMG_EINVAL;
+    if (m->bc != BC_ALL_DIRICHLET) return fail(PMG_EUNSUP, "Dirichlet data by lifting needs Dirichlet sides only");
     if (!g || !u) return fail(PMG_EINVAL, "null pointer");
     launch_set_boundary(m->lv.back().lay.N, g, u, S(stream));
     HIPCHK(hipGetLastError());
@@ -1374,6 +1447,7 @@ int pmg_set_boundary(pmg_mesh* m, const double* g, double* u, void* stream) {
 int pmg_pcg_solve_dirichlet(pmg_mesh* m, const double* f, const double* g, double* u, double rtol, int maxit,
                             int pdt, pmg_stats* st, void* stream) {
     if (check_mesh(m)) return PMG_EINVAL;
+    if (m->bc != BC_ALL_DIRICHLET) return fail(PMG_EUNSUP, "Dirichlet data by lifting needs Dirichlet sides only");
     if (!f || !g || !u) return fail(PMG_EINVAL, "null pointer");
     if (u == g) return fail(PMG_EINVAL, "u must not alias g");
     const int* N = m->lv.back().lay.N;

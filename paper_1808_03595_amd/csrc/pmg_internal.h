@@ -17,7 +17,18 @@ namespace pmg {
 // Every condensed unknown is stored once: nodes with i1 % p == 0 live in
 // family 0, else nodes with i2 % p == 0 in family 1, else family 2.  All
 // other slots and the Dirichlet nodes are kept at zero.
+//
+// Boundary kinds (Sec. 3.3), per direction and side: homogeneous Dirichlet,
+// homogeneous Neumann (the boundary nodes are unknowns) or periodic.  In a
+// periodic direction the node layer i_d = N_d - 1 is the layer i_d = 0
+// again; its slots (the mirror slots) carry no unknown and are zero between
+// operations, so that sums over a vector count every unknown once.  The
+// element kernels see the mesh unfolded: before them the mirror slots of
+// their input receive a copy of the slots they repeat, after them the
+// mirror slots of an accumulated output are added onto those slots.
 // ---------------------------------------------------------------------------
+constexpr int BC_ALL_DIRICHLET = 0x3f;
+
 struct Layout {
     int p;
     int n[3];
@@ -27,6 +38,14 @@ struct Layout {
     int64_t pstride[3];  // elements per family-d plane
     int64_t off[3];      // start of family d
     int64_t len;         // total length
+    // bit d: Dirichlet at the low end of direction d; bit 3 + d: Dirichlet at
+    // its high end; bit 6 + d: direction d periodic (Neumann where no bit)
+    int bc;
+
+    __host__ __device__ inline bool dlo(int d) const { return (bc >> d) & 1; }
+    __host__ __device__ inline bool dhi(int d) const { return (bc >> (3 + d)) & 1; }
+    __host__ __device__ inline bool per(int d) const { return (bc >> (6 + d)) & 1; }
+    __host__ __device__ inline bool any_per() const { return (bc >> 6) & 7; }
 
     // Storage slot of the skeleton node (i1, i2, i3); the caller guarantees
     // that it is a skeleton node and states which of i_d are multiples of p.
@@ -41,7 +60,7 @@ struct Layout {
     __host__ __device__ inline int64_t plane2(int j) const { return off[2] + (int64_t)j * pstride[2]; }
 };
 
-Layout make_layout(int n1, int n2, int n3, int p);
+Layout make_layout(int n1, int n2, int n3, int p, int bc = BC_ALL_DIRICHLET);
 
 // Device tables of one level, element type T.  Per-direction tables are
 // indexed by element index (el_*) or vertex index (st_*).
@@ -134,11 +153,13 @@ constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 
 // Exact solve of a level's condensed system by fast diagonalization of the
 // whole mesh (the full system with zero interior right-hand side): per
-// direction m_d = n_d p - 1 unknowns, the forward (S^T) and backward (S)
-// transform matrices, row-major, and the eigenvalues; two [m3][m2][m1] work
-// arrays.
+// direction m_d unknown node indices starting at o_d (n_d p - 1 from 1
+// between two Dirichlet ends; a Neumann end adds its node, a periodic
+// direction has n_d p from 0), the forward (S^T) and backward (S) transform
+// matrices, row-major, and the eigenvalues; two [m3][m2][m1] work arrays.
 struct FdTabs {
     int m[3];
+    int o[3];
     const double* Af[3];
     const double* Ab[3];
     const double* mu[3];
@@ -168,9 +189,11 @@ void gen_eig_diag(int n, const double* L, const double* m, std::vector<double>& 
 void lagrange_interp(const std::vector<double>& xf, const std::vector<double>& xt,
                      std::vector<double>& J);
 double smoothstep(int pw, double t);
-void build_level_tables(int p, int pc, const std::vector<double> h[3], HostTables& t);
-void build_fd_tables(int p, const std::vector<double>& h, std::vector<double>& Af, std::vector<double>& Ab,
-                     std::vector<double>& mu);
+void build_level_tables(int p, int pc, const std::vector<double> h[3], HostTables& t,
+                        int bc = BC_ALL_DIRICHLET);
+// bc_d: bit 0 Dirichlet low end, bit 1 Dirichlet high end, bit 2 periodic
+void build_fd_tables(int p, const std::vector<double>& h, int bc_d, std::vector<double>& Af,
+                     std::vector<double>& Ab, std::vector<double>& mu, int& first);
 void build_block_tables(int p, const std::vector<double>& h, int np, std::vector<double>& S,
                         std::vector<double>& lam, std::vector<double>& w);
 void coarse_diagonal(const Layout& lay, double lam, const std::vector<double> h[3],

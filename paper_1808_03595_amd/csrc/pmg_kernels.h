@@ -18,6 +18,8 @@ constexpr int COARSE_GRAPH_MAXN = 256;  // longest captured chain of coarse iter
 hipError_t launch_coarse_init(const CoarseArgs& a, const double* b, int maxit, double rtol, hipStream_t st);
 // exact solve of the level's condensed system by fast diagonalization: x = Hhat^-1 b
 void launch_fd_solve(const Layout& L, const FdTabs& fd, double lam, const double* b, double* x, hipStream_t st);
+// copy of a node grid with each periodic direction's last layer set to its first
+void launch_grid_seam_copy(const Layout& L, const double* f, double* out, hipStream_t st);
 void launch_publish(const double* sc, int n, int64_t* cnt, HostMail* mail, hipStream_t st);
 void launch_pcg_start(const double* F, double* r, double* s, double* u, double* p, double* delta, int64_t n,
                       hipStream_t st);

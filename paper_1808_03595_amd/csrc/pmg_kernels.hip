@@ -13,9 +13,39 @@ namespace pmg {
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
+// Node on a Dirichlet side of the domain (Sec. 3.3).
 __device__ inline bool is_dir(const Layout& L, int i1, int i2, int i3) {
-    return i1 == 0 || i2 == 0 || i3 == 0 || i1 == L.N[0] - 1 || i2 == L.N[1] - 1 ||
-           i3 == L.N[2] - 1;
+    const int b = L.bc;
+    return ((b & 1) && i1 == 0) || ((b & 2) && i2 == 0) || ((b & 4) && i3 == 0) ||
+           ((b & 8) && i1 == L.N[0] - 1) || ((b & 16) && i2 == L.N[1] - 1) || ((b & 32) && i3 == L.N[2] - 1);
+}
+
+// Node of the last layer of a periodic direction (a mirror of the first).
+__device__ inline bool is_mirror(const Layout& L, int i1, int i2, int i3) {
+    const int b = L.bc;
+    return ((b & 64) && i1 == L.N[0] - 1) || ((b & 128) && i2 == L.N[1] - 1) || ((b & 256) && i3 == L.N[2] - 1);
+}
+
+// Node index i of direction d taken across the seam of a periodic
+// direction (-p < i < N_d - 1 + p onto 0..N_d - 2); unchanged otherwise.
+__device__ __forceinline__ int wrap_idx(const Layout& L, int d, int i) {
+    if (!L.per(d)) return i;
+    const int m = L.N[d] - 1;
+    return i < 0 ? i + m : (i >= m ? i - m : i);
+}
+
+// The star of vertex (v1, v2, v3) does work: not when all three of its
+// planes lie on Dirichlet sides, nor at the last vertex of a periodic
+// direction (the same star as vertex 0).
+__device__ inline bool star_live(const Layout& L, int v1, int v2, int v3) {
+    const int v[3] = {v1, v2, v3};
+    bool all_dir = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (L.per(d) && v[d] == L.n[d]) return false;
+        all_dir = all_dir && ((v[d] == 0 && L.dlo(d)) || (v[d] == L.n[d] && L.dhi(d)));
+    }
+    return !all_dir;
 }
 
 // Element (e1, e2, e3) of block b among the elements of parity `color`
@@ -95,7 +125,7 @@ __global__ void k_grid_to_skel(Layout L, const double* __restrict__ g, T* __rest
         if (d == 0) { i1 = j * p; i3 = r; i2 = c; canon = c < L.N[1]; }
         else if (d == 1) { i2 = j * p; i3 = r; i1 = c; canon = c < L.N[0] && (c % p) != 0; }
         else { i3 = j * p; i2 = r; i1 = c; canon = c < L.N[0] && (c % p) != 0 && (r % p) != 0; }
-        if (canon && !is_dir(L, i1, i2, i3))
+        if (canon && !is_dir(L, i1, i2, i3) && !is_mirror(L, i1, i2, i3))
             v = (T)g[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1];
     }
     s[i] = v;
@@ -113,7 +143,9 @@ __global__ void k_skel_to_grid(Layout L, const T* __restrict__ s, double* __rest
     int p = L.p;
     bool on1 = i1 % p == 0, on2 = i2 % p == 0, on3 = i3 % p == 0;
     double v = 0.0;
-    if ((on1 || on2 || on3) && !is_dir(L, i1, i2, i3)) v = (double)s[L.slot(i1, i2, i3, on1, on2)];
+    // a mirror node takes the value of the node it repeats
+    const int j1 = wrap_idx(L, 0, i1), j2 = wrap_idx(L, 1, i2), j3 = wrap_idx(L, 2, i3);
+    if ((on1 || on2 || on3) && !is_dir(L, j1, j2, j3)) v = (double)s[L.slot(j1, j2, j3, on1, on2)];
     g[i] = v;
 }
 
@@ -1102,10 +1134,7 @@ __global__ void __launch_bounds__(256) k_smoother(LevelTabs<T> tb, const T* __re
     int nv[3] = {L.n[0] + 1, L.n[1] + 1, L.n[2] + 1};
     int v[3];
     color_coords(blockIdx.x, color, nv, v);
-    // stars whose three planes are all Dirichlet (domain corners) are empty
-    bool b1 = v[0] == 0 || v[0] == L.n[0], b2 = v[1] == 0 || v[1] == L.n[1],
-         b3 = v[2] == 0 || v[2] == L.n[2];
-    if (b1 && b2 && b3) return;
+    if (!star_live(L, v[0], v[1], v[2])) return;
     StarPtrs<T> P;
     for (int d = 0; d < 3; ++d) {
         P.S[d] = tb.st_S[d] + (int64_t)v[d] * s2;
@@ -1121,15 +1150,15 @@ __global__ void __launch_bounds__(256) k_smoother(LevelTabs<T> tb, const T* __re
         int oa = a - c, ob = b - c;
         T val = 0;
         if (f == 0) {
-            int i2 = c2 + ob, i3 = c3 + oa;
+            int i2 = wrap_idx(L, 1, c2 + ob), i3 = wrap_idx(L, 2, c3 + oa);
             if (i2 >= 0 && i2 < L.N[1] && i3 >= 0 && i3 < L.N[2])
                 val = r[L.plane0(v[0]) + (int64_t)i3 * L.pitch[0] + i2];
         } else if (f == 1) {
-            int i1 = c1 + ob, i3 = c3 + oa;
+            int i1 = wrap_idx(L, 0, c1 + ob), i3 = wrap_idx(L, 2, c3 + oa);
             if (i1 >= 0 && i1 < L.N[0] && i3 >= 0 && i3 < L.N[2])
                 val = r[L.plane1(v[1]) + (int64_t)i3 * L.pitch[1] + i1];
         } else {
-            int i1 = c1 + ob, i2 = c2 + oa;
+            int i1 = wrap_idx(L, 0, c1 + ob), i2 = wrap_idx(L, 1, c2 + oa);
             if (i1 >= 0 && i1 < L.N[0] && i2 >= 0 && i2 < L.N[1])
                 val = r[L.plane2(v[2]) + (int64_t)i2 * L.pitch[2] + i1];
         }
@@ -1193,9 +1222,9 @@ __global__ void __launch_bounds__(256) k_smoother(LevelTabs<T> tb, const T* __re
         int oa = a - c, ob = b - c;
         int64_t slot;
         int i1, i2, i3;
-        if (f == 0) { i1 = c1; i2 = c2 + ob; i3 = c3 + oa; }
-        else if (f == 1) { if (ob == 0) continue; i1 = c1 + ob; i2 = c2; i3 = c3 + oa; }
-        else { if (ob == 0 || oa == 0) continue; i1 = c1 + ob; i2 = c2 + oa; i3 = c3; }
+        if (f == 0) { i1 = c1; i2 = wrap_idx(L, 1, c2 + ob); i3 = wrap_idx(L, 2, c3 + oa); }
+        else if (f == 1) { if (ob == 0) continue; i1 = wrap_idx(L, 0, c1 + ob); i2 = c2; i3 = wrap_idx(L, 2, c3 + oa); }
+        else { if (ob == 0 || oa == 0) continue; i1 = wrap_idx(L, 0, c1 + ob); i2 = wrap_idx(L, 1, c2 + oa); i3 = c3; }
         if (i1 < 0 || i1 >= L.N[0] || i2 < 0 || i2 >= L.N[1] || i3 < 0 || i3 >= L.N[2]) continue;
         if (is_dir(L, i1, i2, i3)) continue;
         if (f == 0) slot = L.plane0(v[0]) + (int64_t)i3 * L.pitch[0] + i2;
@@ -1291,8 +1320,7 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
         v1 = star % nv1;
         v2 = (star / nv1) % nv2;
         v3 = star / (nv1 * nv2);
-        bool b1 = v1 == 0 || v1 == L.n[0], b2 = v2 == 0 || v2 == L.n[1], b3 = v3 == 0 || v3 == L.n[2];
-        if (b1 && b2 && b3) active = false;  // corner: all three planes Dirichlet
+        active = star_live(L, v1, v2, v3);
     }
     // interior star (1 <= v_d <= n_d - 1): its windows lie inside the node
     // grid and hold no Dirichlet node, so loads and atomics skip those tests
@@ -1353,7 +1381,11 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
                 x1 = r[L.plane0(v1) + (int64_t)i3 * L.pitch[0] + i2];
                 x2 = r[L.plane1(v2) + (int64_t)i3 * L.pitch[1] + i1];
                 x3 = r[L.plane2(v3) + (int64_t)i2a * L.pitch[2] + i1];
-            } else {
+            } else {   // windows cross the seam of a periodic direction
+                i1 = wrap_idx(L, 0, i1);
+                i2 = wrap_idx(L, 1, i2);
+                i3 = wrap_idx(L, 2, i3);
+                i2a = wrap_idx(L, 1, i2a);
                 if (i2 >= 0 && i2 < L.N[1] && i3 >= 0 && i3 < L.N[2])
                     x1 = r[L.plane0(v1) + (int64_t)i3 * L.pitch[0] + i2];
                 if (i1 >= 0 && i1 < L.N[0] && i3 >= 0 && i3 < L.N[2])
@@ -1510,17 +1542,17 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
         if (a >= nS || j >= nS) continue;
         const T wt = wj * wr[v];
         {   // face normal to x1: (i1, i2, i3) = (c1, c2 + ob, c3 + oa)
-            int i1 = c1, i2 = c2 + ob, i3 = c3 + oa;
+            int i1 = c1, i2 = wrap_idx(L, 1, c2 + ob), i3 = wrap_idx(L, 2, c3 + oa);
             if (i2 >= 0 && i2 < L.N[1] && i3 >= 0 && i3 < L.N[2] && !is_dir(L, i1, i2, i3))
                 unsafeAtomicAdd(du + L.plane0(v1) + (int64_t)i3 * L.pitch[0] + i2, wt * u1[v]);
         }
         if (ob != 0) {  // face normal to x2 without the x3-axis line (stored in family 0)
-            int i1 = c1 + ob, i2 = c2, i3 = c3 + oa;
+            int i1 = wrap_idx(L, 0, c1 + ob), i2 = c2, i3 = wrap_idx(L, 2, c3 + oa);
             if (i1 >= 0 && i1 < L.N[0] && i3 >= 0 && i3 < L.N[2] && !is_dir(L, i1, i2, i3))
                 unsafeAtomicAdd(du + L.plane1(v2) + (int64_t)i3 * L.pitch[1] + i1, wt * u2[v]);
         }
         if (ob != 0 && oa != 0) {  // face normal to x3 without both axis lines
-            int i1 = c1 + ob, i2 = c2 + oa, i3 = c3;
+            int i1 = wrap_idx(L, 0, c1 + ob), i2 = wrap_idx(L, 1, c2 + oa), i3 = c3;
             if (i1 >= 0 && i1 < L.N[0] && i2 >= 0 && i2 < L.N[1] && !is_dir(L, i1, i2, i3))
                 unsafeAtomicAdd(du + L.plane2(v3) + (int64_t)i2 * L.pitch[2] + i1, wt * u3[v]);
         }
@@ -1587,8 +1619,7 @@ __global__ void __launch_bounds__(256) k_smoother_small(LevelTabs<T> tb, const T
             v2 = (star / nv1) % nv2;
             v3 = star / (nv1 * nv2);
         }
-        bool b1 = v1 == 0 || v1 == L.n[0], b2 = v2 == 0 || v2 == L.n[1], b3 = v3 == 0 || v3 == L.n[2];
-        if (b1 && b2 && b3) active = false;  // corner: all three planes Dirichlet
+        active = star_live(L, v1, v2, v3);
     }
     const int c1 = v1 * p, c2 = v2 * p, c3 = v3 * p;
     const bool in = i < nS && j < nS;
@@ -1613,7 +1644,8 @@ __global__ void __launch_bounds__(256) k_smoother_small(LevelTabs<T> tb, const T
         // F3 at (c1 + ob, c2 + oa, c3); a = i, b = j
         T x1 = 0, x2 = 0, x3 = 0;
         if (active && in) {
-            const int i1 = c1 + ob, i2 = c2 + ob, i3 = c3 + oa, i2a = c2 + oa;
+            const int i1 = wrap_idx(L, 0, c1 + ob), i2 = wrap_idx(L, 1, c2 + ob), i3 = wrap_idx(L, 2, c3 + oa),
+                      i2a = wrap_idx(L, 1, c2 + oa);
             if (i2 >= 0 && i2 < L.N[1] && i3 >= 0 && i3 < L.N[2])
                 x1 = r[L.plane0(v1) + (int64_t)i3 * L.pitch[0] + i2];
             if (i1 >= 0 && i1 < L.N[0] && i3 >= 0 && i3 < L.N[2])
@@ -1701,17 +1733,17 @@ __global__ void __launch_bounds__(256) k_smoother_small(LevelTabs<T> tb, const T
     }
     const T wt = omega * tb.st_w[i] * tb.st_w[j];
     {
-        const int i1 = c1, i2 = c2 + ob, i3 = c3 + oa;
+        const int i1 = c1, i2 = wrap_idx(L, 1, c2 + ob), i3 = wrap_idx(L, 2, c3 + oa);
         if (i2 >= 0 && i2 < L.N[1] && i3 >= 0 && i3 < L.N[2] && !is_dir(L, i1, i2, i3))
             star_add(color, du + L.plane0(v1) + (int64_t)i3 * L.pitch[0] + i2, wt * u[0]);
     }
     if (ob != 0) {  // without the x3-axis line (stored in family 0)
-        const int i1 = c1 + ob, i2 = c2, i3 = c3 + oa;
+        const int i1 = wrap_idx(L, 0, c1 + ob), i2 = c2, i3 = wrap_idx(L, 2, c3 + oa);
         if (i1 >= 0 && i1 < L.N[0] && i3 >= 0 && i3 < L.N[2] && !is_dir(L, i1, i2, i3))
             star_add(color, du + L.plane1(v2) + (int64_t)i3 * L.pitch[1] + i1, wt * u[1]);
     }
     if (ob != 0 && oa != 0) {  // without both axis lines
-        const int i1 = c1 + ob, i2 = c2 + oa, i3 = c3;
+        const int i1 = wrap_idx(L, 0, c1 + ob), i2 = wrap_idx(L, 1, c2 + oa), i3 = c3;
         if (i1 >= 0 && i1 < L.N[0] && i2 >= 0 && i2 < L.N[1] && !is_dir(L, i1, i2, i3))
             star_add(color, du + L.plane2(v3) + (int64_t)i2 * L.pitch[2] + i1, wt * u[2]);
     }
@@ -1737,8 +1769,7 @@ __device__ inline bool star_vertex(const Layout& L, int s, int& v1, int& v2, int
     v1 = s % nv1;
     v2 = (s / nv1) % nv2;
     v3 = s / (nv1 * nv2);
-    const bool b1 = v1 == 0 || v1 == L.n[0], b2 = v2 == 0 || v2 == L.n[1], b3 = v3 == 0 || v3 == L.n[2];
-    return !(b1 && b2 && b3);  // corner stars (all three planes Dirichlet) are empty
+    return star_live(L, v1, v2, v3);
 }
 
 template <typename T, int MODE>
@@ -1763,16 +1794,22 @@ __global__ void __launch_bounds__(64) k_star_gemm(LevelTabs<T> tb, const T* __re
     int64_t wbase = 0, wpitch = 0;
     bool rowok = false;
     int lo = 0, hi = 0;   // admissible column offsets b - c with the node inside the domain
+    int cdir = 0, cstart = 0;
     if (MODE == SG_FWD1) {
         const int a = row0 + j, oa = a - c;
         int ir, nr, ncol, cbase;
-        if (f == 0) { ir = c3 + oa; nr = L.N[2]; ncol = L.N[1]; cbase = c2; wbase = L.plane0(v1); wpitch = L.pitch[0]; }
-        else if (f == 1) { ir = c3 + oa; nr = L.N[2]; ncol = L.N[0]; cbase = c1; wbase = L.plane1(v2); wpitch = L.pitch[1]; }
-        else { ir = c2 + oa; nr = L.N[1]; ncol = L.N[0]; cbase = c1; wbase = L.plane2(v3); wpitch = L.pitch[2]; }
+        if (f == 0) { ir = wrap_idx(L, 2, c3 + oa); nr = L.N[2]; ncol = L.N[1]; cbase = c2; cdir = 1; wbase = L.plane0(v1); wpitch = L.pitch[0]; }
+        else if (f == 1) { ir = wrap_idx(L, 2, c3 + oa); nr = L.N[2]; ncol = L.N[0]; cbase = c1; cdir = 0; wbase = L.plane1(v2); wpitch = L.pitch[1]; }
+        else { ir = wrap_idx(L, 1, c2 + oa); nr = L.N[1]; ncol = L.N[0]; cbase = c1; cdir = 0; wbase = L.plane2(v3); wpitch = L.pitch[2]; }
         rowok = a < nS && ir >= 0 && ir < nr;
-        wbase += (int64_t)ir * wpitch + cbase - c;   // + b gives the slot of column offset b - c
+        wbase += (int64_t)ir * wpitch;
+        cstart = cbase - c;                          // column index of offset b: cstart + b
         lo = c - cbase;                              // b >= lo keeps the column index >= 0
         hi = ncol - 1 - cbase + c;                   // b <= hi keeps it < ncol
+        if (L.per(cdir)) {                           // the window continues across the seam
+            lo = 0;
+            hi = nS - 1;
+        }
     }
     const T* Xm = X + mo;
     typename M::v4 acc = {0, 0, 0, 0};
@@ -1780,7 +1817,7 @@ __global__ void __launch_bounds__(64) k_star_gemm(LevelTabs<T> tb, const T* __re
         const int k = k0 + q;
         T a, b;
         if (MODE == SG_FWD1) {
-            a = (rowok && k < nS && k >= lo && k <= hi) ? r[wbase + k] : (T)0;
+            a = (rowok && k < nS && k >= lo && k <= hi) ? r[wbase + wrap_idx(L, cdir, cstart + k)] : (T)0;
             b = SC[k * np + col0 + j];
         } else if (MODE == SG_FWD2) {
             a = SR[k * np + row0 + j];
@@ -1810,15 +1847,15 @@ __global__ void __launch_bounds__(64) k_star_gemm(LevelTabs<T> tb, const T* __re
         int i1, i2, i3;
         int64_t slot;
         if (f == 0) {
-            i1 = c1; i2 = c2 + ob; i3 = c3 + oa;
+            i1 = c1; i2 = wrap_idx(L, 1, c2 + ob); i3 = wrap_idx(L, 2, c3 + oa);
             slot = L.plane0(v1) + (int64_t)i3 * L.pitch[0] + i2;
         } else if (f == 1) {
             if (ob == 0) continue;   // x3-axis line: stored in family 0
-            i1 = c1 + ob; i2 = c2; i3 = c3 + oa;
+            i1 = wrap_idx(L, 0, c1 + ob); i2 = c2; i3 = wrap_idx(L, 2, c3 + oa);
             slot = L.plane1(v2) + (int64_t)i3 * L.pitch[1] + i1;
         } else {
             if (ob == 0 || oa == 0) continue;   // axis lines: stored in families 0 and 1
-            i1 = c1 + ob; i2 = c2 + oa; i3 = c3;
+            i1 = wrap_idx(L, 0, c1 + ob); i2 = wrap_idx(L, 1, c2 + oa); i3 = c3;
             slot = L.plane2(v3) + (int64_t)i2 * L.pitch[2] + i1;
         }
         if (i1 < 0 || i1 >= L.N[0] || i2 < 0 || i2 >= L.N[1] || i3 < 0 || i3 >= L.N[2] || is_dir(L, i1, i2, i3))
@@ -2096,11 +2133,12 @@ __global__ void __launch_bounds__(256) k_blk_eigen(LevelTabs<T> tb, const T* __r
 // three backward passes, and the skeleton values back into the plane
 // layout.  The condensed solution is the skeleton part of the full solution.
 // ---------------------------------------------------------------------------
-__global__ void k_fd_scatter(Layout L, const double* __restrict__ b, double* __restrict__ X, int m1, int m2, int m3) {
+__global__ void k_fd_scatter(Layout L, const double* __restrict__ b, double* __restrict__ X, int m1, int m2, int m3,
+                             int o1, int o2, int o3) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)m1 * m2 * m3) return;
     const int a1 = (int)(t % m1), a2 = (int)((t / m1) % m2), a3 = (int)(t / ((int64_t)m1 * m2));
-    const int i1 = a1 + 1, i2 = a2 + 1, i3 = a3 + 1, p = L.p;
+    const int i1 = a1 + o1, i2 = a2 + o2, i3 = a3 + o3, p = L.p;
     const bool on1 = i1 % p == 0, on2 = i2 % p == 0, on3 = i3 % p == 0;
     X[t] = (on1 || on2 || on3) ? b[L.slot(i1, i2, i3, on1, on2)] : 0.0;
 }
@@ -2146,7 +2184,8 @@ __global__ void k_fd_scale(double* __restrict__ X, const double* __restrict__ mu
 
 // Every slot of the plane layout: the solution at a free skeleton node (in
 // its storing family), zero elsewhere.
-__global__ void k_fd_gather(Layout L, const double* __restrict__ X, double* __restrict__ x, int m1, int m2) {
+__global__ void k_fd_gather(Layout L, const double* __restrict__ X, double* __restrict__ x, int m1, int m2, int o1,
+                            int o2, int o3) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= L.len) return;
     const int d = (s >= L.off[2]) ? 2 : (s >= L.off[1] ? 1 : 0);
@@ -2162,8 +2201,8 @@ __global__ void k_fd_gather(Layout L, const double* __restrict__ X, double* __re
         if (d == 0) { i1 = j * p; i3 = r; i2 = c; canon = c < L.N[1]; }
         else if (d == 1) { i2 = j * p; i3 = r; i1 = c; canon = c < L.N[0] && (c % p) != 0; }
         else { i3 = j * p; i2 = r; i1 = c; canon = c < L.N[0] && (c % p) != 0 && (r % p) != 0; }
-        if (canon && !is_dir(L, i1, i2, i3))
-            v = X[((int64_t)(i3 - 1) * m2 + (i2 - 1)) * m1 + (i1 - 1)];
+        if (canon && !is_dir(L, i1, i2, i3) && !is_mirror(L, i1, i2, i3))
+            v = X[((int64_t)(i3 - o3) * m2 + (i2 - o2)) * m1 + (i1 - o1)];
     }
     x[s] = v;
 }
@@ -2171,7 +2210,8 @@ __global__ void k_fd_gather(Layout L, const double* __restrict__ X, double* __re
 void launch_fd_solve(const Layout& L, const FdTabs& fd, double lam, const double* b, double* x, hipStream_t st) {
     const int m1 = fd.m[0], m2 = fd.m[1], m3 = fd.m[2];
     const int64_t M = (int64_t)m1 * m2 * m3;
-    hipLaunchKernelGGL(k_fd_scatter, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, L, b, fd.X, m1, m2, m3);
+    hipLaunchKernelGGL(k_fd_scatter, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, L, b, fd.X, m1, m2, m3,
+                       fd.o[0], fd.o[1], fd.o[2]);
     // direction d of the [m3][m2][m1] array X with the m x m matrix A
     // (out[.., k, ..] = sum_i A[k][i] in[.., i, ..]):
     //   d = 0: out[o][k] = sum_i in[o][i] A[k][i]        (o over m2 m3)
@@ -2211,7 +2251,68 @@ void launch_fd_solve(const Layout& L, const FdTabs& fd, double lam, const double
     pass(1, fd.Ab[1], fd.X, fd.Y);
     pass(0, fd.Ab[0], fd.Y, fd.X);
     hipLaunchKernelGGL(k_fd_gather, dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, st, L, (const double*)fd.X,
-                       x, m1, m2);
+                       x, m1, m2, fd.o[0], fd.o[1], fd.o[2]);
+}
+
+// ---------------------------------------------------------------------------
+// Periodic seams.  Direction d's mirror slots are the nodes with i_d =
+// N_d - 1; each repeats the node with i_d = 0 and the same other indices
+// (both stored in the same plane family).  One thread per (i_a, i_b) of the
+// other two directions; mode 0: mirror = its node (expand), 1: node +=
+// mirror, mirror = 0 (fold), 2: mirror = 0.  Run per periodic direction in
+// the order x1, x2, x3, so that a node mirrored in two or three directions
+// ends up on (or takes its value from) the node at the origin of both.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_seam(Layout L, int d, int mode, T* __restrict__ x) {
+    const int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)L.N[da] * L.N[db]) return;
+    int g[3];
+    g[da] = (int)(t % L.N[da]);
+    g[db] = (int)(t / L.N[da]);
+    const int p = L.p;
+    g[d] = 0;
+    const bool on1 = g[0] % p == 0, on2 = g[1] % p == 0;
+    const int64_t sc = L.slot(g[0], g[1], g[2], on1, on2);
+    g[d] = L.N[d] - 1;
+    const int64_t sm = L.slot(g[0], g[1], g[2], on1, on2);
+    // skeleton nodes only: i_d = 0 is an element boundary, so every node of
+    // the seam is one; both slots are owned by the same family
+    if (mode == 0) x[sm] = x[sc];
+    else if (mode == 1) {
+        x[sc] += x[sm];
+        x[sm] = T(0);
+    } else x[sm] = T(0);
+}
+
+template <typename T>
+void launch_seam(const Layout& L, int mode, T* x, hipStream_t st) {
+    if (!L.any_per()) return;
+    for (int d = 0; d < 3; ++d) {
+        if (!L.per(d)) continue;
+        const int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
+        const int64_t n = (int64_t)L.N[da] * L.N[db];
+        hipLaunchKernelGGL(k_seam<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, L, d, mode, x);
+    }
+}
+
+// Copy of a node grid with each periodic direction's last layer set to its
+// first (the element kernels of condensation read f there).
+__global__ void k_grid_seam_copy(Layout L, const double* __restrict__ f, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)L.N[0] * L.N[1] * L.N[2];
+    if (i >= tot) return;
+    const int i1 = (int)(i % L.N[0]);
+    const int64_t t = i / L.N[0];
+    const int i2 = (int)(t % L.N[1]), i3 = (int)(t / L.N[1]);
+    const int j1 = wrap_idx(L, 0, i1), j2 = wrap_idx(L, 1, i2), j3 = wrap_idx(L, 2, i3);
+    out[i] = f[((int64_t)j3 * L.N[1] + j2) * L.N[0] + j1];
+}
+
+void launch_grid_seam_copy(const Layout& L, const double* f, double* out, hipStream_t st) {
+    const int64_t tot = (int64_t)L.N[0] * L.N[1] * L.N[2];
+    hipLaunchKernelGGL(k_grid_seam_copy, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L, f, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -2632,9 +2733,10 @@ __device__ inline double tiny_fi(const LevelTabs<double>& tb, const TinyElem& t,
 }
 
 // p = 2: one thread per element corrects the three face centres on its
-// lower faces (each face centre belongs to one element below and one above;
-// on the domain boundary it is a Dirichlet node), with both elements' terms
-// in a fixed order: deterministic, no atomics.
+// lower faces (each face centre belongs to one element below and one above)
+// with both elements' terms in a fixed order, and a face centre on the
+// domain boundary that is not a Dirichlet node with its one element's term:
+// deterministic, no atomics.
 __global__ void k_condense_tiny(LevelTabs<double> tb, const double* __restrict__ f, double* __restrict__ Fh) {
     const Layout& L = tb.lay;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2646,7 +2748,17 @@ __global__ void k_condense_tiny(LevelTabs<double> tb, const double* __restrict__
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int cd = d == 0 ? c0 : (d == 1 ? c1 : c2);
-        if (cd == 0) continue;
+        if (cd == L.n[d] - 1 && !(d == 0 ? L.dhi(0) : (d == 1 ? L.dhi(1) : L.dhi(2)))) {
+            const int64_t up = elem_slot(L, ec, d == 0 ? 2 : 1, d == 1 ? 2 : 1, d == 2 ? 2 : 1);
+            Fh[up] -= tiny_hib(te, d, 2) * se;
+        }
+        if (cd == 0) {
+            if (!(d == 0 ? L.dlo(0) : (d == 1 ? L.dlo(1) : L.dlo(2)))) {
+                const int64_t lo = elem_slot(L, ec, d == 0 ? 0 : 1, d == 1 ? 0 : 1, d == 2 ? 0 : 1);
+                Fh[lo] -= tiny_hib(te, d, 0) * se;
+            }
+            continue;
+        }
         const int n0 = d == 0 ? c0 - 1 : c0, n1 = d == 1 ? c1 - 1 : c1, n2 = d == 2 ? c2 - 1 : c2;
         const TinyElem tn = tiny_elem(tb, n0, n1, n2);
         const double sn = tiny_fi(tb, tn, f, n0, n1, n2) / tiny_hii(tn, tb.lam);
@@ -3545,7 +3657,8 @@ struct CoarseShape {
 // element interiors, whose value counts as zero.
 template <int P>
 __device__ __forceinline__ int64_t skel_slot(const Layout& L, int i1, int i2, int i3, int64_t dflt, bool& ok) {
-    const bool in = i1 > 0 && i2 > 0 && i3 > 0 && i1 < L.N[0] - 1 && i2 < L.N[1] - 1 && i3 < L.N[2] - 1;
+    const bool in = i1 >= 0 && i2 >= 0 && i3 >= 0 && i1 < L.N[0] && i2 < L.N[1] && i3 < L.N[2] &&
+                    !is_dir(L, i1, i2, i3);
     const bool on1 = i1 % P == 0, on2 = i2 % P == 0, on3 = i3 % P == 0;
     ok = in && (on1 || on2 || on3);
     return ok ? L.slot(i1, i2, i3, on1, on2) : dflt;
@@ -3662,9 +3775,12 @@ __global__ void __launch_bounds__(256) k_condensed_op_low(LevelTabs<T> tb, const
         if ((int)b1 + (int)b2 + (int)b3 == 1) {
             const int dd = b1 ? 0 : (b2 ? 1 : 2);
             const int f1 = g1 >> 1, f2 = g2 >> 1, f3 = g3 >> 1;  // element above the face
+            const int fd = dd == 0 ? f1 : (dd == 1 ? f2 : f3);
             const int64_t eh = ((int64_t)f3 * L.n[1] + f2) * L.n[0] + f1;
             const int64_t el = eh - (dd == 0 ? 1 : (dd == 1 ? L.n[0] : (int64_t)L.n[0] * L.n[1]));
-            const T tl = tb.tc[el], th = tb.tc[eh];
+            // on a boundary face (Neumann, or the unfolded seam of a periodic
+            // direction) only the element inside the mesh contributes
+            const T tl = fd > 0 ? tb.tc[el] : T(0), th = fd < L.n[dd] ? tb.tc[eh] : T(0);
             const T mo = dd == 0 ? m2 * m3 : (dd == 1 ? m1 * m3 : m1 * m2);
             const T cl = dd == 0 ? c1[1] : (dd == 1 ? c2[1] : c3[1]);
             const T ch = dd == 0 ? c1[3] : (dd == 1 ? c2[3] : c3[3]);
@@ -3716,7 +3832,7 @@ __global__ void __launch_bounds__(256) k_condensed_op_box2(LevelTabs<T> tb, cons
     const int tx = threadIdx.x % BOX_X, ty = threadIdx.x / BOX_X;   // 32 x 8
     const int g1 = X0 + tx, g2 = Y0 + ty;
     T m1 = 0, m2 = 0, c1[5] = {0, 0, 0, 0, 0}, c2[5] = {0, 0, 0, 0, 0};
-    const bool in12 = g1 > 0 && g1 < L.N[0] - 1 && g2 > 0 && g2 < L.N[1] - 1;
+    const bool in12 = g1 < L.N[0] && g2 < L.N[1] && !is_dir(L, g1, g2, 1);
     if (in12) {
         axis_rec<T, 2>(tb.ax[0], g1, m1, c1);
         axis_rec<T, 2>(tb.ax[1], g2, m2, c2);
@@ -3725,7 +3841,7 @@ __global__ void __launch_bounds__(256) k_condensed_op_box2(LevelTabs<T> tb, cons
         const int g3 = Z0 + tz;
         const int lx = tx + 2, ly = ty + 2, lz = tz + 2;
         T out = 0;
-        const bool unk = in12 && g3 > 0 && g3 < L.N[2] - 1 && !((g1 & 1) && (g2 & 1) && (g3 & 1));
+        const bool unk = in12 && g3 < L.N[2] && !is_dir(L, g1, g2, g3) && !((g1 & 1) && (g2 & 1) && (g3 & 1));
         if (unk) {
             T m3, c3[5];
             axis_rec<T, 2>(tb.ax[2], g3, m3, c3);
@@ -3743,9 +3859,10 @@ __global__ void __launch_bounds__(256) k_condensed_op_box2(LevelTabs<T> tb, cons
             const bool b1 = (g1 & 1) == 0, b2 = (g2 & 1) == 0, b3 = (g3 & 1) == 0;
             if ((int)b1 + (int)b2 + (int)b3 == 1) {   // face centre (as in k_condensed_op_low)
                 const int dd = b1 ? 0 : (b2 ? 1 : 2);
+                const int fd = (dd == 0 ? g1 : (dd == 1 ? g2 : g3)) >> 1;
                 const int64_t eh = ((int64_t)(g3 >> 1) * L.n[1] + (g2 >> 1)) * L.n[0] + (g1 >> 1);
                 const int64_t el = eh - (dd == 0 ? 1 : (dd == 1 ? L.n[0] : (int64_t)L.n[0] * L.n[1]));
-                const T tl = tb.tc[el], th = tb.tc[eh];
+                const T tl = fd > 0 ? tb.tc[el] : T(0), th = fd < L.n[dd] ? tb.tc[eh] : T(0);
                 const T mo = dd == 0 ? m2 * m3 : (dd == 1 ? m1 * m3 : m1 * m2);
                 const T cl = dd == 0 ? c1[1] : (dd == 1 ? c2[1] : c3[1]);
                 const T ch = dd == 0 ? c1[3] : (dd == 1 ? c2[3] : c3[3]);
@@ -4154,7 +4271,25 @@ static void launch_gather_elem(const Layout& L, const T* E, const T* F, T* y, hi
 }
 
 template <typename T>
+void condensed_op_unfolded(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t st, const T* F);
+
+template <typename T>
 void launch_condensed_op(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t st, const T* F) {
+    // periodic seams: the element kernels read u unfolded (its mirror slots
+    // filled for the call and cleared after it) and their sums at the mirror
+    // nodes are folded onto the nodes those repeat
+    if (tb.lay.any_per()) {
+        launch_seam<T>(tb.lay, 0, const_cast<T*>(u), st);
+        condensed_op_unfolded<T>(tb, u, y, st, F);
+        launch_seam<T>(tb.lay, 1, y, st);
+        launch_seam<T>(tb.lay, 2, const_cast<T*>(u), st);
+        return;
+    }
+    condensed_op_unfolded<T>(tb, u, y, st, F);
+}
+
+template <typename T>
+void condensed_op_unfolded(const LevelTabs<T>& tb, const T* u, T* y, hipStream_t st, const T* F) {
     const int ne = tb.lay.n[0] * tb.lay.n[1] * tb.lay.n[2];
     if (tb.lay.p <= 2) {
         const Layout& L = tb.lay;
@@ -4223,7 +4358,9 @@ void launch_smoother_add(const LevelTabs<T>& tb, const T* r, T* du, T omega, hip
         // 19 per star; measured 1.3x (FP64) and 1.9x (FP32) faster at 1.3M
         // stars, slower at 166k stars and at p = 4 in FP64); otherwise one
         // launch with atomics
-        if (tb.lay.p <= 2 && nstars >= (1 << 19)) {
+        // (stars on both sides of a periodic seam can share a parity and
+        // overlap there: atomics then)
+        if (tb.lay.p <= 2 && nstars >= (1 << 19) && !tb.lay.any_per()) {
             int nv[3] = {tb.lay.n[0] + 1, tb.lay.n[1] + 1, tb.lay.n[2] + 1};
             for (int col = 0; col < 8; ++col) {
                 const int cnt = color_count(nv, col);
@@ -4314,7 +4451,20 @@ int64_t restrict_work_len(const Layout& Lf, const Layout& Lc) {
 }
 
 template <typename T, typename TC>
+void prolong_unfolded(const Layout& Lc, const Layout& Lf, const T* J, const TC* uc, T* uf, hipStream_t st);
+
+template <typename T, typename TC>
 void launch_prolong_add(const Layout& Lc, const Layout& Lf, const T* J, const TC* uc, T* uf, hipStream_t st) {
+    // periodic seams: interpolate from the unfolded coarse vector; the fine
+    // mirror slots then hold copies and are cleared
+    launch_seam<TC>(Lc, 0, const_cast<TC*>(uc), st);
+    prolong_unfolded<T, TC>(Lc, Lf, J, uc, uf, st);
+    launch_seam<T>(Lf, 2, uf, st);
+    launch_seam<TC>(Lc, 2, const_cast<TC*>(uc), st);
+}
+
+template <typename T, typename TC>
+void prolong_unfolded(const Layout& Lc, const Layout& Lf, const T* J, const TC* uc, T* uf, hipStream_t st) {
     const dim3 g = plane_grid(Lf, max_cols(Lf), max_rows(Lf)), b(64, 4);
 #define PMG_PRO(A, B) hipLaunchKernelGGL((k_prolong_direct<T, TC, A, B>), g, b, 0, st, Lc, Lf, J, uc, uf)
     if (Lf.p == 2 && Lc.p == 1) PMG_PRO(2, 1);
@@ -4347,6 +4497,7 @@ void launch_restrict(const Layout& Lf, const Layout& Lc, const T* J, const T* rf
     else PMG_RES(0, 0);
 #undef PMG_RES
     hipLaunchKernelGGL((k_restrict_combine<T, TC>), dim3(nblk(Lc.len)), dim3(256), 0, st, Lc, (const T*)tbuf, rc);
+    launch_seam<TC>(Lc, 1, rc, st);   // sums at coarse mirror nodes onto the nodes they repeat
 }
 
 template <typename T, typename TC>
@@ -4384,8 +4535,19 @@ static unsigned int_blocks(const LevelTabs<double>& tb) {
     return (unsigned)std::min<size_t>((n + 255) / 256, 65536);
 }
 
+static void condense_unfolded(const LevelTabs<double>& tb, const double* m1, const double* m2, const double* m3,
+                              const double* f, double* Fh, hipStream_t st);
+
+// f: on a mesh with a periodic direction, a grid whose last layer repeats
+// the first (the element kernels read it there)
 void launch_condense(const LevelTabs<double>& tb, const double* m1, const double* m2, const double* m3,
                      const double* f, double* Fh, hipStream_t st) {
+    condense_unfolded(tb, m1, m2, m3, f, Fh, st);
+    launch_seam<double>(tb.lay, 1, Fh, st);
+}
+
+static void condense_unfolded(const LevelTabs<double>& tb, const double* m1, const double* m2, const double* m3,
+                              const double* f, double* Fh, hipStream_t st) {
     const Layout& L = tb.lay;
     hipLaunchKernelGGL(k_mass_skeleton, dim3(nblk(L.len)), dim3(256), 0, st, L, m1, m2, m3, f, Fh);
     int q = L.p - 1;
@@ -4438,7 +4600,17 @@ void launch_condense(const LevelTabs<double>& tb, const double* m1, const double
     }
 }
 
+static void recover_unfolded(const LevelTabs<double>& tb, const double* f, const double* uh, double* ug,
+                             hipStream_t st);
+
 void launch_recover(const LevelTabs<double>& tb, const double* f, const double* uh, double* ug, hipStream_t st) {
+    launch_seam<double>(tb.lay, 0, const_cast<double*>(uh), st);
+    recover_unfolded(tb, f, uh, ug, st);
+    launch_seam<double>(tb.lay, 2, const_cast<double*>(uh), st);
+}
+
+static void recover_unfolded(const LevelTabs<double>& tb, const double* f, const double* uh, double* ug,
+                             hipStream_t st) {
     const Layout& L = tb.lay;
     if (L.p <= 2) {
         const int64_t ne = (int64_t)L.n[0] * L.n[1] * L.n[2];

@@ -15,9 +15,10 @@
 
 namespace pmg {
 
-Layout make_layout(int n1, int n2, int n3, int p) {
+Layout make_layout(int n1, int n2, int n3, int p, int bc) {
     Layout L{};
     L.p = p;
+    L.bc = bc;
     L.n[0] = n1; L.n[1] = n2; L.n[2] = n3;
     for (int d = 0; d < 3; ++d) L.N[d] = L.n[d] * p + 1;
     auto pad = [](int v) { return (v + 3) & ~3; };
@@ -290,22 +291,28 @@ void build_block_tables(int p, const std::vector<double>& h, int np, std::vector
 // n p + 1 nodes, the two Dirichlet end nodes removed, and their generalized
 // eigenpairs S^T L S = diag(mu), S^T M S = I.  Outputs (m = n p - 1):
 // Af[k][i] = S[i][k] (forward transform), Ab[i][k] = S[i][k] (backward), mu.
-void build_fd_tables(int p, const std::vector<double>& h, std::vector<double>& Af, std::vector<double>& Ab,
-                     std::vector<double>& mu) {
+void build_fd_tables(int p, const std::vector<double>& h, int bc_d, std::vector<double>& Af,
+                     std::vector<double>& Ab, std::vector<double>& mu, int& first) {
     std::vector<double> x, w, Ls;
     gll_nodes_weights(p, x, w);
     stiffness_std(p, x, w, Ls);
-    const int n = (int)h.size(), N = n * p + 1, m = N - 2, n1 = p + 1;
+    const bool per = (bc_d >> 2) & 1, dl = !per && (bc_d & 1), dh = !per && ((bc_d >> 1) & 1);
+    // assembled on the n p + 1 nodes, or on the n p distinct ones of a
+    // periodic direction (the last element's end node is node 0)
+    const int n = (int)h.size(), N = per ? n * p : n * p + 1, n1 = p + 1;
     std::vector<double> M(N, 0.0), L((size_t)N * N, 0.0);
     for (int e = 0; e < n; ++e)
         for (int a = 0; a < n1; ++a) {
-            M[e * p + a] += 0.5 * h[e] * w[a];
-            for (int b = 0; b < n1; ++b) L[(size_t)(e * p + a) * N + e * p + b] += (2.0 / h[e]) * Ls[a * n1 + b];
+            const int ga = (e * p + a) % N;
+            M[ga] += 0.5 * h[e] * w[a];
+            for (int b = 0; b < n1; ++b) L[(size_t)ga * N + (e * p + b) % N] += (2.0 / h[e]) * Ls[a * n1 + b];
         }
+    first = dl ? 1 : 0;
+    const int m = N - (dl ? 1 : 0) - (dh ? 1 : 0);
     std::vector<double> Li((size_t)m * m), Mi(m), S;
     for (int a = 0; a < m; ++a) {
-        Mi[a] = M[a + 1];
-        for (int b = 0; b < m; ++b) Li[(size_t)a * m + b] = L[(size_t)(a + 1) * N + b + 1];
+        Mi[a] = M[a + first];
+        for (int b = 0; b < m; ++b) Li[(size_t)a * m + b] = L[(size_t)(a + first) * N + b + first];
     }
     gen_eig_diag(m, Li.data(), Mi.data(), S, mu);
     Af.assign((size_t)m * m, 0.0);
@@ -317,7 +324,7 @@ void build_fd_tables(int p, const std::vector<double>& h, std::vector<double>& A
         }
 }
 
-void build_level_tables(int p, int pc, const std::vector<double> h[3], HostTables& t) {
+void build_level_tables(int p, int pc, const std::vector<double> h[3], HostTables& t, int bc) {
     std::vector<double> x, w, Ls;
     gll_nodes_weights(p, x, w);
     stiffness_std(p, x, w, Ls);
@@ -357,7 +364,13 @@ void build_level_tables(int p, int pc, const std::vector<double> h[3], HostTable
                 }
             }
         }
-        // stars: block positions -p..p -> 0..2p; keep 1..2p-1
+        // stars: block positions -p..p -> 0..2p; keep 1..2p-1.  Sec. 3.3: an
+        // element outside the domain is decoupled (identity), and so is a
+        // Dirichlet vertex; a Neumann vertex stays coupled; in a periodic
+        // direction the element before vertex 0 is the last one (the star of
+        // vertex ne duplicates it and is never used)
+        const bool per = (bc >> (6 + d)) & 1;
+        const bool dlo = !per && ((bc >> d) & 1), dhi = !per && ((bc >> (3 + d)) & 1);
         for (int v = 0; v <= ne; ++v) {
             std::vector<double> M(2 * p + 1, 0.0), L((2 * p + 1) * (2 * p + 1), 0.0);
             std::vector<char> cpl(2 * p + 1, 0);
@@ -371,8 +384,9 @@ void build_level_tables(int p, int pc, const std::vector<double> h[3], HostTable
                 }
             };
             if (v >= 1) add_el(v - 1, 0);
+            else if (per) add_el(ne - 1, 0);
             if (v <= ne - 1) add_el(v, p);
-            if (v == 0 || v == ne) cpl[p] = 0;
+            if ((v == 0 && dlo) || (v == ne && dhi)) cpl[p] = 0;
             std::vector<int> c;
             for (int i = 1; i < 2 * p; ++i)
                 if (cpl[i]) c.push_back(i);

@@ -8,8 +8,14 @@ import paper_1808_03595_amd as pmg
 from oracle import mesh as omesh
 
 
-def make_pair(n, p, lam, alpha=1.0, widths=None):
-    """Build the GPU mesh and the oracle mesh of the same problem."""
+def make_pair(n, p, lam, alpha=1.0, widths=None, bc=None):
+    """Build the GPU mesh and the oracle mesh of the same problem (boundary
+    kinds ``bc`` as the oracle's mesh takes them; Dirichlet if None)."""
+    if bc is not None:
+        o = omesh.Mesh.box(n, p, lam, alpha, bc=bc) if widths is None else \
+            omesh.Mesh(widths[0], widths[1], widths[2], p, lam, bc)
+        g = pmg.create_mesh_bc(o.h[0], o.h[1], o.h[2], p, lam, o.bc)
+        return g, o
     if widths is None:
         g = pmg.create_mesh(n[0], n[1], n[2], p, lam, alpha)
         o = omesh.Mesh.box(n, p, lam, alpha)
@@ -49,7 +55,7 @@ class LevelIO:
     family 2), which the finest-level round trip pins.
     """
 
-    def __init__(self, g, level):
+    def __init__(self, g, level, bc=None):
         self.g = g
         self.p = g.level_degree(level)
         n = g.n
@@ -64,8 +70,17 @@ class LevelIO:
         assert off[2] + (n[2] + 1) * pst[2] == self.len
         i3, i2, i1 = np.meshgrid(np.arange(N[2]), np.arange(N[1]), np.arange(N[0]), indexing="ij")
         on1, on2, on3 = i1 % p == 0, i2 % p == 0, i3 % p == 0
-        dirichlet = ((i1 == 0) | (i2 == 0) | (i3 == 0) | (i1 == N[0] - 1)
-                     | (i2 == N[1] - 1) | (i3 == N[2] - 1))
+        kinds = omesh.parse_bc(bc)
+        ii = (i1, i2, i3)
+        dirichlet = np.zeros(i1.shape, dtype=bool)
+        for d in range(3):
+            lo, hi = kinds[d]
+            if lo == "D":
+                dirichlet |= ii[d] == 0
+            if hi == "D":
+                dirichlet |= ii[d] == N[d] - 1
+            if lo == "P":             # mirror layer: no unknown of its own
+                dirichlet |= ii[d] == N[d] - 1
         skel = (on1 | on2 | on3) & ~dirichlet
         slot = np.where(on1, off[0] + (i1 // p) * pst[0] + i3 * pitch[0] + i2,
                         np.where(on2, off[1] + (i2 // p) * pst[1] + i3 * pitch[1] + i1,

@@ -54,6 +54,27 @@ def test_invalid_mesh_arguments(lib):
     assert lib.pmg_create_mesh_widths(2, 2, 2, 4, 1.0, None, ok, ok, ctypes.byref(h)) == -1
 
 
+def test_invalid_boundary_kinds(lib):
+    """Boundary kinds are checked before any device work (Sec. 3.3 kinds:
+    0 Dirichlet, 1 Neumann, 2 periodic on both sides of a direction)."""
+    h = ctypes.c_void_p()
+    w3 = (ctypes.c_double * 3)(0.3, 0.3, 0.4)
+    w2 = (ctypes.c_double * 2)(0.5, 0.5)
+    bad = [
+        (w3, (0, 0, 3, 0, 0, 0), 1.0),    # unknown kind
+        (w3, (2, 0, 0, 0, 0, 0), 1.0),    # periodic on one side only
+        (w3, (1, 1, 1, 1, 1, 1), 0.0),    # no Dirichlet side and lambda = 0: singular
+        (w3, (2, 2, 1, 1, 2, 2), 0.0),
+        (w2, (2, 2, 0, 0, 0, 0), 1.0),    # periodic direction with 2 elements
+    ]
+    for w, kinds, lam in bad:
+        k = (ctypes.c_int * 6)(*kinds)
+        n = len(w)
+        assert lib.pmg_create_mesh_bc(n, 3, 3, 4, lam, w, w3, w3, k, ctypes.byref(h)) == -1, kinds
+        assert lib.pmg_last_error()
+    assert lib.pmg_create_mesh_bc(3, 3, 3, 4, 1.0, w3, w3, w3, None, ctypes.byref(h)) == -1
+
+
 def test_null_handles_and_pointers(lib):
     L = ctypes.c_int()
     n = ctypes.c_int64()
