@@ -51,8 +51,19 @@ class Hierarchy:
                  coarse_rtol: float = 1e-8, coarse_maxit: int = 2000,
                  exact_coarse: bool = False, hmg_levels: int = 0,
                  hmg_omega: float = 0.6, hmg_nu: int = 1,
-                 smoother: str = "star", block_weights: str = "smooth", coarse: str = "cg"):
+                 smoother: str = "star", block_weights: str = "smooth", coarse: str = "cg",
+                 coarse_level: int = 0):
+        # coarse_level k > 0: the exact coarse solve inverts the condensed
+        # system of p-level k; the levels below it are not part of the cycle
         self.degs = level_degrees(mesh.p)
+        if coarse_level:
+            if coarse != "fd" and not exact_coarse:
+                raise ValueError("a coarse level above 0 needs an exact coarse solve")
+            if hmg_levels:
+                raise ValueError("a coarse level above 0 excludes degree-1 levels")
+            if not 0 < coarse_level < len(self.degs):
+                raise ValueError("coarse level out of range")
+            self.degs = self.degs[coarse_level:]
         Lp = len(self.degs) - 1
         pmeshes = [mesh.with_degree(q) for q in self.degs]
         pmeshes[-1] = mesh

@@ -47,3 +47,30 @@ def test_vcycle_with_fd_coarse_equals_dense_coarse():
     a = solver.Hierarchy(m, coarse="fd").vcycle(None, r)
     b = solver.Hierarchy(m, exact_coarse=True).vcycle(None, r)
     assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
+
+
+def test_coarse_level_above_zero():
+    """Exact coarse solve on p-level k > 0 (the levels below it dropped):
+    with k = L the V-cycle is the exact condensed solve (dense
+    Schur-complement solve); with 0 < k < L the cycle with the fast
+    diagonalization equals the one with the dense coarse solve; whole solves
+    meet the tolerance against the dense full solve."""
+    m = omesh.Mesh.box((3, 2, 3), 8, 1.0, 1.2)          # levels 2, 4, 8
+    cs = CondensedSystem(m)
+    r = synth.random_grid(m.shape, 5) * m.free_skeleton_mask()
+    top = solver.Hierarchy(m, coarse="fd", coarse_level=2)
+    assert top.L == 0
+    ref = cs.to_grid(np.linalg.solve(cs.Hhat, cs.to_vec(r)))
+    assert np.linalg.norm(top.vcycle(None, r) - ref) <= 1e-12 * np.linalg.norm(ref)
+    a = solver.Hierarchy(m, coarse="fd", coarse_level=1).vcycle(None, r)
+    b = solver.Hierarchy(m, exact_coarse=True, coarse_level=1).vcycle(None, r)
+    assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
+    assert np.linalg.norm(a - ref) > 1e-6 * np.linalg.norm(ref)    # one smoothed level left
+    f = synth.random_grid(m.shape, 6)
+    res = solver.solve(m, f, rtol=1e-11, coarse="fd", coarse_level=1)
+    full = cs.full_solve(m.assembled_mass() * f)
+    assert np.linalg.norm(res.u - full) <= 1e-9 * np.linalg.norm(full)
+    with pytest.raises(ValueError):
+        solver.Hierarchy(m, coarse_level=1)                   # coarse CG: level 0 only
+    with pytest.raises(ValueError):
+        solver.Hierarchy(m, coarse="fd", coarse_level=3)
