@@ -174,7 +174,7 @@ def coarse_levels(p, uniform, ne):
 # coarse solver of every solve: "fd" (exact solve by fast diagonalization of
 # the whole coarse mesh) or "cg" (the paper's Jacobi CG on p_0 = 2, with the
 # degree-1 levels of coarse_levels below it)
-COARSE = {"kind": "fd"}
+COARSE = {"kind": "fd", "level": "auto"}
 
 
 def configure_coarse(g, wl, coarse_rtol):
@@ -194,6 +194,39 @@ def configure_coarse(g, wl, coarse_rtol):
     if hmg:
         kw.update(hmg_levels=hmg, hmg_omega=0.8, hmg_nu=2)
     return desc, kw
+
+
+FD_MAX = 200   # largest fast-diagonalization size n_d p_k per direction a coarse level may have
+
+
+def coarse_candidates(g):
+    """p-levels k whose condensed system the exact coarse solve may invert:
+    0 <= k < L (at least one smoothed level stays) with n_d p_k <= FD_MAX."""
+    L = g.num_levels()
+    return [k for k in range(max(L, 1)) if max(g.n) * g.level_degree(k) <= FD_MAX] or [0]
+
+
+def tune_coarse_level(g, solve, torch, reps=2):
+    """The exact coarse level whose whole solve measures fastest (one warm-up
+    and `reps` timed solves per candidate, outside every timed region);
+    returns (level, {level: ms})."""
+    if COARSE["kind"] != "fd" or g.num_levels() == 0:
+        return 0, {}
+    if COARSE["level"] != "auto":
+        return int(COARSE["level"]), {}
+    ms = {}
+    for k in coarse_candidates(g):
+        g.set_coarse_level(k)
+        solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            solve()
+        torch.cuda.synchronize()
+        ms[k] = (time.perf_counter() - t0) / reps * 1e3
+    best = min(ms, key=ms.get)
+    g.set_coarse_level(best)
+    return best, ms
 
 
 def learned_damping(wl, L):
@@ -363,14 +396,20 @@ def solver_row(g, wl, torch, synth, dev, steps, warm, with_omega1=False, keep=Fa
         runs.insert(1, ("mixed_omega1", pmg.F32, None))
     row, sols = {}, {}
     for name, dtype, om in runs:
+        g.set_damping(om)
+        cl, cand = tune_coarse_level(g, lambda: g.pcg_solve(f, u, 1e-10, 300, dtype), torch)
         mean, best, st = timed_solves(g, f, u, dtype, om, steps, warm, torch)
         err = (torch.linalg.vector_norm(u - u_ex) / torch.linalg.vector_norm(u_ex)).item()
         row[name] = {"unknowns_per_s": ndof / mean, "ms": mean * 1e3, "ms_min": best * 1e3,
                      "iters": st.iters, "coarse_iters": st.coarse_iters, "rel_res": st.rel_res,
-                     "status": st.status, "rel_err_vs_exact": err}
+                     "status": st.status, "rel_err_vs_exact": err,
+                     "coarse_level": cl, "coarse_degree": g.level_degree(cl),
+                     "coarse_level_ms": {str(k): v for k, v in cand.items()}}
         if keep:
             sols[name] = u.cpu().numpy()
     g.set_damping(None)
+    if COARSE["kind"] == "fd":
+        g.set_coarse_level(0)
     row["omega"] = omega
     return row, ndof, (f.cpu().numpy() if keep else None), sols
 
@@ -478,6 +517,7 @@ def n_sweep(torch, pmg, synth, dev, coarse_rtol, steps, warm):
         omega = learned_damping(wln, L)
         for name, dtype, om in (("fp64", pmg.F64, None), ("mixed_learned", pmg.F32, omega)):
             g.set_damping(om)
+            cl, _ = tune_coarse_level(g, lambda: g.pcg_solve_dirichlet(f, u_ex, u, 1e-10, 300, dtype), torch)
             for _ in range(warm):
                 g.pcg_solve_dirichlet(f, u_ex, u, 1e-10, 300, dtype)
             torch.cuda.synchronize()
@@ -488,6 +528,7 @@ def n_sweep(torch, pmg, synth, dev, coarse_rtol, steps, warm):
             dt = (time.perf_counter() - t0) / steps
             err = (u - u_ex).abs().max().item()
             row[name] = {"ms": dt * 1e3, "iters": st.iters, "ns_per_unknown": dt * 1e9 / ndof,
+                         "coarse_level": cl, "coarse_degree": g.level_degree(cl),
                          "ns_per_unknown_iter": dt * 1e9 / ndof / max(st.iters, 1),
                          "coarse_iters": st.coarse_iters, "rel_res": st.rel_res,
                          "max_err_vs_exact": err, "status": st.status}
@@ -592,6 +633,10 @@ def main():
                     help="coarse solver: exact fast-diagonalization solve (default) or the paper's Jacobi CG "
                          "(with degree-1 levels below p_0 = 2: 6 at p <= 4; 1 at p <= 8 on uniform meshes of "
                          ">= 16^3 elements; else none)")
+    ap.add_argument("--coarse-level", default="auto",
+                    help="p-level of the exact coarse solve: 'auto' (the fastest of the levels below the finest "
+                         "whose fast-diagonalization size is at most 200 per direction, measured per solver "
+                         "before its timed solves) or a level index")
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the smoother timing loop (for counter profiles)")
     ap.add_argument("--op-only", action="store_true",
@@ -646,20 +691,26 @@ def main():
         log(f"[bench] {'smoother' if args.kernel_only else 'operator'} f32: {t * 1e6:.2f} us per launch")
         return
     COARSE["kind"] = args.coarse
+    COARSE["level"] = args.coarse_level
     cdesc, _ = configure_coarse(g, wl, args.coarse_rtol)
     log(f"[bench] workload {args.workload}: {wl['desc']}; coarse solver: {cdesc}")
     if args.profile_solve:
         u_ex, f = make_rhs(g, wl, torch, synth, dev)
         u = torch.zeros_like(f)
-        mean, best, st = timed_solves(g, f, u, pmg.F32, learned_damping(wl, L), args.steps, args.warmup, torch)
-        log(f"[bench] mixed learned: {mean * 1e3:.2f} ms/solve iters={st.iters} rel_res={st.rel_res:.2e}")
+        om = learned_damping(wl, L)
+        g.set_damping(om)
+        cl, _ = tune_coarse_level(g, lambda: g.pcg_solve(f, u, 1e-10, 300, pmg.F32), torch)
+        mean, best, st = timed_solves(g, f, u, pmg.F32, om, args.steps, args.warmup, torch)
+        log(f"[bench] mixed learned: {mean * 1e3:.2f} ms/solve iters={st.iters} rel_res={st.rel_res:.2e} "
+            f"coarse level {cl} (p = {g.level_degree(cl)})")
         return
     head, ndof, f_head, sols = solver_row(g, wl, torch, synth, dev, args.steps, args.warmup,
                                           with_omega1=True, keep=not args.no_cpu)
     for k in ("fp64", "mixed_omega1", "mixed_learned"):
         r = head[k]
         log(f"[bench] {k}: {r['ms']:.2f} ms/solve (min {r['ms_min']:.2f}) iters={r['iters']} "
-            f"rel_res={r['rel_res']:.2e} coarse_iters={r['coarse_iters']} err_vs_exact={r['rel_err_vs_exact']:.2e}")
+            f"rel_res={r['rel_res']:.2e} coarse_iters={r['coarse_iters']} err_vs_exact={r['rel_err_vs_exact']:.2e} "
+            f"coarse level {r['coarse_level']} (p = {r['coarse_degree']}) {r['coarse_level_ms']}")
     mixed = head["mixed_learned"]
 
     roof, kern = None, None
@@ -718,6 +769,7 @@ def main():
                    "damping": "learned" if head["omega"] is not None else "omega=1 (paper)",
                    "omega": head["omega"],
                    "coarse": cdesc,
+                   "coarse_level": mixed["coarse_level"], "coarse_degree": mixed["coarse_degree"],
                    "coarse_iters_per_solve": mixed["coarse_iters"],
                    "solvers": {k: head[k] for k in ("fp64", "mixed_omega1", "mixed_learned")}},
         "roofline": roof,

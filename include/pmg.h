@@ -188,6 +188,16 @@ int pmg_set_coarse_mg(pmg_mesh *m, int levels, double omega, int nu);
  * bottom level.  Synchronizes the device. */
 int pmg_set_coarse_solver(pmg_mesh *m, int kind);
 
+/* The p-level whose condensed system the exact coarse solve inverts at the
+ * bottom of the V-cycle (Alg. 3): 0 (p_0 = 2, the default) up to the finest
+ * level; the levels below it are not used.  A higher coarse level trades the
+ * V-cycle work of the levels below it for a larger fast-diagonalization solve
+ * (6 m^4 operations for m = n p_l per direction, Sec. 4.2's O(n_e^{4/3})
+ * term with a larger constant).  Needs the exact coarse solve
+ * (pmg_set_coarse_solver(m, 1)) and no degree-1 levels, else PMG_EUNSUP.
+ * pmg_coarse_solve then solves that level's system. */
+int pmg_set_coarse_level(pmg_mesh *m, int level);
+
 /* Smoother of every level of degree >= 2 (pmg_schwarz_smooth(_add) and the
  * V-cycle): kind 0 = the vertex-centred star smoother of Alg. 2 (default);
  * kind 1 = the element-centred block smoother of Sec. 3.4: one subdomain

@@ -80,6 +80,7 @@ SIGNATURES = {
     "pmg_restrict": (_I, [_VP, _I, _I, _VP, _VP, _VP]),
     "pmg_set_cycle": (_I, [_VP, _I, _D, _I]),
     "pmg_set_smoother": (_I, [_VP, _I]),
+    "pmg_set_coarse_level": (_I, [_VP, _I]),
     "pmg_set_coarse_solver": (_I, [_VP, _I]),
     "pmg_set_damping": (_I, [_VP, _FP, _I]),
     "pmg_set_coarse_mg": (_I, [_VP, _I, _D, _I]),
@@ -224,6 +225,9 @@ class Mesh:
     def set_coarse_solver(self, kind=0):
         """0: Jacobi CG (Sec. 4.1); 1: exact solve by fast diagonalization."""
         _check(lib().pmg_set_coarse_solver(self.h, kind))
+
+    def set_coarse_level(self, level=0):
+        _check(lib().pmg_set_coarse_level(self.h, level))
 
     def set_smoother(self, kind=0):
         """0: star smoother (Alg. 2); 1: element-centred blocks (Sec. 3.4)."""

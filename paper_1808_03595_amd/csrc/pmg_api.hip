@@ -115,6 +115,7 @@ struct pmg_mesh {
     int bc = BC_ALL_DIRICHLET;  // boundary kinds, as Layout::bc
     double* w_fgrid = nullptr;  // periodic meshes: right-hand side grid with its seam layers equal
     int coarse_kind = 0;        // 0: Jacobi CG (Sec. 4.1), 1: exact solve by fast diagonalization
+    int coarse_level = 0;       // p-level solved exactly at the bottom of the cycle (levels below unused)
     // coarse CG counters shared by all bottom levels
     int* d_coarse_iters = nullptr;
     // number of coarse solves started, counted on the device by every coarse
@@ -448,7 +449,7 @@ int rebuild_active(pmg_mesh* m) {
     int nh = std::min(m->hmg_levels, (int)m->hlv.size());
     m->act.clear();
     for (int k = nh - 1; k >= 0; --k) m->act.push_back(&m->hlv[k]);
-    for (auto& L : m->lv) m->act.push_back(&L);
+    for (size_t k = (size_t)m->coarse_level; k < m->lv.size(); ++k) m->act.push_back(&m->lv[k]);
     const int L = (int)m->act.size() - 1;
     for (int l = 0; l <= L; ++l) {
         Level& v = *m->act[l];
@@ -457,7 +458,7 @@ int rebuild_active(pmg_mesh* m) {
             v.omega = m->hmg_omega;
         } else {
             v.nu = m->nu_mode == 0 ? 1 : (1 << std::min(20, L - l));
-            v.omega = m->omega[l - nh];
+            v.omega = m->omega[l - nh + m->coarse_level];
         }
         if (l > 0) {
             const Level& c = *m->act[l - 1];
@@ -1178,6 +1179,7 @@ int pmg_set_coarse_mg(pmg_mesh* m, int levels, double omega, int nu) {
     if (levels > 0 && m->lv[0].p < 2) return fail(PMG_EUNSUP, "degree-1 levels need p_0 = 2");
     if (levels > 0 && m->bc != BC_ALL_DIRICHLET)
         return fail(PMG_EUNSUP, "degree-1 levels are built for Dirichlet sides only");
+    if (levels > 0 && m->coarse_level != 0) return fail(PMG_EUNSUP, "degree-1 levels need the coarse level 0");
     int rc;
     if ((rc = build_h_levels(m, levels))) return rc;
     m->hmg_levels = levels;
@@ -1193,7 +1195,19 @@ int pmg_set_coarse_solver(pmg_mesh* m, int kind) {
     if (kind != 0 && kind != 1) return fail(PMG_EINVAL, "coarse solver kind must be 0 (CG) or 1 (exact)");
     if (kind == 0 && m->bc != BC_ALL_DIRICHLET)
         return fail(PMG_EUNSUP, "the coarse CG is built for Dirichlet sides only; this mesh keeps the exact solve");
+    if (kind == 0 && m->coarse_level != 0) return fail(PMG_EUNSUP, "the coarse CG runs on level 0 only");
     m->coarse_kind = kind;
+    int rc;
+    if ((rc = rebuild_active(m))) return rc;
+    HIPCHK(hipDeviceSynchronize());
+    return 0;
+}
+
+int pmg_set_coarse_level(pmg_mesh* m, int level) {
+    if (check_level(m, level)) return PMG_EINVAL;
+    if (level > 0 && m->coarse_kind != 1) return fail(PMG_EUNSUP, "a coarse level above 0 needs the exact coarse solve");
+    if (level > 0 && m->hmg_levels > 0) return fail(PMG_EUNSUP, "a coarse level above 0 excludes degree-1 levels");
+    m->coarse_level = level;
     int rc;
     if ((rc = rebuild_active(m))) return rc;
     HIPCHK(hipDeviceSynchronize());

@@ -144,3 +144,64 @@ def test_fd_coarse_full_size(gpu, p):
         assert np.linalg.norm(r[mask]) <= 2e-10 * np.linalg.norm(F_hat[mask])
         assert rel(uh, matfree.recover_interior(o, f_h, uh * mask)) <= 1e-12
     g.close()
+
+
+@pytest.mark.parametrize("case,level", [(((3, 2, 3), 8, 1.0, 1.2), 1), (((2, 3, 2), 12, 0.5, 1.0), 2),
+                                        (((3, 3, 2), 16, 1.0, 1.1), 1)])
+def test_coarse_level_above_zero(gpu, case, level):
+    """Exact solve on p-level k > 0: the coarse solve of that level, the
+    V-cycle (FP64 and FP32) and whole solves against the oracle's hierarchy
+    with the same coarse level."""
+    n, p, lam, alpha = case
+    g, o = make_pair(n, p, lam, alpha)
+    g.set_coarse_solver(1)
+    g.set_coarse_level(level)
+    ioc = LevelIO(g, level)
+    oc = o.with_degree(ioc.p)
+    b = synth.random_grid(oc.shape, 61) * oc.free_skeleton_mask()
+    x = torch.full((ioc.len,), float("nan"), dtype=torch.float64, device=gpu)
+    assert g.coarse_solve(ioc.to_dev(b), x) == 0
+    assert rel(ioc.to_grid(x), coarse_fd.fd_condensed_solve(oc, b)) <= 1e-12
+    io = LevelIO(g, g.num_levels())
+    r = synth.random_grid(o.shape, 62) * o.free_skeleton_mask()
+    ref = solver.Hierarchy(o, coarse="fd", coarse_level=level).vcycle(None, r)
+    z = torch.full((io.len,), float("nan"), dtype=torch.float64, device=gpu)
+    g.vcycle(io.to_dev(r), z, pmg.F64)
+    torch.cuda.synchronize()
+    assert rel(io.to_grid(z), ref) <= 1e-11
+    z32 = torch.full((io.len,), float("nan"), dtype=torch.float32, device=gpu)
+    g.vcycle(io.to_dev(r / np.linalg.norm(r), torch.float32), z32, pmg.F32)
+    torch.cuda.synchronize()
+    assert rel(io.to_grid(z32) * np.linalg.norm(r), ref) <= 1e-4
+    f = synth.random_grid(o.shape, 63)
+    sref = solver.solve(o, f, method="kMG", rtol=1e-10, coarse="fd", coarse_level=level)
+    for dt in (pmg.F64, pmg.F32):
+        u = torch.zeros(o.shape, dtype=torch.float64, device=gpu)
+        st = g.pcg_solve(torch.as_tensor(f, device=gpu), u, 1e-10, 100, dt)
+        assert st.status == 0 and st.rel_res <= 1e-10
+        assert abs(st.iters - sref.iters) <= 1, (dt, st.iters, sref.iters)
+        assert rel(u.cpu().numpy(), sref.u) <= 1e-9
+    # back to level 0: the default cycle again
+    g.set_coarse_level(0)
+    u = torch.zeros(o.shape, dtype=torch.float64, device=gpu)
+    st = g.pcg_solve(torch.as_tensor(f, device=gpu), u, 1e-10, 100, pmg.F64)
+    assert st.status == 0
+    assert abs(st.iters - solver.solve(o, f, rtol=1e-10, coarse="fd").iters) <= 1
+    g.close()
+
+
+def test_coarse_level_refusals(gpu):
+    g, o = make_pair((3, 2, 3), 8, 1.0, 1.0)
+    g.set_coarse_solver(0)
+    with pytest.raises(pmg.PmgError) as ei:
+        g.set_coarse_level(1)                 # the coarse CG runs on level 0
+    assert ei.value.code == pmg.EUNSUP
+    g.set_coarse_solver(1)
+    g.set_coarse_level(1)
+    with pytest.raises(pmg.PmgError) as ei:
+        g.set_coarse_solver(0)
+    assert ei.value.code == pmg.EUNSUP
+    with pytest.raises(pmg.PmgError) as ei:
+        g.set_coarse_level(3)                 # levels 0..2
+    assert ei.value.code == pmg.EINVAL
+    g.close()
