@@ -2174,6 +2174,77 @@ __global__ void __launch_bounds__(64) k_fd_gemm(FdMat P, FdMat Q, double* __rest
     }
 }
 
+// The same product tiled for large passes: a workgroup of four wavefronts
+// owns a 64 x 64 block of C, each wavefront a 32 x 32 quarter (2 x 2 MFMA
+// tiles, so every operand fragment read from LDS feeds two products).  K
+// advances in slabs of 16: the 64 x 16 slab of P and the 16 x 64 slab of Q
+// are staged in LDS (rows padded by one double against bank conflicts), the
+// next slab's global loads issued before the current slab's products.
+constexpr int FDT = 64, FDK = 16;
+__global__ void __launch_bounds__(256) k_fd_gemm_tiled(FdMat P, FdMat Q, double* __restrict__ C, int64_t c_rs,
+                                                       int64_t c_cs, int64_t c_bs, int M, int N, int K,
+                                                       int tiles_n) {
+    typedef Mfma<double> MF;
+    __shared__ double As[FDT][FDK + 1];
+    __shared__ double Bs[FDK][FDT + 1];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, q = lane >> 4, j = lane & 15;
+    const int tr = blockIdx.x / tiles_n, tc = blockIdx.x - tr * tiles_n, b = blockIdx.y;
+    const int row0 = tr * FDT, col0 = tc * FDT, wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const double* pb = P.p + b * P.bs;
+    const double* qb = Q.p + b * Q.bs;
+    // this thread's four staging entries of each slab: P entry (r, k) with
+    // r = idx / 16, k = idx % 16; Q entry (k, c) with k = idx / 64, c = idx % 64
+    double pa[4], qa[4];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int idx = tid + 256 * s;
+            const int r = idx >> 4, kp = idx & 15, kq = idx >> 6, c = idx & 63;
+            const int gr = row0 + r, gkp = k0 + kp, gkq = k0 + kq, gc = col0 + c;
+            pa[s] = (gr < M && gkp < K) ? pb[(int64_t)gr * P.rs + (int64_t)gkp * P.cs] : 0.0;
+            qa[s] = (gkq < K && gc < N) ? qb[(int64_t)gkq * Q.rs + (int64_t)gc * Q.cs] : 0.0;
+        }
+    };
+    MF::v4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = MF::v4{0, 0, 0, 0};
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += FDK) {
+        __syncthreads();   // the previous slab's reads are done
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int idx = tid + 256 * s;
+            As[idx >> 4][idx & 15] = pa[s];
+            Bs[idx >> 6][idx & 63] = qa[s];
+        }
+        __syncthreads();
+        if (k0 + FDK < K) fetch(k0 + FDK);
+#pragma unroll
+        for (int kk = 0; kk < FDK; kk += 4) {
+            const double a0 = As[wr + j][kk + q], a1 = As[wr + 16 + j][kk + q];
+            const double b0 = Bs[kk + q][wc + j], b1 = Bs[kk + q][wc + 16 + j];
+            acc[0][0] = MF::mma(a0, b0, acc[0][0]);
+            acc[0][1] = MF::mma(a0, b1, acc[0][1]);
+            acc[1][0] = MF::mma(a1, b0, acc[1][0]);
+            acc[1][1] = MF::mma(a1, b1, acc[1][1]);
+        }
+    }
+    double* cc = C + b * c_bs;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int col = col0 + wc + 16 * c + j;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = row0 + wr + 16 * a + MF::row(q, v);
+                if (r < M && col < N) cc[(int64_t)r * c_rs + (int64_t)col * c_cs] = acc[a][c][v];
+            }
+        }
+}
+
 __global__ void k_fd_scale(double* __restrict__ X, const double* __restrict__ mu1, const double* __restrict__ mu2,
                            const double* __restrict__ mu3, double lam, int m1, int m2, int m3) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2237,6 +2308,14 @@ void launch_fd_solve(const Layout& L, const FdTabs& fd, double lam, const double
             P = {A, m, 1, 0};
             Q = {in, (int64_t)m1 * m2, 1, 0};
             crs = (int64_t)m1 * m2; ccs = 1; cbs = 0;
+        }
+        // 64 x 64 blocks per workgroup when there are enough of them to fill
+        // the chip; else one wavefront per 16 x 16 tile
+        const int tn64 = (Nc + FDT - 1) / FDT, tm64 = (Mr + FDT - 1) / FDT;
+        if ((int64_t)tn64 * tm64 * nb >= 256) {
+            hipLaunchKernelGGL(k_fd_gemm_tiled, dim3((unsigned)(tm64 * tn64), (unsigned)nb), dim3(256), 0, st, P, Q,
+                               out, crs, ccs, cbs, Mr, Nc, m, tn64);
+            return;
         }
         const int tn = (Nc + 15) / 16, tm = (Mr + 15) / 16;
         hipLaunchKernelGGL(k_fd_gemm, dim3((unsigned)(tm * tn), (unsigned)nb), dim3(64), 0, st, P, Q, out, crs, ccs,
