@@ -2424,12 +2424,15 @@ __device__ inline int plane_family(const Layout& L, int z, int& j) {
 }
 
 // uf += P uc on every canonical, non-Dirichlet fine node, separably (any
-// degree pair): four threads per fine column gc of one element row Er of a
-// plane form the pc + 1 column interpolations of the element's coarse rows
-// once (in LDS, split over the four), then each fine row of the element
-// (rows split over the four) takes its (pc + 1)-term row interpolation:
-// 2 (pc + 1) operations per fine node instead of (pc + 1)^2.  Element Er writes its rows 0..pf-1, the last element also
-// row pf (a boundary row interpolates to the same value from either side).
+// degree pair): the workgroup stages the coarse values its 64 fine columns
+// of element row Er need (pc + 1 coarse rows, the coarse columns of the
+// elements those columns lie in) in LDS once, four threads per fine column
+// gc form its pc + 1 column interpolations (in LDS, split over the four),
+// then each fine row of the element (rows split over the four) takes its
+// (pc + 1)-term row interpolation: 2 (pc + 1) operations per fine node
+// instead of (pc + 1)^2.  Element Er writes its rows 0..pf-1, the last
+// element also row pf (a boundary row interpolates to the same value from
+// either side).
 template <typename T, typename TC>
 __global__ void __launch_bounds__(256) k_prolong_sep(Layout Lc, Layout Lf, const T* __restrict__ J,
                                                      const TC* __restrict__ uc, T* __restrict__ uf) {
@@ -2441,14 +2444,25 @@ __global__ void __launch_bounds__(256) k_prolong_sep(Layout Lc, Layout Lf, const
     const int Er = blockIdx.y, tx = threadIdx.x, ty = threadIdx.y, gc = blockIdx.x * 64 + tx;
     if (Er >= Lf.n[dr]) return;   // uniform over the workgroup
     const bool col = gc < Lf.N[dc];
+    // the coarse block: rows Er pc .. Er pc + pc, columns cbase .. cbase +
+    // ncol - 1 (the elements of the block's first and last valid columns)
+    const int g0 = blockIdx.x * 64, g1 = min(g0 + 63, Lf.N[dc] - 1);
+    const int E0 = min(g0 / pf, Lf.n[dc] - 1), E1 = min(g1 / pf, Lf.n[dc] - 1);
+    const int cbase = E0 * pc, ncol = (E1 - E0) * pc + nc1;
+    T* cs = reinterpret_cast<T*>(smem_raw) + 64 * nc1;
+    for (int idx = ty * 64 + tx; idx < nc1 * ncol; idx += 256) {
+        const int R = idx / ncol, Cc = idx - R * ncol;
+        cs[idx] = coarse_plane_value<T>(Lc, uc, d, j, Er * pc + R, cbase + Cc, pc);
+    }
+    __syncthreads();
     // the four threads (ty) of a column share its pc + 1 column interpolations
     T* t = reinterpret_cast<T*>(smem_raw) + tx * nc1;
     const int Ec = col ? min(gc / pf, Lf.n[dc] - 1) : 0, lc = gc - Ec * pf;
     if (col)
         for (int R = ty; R < nc1; R += 4) {
+            const T* row = cs + R * ncol + (Ec * pc - cbase);
             T a = 0;
-            for (int C = 0; C < nc1; ++C)
-                a += J[lc * nc1 + C] * coarse_plane_value<T>(Lc, uc, d, j, Er * pc + R, Ec * pc + C, pc);
+            for (int C = 0; C < nc1; ++C) a += J[lc * nc1 + C] * row[C];
             t[R] = a;
         }
     __syncthreads();
@@ -4552,8 +4566,9 @@ void prolong_unfolded(const Layout& Lc, const Layout& Lf, const T* J, const TC* 
         int mr = 0;
         for (int dd = 0; dd < 3; ++dd) mr = std::max(mr, Lf.n[dd]);
         const dim3 gs((max_cols(Lf) + 63) / 64, mr, Lf.n[0] + Lf.n[1] + Lf.n[2] + 3);
-        hipLaunchKernelGGL((k_prolong_sep<T, TC>), gs, dim3(64, 4), sizeof(T) * 64 * (Lc.p + 1), st, Lc, Lf, J, uc,
-                           uf);
+        const int nc1 = Lc.p + 1, ncol_max = ((63 + Lf.p - 1) / Lf.p + 1) * Lc.p + 1;
+        hipLaunchKernelGGL((k_prolong_sep<T, TC>), gs, dim3(64, 4), sizeof(T) * nc1 * (64 + ncol_max), st, Lc, Lf, J,
+                           uc, uf);
     }
 #undef PMG_PRO
 }
