@@ -43,31 +43,36 @@ from . import sem1d
 from .mesh import Mesh
 
 
-def block_tables_1d(hs, p, e):
+def block_tables_1d(hs, p, e, bc=("D", "D")):
     """1D matrices of the block of element e on the element widths ``hs``.
 
     Elements e-1, e, e+1 are assembled on positions 0..3p and the outer ends
     0 and 3p are dropped, leaving n_S = 3p - 1 positions.  Positions inside a
     ghost element and Dirichlet boundary vertices are decoupled: S =
     identity and eigenvalue 1 there; the eigenpairs of the coupled block
-    fill the rest.  Returns (S, lam, coupled) with S^T M S = I and
+    fill the rest (Sec. 3.3: a Neumann vertex stays coupled; in a periodic
+    direction the neighbours of the end elements wrap round and nothing is
+    decoupled).  Returns (S, lam, coupled) with S^T M S = I and
     S^T L S = diag(lam) on the coupled positions.
     """
     n = len(hs)
     nS = 3 * p - 1
+    per = bc[0] == "P"
     M = np.zeros(3 * p + 1)
     L = np.zeros((3 * p + 1, 3 * p + 1))
     coupled = np.zeros(3 * p + 1, dtype=bool)
     for j, el in enumerate((e - 1, e, e + 1)):
+        if per:
+            el %= n
         if 0 <= el <= n - 1:
             m, Le = sem1d.element_matrices(p, hs[el])
             sl = slice(j * p, (j + 1) * p + 1)
             M[sl] += m
             L[sl, sl] += Le
             coupled[sl] = True
-    if e == 0:
+    if e == 0 and bc[0] == "D":
         coupled[p] = False          # the domain boundary x = 0 (Dirichlet)
-    if e == n - 1:
+    if e == n - 1 and bc[1] == "D":
         coupled[2 * p] = False      # the domain boundary x = end (Dirichlet)
     M, L, coupled = M[1:3 * p], L[1:3 * p, 1:3 * p], coupled[1:3 * p]
     S = np.eye(nS)
@@ -80,25 +85,27 @@ def block_tables_1d(hs, p, e):
     return S, lam, coupled
 
 
-def _phi(n, p, x_ref, eb, g, pw):
+def _phi(n, p, x_ref, eb, g, pw, periodic=False):
     """Unnormalised distance weight of the block of element eb at global
     position g (valid only where the block covers g)."""
     m, j = divmod(g, p)                     # g lies in element m at local node j
     if m >= n:                              # the last grid point: t = 1 of element n-1
         m, j = n - 1, p
     t = (x_ref[j] + 1.0) / 2.0
-    if m == eb:
+    rel = (m - eb) % n if periodic else m - eb
+    if rel == 0:
         return 0.5
-    if m == eb - 1:                         # the block's left element
+    if rel == -1 or (periodic and rel == n - 1):   # the block's left element
         return 0.5 * float(sem1d.weight_poly(t, pw))
-    if m == eb + 1:                         # the block's right element
+    if rel == 1:                            # the block's right element
         return 0.5 * float(sem1d.weight_poly(1.0 - t, pw))
     return 0.0
 
 
-def block_weights_1d(n, p, e, weights="smooth", pw=7):
+def block_weights_1d(n, p, e, weights="smooth", pw=7, periodic=False):
     """1D weights of the block of element e at its n_S positions (global
-    node index g = (e-1) p + 1 + o for position o), on n elements.
+    node index g = (e-1) p + 1 + o for position o, modulo n p in a periodic
+    direction), on n elements.
 
     Summed over all blocks of the mesh that cover a node they give one.
     """
@@ -107,9 +114,13 @@ def block_weights_1d(n, p, e, weights="smooth", pw=7):
     w = np.zeros(nS)
     for o in range(nS):
         g = (e - 1) * p + 1 + o
-        if g < 0 or g > n * p:
-            continue
-        cover = [b for b in range(n) if (b - 1) * p < g < (b + 2) * p]
+        if periodic:
+            g %= n * p
+            cover = [b for b in range(n) if 0 < (g - (b - 1) * p) % (n * p) < 3 * p]
+        else:
+            if g < 0 or g > n * p:
+                continue
+            cover = [b for b in range(n) if (b - 1) * p < g < (b + 2) * p]
         if e not in cover:
             continue
         if weights == "mult":
@@ -117,8 +128,8 @@ def block_weights_1d(n, p, e, weights="smooth", pw=7):
         else:
             # at an element boundary the node is t = 1 of the left element
             # and t = 0 of the right one; the weight functions are continuous
-            tot = sum(_phi(n, p, x_ref, b, g, pw) for b in cover)
-            w[o] = _phi(n, p, x_ref, e, g, pw) / tot
+            tot = sum(_phi(n, p, x_ref, b, g, pw, periodic) for b in cover)
+            w[o] = _phi(n, p, x_ref, e, g, pw, periodic) / tot
     return w
 
 
@@ -213,8 +224,6 @@ class _Blocks:
     """Block index maps and gathered 1D tables for a mesh."""
 
     def __init__(self, mesh: Mesh, weights="smooth"):
-        if not mesh.all_dirichlet():
-            raise NotImplementedError("element-centred blocks: Dirichlet boundaries only")
         p = mesh.p
         nS = 3 * p - 1
         n1, n2, n3 = mesh.n
@@ -224,10 +233,10 @@ class _Blocks:
         for d in range(3):
             Ss, ls, ws = [], [], []
             for e in range(mesh.n[d]):
-                S, lam, _ = block_tables_1d(mesh.h[d], p, e)
+                S, lam, _ = block_tables_1d(mesh.h[d], p, e, mesh.bc[d])
                 Ss.append(S)
                 ls.append(lam)
-                ws.append(block_weights_1d(mesh.n[d], p, e, weights))
+                ws.append(block_weights_1d(mesh.n[d], p, e, weights, periodic=mesh.periodic[d]))
             tabs.append((np.array(Ss), np.array(ls), np.array(ws)))
         e3, e2, e1 = np.meshgrid(np.arange(n3), np.arange(n2), np.arange(n1), indexing="ij")
         e1, e2, e3 = e1.ravel(), e2.ravel(), e3.ravel()
@@ -238,6 +247,7 @@ class _Blocks:
         self.sentinel = sentinel
 
         def flat(i1, i2, i3):
+            i1, i2, i3 = mesh.wrap(0, i1), mesh.wrap(1, i2), mesh.wrap(2, i3)
             ok = (i1 >= 0) & (i1 < N1) & (i2 >= 0) & (i2 < N2) & (i3 >= 0) & (i3 < N3)
             return np.where(ok, (i3 * N2 + i2) * N1 + i1, sentinel)
 

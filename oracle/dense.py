@@ -177,14 +177,19 @@ def block_nodes(cs: CondensedSystem, e):
     """
     m = cs.mesh
     p = m.p
-    if not m.all_dirichlet():
-        raise NotImplementedError("element-centred blocks: Dirichlet boundaries only")
     lo = [(e[d] - 1) * p for d in range(3)]
+    rng = []
+    for d in range(3):          # positions along d: the open block, across a periodic seam
+        if m.periodic[d]:
+            rng.append(range(lo[d] + 1, lo[d] + 3 * p))
+        else:
+            rng.append(range(max(lo[d] + 1, 0), min(lo[d] + 3 * p, m.N[d])))
     out, offs = [], []
-    for i3 in range(max(lo[2] + 1, 0), min(lo[2] + 3 * p, m.N[2])):
-        for i2 in range(max(lo[1] + 1, 0), min(lo[1] + 3 * p, m.N[1])):
-            for i1 in range(max(lo[0] + 1, 0), min(lo[0] + 3 * p, m.N[0])):
-                g = (i3 * m.N[1] + i2) * m.N[0] + i1
+    for i3 in rng[2]:
+        for i2 in rng[1]:
+            for i1 in rng[0]:
+                j1, j2, j3 = int(m.wrap(0, i1)), int(m.wrap(1, i2)), int(m.wrap(2, i3))
+                g = (j3 * m.N[1] + j2) * m.N[0] + j1
                 if g in cs.pos:
                     out.append(g)
                     offs.append((i1 - lo[0] - 1, i2 - lo[1] - 1, i3 - lo[2] - 1))
@@ -211,7 +216,7 @@ def block_smoother_matrix(cs: CondensedSystem, omega=1.0, weights="smooth", unit
                 if unit_weights:
                     W = np.ones(len(k))
                 else:
-                    w = [block_weights_1d(m.n[d], p, e[d], weights) for d in range(3)]
+                    w = [block_weights_1d(m.n[d], p, e[d], weights, periodic=m.periodic[d]) for d in range(3)]
                     W = w[0][offs[:, 0]] * w[1][offs[:, 1]] * w[2][offs[:, 2]]
                 Smat[np.ix_(k, k)] += W[:, None] * Hi_inv
     return omega * Smat

@@ -265,5 +265,44 @@ def test_unsupported_combinations_raise():
     m = M.Mesh.box((4, 4, 4), 4, 1.0, bc=("P", "N", "D"))
     with pytest.raises(NotImplementedError):
         solver.Hierarchy(m, hmg_levels=1)
-    with pytest.raises(NotImplementedError):
-        dense.block_nodes(dense.CondensedSystem(M.Mesh.box((3, 2, 2), 2, 1.0, bc=("P", "N", "D"))), (0, 0, 0))
+
+
+@pytest.mark.parametrize("case", [c for c in TINY if c[1] >= 2], ids=_ids)
+@pytest.mark.parametrize("route", ["tpc", "tpf"])
+def test_block_smoother_matches_dense(systems, case, route):
+    """The element-centred blocks of Sec. 3.4 with the boundary treatment of
+    Sec. 3.3 (ghost elements and Dirichlet vertices identity-padded, a
+    periodic block continuing across the seam) equal the weighted inverses
+    of the principal submatrices of Hhat on the block nodes."""
+    from oracle import blocks
+    m, cs = systems(case)
+    S = dense.block_smoother_matrix(cs, omega=0.9)
+    r = synth.random_grid(m.shape, 13) * m.free_skeleton_mask()
+    ref = cs.to_grid(S @ cs.to_vec(r))
+    assert rel(blocks.block_smoother(m, r, omega=0.9, route=route), ref) < 1e-11
+
+
+@pytest.mark.parametrize("case", [c for c in TINY if c[1] >= 2], ids=_ids)
+def test_block_weights_partition_of_unity(systems, case):
+    m, cs = systems(case)
+    from oracle.blocks import block_weights_1d
+    tot = np.zeros(len(cs.B))
+    for e3 in range(m.n[2]):
+        for e2 in range(m.n[1]):
+            for e1 in range(m.n[0]):
+                g, offs = dense.block_nodes(cs, (e1, e2, e3))
+                k = np.array([cs.pos[x] for x in g], dtype=np.int64)
+                w = [block_weights_1d(m.n[d], m.p, (e1, e2, e3)[d], periodic=m.periodic[d]) for d in range(3)]
+                tot[k] += w[0][offs[:, 0]] * w[1][offs[:, 1]] * w[2][offs[:, 2]]
+    assert np.allclose(tot, 1.0, atol=1e-13)
+
+
+def test_block_smoother_solve_with_seams():
+    """ipCG with the element-centred smoother on a mesh with every kind of
+    side reaches the manufactured solution's discrete solution."""
+    m = M.Mesh.box((3, 3, 3), 6, 1.0, 1.2, bc=("P", ("N", "D"), "N"))
+    f = synth.random_grid(m.shape, 14)
+    a = solver.solve(m, f, rtol=1e-11, coarse="fd", smoother="element")
+    b = solver.solve(m, f, rtol=1e-11, coarse="fd")
+    assert rel(a.u, b.u) < 1e-9
+    assert a.iters <= b.iters
