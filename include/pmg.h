@@ -93,9 +93,10 @@ int pmg_create_mesh_widths(int n1, int n2, int n3, int p, double lambda,
  * direction the ghost element is the last element.  Without a Dirichlet
  * side lambda must be > 0 (else the operator is singular): PMG_EINVAL.
  * Such a mesh always uses the exact coarse solve; pmg_set_coarse_solver(0),
- * pmg_set_coarse_mg with levels > 0, pmg_set_smoother(1) and the lifting
- * calls (pmg_lift_dirichlet, pmg_set_boundary, pmg_pcg_solve_dirichlet)
- * return PMG_EUNSUP on it unless every side is Dirichlet. */
+ * pmg_set_coarse_mg with levels > 0 and the lifting calls
+ * (pmg_lift_dirichlet, pmg_set_boundary, pmg_pcg_solve_dirichlet) return
+ * PMG_EUNSUP on it unless every side is Dirichlet.  The element-centred
+ * blocks (pmg_set_smoother(1)) take the same boundary treatment. */
 int pmg_create_mesh_bc(int n1, int n2, int n3, int p, double lambda,
                        const double *h_hx, const double *h_hy,
                        const double *h_hz, const int *h_bc, pmg_mesh **out);

@@ -645,7 +645,8 @@ int setup_blocks(pmg_mesh* m, Level& L) {
     int rc;
     for (int d = 0; d < 3; ++d) {
         std::vector<double> S, lam, w;
-        build_block_tables(p, L.h[d], np, S, lam, w);
+        const int bcd = (L.lay.dlo(d) ? 1 : 0) | (L.lay.dhi(d) ? 2 : 0) | (L.lay.per(d) ? 4 : 0);
+        build_block_tables(p, L.h[d], np, bcd, S, lam, w);
         if ((rc = m->upload(&L.t64.bl_S[d], S)) || (rc = m->upload(&L.t32.bl_S[d], S)) ||
             (rc = m->upload(&L.t64.bl_lam[d], lam)) || (rc = m->upload(&L.t32.bl_lam[d], lam)) ||
             (rc = m->upload(&L.t64.bl_w[d], w)) || (rc = m->upload(&L.t32.bl_w[d], w)))
@@ -1217,8 +1218,6 @@ int pmg_set_coarse_level(pmg_mesh* m, int level) {
 int pmg_set_smoother(pmg_mesh* m, int kind) {
     if (check_mesh(m)) return PMG_EINVAL;
     if (kind != 0 && kind != 1) return fail(PMG_EINVAL, "smoother kind must be 0 (star) or 1 (element-centred)");
-    if (kind == 1 && m->bc != BC_ALL_DIRICHLET)
-        return fail(PMG_EUNSUP, "the element-centred smoother is built for Dirichlet sides only");
     int rc;
     if (kind == 1)
         for (auto& L : m->lv)

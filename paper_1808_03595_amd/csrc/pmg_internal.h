@@ -194,7 +194,7 @@ void build_level_tables(int p, int pc, const std::vector<double> h[3], HostTable
 // bc_d: bit 0 Dirichlet low end, bit 1 Dirichlet high end, bit 2 periodic
 void build_fd_tables(int p, const std::vector<double>& h, int bc_d, std::vector<double>& Af,
                      std::vector<double>& Ab, std::vector<double>& mu, int& first);
-void build_block_tables(int p, const std::vector<double>& h, int np, std::vector<double>& S,
+void build_block_tables(int p, const std::vector<double>& h, int np, int bc_d, std::vector<double>& S,
                         std::vector<double>& lam, std::vector<double>& w);
 void coarse_diagonal(const Layout& lay, double lam, const std::vector<double> h[3],
                      std::vector<double>& diag);

@@ -1986,17 +1986,23 @@ __global__ void __launch_bounds__(64) k_blk_gemm(LevelTabs<T> tb, const T* __res
     const int row0 = tr * 16, col0 = tc * 16;
     const int gR = (e[dR] - 1) * p + 1, gC = (e[dC] - 1) * p + 1;   // global index of position 0
     const int NR = L.N[dR], NC = L.N[dC];
-    const int64_t pbase = d == 0 ? L.plane0(e[0] + sf) : (d == 1 ? L.plane1(e[1] + sf) : L.plane2(e[2] + sf));
+    // the block's face plane (in a periodic direction the last plane is plane 0)
+    const int jp = L.per(d) && e[d] + sf == L.n[d] ? 0 : e[d] + sf;
+    const int64_t pbase = d == 0 ? L.plane0(jp) : (d == 1 ? L.plane1(jp) : L.plane2(jp));
     const int pitch = L.pitch[d];
     int64_t wbase = 0;
     bool rowok = false;
     int lo = 0, hi = 0;   // admissible column positions: global column index inside the grid
     if (MODE == SG_FWD1) {
-        const int a = row0 + j, ir = gR + a;
+        const int a = row0 + j, ir = wrap_idx(L, dR, gR + a);
         rowok = a < nS && ir >= 0 && ir < NR;
-        wbase = pbase + (int64_t)ir * pitch + gC;   // + k gives the slot of column position k
+        wbase = pbase + (int64_t)ir * pitch;   // + the column index of position k
         lo = -gC;
         hi = NC - 1 - gC;
+        if (L.per(dC)) {                       // the window continues across the seam
+            lo = 0;
+            hi = nS - 1;
+        }
     }
     const T* Xm = X + mo;
     typename M::v4 acc = {0, 0, 0, 0};
@@ -2004,7 +2010,7 @@ __global__ void __launch_bounds__(64) k_blk_gemm(LevelTabs<T> tb, const T* __res
         const int k = k0 + q;
         T a, bb;
         if (MODE == SG_FWD1) {
-            a = (rowok && k < nS && k >= lo && k <= hi) ? r[wbase + k] : (T)0;
+            a = (rowok && k < nS && k >= lo && k <= hi) ? r[wbase + wrap_idx(L, dC, gC + k)] : (T)0;
             bb = SC[k * np + col0 + j];
         } else if (MODE == SG_FWD2) {
             a = SR[k * np + row0 + j];
@@ -2038,10 +2044,10 @@ __global__ void __launch_bounds__(64) k_blk_gemm(LevelTabs<T> tb, const T* __res
         // the owning copy: family 1 skips x1-planes (columns); family 2 skips
         // x1-planes (columns) and x2-planes (rows)
         if ((d >= 1 && col_line) || (d == 2 && row_line)) continue;
-        const int ir = gR + a, ic = gC + bc;
+        const int ir = wrap_idx(L, dR, gR + a), ic = wrap_idx(L, dC, gC + bc);
         if (ir < 0 || ir >= NR || ic < 0 || ic >= NC) continue;
         int i[3];
-        i[d] = (e[d] + sf) * p;
+        i[d] = jp * p;
         i[dR] = ir;
         i[dC] = ic;
         if (is_dir(L, i[0], i[1], i[2])) continue;

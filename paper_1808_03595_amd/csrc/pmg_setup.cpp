@@ -222,8 +222,10 @@ double smoothstep(int pw, double t) {
 // the sum over all blocks of the mesh that cover it, so the weights of the
 // covering blocks add up to one.  Outputs padded to np per block: S [e][i][k]
 // (np x np), lam [e][np], w [e][np] (zero on padding and ghost positions).
-void build_block_tables(int p, const std::vector<double>& h, int np, std::vector<double>& Sout,
+void build_block_tables(int p, const std::vector<double>& h, int np, int bc_d, std::vector<double>& Sout,
                         std::vector<double>& lamout, std::vector<double>& wout) {
+    // bc_d: bit 0 Dirichlet low end, bit 1 Dirichlet high end, bit 2 periodic
+    const bool per = (bc_d >> 2) & 1, dl = !per && (bc_d & 1), dh = !per && ((bc_d >> 1) & 1);
     std::vector<double> x, w, Ls;
     gll_nodes_weights(p, x, w);
     stiffness_std(p, x, w, Ls);
@@ -231,21 +233,24 @@ void build_block_tables(int p, const std::vector<double>& h, int np, std::vector
     Sout.assign((size_t)nb * np * np, 0.0);
     lamout.assign((size_t)nb * np, 1.0);
     wout.assign((size_t)nb * np, 0.0);
-    // distance function of block b at global position g it covers
+    // distance function of block b at global position g it covers (in a
+    // periodic direction g in 0..nb p - 1 and the neighbours wrap round)
     auto phi = [&](int b, int g) -> double {
         int m = g / p, j = g - m * p;
         if (m >= nb) { m = nb - 1; j = p; }
         const double t = 0.5 * (x[j] + 1.0);
-        if (m == b) return 0.5;
-        if (m == b - 1) return 0.5 * smoothstep(7, t);
-        if (m == b + 1) return 0.5 * smoothstep(7, 1.0 - t);
+        const int rel = per ? ((m - b) % nb + nb) % nb : m - b;
+        if (rel == 0) return 0.5;
+        if (rel == -1 || (per && rel == nb - 1)) return 0.5 * smoothstep(7, t);
+        if (rel == 1) return 0.5 * smoothstep(7, 1.0 - t);
         return 0.0;
     };
     for (int e = 0; e < nb; ++e) {
         std::vector<double> M(W, 0.0), L((size_t)W * W, 0.0);
         std::vector<char> cpl(W, 0);
         for (int j = 0; j < 3; ++j) {
-            const int el = e - 1 + j;
+            int el = e - 1 + j;
+            if (per) el = (el + nb) % nb;
             if (el < 0 || el >= nb) continue;
             const double he = h[el];
             for (int a = 0; a < n1; ++a) {
@@ -254,8 +259,8 @@ void build_block_tables(int p, const std::vector<double>& h, int np, std::vector
                 for (int b = 0; b < n1; ++b) L[(size_t)(j * p + a) * W + j * p + b] += (2.0 / he) * Ls[a * n1 + b];
             }
         }
-        if (e == 0) cpl[p] = 0;            // domain boundary at the block's left face
-        if (e == nb - 1) cpl[2 * p] = 0;   // domain boundary at the block's right face
+        if (e == 0 && dl) cpl[p] = 0;            // Dirichlet boundary at the block's left face
+        if (e == nb - 1 && dh) cpl[2 * p] = 0;   // Dirichlet boundary at the block's right face
         std::vector<int> c;
         for (int i = 1; i < 3 * p; ++i)
             if (cpl[i]) c.push_back(i);
@@ -276,11 +281,20 @@ void build_block_tables(int p, const std::vector<double>& h, int np, std::vector
             }
         }
         for (int o = 0; o < nS; ++o) {
-            const int g = (e - 1) * p + 1 + o;
-            if (g < 0 || g > nb * p) continue;
+            int g = (e - 1) * p + 1 + o;
             double tot = 0.0;
-            for (int b = std::max(0, g / p - 2); b <= std::min(nb - 1, g / p + 1); ++b)
-                if ((b - 1) * p < g && g < (b + 2) * p) tot += phi(b, g);
+            if (per) {
+                const int P = nb * p;
+                g = (g % P + P) % P;
+                for (int b = 0; b < nb; ++b) {
+                    const int rel = ((g - (b - 1) * p) % P + P) % P;
+                    if (rel > 0 && rel < 3 * p) tot += phi(b, g);
+                }
+            } else {
+                if (g < 0 || g > nb * p) continue;
+                for (int b = std::max(0, g / p - 2); b <= std::min(nb - 1, g / p + 1); ++b)
+                    if ((b - 1) * p < g && g < (b + 2) * p) tot += phi(b, g);
+            }
             wout[(size_t)e * np + o] = tot > 0.0 ? phi(e, g) / tot : 0.0;
         }
     }

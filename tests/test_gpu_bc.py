@@ -191,6 +191,35 @@ def test_pcg_solve_with_seams(gpu, case):
     g.close()
 
 
+@pytest.mark.parametrize("case", [c for c in CASES if 2 <= c[1] <= 16], ids=_ids)
+def test_block_smoother_with_seams(gpu, case):
+    """Element-centred blocks (Sec. 3.4) on every level of degree >= 2 with
+    Neumann and periodic sides, FP64 and FP32, and a whole solve with them."""
+    from oracle import blocks
+    g, o = _pair(case)
+    g.set_smoother(1)
+    for level in range(g.num_levels() + 1):
+        io = LevelIO(g, level, o.bc)
+        if io.p < 2:
+            continue
+        ol = o.with_degree(io.p)
+        r = synth.random_grid(ol.shape, 71 + level) * ol.free_skeleton_mask()
+        ref = blocks.block_smoother(ol, r, 0.8)
+        for dt, tdt, tol in ((pmg.F64, torch.float64, TOL64), (pmg.F32, torch.float32, TOL32)):
+            z = torch.full((io.len,), float("nan"), dtype=tdt, device=gpu)
+            g.schwarz_smooth(level, io.to_dev(r, tdt), z, 0.8, dt)
+            torch.cuda.synchronize()
+            assert rel(io.to_grid(z), ref) <= tol, (level, dt)
+            assert float(z.double().abs().sum()) == pytest.approx(float(np.abs(io.to_grid(z)).sum()), rel=1e-12)
+    f = synth.random_grid(o.shape, 75)
+    sref = solver.solve(o, f, rtol=1e-10, coarse="fd", smoother="element")
+    u = torch.zeros(o.shape, dtype=torch.float64, device=gpu)
+    st = g.pcg_solve(torch.as_tensor(f, device=gpu), u, 1e-10, 100, pmg.F64)
+    assert st.status == 0 and abs(st.iters - sref.iters) <= 1
+    assert rel(u.cpu().numpy(), sref.u) <= 1e-9
+    g.close()
+
+
 @pytest.mark.parametrize("kinds", [(("N", "N"), ("D", "N")), (("N", "D"), "P")])
 def test_manufactured_solution(gpu, kinds):
     """sin(x1 + 0.3) periodic on (0, 2 pi) times factors meeting the other
@@ -218,7 +247,7 @@ def test_manufactured_solution(gpu, kinds):
 
 def test_unsupported_calls_on_bc_meshes(gpu):
     g, o = make_pair((3, 3, 3), 4, 1.0, bc=("P", "N", "D"))
-    for call in (lambda: g.set_coarse_solver(0), lambda: g.set_smoother(1), lambda: g.set_coarse_mg(1)):
+    for call in (lambda: g.set_coarse_solver(0), lambda: g.set_coarse_mg(1)):
         with pytest.raises(pmg.PmgError) as ei:
             call()
         assert ei.value.code == pmg.EUNSUP
