@@ -35,7 +35,7 @@ static int fail(int code, const std::string& msg) {
 namespace {
 
 // scalar slots in device memory
-enum { SC_GAMMA = 0, SC_GAMMA0 = 1, SC_DELTA = 2, SC_QP = 3, SC_RR = 4, SC_RZ = 5, SC_PQ = 6, SC_RZN = 7,
+enum { SC_GAMMA = 0, SC_GAMMA0 = 1, SC_DELTA = 2, SC_QP = 3, SC_RR = 4, SC_RZ = 5, SC_PQ = 6, SC_RZN = 7, SC_ZS = 8,
        SC_N = 16 };
 
 struct Level {
@@ -1324,6 +1324,10 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
     const double eps = rtol * stats.res0;
     int it = 0;
     if (!std::isfinite(rr0)) status = PMG_BREAKDOWN;  // NaN or Inf in the condensed right-hand side
+    // FP32 preconditioner: the first cycle's input r / |r| (each later one is
+    // written by the update that produces its residual)
+    if (mode == 0 && pdt == PMG_F32 && !status)
+        launch_cast_down(m->w_r, m->w_r32, m->scal + SC_RR, m->scal + SC_ZS, n, st);
     while (!status && std::sqrt(rr) > eps && it < maxit) {
         if (mode == 1) {
             // Alg. 4: u <- MultigridCycle(u, F); r = F - H u
@@ -1351,12 +1355,8 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
             if (!m->solver_graphs[gi]) {
                 auto part_a = [&](hipStream_t s) -> int {
                     int r2;
-                    if (pdt == PMG_F64) {
-                        r2 = vc_down<double>(m, m->w_r, m->w_z, false, s);
-                    } else {
-                        launch_cast_scale<double, float>(m->w_r, m->w_r32, m->scal + SC_RR, 2, n, s);
-                        r2 = vc_down<float>(m, m->w_r32, m->w_z32, false, s);
-                    }
+                    if (pdt == PMG_F64) r2 = vc_down<double>(m, m->w_r, m->w_z, false, s);
+                    else r2 = vc_down<float>(m, m->w_r32, m->w_z32, false, s);
                     if (r2) return r2;
                     if (m->coarse_kind == 1) {   // the exact coarse solve, inside the graph
                         Level& L0 = *m->act[0];
@@ -1371,14 +1371,23 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
                     int r2 = pdt == PMG_F64 ? vc_up<double>(m, m->w_r, m->w_z, s)
                                             : vc_up<float>(m, m->w_r32, m->w_z32, s);
                     if (r2) return r2;
-                    if (pdt != PMG_F64)
-                        launch_cast_scale<float, double>(m->w_z32, m->w_z, m->scal + SC_RR, 3, n, s);
-                    launch_dot2<double>(m->w_z, m->w_r, m->w_s, n, m->partials, m->counter, m->scal + SC_GAMMA, s);
-                    launch_pcg_dir(m->w_p, m->w_z, m->scal, n, s);
+                    // gamma = z . r, gamma0 = z . s, p = beta p + z, q = H p,
+                    // q . p, the update (FP32: z = zs z32 taken on the fly, and
+                    // the update writes the next cycle's r32)
+                    if (pdt == PMG_F64) {
+                        launch_dot2<double>(m->w_z, m->w_r, m->w_s, n, m->partials, m->counter, m->scal + SC_GAMMA,
+                                            s);
+                        launch_pcg_dir(m->w_p, m->w_z, m->scal, n, s);
+                    } else {
+                        launch_dot_zmix(m->w_z32, m->scal + SC_ZS, m->w_r, m->w_s, n, m->partials, m->counter,
+                                        m->scal + SC_GAMMA, s);
+                        launch_pcg_dir_mixed(m->w_p, m->w_z32, m->scal + SC_ZS, m->scal, n, s);
+                    }
                     launch_condensed_op<double>(m->lv.back().t64, m->w_p, m->w_q, s);
                     launch_dot2<double>(m->w_q, m->w_p, nullptr, n, m->partials, m->counter, m->scal + SC_QP, s);
                     launch_pcg_update(m->w_u, m->w_r, m->w_s, m->w_p, m->w_q, m->scal + SC_GAMMA, m->scal + SC_QP,
-                                      n, m->partials, m->counter, m->scal + SC_RR, m->scal + SC_DELTA, s);
+                                      n, m->partials, m->counter, m->scal + SC_RR, m->scal + SC_DELTA, s,
+                                      pdt == PMG_F64 ? nullptr : m->w_r32, m->scal + SC_ZS);
                     launch_publish(m->scal, SC_N, m->d_pubcnt, m->dmail, s);
                     return 0;
                 };

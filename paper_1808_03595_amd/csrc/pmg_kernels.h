@@ -5,7 +5,7 @@
 
 namespace pmg {
 
-constexpr int REDUCE_BLOCKS = 128;   // workgroups of the reduction kernels
+constexpr int REDUCE_BLOCKS = 512;   // workgroups of the reduction kernels (two per CU)
 constexpr int REDUCE_THREADS = 1024;
 
 hipError_t init_kernel_attributes();
@@ -67,7 +67,14 @@ void launch_set_boundary(const int N[3], const double* g, double* u, hipStream_t
 void launch_pcg_dir(double* p, const double* z, const double* sc, int64_t n, hipStream_t);
 void launch_pcg_update(double* u, double* r, double* s, const double* p, const double* q, const double* gam,
                        const double* qp, int64_t n, double* partials, unsigned* counter, double* out,
-                       double* delta_out, hipStream_t st);
+                       double* delta_out, hipStream_t st, float* r32 = nullptr, double* sc_zs = nullptr);
+// FP32 preconditioner: r32 = r / sqrt(r.r) and the scale; gamma, gamma0 and
+// the direction update from the FP32 result scaled back on the fly
+void launch_cast_down(const double* r, float* r32, const double* sc_rr, double* sc_zs, int64_t n, hipStream_t st);
+void launch_dot_zmix(const float* z32, const double* sc_zs, const double* r, const double* s, int64_t n,
+                     double* partials, unsigned* counter, double* out, hipStream_t st);
+void launch_pcg_dir_mixed(double* p, const float* z32, const double* sc_zs, const double* sc, int64_t n,
+                          hipStream_t st);
 template <typename T> void launch_fill_zero(T* x, int64_t n, hipStream_t st);
 void launch_jacobi(const double* r, const double* dg, double* z, int64_t n, double* partials,
                    unsigned* counter, double* out, hipStream_t);

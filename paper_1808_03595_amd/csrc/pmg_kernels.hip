@@ -3035,7 +3035,11 @@ struct CRShape {
     __host__ __device__ static constexpr int o_SS(int d) { return o_STS + d * 2 * q2 + q2; }
     // LDS: tables | ST/SS | a[q3] | b[q3] | G[6 q2] | tmp[6 q2] | tile[6 t2] (recovery)
     static constexpr int o_a = o_STS + sts, o_b = o_a + q3, o_G = o_b + q3, o_tmp = o_G + 6 * q2,
-                         o_tile = o_tmp + 6 * q2, cond_total = o_tile, rec_total = o_tile + 6 * t2;
+                         o_tile = o_tmp + 6 * q2, cond_total = o_tile;
+    // recovery: tmp shares b's region (b is free between the two interior
+    // transforms) and G the tile's (the tile is dead once tmp is formed):
+    // tables | ST/SS | a[q3] | b/tmp | tile/G
+    static constexpr int rb = q3 > 6 * q2 ? q3 : 6 * q2, o_rtile = o_b + rb, rec_total = o_rtile + 6 * t2;
 };
 
 // The packed tables of element e into LDS (CRShape layout), then the interior
@@ -3264,9 +3268,9 @@ __global__ void __launch_bounds__(64) k_recover_w(LevelTabs<double> tb, const do
     double* tabs = sm;
     double* a = sm + K::o_a;
     double* b = sm + K::o_b;
-    double* G = sm + K::o_G;
-    double* tmp = sm + K::o_tmp;
-    double* tile = sm + K::o_tile;
+    double* tmp = b;                    // after the forward transform
+    double* tile = sm + K::o_rtile;
+    double* G = tile;                   // after tmp is formed from the tile
     const Layout& L = tb.lay;
     const int lane = threadIdx.x;
     const int eid = xcd_remap(blockIdx.x, gridDim.x);
@@ -3508,7 +3512,7 @@ __device__ inline void finish_reduce(double* partials, const double* mine, int n
     if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// out[0] = x . y ; out[1] = x . z (if z non-null)
+// out[0] = x . y ; out[1] = x . z (if z non-null; out[1] is left alone otherwise)
 template <typename T>
 __global__ void __launch_bounds__(REDUCE_THREADS) k_dot2(const T* __restrict__ x, const T* __restrict__ y,
                                               const T* __restrict__ z, int64_t n, double* partials,
@@ -3524,7 +3528,7 @@ __global__ void __launch_bounds__(REDUCE_THREADS) k_dot2(const T* __restrict__ x
     mine[0] = block_sum(s0, red);
     __syncthreads();
     mine[1] = block_sum(s1, red);
-    finish_reduce(partials, mine, 2, counter, out);
+    finish_reduce(partials, mine, z ? 2 : 1, counter, out);
 }
 
 // ipCG direction update (Alg. 5): beta = (gamma - gamma0) / delta,
@@ -3549,16 +3553,26 @@ __global__ void k_pcg_dir(double* __restrict__ p, const double* __restrict__ z, 
     p[i] = beta * p[i] + z[i];
 }
 
-// alpha = gamma / (q . p); s = r; u += alpha p; r -= alpha q; partial r.r
+// alpha = gamma / (q . p); s = r; u += alpha p; r -= alpha q; partial r.r.
+// With r32 (FP32 preconditioner): also r32 = r / zs for the next cycle, zs
+// = |r| before this update (out[0] = r.r still holds it when the blocks
+// start: the last block writes the new value only after every block has
+// arrived), and *sc_zs = zs for the way back (the cycle is linear, so any
+// scale that keeps FP32 in range serves).
 __global__ void __launch_bounds__(REDUCE_THREADS) k_pcg_update(double* __restrict__ u, double* __restrict__ r,
                                                     double* __restrict__ s, const double* __restrict__ p,
                                                     const double* __restrict__ q, const double* sc_gamma,
                                                     const double* sc_qp, int64_t n, double* partials,
-                                                    unsigned* counter, double* out, double* delta_out) {
+                                                    unsigned* counter, double* out, double* delta_out,
+                                                    float* __restrict__ r32, double* sc_zs) {
     __shared__ double red[16];
     const double alpha = sc_gamma[0] / sc_qp[0];
+    const double zs = r32 ? sqrt(out[0]) : 1.0, izs = 1.0 / zs;
     // delta <- gamma for the next direction update (Alg. 5)
-    if (delta_out && blockIdx.x == 0 && threadIdx.x == 0) *delta_out = sc_gamma[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (delta_out) *delta_out = sc_gamma[0];
+        if (r32) *sc_zs = zs;
+    }
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double ri = r[i];
@@ -3566,11 +3580,50 @@ __global__ void __launch_bounds__(REDUCE_THREADS) k_pcg_update(double* __restric
         u[i] += alpha * p[i];
         ri -= alpha * q[i];
         r[i] = ri;
+        if (r32) r32[i] = (float)(ri * izs);
         acc += ri * ri;
     }
     double mine[1];
     mine[0] = block_sum(acc, red);
     finish_reduce(partials, mine, 1, counter, out);
+}
+
+// FP32 preconditioner start: r32 = r / zs, zs = sqrt(r.r); *sc_zs = zs.
+__global__ void k_cast_down(const double* __restrict__ r, float* __restrict__ r32, const double* sc_rr,
+                            double* sc_zs, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double zs = sqrt(sc_rr[0]);
+    if (i == 0) *sc_zs = zs;
+    if (i < n) r32[i] = (float)(r[i] / zs);
+}
+
+// gamma = z . r and gamma0 = z . s with z = zs z32 (the FP32 cycle's result
+// scaled back), without forming z.
+__global__ void __launch_bounds__(REDUCE_THREADS) k_dot_zmix(const float* __restrict__ z32, const double* sc_zs,
+                                                  const double* __restrict__ r, const double* __restrict__ s,
+                                                  int64_t n, double* partials, unsigned* counter, double* out) {
+    __shared__ double red[16];
+    const double zs = sc_zs[0];
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double zv = zs * (double)z32[i];
+        s0 += zv * r[i];
+        s1 += zv * s[i];
+    }
+    double mine[2];
+    mine[0] = block_sum(s0, red);
+    __syncthreads();
+    mine[1] = block_sum(s1, red);
+    finish_reduce(partials, mine, 2, counter, out);
+}
+
+// p = beta p + zs z32 (the direction update of Alg. 5 with the FP32 result)
+__global__ void k_pcg_dir_mixed(double* __restrict__ p, const float* __restrict__ z32, const double* sc_zs,
+                                const double* sc, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double beta = (sc[0] - sc[1]) / sc[2];
+    p[i] = beta * p[i] + sc_zs[0] * (double)z32[i];
 }
 
 // Jacobi-PCG pieces for the coarse solve (FP64).
@@ -4821,9 +4874,24 @@ void launch_pcg_dir(double* p, const double* z, const double* sc, int64_t n, hip
 
 void launch_pcg_update(double* u, double* r, double* s, const double* p, const double* q, const double* gam,
                        const double* qp, int64_t n, double* partials, unsigned* counter, double* out,
-                       double* delta_out, hipStream_t st) {
+                       double* delta_out, hipStream_t st, float* r32, double* sc_zs) {
     hipLaunchKernelGGL(k_pcg_update, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, st, u, r, s, p, q, gam, qp, n, partials,
-                       counter, out, delta_out);
+                       counter, out, delta_out, r32, sc_zs);
+}
+
+void launch_cast_down(const double* r, float* r32, const double* sc_rr, double* sc_zs, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_cast_down, dim3(nblk(n)), dim3(256), 0, st, r, r32, sc_rr, sc_zs, n);
+}
+
+void launch_dot_zmix(const float* z32, const double* sc_zs, const double* r, const double* s, int64_t n,
+                     double* partials, unsigned* counter, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot_zmix, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, st, z32, sc_zs, r, s, n, partials,
+                       counter, out);
+}
+
+void launch_pcg_dir_mixed(double* p, const float* z32, const double* sc_zs, const double* sc, int64_t n,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_dir_mixed, dim3(nblk(n)), dim3(256), 0, st, p, z32, sc_zs, sc, n);
 }
 
 // Copy the solver scalars to the host notice block, then bump its sequence
