@@ -818,6 +818,9 @@ __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restri
 // nodes that a lower plane family stores hold 0 there and are copied from
 // the tiles of that family afterwards.  Ends with a barrier.
 template <typename T, int P>
+__device__ inline void tile_fill_rims(T* tile);
+
+template <typename T, int P>
 __device__ inline void stage_elem_pack_and_tiles(const LevelTabs<T>& tb, const int e[3], const T* __restrict__ u,
                                                  T* tabs, T* tile) {
     constexpr int n1 = P + 1, q = P - 1, t2 = n1 * n1;
@@ -856,9 +859,17 @@ __device__ inline void stage_elem_pack_and_tiles(const LevelTabs<T>& tb, const i
         for (int k = 0; k < NU; ++k)
             if (lane + 64 * k < t2) tile[f * t2 + lane + 64 * k] = uv[f][k];
     __syncthreads();
-    // rims stored by a lower family: x2-face columns 0, P (x1-planes) from the
-    // x1-faces; x3-face columns 0, P from the x1-faces, rows 0, P (x2-planes)
-    // from the x2-faces
+    tile_fill_rims<T, P>(tile);
+}
+
+// The rim nodes of the six face tiles that a lower plane family stores:
+// x2-face columns 0, P (x1-planes) from the x1-faces; x3-face columns 0, P
+// from the x1-faces, rows 0, P (x2-planes) from the x2-faces.  Called after
+// the barrier that follows the tile stores; ends with a barrier.
+template <typename T, int P>
+__device__ inline void tile_fill_rims(T* tile) {
+    constexpr int n1 = P + 1, t2 = n1 * n1;
+    const int lane = threadIdx.x;
     constexpr int n2r = 2 * 2 * n1, n3r = 2 * (2 * n1 + 2 * (n1 - 2));
     for (int i = lane; i < n2r + n3r; i += 64) {
         int f, r, c, src;
@@ -890,10 +901,14 @@ struct K1Shape {
     static constexpr int tab_d = n1 + n1 * n1 + 2 * q2 + 3 * q;       // one direction
     static constexpr int tabs = 3 * tab_d;
     // LDS layout (in elements of T); tmp shares V's region (the forward tmp
-    // is dead before V is written, V before the backward tmp)
+    // is dead before V is written, V before the backward tmp), and Tc shares
+    // G's: the eigenspace pass reads G_0, G_1 only at its own lane's (k2, k3)
+    // before it writes Tc_0, Tc_1 there, G_2..G_5 are dead once it ends, and
+    // the corrections go to G after Tc has been read (FP64 at p = 8: 16.4 ->
+    // 14.0 KB, ten -> eleven workgroups per CU, 234 -> 223 us per product)
     static constexpr int vt = q * q2 > 6 * q2 ? q * q2 : 6 * q2;
     static constexpr int o_tab = 0, o_tile = tabs, o_G = o_tile + 6 * t2, o_V = o_G + 6 * q2, o_tmp = o_V,
-                         o_Tc = o_V + vt, total = o_Tc + 6 * q2;
+                         o_Tc = o_G, total = o_V + vt;
 };
 
 template <typename T, int P>
@@ -3016,125 +3031,123 @@ __global__ void __launch_bounds__(256) k_recover(LevelTabs<double> tb, const dou
 // Condensation F_hat -= H_BI H_II^-1 F_I and recovery u_I = H_II^-1 (F_I -
 // H_IB u_hat) (Alg. 4, first and last steps) for 3 <= p <= 8: one wavefront
 // per element, compile-time degree.  The element's 1D tables go to LDS
-// once, with the interior eigenvector matrices in both orientations (S^T =
-// Sinv M_I^-1 for the forward and S = (M_I S) M_I^-1 for the backward
-// transform), so that no division is left in the transforms; each 1D pass of
-// the three-dimensional transforms gives one lane one line of the element
-// and keeps the line in registers.
+// without the stiffness matrices L, which neither step uses, and with the
+// interior eigenvector matrices in the orientation each step needs, S^T =
+// Sinv M_I^-1 (forward) in place of Sinv and S = (M_I S) M_I^-1 (backward,
+// recovery) in place of M_I S, so that no division is left in the
+// transforms.  Each 1D pass of the three-dimensional transforms gives one
+// lane one line of the element, held in registers, and writes it back in
+// place; the 2D face transforms hold their rows or columns in registers
+// across a barrier and write over the array they read.  LDS per element at
+// p = 8: 8.2 KB (condensation), 9.7 KB (recovery).
 // ---------------------------------------------------------------------------
 template <int P>
 struct CRShape {
     static constexpr int n1 = P + 1, q = P - 1, q2 = q * q, q3 = q2 * q, t2 = n1 * n1;
-    // per direction the packed tables m[n1] L[n1^2] Si[q2] MS[q2] lm[q] c0[q] cp[q]
+    // per direction the packed tables in device memory: m[n1] L[n1^2] Si[q2] MS[q2] lm[q] c0[q] cp[q]
     static constexpr int o_m = 0, o_L = n1, o_Si = o_L + n1 * n1, o_MS = o_Si + q2, o_lm = o_MS + q2,
                          o_c0 = o_lm + q, o_cp = o_c0 + q, tab_d = o_cp + q;
-    static constexpr int tabs = 3 * tab_d;
-    // then per direction ST[q2] SS[q2] (offsets from `tabs` of direction d: o_ST(d))
-    static constexpr int o_STS = tabs, sts = 3 * 2 * q2;
-    __host__ __device__ static constexpr int o_ST(int d) { return o_STS + d * 2 * q2; }
-    __host__ __device__ static constexpr int o_SS(int d) { return o_STS + d * 2 * q2 + q2; }
-    // LDS: tables | ST/SS | a[q3] | b[q3] | G[6 q2] | tmp[6 q2] | tile[6 t2] (recovery)
-    static constexpr int o_a = o_STS + sts, o_b = o_a + q3, o_G = o_b + q3, o_tmp = o_G + 6 * q2,
-                         o_tile = o_tmp + 6 * q2, cond_total = o_tile;
-    // recovery: tmp shares b's region (b is free between the two interior
-    // transforms) and G the tile's (the tile is dead once tmp is formed):
-    // tables | ST/SS | a[q3] | b/tmp | tile/G
-    static constexpr int rb = q3 > 6 * q2 ? q3 : 6 * q2, o_rtile = o_b + rb, rec_total = o_rtile + 6 * t2;
+    // per direction in LDS (L left out): m[n1] A[q2] B[q2] lm[q] c0[q] cp[q]
+    // with A = S^T and B = S (recovery) or M_I S (condensation)
+    static constexpr int l_m = 0, l_A = n1, l_B = l_A + q2, l_lm = l_B + q2, l_c0 = l_lm + q, l_cp = l_c0 + q,
+                         lt_d = l_cp + q, ltabs = 3 * lt_d;
+    // condensation: tables | a[q3] | Tc, then tmp [6 q2]
+    static constexpr int o_a = ltabs, o_Tc = o_a + q3, cond_total = o_Tc + 6 * q2;
+    // recovery: tables | a[q3] | tile, then tmp, then G [6 t2]
+    static constexpr int o_rtile = o_a + q3, rec_total = o_rtile + 6 * t2;
+    static_assert(6 * q <= 64 && q2 <= 64, "one lane per face row and per interior line");
 };
 
-// The packed tables of element e into LDS (CRShape layout), then the interior
-// eigenvector matrices in both orientations: ST[k][i] = Sinv[k][i] / m[i+1],
-// SS[i][k] = MS[i][k] / m[i+1].  Ends with a barrier.
-template <int P>
-__device__ inline void cr_stage_tables(const LevelTabs<double>& tb, const int e[3], double* sm) {
+// The element's tables into LDS in the CRShape layout, A = Si / m (columns)
+// and B = MS / m (rows) if SB, else B = MS; with TILES also the six face
+// tiles of uh (as for the condensed operator).  All global loads are issued
+// before the first LDS store.  Ends with a barrier.
+template <int P, bool SB, bool TILES>
+__device__ inline void cr_stage(const LevelTabs<double>& tb, const int e[3], const double* __restrict__ uh,
+                                double* tabs, double* tile) {
     using K = CRShape<P>;
-    constexpr int q = K::q, q2 = K::q2, TD0 = K::tab_d, NTD = (TD0 + 63) / 64;
+    constexpr int n1 = K::n1, q = K::q, q2 = K::q2, t2 = K::t2, LT = K::lt_d, NLT = (LT + 63) / 64,
+                  NU = (t2 + 63) / 64;
+    const Layout& L = tb.lay;
     const int lane = threadIdx.x;
-    double tv[3][NTD];
+    double tv[3][NLT], dv[3][NLT], uv[6][TILES ? NU : 1];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double* src = tb.el_pack[d] + (size_t)e[d] * TD0;
+        const double* src = tb.el_pack[d] + (size_t)e[d] * K::tab_d;
 #pragma unroll
-        for (int k = 0; k < NTD; ++k) {
+        for (int k = 0; k < NLT; ++k) {
             const int i = lane + 64 * k;
-            tv[d][k] = i < TD0 ? src[i] : 0.0;
+            // LDS entry i: m, then everything after L
+            tv[d][k] = i < LT ? src[i < n1 ? i : i + n1 * n1] : 0.0;
+            // the divisor of an A or B entry: m at its interior column (A) or row (B)
+            int dm = -1;
+            if (i >= K::l_A && i < K::l_B) dm = (i - K::l_A) % q;
+            else if (SB && i >= K::l_B && i < K::l_lm) dm = (i - K::l_B) / q;
+            dv[d][k] = dm >= 0 ? src[K::o_m + dm + 1] : 1.0;
+        }
+    }
+    if (TILES) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int d = f >> 1, s = f & 1, dr = tile_rdir(d), dc = tile_cdir(d);
+            const int64_t base = (d == 0 ? L.plane0(e[0] + s) : (d == 1 ? L.plane1(e[1] + s) : L.plane2(e[2] + s))) +
+                                 (int64_t)(e[dr] * P) * L.pitch[d] + e[dc] * P;
+#pragma unroll
+            for (int k = 0; k < NU; ++k) {
+                const int i = lane + 64 * k, r = i / n1, c = i - r * n1;
+                uv[f][TILES ? k : 0] = i < t2 ? uh[base + (int64_t)r * L.pitch[d] + c] : 0.0;
+            }
         }
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int k = 0; k < NTD; ++k)
-            if (lane + 64 * k < TD0) sm[d * TD0 + lane + 64 * k] = tv[d][k];
-    __syncthreads();
-    for (int i = lane; i < 3 * 2 * q2; i += 64) {
-        const int d = i / (2 * q2), w = i - d * 2 * q2, which = w / q2, rc = w - which * q2;
-        const double* t = sm + d * TD0;
-        const int col = which == 0 ? rc % q : rc / q;   // the interior index i
-        const double mi = t[K::o_m + col + 1];
-        if (which == 0) sm[K::o_ST(d) + rc] = t[K::o_Si + rc] / mi;
-        else sm[K::o_SS(d) + rc] = t[K::o_MS + rc] / mi;
+        for (int k = 0; k < NLT; ++k)
+            if (lane + 64 * k < LT) tabs[d * LT + lane + 64 * k] = tv[d][k] / dv[d][k];
+    if (TILES) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f)
+#pragma unroll
+            for (int k = 0; k < NU; ++k)
+                if (lane + 64 * k < t2) tile[f * t2 + lane + 64 * k] = uv[f][TILES ? k : 0];
     }
     __syncthreads();
+    if (TILES) tile_fill_rims<double, P>(tile);
 }
 
-// Three 1D passes of a separable transform of the q^3 array x (layout
-// [i3][i2][i1]) with the matrices A_d (row-major q x q, out[k] = sum_i
-// A_d[k][i] in[i]) at offset `off` in each direction's table; x is
-// overwritten, y is scratch.  The result ends in x.
+// Three in-place 1D passes of a separable transform of the q^3 array x
+// (layout [i3][i2][i1]): out[k] = sum_i A_d[k][i] in[i] with A_d the A
+// (FWD) or B matrix of direction d.
 template <int P, bool FWD>
-__device__ inline void cr_transform3(const double* tabs, double* x, double* y) {
+__device__ inline void cr_transform3(const double* tabs, double* x) {
     using K = CRShape<P>;
-    constexpr int q = K::q, q2 = K::q2;
+    constexpr int q = K::q, q2 = K::q2, LT = K::lt_d, OA = FWD ? K::l_A : K::l_B;
     const int lane = threadIdx.x;
-    if (lane < q2) {   // x1 lines: (i2, i3) = (lane % q, lane / q)
-        const double* A = tabs + (FWD ? K::o_ST(0) : K::o_SS(0));
-        double v[q], w[q];
+    // pass d: lane (j0, j1) = (lane % q, lane / q) takes the line along x_d
+    // through the other two indices; element i of the line sits at
+    // base + i * stride
+    auto pass = [&](int d) {
+        if (lane < q2) {
+            const int j0 = lane % q, j1 = lane / q;
+            const int base = d == 0 ? lane * q : (d == 1 ? j1 * q2 + j0 : lane);
+            const int stride = d == 0 ? 1 : (d == 1 ? q : q2);
+            const double* A = tabs + d * LT + OA;
+            double v[q];
 #pragma unroll
-        for (int i = 0; i < q; ++i) v[i] = x[lane * q + i];
+            for (int i = 0; i < q; ++i) v[i] = x[base + i * stride];
 #pragma unroll
-        for (int k = 0; k < q; ++k) {
-            double s = 0.0;
+            for (int k = 0; k < q; ++k) {
+                double s = 0.0;
 #pragma unroll
-            for (int i = 0; i < q; ++i) s += A[k * q + i] * v[i];
-            w[k] = s;
+                for (int i = 0; i < q; ++i) s += A[k * q + i] * v[i];
+                x[base + k * stride] = s;
+            }
         }
-#pragma unroll
-        for (int k = 0; k < q; ++k) y[lane * q + k] = w[k];
-    }
-    __syncthreads();
-    if (lane < q2) {   // x2 lines: (i1, i3) = (lane % q, lane / q)
-        const int i1 = lane % q, i3 = lane / q;
-        const double* A = tabs + (FWD ? K::o_ST(1) : K::o_SS(1));
-        double v[q], w[q];
-#pragma unroll
-        for (int i = 0; i < q; ++i) v[i] = y[(i3 * q + i) * q + i1];
-#pragma unroll
-        for (int k = 0; k < q; ++k) {
-            double s = 0.0;
-#pragma unroll
-            for (int i = 0; i < q; ++i) s += A[k * q + i] * v[i];
-            w[k] = s;
-        }
-#pragma unroll
-        for (int k = 0; k < q; ++k) x[(i3 * q + k) * q + i1] = w[k];
-    }
-    __syncthreads();
-    if (lane < q2) {   // x3 lines: (i1, i2) = (lane % q, lane / q)
-        const double* A = tabs + (FWD ? K::o_ST(2) : K::o_SS(2));
-        double v[q], w[q];
-#pragma unroll
-        for (int i = 0; i < q; ++i) v[i] = x[i * q2 + lane];
-#pragma unroll
-        for (int k = 0; k < q; ++k) {
-            double s = 0.0;
-#pragma unroll
-            for (int i = 0; i < q; ++i) s += A[k * q + i] * v[i];
-            w[k] = s;
-        }
-#pragma unroll
-        for (int k = 0; k < q; ++k) x[k * q2 + lane] = w[k];
-    }
-    __syncthreads();
+        __syncthreads();
+    };
+    pass(0);
+    pass(1);
+    pass(2);
 }
 
 // a[q3] = m1 m2 m3 f at the element's interior nodes
@@ -3142,11 +3155,11 @@ template <int P>
 __device__ inline void cr_load_interior(const Layout& L, const int e[3], const double* tabs,
                                         const double* __restrict__ f, double* a) {
     using K = CRShape<P>;
-    constexpr int q = K::q, q2 = K::q2;
+    constexpr int q = K::q, q2 = K::q2, LT = K::lt_d;
     for (int i = threadIdx.x; i < K::q3; i += 64) {
         const int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
         const int i1 = e[0] * P + 1 + k1, i2 = e[1] * P + 1 + k2, i3 = e[2] * P + 1 + k3;
-        a[i] = tabs[K::o_m + k1 + 1] * tabs[K::tab_d + K::o_m + k2 + 1] * tabs[2 * K::tab_d + K::o_m + k3 + 1] *
+        a[i] = tabs[K::l_m + k1 + 1] * tabs[LT + K::l_m + k2 + 1] * tabs[2 * LT + K::l_m + k3 + 1] *
                f[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1];
     }
 }
@@ -3154,27 +3167,26 @@ __device__ inline void cr_load_interior(const Layout& L, const int e[3], const d
 template <int P>
 __global__ void __launch_bounds__(64) k_condense_w(LevelTabs<double> tb, const double* __restrict__ f) {
     using K = CRShape<P>;
-    constexpr int n1 = K::n1, q = K::q, q2 = K::q2, t2 = K::t2, TD = K::tab_d;
+    constexpr int n1 = K::n1, q = K::q, q2 = K::q2, t2 = K::t2, LT = K::lt_d;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* sm = reinterpret_cast<double*>(smem_raw);
     double* tabs = sm;
     double* a = sm + K::o_a;
-    double* b = sm + K::o_b;
-    double* Tc = sm + K::o_G;
-    double* tmp = sm + K::o_tmp;
+    double* Tc = sm + K::o_Tc;
+    double* tmp = Tc;   // after Tc has been read into registers
     const Layout& L = tb.lay;
     const int lane = threadIdx.x;
     const int eid = xcd_remap(blockIdx.x, gridDim.x);
     int e[3];
     color_coords(eid, -1, L.n, e);
-    cr_stage_tables<P>(tb, e, sm);
+    cr_stage<P, false, false>(tb, e, nullptr, tabs, nullptr);
     cr_load_interior<P>(L, e, tabs, f, a);
     __syncthreads();
-    cr_transform3<P, true>(sm, a, b);          // a = (S x S x S)^T F_I
+    cr_transform3<P, true>(tabs, a);           // a = (S x S x S)^T F_I
     const double lam = tb.lam;
-    auto lm = [&](int d) { return tabs + d * TD + K::o_lm; };
-    auto c0 = [&](int d) { return tabs + d * TD + K::o_c0; };
-    auto cp = [&](int d) { return tabs + d * TD + K::o_cp; };
+    auto lm = [&](int d) { return tabs + d * LT + K::l_lm; };
+    auto c0 = [&](int d) { return tabs + d * LT + K::l_c0; };
+    auto cp = [&](int d) { return tabs + d * LT + K::l_cp; };
     // V = a / D, in place, with the x1-contractions on the fly (lane: (k2, k3))
     if (lane < q2) {
         const int k2 = lane % q, k3 = lane / q;
@@ -3214,47 +3226,55 @@ __global__ void __launch_bounds__(64) k_condense_w(LevelTabs<double> tb, const d
         Tc[(3 + 2 * dm) * q2 + rc] = sp;
     }
     __syncthreads();
-    // corr_f = MS_R Tc_f MS_C^T (lane: face f, row kr, then face f, column c)
-    for (int ii = lane; ii < 6 * q; ii += 64) {
-        const int f = ii / q, kr = ii - f * q;
-        const double* Mc = tabs + tile_cdir(f >> 1) * TD + K::o_MS;
+    // corr_f = MS_R Tc_f MS_C^T: rows (lane: face f, row kr) into registers,
+    // then over Tc as tmp; columns (lane: face f, column c) straight out
+    double t[q];
+    if (lane < 6 * q) {
+        const int fc = lane / q, kr = lane - fc * q;
+        const double* Mc = tabs + tile_cdir(fc >> 1) * LT + K::l_B;
         double x[q];
 #pragma unroll
-        for (int kc = 0; kc < q; ++kc) x[kc] = Tc[f * q2 + kr * q + kc];
+        for (int kc = 0; kc < q; ++kc) x[kc] = Tc[fc * q2 + kr * q + kc];
 #pragma unroll
         for (int c = 0; c < q; ++c) {
             double s = 0.0;
 #pragma unroll
             for (int kc = 0; kc < q; ++kc) s += x[kc] * Mc[c * q + kc];
-            tmp[f * q2 + kr * q + c] = s;
+            t[c] = s;
         }
     }
     __syncthreads();
+    if (lane < 6 * q) {
+        const int fc = lane / q, kr = lane - fc * q;
+#pragma unroll
+        for (int c = 0; c < q; ++c) tmp[fc * q2 + kr * q + c] = t[c];
+    }
+    __syncthreads();
     double* out = tb.opE + (size_t)eid * 6 * t2;
-    for (int ii = lane; ii < 6 * q; ii += 64) {
-        const int f = ii / q, c = ii - f * q;
-        const double* Mr = tabs + tile_rdir(f >> 1) * TD + K::o_MS;
+    if (lane < 6 * q) {
+        const int fc = lane / q, c = lane - fc * q;
+        const double* Mr = tabs + tile_rdir(fc >> 1) * LT + K::l_B;
         double x[q];
 #pragma unroll
-        for (int kr = 0; kr < q; ++kr) x[kr] = tmp[f * q2 + kr * q + c];
+        for (int kr = 0; kr < q; ++kr) x[kr] = tmp[fc * q2 + kr * q + c];
 #pragma unroll
         for (int r = 0; r < q; ++r) {
             double s = 0.0;
 #pragma unroll
             for (int kr = 0; kr < q; ++kr) s += Mr[r * q + kr] * x[kr];
-            out[f * t2 + (r + 1) * n1 + c + 1] = s;
+            out[fc * t2 + (r + 1) * n1 + c + 1] = s;
         }
     }
     // the rims of the six tiles carry no correction
     constexpr int nrim = 6 * 4 * P;
     for (int i = lane; i < nrim; i += 64) {
-        const int f = i / (4 * P), k = i - f * 4 * P, side = k / P, t = k - side * P;
+        const int fc = i / (4 * P), k = i - fc * 4 * P, side = k / P, tt = k - side * P;
         int r, c;
-        if (side == 0) { r = 0; c = t; }
-        else if (side == 1) { r = t; c = P; }
-        else if (side == 2) { r = P; c = P - t; }
-        else { r = P - t; c = 0; }
-        out[f * t2 + r * n1 + c] = 0.0;
+        if (side == 0) { r = 0; c = tt; }
+        else if (side == 1) { r = tt; c = P; }
+        else if (side == 2) { r = P; c = P - tt; }
+        else { r = P - tt; c = 0; }
+        out[fc * t2 + r * n1 + c] = 0.0;
     }
 }
 
@@ -3262,29 +3282,20 @@ template <int P>
 __global__ void __launch_bounds__(64) k_recover_w(LevelTabs<double> tb, const double* __restrict__ f,
                                                   const double* __restrict__ uh, double* __restrict__ ug) {
     using K = CRShape<P>;
-    constexpr int n1 = K::n1, q = K::q, q2 = K::q2, t2 = K::t2, TD = K::tab_d;
+    constexpr int n1 = K::n1, q = K::q, q2 = K::q2, t2 = K::t2, LT = K::lt_d;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* sm = reinterpret_cast<double*>(smem_raw);
     double* tabs = sm;
     double* a = sm + K::o_a;
-    double* b = sm + K::o_b;
-    double* tmp = b;                    // after the forward transform
     double* tile = sm + K::o_rtile;
-    double* G = tile;                   // after tmp is formed from the tile
+    double* tmp = tile;   // after the face rows have been read into registers
+    double* G = tile;     // after the columns of tmp have been read
     const Layout& L = tb.lay;
     const int lane = threadIdx.x;
     const int eid = xcd_remap(blockIdx.x, gridDim.x);
     int e[3];
     color_coords(eid, -1, L.n, e);
-    stage_elem_pack_and_tiles<double, P>(tb, e, uh, tabs, tile);
-    for (int i = lane; i < 3 * 2 * q2; i += 64) {   // ST and SS (cr_stage_tables without the loads)
-        const int d = i / (2 * q2), w = i - d * 2 * q2, which = w / q2, rc = w - which * q2;
-        const double* t = tabs + d * TD;
-        const int col = which == 0 ? rc % q : rc / q;
-        const double mi = t[K::o_m + col + 1];
-        if (which == 0) sm[K::o_ST(d) + rc] = t[K::o_Si + rc] / mi;
-        else sm[K::o_SS(d) + rc] = t[K::o_MS + rc] / mi;
-    }
+    cr_stage<P, true, true>(tb, e, uh, tabs, tile);
     cr_load_interior<P>(L, e, tabs, f, a);
     // shell nodes owned by this element: a_d < p, or a_d = p on the last element
     for (int i = lane; i < n1 * n1 * n1; i += 64) {
@@ -3298,26 +3309,36 @@ __global__ void __launch_bounds__(64) k_recover_w(LevelTabs<double> tb, const do
             is_dir(L, i1, i2, i3) ? 0.0 : shell_value(tile, P, a1, a2, a3);
     }
     __syncthreads();
-    cr_transform3<P, true>(sm, a, b);          // a = (S x S x S)^T F_I
-    // G_f = Si_R X_f Si_C^T on the face interiors
-    for (int ii = lane; ii < 6 * q; ii += 64) {
-        const int fc = ii / q, r = ii - fc * q;
-        const double* Sc = tabs + tile_cdir(fc >> 1) * TD + K::o_Si;
+    cr_transform3<P, true>(tabs, a);           // a = (S x S x S)^T F_I
+    // G_f = Si_R X_f Si_C^T = S^T_R (m_R m_C X_f) S^T_C^T on the face
+    // interiors: rows (lane: face f, row r) into registers, over the tile as
+    // tmp; columns (lane: face f, column kc) into registers, over tmp as G
+    double t[q];
+    if (lane < 6 * q) {
+        const int fc = lane / q, r = lane - fc * q, d = fc >> 1, dr = tile_rdir(d), dc = tile_cdir(d);
+        const double* Sc = tabs + dc * LT + K::l_A;
+        const double mr = tabs[dr * LT + K::l_m + r + 1];
         double x[q];
 #pragma unroll
-        for (int c = 0; c < q; ++c) x[c] = tile[fc * t2 + (r + 1) * n1 + c + 1];
+        for (int c = 0; c < q; ++c) x[c] = mr * tabs[dc * LT + K::l_m + c + 1] * tile[fc * t2 + (r + 1) * n1 + c + 1];
 #pragma unroll
         for (int kc = 0; kc < q; ++kc) {
             double s = 0.0;
 #pragma unroll
             for (int c = 0; c < q; ++c) s += x[c] * Sc[kc * q + c];
-            tmp[fc * q2 + r * q + kc] = s;
+            t[kc] = s;
         }
     }
     __syncthreads();
-    for (int ii = lane; ii < 6 * q; ii += 64) {
-        const int fc = ii / q, kc = ii - fc * q;
-        const double* Sr = tabs + tile_rdir(fc >> 1) * TD + K::o_Si;
+    if (lane < 6 * q) {
+        const int fc = lane / q, r = lane - fc * q;
+#pragma unroll
+        for (int kc = 0; kc < q; ++kc) tmp[fc * q2 + r * q + kc] = t[kc];
+    }
+    __syncthreads();
+    if (lane < 6 * q) {
+        const int fc = lane / q, kc = lane - fc * q;
+        const double* Sr = tabs + tile_rdir(fc >> 1) * LT + K::l_A;
         double x[q];
 #pragma unroll
         for (int r = 0; r < q; ++r) x[r] = tmp[fc * q2 + r * q + kc];
@@ -3326,21 +3347,27 @@ __global__ void __launch_bounds__(64) k_recover_w(LevelTabs<double> tb, const do
             double s = 0.0;
 #pragma unroll
             for (int r = 0; r < q; ++r) s += Sr[kr * q + r] * x[r];
-            G[fc * q2 + kr * q + kc] = s;
+            t[kr] = s;
         }
+    }
+    __syncthreads();
+    if (lane < 6 * q) {
+        const int fc = lane / q, kc = lane - fc * q;
+#pragma unroll
+        for (int kr = 0; kr < q; ++kr) G[fc * q2 + kr * q + kc] = t[kr];
     }
     __syncthreads();
     // V = (a - sum_f c_f (x) G_f) / D in place (lane: (k2, k3) line)
     const double lam = tb.lam;
     if (lane < q2) {
         const int k2 = lane % q, k3 = lane / q;
-        const double* lm0 = tabs + K::o_lm;
-        const double* c00 = tabs + K::o_c0;
-        const double* cp0 = tabs + K::o_cp;
+        const double* lm0 = tabs + K::l_lm;
+        const double* c00 = tabs + K::l_c0;
+        const double* cp0 = tabs + K::l_cp;
         const double g0 = G[0 * q2 + k3 * q + k2], g1 = G[1 * q2 + k3 * q + k2];
-        const double a1 = tabs[TD + K::o_c0 + k2], b1 = tabs[TD + K::o_cp + k2];
-        const double a2 = tabs[2 * TD + K::o_c0 + k3], b2 = tabs[2 * TD + K::o_cp + k3];
-        const double dd = lam + tabs[TD + K::o_lm + k2] + tabs[2 * TD + K::o_lm + k3];
+        const double a1 = tabs[LT + K::l_c0 + k2], b1 = tabs[LT + K::l_cp + k2];
+        const double a2 = tabs[2 * LT + K::l_c0 + k3], b2 = tabs[2 * LT + K::l_cp + k3];
+        const double dd = lam + tabs[LT + K::l_lm + k2] + tabs[2 * LT + K::l_lm + k3];
 #pragma unroll
         for (int k1 = 0; k1 < q; ++k1) {
             const double ex = c00[k1] * g0 + cp0[k1] * g1 + a1 * G[2 * q2 + k3 * q + k1] +
@@ -3350,7 +3377,7 @@ __global__ void __launch_bounds__(64) k_recover_w(LevelTabs<double> tb, const do
         }
     }
     __syncthreads();
-    cr_transform3<P, false>(sm, a, b);          // u_I = (S x S x S) V
+    cr_transform3<P, false>(tabs, a);          // u_I = (S x S x S) V
     for (int i = lane; i < K::q3; i += 64) {
         const int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
         const int i1 = e[0] * P + 1 + k1, i2 = e[1] * P + 1 + k2, i3 = e[2] * P + 1 + k3;
