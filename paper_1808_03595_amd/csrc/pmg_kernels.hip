@@ -895,20 +895,82 @@ __device__ inline void tile_fill_rims(T* tile) {
     __syncthreads();
 }
 
+// Canonical edge and vertex nodes of the condensed operator's element
+// product (shell part only; no interior correction reaches them): rims of
+// the x1-faces (4P each) and the two rows of the x2-faces that no x1-face
+// holds (P - 1 each).  tabs and tile as staged by stage_elem_pack_and_tiles.
+template <typename T, int P>
+__device__ inline void k1_rims(const T* tabs, const T* tile, T lam, T* __restrict__ out) {
+    constexpr int n1 = P + 1, q = P - 1, t2 = n1 * n1, q2 = q * q;
+    constexpr int TD = n1 + n1 * n1 + 2 * q2 + 3 * q;
+    const int lane = threadIdx.x;
+    auto Tm = [&](int d) { return tabs + d * TD; };
+    auto TL = [&](int d) { return tabs + d * TD + n1; };
+    // canonical edge and vertex nodes: rims of the x1-faces (4P each) and
+    // the two non-canonical-free rows of the x2-faces (P - 1 each)
+    constexpr int nrim0 = 4 * P, nrim1 = 2 * (P - 1), nrim = 2 * nrim0 + 2 * nrim1;
+    for (int i = lane; i < nrim; i += 64) {
+        int f, r, c;
+        if (i < 2 * nrim0) {
+            f = i / nrim0;
+            const int k = i - f * nrim0, side = k / P, t = k - side * P;
+            // walk the rim: r = 0 row, c = P column, r = P row, c = 0 column
+            if (side == 0) { r = 0; c = t; }
+            else if (side == 1) { r = t; c = P; }
+            else if (side == 2) { r = P; c = P - t; }
+            else { r = P - t; c = 0; }
+        } else {
+            const int k = i - 2 * nrim0, ff = k / nrim1, t = k - ff * nrim1;
+            f = 2 + ff;
+            r = t < P - 1 ? 0 : P;
+            c = 1 + (t < P - 1 ? t : t - (P - 1));
+        }
+        int A0, A1, A2;
+        tile_node(P, f, r, c, A0, A1, A2);
+        auto av = [&](int d) { return d == 0 ? A0 : (d == 1 ? A1 : A2); };
+        // every line through an edge or vertex node lies in a face tile:
+        // take the face normal to the first other direction whose local
+        // coordinate is 0 or P, and walk its row or column
+        T acc = 0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
+            const int dn = (av(o1) == 0 || av(o1) == P) ? o1 : o2;
+            const int ft = 2 * dn + (av(dn) == P ? 1 : 0);
+            const int rd = tile_rdir(dn), cd = tile_cdir(dn);
+            int base, stride;
+            if (d == rd) { base = ft * t2 + av(cd); stride = n1; }
+            else { base = ft * t2 + av(rd) * n1; stride = 1; }
+            const T* Ld = TL(d) + av(d) * n1;
+            T x = 0;
+#pragma unroll
+            for (int j = 0; j < n1; ++j) x += Ld[j] * tile[base + j * stride];
+            acc += Tm(o1)[av(o1)] * Tm(o2)[av(o2)] * x;
+        }
+        out[f * t2 + r * n1 + c] = lam * Tm(0)[A0] * Tm(1)[A1] * Tm(2)[A2] * tile[f * t2 + r * n1 + c] + acc;
+    }
+}
+
 template <int P>
 struct K1Shape {
     static constexpr int n1 = P + 1, q = P - 1, t2 = n1 * n1, q2 = q * q;
     static constexpr int tab_d = n1 + n1 * n1 + 2 * q2 + 3 * q;       // one direction
     static constexpr int tabs = 3 * tab_d;
-    // LDS layout (in elements of T); tmp shares V's region (the forward tmp
+    // One lane per face-interior row (6 (p - 1) <= 64): the row's shell part
+    // and its first forward product stay in registers, so the tile is dead
+    // after the first pass and G and V take its place in LDS
+    static constexpr bool early = 6 * q <= 64;
+    // LDS layout (in elements of T): tables | tile | G | V, the tile region
+    // shared with G and V when early.  tmp shares V's region (the forward tmp
     // is dead before V is written, V before the backward tmp), and Tc shares
     // G's: the eigenspace pass reads G_0, G_1 only at its own lane's (k2, k3)
     // before it writes Tc_0, Tc_1 there, G_2..G_5 are dead once it ends, and
-    // the corrections go to G after Tc has been read (FP64 at p = 8: 16.4 ->
-    // 14.0 KB, ten -> eleven workgroups per CU, 234 -> 223 us per product)
+    // the corrections go to G after Tc has been read.  FP64 at p = 8: 10.1 KB
+    // per element, sixteen workgroups per CU
     static constexpr int vt = q * q2 > 6 * q2 ? q * q2 : 6 * q2;
-    static constexpr int o_tab = 0, o_tile = tabs, o_G = o_tile + 6 * t2, o_V = o_G + 6 * q2, o_tmp = o_V,
-                         o_Tc = o_G, total = o_V + vt;
+    static constexpr int o_tab = 0, o_tile = tabs, o_G = early ? tabs : o_tile + 6 * t2, o_V = o_G + 6 * q2,
+                         o_tmp = o_V, o_Tc = o_G,
+                         total = early ? tabs + (6 * t2 > 6 * q2 + vt ? 6 * t2 : 6 * q2 + vt) : o_V + vt;
 };
 
 template <typename T, int P>
@@ -941,23 +1003,73 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
     auto Tlm = [&](int d) { return tabs + d * TD + n1 + n1 * n1 + 2 * q2; };
     auto Tc0 = [&](int d) { return tabs + d * TD + n1 + n1 * n1 + 2 * q2 + q; };
     auto Tcp = [&](int d) { return tabs + d * TD + n1 + n1 * n1 + 2 * q2 + 2 * q; };
-    if (q > 0) {
-        // tmp_f = X_f Si_C^T (lane: face f, row r)
-        for (int ii = lane; ii < 6 * q; ii += 64) {
-            const int f = ii / q, r = ii - f * q;
-            const T* Sc = TSi(tile_cdir(f >> 1));
-            T x[q > 0 ? q : 1];
+    constexpr int QR = q > 0 ? q : 1;
+    // tmp row r of face f: X_f Si_C^T (interior row r + 1 of the tile)
+    auto fwd_row = [&](int f, int r, T t[]) {
+        const T* Sc = TSi(tile_cdir(f >> 1));
+        T x[QR];
 #pragma unroll
-            for (int c = 0; c < q; ++c) x[c] = tile[f * t2 + (r + 1) * n1 + c + 1];
+        for (int c = 0; c < q; ++c) x[c] = tile[f * t2 + (r + 1) * n1 + c + 1];
 #pragma unroll
-            for (int kc = 0; kc < q; ++kc) {
-                T s = 0;
+        for (int kc = 0; kc < q; ++kc) {
+            T s = 0;
 #pragma unroll
-                for (int c = 0; c < q; ++c) s += x[c] * Sc[kc * q + c];
-                tmp[f * q2 + r * q + kc] = s;
-            }
+            for (int c = 0; c < q; ++c) s += x[c] * Sc[kc * q + c];
+            t[kc] = s;
+        }
+    };
+    // shell part H_BB u_B at face-interior node (r, c) (1..q) of face f,
+    // row = the tile's row r: in-face lines stay in the tile, the normal line
+    // meets the shell only at the two opposite faces
+    auto shell_at = [&](int f, int r, int c, const T row[]) -> T {
+        const int d = f >> 1, s = f & 1, dr = tile_rdir(d), dc = tile_cdir(d);
+        const T* Lr = TL(dr) + r * n1;
+        const T* Lc = TL(dc);
+        const T* Ln = TL(d) + (s ? P : 0) * n1;
+        const T md = Tm(d)[s ? P : 0], mr = Tm(dr)[r];
+        T xr = 0, xc = 0;
+#pragma unroll
+        for (int j = 0; j < n1; ++j) {
+            xr += Lr[j] * tile[f * t2 + j * n1 + c];
+            xc += Lc[c * n1 + j] * row[j];
+        }
+        const T mc = Tm(dc)[c];
+        return lam * md * mr * mc * row[c] + md * mc * xr + md * mr * xc +
+               mr * mc * (Ln[0] * tile[(2 * d) * t2 + r * n1 + c] + Ln[P] * tile[(2 * d + 1) * t2 + r * n1 + c]);
+    };
+    auto load_row = [&](int f, int r, T row[]) {
+#pragma unroll
+        for (int j = 0; j < n1; ++j) row[j] = tile[f * t2 + r * n1 + j];
+    };
+    T hb[QR], t[QR];
+    if (K::early) {
+        if (lane < 6 * q) {
+            const int f = lane / q, r = lane - f * q;
+            T row[n1];
+            load_row(f, r + 1, row);
+#pragma unroll
+            for (int c = 1; c <= q; ++c) hb[c - 1] = shell_at(f, r + 1, c, row);
+            fwd_row(f, r, t);
+        }
+        k1_rims<T, P>(tabs, tile, lam, out);
+        __syncthreads();   // every tile read done: G and V may overwrite it
+        if (lane < 6 * q) {
+            const int f = lane / q, r = lane - f * q;
+#pragma unroll
+            for (int kc = 0; kc < q; ++kc) tmp[f * q2 + r * q + kc] = t[kc];
         }
         __syncthreads();
+    }
+    if (q > 0) {
+        if (!K::early) {
+            for (int ii = lane; ii < 6 * q; ii += 64) {
+                const int f = ii / q, r = ii - f * q;
+                fwd_row(f, r, t);
+#pragma unroll
+                for (int kc = 0; kc < q; ++kc) tmp[f * q2 + r * q + kc] = t[kc];
+            }
+            __syncthreads();
+        }
         // G_f = Si_R tmp_f (lane: face f, column kc)
         for (int ii = lane; ii < 6 * q; ii += 64) {
             const int f = ii / q, kc = ii - f * q;
@@ -1050,79 +1162,21 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
         }
         __syncthreads();
     }
-    // face-interior nodes (lane: face f, row r): in-face lines stay in the
-    // tile, the normal line meets the shell only at the two opposite faces
-    for (int ii = lane; ii < 6 * q; ii += 64) {
-        const int f = ii / q, r = ii - f * q + 1, d = f >> 1, s = f & 1;
-        {
-            const int dr = tile_rdir(d), dc = tile_cdir(d);
-            const T* Lr = TL(dr) + r * n1;
-            const T* Lc = TL(dc);
-            const T* Ln = TL(d) + (s ? P : 0) * n1;
-            const T md = Tm(d)[s ? P : 0], mr = Tm(dr)[r];
-            const T* trow = tile + f * t2 + r * n1;
-            const T* t0 = tile + (2 * d) * t2 + r * n1;
-            const T* t1 = tile + (2 * d + 1) * t2 + r * n1;
+    if (K::early) {
+        if (lane < 6 * q) {
+            const int f = lane / q, r = lane - f * q;
+#pragma unroll
+            for (int c = 0; c < q; ++c) out[f * t2 + (r + 1) * n1 + c + 1] = hb[c] - G[f * q2 + r * q + c];
+        }
+    } else {
+        for (int ii = lane; ii < 6 * q; ii += 64) {
+            const int f = ii / q, r = ii - f * q + 1;
             T row[n1];
-#pragma unroll
-            for (int j = 0; j < n1; ++j) row[j] = trow[j];
-            for (int c = 1; c <= q; ++c) {
-                T xr = 0, xc = 0;
-#pragma unroll
-                for (int j = 0; j < n1; ++j) {
-                    xr += Lr[j] * tile[f * t2 + j * n1 + c];
-                    xc += Lc[c * n1 + j] * row[j];
-                }
-                const T mc = Tm(dc)[c];
-                T v = lam * md * mr * mc * row[c] + md * mc * xr + md * mr * xc +
-                      mr * mc * (Ln[0] * t0[c] + Ln[P] * t1[c]);
-                v -= G[f * q2 + (r - 1) * q + (c - 1)];
-                out[f * t2 + r * n1 + c] = v;
-            }
+            load_row(f, r, row);
+            for (int c = 1; c <= q; ++c)
+                out[f * t2 + r * n1 + c] = shell_at(f, r, c, row) - G[f * q2 + (r - 1) * q + (c - 1)];
         }
-    }
-    // canonical edge and vertex nodes: rims of the x1-faces (4P each) and
-    // the two non-canonical-free rows of the x2-faces (P - 1 each)
-    constexpr int nrim0 = 4 * P, nrim1 = 2 * (P - 1), nrim = 2 * nrim0 + 2 * nrim1;
-    for (int i = lane; i < nrim; i += 64) {
-        int f, r, c;
-        if (i < 2 * nrim0) {
-            f = i / nrim0;
-            const int k = i - f * nrim0, side = k / P, t = k - side * P;
-            // walk the rim: r = 0 row, c = P column, r = P row, c = 0 column
-            if (side == 0) { r = 0; c = t; }
-            else if (side == 1) { r = t; c = P; }
-            else if (side == 2) { r = P; c = P - t; }
-            else { r = P - t; c = 0; }
-        } else {
-            const int k = i - 2 * nrim0, ff = k / nrim1, t = k - ff * nrim1;
-            f = 2 + ff;
-            r = t < P - 1 ? 0 : P;
-            c = 1 + (t < P - 1 ? t : t - (P - 1));
-        }
-        int A0, A1, A2;
-        tile_node(P, f, r, c, A0, A1, A2);
-        auto av = [&](int d) { return d == 0 ? A0 : (d == 1 ? A1 : A2); };
-        // every line through an edge or vertex node lies in a face tile:
-        // take the face normal to the first other direction whose local
-        // coordinate is 0 or P, and walk its row or column
-        T acc = 0;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int o1 = d == 0 ? 1 : 0, o2 = d == 2 ? 1 : 2;
-            const int dn = (av(o1) == 0 || av(o1) == P) ? o1 : o2;
-            const int ft = 2 * dn + (av(dn) == P ? 1 : 0);
-            const int rd = tile_rdir(dn), cd = tile_cdir(dn);
-            int base, stride;
-            if (d == rd) { base = ft * t2 + av(cd); stride = n1; }
-            else { base = ft * t2 + av(rd) * n1; stride = 1; }
-            const T* Ld = TL(d) + av(d) * n1;
-            T x = 0;
-#pragma unroll
-            for (int j = 0; j < n1; ++j) x += Ld[j] * tile[base + j * stride];
-            acc += Tm(o1)[av(o1)] * Tm(o2)[av(o2)] * x;
-        }
-        out[f * t2 + r * n1 + c] = lam * Tm(0)[A0] * Tm(1)[A1] * Tm(2)[A2] * tile[f * t2 + r * n1 + c] + acc;
+        k1_rims<T, P>(tabs, tile, lam, out);
     }
 }
 
