@@ -1368,7 +1368,7 @@ __device__ __forceinline__ void v4_to(const typename Mfma<T>::v4& c, T o[4]) {
 
 // LDS entries per wavefront of the matrix-core smoother
 template <typename T>
-constexpr int sm_mfma_per_wave() { return sizeof(T) == 4 ? 3072 : 1024; }
+constexpr int sm_mfma_per_wave() { return 1024; }
 
 template <typename T, int WPB>
 __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, const T* __restrict__ r,
@@ -1400,11 +1400,10 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
     const T* S3 = tb.st_SP[2] + (size_t)v3 * 256;
     const int c1 = v1 * p, c2 = v2 * p, c3 = v3 * p;
     // the eigenspace pass works on the 4x4x4 tile (t1, t2, t3) of this lane;
-    // its vectors a_d (row c of S_d), the eigenvalues, the weights and the
-    // A-pattern copies of S for the back transforms are loaded with the
-    // operands in FP32, so that no later step waits on memory for them; FP64
-    // lacks the registers and loads each set where it is needed
-    constexpr bool early = sizeof(T) == 4;
+    // its vectors a_d (row c of S_d) and the eigenvalues, the A-pattern
+    // copies of S for the back transforms and the weights are each loaded
+    // where they are needed (loading them all with the first operands
+    // measured 12 % slower in FP32: 166.6 -> 145.6 us at 32^3, p = 8)
     const int t1 = lane & 3, t2 = (lane >> 2) & 3, t3 = lane >> 4;
     const int k1b = 4 * t1, k2b = 4 * t2, k3b = 4 * t3;
     T a1[4], a2[4], a3[4], l1[4], l2[4], l3[4], wr[4], wj;
@@ -1427,10 +1426,6 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
         for (int i = 0; i < 4; ++i) wr[i] = tb.st_wP[M::row(q, i)];
         wj = omega * tb.st_wP[j];
     };
-    if (early) {
-        load_eig();
-        load_w();
-    }
     // S in both operand patterns: Sb[s] = S[row(q,s)][j], Sa[s] = S[j][row(q,s)]
     T Sb1[4], Sb2[4], Sb3[4], Sa1[4], Sa2[4], Sa3[4];
     T f1[4], f2[4], f3[4];
@@ -1482,20 +1477,11 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
         sm[256 + rr * 16 + j] = g2[v];  // G2[k3][k1]
         sm[512 + rr * 16 + j] = g3[v];  // G3[k2][k1]
     }
-    if (early) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int k = M::row(q, s);
-            Sa1[s] = S1[j * 16 + k];
-            Sa2[s] = S2[j * 16 + k];
-            Sa3[s] = S3[j * 16 + k];
-        }
-    }
     __syncthreads();
     // eigenspace pass on this lane's tile: V = (a1 G1 + a2 G2 + a3 G3) /
     // (lambda + l1 + l2 + l3), the three contractions accumulated in registers
     T H1p[4][4], H2p[4][4], H3p[4][4];
-    if (!early) load_eig();
+    load_eig();
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -1526,9 +1512,9 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
             }
     }
     // the three contractions are summed over the four tiles that share an
-    // index through LDS: P1[t1][k3][k2], P2[t2][k3][k1], P3[t3][k2][k1]; FP32
-    // stages all three at once, FP64 one after the other (a third of the LDS,
-    // so that LDS does not limit its occupancy)
+    // index through LDS: P1[t1][k3][k2], P2[t2][k3][k1], P3[t3][k2][k1], one
+    // after the other in the same 1024 entries (so that LDS does not limit
+    // the occupancy)
     auto stage = [&](int d, T* P) {
 #pragma unroll
         for (int b = 0; b < 4; ++b)
@@ -1552,36 +1538,24 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
     };
     T h1[4], h2[4], h3[4];
     __syncthreads();  // all G reads done; reuse the region for the partials
-    if (early) {
-        stage(0, sm);
-        stage(1, sm + 1024);
-        stage(2, sm + 2048);
-        __syncthreads();
-        reduce(sm, h1);
-        reduce(sm + 1024, h2);
-        reduce(sm + 2048, h3);
-    } else {
-        stage(0, sm);
-        __syncthreads();
-        reduce(sm, h1);
-        __syncthreads();
-        stage(1, sm);
-        __syncthreads();
-        reduce(sm, h2);
-        __syncthreads();
-        stage(2, sm);
-        __syncthreads();
-        reduce(sm, h3);
-    }
+    stage(0, sm);
+    __syncthreads();
+    reduce(sm, h1);
+    __syncthreads();
+    stage(1, sm);
+    __syncthreads();
+    reduce(sm, h2);
+    __syncthreads();
+    stage(2, sm);
+    __syncthreads();
+    reduce(sm, h3);
     // U1 = S3 (H1 S2^T), U2 = S3 (H2 S1^T), U3 = S2 (H3 S1^T)
-    if (!early) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int k = M::row(q, s);
-            Sa1[s] = S1[j * 16 + k];
-            Sa2[s] = S2[j * 16 + k];
-            Sa3[s] = S3[j * 16 + k];
-        }
+    for (int s = 0; s < 4; ++s) {
+        const int k = M::row(q, s);
+        Sa1[s] = S1[j * 16 + k];
+        Sa2[s] = S2[j * 16 + k];
+        Sa3[s] = S3[j * 16 + k];
     }
     v4_to<T>(gemm16<T>(h1, Sa2), t);
     v4 u1 = gemm16<T>(Sa3, t);
@@ -1590,7 +1564,7 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
     v4_to<T>(gemm16<T>(h3, Sa1), t);
     v4 u3 = gemm16<T>(Sa2, t);
     if (!active) return;
-    if (!early) load_w();
+    load_w();
     const int ob = j - c;
     if (inner) {
 #pragma unroll
