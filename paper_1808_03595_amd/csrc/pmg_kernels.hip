@@ -809,8 +809,9 @@ __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restri
 // contributions of all elements at each skeleton node.
 // ---------------------------------------------------------------------------
 // One wavefront per element, compile-time degree P: the element's 1D tables
-// (per direction one contiguous block m[n1] L[n1^2] Sinv[q^2] MS[q^2] lm[q]
-// c0[q] cp[q], tab_d entries) into `tabs`, and its six face tiles of u into
+// (in device memory per direction one contiguous block m[n1] L[n1^2]
+// Sinv[q^2] MS[q^2] lm[q] c0[q] cp[q]; in LDS the same without Sinv and MS,
+// which the face transforms read through the scalar cache) into `tabs`, and its six face tiles of u into
 // `tile` ([f][r][c], (p+1)^2 each; f = 2d + s, rows / columns along
 // tile_rdir(d) / tile_cdir(d)).  All global loads are issued before the first
 // LDS store, so their latencies overlap.  A tile is the (p+1) x (p+1) window
@@ -823,8 +824,8 @@ __device__ inline void tile_fill_rims(T* tile);
 template <typename T, int P>
 __device__ inline void stage_elem_pack_and_tiles(const LevelTabs<T>& tb, const int e[3], const T* __restrict__ u,
                                                  T* tabs, T* tile) {
-    constexpr int n1 = P + 1, q = P - 1, t2 = n1 * n1;
-    constexpr int TD0 = n1 + n1 * n1 + 2 * q * q + 3 * q, NTD = (TD0 + 63) / 64, NU = (t2 + 63) / 64;
+    constexpr int n1 = P + 1, q = P - 1, t2 = n1 * n1, NML = n1 + n1 * n1;
+    constexpr int TD0 = NML + 2 * q * q + 3 * q, TDL = NML + 3 * q, NTD = (TDL + 63) / 64, NU = (t2 + 63) / 64;
     const Layout& L = tb.lay;
     const int lane = threadIdx.x;
     T tv[3][NTD], uv[6][NU];
@@ -833,8 +834,8 @@ __device__ inline void stage_elem_pack_and_tiles(const LevelTabs<T>& tb, const i
         const T* src = tb.el_pack[d] + (size_t)e[d] * TD0;
 #pragma unroll
         for (int k = 0; k < NTD; ++k) {
-            const int i = lane + 64 * k;
-            tv[d][k] = i < TD0 ? src[i] : (T)0;
+            const int i = lane + 64 * k;   // LDS entry i: m and L, then lm, c0, cp
+            tv[d][k] = i < TDL ? src[i < NML ? i : i + 2 * q * q] : (T)0;
         }
     }
 #pragma unroll
@@ -852,7 +853,7 @@ __device__ inline void stage_elem_pack_and_tiles(const LevelTabs<T>& tb, const i
     for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int k = 0; k < NTD; ++k)
-            if (lane + 64 * k < TD0) tabs[d * TD0 + lane + 64 * k] = tv[d][k];
+            if (lane + 64 * k < TDL) tabs[d * TDL + lane + 64 * k] = tv[d][k];
 #pragma unroll
     for (int f = 0; f < 6; ++f)
 #pragma unroll
@@ -901,11 +902,11 @@ __device__ inline void tile_fill_rims(T* tile) {
 // holds (P - 1 each).  tabs and tile as staged by stage_elem_pack_and_tiles.
 template <typename T, int P>
 __device__ inline void k1_rims(const T* tabs, const T* tile, T lam, T* __restrict__ out) {
-    constexpr int n1 = P + 1, q = P - 1, t2 = n1 * n1, q2 = q * q;
-    constexpr int TD = n1 + n1 * n1 + 2 * q2 + 3 * q;
+    constexpr int n1 = P + 1, q = P - 1, t2 = n1 * n1;
+    constexpr int TDL = n1 + n1 * n1 + 3 * q;   // one direction's LDS tables
     const int lane = threadIdx.x;
-    auto Tm = [&](int d) { return tabs + d * TD; };
-    auto TL = [&](int d) { return tabs + d * TD + n1; };
+    auto Tm = [&](int d) { return tabs + d * TDL; };
+    auto TL = [&](int d) { return tabs + d * TDL + n1; };
     // canonical edge and vertex nodes: rims of the x1-faces (4P each) and
     // the two non-canonical-free rows of the x2-faces (P - 1 each)
     constexpr int nrim0 = 4 * P, nrim1 = 2 * (P - 1), nrim = 2 * nrim0 + 2 * nrim1;
@@ -951,26 +952,72 @@ __device__ inline void k1_rims(const T* tabs, const T* tile, T lam, T* __restric
     }
 }
 
+// Read-only tables seen through the constant address space: the compiler
+// may then read entries at wave-uniform addresses through the scalar cache
+// into scalar registers (the tables are not written while a kernel runs)
+template <typename T>
+using ctab_t = const __attribute__((address_space(4))) T*;
+
+// One 1D transform of the six q x q face arrays of the condensed operator's
+// element product, in[f * fs + row * rs + col] -> out[f][row][col] (q x q
+// each): along rows (ROWS: out[f][l][k] = sum_i A_f[k][i] in[f][l][i], A_f
+// of face f's column direction) or along columns (out[f][k][l] = sum_i
+// A_f[k][i] in[f][i][l], A_f of its row direction), A_f at offset off of the
+// element's packed table of that direction.  The faces go in two groups of
+// one direction each (rows: the x2- and x3-faces take x1, the x1-faces x2;
+// columns: the x1- and x2-faces take x3, the x3-faces x2), so that all lanes
+// of a group read the same entry of A_f at a time and A_f comes through the
+// scalar cache instead of LDS.
+template <typename T, int P, bool ROWS>
+__device__ inline void k1_face_tx(const LevelTabs<T>& tb, const int e[3], int off, const T* in, int fs, int rs,
+                                  T* out) {
+    constexpr int n1 = P + 1, q = P - 1, q2 = q * q, TD = n1 + n1 * n1 + 2 * q2 + 3 * q;
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        const int dir = ROWS ? (g == 0 ? 0 : 1) : (g == 0 ? 2 : 1);
+        const int f0 = ROWS ? (g == 0 ? 2 : 0) : (g == 0 ? 0 : 4), nf = g == 0 ? 4 : 2;
+        const T* base = dir == 0 ? tb.el_pack[0] + (size_t)e[0] * TD
+                                 : (dir == 1 ? tb.el_pack[1] + (size_t)e[1] * TD : tb.el_pack[2] + (size_t)e[2] * TD);
+        const ctab_t<T> A = (ctab_t<T>)(base + off);
+        for (int ii = lane; ii < nf * q; ii += 64) {
+            const int fl = ii / q, l = ii - fl * q, f = f0 + fl;
+            T x[q > 0 ? q : 1];
+#pragma unroll
+            for (int i = 0; i < q; ++i) x[i] = ROWS ? in[f * fs + l * rs + i] : in[f * fs + i * rs + l];
+#pragma unroll
+            for (int k = 0; k < q; ++k) {
+                T v = 0;
+#pragma unroll
+                for (int i = 0; i < q; ++i) v += A[k * q + i] * x[i];
+                out[ROWS ? f * q2 + l * q + k : f * q2 + k * q + l] = v;
+            }
+        }
+    }
+}
+
 template <int P>
 struct K1Shape {
     static constexpr int n1 = P + 1, q = P - 1, t2 = n1 * n1, q2 = q * q;
-    static constexpr int tab_d = n1 + n1 * n1 + 2 * q2 + 3 * q;       // one direction
-    static constexpr int tabs = 3 * tab_d;
+    static constexpr int tab_d = n1 + n1 * n1 + 2 * q2 + 3 * q;       // one direction in device memory
+    static constexpr int tab_l = n1 + n1 * n1 + 3 * q;                // one direction in LDS
+    static constexpr int tabs = 3 * tab_l;
     // One lane per face-interior row (6 (p - 1) <= 64): the row's shell part
     // and its first forward product stay in registers, so the tile is dead
     // after the first pass and G and V take its place in LDS
     static constexpr bool early = 6 * q <= 64;
-    // LDS layout (in elements of T): tables | tile | G | V, the tile region
-    // shared with G and V when early.  tmp shares V's region (the forward tmp
-    // is dead before V is written, V before the backward tmp), and Tc shares
-    // G's: the eigenspace pass reads G_0, G_1 only at its own lane's (k2, k3)
-    // before it writes Tc_0, Tc_1 there, G_2..G_5 are dead once it ends, and
-    // the corrections go to G after Tc has been read.  FP64 at p = 8: 10.1 KB
-    // per element, sixteen workgroups per CU
+    // LDS layout (in elements of T): tables | tile | G | V; when early,
+    // tables | tmp1 | tile, then G and V in the tile's place.  tmp1 is the
+    // first forward product (in V's region unless early, dead before V is
+    // written), tmp the backward one (in V's region, V being dead by then),
+    // and Tc shares G's: the eigenspace pass reads G_0, G_1 only at its own
+    // lane's (k2, k3) before it writes Tc_0, Tc_1 there, G_2..G_5 are dead
+    // once it ends, and the corrections go to G after Tc has been read.
+    // FP64 at p = 8: 10.1 KB per element, sixteen workgroups per CU
     static constexpr int vt = q * q2 > 6 * q2 ? q * q2 : 6 * q2;
-    static constexpr int o_tab = 0, o_tile = tabs, o_G = early ? tabs : o_tile + 6 * t2, o_V = o_G + 6 * q2,
-                         o_tmp = o_V, o_Tc = o_G,
-                         total = early ? tabs + (6 * t2 > 6 * q2 + vt ? 6 * t2 : 6 * q2 + vt) : o_V + vt;
+    static constexpr int o_tab = 0, o_tile = early ? tabs + 6 * q2 : tabs, o_G = early ? o_tile : o_tile + 6 * t2,
+                         o_V = o_G + 6 * q2, o_tmp = o_V, o_tmp1 = early ? tabs : o_V, o_Tc = o_G,
+                         total = early ? o_tile + (6 * t2 > 6 * q2 + vt ? 6 * t2 : 6 * q2 + vt) : o_V + vt;
 };
 
 template <typename T, int P>
@@ -983,6 +1030,7 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
     T* tile = sm + K::o_tile;
     T* G = sm + K::o_G;
     T* tmp = sm + K::o_tmp;
+    T* tmp1 = sm + K::o_tmp1;
     T* V = sm + K::o_V;
     T* Tc = sm + K::o_Tc;
     const Layout& L = tb.lay;
@@ -993,31 +1041,16 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
     const T lam = tb.lam;
     T* out = tb.opE + (size_t)eid * 6 * t2;
     stage_elem_pack_and_tiles<T, P>(tb, e, u, tabs, tile);
-    // table of direction d (runtime d: offsets, not a pointer array, so
-    // nothing is placed in private memory)
-    constexpr int TD = K::tab_d;
-    auto Tm = [&](int d) { return tabs + d * TD; };
-    auto TL = [&](int d) { return tabs + d * TD + n1; };
-    auto TSi = [&](int d) { return tabs + d * TD + n1 + n1 * n1; };
-    auto TMS = [&](int d) { return tabs + d * TD + n1 + n1 * n1 + q2; };
-    auto Tlm = [&](int d) { return tabs + d * TD + n1 + n1 * n1 + 2 * q2; };
-    auto Tc0 = [&](int d) { return tabs + d * TD + n1 + n1 * n1 + 2 * q2 + q; };
-    auto Tcp = [&](int d) { return tabs + d * TD + n1 + n1 * n1 + 2 * q2 + 2 * q; };
+    // LDS table of direction d (runtime d: offsets, not a pointer array, so
+    // nothing is placed in private memory); TD strides the packed tables in
+    // device memory
+    constexpr int TD = K::tab_d, TDL = K::tab_l;
+    auto Tm = [&](int d) { return tabs + d * TDL; };
+    auto TL = [&](int d) { return tabs + d * TDL + n1; };
+    auto Tlm = [&](int d) { return tabs + d * TDL + n1 + n1 * n1; };
+    auto Tc0 = [&](int d) { return tabs + d * TDL + n1 + n1 * n1 + q; };
+    auto Tcp = [&](int d) { return tabs + d * TDL + n1 + n1 * n1 + 2 * q; };
     constexpr int QR = q > 0 ? q : 1;
-    // tmp row r of face f: X_f Si_C^T (interior row r + 1 of the tile)
-    auto fwd_row = [&](int f, int r, T t[]) {
-        const T* Sc = TSi(tile_cdir(f >> 1));
-        T x[QR];
-#pragma unroll
-        for (int c = 0; c < q; ++c) x[c] = tile[f * t2 + (r + 1) * n1 + c + 1];
-#pragma unroll
-        for (int kc = 0; kc < q; ++kc) {
-            T s = 0;
-#pragma unroll
-            for (int c = 0; c < q; ++c) s += x[c] * Sc[kc * q + c];
-            t[kc] = s;
-        }
-    };
     // shell part H_BB u_B at face-interior node (r, c) (1..q) of face f,
     // row = the tile's row r: in-face lines stay in the tile, the normal line
     // meets the shell only at the two opposite faces
@@ -1041,50 +1074,29 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
 #pragma unroll
         for (int j = 0; j < n1; ++j) row[j] = tile[f * t2 + r * n1 + j];
     };
-    T hb[QR], t[QR];
-    if (K::early) {
-        if (lane < 6 * q) {
-            const int f = lane / q, r = lane - f * q;
-            T row[n1];
-            load_row(f, r + 1, row);
+    // the element's packed tables in device memory: entries that every
+    // lane reads at once (the eigenvalues and coupling vectors indexed by the
+    // loop, not the lane) come through the scalar cache instead of LDS
+    constexpr int OLM = n1 + n1 * n1 + 2 * q2;
+    typedef ctab_t<T> ctab;
+    const ctab gk0 = (ctab)(tb.el_pack[0] + (size_t)e[0] * TD + OLM);
+    const ctab gk1 = (ctab)(tb.el_pack[1] + (size_t)e[1] * TD + OLM);
+    const ctab gk2 = (ctab)(tb.el_pack[2] + (size_t)e[2] * TD + OLM);
+    T hb[QR];
+    if (K::early && lane < 6 * q) {
+        const int f = lane / q, r = lane - f * q;
+        T row[n1];
+        load_row(f, r + 1, row);
 #pragma unroll
-            for (int c = 1; c <= q; ++c) hb[c - 1] = shell_at(f, r + 1, c, row);
-            fwd_row(f, r, t);
-        }
-        k1_rims<T, P>(tabs, tile, lam, out);
-        __syncthreads();   // every tile read done: G and V may overwrite it
-        if (lane < 6 * q) {
-            const int f = lane / q, r = lane - f * q;
-#pragma unroll
-            for (int kc = 0; kc < q; ++kc) tmp[f * q2 + r * q + kc] = t[kc];
-        }
-        __syncthreads();
+        for (int c = 1; c <= q; ++c) hb[c - 1] = shell_at(f, r + 1, c, row);
     }
+    // tmp1_f = X_f Si_C^T (rows of the face interiors)
+    if (q > 0) k1_face_tx<T, P, true>(tb, e, n1 + n1 * n1, tile + n1 + 1, t2, n1, tmp1);
+    if (K::early) k1_rims<T, P>(tabs, tile, lam, out);
+    __syncthreads();   // when early, every tile read is done: G and V may overwrite it
     if (q > 0) {
-        if (!K::early) {
-            for (int ii = lane; ii < 6 * q; ii += 64) {
-                const int f = ii / q, r = ii - f * q;
-                fwd_row(f, r, t);
-#pragma unroll
-                for (int kc = 0; kc < q; ++kc) tmp[f * q2 + r * q + kc] = t[kc];
-            }
-            __syncthreads();
-        }
-        // G_f = Si_R tmp_f (lane: face f, column kc)
-        for (int ii = lane; ii < 6 * q; ii += 64) {
-            const int f = ii / q, kc = ii - f * q;
-            const T* Sr = TSi(tile_rdir(f >> 1));
-            T x[q > 0 ? q : 1];
-#pragma unroll
-            for (int r = 0; r < q; ++r) x[r] = tmp[f * q2 + r * q + kc];
-#pragma unroll
-            for (int kr = 0; kr < q; ++kr) {
-                T s = 0;
-#pragma unroll
-                for (int r = 0; r < q; ++r) s += Sr[kr * q + r] * x[r];
-                G[f * q2 + kr * q + kc] = s;
-            }
-        }
+        // G_f = Si_R tmp1_f (columns of tmp1)
+        k1_face_tx<T, P, false>(tb, e, n1 + n1 * n1, tmp1, q2, q, G);
         __syncthreads();
         // V over the (k2, k3) line of lane; x1-contractions on the fly
         for (int ii = lane; ii < q2; ii += 64) {
@@ -1095,12 +1107,13 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
             T s0 = 0, sp = 0;
 #pragma unroll
             for (int k1 = 0; k1 < q; ++k1) {
-                T v = Tc0(0)[k1] * g0 + Tcp(0)[k1] * g1 + a1 * G[2 * q2 + k3 * q + k1] +
+                const T c0k = gk0[q + k1], cpk = gk0[2 * q + k1];
+                T v = c0k * g0 + cpk * g1 + a1 * G[2 * q2 + k3 * q + k1] +
                       b1 * G[3 * q2 + k3 * q + k1] + a2 * G[4 * q2 + k2 * q + k1] + b2 * G[5 * q2 + k2 * q + k1];
-                v = v * recip(dd + Tlm(0)[k1]);
+                v = v * recip(dd + gk0[k1]);
                 V[(k3 * q + k2) * q + k1] = v;
-                s0 += Tc0(0)[k1] * v;
-                sp += Tcp(0)[k1] * v;
+                s0 += c0k * v;
+                sp += cpk * v;
             }
             Tc[0 * q2 + k3 * q + k2] = s0;
             Tc[1 * q2 + k3 * q + k2] = sp;
@@ -1114,52 +1127,26 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
 #pragma unroll
                 for (int k = 0; k < q; ++k) {
                     const T v = V[(r * q + k) * q + c];
-                    s0 += Tc0(1)[k] * v;
-                    sp += Tcp(1)[k] * v;
+                    s0 += gk1[q + k] * v;
+                    sp += gk1[2 * q + k] * v;
                 }
             } else {                // d = 2: (r, c) = (k2, k1), sum over k3
 #pragma unroll
                 for (int k = 0; k < q; ++k) {
                     const T v = V[(k * q + r) * q + c];
-                    s0 += Tc0(2)[k] * v;
-                    sp += Tcp(2)[k] * v;
+                    s0 += gk2[q + k] * v;
+                    sp += gk2[2 * q + k] * v;
                 }
             }
             Tc[(2 + 2 * dm) * q2 + rc] = s0;
             Tc[(3 + 2 * dm) * q2 + rc] = sp;
         }
         __syncthreads();
-        // tmp_f = Tc_f MS_C^T (lane: face f, row kr)
-        for (int ii = lane; ii < 6 * q; ii += 64) {
-            const int f = ii / q, kr = ii - f * q;
-            const T* Mc = TMS(tile_cdir(f >> 1));
-            T x[q > 0 ? q : 1];
-#pragma unroll
-            for (int kc = 0; kc < q; ++kc) x[kc] = Tc[f * q2 + kr * q + kc];
-#pragma unroll
-            for (int c = 0; c < q; ++c) {
-                T s = 0;
-#pragma unroll
-                for (int kc = 0; kc < q; ++kc) s += x[kc] * Mc[c * q + kc];
-                tmp[f * q2 + kr * q + c] = s;
-            }
-        }
+        // tmp_f = Tc_f MS_C^T (rows of Tc)
+        k1_face_tx<T, P, true>(tb, e, n1 + n1 * n1 + q2, Tc, q2, q, tmp);
         __syncthreads();
-        // corr_f = MS_R tmp_f, stored in G (lane: face f, column c)
-        for (int ii = lane; ii < 6 * q; ii += 64) {
-            const int f = ii / q, c = ii - f * q;
-            const T* Mr = TMS(tile_rdir(f >> 1));
-            T x[q > 0 ? q : 1];
-#pragma unroll
-            for (int kr = 0; kr < q; ++kr) x[kr] = tmp[f * q2 + kr * q + c];
-#pragma unroll
-            for (int r = 0; r < q; ++r) {
-                T s = 0;
-#pragma unroll
-                for (int kr = 0; kr < q; ++kr) s += Mr[r * q + kr] * x[kr];
-                G[f * q2 + r * q + c] = s;
-            }
-        }
+        // corr_f = MS_R tmp_f (columns of tmp), stored in G
+        k1_face_tx<T, P, false>(tb, e, n1 + n1 * n1 + q2, tmp, q2, q, G);
         __syncthreads();
     }
     if (K::early) {
