@@ -221,6 +221,25 @@ int fill_tabs(pmg_mesh* m, LevelTabs<T>& tb, const HostTables& t, const Layout& 
                 if (sz[k] && src[k]->size() >= (e + 1) * sz[k])
                     pack.insert(pack.end(), src[k]->begin() + e * sz[k], src[k]->begin() + (e + 1) * sz[k]);
         if ((rc = m->upload(&tb.el_pack[d], pack))) break;
+        // per element S^T then S (each the division the condensation and
+        // recovery would otherwise do per element on the device)
+        std::vector<double> st;
+        if (q > 0 && t.el_Sinv[d].size() >= (size_t)ne * q * q && t.el_MS[d].size() >= (size_t)ne * q * q &&
+            t.el_m[d].size() >= (size_t)ne * n1) {
+            st.resize((size_t)ne * 2 * q * q);
+            for (int e = 0; e < ne; ++e) {
+                const double* mm = t.el_m[d].data() + (size_t)e * n1;
+                const double* si = t.el_Sinv[d].data() + (size_t)e * q * q;
+                const double* ms = t.el_MS[d].data() + (size_t)e * q * q;
+                double* o = st.data() + (size_t)e * 2 * q * q;
+                for (int r = 0; r < q; ++r)
+                    for (int c = 0; c < q; ++c) {
+                        o[r * q + c] = si[r * q + c] / mm[c + 1];
+                        o[q * q + r * q + c] = ms[r * q + c] / mm[r + 1];
+                    }
+            }
+        }
+        if ((rc = m->upload(&tb.el_st[d], st))) break;
     }
     if (!rc) rc = m->upload(&tb.st_wP, t.st_wP);
     if (!rc) rc = m->upload(&tb.st_w, t.st_w);

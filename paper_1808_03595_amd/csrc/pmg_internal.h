@@ -80,6 +80,11 @@ struct LevelTabs {
     // MS, lam, c0, cp): one contiguous block of elem_table_size(p) / 3
     // entries per direction and element
     const T* el_pack[3];
+    // per direction and element the interior eigenvector matrices in the
+    // orientations the condensation and recovery apply: S^T = Sinv M_I^-1
+    // ([k][i] = Sinv[k][i] / m_{i+1}), then S = (M_I S) M_I^-1 ([i][k] =
+    // MS[i][k] / m_{i+1}); 2 (p-1)^2 entries per element
+    const T* el_st[3];
     // star tables, direction d, vertex v: offsets v * size
     const T* st_S[3];     // nS^2         [i][k], identity padded
     const T* st_lam[3];   // nS           padded eigenvalues = 1

@@ -958,9 +958,8 @@ __device__ inline void k1_rims(const T* tabs, const T* tile, T lam, T* __restric
 template <typename T>
 using ctab_t = const __attribute__((address_space(4))) T*;
 
-// One 1D transform of the six q x q face arrays of the condensed operator's
-// element product, in[f * fs + row * rs + col] -> out[f][row][col] (q x q
-// each): along rows (ROWS: out[f][l][k] = sum_i A_f[k][i] in[f][l][i], A_f
+// One 1D transform of six q x q face arrays, in[f * fs + row * rs + col] ->
+// out[f * ofs + row * ors + col]: along rows (ROWS: out[f][l][k] = sum_i A_f[k][i] in[f][l][i], A_f
 // of face f's column direction) or along columns (out[f][k][l] = sum_i
 // A_f[k][i] in[f][i][l], A_f of its row direction), A_f at offset off of the
 // element's packed table of that direction.  The faces go in two groups of
@@ -970,7 +969,7 @@ using ctab_t = const __attribute__((address_space(4))) T*;
 // scalar cache instead of LDS.
 template <typename T, int P, bool ROWS>
 __device__ inline void k1_face_tx(const LevelTabs<T>& tb, const int e[3], int off, const T* in, int fs, int rs,
-                                  T* out) {
+                                  T* out, int ofs, int ors) {
     constexpr int n1 = P + 1, q = P - 1, q2 = q * q, TD = n1 + n1 * n1 + 2 * q2 + 3 * q;
     const int lane = threadIdx.x;
 #pragma unroll
@@ -990,7 +989,7 @@ __device__ inline void k1_face_tx(const LevelTabs<T>& tb, const int e[3], int of
                 T v = 0;
 #pragma unroll
                 for (int i = 0; i < q; ++i) v += A[k * q + i] * x[i];
-                out[ROWS ? f * q2 + l * q + k : f * q2 + k * q + l] = v;
+                out[ROWS ? f * ofs + l * ors + k : f * ofs + k * ors + l] = v;
             }
         }
     }
@@ -1091,12 +1090,12 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
         for (int c = 1; c <= q; ++c) hb[c - 1] = shell_at(f, r + 1, c, row);
     }
     // tmp1_f = X_f Si_C^T (rows of the face interiors)
-    if (q > 0) k1_face_tx<T, P, true>(tb, e, n1 + n1 * n1, tile + n1 + 1, t2, n1, tmp1);
+    if (q > 0) k1_face_tx<T, P, true>(tb, e, n1 + n1 * n1, tile + n1 + 1, t2, n1, tmp1, q2, q);
     if (K::early) k1_rims<T, P>(tabs, tile, lam, out);
     __syncthreads();   // when early, every tile read is done: G and V may overwrite it
     if (q > 0) {
         // G_f = Si_R tmp1_f (columns of tmp1)
-        k1_face_tx<T, P, false>(tb, e, n1 + n1 * n1, tmp1, q2, q, G);
+        k1_face_tx<T, P, false>(tb, e, n1 + n1 * n1, tmp1, q2, q, G, q2, q);
         __syncthreads();
         // V over the (k2, k3) line of lane; x1-contractions on the fly
         for (int ii = lane; ii < q2; ii += 64) {
@@ -1143,10 +1142,10 @@ __global__ void __launch_bounds__(64) k_condensed_op_w(LevelTabs<T> tb, const T*
         }
         __syncthreads();
         // tmp_f = Tc_f MS_C^T (rows of Tc)
-        k1_face_tx<T, P, true>(tb, e, n1 + n1 * n1 + q2, Tc, q2, q, tmp);
+        k1_face_tx<T, P, true>(tb, e, n1 + n1 * n1 + q2, Tc, q2, q, tmp, q2, q);
         __syncthreads();
         // corr_f = MS_R tmp_f (columns of tmp), stored in G
-        k1_face_tx<T, P, false>(tb, e, n1 + n1 * n1 + q2, tmp, q2, q, G);
+        k1_face_tx<T, P, false>(tb, e, n1 + n1 * n1 + q2, tmp, q2, q, G, q2, q);
         __syncthreads();
     }
     if (K::early) {
@@ -3053,16 +3052,16 @@ __global__ void __launch_bounds__(256) k_recover(LevelTabs<double> tb, const dou
 // ---------------------------------------------------------------------------
 // Condensation F_hat -= H_BI H_II^-1 F_I and recovery u_I = H_II^-1 (F_I -
 // H_IB u_hat) (Alg. 4, first and last steps) for 3 <= p <= 8: one wavefront
-// per element, compile-time degree.  The element's 1D tables go to LDS
-// without the stiffness matrices L, which neither step uses, and with the
-// interior eigenvector matrices in the orientation each step needs, S^T =
-// Sinv M_I^-1 (forward) in place of Sinv and S = (M_I S) M_I^-1 (backward,
-// recovery) in place of M_I S, so that no division is left in the
-// transforms.  Each 1D pass of the three-dimensional transforms gives one
-// lane one line of the element, held in registers, and writes it back in
-// place; the 2D face transforms hold their rows or columns in registers
-// across a barrier and write over the array they read.  LDS per element at
-// p = 8: 8.2 KB (condensation), 9.7 KB (recovery).
+// per element, compile-time degree.  The 1D interior eigenvector matrices,
+// S^T = Sinv M_I^-1 and S = (M_I S) M_I^-1 for the 3D interior transforms
+// (set up on the host, so no division is left in them) and Sinv and M_I S
+// for the 2D face transforms, are read from device memory as constant
+// memory: each 1D pass gives every lane the same matrix entry at a time, so
+// they come through the scalar cache instead of LDS.  LDS holds the masses,
+// eigenvalues and coupling vectors, the element's interior array, the face
+// transforms' scratch and (recovery) the face tiles.  Each 1D pass of the
+// three-dimensional transforms gives one lane one line of the element, held
+// in registers, and writes it back in place.
 // ---------------------------------------------------------------------------
 template <int P>
 struct CRShape {
@@ -3070,43 +3069,36 @@ struct CRShape {
     // per direction the packed tables in device memory: m[n1] L[n1^2] Si[q2] MS[q2] lm[q] c0[q] cp[q]
     static constexpr int o_m = 0, o_L = n1, o_Si = o_L + n1 * n1, o_MS = o_Si + q2, o_lm = o_MS + q2,
                          o_c0 = o_lm + q, o_cp = o_c0 + q, tab_d = o_cp + q;
-    // per direction in LDS (L left out): m[n1] A[q2] B[q2] lm[q] c0[q] cp[q]
-    // with A = S^T and B = S (recovery) or M_I S (condensation)
-    static constexpr int l_m = 0, l_A = n1, l_B = l_A + q2, l_lm = l_B + q2, l_c0 = l_lm + q, l_cp = l_c0 + q,
-                         lt_d = l_cp + q, ltabs = 3 * lt_d;
-    // condensation: tables | a[q3] | Tc, then tmp [6 q2]
-    static constexpr int o_a = ltabs, o_Tc = o_a + q3, cond_total = o_Tc + 6 * q2;
-    // recovery: tables | a[q3] | tile, then tmp, then G [6 t2]
-    static constexpr int o_rtile = o_a + q3, rec_total = o_rtile + 6 * t2;
-    static_assert(6 * q <= 64 && q2 <= 64, "one lane per face row and per interior line");
+    // per direction in LDS: m[n1] lm[q] c0[q] cp[q]
+    static constexpr int l_m = 0, l_lm = n1, l_c0 = l_lm + q, l_cp = l_c0 + q, lt_d = l_cp + q, ltabs = 3 * lt_d;
+    // condensation: tables | a[q3] | Tc[6 q2] | tmp[6 q2], tmp in a's place
+    // where it fits (p >= 7; a is dead once the contractions have read it)
+    static constexpr bool tmp_in_a = 6 * q2 <= q3;
+    static constexpr int o_a = ltabs, o_Tc = o_a + q3, o_ctmp = tmp_in_a ? o_a : o_Tc + 6 * q2,
+                         cond_total = tmp_in_a ? o_Tc + 6 * q2 : o_ctmp + 6 * q2;
+    // recovery: tables | a[q3] | tmp[6 q2] | tile, then G [6 t2]
+    static constexpr int o_rtmp = o_a + q3, o_rtile = o_rtmp + 6 * q2, rec_total = o_rtile + 6 * t2;
+    static_assert(q2 <= 64, "one lane per interior line");
 };
 
-// The element's tables into LDS in the CRShape layout, A = Si / m (columns)
-// and B = MS / m (rows) if SB, else B = MS; with TILES also the six face
-// tiles of uh (as for the condensed operator).  All global loads are issued
-// before the first LDS store.  Ends with a barrier.
-template <int P, bool SB, bool TILES>
+// The element's LDS tables (CRShape layout) and with TILES its six face tiles
+// of uh (as for the condensed operator).  All global loads are issued before
+// the first LDS store.  Ends with a barrier.
+template <int P, bool TILES>
 __device__ inline void cr_stage(const LevelTabs<double>& tb, const int e[3], const double* __restrict__ uh,
                                 double* tabs, double* tile) {
     using K = CRShape<P>;
-    constexpr int n1 = K::n1, q = K::q, q2 = K::q2, t2 = K::t2, LT = K::lt_d, NLT = (LT + 63) / 64,
-                  NU = (t2 + 63) / 64;
+    constexpr int n1 = K::n1, q = K::q, t2 = K::t2, LT = K::lt_d, NLT = (LT + 63) / 64, NU = (t2 + 63) / 64;
     const Layout& L = tb.lay;
     const int lane = threadIdx.x;
-    double tv[3][NLT], dv[3][NLT], uv[6][TILES ? NU : 1];
+    double tv[3][NLT], uv[6][TILES ? NU : 1];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const double* src = tb.el_pack[d] + (size_t)e[d] * K::tab_d;
 #pragma unroll
         for (int k = 0; k < NLT; ++k) {
-            const int i = lane + 64 * k;
-            // LDS entry i: m, then everything after L
-            tv[d][k] = i < LT ? src[i < n1 ? i : i + n1 * n1] : 0.0;
-            // the divisor of an A or B entry: m at its interior column (A) or row (B)
-            int dm = -1;
-            if (i >= K::l_A && i < K::l_B) dm = (i - K::l_A) % q;
-            else if (SB && i >= K::l_B && i < K::l_lm) dm = (i - K::l_B) / q;
-            dv[d][k] = dm >= 0 ? src[K::o_m + dm + 1] : 1.0;
+            const int i = lane + 64 * k;   // LDS entry i: m, then lm, c0, cp
+            tv[d][k] = i < LT ? src[i < n1 ? i : i - n1 + K::o_lm] : 0.0;
         }
     }
     if (TILES) {
@@ -3126,7 +3118,7 @@ __device__ inline void cr_stage(const LevelTabs<double>& tb, const int e[3], con
     for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int k = 0; k < NLT; ++k)
-            if (lane + 64 * k < LT) tabs[d * LT + lane + 64 * k] = tv[d][k] / dv[d][k];
+            if (lane + 64 * k < LT) tabs[d * LT + lane + 64 * k] = tv[d][k];
     if (TILES) {
 #pragma unroll
         for (int f = 0; f < 6; ++f)
@@ -3139,22 +3131,24 @@ __device__ inline void cr_stage(const LevelTabs<double>& tb, const int e[3], con
 }
 
 // Three in-place 1D passes of a separable transform of the q^3 array x
-// (layout [i3][i2][i1]): out[k] = sum_i A_d[k][i] in[i] with A_d the A
-// (FWD) or B matrix of direction d.
+// (layout [i3][i2][i1]): out[k] = sum_i A_d[k][i] in[i] with A_d = S_d^T
+// (FWD) or S_d of the element in direction d (scalar cache).
 template <int P, bool FWD>
-__device__ inline void cr_transform3(const double* tabs, double* x) {
+__device__ inline void cr_transform3(const LevelTabs<double>& tb, const int e[3], double* x) {
     using K = CRShape<P>;
-    constexpr int q = K::q, q2 = K::q2, LT = K::lt_d, OA = FWD ? K::l_A : K::l_B;
+    constexpr int q = K::q, q2 = K::q2;
     const int lane = threadIdx.x;
     // pass d: lane (j0, j1) = (lane % q, lane / q) takes the line along x_d
     // through the other two indices; element i of the line sits at
     // base + i * stride
     auto pass = [&](int d) {
+        const double* st = d == 0 ? tb.el_st[0] + (size_t)e[0] * 2 * q2
+                                  : (d == 1 ? tb.el_st[1] + (size_t)e[1] * 2 * q2 : tb.el_st[2] + (size_t)e[2] * 2 * q2);
+        const ctab_t<double> A = (ctab_t<double>)(st + (FWD ? 0 : q2));
         if (lane < q2) {
             const int j0 = lane % q, j1 = lane / q;
             const int base = d == 0 ? lane * q : (d == 1 ? j1 * q2 + j0 : lane);
             const int stride = d == 0 ? 1 : (d == 1 ? q : q2);
-            const double* A = tabs + d * LT + OA;
             double v[q];
 #pragma unroll
             for (int i = 0; i < q; ++i) v[i] = x[base + i * stride];
@@ -3190,26 +3184,28 @@ __device__ inline void cr_load_interior(const Layout& L, const int e[3], const d
 template <int P>
 __global__ void __launch_bounds__(64) k_condense_w(LevelTabs<double> tb, const double* __restrict__ f) {
     using K = CRShape<P>;
-    constexpr int n1 = K::n1, q = K::q, q2 = K::q2, t2 = K::t2, LT = K::lt_d;
+    constexpr int n1 = K::n1, q = K::q, q2 = K::q2, t2 = K::t2, LT = K::lt_d, TD = K::tab_d;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* sm = reinterpret_cast<double*>(smem_raw);
     double* tabs = sm;
     double* a = sm + K::o_a;
     double* Tc = sm + K::o_Tc;
-    double* tmp = Tc;   // after Tc has been read into registers
+    double* tmp = sm + K::o_ctmp;
     const Layout& L = tb.lay;
     const int lane = threadIdx.x;
     const int eid = xcd_remap(blockIdx.x, gridDim.x);
     int e[3];
     color_coords(eid, -1, L.n, e);
-    cr_stage<P, false, false>(tb, e, nullptr, tabs, nullptr);
+    cr_stage<P, false>(tb, e, nullptr, tabs, nullptr);
     cr_load_interior<P>(L, e, tabs, f, a);
     __syncthreads();
-    cr_transform3<P, true>(tabs, a);           // a = (S x S x S)^T F_I
+    cr_transform3<P, true>(tb, e, a);          // a = (S x S x S)^T F_I
     const double lam = tb.lam;
     auto lm = [&](int d) { return tabs + d * LT + K::l_lm; };
-    auto c0 = [&](int d) { return tabs + d * LT + K::l_c0; };
-    auto cp = [&](int d) { return tabs + d * LT + K::l_cp; };
+    // the eigenvalues and coupling vectors of x1 indexed by the loop (scalar cache)
+    const ctab_t<double> g0 = (ctab_t<double>)(tb.el_pack[0] + (size_t)e[0] * TD + K::o_lm);
+    const ctab_t<double> g1 = (ctab_t<double>)(tb.el_pack[1] + (size_t)e[1] * TD + K::o_lm);
+    const ctab_t<double> g2 = (ctab_t<double>)(tb.el_pack[2] + (size_t)e[2] * TD + K::o_lm);
     // V = a / D, in place, with the x1-contractions on the fly (lane: (k2, k3))
     if (lane < q2) {
         const int k2 = lane % q, k3 = lane / q;
@@ -3217,10 +3213,10 @@ __global__ void __launch_bounds__(64) k_condense_w(LevelTabs<double> tb, const d
         double s0 = 0.0, sp = 0.0;
 #pragma unroll
         for (int k1 = 0; k1 < q; ++k1) {
-            const double v = a[lane * q + k1] * recip(dd + lm(0)[k1]);
+            const double v = a[lane * q + k1] * recip(dd + g0[k1]);
             a[lane * q + k1] = v;
-            s0 += c0(0)[k1] * v;
-            sp += cp(0)[k1] * v;
+            s0 += g0[q + k1] * v;
+            sp += g0[2 * q + k1] * v;
         }
         Tc[0 * q2 + k3 * q + k2] = s0;
         Tc[1 * q2 + k3 * q + k2] = sp;
@@ -3234,60 +3230,27 @@ __global__ void __launch_bounds__(64) k_condense_w(LevelTabs<double> tb, const d
 #pragma unroll
             for (int k = 0; k < q; ++k) {
                 const double v = a[(r * q + k) * q + c];
-                s0 += c0(1)[k] * v;
-                sp += cp(1)[k] * v;
+                s0 += g1[q + k] * v;
+                sp += g1[2 * q + k] * v;
             }
         } else {                // (r, c) = (k2, k1), sum over k3
 #pragma unroll
             for (int k = 0; k < q; ++k) {
                 const double v = a[(k * q + r) * q + c];
-                s0 += c0(2)[k] * v;
-                sp += cp(2)[k] * v;
+                s0 += g2[q + k] * v;
+                sp += g2[2 * q + k] * v;
             }
         }
         Tc[(2 + 2 * dm) * q2 + rc] = s0;
         Tc[(3 + 2 * dm) * q2 + rc] = sp;
     }
     __syncthreads();
-    // corr_f = MS_R Tc_f MS_C^T: rows (lane: face f, row kr) into registers,
-    // then over Tc as tmp; columns (lane: face f, column c) straight out
-    double t[q];
-    if (lane < 6 * q) {
-        const int fc = lane / q, kr = lane - fc * q;
-        const double* Mc = tabs + tile_cdir(fc >> 1) * LT + K::l_B;
-        double x[q];
-#pragma unroll
-        for (int kc = 0; kc < q; ++kc) x[kc] = Tc[fc * q2 + kr * q + kc];
-#pragma unroll
-        for (int c = 0; c < q; ++c) {
-            double s = 0.0;
-#pragma unroll
-            for (int kc = 0; kc < q; ++kc) s += x[kc] * Mc[c * q + kc];
-            t[c] = s;
-        }
-    }
-    __syncthreads();
-    if (lane < 6 * q) {
-        const int fc = lane / q, kr = lane - fc * q;
-#pragma unroll
-        for (int c = 0; c < q; ++c) tmp[fc * q2 + kr * q + c] = t[c];
-    }
-    __syncthreads();
+    // corr_f = MS_R Tc_f MS_C^T: rows of Tc into tmp, then the columns of
+    // tmp straight into the face tiles of the workspace
     double* out = tb.opE + (size_t)eid * 6 * t2;
-    if (lane < 6 * q) {
-        const int fc = lane / q, c = lane - fc * q;
-        const double* Mr = tabs + tile_rdir(fc >> 1) * LT + K::l_B;
-        double x[q];
-#pragma unroll
-        for (int kr = 0; kr < q; ++kr) x[kr] = tmp[fc * q2 + kr * q + c];
-#pragma unroll
-        for (int r = 0; r < q; ++r) {
-            double s = 0.0;
-#pragma unroll
-            for (int kr = 0; kr < q; ++kr) s += Mr[r * q + kr] * x[kr];
-            out[fc * t2 + (r + 1) * n1 + c + 1] = s;
-        }
-    }
+    k1_face_tx<double, P, true>(tb, e, K::o_MS, Tc, q2, q, tmp, q2, q);
+    __syncthreads();
+    k1_face_tx<double, P, false>(tb, e, K::o_MS, tmp, q2, q, out + n1 + 1, t2, n1);
     // the rims of the six tiles carry no correction
     constexpr int nrim = 6 * 4 * P;
     for (int i = lane; i < nrim; i += 64) {
@@ -3305,20 +3268,20 @@ template <int P>
 __global__ void __launch_bounds__(64) k_recover_w(LevelTabs<double> tb, const double* __restrict__ f,
                                                   const double* __restrict__ uh, double* __restrict__ ug) {
     using K = CRShape<P>;
-    constexpr int n1 = K::n1, q = K::q, q2 = K::q2, t2 = K::t2, LT = K::lt_d;
+    constexpr int n1 = K::n1, q = K::q, q2 = K::q2, t2 = K::t2, LT = K::lt_d, TD = K::tab_d;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* sm = reinterpret_cast<double*>(smem_raw);
     double* tabs = sm;
     double* a = sm + K::o_a;
+    double* tmp = sm + K::o_rtmp;
     double* tile = sm + K::o_rtile;
-    double* tmp = tile;   // after the face rows have been read into registers
-    double* G = tile;     // after the columns of tmp have been read
+    double* G = tile;     // after the face rows have been transformed into tmp
     const Layout& L = tb.lay;
     const int lane = threadIdx.x;
     const int eid = xcd_remap(blockIdx.x, gridDim.x);
     int e[3];
     color_coords(eid, -1, L.n, e);
-    cr_stage<P, true, true>(tb, e, uh, tabs, tile);
+    cr_stage<P, true>(tb, e, uh, tabs, tile);
     cr_load_interior<P>(L, e, tabs, f, a);
     // shell nodes owned by this element: a_d < p, or a_d = p on the last element
     for (int i = lane; i < n1 * n1 * n1; i += 64) {
@@ -3331,76 +3294,31 @@ __global__ void __launch_bounds__(64) k_recover_w(LevelTabs<double> tb, const do
         ug[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1] =
             is_dir(L, i1, i2, i3) ? 0.0 : shell_value(tile, P, a1, a2, a3);
     }
+    // G_f = Si_R X_f Si_C^T on the face interiors: rows of the tile into tmp
+    k1_face_tx<double, P, true>(tb, e, K::o_Si, tile + n1 + 1, t2, n1, tmp, q2, q);
     __syncthreads();
-    cr_transform3<P, true>(tabs, a);           // a = (S x S x S)^T F_I
-    // G_f = Si_R X_f Si_C^T = S^T_R (m_R m_C X_f) S^T_C^T on the face
-    // interiors: rows (lane: face f, row r) into registers, over the tile as
-    // tmp; columns (lane: face f, column kc) into registers, over tmp as G
-    double t[q];
-    if (lane < 6 * q) {
-        const int fc = lane / q, r = lane - fc * q, d = fc >> 1, dr = tile_rdir(d), dc = tile_cdir(d);
-        const double* Sc = tabs + dc * LT + K::l_A;
-        const double mr = tabs[dr * LT + K::l_m + r + 1];
-        double x[q];
-#pragma unroll
-        for (int c = 0; c < q; ++c) x[c] = mr * tabs[dc * LT + K::l_m + c + 1] * tile[fc * t2 + (r + 1) * n1 + c + 1];
-#pragma unroll
-        for (int kc = 0; kc < q; ++kc) {
-            double s = 0.0;
-#pragma unroll
-            for (int c = 0; c < q; ++c) s += x[c] * Sc[kc * q + c];
-            t[kc] = s;
-        }
-    }
-    __syncthreads();
-    if (lane < 6 * q) {
-        const int fc = lane / q, r = lane - fc * q;
-#pragma unroll
-        for (int kc = 0; kc < q; ++kc) tmp[fc * q2 + r * q + kc] = t[kc];
-    }
-    __syncthreads();
-    if (lane < 6 * q) {
-        const int fc = lane / q, kc = lane - fc * q;
-        const double* Sr = tabs + tile_rdir(fc >> 1) * LT + K::l_A;
-        double x[q];
-#pragma unroll
-        for (int r = 0; r < q; ++r) x[r] = tmp[fc * q2 + r * q + kc];
-#pragma unroll
-        for (int kr = 0; kr < q; ++kr) {
-            double s = 0.0;
-#pragma unroll
-            for (int r = 0; r < q; ++r) s += Sr[kr * q + r] * x[r];
-            t[kr] = s;
-        }
-    }
-    __syncthreads();
-    if (lane < 6 * q) {
-        const int fc = lane / q, kc = lane - fc * q;
-#pragma unroll
-        for (int kr = 0; kr < q; ++kr) G[fc * q2 + kr * q + kc] = t[kr];
-    }
+    cr_transform3<P, true>(tb, e, a);          // a = (S x S x S)^T F_I
+    k1_face_tx<double, P, false>(tb, e, K::o_Si, tmp, q2, q, G, q2, q);   // columns of tmp, over the tile
     __syncthreads();
     // V = (a - sum_f c_f (x) G_f) / D in place (lane: (k2, k3) line)
     const double lam = tb.lam;
+    const ctab_t<double> g0 = (ctab_t<double>)(tb.el_pack[0] + (size_t)e[0] * TD + K::o_lm);
     if (lane < q2) {
         const int k2 = lane % q, k3 = lane / q;
-        const double* lm0 = tabs + K::l_lm;
-        const double* c00 = tabs + K::l_c0;
-        const double* cp0 = tabs + K::l_cp;
-        const double g0 = G[0 * q2 + k3 * q + k2], g1 = G[1 * q2 + k3 * q + k2];
+        const double g0v = G[0 * q2 + k3 * q + k2], g1v = G[1 * q2 + k3 * q + k2];
         const double a1 = tabs[LT + K::l_c0 + k2], b1 = tabs[LT + K::l_cp + k2];
         const double a2 = tabs[2 * LT + K::l_c0 + k3], b2 = tabs[2 * LT + K::l_cp + k3];
         const double dd = lam + tabs[LT + K::l_lm + k2] + tabs[2 * LT + K::l_lm + k3];
 #pragma unroll
         for (int k1 = 0; k1 < q; ++k1) {
-            const double ex = c00[k1] * g0 + cp0[k1] * g1 + a1 * G[2 * q2 + k3 * q + k1] +
+            const double ex = g0[q + k1] * g0v + g0[2 * q + k1] * g1v + a1 * G[2 * q2 + k3 * q + k1] +
                               b1 * G[3 * q2 + k3 * q + k1] + a2 * G[4 * q2 + k2 * q + k1] +
                               b2 * G[5 * q2 + k2 * q + k1];
-            a[lane * q + k1] = (a[lane * q + k1] - ex) * recip(dd + lm0[k1]);
+            a[lane * q + k1] = (a[lane * q + k1] - ex) * recip(dd + g0[k1]);
         }
     }
     __syncthreads();
-    cr_transform3<P, false>(tabs, a);          // u_I = (S x S x S) V
+    cr_transform3<P, false>(tb, e, a);          // u_I = (S x S x S) V
     for (int i = lane; i < K::q3; i += 64) {
         const int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
         const int i1 = e[0] * P + 1 + k1, i2 = e[1] * P + 1 + k2, i3 = e[2] * P + 1 + k3;
