@@ -729,71 +729,86 @@ __global__ void __launch_bounds__(256) k_rec_big_shell(LevelTabs<T> tb, const T*
 // contain it (or F minus that sum, the residual, when F is given), every
 // other slot zero.  With `sub`, y -= sum at those nodes and every other
 // slot is left as it is.  Deterministic, no atomics.
-// Grid: x over columns (64 per block), y over rows (4 per block, the plane's
-// padding rows included), z over the planes of all three families.
+// Grid: x over columns (64 per block), y over rows (8 per block, the plane's
+// padding rows included: each thread takes two rows of its column, their
+// loads issued before either sum, measured 111.4 -> 106.6 us per FP32
+// product at 32^3, p = 8), z over the planes of all three families.
 template <typename T, int P>
 __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restrict__ E, const T* __restrict__ F,
                                                      T* __restrict__ y, int sub) {
     const int z = blockIdx.z;
     const int d = z >= L.n[0] + L.n[1] + 2 ? 2 : (z >= L.n[0] + 1 ? 1 : 0);
     const int j = z - (d == 0 ? 0 : (d == 1 ? L.n[0] + 1 : L.n[0] + L.n[1] + 2));
-    const int r = blockIdx.y * 4 + threadIdx.y, c = blockIdx.x * 64 + threadIdx.x;
+    const int c = blockIdx.x * 64 + threadIdx.x;
     const int pitch = L.pitch[d];
     if (c >= pitch) return;
-    const int64_t within = (int64_t)r * pitch + c;
-    if (within >= L.pstride[d]) return;
-    const int64_t s = L.off[d] + (int64_t)j * L.pstride[d] + within;
     const int p = P > 0 ? P : L.p, n1 = p + 1, t2 = n1 * n1;
-    int g[3];
-    bool canon = r < L.rows[d];
-    if (d == 0) { g[0] = j * p; g[2] = r; g[1] = c; canon = canon && c < L.N[1]; }
-    else if (d == 1) { g[1] = j * p; g[2] = r; g[0] = c; canon = canon && c < L.N[0] && c % p != 0; }
-    else { g[2] = j * p; g[1] = r; g[0] = c; canon = canon && c < L.N[0] && c % p != 0 && r % p != 0; }
-    if (!canon || is_dir(L, g[0], g[1], g[2])) {
-        if (!sub) y[s] = (T)0;
-        return;
+    T v[2][8];
+    int64_t slot[2];
+    int mode[2];   // 0: nothing, 1: zero, 2: sum
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+        const int r = (blockIdx.y * 2 + rr) * 4 + threadIdx.y;
+        mode[rr] = 0;
+        slot[rr] = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[rr][k] = 0;
+        const int64_t within = (int64_t)r * pitch + c;
+        if (within >= L.pstride[d]) continue;
+        const int64_t s = L.off[d] + (int64_t)j * L.pstride[d] + within;
+        slot[rr] = s;
+        int g[3];
+        bool canon = r < L.rows[d];
+        if (d == 0) { g[0] = j * p; g[2] = r; g[1] = c; canon = canon && c < L.N[1]; }
+        else if (d == 1) { g[1] = j * p; g[2] = r; g[0] = c; canon = canon && c < L.N[0] && c % p != 0; }
+        else { g[2] = j * p; g[1] = r; g[0] = c; canon = canon && c < L.N[0] && c % p != 0 && r % p != 0; }
+        if (!canon || is_dir(L, g[0], g[1], g[2])) {
+            mode[rr] = sub ? 0 : 1;
+            continue;
+        }
+        mode[rr] = 2;
+        int e0[3], a0[3], e1[3], a1[3];
+        bool two[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int qk = g[k] / p, ak = g[k] - qk * p;
+            const bool bnd = ak == 0;
+            const bool lo = bnd && qk > 0, hi = !bnd || qk < L.n[k];
+            e0[k] = lo ? qk - 1 : qk;
+            a0[k] = lo ? p : ak;
+            two[k] = lo && hi;
+            e1[k] = qk;
+            a1[k] = 0;
+        }
+#pragma unroll
+        for (int zz = 0; zz < 2; ++zz)
+#pragma unroll
+            for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+                for (int x = 0; x < 2; ++x) {
+                    const int k = (zz * 2 + yy) * 2 + x;
+                    if ((x && !two[0]) || (yy && !two[1]) || (zz && !two[2])) continue;
+                    const int c1 = x ? e1[0] : e0[0], c2 = yy ? e1[1] : e0[1], c3 = zz ? e1[2] : e0[2];
+                    const int b1 = x ? a1[0] : a0[0], b2 = yy ? a1[1] : a0[1], b3 = zz ? a1[2] : a0[2];
+                    const int64_t e = ((int64_t)c3 * L.n[1] + c2) * L.n[0] + c1;
+                    int f, tr, tc;
+                    if (b1 == 0 || b1 == p) { f = b1 ? 1 : 0; tr = b3; tc = b2; }
+                    else if (b2 == 0 || b2 == p) { f = b2 ? 3 : 2; tr = b3; tc = b1; }
+                    else { f = b3 ? 5 : 4; tr = b2; tc = b1; }
+                    v[rr][k] = E[e * 6 * t2 + f * t2 + tr * n1 + tc];
+                }
     }
-    // candidate (element index, local index) per direction: one element, or
-    // the two on both sides of an element boundary (clipped at the domain)
-    int e0[3], a0[3], e1[3], a1[3];
-    bool two[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int qk = g[k] / p, ak = g[k] - qk * p;
-        const bool bnd = ak == 0;
-        const bool lo = bnd && qk > 0, hi = !bnd || qk < L.n[k];
-        // first candidate: the element below the boundary if it exists
-        e0[k] = lo ? qk - 1 : qk;
-        a0[k] = lo ? p : ak;
-        two[k] = lo && hi;
-        e1[k] = qk;
-        a1[k] = 0;
+    for (int rr = 0; rr < 2; ++rr) {
+        if (mode[rr] == 0) continue;
+        const int64_t s = slot[rr];
+        if (mode[rr] == 1) { y[s] = (T)0; continue; }
+        T acc = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += v[rr][k];
+        if (sub) y[s] -= acc;
+        else y[s] = F ? F[s] - acc : acc;
     }
-    // all (up to eight) loads first, then the sum in a fixed order
-    T v[8];
-#pragma unroll
-    for (int z = 0; z < 2; ++z)
-#pragma unroll
-        for (int yy = 0; yy < 2; ++yy)
-#pragma unroll
-            for (int x = 0; x < 2; ++x) {
-                const int k = (z * 2 + yy) * 2 + x;
-                v[k] = 0;
-                if ((x && !two[0]) || (yy && !two[1]) || (z && !two[2])) continue;
-                const int c1 = x ? e1[0] : e0[0], c2 = yy ? e1[1] : e0[1], c3 = z ? e1[2] : e0[2];
-                const int b1 = x ? a1[0] : a0[0], b2 = yy ? a1[1] : a0[1], b3 = z ? a1[2] : a0[2];
-                const int64_t e = ((int64_t)c3 * L.n[1] + c2) * L.n[0] + c1;
-                int f, tr, tc;
-                if (b1 == 0 || b1 == p) { f = b1 ? 1 : 0; tr = b3; tc = b2; }
-                else if (b2 == 0 || b2 == p) { f = b2 ? 3 : 2; tr = b3; tc = b1; }
-                else { f = b3 ? 5 : 4; tr = b2; tc = b1; }
-                v[k] = E[e * 6 * t2 + f * t2 + tr * n1 + tc];
-            }
-    T acc = 0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) acc += v[k];
-    if (sub) y[s] -= acc;
-    else y[s] = F ? F[s] - acc : acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -4381,7 +4396,7 @@ static void launch_gather_elem(const Layout& L, const T* E, const T* F, T* y, hi
         mr = std::max(mr, (int)((L.pstride[d] + L.pitch[d] - 1) / L.pitch[d]));
     }
     const int planes = L.n[0] + L.n[1] + L.n[2] + 3;
-    const dim3 grid((mp + 63) / 64, (mr + 3) / 4, planes), block(64, 4);
+    const dim3 grid((mp + 63) / 64, (mr + 7) / 8, planes), block(64, 4);
     switch (L.p) {
         case 4: hipLaunchKernelGGL((k_gather_elem<T, 4>), grid, block, 0, st, L, E, F, y, sub); break;
         case 8: hipLaunchKernelGGL((k_gather_elem<T, 8>), grid, block, 0, st, L, E, F, y, sub); break;
