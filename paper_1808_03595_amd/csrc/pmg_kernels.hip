@@ -2209,8 +2209,21 @@ struct FdMat {
     const double* p;
     int64_t rs, cs, bs;   // row, column and batch strides
 };
+// Optional division of the product's output by the eigenvalue sums, for the
+// last forward pass (C[i3][i2 m1 + i1] /= lam + mu1[i1] + mu2[i2] + mu3[i3]);
+// mu1 = nullptr: none
+struct FdScale {
+    const double *mu1, *mu2, *mu3;
+    double lam;
+    int m1;
+    __device__ double apply(double v, int r, int c) const {
+        if (!mu1) return v;
+        const int i2 = c / m1, i1 = c - i2 * m1;
+        return v / (lam + mu1[i1] + mu2[i2] + mu3[r]);
+    }
+};
 __global__ void __launch_bounds__(64) k_fd_gemm(FdMat P, FdMat Q, double* __restrict__ C, int64_t c_rs, int64_t c_cs,
-                                                int64_t c_bs, int M, int N, int K, int tiles_n) {
+                                                int64_t c_bs, int M, int N, int K, int tiles_n, FdScale sc) {
     typedef Mfma<double> MF;
     const int lane = threadIdx.x, q = lane >> 4, j = lane & 15;
     const int tr = blockIdx.x / tiles_n, tc = blockIdx.x - tr * tiles_n, b = blockIdx.y;
@@ -2228,7 +2241,7 @@ __global__ void __launch_bounds__(64) k_fd_gemm(FdMat P, FdMat Q, double* __rest
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int r = tr * 16 + MF::row(q, v);
-        if (r < M && col < N) cc[(int64_t)r * c_rs + (int64_t)col * c_cs] = acc[v];
+        if (r < M && col < N) cc[(int64_t)r * c_rs + (int64_t)col * c_cs] = sc.apply(acc[v], r, col);
     }
 }
 
@@ -2241,7 +2254,7 @@ __global__ void __launch_bounds__(64) k_fd_gemm(FdMat P, FdMat Q, double* __rest
 constexpr int FDT = 64, FDK = 16;
 __global__ void __launch_bounds__(256) k_fd_gemm_tiled(FdMat P, FdMat Q, double* __restrict__ C, int64_t c_rs,
                                                        int64_t c_cs, int64_t c_bs, int M, int N, int K,
-                                                       int tiles_n) {
+                                                       int tiles_n, FdScale sc) {
     typedef Mfma<double> MF;
     __shared__ double As[FDT][FDK + 1];
     __shared__ double Bs[FDK][FDT + 1];
@@ -2298,17 +2311,9 @@ __global__ void __launch_bounds__(256) k_fd_gemm_tiled(FdMat P, FdMat Q, double*
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = row0 + wr + 16 * a + MF::row(q, v);
-                if (r < M && col < N) cc[(int64_t)r * c_rs + (int64_t)col * c_cs] = acc[a][c][v];
+                if (r < M && col < N) cc[(int64_t)r * c_rs + (int64_t)col * c_cs] = sc.apply(acc[a][c][v], r, col);
             }
         }
-}
-
-__global__ void k_fd_scale(double* __restrict__ X, const double* __restrict__ mu1, const double* __restrict__ mu2,
-                           const double* __restrict__ mu3, double lam, int m1, int m2, int m3) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)m1 * m2 * m3) return;
-    const int a1 = (int)(t % m1), a2 = (int)((t / m1) % m2), a3 = (int)(t / ((int64_t)m1 * m2));
-    X[t] = X[t] / (lam + mu1[a1] + mu2[a2] + mu3[a3]);
 }
 
 // Every slot of the plane layout: the solution at a free skeleton node (in
@@ -2346,7 +2351,7 @@ void launch_fd_solve(const Layout& L, const FdTabs& fd, double lam, const double
     //   d = 0: out[o][k] = sum_i in[o][i] A[k][i]        (o over m2 m3)
     //   d = 1: out[o][k][c] = sum_i A[k][i] in[o][i][c]  (batch o over m3)
     //   d = 2: out[k][c] = sum_i A[k][i] in[i][c]        (c over m1 m2)
-    auto pass = [&](int d, const double* A, const double* in, double* out) {
+    auto pass = [&](int d, const double* A, const double* in, double* out, FdScale sc) {
         const int m = fd.m[d];
         int Mr, Nc, nb;
         FdMat P, Q;
@@ -2372,21 +2377,22 @@ void launch_fd_solve(const Layout& L, const FdTabs& fd, double lam, const double
         const int tn64 = (Nc + FDT - 1) / FDT, tm64 = (Mr + FDT - 1) / FDT;
         if ((int64_t)tn64 * tm64 * nb >= 256) {
             hipLaunchKernelGGL(k_fd_gemm_tiled, dim3((unsigned)(tm64 * tn64), (unsigned)nb), dim3(256), 0, st, P, Q,
-                               out, crs, ccs, cbs, Mr, Nc, m, tn64);
+                               out, crs, ccs, cbs, Mr, Nc, m, tn64, sc);
             return;
         }
         const int tn = (Nc + 15) / 16, tm = (Mr + 15) / 16;
         hipLaunchKernelGGL(k_fd_gemm, dim3((unsigned)(tm * tn), (unsigned)nb), dim3(64), 0, st, P, Q, out, crs, ccs,
-                           cbs, Mr, Nc, m, tn);
+                           cbs, Mr, Nc, m, tn, sc);
     };
-    pass(0, fd.Af[0], fd.X, fd.Y);
-    pass(1, fd.Af[1], fd.Y, fd.X);
-    pass(2, fd.Af[2], fd.X, fd.Y);
-    hipLaunchKernelGGL(k_fd_scale, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, fd.Y, fd.mu[0], fd.mu[1],
-                       fd.mu[2], lam, m1, m2, m3);
-    pass(2, fd.Ab[2], fd.Y, fd.X);
-    pass(1, fd.Ab[1], fd.X, fd.Y);
-    pass(0, fd.Ab[0], fd.Y, fd.X);
+    // the division by the eigenvalue sums rides on the last forward pass,
+    // whose output is [i3][i2 m1 + i1]
+    const FdScale none{nullptr, nullptr, nullptr, 0.0, 1}, eig{fd.mu[0], fd.mu[1], fd.mu[2], lam, m1};
+    pass(0, fd.Af[0], fd.X, fd.Y, none);
+    pass(1, fd.Af[1], fd.Y, fd.X, none);
+    pass(2, fd.Af[2], fd.X, fd.Y, eig);
+    pass(2, fd.Ab[2], fd.Y, fd.X, none);
+    pass(1, fd.Ab[1], fd.X, fd.Y, none);
+    pass(0, fd.Ab[0], fd.Y, fd.X, none);
     hipLaunchKernelGGL(k_fd_gather, dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, st, L, (const double*)fd.X,
                        x, m1, m2, fd.o[0], fd.o[1], fd.o[2]);
 }
