@@ -1374,10 +1374,17 @@ __device__ __forceinline__ void v4_to(const typename Mfma<T>::v4& c, T o[4]) {
 // 4-way (FP64 at 32^3, p = 8: 264.5 -> 206 us; FP32 unchanged)
 constexpr int SM_RS = 20;
 
-// LDS entries per wavefront of the matrix-core smoother: the three G tiles,
-// then the 4 x 16 partial-sum rows of one contraction
+// FP64 stages its star's three eigenvector matrices (rows padded to 17) and
+// its eigenvalues and weights in LDS; FP32 reads them from memory (staging
+// both sets slowed FP32 145 -> 172 us at 32^3, p = 8, either one alone was
+// neutral; FP64 206 -> 197 us)
 template <typename T>
-constexpr int sm_mfma_per_wave() { return 64 * SM_RS; }
+constexpr bool sm_lds_tables() { return sizeof(T) == 8; }
+
+// LDS entries per wavefront of the matrix-core smoother: the three G tiles,
+// then the 4 x 16 partial-sum rows of one contraction, then (FP64) the tables
+template <typename T>
+constexpr int sm_mfma_per_wave() { return 64 * SM_RS + (sm_lds_tables<T>() ? 3 * 16 * 17 + 64 : 0); }
 
 template <typename T, int WPB>
 __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, const T* __restrict__ r,
@@ -1408,23 +1415,35 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
     const T* S2 = tb.st_SP[1] + (size_t)v2 * 256;
     const T* S3 = tb.st_SP[2] + (size_t)v3 * 256;
     const int c1 = v1 * p, c2 = v2 * p, c3 = v3 * p;
+    // staged tables: st[d][k][i] = S_d[k][i] (rows of 17), then ev[16 d + k]
+    // = lambda_d,k and ev[48 + k] = w_k, fetched by one load per lane here
+    constexpr bool LT = sm_lds_tables<T>();
+    T* st = sm + 64 * SM_RS;
+    T* ev = st + 3 * 16 * 17;
+    T evw = 0;
+    if (LT) {
+        const int dd = lane >> 4;
+        const int vv = dd == 0 ? v1 : dd == 1 ? v2 : v3;
+        evw = lane < 48 ? tb.st_lamP[dd][vv * 16 + (lane & 15)] : tb.st_wP[lane - 48];
+    }
     // the eigenspace pass works on the 4x4x4 tile (t1, t2, t3) of this lane;
     // its vectors a_d (row c of S_d) and the eigenvalues, the A-pattern
-    // copies of S for the back transforms and the weights are each loaded
-    // where they are needed (loading them all with the first operands
-    // measured 12 % slower in FP32: 166.6 -> 145.6 us at 32^3, p = 8)
+    // copies of S for the back transforms and the weights are each read
+    // where they are needed, from the staged tables in FP64 (loading them all
+    // into registers with the first operands measured 12 % slower in FP32:
+    // 166.6 -> 145.6 us at 32^3, p = 8)
     const int t1 = lane & 3, t2 = (lane >> 2) & 3, t3 = lane >> 4;
     const int k1b = 4 * t1, k2b = 4 * t2, k3b = 4 * t3;
     T a1[4], a2[4], a3[4], l1[4], l2[4], l3[4], wr[4], wj;
     auto load_eig = [&]() {
-        const T* L1 = tb.st_lamP[0] + v1 * 16;
-        const T* L2 = tb.st_lamP[1] + v2 * 16;
-        const T* L3 = tb.st_lamP[2] + v3 * 16;
+        const T* L1 = LT ? ev : tb.st_lamP[0] + v1 * 16;
+        const T* L2 = LT ? ev + 16 : tb.st_lamP[1] + v2 * 16;
+        const T* L3 = LT ? ev + 32 : tb.st_lamP[2] + v3 * 16;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            a1[i] = S1[c * 16 + k1b + i];
-            a2[i] = S2[c * 16 + k2b + i];
-            a3[i] = S3[c * 16 + k3b + i];
+            a1[i] = LT ? st[c * 17 + k1b + i] : S1[c * 16 + k1b + i];
+            a2[i] = LT ? st[(16 + c) * 17 + k2b + i] : S2[c * 16 + k2b + i];
+            a3[i] = LT ? st[(32 + c) * 17 + k3b + i] : S3[c * 16 + k3b + i];
             l1[i] = L1[k1b + i] + tb.lam;
             l2[i] = L2[k2b + i];
             l3[i] = L3[k3b + i];
@@ -1432,8 +1451,8 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
     };
     auto load_w = [&]() {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) wr[i] = tb.st_wP[M::row(q, i)];
-        wj = omega * tb.st_wP[j];
+        for (int i = 0; i < 4; ++i) wr[i] = LT ? ev[48 + M::row(q, i)] : tb.st_wP[M::row(q, i)];
+        wj = omega * (LT ? ev[48 + j] : tb.st_wP[j]);
     };
     // S in both operand patterns: Sb[s] = S[row(q,s)][j], Sa[s] = S[j][row(q,s)]
     T Sb1[4], Sb2[4], Sb3[4], Sa1[4], Sa2[4], Sa3[4];
@@ -1470,6 +1489,16 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
         f1[s] = x1;
         f2[s] = x2;
         f3[s] = x3;
+    }
+    if (LT) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = M::row(q, s);
+            st[k * 17 + j] = Sb1[s];
+            st[(16 + k) * 17 + j] = Sb2[s];
+            st[(32 + k) * 17 + j] = Sb3[s];
+        }
+        ev[lane] = evw;
     }
     // G1 = S3^T (F1 S2), G2 = S3^T (F2 S1), G3 = S2^T (F3 S1)
     T t[4];
@@ -1562,9 +1591,9 @@ __global__ void __launch_bounds__(64 * WPB) k_smoother_mfma(LevelTabs<T> tb, con
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int k = M::row(q, s);
-        Sa1[s] = S1[j * 16 + k];
-        Sa2[s] = S2[j * 16 + k];
-        Sa3[s] = S3[j * 16 + k];
+        Sa1[s] = LT ? st[j * 17 + k] : S1[j * 16 + k];
+        Sa2[s] = LT ? st[(16 + j) * 17 + k] : S2[j * 16 + k];
+        Sa3[s] = LT ? st[(32 + j) * 17 + k] : S3[j * 16 + k];
     }
     v4_to<T>(gemm16<T>(h1, Sa2), t);
     v4 u1 = gemm16<T>(Sa3, t);
