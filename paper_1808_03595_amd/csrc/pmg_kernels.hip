@@ -3111,7 +3111,12 @@ __global__ void __launch_bounds__(256) k_recover(LevelTabs<double> tb, const dou
 // eigenvalues and coupling vectors, the element's interior array, the face
 // transforms' scratch and (recovery) the face tiles.  Each 1D pass of the
 // three-dimensional transforms gives one lane one line of the element, held
-// in registers, and writes it back in place.
+// in registers, and writes it back in place.  The interior values of f are
+// loaded into registers with the staging loads (one round trip to memory
+// instead of two), and recovery writes them to LDS only after the face
+// transforms, whose scratch they then overwrite (32^3, p = 8: recovery 200
+// -> 171 us at 21 instead of 16 workgroups per CU, condensation 202 -> 191
+// us with the skeleton mass and gather)
 // ---------------------------------------------------------------------------
 template <int P>
 struct CRShape {
@@ -3126,8 +3131,11 @@ struct CRShape {
     static constexpr bool tmp_in_a = 6 * q2 <= q3;
     static constexpr int o_a = ltabs, o_Tc = o_a + q3, o_ctmp = tmp_in_a ? o_a : o_Tc + 6 * q2,
                          cond_total = tmp_in_a ? o_Tc + 6 * q2 : o_ctmp + 6 * q2;
-    // recovery: tables | a[q3] | tmp[6 q2] | tile, then G [6 t2]
-    static constexpr int o_rtmp = o_a + q3, o_rtile = o_rtmp + 6 * q2, rec_total = o_rtile + 6 * t2;
+    // recovery: tables | a[q3] | tile, then G [6 t2]; the face rows'
+    // scratch tmp[6 q2] in a's place where it fits (a is written from
+    // registers after the face transforms)
+    static constexpr int o_rtmp = tmp_in_a ? o_a : o_a + q3, o_rtile = tmp_in_a ? o_a + q3 : o_rtmp + 6 * q2,
+                         rec_total = o_rtile + 6 * t2;
     static_assert(q2 <= 64, "one lane per interior line");
 };
 
@@ -3217,19 +3225,34 @@ __device__ inline void cr_transform3(const LevelTabs<double>& tb, const int e[3]
     pass(2);
 }
 
-// a[q3] = m1 m2 m3 f at the element's interior nodes
+// The element's interior values of f into registers (fv[k] for entry
+// lane + 64 k of the q^3 array), issued with the staging loads, and later
+// a[q3] = m1 m2 m3 f from them
 template <int P>
-__device__ inline void cr_load_interior(const Layout& L, const int e[3], const double* tabs,
-                                        const double* __restrict__ f, double* a) {
-    using K = CRShape<P>;
-    constexpr int q = K::q, q2 = K::q2, LT = K::lt_d;
-    for (int i = threadIdx.x; i < K::q3; i += 64) {
-        const int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
-        const int i1 = e[0] * P + 1 + k1, i2 = e[1] * P + 1 + k2, i3 = e[2] * P + 1 + k3;
-        a[i] = tabs[K::l_m + k1 + 1] * tabs[LT + K::l_m + k2 + 1] * tabs[2 * LT + K::l_m + k3 + 1] *
-               f[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1];
+struct CRInterior {
+    static constexpr int q = P - 1, q2 = q * q, q3 = q2 * q, NI = (q3 + 63) / 64;
+    double fv[NI];
+    __device__ inline void fetch(const Layout& L, const int e[3], const double* __restrict__ f) {
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int i = threadIdx.x + 64 * k;
+            const int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
+            const int i1 = e[0] * P + 1 + k1, i2 = e[1] * P + 1 + k2, i3 = e[2] * P + 1 + k3;
+            fv[k] = i < q3 ? f[((int64_t)i3 * L.N[1] + i2) * L.N[0] + i1] : 0.0;
+        }
     }
-}
+    __device__ inline void scale_to(const double* tabs, double* a) const {
+        using K = CRShape<P>;
+        constexpr int LT = K::lt_d;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int i = threadIdx.x + 64 * k;
+            const int k1 = i % q, k2 = (i / q) % q, k3 = i / q2;
+            if (i < q3)
+                a[i] = tabs[K::l_m + k1 + 1] * tabs[LT + K::l_m + k2 + 1] * tabs[2 * LT + K::l_m + k3 + 1] * fv[k];
+        }
+    }
+};
 
 template <int P>
 __global__ void __launch_bounds__(64) k_condense_w(LevelTabs<double> tb, const double* __restrict__ f) {
@@ -3246,8 +3269,10 @@ __global__ void __launch_bounds__(64) k_condense_w(LevelTabs<double> tb, const d
     const int eid = xcd_remap(blockIdx.x, gridDim.x);
     int e[3];
     color_coords(eid, -1, L.n, e);
+    CRInterior<P> fin;
+    fin.fetch(L, e, f);
     cr_stage<P, false>(tb, e, nullptr, tabs, nullptr);
-    cr_load_interior<P>(L, e, tabs, f, a);
+    fin.scale_to(tabs, a);
     __syncthreads();
     cr_transform3<P, true>(tb, e, a);          // a = (S x S x S)^T F_I
     const double lam = tb.lam;
@@ -3331,8 +3356,9 @@ __global__ void __launch_bounds__(64) k_recover_w(LevelTabs<double> tb, const do
     const int eid = xcd_remap(blockIdx.x, gridDim.x);
     int e[3];
     color_coords(eid, -1, L.n, e);
+    CRInterior<P> fin;
+    fin.fetch(L, e, f);
     cr_stage<P, true>(tb, e, uh, tabs, tile);
-    cr_load_interior<P>(L, e, tabs, f, a);
     // shell nodes owned by this element: a_d < p, or a_d = p on the last element
     for (int i = lane; i < n1 * n1 * n1; i += 64) {
         const int a1 = i % n1, a2 = (i / n1) % n1, a3 = i / t2;
@@ -3347,9 +3373,11 @@ __global__ void __launch_bounds__(64) k_recover_w(LevelTabs<double> tb, const do
     // G_f = Si_R X_f Si_C^T on the face interiors: rows of the tile into tmp
     k1_face_tx<double, P, true>(tb, e, K::o_Si, tile + n1 + 1, t2, n1, tmp, q2, q);
     __syncthreads();
-    cr_transform3<P, true>(tb, e, a);          // a = (S x S x S)^T F_I
     k1_face_tx<double, P, false>(tb, e, K::o_Si, tmp, q2, q, G, q2, q);   // columns of tmp, over the tile
     __syncthreads();
+    fin.scale_to(tabs, a);                     // over tmp
+    __syncthreads();
+    cr_transform3<P, true>(tb, e, a);          // a = (S x S x S)^T F_I
     // V = (a - sum_f c_f (x) G_f) / D in place (lane: (k2, k3) line)
     const double lam = tb.lam;
     const ctab_t<double> g0 = (ctab_t<double>)(tb.el_pack[0] + (size_t)e[0] * TD + K::o_lm);
