@@ -3558,6 +3558,14 @@ __device__ inline void finish_reduce(double* partials, const double* mine, int n
     if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Are all the given pointers 16-byte aligned (null counts as aligned)?  The
+// vector kernels below then take two entries per thread and step with
+// 16-byte loads and stores, the odd last entry left to the scalar loop.
+__device__ inline bool al16(const void* a, const void* b = nullptr, const void* c = nullptr,
+                            const void* d = nullptr) {
+    return (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c | (uintptr_t)d) & 15) == 0;
+}
+
 // out[0] = x . y ; out[1] = x . z (if z non-null; out[1] is left alone otherwise)
 template <typename T>
 __global__ void __launch_bounds__(REDUCE_THREADS) k_dot2(const T* __restrict__ x, const T* __restrict__ y,
@@ -3565,7 +3573,26 @@ __global__ void __launch_bounds__(REDUCE_THREADS) k_dot2(const T* __restrict__ x
                                               unsigned* counter, double* out) {
     __shared__ double red[16];
     double s0 = 0.0, s1 = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nth = (int64_t)gridDim.x * blockDim.x;
+    int64_t i0 = tid;
+    if constexpr (sizeof(T) == 8) {
+        if (al16(x, y, z)) {
+            const int64_t np = n >> 1;
+            const double2* x2 = reinterpret_cast<const double2*>(x);
+            const double2* y2 = reinterpret_cast<const double2*>(y);
+            const double2* z2 = reinterpret_cast<const double2*>(z);
+            for (int64_t j = tid; j < np; j += nth) {
+                const double2 xv = x2[j], yv = y2[j];
+                s0 += xv.x * yv.x + xv.y * yv.y;
+                if (z) {
+                    const double2 zv = z2[j];
+                    s1 += xv.x * zv.x + xv.y * zv.y;
+                }
+            }
+            i0 = 2 * np + tid;
+        }
+    }
+    for (int64_t i = i0; i < n; i += nth) {
         double xv = (double)x[i];
         s0 += xv * (double)y[i];
         if (z) s1 += xv * (double)z[i];
@@ -3620,7 +3647,32 @@ __global__ void __launch_bounds__(REDUCE_THREADS) k_pcg_update(double* __restric
         if (r32) *sc_zs = zs;
     }
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nth = (int64_t)gridDim.x * blockDim.x;
+    int64_t i0 = tid;
+    if (al16(u, r, s, p) && al16(q, r32)) {
+        const int64_t np = n >> 1;
+        double2* u2 = reinterpret_cast<double2*>(u);
+        double2* r2 = reinterpret_cast<double2*>(r);
+        double2* s2 = reinterpret_cast<double2*>(s);
+        const double2* p2 = reinterpret_cast<const double2*>(p);
+        const double2* q2 = reinterpret_cast<const double2*>(q);
+        float2* r32v = reinterpret_cast<float2*>(r32);
+        for (int64_t j = tid; j < np; j += nth) {
+            double2 ri = r2[j], ui = u2[j];
+            const double2 pi = p2[j], qi = q2[j];
+            if (s) s2[j] = ri;
+            ui.x += alpha * pi.x;
+            ui.y += alpha * pi.y;
+            u2[j] = ui;
+            ri.x -= alpha * qi.x;
+            ri.y -= alpha * qi.y;
+            r2[j] = ri;
+            if (r32) r32v[j] = make_float2((float)(ri.x * izs), (float)(ri.y * izs));
+            acc += ri.x * ri.x + ri.y * ri.y;
+        }
+        i0 = 2 * np + tid;
+    }
+    for (int64_t i = i0; i < n; i += nth) {
         double ri = r[i];
         if (s) s[i] = ri;
         u[i] += alpha * p[i];
@@ -3651,7 +3703,23 @@ __global__ void __launch_bounds__(REDUCE_THREADS) k_dot_zmix(const float* __rest
     __shared__ double red[16];
     const double zs = sc_zs[0];
     double s0 = 0.0, s1 = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nth = (int64_t)gridDim.x * blockDim.x;
+    int64_t i0 = tid;
+    if (al16(z32, r, s)) {
+        const int64_t np = n >> 1;
+        const float2* z2 = reinterpret_cast<const float2*>(z32);
+        const double2* r2 = reinterpret_cast<const double2*>(r);
+        const double2* s2 = reinterpret_cast<const double2*>(s);
+        for (int64_t j = tid; j < np; j += nth) {
+            const float2 zv = z2[j];
+            const double2 rv = r2[j], sv = s2[j];
+            const double za = zs * (double)zv.x, zb = zs * (double)zv.y;
+            s0 += za * rv.x + zb * rv.y;
+            s1 += za * sv.x + zb * sv.y;
+        }
+        i0 = 2 * np + tid;
+    }
+    for (int64_t i = i0; i < n; i += nth) {
         const double zv = zs * (double)z32[i];
         s0 += zv * r[i];
         s1 += zv * s[i];
@@ -3666,10 +3734,20 @@ __global__ void __launch_bounds__(REDUCE_THREADS) k_dot_zmix(const float* __rest
 // p = beta p + zs z32 (the direction update of Alg. 5 with the FP32 result)
 __global__ void k_pcg_dir_mixed(double* __restrict__ p, const float* __restrict__ z32, const double* sc_zs,
                                 const double* sc, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, i = 2 * j;
     if (i >= n) return;
-    const double beta = (sc[0] - sc[1]) / sc[2];
-    p[i] = beta * p[i] + sc_zs[0] * (double)z32[i];
+    const double beta = (sc[0] - sc[1]) / sc[2], zs = sc_zs[0];
+    if (i + 1 < n && al16(p, z32)) {   // entries 2 j and 2 j + 1
+        double2* p2 = reinterpret_cast<double2*>(p);
+        const float2 zv = reinterpret_cast<const float2*>(z32)[j];
+        double2 pv = p2[j];
+        pv.x = beta * pv.x + zs * (double)zv.x;
+        pv.y = beta * pv.y + zs * (double)zv.y;
+        p2[j] = pv;
+        return;
+    }
+    p[i] = beta * p[i] + zs * (double)z32[i];
+    if (i + 1 < n) p[i + 1] = beta * p[i + 1] + zs * (double)z32[i + 1];
 }
 
 // Jacobi-PCG pieces for the coarse solve (FP64).
@@ -4937,7 +5015,7 @@ void launch_dot_zmix(const float* z32, const double* sc_zs, const double* r, con
 
 void launch_pcg_dir_mixed(double* p, const float* z32, const double* sc_zs, const double* sc, int64_t n,
                           hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_dir_mixed, dim3(nblk(n)), dim3(256), 0, st, p, z32, sc_zs, sc, n);
+    hipLaunchKernelGGL(k_pcg_dir_mixed, dim3(nblk((n + 1) / 2)), dim3(256), 0, st, p, z32, sc_zs, sc, n);
 }
 
 // Copy the solver scalars to the host notice block, then bump its sequence
