@@ -2220,11 +2220,26 @@ __global__ void __launch_bounds__(256) k_blk_eigen(LevelTabs<T> tb, const T* __r
 // three backward passes, and the skeleton values back into the plane
 // layout.  The condensed solution is the skeleton part of the full solution.
 // ---------------------------------------------------------------------------
+// Plane-layout slot s -> family d, plane j, row r, column c, in the index
+// type I (32-bit unsigned where the layout has fewer than 2^31 slots, whose
+// divisions are several times cheaper than 64-bit ones)
+template <typename I>
+__device__ inline void slot_decode(const Layout& L, I s, int& d, int& j, int& r, int& c) {
+    d = (s >= (I)L.off[2]) ? 2 : (s >= (I)L.off[1] ? 1 : 0);
+    const I loc = s - (I)L.off[d];
+    j = (int)(loc / (I)L.pstride[d]);
+    const I rem = loc - (I)j * (I)L.pstride[d];
+    r = (int)(rem / (I)L.pitch[d]);
+    c = (int)(rem - (I)r * (I)L.pitch[d]);
+}
+
+template <typename I>
 __global__ void k_fd_scatter(Layout L, const double* __restrict__ b, double* __restrict__ X, int m1, int m2, int m3,
                              int o1, int o2, int o3) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)m1 * m2 * m3) return;
-    const int a1 = (int)(t % m1), a2 = (int)((t / m1) % m2), a3 = (int)(t / ((int64_t)m1 * m2));
+    const I t = (I)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((int64_t)t >= (int64_t)m1 * m2 * m3) return;
+    const I t1 = t / (I)m1;
+    const int a1 = (int)(t - t1 * (I)m1), a3 = (int)(t1 / (I)m2), a2 = (int)(t1 - (I)a3 * (I)m2);
     const int i1 = a1 + o1, i2 = a2 + o2, i3 = a3 + o3, p = L.p;
     const bool on1 = i1 % p == 0, on2 = i2 % p == 0, on3 = i3 % p == 0;
     X[t] = (on1 || on2 || on3) ? b[L.slot(i1, i2, i3, on1, on2)] : 0.0;
@@ -2347,15 +2362,13 @@ __global__ void __launch_bounds__(256) k_fd_gemm_tiled(FdMat P, FdMat Q, double*
 
 // Every slot of the plane layout: the solution at a free skeleton node (in
 // its storing family), zero elsewhere.
+template <typename I>
 __global__ void k_fd_gather(Layout L, const double* __restrict__ X, double* __restrict__ x, int m1, int m2, int o1,
                             int o2, int o3) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= L.len) return;
-    const int d = (s >= L.off[2]) ? 2 : (s >= L.off[1] ? 1 : 0);
-    const int64_t loc = s - L.off[d];
-    const int j = (int)(loc / L.pstride[d]);
-    const int64_t rem = loc - (int64_t)j * L.pstride[d];
-    const int r = (int)(rem / L.pitch[d]), c = (int)(rem - (int64_t)r * L.pitch[d]);
+    const I s = (I)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((int64_t)s >= L.len) return;
+    int d, j, r, c;
+    slot_decode<I>(L, s, d, j, r, c);
     const int p = L.p;
     double v = 0.0;
     if (r < L.rows[d]) {
@@ -2373,8 +2386,12 @@ __global__ void k_fd_gather(Layout L, const double* __restrict__ X, double* __re
 void launch_fd_solve(const Layout& L, const FdTabs& fd, double lam, const double* b, double* x, hipStream_t st) {
     const int m1 = fd.m[0], m2 = fd.m[1], m3 = fd.m[2];
     const int64_t M = (int64_t)m1 * m2 * m3;
-    hipLaunchKernelGGL(k_fd_scatter, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, L, b, fd.X, m1, m2, m3,
-                       fd.o[0], fd.o[1], fd.o[2]);
+    if (M < ((int64_t)1 << 31))
+        hipLaunchKernelGGL(k_fd_scatter<uint32_t>, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, L, b, fd.X, m1,
+                           m2, m3, fd.o[0], fd.o[1], fd.o[2]);
+    else
+        hipLaunchKernelGGL(k_fd_scatter<uint64_t>, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, L, b, fd.X, m1,
+                           m2, m3, fd.o[0], fd.o[1], fd.o[2]);
     // direction d of the [m3][m2][m1] array X with the m x m matrix A
     // (out[.., k, ..] = sum_i A[k][i] in[.., i, ..]):
     //   d = 0: out[o][k] = sum_i in[o][i] A[k][i]        (o over m2 m3)
@@ -2422,8 +2439,12 @@ void launch_fd_solve(const Layout& L, const FdTabs& fd, double lam, const double
     pass(2, fd.Ab[2], fd.Y, fd.X, none);
     pass(1, fd.Ab[1], fd.X, fd.Y, none);
     pass(0, fd.Ab[0], fd.Y, fd.X, none);
-    hipLaunchKernelGGL(k_fd_gather, dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, st, L, (const double*)fd.X,
-                       x, m1, m2, fd.o[0], fd.o[1], fd.o[2]);
+    if (L.len < ((int64_t)1 << 31))
+        hipLaunchKernelGGL(k_fd_gather<uint32_t>, dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, st, L,
+                           (const double*)fd.X, x, m1, m2, fd.o[0], fd.o[1], fd.o[2]);
+    else
+        hipLaunchKernelGGL(k_fd_gather<uint64_t>, dim3((unsigned)((L.len + 255) / 256)), dim3(256), 0, st, L,
+                           (const double*)fd.X, x, m1, m2, fd.o[0], fd.o[1], fd.o[2]);
 }
 
 // ---------------------------------------------------------------------------
@@ -2701,15 +2722,12 @@ __global__ void __launch_bounds__(256) k_restrict_cols(Layout Lc, Layout Lf, con
 
 // Restriction pass B: coarse unknown = sum of T_d over the plane families
 // that contain it.
-template <typename T, typename TC>
+template <typename T, typename TC, typename I>
 __global__ void k_restrict_combine(Layout L, const T* __restrict__ tbuf, TC* __restrict__ rc) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= L.len) return;
-    int d = (i >= L.off[2]) ? 2 : (i >= L.off[1] ? 1 : 0);
-    int64_t loc = i - L.off[d];
-    int j = (int)(loc / L.pstride[d]);
-    int64_t rem = loc - (int64_t)j * L.pstride[d];
-    int r = (int)(rem / L.pitch[d]), c = (int)(rem - (int64_t)r * L.pitch[d]);
+    const I i = (I)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((int64_t)i >= L.len) return;
+    int d, j, r, c;
+    slot_decode<I>(L, i, d, j, r, c);
     const int p = L.p;
     T v = 0;
     if (r < L.rows[d]) {
@@ -2887,16 +2905,14 @@ __device__ void interior_backward(const ElemPtrs<T>& P, int q, T* a, T* b) {
 }
 
 // Fhat (skeleton part) = assembled mass * f at the free skeleton nodes.
+template <typename I>
 __global__ void k_mass_skeleton(Layout L, const double* __restrict__ m1, const double* __restrict__ m2,
                                 const double* __restrict__ m3, const double* __restrict__ f,
                                 double* __restrict__ Fh) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= L.len) return;
-    int d = (i >= L.off[2]) ? 2 : (i >= L.off[1] ? 1 : 0);
-    int64_t loc = i - L.off[d];
-    int j = (int)(loc / L.pstride[d]);
-    int64_t rem = loc - (int64_t)j * L.pstride[d];
-    int r = (int)(rem / L.pitch[d]), c = (int)(rem - (int64_t)r * L.pitch[d]);
+    const I i = (I)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((int64_t)i >= L.len) return;
+    int d, j, r, c;
+    slot_decode<I>(L, i, d, j, r, c);
     const int p = L.p;
     double v = 0;
     if (r < L.rows[d]) {
@@ -4815,7 +4831,12 @@ void launch_restrict(const Layout& Lf, const Layout& Lc, const T* J, const T* rf
     else if (Lf.p == 16 && Lc.p == 8) PMG_RES(16, 8);
     else PMG_RES(0, 0);
 #undef PMG_RES
-    hipLaunchKernelGGL((k_restrict_combine<T, TC>), dim3(nblk(Lc.len)), dim3(256), 0, st, Lc, (const T*)tbuf, rc);
+    if (Lc.len < ((int64_t)1 << 31))
+        hipLaunchKernelGGL((k_restrict_combine<T, TC, uint32_t>), dim3(nblk(Lc.len)), dim3(256), 0, st, Lc,
+                           (const T*)tbuf, rc);
+    else
+        hipLaunchKernelGGL((k_restrict_combine<T, TC, uint64_t>), dim3(nblk(Lc.len)), dim3(256), 0, st, Lc,
+                           (const T*)tbuf, rc);
     launch_seam<TC>(Lc, 1, rc, st);   // sums at coarse mirror nodes onto the nodes they repeat
 }
 
@@ -4868,7 +4889,10 @@ void launch_condense(const LevelTabs<double>& tb, const double* m1, const double
 static void condense_unfolded(const LevelTabs<double>& tb, const double* m1, const double* m2, const double* m3,
                               const double* f, double* Fh, hipStream_t st) {
     const Layout& L = tb.lay;
-    hipLaunchKernelGGL(k_mass_skeleton, dim3(nblk(L.len)), dim3(256), 0, st, L, m1, m2, m3, f, Fh);
+    if (L.len < ((int64_t)1 << 31))
+        hipLaunchKernelGGL(k_mass_skeleton<uint32_t>, dim3(nblk(L.len)), dim3(256), 0, st, L, m1, m2, m3, f, Fh);
+    else
+        hipLaunchKernelGGL(k_mass_skeleton<uint64_t>, dim3(nblk(L.len)), dim3(256), 0, st, L, m1, m2, m3, f, Fh);
     int q = L.p - 1;
     if (q < 1) return;
     if (L.p == 2) {
