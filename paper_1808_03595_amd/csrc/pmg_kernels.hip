@@ -733,9 +733,15 @@ __global__ void __launch_bounds__(256) k_rec_big_shell(LevelTabs<T> tb, const T*
 // padding rows included: each thread takes two rows of its column, their
 // loads issued before either sum, measured 111.4 -> 106.6 us per FP32
 // product at 32^3, p = 8), z over the planes of all three families.
+// With mf.f (condensation, sub = 0) the minuend is M f at the node, m1 m2 m3
+// f taken from the grid, in place of F: the skeleton part of the condensed
+// right-hand side in the same pass, no separate mass pass writing it first.
+struct MassF {
+    const double *m1 = nullptr, *m2 = nullptr, *m3 = nullptr, *f = nullptr;
+};
 template <typename T, int P>
 __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restrict__ E, const T* __restrict__ F,
-                                                     T* __restrict__ y, int sub) {
+                                                     T* __restrict__ y, int sub, MassF mf) {
     const int z = blockIdx.z;
     const int d = z >= L.n[0] + L.n[1] + 2 ? 2 : (z >= L.n[0] + 1 ? 1 : 0);
     const int j = z - (d == 0 ? 0 : (d == 1 ? L.n[0] + 1 : L.n[0] + L.n[1] + 2));
@@ -743,7 +749,7 @@ __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restri
     const int pitch = L.pitch[d];
     if (c >= pitch) return;
     const int p = P > 0 ? P : L.p, n1 = p + 1, t2 = n1 * n1;
-    T v[2][8];
+    T v[2][8], fv[2] = {0, 0};
     int64_t slot[2];
     int mode[2];   // 0: nothing, 1: zero, 2: sum
 #pragma unroll
@@ -767,6 +773,9 @@ __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restri
             continue;
         }
         mode[rr] = 2;
+        if (mf.f)
+            fv[rr] = (T)(mf.m1[g[0]] * mf.m2[g[1]] * mf.m3[g[2]] *
+                         mf.f[((int64_t)g[2] * L.N[1] + g[1]) * L.N[0] + g[0]]);
         int e0[3], a0[3], e1[3], a1[3];
         bool two[3];
 #pragma unroll
@@ -807,6 +816,7 @@ __global__ void __launch_bounds__(256) k_gather_elem(Layout L, const T* __restri
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc += v[rr][k];
         if (sub) y[s] -= acc;
+        else if (mf.f) y[s] = fv[rr] - acc;
         else y[s] = F ? F[s] - acc : acc;
     }
 }
@@ -4638,7 +4648,8 @@ void launch_skel_to_grid(const Layout& L, const T* s, double* g, hipStream_t st)
 // assembly of the per-element face tiles of the condensed operator (p >= 3)
 
 template <typename T>
-static void launch_gather_elem(const Layout& L, const T* E, const T* F, T* y, hipStream_t st, int sub = 0) {
+static void launch_gather_elem(const Layout& L, const T* E, const T* F, T* y, hipStream_t st, int sub = 0,
+                               MassF mf = MassF{}) {
     int mp = 0, mr = 0;
     for (int d = 0; d < 3; ++d) {
         mp = std::max(mp, L.pitch[d]);
@@ -4647,10 +4658,10 @@ static void launch_gather_elem(const Layout& L, const T* E, const T* F, T* y, hi
     const int planes = L.n[0] + L.n[1] + L.n[2] + 3;
     const dim3 grid((mp + 63) / 64, (mr + 7) / 8, planes), block(64, 4);
     switch (L.p) {
-        case 4: hipLaunchKernelGGL((k_gather_elem<T, 4>), grid, block, 0, st, L, E, F, y, sub); break;
-        case 8: hipLaunchKernelGGL((k_gather_elem<T, 8>), grid, block, 0, st, L, E, F, y, sub); break;
-        case 16: hipLaunchKernelGGL((k_gather_elem<T, 16>), grid, block, 0, st, L, E, F, y, sub); break;
-        default: hipLaunchKernelGGL((k_gather_elem<T, 0>), grid, block, 0, st, L, E, F, y, sub);
+        case 4: hipLaunchKernelGGL((k_gather_elem<T, 4>), grid, block, 0, st, L, E, F, y, sub, mf); break;
+        case 8: hipLaunchKernelGGL((k_gather_elem<T, 8>), grid, block, 0, st, L, E, F, y, sub, mf); break;
+        case 16: hipLaunchKernelGGL((k_gather_elem<T, 16>), grid, block, 0, st, L, E, F, y, sub, mf); break;
+        default: hipLaunchKernelGGL((k_gather_elem<T, 0>), grid, block, 0, st, L, E, F, y, sub, mf);
     }
 }
 
@@ -4949,10 +4960,16 @@ void launch_condense(const LevelTabs<double>& tb, const double* m1, const double
 static void condense_unfolded(const LevelTabs<double>& tb, const double* m1, const double* m2, const double* m3,
                               const double* f, double* Fh, hipStream_t st) {
     const Layout& L = tb.lay;
-    if (L.len < ((int64_t)1 << 31))
-        hipLaunchKernelGGL(k_mass_skeleton<uint32_t>, dim3(nblk(L.len)), dim3(256), 0, st, L, m1, m2, m3, f, Fh);
-    else
-        hipLaunchKernelGGL(k_mass_skeleton<uint64_t>, dim3(nblk(L.len)), dim3(256), 0, st, L, m1, m2, m3, f, Fh);
+    // the skeleton part M f: its own pass, unless the gather of the element
+    // corrections forms it (p >= 3 with the face-tile workspace)
+    const MassF mf{m1, m2, m3, f};
+    const bool fused = tb.opE && L.p >= 3 && (tb.ixX[0] || L.p <= 8);
+    if (!fused) {
+        if (L.len < ((int64_t)1 << 31))
+            hipLaunchKernelGGL(k_mass_skeleton<uint32_t>, dim3(nblk(L.len)), dim3(256), 0, st, L, m1, m2, m3, f, Fh);
+        else
+            hipLaunchKernelGGL(k_mass_skeleton<uint64_t>, dim3(nblk(L.len)), dim3(256), 0, st, L, m1, m2, m3, f, Fh);
+    }
     int q = L.p - 1;
     if (q < 1) return;
     if (L.p == 2) {
@@ -4966,7 +4983,7 @@ static void condense_unfolded(const LevelTabs<double>& tb, const double* m1, con
         hipLaunchKernelGGL(k_cond_big_contract<double>, dim3(ne, (3 * q2 + 255) / 256), dim3(256), 0, st, tb, tb.qp,
                            (const double*)tb.ixX[1]);
         hipLaunchKernelGGL(k_cond_big_back<double>, dim3(ne, 6), dim3(256), sizeof(double) * 4 * q2, st, tb);
-        launch_gather_elem(L, (const double*)tb.opE, (const double*)nullptr, Fh, st, 1);
+        launch_gather_elem(L, (const double*)tb.opE, (const double*)nullptr, Fh, st, 0, mf);
         return;
     }
     if (tb.opE && L.p >= 3 && L.p <= 8) {
@@ -4981,7 +4998,7 @@ static void condense_unfolded(const LevelTabs<double>& tb, const double* m1, con
             PMG_CW(3) PMG_CW(4) PMG_CW(5) PMG_CW(6) PMG_CW(7) PMG_CW(8)
 #undef PMG_CW
         }
-        launch_gather_elem(L, (const double*)tb.opE, (const double*)nullptr, Fh, st, 1);
+        launch_gather_elem(L, (const double*)tb.opE, (const double*)nullptr, Fh, st, 0, mf);
         return;
     }
     LevelTabs<double> t = tb;
