@@ -820,8 +820,10 @@ void prolong_from(Level& lc, Level& lv, const TC* uc, T* u, hipStream_t st) {
     else launch_hprolong_add<T>(lc.lay, lv.lay, hweights<T>(lv), uc, u, st);
 }
 
+// z_clear: z already holds zeros (the mixed-precision CG clears it in its
+// update), so no fill before the first smoothing
 template <typename T>
-int vc_down(pmg_mesh* m, const T* r, T* z, bool nonzero_u, hipStream_t st) {
+int vc_down(pmg_mesh* m, const T* r, T* z, bool nonzero_u, hipStream_t st, bool z_clear = false) {
     auto& A = m->act;
     const int L = (int)A.size() - 1;
     Level& l0 = *A[0];
@@ -829,7 +831,7 @@ int vc_down(pmg_mesh* m, const T* r, T* z, bool nonzero_u, hipStream_t st) {
         if (!std::is_same<T, double>::value) launch_cast_scale<T, double>(r, l0.F64, nullptr, 0, l0.lay.len, st);
         return 0;
     }
-    if (!nonzero_u) launch_fill_zero<T>(z, A[L]->lay.len, st);
+    if (!nonzero_u && !z_clear) launch_fill_zero<T>(z, A[L]->lay.len, st);
     const T* F = r;
     for (int l = L; l >= 1; --l) {
         Level& lv = *A[l];
@@ -1346,7 +1348,7 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
     // FP32 preconditioner: the first cycle's input r / |r| (each later one is
     // written by the update that produces its residual)
     if (mode == 0 && pdt == PMG_F32 && !status)
-        launch_cast_down(m->w_r, m->w_r32, m->scal + SC_RR, m->scal + SC_ZS, n, st);
+        launch_cast_down(m->w_r, m->w_r32, m->scal + SC_RR, m->scal + SC_ZS, n, st, m->w_z32);
     while (!status && std::sqrt(rr) > eps && it < maxit) {
         if (mode == 1) {
             // Alg. 4: u <- MultigridCycle(u, F); r = F - H u
@@ -1375,7 +1377,7 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
                 auto part_a = [&](hipStream_t s) -> int {
                     int r2;
                     if (pdt == PMG_F64) r2 = vc_down<double>(m, m->w_r, m->w_z, false, s);
-                    else r2 = vc_down<float>(m, m->w_r32, m->w_z32, false, s);
+                    else r2 = vc_down<float>(m, m->w_r32, m->w_z32, false, s, true);   // cleared by the update
                     if (r2) return r2;
                     if (m->coarse_kind == 1) {   // the exact coarse solve, inside the graph
                         Level& L0 = *m->act[0];
@@ -1406,7 +1408,8 @@ static int solve_common(pmg_mesh* m, const double* f, double* ug, double rtol, i
                     launch_dot2<double>(m->w_q, m->w_p, nullptr, n, m->partials, m->counter, m->scal + SC_QP, s);
                     launch_pcg_update(m->w_u, m->w_r, m->w_s, m->w_p, m->w_q, m->scal + SC_GAMMA, m->scal + SC_QP,
                                       n, m->partials, m->counter, m->scal + SC_RR, m->scal + SC_DELTA, s,
-                                      pdt == PMG_F64 ? nullptr : m->w_r32, m->scal + SC_ZS);
+                                      pdt == PMG_F64 ? nullptr : m->w_r32, m->scal + SC_ZS,
+                                      pdt == PMG_F64 ? nullptr : m->w_z32);
                     launch_publish(m->scal, SC_N, m->d_pubcnt, m->dmail, s);
                     return 0;
                 };

@@ -67,10 +67,14 @@ void launch_set_boundary(const int N[3], const double* g, double* u, hipStream_t
 void launch_pcg_dir(double* p, const double* z, const double* sc, int64_t n, hipStream_t);
 void launch_pcg_update(double* u, double* r, double* s, const double* p, const double* q, const double* gam,
                        const double* qp, int64_t n, double* partials, unsigned* counter, double* out,
-                       double* delta_out, hipStream_t st, float* r32 = nullptr, double* sc_zs = nullptr);
+                       double* delta_out, hipStream_t st, float* r32 = nullptr, double* sc_zs = nullptr,
+                       float* z32 = nullptr);
 // FP32 preconditioner: r32 = r / sqrt(r.r) and the scale; gamma, gamma0 and
-// the direction update from the FP32 result scaled back on the fly
-void launch_cast_down(const double* r, float* r32, const double* sc_rr, double* sc_zs, int64_t n, hipStream_t st);
+// the direction update from the FP32 result scaled back on the fly.  With
+// z32 the update and the cast also clear the FP32 cycle's correction, which
+// the next cycle then accumulates into without a fill of its own.
+void launch_cast_down(const double* r, float* r32, const double* sc_rr, double* sc_zs, int64_t n, hipStream_t st,
+                      float* z32 = nullptr);
 void launch_dot_zmix(const float* z32, const double* sc_zs, const double* r, const double* s, int64_t n,
                      double* partials, unsigned* counter, double* out, hipStream_t st);
 void launch_pcg_dir_mixed(double* p, const float* z32, const double* sc_zs, const double* sc, int64_t n,

@@ -3749,13 +3749,14 @@ __global__ void k_pcg_dir(double* __restrict__ p, const double* __restrict__ z, 
 // = |r| before this update (out[0] = r.r still holds it when the blocks
 // start: the last block writes the new value only after every block has
 // arrived), and *sc_zs = zs for the way back (the cycle is linear, so any
-// scale that keeps FP32 in range serves).
+// scale that keeps FP32 in range serves); with z32 also z32 = 0, the next
+// cycle's correction (its last readers ran before this update).
 __global__ void __launch_bounds__(REDUCE_THREADS) k_pcg_update(double* __restrict__ u, double* __restrict__ r,
                                                     double* __restrict__ s, const double* __restrict__ p,
                                                     const double* __restrict__ q, const double* sc_gamma,
                                                     const double* sc_qp, int64_t n, double* partials,
                                                     unsigned* counter, double* out, double* delta_out,
-                                                    float* __restrict__ r32, double* sc_zs) {
+                                                    float* __restrict__ r32, double* sc_zs, float* __restrict__ z32) {
     __shared__ double red[16];
     const double alpha = sc_gamma[0] / sc_qp[0];
     const double zs = r32 ? sqrt(out[0]) : 1.0, izs = 1.0 / zs;
@@ -3767,7 +3768,7 @@ __global__ void __launch_bounds__(REDUCE_THREADS) k_pcg_update(double* __restric
     double acc = 0.0;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nth = (int64_t)gridDim.x * blockDim.x;
     int64_t i0 = tid;
-    if (al16(u, r, s, p) && al16(q, r32)) {
+    if (al16(u, r, s, p) && al16(q, r32, z32)) {
         const int64_t np = n >> 1;
         double2* u2 = reinterpret_cast<double2*>(u);
         double2* r2 = reinterpret_cast<double2*>(r);
@@ -3786,6 +3787,7 @@ __global__ void __launch_bounds__(REDUCE_THREADS) k_pcg_update(double* __restric
             ri.y -= alpha * qi.y;
             r2[j] = ri;
             if (r32) r32v[j] = make_float2((float)(ri.x * izs), (float)(ri.y * izs));
+            if (z32) reinterpret_cast<float2*>(z32)[j] = make_float2(0.f, 0.f);
             acc += ri.x * ri.x + ri.y * ri.y;
         }
         i0 = 2 * np + tid;
@@ -3797,6 +3799,7 @@ __global__ void __launch_bounds__(REDUCE_THREADS) k_pcg_update(double* __restric
         ri -= alpha * q[i];
         r[i] = ri;
         if (r32) r32[i] = (float)(ri * izs);
+        if (z32) z32[i] = 0.f;
         acc += ri * ri;
     }
     double mine[1];
@@ -3804,13 +3807,17 @@ __global__ void __launch_bounds__(REDUCE_THREADS) k_pcg_update(double* __restric
     finish_reduce(partials, mine, 1, counter, out);
 }
 
-// FP32 preconditioner start: r32 = r / zs, zs = sqrt(r.r); *sc_zs = zs.
+// FP32 preconditioner start: r32 = r / zs, zs = sqrt(r.r); *sc_zs = zs;
+// with z32 also z32 = 0 (the first cycle's correction).
 __global__ void k_cast_down(const double* __restrict__ r, float* __restrict__ r32, const double* sc_rr,
-                            double* sc_zs, int64_t n) {
+                            double* sc_zs, int64_t n, float* __restrict__ z32) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const double zs = sqrt(sc_rr[0]);
     if (i == 0) *sc_zs = zs;
-    if (i < n) r32[i] = (float)(r[i] / zs);
+    if (i < n) {
+        r32[i] = (float)(r[i] / zs);
+        if (z32) z32[i] = 0.f;
+    }
 }
 
 // gamma = z . r and gamma0 = z . s with z = zs z32 (the FP32 cycle's result
@@ -5141,13 +5148,14 @@ void launch_pcg_dir(double* p, const double* z, const double* sc, int64_t n, hip
 
 void launch_pcg_update(double* u, double* r, double* s, const double* p, const double* q, const double* gam,
                        const double* qp, int64_t n, double* partials, unsigned* counter, double* out,
-                       double* delta_out, hipStream_t st, float* r32, double* sc_zs) {
+                       double* delta_out, hipStream_t st, float* r32, double* sc_zs, float* z32) {
     hipLaunchKernelGGL(k_pcg_update, dim3(REDUCE_BLOCKS), dim3(REDUCE_THREADS), 0, st, u, r, s, p, q, gam, qp, n, partials,
-                       counter, out, delta_out, r32, sc_zs);
+                       counter, out, delta_out, r32, sc_zs, z32);
 }
 
-void launch_cast_down(const double* r, float* r32, const double* sc_rr, double* sc_zs, int64_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_cast_down, dim3(nblk(n)), dim3(256), 0, st, r, r32, sc_rr, sc_zs, n);
+void launch_cast_down(const double* r, float* r32, const double* sc_rr, double* sc_zs, int64_t n, hipStream_t st,
+                      float* z32) {
+    hipLaunchKernelGGL(k_cast_down, dim3(nblk(n)), dim3(256), 0, st, r, r32, sc_rr, sc_zs, n, z32);
 }
 
 void launch_dot_zmix(const float* z32, const double* sc_zs, const double* r, const double* s, int64_t n,
