@@ -3233,8 +3233,8 @@ __global__ void __launch_bounds__(256) k_recover(LevelTabs<double> tb, const dou
 // loaded into registers with the staging loads (one round trip to memory
 // instead of two), and recovery writes them to LDS only after the face
 // transforms, whose scratch they then overwrite (32^3, p = 8: recovery 200
-// -> 171 us at 21 instead of 16 workgroups per CU, condensation 202 -> 191
-// us with the skeleton mass and gather)
+// -> 171 us at 21 instead of 16 workgroups per CU; the condensation phase
+// of the solve, event-timed, 202 -> 191 us)
 // ---------------------------------------------------------------------------
 template <int P>
 struct CRShape {
