@@ -752,6 +752,16 @@ def main():
                           f"({cb['oracle_iters']} ipCG iterations to 1e-10), timed once: {cb['oracle_s']:.1f} s"),
                "one_thread": cb["one_thread"]}
 
+    # what the learned damping gains over the paper's omega = 1 on this workload
+    lo, ll = head["mixed_omega1"], head["mixed_learned"]
+    gain = lo["iters"] - ll["iters"]
+    learned_vs = {"iters_learned": ll["iters"], "iters_omega1": lo["iters"], "ms_learned": ll["ms"],
+                  "ms_omega1": lo["ms"],
+                  "summary": ("the learned damping gains no iteration over omega = 1 on this workload"
+                              if gain <= 0 else
+                              f"the learned damping saves {gain} iteration(s) over omega = 1 on this workload")}
+    log(f"[bench] learned damping vs omega = 1: {learned_vs['summary']} "
+        f"({ll['iters']} / {lo['iters']} iterations, {ll['ms']:.2f} / {lo['ms']:.2f} ms)")
     line = {
         "metric": "solved unknowns/s to 1e-10 residual vs p; FP32-MG+learned vs plain FP64",
         "value": mixed["unknowns_per_s"],
@@ -771,7 +781,8 @@ def main():
                    "coarse": cdesc,
                    "coarse_level": mixed["coarse_level"], "coarse_degree": mixed["coarse_degree"],
                    "coarse_iters_per_solve": mixed["coarse_iters"],
-                   "solvers": {k: head[k] for k in ("fp64", "mixed_omega1", "mixed_learned")}},
+                   "solvers": {k: head[k] for k in ("fp64", "mixed_omega1", "mixed_learned")},
+                   "learned_vs_omega1": learned_vs},
         "roofline": roof,
         "kernels": kern,
         "cpu_baseline": cpu,
